@@ -1,0 +1,118 @@
+"""Finite-difference discretization of the state equation (oracle).
+
+The paper discretizes with Q1 finite elements (Sec. 2 and Sec. 6); this
+oracle follows the finite-difference reading used throughout the build:
+
+* grid: N interior points per axis on (0,1)^d, h = 1/(N+1), x_i = i h;
+* Poisson (eq. (eq:lap)): (A y)_i = h^-2 (2d y_i - sum of the 2d neighbours);
+* convection-diffusion (Sec. 6.3, -eps Lap y + w.grad y = u): A = eps A_Poisson + C
+  with first-order upwinding at node values,
+      (C y)_i = sum_a [max(w_a,0)(y_i - y_{i-e_a}) + min(w_a,0)(y_{i+e_a} - y_i)] / h,
+  wind w = (2 x2 (1 - x1^2), -2 x1 (1 - x2^2));
+* unit mass scaling: M = D = D_M = I.  The FEM-style weighting M = h^d I only
+  rescales the objective and the constraint by h^d, which leaves the
+  minimizer unchanged (Sec. 2, eq. (pb_fe)).
+
+Dirichlet data g (eq. (eq:lap), y = g on the boundary) enters through the
+boundary columns of the full operator: A_II y_I = f - A_IB g_B =: f_hat.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+import scipy.sparse as sp
+
+
+def _wind(x1: np.ndarray, x2: np.ndarray):
+    """Wind of the convection-diffusion example, Sec. 6.3."""
+    return 2.0 * x2 * (1.0 - x1 * x1), -2.0 * x1 * (1.0 - x2 * x2)
+
+
+def _all_nodes(dim: int, N: int):
+    """Integer index arrays (0..N+1) of all nodes, lexicographic, x1 fastest."""
+    idx = np.indices((N + 2,) * dim)  # idx[a] is the index along axis a
+    # flatten so that axis 0 (x1) varies fastest
+    return [idx[a].transpose(*range(dim)[::-1]).reshape(-1) for a in range(dim)]
+
+
+def _full_operator(dim: int, N: int, pde: str, eps: float) -> sp.csr_matrix:
+    """Rows for interior nodes, columns for all (N+2)^d nodes."""
+    h = 1.0 / (N + 1)
+    P = N + 2
+    ii = _all_nodes(dim, N)
+    interior = np.ones(P ** dim, dtype=bool)
+    for a in range(dim):
+        interior &= (ii[a] >= 1) & (ii[a] <= N)
+    rows_full = np.nonzero(interior)[0]          # full index of each interior node
+    n = rows_full.size
+    row_of = np.arange(n)
+    stride = [P ** a for a in range(dim)]
+
+    diff = 1.0 if pde == "poisson" else float(eps)
+    R, C, V = [], [], []
+    # diffusion part: diff * h^-2 (2d y_i - sum nbrs)
+    R.append(row_of); C.append(rows_full); V.append(np.full(n, diff * 2 * dim / h ** 2))
+    for a in range(dim):
+        for s in (-1, 1):
+            R.append(row_of); C.append(rows_full + s * stride[a]); V.append(np.full(n, -diff / h ** 2))
+    if pde == "convdiff":
+        if dim != 2:
+            raise ValueError("convection-diffusion is defined in 2D")
+        x1 = ii[0][rows_full] * h
+        x2 = ii[1][rows_full] * h
+        wind = _wind(x1, x2)
+        for a in range(dim):
+            wp = np.maximum(wind[a], 0.0) / h
+            wm = np.minimum(wind[a], 0.0) / h
+            # max(w,0)(y_i - y_{i-e}) + min(w,0)(y_{i+e} - y_i)
+            R.append(row_of); C.append(rows_full); V.append(wp - wm)
+            R.append(row_of); C.append(rows_full - stride[a]); V.append(-wp)
+            R.append(row_of); C.append(rows_full + stride[a]); V.append(wm)
+    elif pde != "poisson":
+        raise ValueError(f"unknown pde {pde!r}")
+    R = np.concatenate(R); C = np.concatenate(C); V = np.concatenate(V)
+    full = sp.csr_matrix((V, (R, C)), shape=(n, P ** dim))
+    full.sum_duplicates()
+    return full, rows_full
+
+
+@dataclass
+class Discretization:
+    dim: int
+    N: int
+    A: sp.csr_matrix       # interior operator A_II (n x n)
+    f_hat: np.ndarray      # f - A_IB g_B
+
+    @property
+    def n(self):
+        return self.N ** self.dim
+
+
+def operator_matrix(dim: int, N: int, pde: str = "poisson", eps: float = 1.0) -> sp.csr_matrix:
+    """A_II, the interior block of the discrete state operator (Sec. 2, matrix L)."""
+    full, rows_full = _full_operator(dim, N, pde, eps)
+    return full[:, rows_full].tocsr()
+
+
+def rhs_offset(dim: int, N: int, pde: str, eps: float, g) -> np.ndarray:
+    """-A_IB g_B: the boundary data moved to the right-hand side."""
+    full, rows_full = _full_operator(dim, N, pde, eps)
+    if g is None:
+        return np.zeros(rows_full.size)
+    gg = np.array(g, dtype=np.float64, copy=True)
+    gg[rows_full] = 0.0  # interior entries of g are ignored
+    return -(full @ gg)
+
+
+def discretize(prob) -> Discretization:
+    """Operator and folded right-hand side for a workloads.ProblemData."""
+    full, rows_full = _full_operator(prob.dim, prob.N, prob.pde, prob.eps)
+    A = full[:, rows_full].tocsr()
+    f = np.zeros(rows_full.size) if prob.f is None else np.asarray(prob.f, dtype=np.float64)
+    f_hat = f.copy()
+    if prob.g is not None:
+        gg = np.array(prob.g, dtype=np.float64, copy=True)
+        gg[rows_full] = 0.0
+        f_hat -= full @ gg
+    return Discretization(prob.dim, prob.N, A, f_hat)

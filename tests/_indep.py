@@ -1,0 +1,161 @@
+"""Independent helpers for pinning the oracle: a dense finite-difference
+operator built node by node with plain loops, a proximal-gradient (FISTA)
+solver for the control-only reduced problem and an exhaustive active-set
+solver for tiny problems.  None of this code is shared with oracle/ or with
+the GPU library."""
+from __future__ import annotations
+
+import itertools
+import math
+
+import numpy as np
+
+
+def wind(x1, x2):
+    # wind field of the convection-diffusion example (Sec. 6.3)
+    return 2.0 * x2 * (1.0 - x1 ** 2), -2.0 * x1 * (1.0 - x2 ** 2)
+
+
+def dense_operator(dim, N, pde="poisson", eps=1.0):
+    """Interior FD operator as a dense matrix, one node at a time."""
+    h = 1.0 / (N + 1)
+    n = N ** dim
+    A = np.zeros((n, n))
+
+    def idx(c):
+        k = 0
+        for a in reversed(range(dim)):
+            k = k * N + (c[a] - 1)
+        return k
+
+    for c in itertools.product(range(1, N + 1), repeat=dim):
+        c = tuple(reversed(c))  # iterate with x1 fastest (not required, but tidy)
+        i = idx(c)
+        d = 1.0 if pde == "poisson" else eps
+        A[i, i] += 2 * dim * d / h ** 2
+        for a in range(dim):
+            for s in (-1, 1):
+                nb = list(c); nb[a] += s
+                if 1 <= nb[a] <= N:
+                    A[i, idx(nb)] -= d / h ** 2
+        if pde == "convdiff":
+            x = [c[a] * h for a in range(dim)]
+            wv = wind(x[0], x[1])
+            for a in range(dim):
+                # upwind: flow in +e_a uses the backward difference, in -e_a the forward one
+                if wv[a] > 0:
+                    A[i, i] += wv[a] / h
+                    nb = list(c); nb[a] -= 1
+                    if nb[a] >= 1:
+                        A[i, idx(nb)] -= wv[a] / h
+                elif wv[a] < 0:
+                    A[i, i] += -wv[a] / h
+                    nb = list(c); nb[a] += 1
+                    if nb[a] <= N:
+                        A[i, idx(nb)] -= -wv[a] / h
+    return A
+
+
+def sine_mode(dim, N, ks):
+    h = 1.0 / (N + 1)
+    t = np.arange(1, N + 1) * h
+    grids = np.meshgrid(*([t] * dim), indexing="ij")
+    out = np.ones_like(grids[0])
+    for a in range(dim):
+        out = out * np.sin(ks[a] * math.pi * grids[a])
+    return out.reshape(-1, order="F")
+
+
+def sine_eigenvalue(dim, N, ks):
+    h = 1.0 / (N + 1)
+    return sum(4.0 / h ** 2 * math.sin(k * math.pi * h / 2) ** 2 for k in ks)
+
+
+def fista(A, yd, fhat, alpha, beta, ua, ub, iters=20000, tol=1e-15):
+    """min_u 1/2|A^-1(u+fhat) - yd|^2 + alpha/2|u|^2 + beta|u|_1, ua <= u <= ub."""
+    Ainv = np.linalg.inv(A)
+    G = Ainv.T @ Ainv
+    L = np.linalg.eigvalsh(G).max() + alpha
+    c = Ainv.T @ (Ainv @ fhat - yd)
+    u = np.zeros(A.shape[0]); z = u.copy(); t = 1.0
+    for _ in range(iters):
+        grad = G @ z + c + alpha * z
+        q = z - grad / L
+        un = np.clip(np.sign(q) * np.maximum(np.abs(q) - beta / L, 0.0), ua, ub)
+        tn = 0.5 * (1 + math.sqrt(1 + 4 * t * t))
+        z = un + ((t - 1) / tn) * (un - u)
+        if np.abs(un - u).max() < tol:
+            u = un
+            break
+        u, t = un, tn
+    return u, Ainv @ (u + fhat)
+
+
+def active_set_qp(A, yd, fhat, alpha, beta, ua, ub, ya=None, yb=None):
+    """Exhaustive active-set solution of the tiny QP in (y, u).
+
+    Each node's control is at u_a, free negative, zero, free positive or at
+    u_b; each state (with bounds) is at y_a, free or at y_b.  For each
+    pattern the equality-constrained QP is solved and the unique pattern
+    whose solution is primal and dual feasible is returned."""
+    n = A.shape[0]
+    u_states = range(5)
+    y_states = range(3) if ya is not None else [1]
+    best = None
+    for up in itertools.product(u_states, repeat=n):
+        for yp in itertools.product(y_states, repeat=n):
+            # unknowns [y (n), u (n), p (n)]; KKT of the pattern
+            K = np.zeros((3 * n, 3 * n)); r = np.zeros(3 * n)
+            # state equation: A y - u = fhat
+            K[2 * n:, :n] = A; K[2 * n:, n:2 * n] = -np.eye(n); r[2 * n:] = fhat
+            for i in range(n):
+                # y row: y - yd + A^T p (+ multiplier) = 0, or y fixed
+                if yp[i] == 1:
+                    K[i, i] = 1.0; K[i, 2 * n:] = A[:, i]; r[i] = yd[i]
+                else:
+                    K[i, i] = 1.0; r[i] = ya[i] if yp[i] == 0 else yb[i]
+                j = n + i
+                if up[i] == 0:
+                    K[j, j] = 1.0; r[j] = ua[i]
+                elif up[i] == 4:
+                    K[j, j] = 1.0; r[j] = ub[i]
+                elif up[i] == 2:
+                    K[j, j] = 1.0; r[j] = 0.0
+                else:  # free: alpha u + beta sign - p = 0
+                    K[j, j] = alpha; K[j, 2 * n + i] = -1.0
+                    r[j] = -beta if up[i] == 3 else beta
+            try:
+                sol = np.linalg.solve(K, r)
+            except np.linalg.LinAlgError:
+                continue
+            y, u, p = sol[:n], sol[n:2 * n], sol[2 * n:]
+            ok = True
+            tol = 1e-10
+            for i in range(n):
+                s = alpha * u[i] - p[i]  # must equal -beta*d|u| - normal cone
+                if up[i] == 0:      # at u_a < 0: multiplier s - beta >= 0
+                    ok &= s - beta >= -tol
+                elif up[i] == 4:    # at u_b > 0: multiplier -(s + beta) >= 0
+                    ok &= s + beta <= tol
+                elif up[i] == 2:
+                    ok &= abs(s) <= beta + tol
+                elif up[i] == 1:
+                    ok &= u[i] < tol and u[i] > ua[i] - tol
+                else:
+                    ok &= u[i] > -tol and u[i] < ub[i] + tol
+                if ya is not None:
+                    g = y[i] - yd[i] + A[:, i] @ p  # = lambda_a - lambda_b
+                    if yp[i] == 1:
+                        ok &= ya[i] - tol <= y[i] <= yb[i] + tol
+                    elif yp[i] == 0:
+                        ok &= g >= -tol
+                    else:
+                        ok &= g <= tol
+                if not ok:
+                    break
+            ok &= np.all(u >= ua - tol) and np.all(u <= ub + tol)
+            if ok:
+                if best is not None and np.abs(best[1] - u).max() > 1e-8:
+                    raise AssertionError("two KKT points found for a strongly convex QP")
+                best = (y, u)
+    return best

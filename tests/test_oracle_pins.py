@@ -1,0 +1,310 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics
+(closed forms, brute force, invariants), not against the oracle itself."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle.fd import discretize, operator_matrix, rhs_offset
+from oracle.ipm import (IPMOptions, initial_state, multiplier_steps, newton_solve,
+                        barrier_diagonals, ipm_step)
+from tests import _indep as I
+
+
+def _coords(dim, N, with_boundary=False):
+    return (W.all_coords if with_boundary else W.interior_coords)(dim, N)
+
+
+# ---------------------------------------------------------------- operators
+
+@pytest.mark.parametrize("dim,N", [(2, 7), (2, 15), (3, 7)])
+def test_poisson_stencil_exact_on_cubics(dim, N):
+    """The 2d+1 point Laplacian is exact on cubic polynomials: A_II q_I + A_IB q_B = -Lap q."""
+    def q(x):
+        if dim == 2:
+            return x[0] ** 3 - 2 * x[0] ** 2 * x[1] + x[1] ** 3 + 0.5 * x[0] * x[1] + 1
+        return x[0] ** 3 + x[1] ** 2 * x[2] - x[2] ** 3 + x[0] * x[1] + 2
+
+    def neg_lap(x):
+        if dim == 2:
+            return -(6 * x[0] - 4 * x[1] + 6 * x[1])
+        return -(6 * x[0] + 2 * x[2] - 6 * x[2])
+
+    A = operator_matrix(dim, N)
+    g = q(_coords(dim, N, True))
+    xi = _coords(dim, N)
+    lhs = A @ q(xi) - rhs_offset(dim, N, "poisson", 1.0, g)
+    np.testing.assert_allclose(lhs, neg_lap(xi), rtol=1e-9, atol=1e-9)
+
+
+@pytest.mark.parametrize("N", [7, 31])
+def test_convdiff_upwind_exact_on_linears(N):
+    """Upwind differences are exact on linear functions: A q = w . grad q (Sec. 6.3 wind)."""
+    eps = 1.0 / 200
+    q = lambda x: 1.0 + 2.0 * x[0] - 3.0 * x[1]
+    A = operator_matrix(2, N, "convdiff", eps)
+    g = q(_coords(2, N, True))
+    xi = _coords(2, N)
+    lhs = A @ q(xi) - rhs_offset(2, N, "convdiff", eps, g)
+    w1, w2 = I.wind(xi[0], xi[1])
+    np.testing.assert_allclose(lhs, 2.0 * w1 - 3.0 * w2, rtol=1e-10, atol=1e-9)
+
+
+@pytest.mark.parametrize("pde,dim,N", [("poisson", 2, 5), ("poisson", 3, 3), ("convdiff", 2, 5)])
+def test_operator_matches_node_by_node_assembly(pde, dim, N):
+    A = operator_matrix(dim, N, pde, 0.05).toarray()
+    np.testing.assert_allclose(A, I.dense_operator(dim, N, pde, 0.05), rtol=1e-14, atol=1e-9)
+
+
+@pytest.mark.parametrize("dim,N,ks", [(2, 31, (1, 1)), (2, 15, (3, 2)), (3, 7, (1, 2, 3))])
+def test_poisson_sine_eigenpairs(dim, N, ks):
+    A = operator_matrix(dim, N)
+    phi = I.sine_mode(dim, N, ks)
+    lam = I.sine_eigenvalue(dim, N, ks)
+    np.testing.assert_allclose(A @ phi, lam * phi, rtol=1e-12, atol=1e-9 * lam)
+
+
+# ---------------------------------------------------------------- Newton system
+
+def _tiny_problem(N=3, state_bounds=True, seed=3):
+    rng = np.random.default_rng(seed)
+    p = W.poisson2d_small(seed=seed, N=N)
+    n = p.n
+    p.u_a = -rng.uniform(0.5, 2.0, n)
+    p.u_b = rng.uniform(0.5, 2.0, n)
+    p.y_d = rng.normal(0, 1, n)
+    if state_bounds:
+        p.y_a = -rng.uniform(0.1, 0.5, n)
+        p.y_b = rng.uniform(0.1, 0.5, n)
+    return p
+
+
+def test_reduced_newton_matches_full_7x7_system():
+    """Eq. (NewtonSystem) + eqs. (zupdate1-4) reproduce the direct solve of eq. (7by7)."""
+    p = _tiny_problem()
+    disc = discretize(p)
+    opts = IPMOptions()
+    st = initial_state(p, opts)
+    # move away from the starting point so that all blocks are generic
+    st, _ = ipm_step(p, disc, st, opts, 0.2, "full")
+    mu = 0.05
+    n = p.n
+    A = disc.A.toarray()
+    a, b = p.alpha, p.beta
+    zaw, zbw, zav, zbv = np.zeros(n), p.u_b, np.zeros(n), -p.u_a
+    # unknowns: dy, dz=[dw,dv], dp, dlya, dlyb, dlza=[dlwa,dlva], dlzb=[dlwb,dlvb]
+    In, I2 = np.eye(n), np.eye(2 * n)
+    Mt = np.block([[In, -In], [-In, In]])
+    Mb = np.hstack([In, -In])
+    Db = np.hstack([In, In])
+    z = np.concatenate([st.w, st.v]); za = np.concatenate([zaw, zav]); zb = np.concatenate([zbw, zbv])
+    lza = np.concatenate([st.lwa, st.lva]); lzb = np.concatenate([st.lwb, st.lvb])
+    Z = np.zeros
+    K = np.block([
+        [In, Z((n, 2 * n)), A.T, -In, In, Z((n, 2 * n)), Z((n, 2 * n))],
+        [Z((2 * n, n)), a * Mt, -Mb.T, Z((2 * n, n)), Z((2 * n, n)), -I2, I2],
+        [A, -Mb, Z((n, n)), Z((n, n)), Z((n, n)), Z((n, 2 * n)), Z((n, 2 * n))],
+        [np.diag(st.lya), Z((n, 2 * n)), Z((n, n)), np.diag(st.y - p.y_a), Z((n, n)), Z((n, 2 * n)), Z((n, 2 * n))],
+        [-np.diag(st.lyb), Z((n, 2 * n)), Z((n, n)), Z((n, n)), np.diag(p.y_b - st.y), Z((n, 2 * n)), Z((n, 2 * n))],
+        [Z((2 * n, n)), np.diag(lza), Z((2 * n, n)), Z((2 * n, n)), Z((2 * n, n)), np.diag(z - za), Z((2 * n, 2 * n))],
+        [Z((2 * n, n)), -np.diag(lzb), Z((2 * n, n)), Z((2 * n, n)), Z((2 * n, n)), Z((2 * n, 2 * n)), np.diag(zb - z)],
+    ])
+    rhs = -np.concatenate([
+        st.y - p.y_d + A.T @ st.p - st.lya + st.lyb,
+        a * Mt @ z + b * Db.T @ np.ones(n) - Mb.T @ st.p - lza + lzb,
+        A @ st.y - Mb @ z - disc.f_hat,
+        (st.y - p.y_a) * st.lya - mu, (p.y_b - st.y) * st.lyb - mu,
+        (z - za) * lza - mu, (zb - z) * lzb - mu,  # lambda_{z,b} in the last block (reading R6)
+    ])
+    sol = np.linalg.solve(K, rhs)
+    dy, dz, dp = sol[:n], sol[n:3 * n], sol[3 * n:4 * n]
+    for mode in ("full", "schur"):
+        ry, rw, rv, rp = newton_solve(p, disc, st, mu, mode)
+        np.testing.assert_allclose(ry, dy, rtol=1e-9, atol=1e-11)
+        np.testing.assert_allclose(np.concatenate([rw, rv]), dz, rtol=1e-9, atol=1e-11)
+        np.testing.assert_allclose(rp, dp, rtol=1e-9, atol=1e-11)
+        dl = multiplier_steps(p, st, ry, rw, rv, mu)
+        off = 4 * n
+        np.testing.assert_allclose(dl["lya"], sol[off:off + n], rtol=1e-8, atol=1e-10)
+        np.testing.assert_allclose(dl["lyb"], sol[off + n:off + 2 * n], rtol=1e-8, atol=1e-10)
+        np.testing.assert_allclose(np.concatenate([dl["lwa"], dl["lva"]]), sol[off + 2 * n:off + 4 * n], rtol=1e-8, atol=1e-10)
+        np.testing.assert_allclose(np.concatenate([dl["lwb"], dl["lvb"]]), sol[off + 4 * n:off + 6 * n], rtol=1e-8, atol=1e-10)
+
+
+def test_schur_complement_formula():
+    """Eq. (Schur) with M = I equals B A^-1 B^T computed by dense inversion."""
+    p = _tiny_problem(N=3)
+    disc = discretize(p)
+    opts = IPMOptions()
+    st = initial_state(p, opts)
+    st, _ = ipm_step(p, disc, st, opts, 0.2)
+    ty, tw, tv = barrier_diagonals(p, st)
+    n, a = p.n, p.alpha
+    A = disc.A.toarray()
+    In = np.eye(n)
+    Ablk = np.block([[np.diag(1 + ty), np.zeros((n, 2 * n))],
+                     [np.zeros((2 * n, n)), np.block([[a * In + np.diag(tw), -a * In], [-a * In, a * In + np.diag(tv)]])]])
+    B = np.hstack([A, -In, In])
+    S = B @ np.linalg.solve(Ablk, B.T)
+    S_paper = A @ np.diag(1 / (1 + ty)) @ A.T + In / a - np.linalg.inv(np.diag(1 / tw + 1 / tv) + In / a) / a ** 2
+    np.testing.assert_allclose(S, S_paper, rtol=1e-10, atol=1e-10)
+
+
+def test_schur_approximation_lower_bound_half():
+    """Theorem (Sec. 4.2): lambda(S_hat^-1 S) >= 1/2 for lumped mass, along an IPM run."""
+    p = _tiny_problem(N=5, state_bounds=True)
+    disc = discretize(p)
+    opts = IPMOptions()
+    st = initial_state(p, opts)
+    n, a = p.n, p.alpha
+    A = disc.A.toarray()
+    for k in range(6):
+        ty, tw, tv = barrier_diagonals(p, st)
+        sig = (tw + tv) / (a * (tw + tv) + tw * tv)
+        S = A @ np.diag(1 / (1 + ty)) @ A.T + np.diag(sig)
+        Mh = np.diag(np.sqrt(sig * (1 + ty)))
+        Sh = (A + Mh) @ np.diag(1 / (1 + ty)) @ (A + Mh).T
+        ev = np.linalg.eigvals(np.linalg.solve(Sh, S)).real
+        assert ev.min() >= 0.5 - 1e-9
+        st, _ = ipm_step(p, disc, st, opts, st.mu * 0.2)
+
+
+# ---------------------------------------------------------------- optimum pins
+
+def test_zero_control_threshold():
+    """u* = 0 iff beta >= |A^-1 y_d|_inf (KKT with u = 0, y = 0): single sine mode, closed form."""
+    N = 31
+    base = W.poisson2d_small(seed=1, N=N)
+    amp = base.meta["amplitude"]
+    lam = I.sine_eigenvalue(2, N, (1, 1))
+    thr = abs(amp) / lam  # max |phi_11| = 1 on this grid (x = 1/2 is a node)
+    opts = IPMOptions(eps_p=1e-10, eps_d=1e-10, eps_c=1e-10)
+    above = base.copy(); above.beta = 1.02 * thr
+    r = oracle.solve(above, opts)
+    assert r.status == "converged"
+    assert np.abs(r.u).max() < 1e-6
+    below = base.copy(); below.beta = 0.98 * thr
+    r = oracle.solve(below, opts)
+    assert np.abs(r.u).max() > 1e-2
+
+
+def test_beta_zero_single_mode_closed_form():
+    """beta = 0, inactive bounds: y = phi/(1+alpha lam^2), u = lam y, p = alpha u (times amplitude)."""
+    N = 15
+    p = W.poisson2d_small(seed=2, N=N)
+    p.beta = 0.0
+    p.u_a[:] = -100.0; p.u_b[:] = 100.0
+    amp = p.meta["amplitude"]
+    lam = I.sine_eigenvalue(2, N, (1, 1))
+    phi = I.sine_mode(2, N, (1, 1))
+    r = oracle.solve(p, IPMOptions(eps_p=1e-11, eps_d=1e-11, eps_c=1e-11))
+    y = amp * phi / (1 + p.alpha * lam ** 2)
+    np.testing.assert_allclose(r.y, y, rtol=0, atol=1e-8 * np.abs(y).max())
+    np.testing.assert_allclose(r.u, lam * y, rtol=0, atol=1e-8 * np.abs(lam * y).max())
+    np.testing.assert_allclose(r.p, p.alpha * lam * y, rtol=0, atol=1e-8 * np.abs(lam * y).max())
+
+
+@pytest.mark.parametrize("pde", ["poisson", "convdiff"])
+def test_matches_proximal_gradient_on_small_grid(pde):
+    """The IPM optimum equals an independent FISTA solution of the reduced problem in u."""
+    N = 7
+    p = W.poisson2d_small(seed=4, N=N)
+    if pde == "convdiff":
+        p.pde, p.eps = "convdiff", 1.0 / 50
+    rng = np.random.default_rng(9)
+    # four sine modes scaled so that zero, free and both bound-active controls all occur
+    p.y_d = W.sine_modes(rng, 2, N, 4, 3)[0] * (4.0 if pde == "poisson" else 0.5)
+    p.beta = 3e-3
+    p.u_a[:] = -1.5; p.u_b[:] = 1.0
+    A = I.dense_operator(2, N, p.pde, p.eps)
+    u_ref, y_ref = I.fista(A, p.y_d, np.zeros(p.n), p.alpha, p.beta, p.u_a, p.u_b)
+    r = oracle.solve(p, IPMOptions(eps_p=1e-12, eps_d=1e-12, eps_c=1e-12))
+    assert r.status == "converged"
+    assert (np.abs(u_ref) < 1e-12).sum() > 0 and (np.abs(u_ref - 1.0) < 1e-12).sum() > 0
+    assert (np.abs(u_ref + 1.5) < 1e-12).sum() > 0
+    np.testing.assert_allclose(r.u, u_ref, rtol=0, atol=1e-7)
+    np.testing.assert_allclose(r.y, y_ref, rtol=0, atol=1e-8)
+
+
+@pytest.mark.parametrize("state_bounds", [False, True])
+def test_matches_exhaustive_active_set(state_bounds):
+    """Brute force over all active sets of a 2x2 grid (with and without state bounds)."""
+    N = 2
+    p = W.poisson2d_small(seed=5, N=N)
+    rng = np.random.default_rng(11)
+    p.y_d = rng.normal(0, 3, p.n)
+    p.f = rng.normal(0, 20, p.n)
+    p.alpha = 2e-2
+    p.beta = 0.05
+    p.u_a = -rng.uniform(2, 8, p.n); p.u_b = rng.uniform(2, 8, p.n)
+    if state_bounds:
+        p.y_a = np.full(p.n, -0.35); p.y_b = np.full(p.n, 0.4)
+    A = I.dense_operator(2, N)
+    ref = I.active_set_qp(A, p.y_d, p.f, p.alpha, p.beta, p.u_a, p.u_b, p.y_a, p.y_b)
+    assert ref is not None
+    r = oracle.solve(p, IPMOptions(eps_p=1e-12, eps_d=1e-12, eps_c=1e-12))
+    assert r.status == "converged"
+    np.testing.assert_allclose(r.u, ref[1], rtol=0, atol=1e-7)
+    np.testing.assert_allclose(r.y, ref[0], rtol=0, atol=1e-8)
+
+
+# ---------------------------------------------------------------- invariants
+
+def test_primal_residual_contracts_by_one_minus_alpha_P():
+    """A y - (w - v) - f_hat is linear: after an exact Newton step it scales by (1 - alpha_P)."""
+    p = W.poisson2d_small(seed=6, N=15)
+    p.u_a[:] = -1.0; p.u_b[:] = 3.0          # asymmetric box: u^0 = 1, so xi_p^0 != 0
+    disc = discretize(p)
+    opts = IPMOptions()
+    st = initial_state(p, opts)
+    for k in range(5):
+        xp0 = disc.A @ st.y - (st.w - st.v) - disc.f_hat
+        st, info = ipm_step(p, disc, st, opts, st.mu * opts.sigma)
+        xp1 = disc.A @ st.y - (st.w - st.v) - disc.f_hat
+        np.testing.assert_allclose(xp1, (1 - info["alpha_P"]) * xp0, rtol=1e-6, atol=1e-12 * np.abs(xp0).max() + 1e-13)
+
+
+def test_paper_convergence_history_fixture():
+    """Fig. convh: mu^k = 0.25^(k-1) from mu_0 = 1, and xi_p shrinks by 1 - alpha_0 = 0.005 per step.
+
+    The oracle on its own problem reproduces both facts at sigma = 0.25."""
+    rows = np.loadtxt(__file__.replace("test_oracle_pins.py", "golden/convh.txt"))
+    k, mu, xip = rows[:, 0], rows[:, 1], rows[:, 2]
+    np.testing.assert_allclose(mu, 0.25 ** (k - 1), rtol=2e-3)
+    np.testing.assert_allclose(xip[1:5] / xip[:4], 0.005, rtol=2e-3)
+    p = W.poisson2d_small(seed=0, N=15)
+    p.u_a[:] = -2.0; p.u_b[:] = 1.5           # the paper's box (Sec. 6.1): u^0 != 0, xi_p^0 != 0
+    r = oracle.solve(p, IPMOptions(sigma=0.25))
+    mus = np.array([h["mu"] for h in r.history])
+    np.testing.assert_allclose(mus, 0.25 ** np.arange(len(mus)), rtol=1e-14)
+    for h0, h1 in zip(r.history[:3], r.history[1:4]):
+        if h0["alpha_P"] == 0.995:
+            assert h1["xi_p"] == pytest.approx(0.005 * h0["xi_p"], rel=1e-6)
+
+
+def test_sign_symmetry():
+    """Negating (y_d, f, bounds) negates (y, u) (the problem is odd under this map)."""
+    p = W.convdiff2d_255(seed=1, N=15)
+    p.u_a[:] = -1.0; p.u_b[:] = 2.0
+    p.y_a = np.full(p.n, -0.3); p.y_b = np.full(p.n, 0.5)
+    q = p.copy()
+    q.y_d = -p.y_d
+    q.u_a, q.u_b = -p.u_b, -p.u_a
+    q.y_a, q.y_b = -p.y_b, -p.y_a
+    r1 = oracle.solve(p); r2 = oracle.solve(q)
+    np.testing.assert_allclose(r2.u, -r1.u, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(r2.y, -r1.y, rtol=0, atol=1e-12)
+
+
+def test_nli_at_sigma_02_and_final_mu():
+    """Sec. 6.1 (Table caption): sigma = 0.2 gives 9 IPM iterations ending at mu = 5e-7
+    when the iterates stay centred; the reading R1 stops exactly there when
+    every step is a full (alpha_0-scaled) step."""
+    p = W.poisson2d_small(seed=0, N=15)
+    p.beta = 0.0
+    p.u_a[:] = -100.0; p.u_b[:] = 100.0
+    r = oracle.solve(p, IPMOptions(sigma=0.2))
+    assert r.nli == 9
+    assert r.state.mu == pytest.approx(5.12e-7, rel=1e-12)
