@@ -1,0 +1,224 @@
+/*
+ * libipmpde — interior point method for sparse (L1), box-constrained
+ * PDE-constrained optimal control on one AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Pearson, Porcelli, Stoll, arXiv 1806.05896, Sec. 1, eqs. (pb),
+ * (eq:lap), (box), (boxs)), in the finite-difference, unit-mass form of
+ * Sec. 2, eq. (pb_fe) with M = D = I:
+ *
+ *   minimize  1/2 |y - y_d|^2 + alpha/2 |u|^2 + beta |u|_1
+ *   s.t.      A y - u = f_hat,  u_a <= u <= u_b,  [y_a <= y <= y_b]
+ *
+ * where A is the 5-point (2D) or 7-point (3D) Laplacian, or (2D) the
+ * upwinded convection-diffusion operator -eps Lap + w.grad with the wind
+ * w = (2 x2 (1 - x1^2), -2 x1 (1 - x2^2)) of Sec. 6.3; f_hat = f minus the
+ * boundary columns of A applied to the Dirichlet data g.
+ *
+ * The solver is the path-following method of the Appendix (Algorithm A.1)
+ * with the l1 splitting u = w - v (Sec. 2, eq. (split)).  Each Newton system
+ * (Sec. 3, eq. (NewtonSystem)) is solved by preconditioned MINRES with the
+ * block-diagonal preconditioner P_D, or by FGMRES with the block-triangular
+ * P_T (Sec. 4, the last two displayed preconditioners), whose Schur block is
+ * the matching approximation S_hat = (A + M_hat)(I + Theta_y)^-1 (A + M_hat)^T
+ * (Sec. 4.2, eq. (SchurApprox)) applied with geometric multigrid V-cycles.
+ *
+ * Conventions for every entry point:
+ *   - Grid: N = 2^k - 1 interior points per axis (k >= 2), h = 1/(N+1);
+ *     n = N^dim unknowns per field.
+ *   - Layout: lexicographic with x1 fastest; node (i1..id) at x = (i1 h, ...).
+ *     Boundary data g has (N+2)^dim entries in the same ordering including the
+ *     boundary nodes; its interior entries are ignored.
+ *   - Host arrays passed to problem_create are copied; the caller keeps
+ *     ownership and may free them after the call.  Device arrays passed to
+ *     the low-level entry points are owned by the caller.
+ *   - All device work is enqueued on the stream argument (NULL = the null
+ *     stream); calls that return host results synchronize that stream.
+ *   - Return value: IPMPDE_OK or one of the error codes below;
+ *     ipmpde_last_error() gives a thread-local message for the last failure.
+ *   - A problem handle must not be used by two threads at once.
+ */
+#ifndef IPMPDE_H
+#define IPMPDE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void* ipmpde_stream; /* a hipStream_t */
+
+enum {
+  IPMPDE_OK = 0,
+  IPMPDE_EINVAL = 1,        /* bad shape, NaN/Inf input, infeasible bounds, bad option */
+  IPMPDE_ENOMEM = 2,        /* device allocation failed */
+  IPMPDE_EDEVICE = 3,       /* a HIP runtime error */
+  IPMPDE_ENOTCONVERGED = 4, /* IPM iteration limit reached; results are queryable */
+  IPMPDE_EKRYLOV = 5,       /* a Krylov solve hit its iteration limit (recorded in stats) */
+  IPMPDE_EBREAKDOWN = 6     /* NaN/Inf in the iterates or a collapsed step length */
+};
+
+enum { IPMPDE_POISSON = 0, IPMPDE_CONVDIFF = 1 };
+enum { IPMPDE_MINRES = 0, IPMPDE_FGMRES = 1 };
+enum { IPMPDE_PD = 0, IPMPDE_PT = 1 };
+enum { IPMPDE_FP64 = 0, IPMPDE_FP32 = 1 };
+
+/* Fields for ipmpde_query / ipmpde_set_field (each n doubles). */
+enum {
+  IPMPDE_FIELD_U = 0, IPMPDE_FIELD_Y = 1, IPMPDE_FIELD_P = 2, IPMPDE_FIELD_W = 3, IPMPDE_FIELD_V = 4,
+  IPMPDE_FIELD_LAM_YA = 5, IPMPDE_FIELD_LAM_YB = 6, IPMPDE_FIELD_LAM_WA = 7, IPMPDE_FIELD_LAM_WB = 8,
+  IPMPDE_FIELD_LAM_VA = 9, IPMPDE_FIELD_LAM_VB = 10,
+  IPMPDE_FIELD_DY = 11, IPMPDE_FIELD_DW = 12, IPMPDE_FIELD_DV = 13, IPMPDE_FIELD_DP = 14,
+  IPMPDE_FIELD_THETA_Y = 15, IPMPDE_FIELD_THETA_W = 16, IPMPDE_FIELD_THETA_V = 17,
+  IPMPDE_FIELD_FHAT = 18
+};
+
+typedef struct { int dim; int n; } ipmpde_grid;          /* dim in {2,3}; n = N interior points per axis */
+typedef struct { int kind; double eps; } ipmpde_pde;     /* kind IPMPDE_POISSON | IPMPDE_CONVDIFF (2D only), eps > 0 */
+
+/* Solver options.  ipmpde_default_options fills the defaults named here. */
+typedef struct {
+  double sigma;        /* barrier reduction factor (0,1); default 0.2 (Sec. 6.1) */
+  double alpha0;       /* fraction to the boundary; default 0.995 (Sec. 6) */
+  double eps_p, eps_d, eps_c; /* stopping tolerances on inf-norms; default 1e-6 (Sec. 6) */
+  double mu0;          /* initial barrier parameter; default 1 */
+  int ipm_maxit;       /* default 200 */
+  int fixed_nli;       /* > 0: take exactly this many IPM steps (parity runs); default 0 */
+  int krylov;          /* IPMPDE_MINRES (default) | IPMPDE_FGMRES */
+  int precond;         /* IPMPDE_PD (default) | IPMPDE_PT (requires FGMRES) */
+  int restart;         /* FGMRES restart length; default 30 */
+  double krylov_tol;   /* relative unpreconditioned residual |b - K x| / |b|; default 1e-10 (Sec. 6) */
+  int krylov_maxit;    /* default 500 */
+  int vcycles;         /* V-cycles per multigrid solve; default 1 */
+  int nu_pre, nu_post; /* Jacobi sweeps; default 2, 2 (MINRES needs nu_pre == nu_post) */
+  double omega;        /* Jacobi damping; 0 = default (0.8 in 2D, 6/7 in 3D) */
+  int mg_precision;    /* IPMPDE_FP64 | IPMPDE_FP32 (default): precision of the V-cycles */
+  int chunk;           /* Krylov iterations per device-side batch between host checks; default 8 */
+  int use_graphs;      /* capture Krylov chunks in HIP graphs; default 1 */
+} ipmpde_options;
+
+#define IPMPDE_MAX_HIST 256
+
+/* Per-solve statistics.  hist_* hold one entry per IPM iteration k (the
+ * measures at the start of iteration k, and for k < nli the Krylov
+ * iterations and step lengths of that iteration). */
+typedef struct {
+  int status;                /* IPMPDE_OK, IPMPDE_ENOTCONVERGED, ... */
+  int nli;                   /* IPM iterations taken */
+  int krylov_its;            /* total Krylov iterations over the solve */
+  int krylov_fail;           /* IPM iterations whose Krylov solve missed krylov_tol */
+  double xi_p, xi_d, xi_c;   /* final inf-norm measures */
+  double mu;                 /* final barrier parameter */
+  double solve_ms;           /* host wall time of the last ipmpde_solve */
+  int hist_len;
+  int hist_krylov[IPMPDE_MAX_HIST];
+  double hist_mu[IPMPDE_MAX_HIST];
+  double hist_xi_p[IPMPDE_MAX_HIST], hist_xi_d[IPMPDE_MAX_HIST], hist_xi_c[IPMPDE_MAX_HIST];
+  double hist_alpha_p[IPMPDE_MAX_HIST], hist_alpha_d[IPMPDE_MAX_HIST];
+  double hist_krylov_relres[IPMPDE_MAX_HIST]; /* true relative residual reached */
+} ipmpde_stats;
+
+typedef struct ipmpde_problem ipmpde_problem;
+
+/* Version string of the library. */
+const char* ipmpde_version(void);
+
+/* Thread-local description of the last error (never NULL). */
+const char* ipmpde_last_error(void);
+
+/* Fill *opts with the defaults documented above. */
+int ipmpde_default_options(ipmpde_options* opts);
+
+/* Optional device allocator (e.g. a framework's caching allocator).  Both
+ * callbacks NULL restores hipMalloc/hipFree.  Affects problems created
+ * afterwards. */
+typedef void* (*ipmpde_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*ipmpde_free_fn)(void* ptr, void* ctx);
+int ipmpde_set_allocator(ipmpde_alloc_fn alloc, ipmpde_free_fn free_, void* ctx);
+
+/* Create a problem instance (Sec. 1 and Sec. 2 data).  u_a, u_b, y_d are
+ * required (n values each) with u_a < 0 < u_b elementwise; y_a, y_b are
+ * both NULL (no state bounds) or both given with y_a < y_b; f may be NULL
+ * (zero); g may be NULL (zero), else (N+2)^dim values.  alpha > 0, beta >= 0.
+ * Returns IPMPDE_EINVAL for bad shapes, N != 2^k - 1, NaN/Inf, or bounds
+ * that violate the above; IPMPDE_ENOMEM if device memory runs out. */
+int ipmpde_problem_create(const ipmpde_grid* grid, const ipmpde_pde* pde, double alpha, double beta,
+                          const double* u_a, const double* u_b, const double* y_a, const double* y_b,
+                          const double* y_d, const double* f, const double* g, ipmpde_problem** out);
+
+void ipmpde_problem_destroy(ipmpde_problem* prob);
+
+/* Bytes of device memory a problem of this shape uses with these options. */
+size_t ipmpde_footprint_bytes(const ipmpde_grid* grid, const ipmpde_pde* pde, int has_state_bounds,
+                              const ipmpde_options* opts);
+
+/* Run the interior point method (Algorithm A.1) from the standard starting
+ * point (box midpoints, centred multipliers, mu = mu0).  opts NULL means
+ * defaults.  Returns IPMPDE_OK on convergence, else an error code; the
+ * iterates stay queryable either way. */
+int ipmpde_solve(ipmpde_problem* prob, const ipmpde_options* opts, ipmpde_stream stream);
+
+/* Copy a field (n doubles) to host memory; count must equal n. */
+int ipmpde_query(const ipmpde_problem* prob, int field, double* host_out, size_t count);
+
+/* Overwrite an iterate field (Y, P, W, V, LAM_*) from host memory, e.g. to
+ * continue from a given IPM state; count must equal n. */
+int ipmpde_set_field(ipmpde_problem* prob, int field, const double* host_in, size_t count);
+
+/* Reset the iterates to the standard starting point with barrier mu0. */
+int ipmpde_reset(ipmpde_problem* prob, const ipmpde_options* opts, ipmpde_stream stream);
+
+/* One IPM iteration from the current iterates with barrier parameter
+ * mu_new (Algorithm A.1 loop body): Newton solve, multiplier steps
+ * (eqs. (zupdate1)-(zupdate4)), step lengths and update.  The Newton
+ * direction stays queryable (FIELD_DY..DP).  alpha_p/alpha_d/krylov_its/
+ * relres may be NULL. */
+int ipmpde_ipm_step(ipmpde_problem* prob, const ipmpde_options* opts, double mu_new, ipmpde_stream stream,
+                    double* alpha_p, double* alpha_d, int* krylov_its, double* relres);
+
+/* Solve only the Newton system eq. (NewtonSystem) at the current iterates
+ * and barrier mu_new; the direction is queryable as FIELD_DY..DP. */
+int ipmpde_newton_direction(ipmpde_problem* prob, const ipmpde_options* opts, double mu_new,
+                            ipmpde_stream stream, int* krylov_its, double* relres);
+
+/* Feasibility and complementarity measures of the current iterates
+ * (inf-norms of eq. (prdu) and of the products of eq. (gap)). */
+int ipmpde_measures(ipmpde_problem* prob, ipmpde_stream stream, double* xi_p, double* xi_d, double* xi_c);
+
+int ipmpde_get_stats(const ipmpde_problem* prob, ipmpde_stats* out);
+
+/* ---- low-level operators on caller-owned device arrays (FP64) ---- */
+
+/* y = A x (transpose = 0) or y = A^T x (transpose = 1), n values each. */
+int ipmpde_apply_operator(const ipmpde_problem* prob, int transpose, const double* x_dev, double* y_dev,
+                          ipmpde_stream stream);
+
+/* y = K x for the 4n saddle matrix of eq. (NewtonSystem) at the current
+ * barrier diagonals (set by the last Newton setup); blocks [y; w; v; p]. */
+int ipmpde_apply_saddle(ipmpde_problem* prob, const double* x_dev, double* y_dev, ipmpde_stream stream);
+
+/* y = P^-1 x for the preconditioner selected by opts (P_D or P_T) at the
+ * current barrier diagonals; 4n values each. */
+int ipmpde_apply_precond(ipmpde_problem* prob, const ipmpde_options* opts, const double* x_dev, double* y_dev,
+                         ipmpde_stream stream);
+
+/* Prepare barrier diagonals, preconditioner data and the Newton right-hand
+ * side at barrier mu_new (needed before apply_saddle/apply_precond). */
+int ipmpde_newton_setup(ipmpde_problem* prob, const ipmpde_options* opts, double mu_new, ipmpde_stream stream);
+
+/* Copy the current Newton right-hand side (4n doubles) to host memory. */
+int ipmpde_query_rhs(const ipmpde_problem* prob, double* host_out, size_t count);
+
+/* Time one hot-path kernel over `reps` back-to-back launches on `stream`
+ * with HIP events; *avg_ms receives the mean duration per launch and
+ * *bytes the algorithmic bytes one launch moves.  kernel ids:
+ * 0 saddle matvec, 1 multigrid smoothing sweep (finest level),
+ * 2 Lanczos update + diagonal preconditioner, 3 one V-cycle. */
+int ipmpde_time_kernel(ipmpde_problem* prob, const ipmpde_options* opts, int kernel, int reps,
+                       ipmpde_stream stream, double* avg_ms, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IPMPDE_H */

@@ -1,0 +1,272 @@
+"""Python binding of libipmpde: argument marshalling only."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass, fields
+from typing import Optional
+
+import numpy as np
+
+from . import _lib as L
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "csrc", "libipmpde.hip")
+_INC = os.path.join(os.path.dirname(_HERE), "include")
+
+HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-shared", "-std=c++17", "-Wno-unused-value",
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+
+def library_path() -> str:
+    return L.LIB_PATH
+
+
+def build_library(verbose: bool = False) -> str:
+    """Compile csrc/libipmpde.hip for gfx950 into the package directory."""
+    tmp = L.LIB_PATH + ".tmp"
+    cmd = ["hipcc", *HIPCC_FLAGS, "-I", _INC, "-o", tmp, _SRC]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed:\n" + r.stderr[-4000:])
+    os.replace(tmp, L.LIB_PATH)
+    if verbose:
+        print(" ".join(cmd))
+    return L.LIB_PATH
+
+
+@dataclass
+class Options:
+    """Solver options (defaults as in include/ipmpde.h)."""
+
+    sigma: float = 0.2
+    alpha0: float = 0.995
+    eps_p: float = 1e-6
+    eps_d: float = 1e-6
+    eps_c: float = 1e-6
+    mu0: float = 1.0
+    ipm_maxit: int = 200
+    fixed_nli: int = 0
+    krylov: str = "minres"          # "minres" | "fgmres"
+    precond: str = "pd"             # "pd" | "pt"
+    restart: int = 30
+    krylov_tol: float = 1e-10
+    krylov_maxit: int = 500
+    vcycles: int = 1
+    nu_pre: int = 2
+    nu_post: int = 2
+    omega: float = 0.0
+    mg_precision: str = "fp32"      # "fp32" | "fp64"
+    chunk: int = 8
+    use_graphs: bool = True
+
+    def to_c(self) -> L.COptions:
+        o = L.COptions()
+        for f in fields(self):
+            v = getattr(self, f.name)
+            if f.name == "krylov":
+                v = {"minres": L.MINRES, "fgmres": L.FGMRES}[v]
+            elif f.name == "precond":
+                v = {"pd": L.PD, "pt": L.PT}[v]
+            elif f.name == "mg_precision":
+                v = {"fp64": L.FP64, "fp32": L.FP32}[v]
+            elif f.name == "use_graphs":
+                v = int(bool(v))
+            setattr(o, f.name, v)
+        return o
+
+
+@dataclass
+class Stats:
+    status: int
+    nli: int
+    krylov_its: int
+    krylov_fail: int
+    xi_p: float
+    xi_d: float
+    xi_c: float
+    mu: float
+    solve_ms: float
+    hist_krylov: list
+    hist_mu: list
+    hist_xi_p: list
+    hist_xi_d: list
+    hist_xi_c: list
+    hist_alpha_p: list
+    hist_alpha_d: list
+    hist_krylov_relres: list
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return torch.cuda.current_stream().cuda_stream
+        except Exception:
+            pass
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a, n, name):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if a.shape != (n,):
+        raise ValueError(f"{name} must have {n} entries")
+    return a
+
+
+class Problem:
+    """One problem instance resident on the GPU (ipmpde_problem)."""
+
+    def __init__(self, data=None, *, dim=None, N=None, pde="poisson", eps=1.0, alpha=None, beta=None,
+                 u_a=None, u_b=None, y_a=None, y_b=None, y_d=None, f=None, g=None):
+        if data is not None:
+            dim, N, pde, eps = data.dim, data.N, data.pde, data.eps
+            alpha, beta = data.alpha, data.beta
+            u_a, u_b, y_a, y_b, y_d, f, g = data.u_a, data.u_b, data.y_a, data.y_b, data.y_d, data.f, data.g
+        self._lib = L.load()
+        self.dim, self.N = int(dim), int(N)
+        self.n = self.N ** self.dim
+        n = self.n
+        self._keep = [_f64(u_a, n, "u_a"), _f64(u_b, n, "u_b"), _f64(y_a, n, "y_a"), _f64(y_b, n, "y_b"),
+                      _f64(y_d, n, "y_d"), _f64(f, n, "f"), _f64(g, (self.N + 2) ** self.dim, "g")]
+        grid = L.Grid(self.dim, self.N)
+        kind = {"poisson": L.POISSON, "convdiff": L.CONVDIFF}[pde]
+        pdes = L.Pde(kind, float(eps))
+        h = C.c_void_p()
+        L.check(self._lib.ipmpde_problem_create(C.byref(grid), C.byref(pdes), float(alpha), float(beta),
+                                                *[_ptr(a) for a in self._keep], C.byref(h)))
+        self._h = h
+        self.has_state_bounds = y_a is not None
+        self._keep = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ipmpde_problem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @staticmethod
+    def _opts(opts):
+        return C.byref((opts or Options()).to_c())
+
+    def solve(self, opts: Optional[Options] = None, stream=None, raise_on_error=False) -> int:
+        rc = self._lib.ipmpde_solve(self._h, self._opts(opts), _stream_handle(stream))
+        if raise_on_error:
+            L.check(rc)
+        elif rc not in (L.OK, L.ENOTCONVERGED, L.EKRYLOV, L.EBREAKDOWN):
+            L.check(rc)
+        return rc
+
+    def reset(self, opts: Optional[Options] = None, stream=None):
+        L.check(self._lib.ipmpde_reset(self._h, self._opts(opts), _stream_handle(stream)))
+
+    def ipm_step(self, mu_new: float, opts: Optional[Options] = None, stream=None):
+        aP, aD, rel = C.c_double(), C.c_double(), C.c_double()
+        its = C.c_int()
+        rc = self._lib.ipmpde_ipm_step(self._h, self._opts(opts), float(mu_new), _stream_handle(stream),
+                                       C.byref(aP), C.byref(aD), C.byref(its), C.byref(rel))
+        L.check(rc, allow=(L.EKRYLOV,))
+        return {"alpha_P": aP.value, "alpha_D": aD.value, "krylov_its": its.value, "relres": rel.value, "rc": rc}
+
+    def newton_direction(self, mu_new: float, opts: Optional[Options] = None, stream=None):
+        its, rel = C.c_int(), C.c_double()
+        rc = self._lib.ipmpde_newton_direction(self._h, self._opts(opts), float(mu_new), _stream_handle(stream),
+                                               C.byref(its), C.byref(rel))
+        L.check(rc, allow=(L.EKRYLOV,))
+        return {"krylov_its": its.value, "relres": rel.value, "rc": rc}
+
+    def newton_setup(self, mu_new: float, opts: Optional[Options] = None, stream=None):
+        L.check(self._lib.ipmpde_newton_setup(self._h, self._opts(opts), float(mu_new), _stream_handle(stream)))
+
+    def measures(self, stream=None):
+        a, b, c = C.c_double(), C.c_double(), C.c_double()
+        L.check(self._lib.ipmpde_measures(self._h, _stream_handle(stream), C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
+    def query(self, field: str) -> np.ndarray:
+        out = np.empty(self.n)
+        L.check(self._lib.ipmpde_query(self._h, L.FIELDS[field], out.ctypes.data_as(C.c_void_p), self.n))
+        return out
+
+    def set_field(self, field: str, values):
+        a = _f64(values, self.n, field)
+        L.check(self._lib.ipmpde_set_field(self._h, L.FIELDS[field], a.ctypes.data_as(C.c_void_p), self.n))
+
+    def query_rhs(self) -> np.ndarray:
+        out = np.empty(4 * self.n)
+        L.check(self._lib.ipmpde_query_rhs(self._h, out.ctypes.data_as(C.c_void_p), 4 * self.n))
+        return out
+
+    def stats(self) -> Stats:
+        s = L.CStats()
+        L.check(self._lib.ipmpde_get_stats(self._h, C.byref(s)))
+        k = s.hist_len
+        return Stats(s.status, s.nli, s.krylov_its, s.krylov_fail, s.xi_p, s.xi_d, s.xi_c, s.mu, s.solve_ms,
+                     list(s.hist_krylov[:k]), list(s.hist_mu[:k]), list(s.hist_xi_p[:k]), list(s.hist_xi_d[:k]),
+                     list(s.hist_xi_c[:k]), list(s.hist_alpha_p[:k]), list(s.hist_alpha_d[:k]),
+                     list(s.hist_krylov_relres[:k]))
+
+    # ---- low-level operators on device tensors (torch.float64 on cuda)
+    @staticmethod
+    def _dptr(t):
+        import torch
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise ValueError("expected a contiguous float64 CUDA tensor")
+        return C.c_void_p(t.data_ptr())
+
+    def apply_operator(self, x, transpose: bool = False, stream=None):
+        import torch
+        y = torch.empty_like(x)
+        L.check(self._lib.ipmpde_apply_operator(self._h, int(transpose), self._dptr(x), self._dptr(y),
+                                                _stream_handle(stream)))
+        return y
+
+    def apply_saddle(self, x, stream=None):
+        import torch
+        y = torch.empty_like(x)
+        L.check(self._lib.ipmpde_apply_saddle(self._h, self._dptr(x), self._dptr(y), _stream_handle(stream)))
+        return y
+
+    def apply_precond(self, x, opts: Optional[Options] = None, stream=None):
+        import torch
+        y = torch.empty_like(x)
+        L.check(self._lib.ipmpde_apply_precond(self._h, self._opts(opts), self._dptr(x), self._dptr(y),
+                                               _stream_handle(stream)))
+        return y
+
+    def time_kernel(self, kernel: int, reps: int = 50, opts: Optional[Options] = None, stream=None):
+        ms, nbytes = C.c_double(), C.c_double()
+        L.check(self._lib.ipmpde_time_kernel(self._h, self._opts(opts), int(kernel), int(reps),
+                                             _stream_handle(stream), C.byref(ms), C.byref(nbytes)))
+        return ms.value, nbytes.value
+
+
+def footprint_bytes(dim: int, N: int, pde: str = "poisson", has_state_bounds: bool = False,
+                    opts: Optional[Options] = None) -> int:
+    lib = L.load()
+    grid = L.Grid(dim, N)
+    p = L.Pde({"poisson": L.POISSON, "convdiff": L.CONVDIFF}[pde], 1.0)
+    return int(lib.ipmpde_footprint_bytes(C.byref(grid), C.byref(p), int(has_state_bounds),
+                                          C.byref((opts or Options()).to_c())))

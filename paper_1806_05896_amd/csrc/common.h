@@ -1,0 +1,261 @@
+// Internal definitions shared by the HIP kernels and the host driver of
+// libipmpde.  Everything here is gfx950-only HIP C++.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace ipm {
+
+constexpr int kMaxLev = 16;
+constexpr int kBS = 256;        // threads per block of the elementwise and stencil kernels
+constexpr int kCoarseBS = 512;  // threads of the single-workgroup coarse-grid kernel
+
+// One multigrid level.  Arrays hold T = float or double (the V-cycle precision).
+struct Level {
+  int N;      // interior points per axis
+  int n;      // N^dim
+  double h;   // mesh width 1/(N+1)
+  void* x;    // iterate
+  void* x2;   // second iterate buffer (Jacobi ping-pong)
+  void* b;    // right-hand side
+  void* mh;   // diagonal reaction term M_hat restricted to this level
+};
+
+// Scalars of one Krylov solve, in device memory.
+struct KrylovCtrl {
+  // MINRES recurrence (Paige-Saunders with a symmetric positive definite preconditioner)
+  double gamma_prev, gamma, delta;
+  double c_prev, c, s_prev, s;
+  double eta, eta0;
+  double a1, a2, a3, coef_x, gamma_w;  // coefficients of the pending direction/solution update
+  double est;          // |eta| / eta0: relative preconditioned residual estimate
+  double trigger;      // estimate at which the host checks the true residual
+  double dot_tmp;      // partial result of a split reduction (diagonal blocks)
+  double bnorm;        // |b|_2 of the right-hand side
+  double rnorm;        // |b - K x|_2 from the last true-residual check
+  double rtarget;      // stop when the tracked residual norm falls to this value
+  double rtrack;       // tracked residual norm |r_j|_2 (recurrence)
+  int iter;            // iterations completed
+  int stop;            // 0 running, 1 stopped (converged estimate, breakdown)
+  int pending;         // a direction/solution update is pending
+  int breakdown;       // 1: preconditioner indefinite or NaN
+  // FGMRES
+  double hcol[64];     // current Hessenberg column
+  double g[64];        // rotated residual vector
+  double cs[64], sn[64];
+  double H[64 * 64];   // Hessenberg (column-major, restart+1 rows)
+  double y[64];        // least-squares solution
+  double hpass[64];    // coefficients of the current Gram-Schmidt pass
+  int j;               // Arnoldi steps completed in this cycle
+};
+
+// Everything a kernel needs to know about one problem instance.  Passed by
+// value as a kernel argument.
+struct Inst {
+  int dim, N, n, pde;  // pde: 0 Poisson, 1 convection-diffusion
+  int has_y;
+  double h, eps, alpha, beta;
+  // data (FP64, n values)
+  const double* ua;
+  const double* ub;
+  const double* ya;
+  const double* yb;
+  const double* yd;
+  const double* fhat;
+  // iterates
+  double *y, *w, *v, *p, *lya, *lyb, *lwa, *lwb, *lva, *lvb;
+  // barrier diagonals and preconditioner data
+  double *ty, *tw, *tv, *mh;
+  // reductions
+  double* partials;     // per-block partial results
+  unsigned* counter;    // ticket for the last-block pattern (must be 0 between kernels)
+  KrylovCtrl* ctrl;
+  double* stat;         // small scalar results (measures, step lengths)
+  // multigrid
+  int nlev;             // number of levels (finest 0)
+  int coarse_lev;       // first level handled by the single-workgroup kernel
+  int mg_fp32;          // 1: levels hold float
+  int nu_pre, nu_post, vcycles;
+  double omega;
+  Level lv[kMaxLev];
+  const Level* lvd;     // the same level table in device memory (for loops over levels)
+};
+
+// ---------------------------------------------------------------------------
+// stencils
+
+// Convection-diffusion wind of Sec. 6.3 at x = (x1, x2).
+__device__ __forceinline__ void wind(double x1, double x2, double& w1, double& w2) {
+  w1 = 2.0 * x2 * (1.0 - x1 * x1);
+  w2 = -2.0 * x1 * (1.0 - x2 * x2);
+}
+
+// Diagonal entry of the operator at node (i1, i2) (0-based) on a grid of width h.
+__device__ __forceinline__ double op_diag(int dim, int pde, double h, double eps, int i1, int i2) {
+  if (pde == 0) return 2.0 * dim / (h * h);
+  double w1, w2;
+  wind((i1 + 1) * h, (i2 + 1) * h, w1, w2);
+  return 4.0 * eps / (h * h) + (fabs(w1) + fabs(w2)) / h;
+}
+
+// (A x)_i or (A^T x)_i at node idx = i1 + N (i2 + N i3).  Off-grid neighbours are 0
+// (homogeneous Dirichlet; inhomogeneous data is folded into f_hat on the host).
+template <typename T>
+__device__ __forceinline__ T apply_op(const T* __restrict__ x, int idx, int i1, int i2, int i3, int N, int dim,
+                                      int pde, double h, double eps, bool transpose) {
+  if (pde == 0) {
+    const T ih2 = (T)(1.0 / (h * h));
+    T nb = 0;
+    if (i1 > 0) nb += x[idx - 1];
+    if (i1 < N - 1) nb += x[idx + 1];
+    if (i2 > 0) nb += x[idx - N];
+    if (i2 < N - 1) nb += x[idx + N];
+    if (dim == 3) {
+      const int NN = N * N;
+      if (i3 > 0) nb += x[idx - NN];
+      if (i3 < N - 1) nb += x[idx + NN];
+    }
+    return ih2 * ((T)(2 * dim) * x[idx] - nb);
+  }
+  // 2D upwind convection-diffusion
+  const double ed = eps / (h * h), ih = 1.0 / h;
+  double w1, w2;
+  const double x1 = (i1 + 1) * h, x2 = (i2 + 1) * h;
+  wind(x1, x2, w1, w2);
+  double r = (4.0 * ed + (fabs(w1) + fabs(w2)) * ih) * (double)x[idx];
+  if (!transpose) {
+    if (i1 > 0) r += (-ed - fmax(w1, 0.0) * ih) * (double)x[idx - 1];
+    if (i1 < N - 1) r += (-ed + fmin(w1, 0.0) * ih) * (double)x[idx + 1];
+    if (i2 > 0) r += (-ed - fmax(w2, 0.0) * ih) * (double)x[idx - N];
+    if (i2 < N - 1) r += (-ed + fmin(w2, 0.0) * ih) * (double)x[idx + N];
+  } else {
+    // column i of A: the neighbour j's coefficient for node i, with the wind at j
+    double a1, a2;
+    if (i1 < N - 1) { wind(x1 + h, x2, a1, a2); r += (-ed - fmax(a1, 0.0) * ih) * (double)x[idx + 1]; }
+    if (i1 > 0)     { wind(x1 - h, x2, a1, a2); r += (-ed + fmin(a1, 0.0) * ih) * (double)x[idx - 1]; }
+    if (i2 < N - 1) { wind(x1, x2 + h, a1, a2); r += (-ed - fmax(a2, 0.0) * ih) * (double)x[idx + N]; }
+    if (i2 > 0)     { wind(x1, x2 - h, a1, a2); r += (-ed + fmin(a2, 0.0) * ih) * (double)x[idx - N]; }
+  }
+  return (T)r;
+}
+
+__device__ __forceinline__ void node_coords(int idx, int N, int dim, int& i1, int& i2, int& i3) {
+  i1 = idx % N;
+  int t = idx / N;
+  if (dim == 2) { i2 = t; i3 = 0; }
+  else { i2 = t % N; i3 = t / N; }
+}
+
+// ---------------------------------------------------------------------------
+// reductions (deterministic: fixed-order trees, no floating-point atomics)
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+// max/min that propagate NaN (so that a broken iterate shows in the measures)
+__device__ __forceinline__ double nmax(double a, double b) { return (a != a) ? a : (a > b ? a : b); }
+__device__ __forceinline__ double nmin(double a, double b) { return (a != a) ? a : (a < b ? a : b); }
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = nmax(v, __shfl_down(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = nmin(v, __shfl_down(v, o, 64));
+  return v;
+}
+
+enum RedOp { kSum = 0, kMax = 1, kMin = 2 };
+
+template <int OP>
+__device__ __forceinline__ double red_op(double a, double b) {
+  if (OP == kSum) return a + b;
+  if (OP == kMax) return nmax(a, b);
+  return nmin(a, b);
+}
+template <int OP>
+__device__ __forceinline__ double red_wave(double v) {
+  if (OP == kSum) return wave_sum(v);
+  if (OP == kMax) return wave_max(v);
+  return wave_min(v);
+}
+template <int OP>
+__device__ __forceinline__ double red_identity() {
+  if (OP == kSum) return 0.0;
+  if (OP == kMax) return -INFINITY;
+  return INFINITY;
+}
+
+// Block-wide reduction of K values per thread; result valid in thread 0.
+template <int OP, int K, int BS>
+__device__ __forceinline__ void block_reduce(double (&v)[K], double* smem /* K * BS/64 */) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  constexpr int NW = BS / 64;
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = red_wave<OP>(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) smem[k * NW + wid] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double a = smem[k * NW];
+      for (int w = 1; w < NW; ++w) a = red_op<OP>(a, smem[k * NW + w]);
+      v[k] = a;
+    }
+  }
+  __syncthreads();
+}
+
+// Grid-wide deterministic reduction with the last-block pattern.  Each block
+// stores K partials; the block that arrives last combines all partials in
+// index order and returns true (thread 0 then holds the results in v).
+//
+// Cross-block visibility without cache-wide maintenance: the partials are
+// written and read with agent-scope relaxed atomic accesses (coherent across
+// the XCDs' L2s), and each block waits for its stores to complete before it
+// takes its ticket.  An agent-scope fence here would write back and
+// invalidate the whole L2 once per block.
+template <int OP, int K, int BS>
+__device__ __forceinline__ bool grid_reduce(double (&v)[K], double* __restrict__ partials, unsigned* counter,
+                                            int nblocks, int bid, double* smem) {
+  block_reduce<OP, K, BS>(v, smem);
+  __shared__ int is_last;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      __hip_atomic_store(&partials[k * nblocks + bid], v[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);
+    const unsigned t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    is_last = (t == (unsigned)(nblocks - 1));
+  }
+  __syncthreads();
+  if (!is_last) return false;
+  double acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    acc[k] = red_identity<OP>();
+    for (int b = threadIdx.x; b < nblocks; b += BS)
+      acc[k] = red_op<OP>(acc[k], __hip_atomic_load(&partials[k * nblocks + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  }
+  block_reduce<OP, K, BS>(acc, smem);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = acc[k];
+    __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  return true;
+}
+
+inline int div_up(long a, long b) { return (int)((a + b - 1) / b); }
+
+}  // namespace ipm

@@ -1,0 +1,238 @@
+// Interior point kernels: starting point, feasibility/complementarity
+// measures, barrier diagonals and Newton right-hand side, step lengths and
+// the iterate update (Algorithm A.1 of the Appendix; Sec. 3).
+//
+// Unit-mass finite-difference form: M = D = I, L = A.  Split bounds
+// (Sec. 2, eq. (split)) with u_a < 0 < u_b: z_a = 0, z_b = [u_b; -u_a], so
+// the gaps are w, u_b - w, v, -u_a - v (and y - y_a, y_b - y with state
+// bounds).
+#include "common.h"
+
+namespace ipm {
+
+// Starting point: box midpoints, p = 0, multipliers mu0 / gap.
+__global__ void __launch_bounds__(kBS) k_init_state(Inst I, double mu0) {
+  const int i = blockIdx.x * kBS + threadIdx.x;
+  if (i >= I.n) return;
+  const double ua = I.ua[i], ub = I.ub[i];
+  const double w = 0.5 * ub, v = -0.5 * ua;
+  I.w[i] = w;
+  I.v[i] = v;
+  I.p[i] = 0.0;
+  I.lwa[i] = mu0 / w;
+  I.lwb[i] = mu0 / (ub - w);
+  I.lva[i] = mu0 / v;
+  I.lvb[i] = mu0 / (-ua - v);
+  if (I.has_y) {
+    const double ya = I.ya[i], yb = I.yb[i], y = 0.5 * (ya + yb);
+    I.y[i] = y;
+    I.lya[i] = mu0 / (y - ya);
+    I.lyb[i] = mu0 / (yb - y);
+  } else {
+    I.y[i] = 0.0;
+  }
+}
+
+// inf-norms of xi_p, xi_d (eq. (prdu)) and of the complementarity products
+// (eq. (gap) without the mu term) -> stat[0..2].
+__global__ void __launch_bounds__(kBS) k_measures(Inst I) {
+  __shared__ double smem[3 * kBS / 64];
+  const int i = blockIdx.x * kBS + threadIdx.x;
+  double r[3] = {0.0, 0.0, 0.0};
+  if (i < I.n) {
+    int i1, i2, i3;
+    node_coords(i, I.N, I.dim, i1, i2, i3);
+    const double y = I.y[i], w = I.w[i], v = I.v[i], p = I.p[i];
+    const double u = w - v;
+    const double Ay = apply_op<double>(I.y, i, i1, i2, i3, I.N, I.dim, I.pde, I.h, I.eps, false);
+    const double ATp = apply_op<double>(I.p, i, i1, i2, i3, I.N, I.dim, I.pde, I.h, I.eps, true);
+    const double ua = I.ua[i], ub = I.ub[i];
+    const double lwa = I.lwa[i], lwb = I.lwb[i], lva = I.lva[i], lvb = I.lvb[i];
+    r[0] = fabs(Ay - u - I.fhat[i]);
+    double dy = y - I.yd[i] + ATp;
+    double pc = nmax(nmax(w * lwa, (ub - w) * lwb), nmax(v * lva, (-ua - v) * lvb));
+    if (I.has_y) {
+      const double lya = I.lya[i], lyb = I.lyb[i];
+      dy += -lya + lyb;
+      pc = nmax(pc, nmax((y - I.ya[i]) * lya, (I.yb[i] - y) * lyb));
+    }
+    const double dw = I.alpha * u + I.beta - p - lwa + lwb;
+    const double dv = -I.alpha * u + I.beta + p - lva + lvb;
+    r[1] = nmax(fabs(dy), nmax(fabs(dw), fabs(dv)));
+    r[2] = fabs(pc);
+  }
+  if (grid_reduce<kMax, 3, kBS>(r, I.partials, I.counter, gridDim.x, blockIdx.x, smem) && threadIdx.x == 0) {
+    I.stat[0] = r[0];
+    I.stat[1] = r[1];
+    I.stat[2] = r[2];
+  }
+}
+
+// Barrier diagonals Theta_y, Theta_w, Theta_v (Sec. 3, below eq.
+// (NewtonSystem)), the matching term M_hat = sqrt(Sigma (1 + Theta_y)) with
+// Sigma = (t_w + t_v) / (alpha (t_w + t_v) + t_w t_v) (eq. (Schur) and the
+// M_hat of Sec. 4.2 with M = D_M = I), and the right-hand side of eq.
+// (NewtonSystem) at barrier mu; |rhs|_2 -> ctrl->bnorm.
+template <typename T>
+__global__ void __launch_bounds__(kBS) k_newton_setup(Inst I, double mu, double* __restrict__ rhs, T* __restrict__ mh0) {
+  __shared__ double smem[kBS / 64];
+  const int i = blockIdx.x * kBS + threadIdx.x;
+  double acc[1] = {0.0};
+  if (i < I.n) {
+    int i1, i2, i3;
+    node_coords(i, I.N, I.dim, i1, i2, i3);
+    const double y = I.y[i], w = I.w[i], v = I.v[i], p = I.p[i];
+    const double ua = I.ua[i], ub = I.ub[i];
+    const double gwb = ub - w, gvb = -ua - v;
+    const double tw = I.lwa[i] / w + I.lwb[i] / gwb;
+    const double tv = I.lva[i] / v + I.lvb[i] / gvb;
+    double ty = 0.0, by = 0.0;
+    if (I.has_y) {
+      const double gya = y - I.ya[i], gyb = I.yb[i] - y;
+      ty = I.lya[i] / gya + I.lyb[i] / gyb;
+      by = -mu / gya + mu / gyb;
+    }
+    const double sig = (tw + tv) / (I.alpha * (tw + tv) + tw * tv);
+    const double mh = sqrt(sig * (1.0 + ty));
+    I.ty[i] = ty;
+    I.tw[i] = tw;
+    I.tv[i] = tv;
+    I.mh[i] = mh;
+    mh0[i] = (T)mh;
+    const double u = w - v;
+    const double Ay = apply_op<double>(I.y, i, i1, i2, i3, I.N, I.dim, I.pde, I.h, I.eps, false);
+    const double ATp = apply_op<double>(I.p, i, i1, i2, i3, I.N, I.dim, I.pde, I.h, I.eps, true);
+    const double ry = -(y - I.yd[i] + ATp + by);
+    const double rw = -(I.alpha * u + I.beta - p - mu / w + mu / gwb);
+    const double rv = -(-I.alpha * u + I.beta + p - mu / v + mu / gvb);
+    const double rp = -(Ay - u - I.fhat[i]);
+    const int n = I.n;
+    rhs[i] = ry;
+    rhs[n + i] = rw;
+    rhs[2 * n + i] = rv;
+    rhs[3 * n + i] = rp;
+    acc[0] = ry * ry + rw * rw + rv * rv + rp * rp;
+  }
+  if (grid_reduce<kSum, 1, kBS>(acc, I.partials, I.counter, gridDim.x, blockIdx.x, smem) && threadIdx.x == 0)
+    I.ctrl->bnorm = sqrt(acc[0]);
+}
+template __global__ void k_newton_setup<float>(Inst, double, double*, float*);
+template __global__ void k_newton_setup<double>(Inst, double, double*, double*);
+
+// Full-weighting restriction of the M_hat diagonal to the next coarser level
+// (tensor product of the weights 1/4, 1/2, 1/4); the coarse operator is the
+// rediscretized stencil plus this restricted reaction term.
+template <typename T>
+__global__ void __launch_bounds__(kBS) k_restrict_diag(const T* __restrict__ fine, T* __restrict__ coarse, int Nf,
+                                                       int Nc, int dim) {
+  const int nc = dim == 2 ? Nc * Nc : Nc * Nc * Nc;
+  const int ic = blockIdx.x * kBS + threadIdx.x;
+  if (ic >= nc) return;
+  int j1, j2, j3;
+  node_coords(ic, Nc, dim, j1, j2, j3);
+  // coarse node J (1-based) sits on fine node 2J (1-based) -> 0-based 2j+1
+  const int f1 = 2 * j1 + 1, f2 = 2 * j2 + 1, f3 = 2 * j3 + 1;
+  double acc = 0.0;
+  const double wt[3] = {0.25, 0.5, 0.25};
+  if (dim == 2) {
+    for (int b = -1; b <= 1; ++b)
+      for (int a = -1; a <= 1; ++a)
+        acc += wt[a + 1] * wt[b + 1] * (double)fine[(f1 + a) + Nf * (f2 + b)];
+  } else {
+    for (int c = -1; c <= 1; ++c)
+      for (int b = -1; b <= 1; ++b)
+        for (int a = -1; a <= 1; ++a)
+          acc += wt[a + 1] * wt[b + 1] * wt[c + 1] * (double)fine[(f1 + a) + Nf * ((f2 + b) + Nf * (f3 + c))];
+  }
+  coarse[ic] = (T)acc;
+}
+template __global__ void k_restrict_diag<float>(const float*, float*, int, int, int);
+template __global__ void k_restrict_diag<double>(const double*, double*, int, int, int);
+
+// Multiplier steps of eqs. (zupdate1)-(zupdate4) for one bound pair.
+struct DL { double a, b; };
+__device__ __forceinline__ DL dlam(double la, double lb, double ga, double gb, double dx, double mu) {
+  DL r;
+  r.a = -(la / ga) * dx - la + mu / ga;
+  r.b = (lb / gb) * dx - lb + mu / gb;
+  return r;
+}
+__device__ __forceinline__ double box_step(double ga, double gb, double dx) {
+  // largest s >= 0 keeping lo <= x + s dx <= hi, given gaps ga = x - lo, gb = hi - x
+  if (dx < 0.0) return ga / (-dx);
+  if (dx > 0.0) return gb / dx;
+  return INFINITY;
+}
+__device__ __forceinline__ double pos_step(double l, double dl) { return dl < 0.0 ? l / (-dl) : INFINITY; }
+
+// Fraction-to-boundary step lengths (Algorithm A.1): alpha_P = alpha0 min(1, max
+// primal step), alpha_D likewise for the multipliers -> stat[3], stat[4].
+__global__ void __launch_bounds__(kBS) k_step_lengths(Inst I, const double* __restrict__ X, double mu, double alpha0) {
+  __shared__ double smem[2 * kBS / 64];
+  const int i = blockIdx.x * kBS + threadIdx.x;
+  double r[2] = {INFINITY, INFINITY};
+  if (i < I.n) {
+    const int n = I.n;
+    const double dy = X[i], dw = X[n + i], dv = X[2 * n + i];
+    const double w = I.w[i], v = I.v[i], ua = I.ua[i], ub = I.ub[i];
+    const double gwa = w, gwb = ub - w, gva = v, gvb = -ua - v;
+    const double lwa = I.lwa[i], lwb = I.lwb[i], lva = I.lva[i], lvb = I.lvb[i];
+    double sp = nmin(box_step(gwa, gwb, dw), box_step(gva, gvb, dv));
+    const DL lw = dlam(lwa, lwb, gwa, gwb, dw, mu), lv = dlam(lva, lvb, gva, gvb, dv, mu);
+    double sd = nmin(nmin(pos_step(lwa, lw.a), pos_step(lwb, lw.b)), nmin(pos_step(lva, lv.a), pos_step(lvb, lv.b)));
+    if (I.has_y) {
+      const double y = I.y[i], gya = y - I.ya[i], gyb = I.yb[i] - y;
+      const double lya = I.lya[i], lyb = I.lyb[i];
+      sp = nmin(sp, box_step(gya, gyb, dy));
+      const DL ly = dlam(lya, lyb, gya, gyb, dy, mu);
+      sd = nmin(sd, nmin(pos_step(lya, ly.a), pos_step(lyb, ly.b)));
+    }
+    // a NaN direction must not pass as a huge step
+    if (dy != dy || dw != dw || dv != dv) sp = NAN;
+    r[0] = sp;
+    r[1] = sd;
+  }
+  if (grid_reduce<kMin, 2, kBS>(r, I.partials, I.counter, gridDim.x, blockIdx.x, smem) && threadIdx.x == 0) {
+    I.stat[3] = alpha0 * nmin(1.0, r[0]);
+    I.stat[4] = alpha0 * nmin(1.0, r[1]);
+  }
+}
+
+// Iterate update of Algorithm A.1: (y, w, v) += alpha_P (dy, dw, dv);
+// (p, lambdas) += alpha_D (dp, dlambdas).
+__global__ void __launch_bounds__(kBS) k_update(Inst I, const double* __restrict__ X, double mu) {
+  const int i = blockIdx.x * kBS + threadIdx.x;
+  if (i >= I.n) return;
+  const int n = I.n;
+  const double aP = I.stat[3], aD = I.stat[4];
+  const double dy = X[i], dw = X[n + i], dv = X[2 * n + i], dp = X[3 * n + i];
+  const double w = I.w[i], v = I.v[i], ua = I.ua[i], ub = I.ub[i];
+  const double lwa = I.lwa[i], lwb = I.lwb[i], lva = I.lva[i], lvb = I.lvb[i];
+  const DL lw = dlam(lwa, lwb, w, ub - w, dw, mu), lv = dlam(lva, lvb, v, -ua - v, dv, mu);
+  if (I.has_y) {
+    const double y = I.y[i];
+    const double lya = I.lya[i], lyb = I.lyb[i];
+    const DL ly = dlam(lya, lyb, y - I.ya[i], I.yb[i] - y, dy, mu);
+    I.lya[i] = lya + aD * ly.a;
+    I.lyb[i] = lyb + aD * ly.b;
+  }
+  I.y[i] += aP * dy;
+  I.w[i] = w + aP * dw;
+  I.v[i] = v + aP * dv;
+  I.p[i] += aD * dp;
+  I.lwa[i] = lwa + aD * lw.a;
+  I.lwb[i] = lwb + aD * lw.b;
+  I.lva[i] = lva + aD * lv.a;
+  I.lvb[i] = lvb + aD * lv.b;
+}
+
+// y = A x or A^T x (FP64).
+__global__ void __launch_bounds__(kBS) k_apply_op(Inst I, const double* __restrict__ x, double* __restrict__ y, int transpose) {
+  const int i = blockIdx.x * kBS + threadIdx.x;
+  if (i >= I.n) return;
+  int i1, i2, i3;
+  node_coords(i, I.N, I.dim, i1, i2, i3);
+  y[i] = apply_op<double>(x, i, i1, i2, i3, I.N, I.dim, I.pde, I.h, I.eps, transpose != 0);
+}
+
+}  // namespace ipm

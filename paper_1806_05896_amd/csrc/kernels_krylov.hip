@@ -1,0 +1,340 @@
+// Krylov kernels for the Newton saddle-point system of eq. (NewtonSystem)
+// with M = I, unknowns [dy; dw; dv; dp] stored as four consecutive blocks of
+// n doubles:
+//
+//   K = [ I+Th_y    0        0       A^T ]
+//       [ 0       a+Th_w    -a       -I  ]
+//       [ 0        -a      a+Th_v     I  ]
+//       [ A        -I        I        0  ]
+//
+// Preconditioned MINRES (Sec. 4: the Krylov method used with P_D) runs with
+// all scalars on the device.  One iteration is
+//   K1  pending direction/solution update of the previous iteration, then
+//       q = K z_j / gamma_j and delta_j = <q, z_j / gamma_j>
+//   K2  Lanczos step v_{j+1} = q - (delta_j/gamma_j) v_j - (gamma_j/gamma_{j-1}) v_{j-1},
+//       exact (1,1)-block inverse of P_D on the y, w, v blocks and their part
+//       of <v_{j+1}, z_{j+1}>; the p block is handed to the multigrid
+//   MG  z_{j+1,p} = S_hat^-1 v_{j+1,p}
+//   K4  rest of <v_{j+1}, z_{j+1}>, gamma_{j+1}, the Givens rotation and the
+//       coefficients of the next update, all in the last block.
+#include "common.h"
+
+namespace ipm {
+
+// Rows of K applied at node i to the 4-block vector x (scaled by s).
+__device__ __forceinline__ void saddle_rows(const Inst& I, const double* __restrict__ x, int i, double s,
+                                            double out[4]) {
+  int i1, i2, i3;
+  node_coords(i, I.N, I.dim, i1, i2, i3);
+  const int n = I.n;
+  const double xy = x[i], xw = x[n + i], xv = x[2 * n + i];
+  const double ty = I.ty[i], tw = I.tw[i], tv = I.tv[i], a = I.alpha;
+  const double ATxp = apply_op<double>(x + 3 * n, i, i1, i2, i3, I.N, I.dim, I.pde, I.h, I.eps, true);
+  const double Axy = apply_op<double>(x, i, i1, i2, i3, I.N, I.dim, I.pde, I.h, I.eps, false);
+  const double xp = x[3 * n + i];
+  out[0] = s * ((1.0 + ty) * xy + ATxp);
+  out[1] = s * ((a + tw) * xw - a * xv - xp);
+  out[2] = s * (-a * xw + (a + tv) * xv + xp);
+  out[3] = s * (Axy - xw + xv);
+}
+
+// Exact inverse of the (1,1) block of P_D at node i: 1/(1+Th_y) on y and the
+// per-node 2x2 inverse of [a+t_w, -a; -a, a+t_v] (Sec. 4.1 with D_M = M = I).
+__device__ __forceinline__ void apply_A11_inv(const Inst& I, int i, double ry, double rw, double rv, double& zy,
+                                              double& zw, double& zv) {
+  const double ty = I.ty[i], tw = I.tw[i], tv = I.tv[i], a = I.alpha;
+  zy = ry / (1.0 + ty);
+  const double det = a * (tw + tv) + tw * tv;
+  zw = ((a + tv) * rw + a * rv) / det;
+  zv = (a * rw + (a + tw) * rv) / det;
+}
+
+// y = K x
+__global__ void __launch_bounds__(kBS) k_saddle(Inst I, const double* __restrict__ x, double* __restrict__ y) {
+  const int i = blockIdx.x * kBS + threadIdx.x;
+  if (i >= I.n) return;
+  double o[4];
+  saddle_rows(I, x, i, 1.0, o);
+  const int n = I.n;
+  y[i] = o[0]; y[n + i] = o[1]; y[2 * n + i] = o[2]; y[3 * n + i] = o[3];
+}
+
+// r = b - K x, |r|_2 -> ctrl->rnorm
+__global__ void __launch_bounds__(kBS) k_true_residual(Inst I, const double* __restrict__ x,
+                                                       const double* __restrict__ b, double* __restrict__ r) {
+  __shared__ double smem[kBS / 64];
+  const int i = blockIdx.x * kBS + threadIdx.x;
+  double acc[1] = {0.0};
+  if (i < I.n) {
+    double o[4];
+    saddle_rows(I, x, i, 1.0, o);
+    const int n = I.n;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double rk = b[k * n + i] - o[k];
+      r[k * n + i] = rk;
+      acc[0] += rk * rk;
+    }
+  }
+  if (grid_reduce<kSum, 1, kBS>(acc, I.partials, I.counter, gridDim.x, blockIdx.x, smem) && threadIdx.x == 0)
+    I.ctrl->rnorm = sqrt(acc[0]);
+}
+
+// Diagonal part of the preconditioner for an arbitrary vector (used by the
+// stand-alone preconditioner entry point and FGMRES): z_{y,w,v} = A11^-1 r,
+// and b_0 = (T) r_p (or r_p - B z for P_T, see k_pt_rhs).
+template <typename T>
+__global__ void __launch_bounds__(kBS) k_precond_diag(Inst I, const double* __restrict__ r, double* __restrict__ z,
+                                                      int pt, int guard) {
+  if (guard && I.ctrl->stop) return;
+  const int i = blockIdx.x * kBS + threadIdx.x;
+  if (i >= I.n) return;
+  const int n = I.n;
+  double zy, zw, zv;
+  apply_A11_inv(I, i, r[i], r[n + i], r[2 * n + i], zy, zw, zv);
+  z[i] = zy; z[n + i] = zw; z[2 * n + i] = zv;
+  if (!pt) ((T*)I.lv[0].b)[i] = (T)r[3 * n + i];
+}
+
+// P_T (Sec. 4, block lower triangular [A11 0; B -S_hat]): the p block solves
+// S_hat z_p = B z_A - r_p with B z_A = A z_y - z_w + z_v (M = I).
+template <typename T>
+__global__ void __launch_bounds__(kBS) k_pt_rhs(Inst I, const double* __restrict__ r, const double* __restrict__ z,
+                                                int guard) {
+  if (guard && I.ctrl->stop) return;
+  const int i = blockIdx.x * kBS + threadIdx.x;
+  if (i >= I.n) return;
+  int i1, i2, i3;
+  node_coords(i, I.N, I.dim, i1, i2, i3);
+  const int n = I.n;
+  const double Bz = apply_op<double>(z, i, i1, i2, i3, I.N, I.dim, I.pde, I.h, I.eps, false) - z[n + i] + z[2 * n + i];
+  ((T*)I.lv[0].b)[i] = (T)(Bz - r[3 * n + i]);
+}
+
+// z_p = (double) x_mg
+template <typename T>
+__global__ void __launch_bounds__(kBS) k_store_p(Inst I, const T* __restrict__ xmg, double* __restrict__ z, int guard) {
+  if (guard && I.ctrl->stop) return;
+  const int i = blockIdx.x * kBS + threadIdx.x;
+  if (i >= I.n) return;
+  z[3 * I.n + i] = (double)xmg[i];
+}
+
+// ---------------------------------------------------------------- MINRES
+
+// Start of a MINRES cycle from residual r: v_1 = r, v_0 = 0, w = 0,
+// z_1 on the diagonal blocks, partial <v_1, z_1>; b_0 = (T) r_p.
+template <typename T>
+__global__ void __launch_bounds__(kBS) k_minres_init(Inst I, const double* __restrict__ r, double* __restrict__ V1,
+                                                     double* __restrict__ V0, double* __restrict__ Z1,
+                                                     double* __restrict__ W0, double* __restrict__ W1,
+                                                     double* __restrict__ KW0, double* __restrict__ KW1,
+                                                     double* __restrict__ Rt) {
+  __shared__ double smem[kBS / 64];
+  const int i = blockIdx.x * kBS + threadIdx.x;
+  double acc[1] = {0.0};
+  if (i < I.n) {
+    const int n = I.n;
+    const double ry = r[i], rw = r[n + i], rv = r[2 * n + i], rp = r[3 * n + i];
+    double zy, zw, zv;
+    apply_A11_inv(I, i, ry, rw, rv, zy, zw, zv);
+    V1[i] = ry; V1[n + i] = rw; V1[2 * n + i] = rv; V1[3 * n + i] = rp;
+    Z1[i] = zy; Z1[n + i] = zw; Z1[2 * n + i] = zv;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int j = k * n + i;
+      V0[j] = 0.0; W0[j] = 0.0; W1[j] = 0.0; KW0[j] = 0.0; KW1[j] = 0.0;
+      Rt[j] = r[j];
+    }
+    ((T*)I.lv[0].b)[i] = (T)rp;
+    acc[0] = ry * zy + rw * zw + rv * zv;
+  }
+  if (grid_reduce<kSum, 1, kBS>(acc, I.partials, I.counter, gridDim.x, blockIdx.x, smem) && threadIdx.x == 0)
+    I.ctrl->dot_tmp = acc[0];
+}
+
+// Apply the pending update of iteration i at node k:
+//   w_i = (z_i/gamma_i - a3 w_{i-2} - a2 w_{i-1}) / a1,  x += coef_x w_i
+__device__ __forceinline__ void minres_pending(const KrylovCtrl& C, const double* __restrict__ Zi,
+                                               double* __restrict__ Wsame, const double* __restrict__ Wother,
+                                               double* __restrict__ X, int k) {
+  const double wi = (Zi[k] / C.gamma_w - C.a3 * Wsame[k] - C.a2 * Wother[k]) / C.a1;
+  Wsame[k] = wi;
+  X[k] += C.coef_x * wi;
+}
+
+// K1: pending update of iteration j-1 (direction w, solution x, and by the
+// same recurrence K w and the residual r = b - K x, with |r|^2), then
+// q = K z_j / gamma_j and delta_j = <q, z_j/gamma_j>.  The last block stops
+// the solve once |r|_2 <= rtarget (the true residual is tracked exactly in
+// exact arithmetic whatever the preconditioner, so FP32 V-cycles cannot fake
+// convergence).
+__global__ void __launch_bounds__(kBS) k_minres_k1(Inst I, const double* __restrict__ Zc,
+                                                   const double* __restrict__ Zprev, double* __restrict__ Wsame,
+                                                   const double* __restrict__ Wother, double* __restrict__ X,
+                                                   double* __restrict__ Q, double* __restrict__ KWsame,
+                                                   const double* __restrict__ KWother, double* __restrict__ Rt) {
+  __shared__ double smem[2 * kBS / 64];
+  KrylovCtrl* C = I.ctrl;
+  if (C->stop) return;
+  const int pending = C->pending;
+  const int i = blockIdx.x * kBS + threadIdx.x;
+  double acc[2] = {0.0, 0.0};
+  if (i < I.n) {
+    const int n = I.n;
+    if (pending) {
+      const double g = C->gamma_w, a1 = C->a1, a2 = C->a2, a3 = C->a3, cx = C->coef_x;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int j = k * n + i;
+        const double wi = (Zprev[j] / g - a3 * Wsame[j] - a2 * Wother[j]) / a1;
+        Wsame[j] = wi;
+        X[j] += cx * wi;
+        const double kwi = (Q[j] - a3 * KWsame[j] - a2 * KWother[j]) / a1;
+        KWsame[j] = kwi;
+        const double r = Rt[j] - cx * kwi;
+        Rt[j] = r;
+        acc[1] += r * r;
+      }
+    }
+    const double s = 1.0 / C->gamma;
+    double o[4];
+    saddle_rows(I, Zc, i, s, o);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      Q[k * n + i] = o[k];
+      acc[0] += o[k] * (Zc[k * n + i] * s);
+    }
+  }
+  if (grid_reduce<kSum, 2, kBS>(acc, I.partials, I.counter, gridDim.x, blockIdx.x, smem) && threadIdx.x == 0) {
+    C->delta = acc[0];
+    if (pending) {
+      C->rtrack = sqrt(acc[1]);
+      C->pending = 0;
+      if (C->rtrack <= C->rtarget || !(acc[1] == acc[1])) C->stop = 1;
+    }
+  }
+}
+
+// K2: Lanczos vector v_{j+1} (overwrites v_{j-1}), z_{j+1} on the diagonal
+// blocks, partial <v_{j+1}, z_{j+1}>, b_0 = (T) v_{j+1,p} for the multigrid.
+template <typename T>
+__global__ void __launch_bounds__(kBS) k_minres_k2(Inst I, const double* __restrict__ Q, const double* __restrict__ Vc,
+                                                   double* __restrict__ Vn, double* __restrict__ Zn) {
+  __shared__ double smem[kBS / 64];
+  const KrylovCtrl* C = I.ctrl;
+  if (C->stop) return;
+  const int i = blockIdx.x * kBS + threadIdx.x;
+  double acc[1] = {0.0};
+  if (i < I.n) {
+    const int n = I.n;
+    const double c1 = C->delta / C->gamma, c2 = C->gamma / C->gamma_prev;
+    double v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[k] = Q[k * n + i] - c1 * Vc[k * n + i] - c2 * Vn[k * n + i];
+      Vn[k * n + i] = v[k];
+    }
+    double zy, zw, zv;
+    apply_A11_inv(I, i, v[0], v[1], v[2], zy, zw, zv);
+    Zn[i] = zy; Zn[n + i] = zw; Zn[2 * n + i] = zv;
+    ((T*)I.lv[0].b)[i] = (T)v[3];
+    acc[0] = v[0] * zy + v[1] * zw + v[2] * zv;
+  }
+  if (grid_reduce<kSum, 1, kBS>(acc, I.partials, I.counter, gridDim.x, blockIdx.x, smem) && threadIdx.x == 0)
+    I.ctrl->dot_tmp = acc[0];
+}
+
+// K4: z_{j+1,p} from the multigrid output, the rest of <v, z>, then the
+// scalar recurrence in the last block.  mode 0 starts a cycle (gamma_1),
+// mode 1 is an iteration.  rtarget: residual norm at which K1 stops (mode 0).
+template <typename T>
+__global__ void __launch_bounds__(kBS) k_minres_k4(Inst I, const T* __restrict__ xmg, const double* __restrict__ Vn,
+                                                   double* __restrict__ Zn, int mode, double rtarget, int maxit) {
+  __shared__ double smem[kBS / 64];
+  KrylovCtrl* C = I.ctrl;
+  if (mode != 0 && C->stop) return;
+  const int i = blockIdx.x * kBS + threadIdx.x;
+  double acc[1] = {0.0};
+  if (i < I.n) {
+    const int n = I.n;
+    const double z = (double)xmg[i];
+    Zn[3 * n + i] = z;
+    acc[0] = Vn[3 * n + i] * z;
+  }
+  if (!grid_reduce<kSum, 1, kBS>(acc, I.partials, I.counter, gridDim.x, blockIdx.x, smem) || threadIdx.x != 0) return;
+  const double dot = C->dot_tmp + acc[0];
+  if (mode == 0) {
+    C->iter = 0;
+    C->pending = 0;
+    C->breakdown = 0;
+    C->rtarget = rtarget;
+    C->rtrack = INFINITY;
+    C->c_prev = C->c = 1.0;
+    C->s_prev = C->s = 0.0;
+    C->gamma_prev = 1.0;
+    C->est = 1.0;
+    if (!(dot > 0.0) || !isfinite(dot)) {  // zero right-hand side, or an indefinite preconditioner
+      C->gamma = 1.0;
+      C->eta = C->eta0 = 0.0;
+      C->breakdown = (dot == 0.0) ? 0 : 1;
+      C->est = 0.0;
+      C->stop = 1;
+      return;
+    }
+    const double g1 = sqrt(dot);
+    C->gamma = g1;
+    C->eta = C->eta0 = g1;
+    C->stop = 0;
+    return;
+  }
+  if (!(dot >= 0.0) || !isfinite(dot)) {
+    C->breakdown = 1;
+    C->stop = 1;
+    C->pending = 0;
+    return;
+  }
+  const double gn = sqrt(dot);
+  const double g = C->gamma, d = C->delta;
+  const double a0 = C->c * d - C->c_prev * C->s * g;
+  const double a1 = sqrt(a0 * a0 + gn * gn);
+  const double a2 = C->s * d + C->c_prev * C->c * g;
+  const double a3 = C->s_prev * g;
+  const double cn = a0 / a1, sn = gn / a1;
+  C->a1 = a1; C->a2 = a2; C->a3 = a3;
+  C->coef_x = cn * C->eta;
+  C->gamma_w = g;
+  C->pending = 1;
+  C->eta = -sn * C->eta;
+  C->c_prev = C->c; C->c = cn;
+  C->s_prev = C->s; C->s = sn;
+  C->gamma_prev = g; C->gamma = gn;
+  C->iter += 1;
+  C->est = fabs(C->eta) / C->eta0;
+  if (gn == 0.0 || C->iter >= maxit || !isfinite(a1) || a1 == 0.0) C->stop = 1;
+}
+
+// Pending update alone (after the loop stopped).
+__global__ void __launch_bounds__(kBS) k_minres_flush(Inst I, const double* __restrict__ Zi, double* __restrict__ Wsame,
+                                                      const double* __restrict__ Wother, double* __restrict__ X) {
+  const KrylovCtrl* C = I.ctrl;
+  if (!C->pending) return;
+  const int i = blockIdx.x * kBS + threadIdx.x;
+  if (i >= I.n) return;
+  const int n = I.n;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) minres_pending(*C, Zi, Wsame, Wother, X, k * n + i);
+}
+
+#define IPM_KRY_INST(T)                                                                              \
+  template __global__ void k_precond_diag<T>(Inst, const double*, double*, int, int);               \
+  template __global__ void k_pt_rhs<T>(Inst, const double*, const double*, int);                    \
+  template __global__ void k_store_p<T>(Inst, const T*, double*, int);                              \
+  template __global__ void k_minres_init<T>(Inst, const double*, double*, double*, double*, double*, double*, double*, double*, double*); \
+  template __global__ void k_minres_k2<T>(Inst, const double*, const double*, double*, double*);    \
+  template __global__ void k_minres_k4<T>(Inst, const T*, const double*, double*, int, double, int);
+IPM_KRY_INST(float)
+IPM_KRY_INST(double)
+#undef IPM_KRY_INST
+
+}  // namespace ipm

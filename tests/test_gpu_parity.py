@@ -1,0 +1,193 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances: operators and the saddle matvec are FP64 stencil sums, compared
+at 1e-13 relative; Newton directions are compared through the oracle's
+FP64 sparse matrix (relative residual <= 1e-9, the Krylov target 1e-10 plus
+the conditioning slack of FP64 accumulation) and against the direct solve;
+whole IPM runs must match the oracle's control and state to relative L2
+<= 1e-6 at the same IPM tolerance, with the same iteration count."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+import workloads as W  # noqa: E402
+from oracle.fd import discretize, operator_matrix  # noqa: E402
+from oracle.ipm import IPMOptions, initial_state, ipm_step, newton_matrix, newton_rhs, newton_solve  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def _api():
+    from paper_1806_05896_amd import Options, Problem
+    return Options, Problem
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _load_state(prob, st, has_y):
+    for f, a in (("y", st.y), ("w", st.w), ("v", st.v), ("p", st.p), ("lam_wa", st.lwa), ("lam_wb", st.lwb),
+                 ("lam_va", st.lva), ("lam_vb", st.lvb)):
+        prob.set_field(f, a)
+    if has_y:
+        prob.set_field("lam_ya", st.lya)
+        prob.set_field("lam_yb", st.lyb)
+
+
+@pytest.mark.parametrize("dim,N,pde", [(2, 3, "poisson"), (2, 31, "poisson"), (2, 127, "poisson"),
+                                       (3, 7, "poisson"), (3, 31, "poisson"), (2, 7, "convdiff"),
+                                       (2, 63, "convdiff")])
+def test_operator_parity(dim, N, pde):
+    Options, Problem = _api()
+    print(f"[operator] dim={dim} N={N} pde={pde}", flush=True)
+    data = W.poisson2d_small(N=N) if dim == 2 else W.poisson3d_127(N=N)
+    if pde == "convdiff":
+        data.pde, data.eps = "convdiff", 1.0 / 200
+    rng = np.random.default_rng(N)
+    x = rng.normal(size=data.n)
+    A = operator_matrix(dim, N, pde, data.eps)
+    with Problem(data) as prob:
+        xt = torch.tensor(x, device="cuda", dtype=torch.float64)
+        for tr in (False, True):
+            y = prob.apply_operator(xt, transpose=tr).cpu().numpy()
+            ref = (A.T if tr else A) @ x
+            assert _rel(y, ref) <= 1e-13, (tr, _rel(y, ref))
+
+
+def _generic_state(data, steps=2):
+    disc = discretize(data)
+    opts = IPMOptions(sigma=data.sigma)
+    st = initial_state(data, opts)
+    for _ in range(steps):
+        st, _ = ipm_step(data, disc, st, opts, st.mu * opts.sigma)
+    return disc, st
+
+
+CASES = {
+    "poisson_small": lambda: W.poisson2d_small(seed=0),
+    "poisson_box63": lambda: W.poisson2d_511(seed=0, N=63),
+    "poisson3d_15": lambda: W.poisson3d_127(seed=0, N=15),
+    "convdiff_31": lambda: W.convdiff2d_255(seed=0, N=31),
+}
+
+
+def _rhs_magnitude(data, disc, st, mu):
+    """Sum of the absolute values of the terms of each right-hand-side entry of eq. (NewtonSystem)."""
+    absA = abs(disc.A)
+    ry = np.abs(st.y) + np.abs(data.y_d) + absA.T @ np.abs(st.p)
+    if data.y_a is not None:
+        ry = ry + mu / np.abs(st.y - data.y_a) + mu / np.abs(data.y_b - st.y)
+    au = data.alpha * (np.abs(st.w) + np.abs(st.v))
+    rw = au + data.beta + np.abs(st.p) + mu / np.abs(st.w) + mu / np.abs(data.u_b - st.w)
+    rv = au + data.beta + np.abs(st.p) + mu / np.abs(st.v) + mu / np.abs(-data.u_a - st.v)
+    rp = absA @ np.abs(st.y) + np.abs(st.w) + np.abs(st.v) + np.abs(disc.f_hat)
+    return np.concatenate([ry, rw, rv, rp])
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_saddle_matvec_parity(case):
+    Options, Problem = _api()
+    print(f"[saddle] {case}", flush=True)
+    data = CASES[case]()
+    disc, st = _generic_state(data)
+    mu = st.mu * data.sigma
+    K = newton_matrix(data, disc, st)
+    b = newton_rhs(data, disc, st, mu)
+    with Problem(data) as prob:
+        _load_state(prob, st, data.y_a is not None)
+        prob.newton_setup(mu, Options())
+        # elementwise rounding bound: 32 ulps of the sum of the magnitudes of the terms
+        assert np.all(np.abs(prob.query_rhs() - b) <= 32 * np.finfo(float).eps * _rhs_magnitude(data, disc, st, mu))
+        x = np.random.default_rng(1).normal(size=4 * data.n)
+        y = prob.apply_saddle(torch.tensor(x, device="cuda", dtype=torch.float64)).cpu().numpy()
+        assert _rel(y, K @ x) <= 1e-13
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", ["poisson_small", "convdiff_31", "poisson3d_15"])
+def test_pd_preconditioner_symmetric_positive(case, prec):
+    """P_D^-1 must be symmetric positive definite for MINRES (exactly so in FP64)."""
+    Options, Problem = _api()
+    print(f"[precond] {case} {prec}", flush=True)
+    data = CASES[case]()
+    disc, st = _generic_state(data)
+    mu = st.mu * data.sigma
+    opts = Options(mg_precision=prec)
+    rng = np.random.default_rng(3)
+    with Problem(data) as prob:
+        _load_state(prob, st, data.y_a is not None)
+        prob.newton_setup(mu, opts)
+        x = rng.normal(size=4 * data.n)
+        z = rng.normal(size=4 * data.n)
+        Px = prob.apply_precond(torch.tensor(x, device="cuda", dtype=torch.float64), opts).cpu().numpy()
+        Pz = prob.apply_precond(torch.tensor(z, device="cuda", dtype=torch.float64), opts).cpu().numpy()
+    asym = abs(Px @ z - x @ Pz) / (np.linalg.norm(Px) * np.linalg.norm(z))
+    assert asym <= (1e-13 if prec == "fp64" else 1e-5), asym
+    assert Px @ x > 0 and Pz @ z > 0
+
+
+@pytest.mark.parametrize("krylov,precond,prec", [("minres", "pd", "fp64"), ("minres", "pd", "fp32"),
+                                                 ("fgmres", "pt", "fp32"), ("fgmres", "pd", "fp64")])
+@pytest.mark.parametrize("case", list(CASES))
+def test_newton_direction_parity(case, krylov, precond, prec):
+    """The Krylov direction solves the oracle's FP64 Newton system (eq. (NewtonSystem))."""
+    Options, Problem = _api()
+    print(f"[newton] {case} {krylov} {precond} {prec}", flush=True)
+    data = CASES[case]()
+    disc, st = _generic_state(data, steps=3)
+    mu = st.mu * data.sigma
+    K = newton_matrix(data, disc, st)
+    b = newton_rhs(data, disc, st, mu)
+    ref = np.concatenate(newton_solve(data, disc, st, mu))
+    opts = Options(krylov=krylov, precond=precond, mg_precision=prec)
+    with Problem(data) as prob:
+        _load_state(prob, st, data.y_a is not None)
+        info = prob.newton_direction(mu, opts)
+        d = np.concatenate([prob.query(f) for f in ("dy", "dw", "dv", "dp")])
+    res = np.linalg.norm(b - K @ d) / np.linalg.norm(b)
+    print(f"  its={info['krylov_its']} relres(gpu)={info['relres']:.2e} relres(oracle K)={res:.2e}", flush=True)
+    assert info["rc"] == 0
+    assert res <= 1e-9
+    assert _rel(d, ref) <= 1e-6
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_ipm_parity_poisson_small(prec):
+    """Whole solve on the 31x31 Poisson workload (MINRES + P_D)."""
+    Options, Problem = _api()
+    print(f"[ipm] poisson2d_small {prec}", flush=True)
+    data = W.poisson2d_small(seed=0)
+    ref = oracle.solve(data, IPMOptions(sigma=data.sigma))
+    with Problem(data) as prob:
+        rc = prob.solve(Options(mg_precision=prec))
+        u, y = prob.query("u"), prob.query("y")
+        s = prob.stats()
+    print(f"  rc={rc} nli={s.nli}/{ref.nli} its={s.krylov_its} rel u={_rel(u, ref.u):.2e} y={_rel(y, ref.y):.2e}")
+    assert rc == 0 and s.nli == ref.nli
+    assert _rel(u, ref.u) <= 1e-6 and _rel(y, ref.y) <= 1e-6
+
+
+@pytest.mark.parametrize("case,krylov,precond", [("poisson_box63", "minres", "pd"), ("poisson3d_15", "minres", "pd"),
+                                                 ("convdiff_31", "fgmres", "pt"), ("convdiff_31", "minres", "pd"),
+                                                 ("poisson_box63", "fgmres", "pt")])
+def test_ipm_parity_cases(case, krylov, precond):
+    Options, Problem = _api()
+    print(f"[ipm] {case} {krylov} {precond}", flush=True)
+    data = CASES[case]()
+    ref = oracle.solve(data, IPMOptions(sigma=data.sigma))
+    with Problem(data) as prob:
+        rc = prob.solve(Options(sigma=data.sigma, krylov=krylov, precond=precond))
+        u, y = prob.query("u"), prob.query("y")
+        s = prob.stats()
+    print(f"  rc={rc} nli={s.nli}/{ref.nli} its={s.krylov_its} rel u={_rel(u, ref.u):.2e} y={_rel(y, ref.y):.2e}")
+    assert rc == 0 and s.nli == ref.nli
+    assert _rel(u, ref.u) <= 1e-6 and _rel(y, ref.y) <= 1e-6
