@@ -11,13 +11,16 @@ namespace ipm {
 
 constexpr int kMaxLev = 16;
 constexpr int kBS = 256;        // threads per block of the elementwise and stencil kernels
-constexpr int kCoarseBS = 512;  // threads of the single-workgroup coarse-grid kernel
+constexpr int kCoarseBS = 1024;  // threads of the single-workgroup coarse-grid kernel
+constexpr int kTicketGroups = 8;   // sub-counters of the grid reduction ticket
+constexpr int kTicketStride = 64;  // unsigned words between sub-counters (one 256-byte line)  // threads of the single-workgroup coarse-grid kernel
 
 // One multigrid level.  Arrays hold T = float or double (the V-cycle precision).
 struct Level {
   int N;      // interior points per axis
   int n;      // N^dim
   double h;   // mesh width 1/(N+1)
+  float invN; // 1/N, for index arithmetic
   void* x;    // iterate
   void* x2;   // second iterate buffer (Jacobi ping-pong)
   void* b;    // right-hand side
@@ -38,6 +41,7 @@ struct KrylovCtrl {
   double rnorm;        // |b - K x|_2 from the last true-residual check
   double rtarget;      // stop when the tracked residual norm falls to this value
   double rtrack;       // tracked residual norm |r_j|_2 (recurrence)
+  double rfloor;       // |(|K||x| + |b|)|_2 from the last true-residual check (rounding floor scale)
   int iter;            // iterations completed
   int stop;            // 0 running, 1 stopped (converged estimate, breakdown)
   int pending;         // a direction/solution update is pending
@@ -101,45 +105,75 @@ __device__ __forceinline__ double op_diag(int dim, int pde, double h, double eps
   return 4.0 * eps / (h * h) + (fabs(w1) + fabs(w2)) / h;
 }
 
-// (A x)_i or (A^T x)_i at node idx = i1 + N (i2 + N i3).  Off-grid neighbours are 0
-// (homogeneous Dirichlet; inhomogeneous data is folded into f_hat on the host).
-template <typename T>
-__device__ __forceinline__ T apply_op(const T* __restrict__ x, int idx, int i1, int i2, int i3, int N, int dim,
-                                      int pde, double h, double eps, bool transpose) {
+// (A x)_i or (A^T x)_i at the node with storage index idx and grid
+// coordinates (i1, i2, i3) (0-based); sy, sz are the storage strides of the
+// second and third axis.  Off-grid neighbours are 0 (homogeneous Dirichlet;
+// inhomogeneous data is folded into f_hat on the host).
+template <typename T, bool ABS = false>
+__device__ __forceinline__ T ldv(const T* __restrict__ x, int k) {
+  return ABS ? (T)fabs(x[k]) : x[k];
+}
+
+// ABS = true evaluates A|x| (used for rounding-error bounds).
+template <typename T, bool ABS = false>
+__device__ __forceinline__ T apply_op_s(const T* __restrict__ x, int idx, int i1, int i2, int i3, int N, int sy, int sz,
+                                        int dim, int pde, double h, double eps, bool transpose) {
+#define X_(k) ldv<T, ABS>(x, (k))
   if (pde == 0) {
     const T ih2 = (T)(1.0 / (h * h));
     T nb = 0;
-    if (i1 > 0) nb += x[idx - 1];
-    if (i1 < N - 1) nb += x[idx + 1];
-    if (i2 > 0) nb += x[idx - N];
-    if (i2 < N - 1) nb += x[idx + N];
+    if (i1 > 0) nb += X_(idx - 1);
+    if (i1 < N - 1) nb += X_(idx + 1);
+    if (i2 > 0) nb += X_(idx - sy);
+    if (i2 < N - 1) nb += X_(idx + sy);
     if (dim == 3) {
-      const int NN = N * N;
-      if (i3 > 0) nb += x[idx - NN];
-      if (i3 < N - 1) nb += x[idx + NN];
+      if (i3 > 0) nb += X_(idx - sz);
+      if (i3 < N - 1) nb += X_(idx + sz);
     }
-    return ih2 * ((T)(2 * dim) * x[idx] - nb);
+    return ih2 * ((T)(2 * dim) * X_(idx) - nb);
   }
   // 2D upwind convection-diffusion
   const double ed = eps / (h * h), ih = 1.0 / h;
   double w1, w2;
   const double x1 = (i1 + 1) * h, x2 = (i2 + 1) * h;
   wind(x1, x2, w1, w2);
-  double r = (4.0 * ed + (fabs(w1) + fabs(w2)) * ih) * (double)x[idx];
+  double r = (4.0 * ed + (fabs(w1) + fabs(w2)) * ih) * (double)X_(idx);
   if (!transpose) {
-    if (i1 > 0) r += (-ed - fmax(w1, 0.0) * ih) * (double)x[idx - 1];
-    if (i1 < N - 1) r += (-ed + fmin(w1, 0.0) * ih) * (double)x[idx + 1];
-    if (i2 > 0) r += (-ed - fmax(w2, 0.0) * ih) * (double)x[idx - N];
-    if (i2 < N - 1) r += (-ed + fmin(w2, 0.0) * ih) * (double)x[idx + N];
+    if (i1 > 0) r += (-ed - fmax(w1, 0.0) * ih) * (double)X_(idx - 1);
+    if (i1 < N - 1) r += (-ed + fmin(w1, 0.0) * ih) * (double)X_(idx + 1);
+    if (i2 > 0) r += (-ed - fmax(w2, 0.0) * ih) * (double)X_(idx - sy);
+    if (i2 < N - 1) r += (-ed + fmin(w2, 0.0) * ih) * (double)X_(idx + sy);
   } else {
     // column i of A: the neighbour j's coefficient for node i, with the wind at j
     double a1, a2;
-    if (i1 < N - 1) { wind(x1 + h, x2, a1, a2); r += (-ed - fmax(a1, 0.0) * ih) * (double)x[idx + 1]; }
-    if (i1 > 0)     { wind(x1 - h, x2, a1, a2); r += (-ed + fmin(a1, 0.0) * ih) * (double)x[idx - 1]; }
-    if (i2 < N - 1) { wind(x1, x2 + h, a1, a2); r += (-ed - fmax(a2, 0.0) * ih) * (double)x[idx + N]; }
-    if (i2 > 0)     { wind(x1, x2 - h, a1, a2); r += (-ed + fmin(a2, 0.0) * ih) * (double)x[idx - N]; }
+    if (i1 < N - 1) { wind(x1 + h, x2, a1, a2); r += (-ed - fmax(a1, 0.0) * ih) * (double)X_(idx + 1); }
+    if (i1 > 0)     { wind(x1 - h, x2, a1, a2); r += (-ed + fmin(a1, 0.0) * ih) * (double)X_(idx - 1); }
+    if (i2 < N - 1) { wind(x1, x2 + h, a1, a2); r += (-ed - fmax(a2, 0.0) * ih) * (double)X_(idx + sy); }
+    if (i2 > 0)     { wind(x1, x2 - h, a1, a2); r += (-ed + fmin(a2, 0.0) * ih) * (double)X_(idx - sy); }
   }
+#undef X_
   return (T)r;
+}
+
+template <typename T>
+__device__ __forceinline__ T apply_op(const T* __restrict__ x, int idx, int i1, int i2, int i3, int N, int dim,
+                                      int pde, double h, double eps, bool transpose) {
+  return apply_op_s<T>(x, idx, i1, i2, i3, N, N, N * N, dim, pde, h, eps, transpose);
+}
+
+// i = q N + r for 0 <= i < 2^22 via a float reciprocal and one correction.
+__device__ __forceinline__ void fast_divmod(int i, int N, int& q, int& r) {
+  q = (int)((float)i * __builtin_amdgcn_rcpf((float)N));
+  r = i - q * N;
+  if (r < 0) { q -= 1; r += N; }
+  else if (r >= N) { q += 1; r -= N; }
+}
+
+__device__ __forceinline__ void node_coords_small(int idx, int N, int dim, int& i1, int& i2, int& i3) {
+  int t;
+  fast_divmod(idx, N, t, i1);
+  if (dim == 2) { i2 = t; i3 = 0; }
+  else fast_divmod(t, N, i3, i2);
 }
 
 __device__ __forceinline__ void node_coords(int idx, int N, int dim, int& i1, int& i2, int& i3) {
@@ -235,8 +269,21 @@ __device__ __forceinline__ bool grid_reduce(double (&v)[K], double* __restrict__
       __hip_atomic_store(&partials[k * nblocks + bid], v[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_s_waitcnt(0);
-    const unsigned t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    is_last = (t == (unsigned)(nblocks - 1));
+    // two-level ticket: blocks are spread over kTicketGroups counters (one
+    // cache line each) so that no single address takes every block's atomic
+    const int g = bid % kTicketGroups;
+    const int gsize = (nblocks - g + kTicketGroups - 1) / kTicketGroups;
+    const int ngroups = nblocks < kTicketGroups ? nblocks : kTicketGroups;
+    unsigned* cg = counter + kTicketStride * (1 + g);
+    int last = 0;
+    const unsigned t1 = __hip_atomic_fetch_add(cg, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (t1 == (unsigned)(gsize - 1)) {
+      __hip_atomic_store(cg, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_s_waitcnt(0);
+      const unsigned t0 = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      last = (t0 == (unsigned)(ngroups - 1));
+    }
+    is_last = last;
   }
   __syncthreads();
   if (!is_last) return false;

@@ -73,7 +73,7 @@ static int fgmres_solve(ipmpde_problem* P, const ipmpde_options& o, hipStream_t 
     const double rel = P->ctrl_h->rnorm / bnorm;
     *its = total;
     *relres = rel;
-    if (rel <= o.krylov_tol) return IPMPDE_OK;
+    if (rel <= std::max(o.krylov_tol, floor_factor() * P->ctrl_h->rfloor / bnorm)) return IPMPDE_OK;
     if (!(rel == rel)) return fail(IPMPDE_EBREAKDOWN, "NaN in the Krylov iterate");
     if (P->ctrl_h->breakdown && P->ctrl_h->j == 0) return fail(IPMPDE_EKRYLOV, "FGMRES breakdown");
     if (total >= o.krylov_maxit) return fail(IPMPDE_EKRYLOV, "Krylov iteration limit reached");

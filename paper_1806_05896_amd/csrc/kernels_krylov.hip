@@ -59,25 +59,49 @@ __global__ void __launch_bounds__(kBS) k_saddle(Inst I, const double* __restrict
   y[i] = o[0]; y[n + i] = o[1]; y[2 * n + i] = o[2]; y[3 * n + i] = o[3];
 }
 
-// r = b - K x, |r|_2 -> ctrl->rnorm
+// |K||x| row by row (all off-diagonal stencil entries are <= 0, so |A||x| = 2 diag |x| - A|x|).
+__device__ __forceinline__ void saddle_rows_abs(const Inst& I, const double* __restrict__ x, int i, double out[4]) {
+  int i1, i2, i3;
+  node_coords(i, I.N, I.dim, i1, i2, i3);
+  const int n = I.n;
+  const double xy = fabs(x[i]), xw = fabs(x[n + i]), xv = fabs(x[2 * n + i]), xp = fabs(x[3 * n + i]);
+  const double ty = I.ty[i], tw = I.tw[i], tv = I.tv[i], a = I.alpha;
+  const double d = op_diag(I.dim, I.pde, I.h, I.eps, i1, i2);
+  const double ATxp = 2.0 * d * xp - apply_op_s<double, true>(x + 3 * n, i, i1, i2, i3, I.N, I.N, I.N * I.N, I.dim, I.pde, I.h, I.eps, true);
+  const double Axy = 2.0 * d * xy - apply_op_s<double, true>(x, i, i1, i2, i3, I.N, I.N, I.N * I.N, I.dim, I.pde, I.h, I.eps, false);
+  out[0] = (1.0 + ty) * xy + ATxp;
+  out[1] = (a + tw) * xw + a * xv + xp;
+  out[2] = a * xw + (a + tv) * xv + xp;
+  out[3] = Axy + xw + xv;
+}
+
+// r = b - K x, |r|_2 -> ctrl->rnorm, and |(|K||x| + |b|)|_2 -> ctrl->rfloor: the
+// scale of the rounding error of evaluating r in FP64, which bounds the
+// attainable relative residual.
 __global__ void __launch_bounds__(kBS) k_true_residual(Inst I, const double* __restrict__ x,
                                                        const double* __restrict__ b, double* __restrict__ r) {
-  __shared__ double smem[kBS / 64];
+  __shared__ double smem[2 * kBS / 64];
   const int i = blockIdx.x * kBS + threadIdx.x;
-  double acc[1] = {0.0};
+  double acc[2] = {0.0, 0.0};
   if (i < I.n) {
-    double o[4];
+    double o[4], m[4];
     saddle_rows(I, x, i, 1.0, o);
+    saddle_rows_abs(I, x, i, m);
     const int n = I.n;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const double rk = b[k * n + i] - o[k];
+      const double bk = b[k * n + i];
+      const double rk = bk - o[k];
       r[k * n + i] = rk;
       acc[0] += rk * rk;
+      const double mk = m[k] + fabs(bk);
+      acc[1] += mk * mk;
     }
   }
-  if (grid_reduce<kSum, 1, kBS>(acc, I.partials, I.counter, gridDim.x, blockIdx.x, smem) && threadIdx.x == 0)
+  if (grid_reduce<kSum, 2, kBS>(acc, I.partials, I.counter, gridDim.x, blockIdx.x, smem) && threadIdx.x == 0) {
     I.ctrl->rnorm = sqrt(acc[0]);
+    I.ctrl->rfloor = sqrt(acc[1]);
+  }
 }
 
 // Diagonal part of the preconditioner for an arbitrary vector (used by the

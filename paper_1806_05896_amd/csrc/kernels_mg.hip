@@ -18,12 +18,13 @@ namespace ipm {
 
 // Jacobi update at node i of level (N, h): x_out = x_in + omega (b - (A + mh) x_in) / d,
 // or omega b / d from a zero iterate.
-template <typename T>
+template <typename T, bool SMALL = false>
 __device__ __forceinline__ T jacobi_node(const T* __restrict__ xin, const T* __restrict__ b, const T* __restrict__ mh,
                                          int i, int N, int dim, int pde, double h, double eps, double omega,
                                          bool first, bool transpose) {
   int i1, i2, i3;
-  node_coords(i, N, dim, i1, i2, i3);
+  if (SMALL) node_coords_small(i, N, dim, i1, i2, i3);
+  else node_coords(i, N, dim, i1, i2, i3);
   const T m = mh[i];
   const T d = (T)op_diag(dim, pde, h, eps, i1, i2) + m;
   if (first) return (T)omega * b[i] / d;
@@ -42,12 +43,13 @@ __device__ __forceinline__ T resid_node(const T* __restrict__ x, const T* __rest
 }
 
 // Full-weighting restriction of the residual onto coarse node ic.
-template <typename T>
+template <typename T, bool SMALL = false>
 __device__ __forceinline__ T restrict_resid_node(const T* __restrict__ x, const T* __restrict__ b,
                                                  const T* __restrict__ mh, int ic, int Nf, int Nc, int dim, int pde,
                                                  double hf, double eps, bool transpose) {
   int j1, j2, j3;
-  node_coords(ic, Nc, dim, j1, j2, j3);
+  if (SMALL) node_coords_small(ic, Nc, dim, j1, j2, j3);
+  else node_coords(ic, Nc, dim, j1, j2, j3);
   const int f1 = 2 * j1 + 1, f2 = 2 * j2 + 1, f3 = 2 * j3 + 1;
   const T wt[3] = {(T)0.25, (T)0.5, (T)0.25};
   T acc = 0;
@@ -66,10 +68,11 @@ __device__ __forceinline__ T restrict_resid_node(const T* __restrict__ x, const 
 }
 
 // Bilinear/trilinear interpolation of the coarse correction at fine node i.
-template <typename T>
+template <typename T, bool SMALL = false>
 __device__ __forceinline__ T prolong_node(const T* __restrict__ xc, int i, int Nf, int Nc, int dim) {
   int i1, i2, i3;
-  node_coords(i, Nf, dim, i1, i2, i3);
+  if (SMALL) node_coords_small(i, Nf, dim, i1, i2, i3);
+  else node_coords(i, Nf, dim, i1, i2, i3);
   // per axis: fine 1-based index F; even -> coarse F/2 (weight 1); odd -> (F-1)/2, (F+1)/2 (1/2 each);
   // coarse 1-based indices 0 and Nc+1 are boundary (zero).
   int lo[3], hi[3];
@@ -137,90 +140,316 @@ __global__ void __launch_bounds__(kBS) k_mg_prolong(Inst I, int l, T* __restrict
 }
 
 // All levels l >= coarse_lev in one workgroup: V-cycle from b at coarse_lev
-// (global) to x at coarse_lev (global), every level's x, x2 and b in LDS.
-// Offsets are recomputed from the level sizes (no per-level pointer tables,
-// which would live in scratch memory); bit l of `alt` records whether level
-// l's iterate currently sits in x2.
+// (global) to x at coarse_lev (global).  Every level's x, x2, b and M_hat
+// diagonal live in LDS, and the level table is staged in LDS once, so the
+// phases (sweeps, restrictions, prolongations) touch no global memory.
+struct CoarseLevel {
+  int N, n, off;     // grid width, nodes, LDS offset (elements) of the level's 4 arrays
+  float hf;          // mesh width
+  double h;
+};
+
 template <typename T>
-__device__ __forceinline__ T* lds_level(T* lds, const Level* __restrict__ LV, int cl, int l, int which) {
-  int off = 0;
-  for (int m = cl; m < l; ++m) off += 3 * LV[m].n;
-  return lds + off + which * LV[l].n;
+__device__ __forceinline__ T coarse_diag(const CoarseLevel& C, int dim, int pde, double eps, int i1, int i2, T m) {
+  if (pde == 0) return (T)(2 * dim) / ((T)C.hf * (T)C.hf) + m;
+  return (T)op_diag(dim, pde, C.h, eps, i1, i2) + m;
+}
+
+template <typename T>
+__device__ __forceinline__ T coarse_resid(const T* __restrict__ x, const T* __restrict__ b, const T* __restrict__ ms,
+                                          int i, int i1, int i2, int i3, const CoarseLevel& C, int dim, int pde,
+                                          double eps, bool tr) {
+  return b[i] - (apply_op_s<T>(x, i, i1, i2, i3, C.N, C.N, C.N * C.N, dim, pde, C.h, eps, tr) + ms[i] * x[i]);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse(Inst I, int transpose, int guard) {
   if (guard && I.ctrl->stop) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ CoarseLevel LI[kMaxLev];
   T* lds = (T*)lds_raw;
   const int cl = I.coarse_lev, L = I.nlev;
-  const Level* __restrict__ LV = I.lvd;
   const bool tr = transpose != 0;
-  const int tid = threadIdx.x;
-  unsigned alt = 0;
-  {
-    const T* bg = (const T*)LV[cl].b;
-    T* B = lds_level(lds, LV, cl, cl, 2);
-    for (int i = tid; i < LV[cl].n; i += kCoarseBS) B[i] = bg[i];
+  const int tid = threadIdx.x, dim = I.dim, pde = I.pde;
+  const double eps = I.eps;
+  const T om = (T)I.omega;
+  if (tid == 0) {
+    int off = 0;
+    for (int l = cl; l < L; ++l) {
+      const Level& Lv = I.lvd[l];
+      LI[l].N = Lv.N;
+      LI[l].n = Lv.n;
+      LI[l].off = off;
+      LI[l].h = Lv.h;
+      LI[l].hf = (float)Lv.h;
+      off += 4 * Lv.n;
+    }
   }
   __syncthreads();
+  // stage b at the top level and M_hat at every level
+  for (int l = cl; l < L; ++l) {
+    const CoarseLevel C = LI[l];
+    const T* mg = (const T*)I.lvd[l].mh;
+    T* ms = lds + C.off + 3 * C.n;
+    for (int i = tid; i < C.n; i += kCoarseBS) ms[i] = mg[i];
+  }
+  {
+    const CoarseLevel C = LI[cl];
+    const T* bg = (const T*)I.lvd[cl].b;
+    T* B = lds + C.off + 2 * C.n;
+    for (int i = tid; i < C.n; i += kCoarseBS) B[i] = bg[i];
+  }
+  __syncthreads();
+  unsigned alt = 0;  // bit l: level l's iterate sits in x2
   // descend
   for (int l = cl; l < L - 1; ++l) {
-    const Level& Lv = LV[l];
-    const T* mh = (const T*)Lv.mh;
-    T* a = lds_level(lds, LV, cl, l, 0);
-    T* c = lds_level(lds, LV, cl, l, 1);
-    const T* B = lds_level(lds, LV, cl, l, 2);
+    const CoarseLevel C = LI[l];
+    T* a = lds + C.off;
+    T* c = a + C.n;
+    const T* B = a + 2 * C.n;
+    const T* ms = a + 3 * C.n;
     for (int s = 0; s < I.nu_pre; ++s) {
-      for (int i = tid; i < Lv.n; i += kCoarseBS)
-        c[i] = jacobi_node<T>(a, B, mh, i, Lv.N, I.dim, I.pde, Lv.h, I.eps, I.omega, s == 0, tr);
+      for (int i = tid; i < C.n; i += kCoarseBS) {
+        int i1, i2, i3;
+        node_coords_small(i, C.N, dim, i1, i2, i3);
+        const T d = coarse_diag<T>(C, dim, pde, eps, i1, i2, ms[i]);
+        c[i] = (s == 0) ? om * B[i] / d : a[i] + om * coarse_resid<T>(a, B, ms, i, i1, i2, i3, C, dim, pde, eps, tr) / d;
+      }
       __syncthreads();
       T* t = a; a = c; c = t;
       alt ^= 1u << l;
     }
-    const Level& Cv = LV[l + 1];
-    T* Bc = lds_level(lds, LV, cl, l + 1, 2);
-    for (int ic = tid; ic < Cv.n; ic += kCoarseBS)
-      Bc[ic] = restrict_resid_node<T>(a, B, mh, ic, Lv.N, Cv.N, I.dim, I.pde, Lv.h, I.eps, tr);
+    // residual into c, then full weighting into the next level's b
+    for (int i = tid; i < C.n; i += kCoarseBS) {
+      int i1, i2, i3;
+      node_coords_small(i, C.N, dim, i1, i2, i3);
+      c[i] = coarse_resid<T>(a, B, ms, i, i1, i2, i3, C, dim, pde, eps, tr);
+    }
+    __syncthreads();
+    const CoarseLevel Cc = LI[l + 1];
+    T* Bc = lds + Cc.off + 2 * Cc.n;
+    const int N = C.N;
+    for (int ic = tid; ic < Cc.n; ic += kCoarseBS) {
+      int j1, j2, j3;
+      node_coords_small(ic, Cc.N, dim, j1, j2, j3);
+      const int f = (2 * j1 + 1) + N * ((2 * j2 + 1) + (dim == 3 ? N * (2 * j3 + 1) : 0));
+      T acc;
+      if (dim == 2) {
+        acc = (T)0.25 * c[f] + (T)0.125 * (c[f - 1] + c[f + 1] + c[f - N] + c[f + N]) +
+              (T)0.0625 * (c[f - 1 - N] + c[f + 1 - N] + c[f - 1 + N] + c[f + 1 + N]);
+      } else {
+        acc = 0;
+        const int NN = N * N;
+        for (int cc = -1; cc <= 1; ++cc)
+          for (int bb = -1; bb <= 1; ++bb)
+            for (int aa = -1; aa <= 1; ++aa) {
+              const T w = (aa ? (T)0.25 : (T)0.5) * (bb ? (T)0.25 : (T)0.5) * (cc ? (T)0.25 : (T)0.5);
+              acc += w * c[f + aa + N * bb + NN * cc];
+            }
+      }
+      Bc[ic] = acc;
+    }
     __syncthreads();
   }
   // coarsest grid (a single node): exact solve
   {
-    const Level& Lv = LV[L - 1];
-    const T* mh = (const T*)Lv.mh;
-    T* X = lds_level(lds, LV, cl, L - 1, 0);
-    const T* B = lds_level(lds, LV, cl, L - 1, 2);
-    for (int i = tid; i < Lv.n; i += kCoarseBS) {
+    const CoarseLevel C = LI[L - 1];
+    T* X = lds + C.off;
+    const T* B = X + 2 * C.n;
+    const T* ms = X + 3 * C.n;
+    for (int i = tid; i < C.n; i += kCoarseBS) {
       int i1, i2, i3;
-      node_coords(i, Lv.N, I.dim, i1, i2, i3);
-      X[i] = B[i] / ((T)op_diag(I.dim, I.pde, Lv.h, I.eps, i1, i2) + mh[i]);
+      node_coords_small(i, C.N, dim, i1, i2, i3);
+      X[i] = B[i] / coarse_diag<T>(C, dim, pde, eps, i1, i2, ms[i]);
     }
     __syncthreads();
   }
   // ascend
   for (int l = L - 2; l >= cl; --l) {
-    const Level& Lv = LV[l];
-    const T* mh = (const T*)Lv.mh;
+    const CoarseLevel C = LI[l];
+    const CoarseLevel Cc = LI[l + 1];
     const int ca = (alt >> l) & 1u;
-    T* a = lds_level(lds, LV, cl, l, ca);
-    T* c = lds_level(lds, LV, cl, l, 1 - ca);
-    const T* B = lds_level(lds, LV, cl, l, 2);
-    const T* xc = lds_level(lds, LV, cl, l + 1, (alt >> (l + 1)) & 1u);
-    const int Nc = LV[l + 1].N;
-    for (int i = tid; i < Lv.n; i += kCoarseBS) a[i] += prolong_node<T>(xc, i, Lv.N, Nc, I.dim);
+    T* a = lds + C.off + ca * C.n;
+    T* c = lds + C.off + (1 - ca) * C.n;
+    const T* B = lds + C.off + 2 * C.n;
+    const T* ms = lds + C.off + 3 * C.n;
+    const T* xc = lds + Cc.off + ((alt >> (l + 1)) & 1u) * Cc.n;
+    for (int i = tid; i < C.n; i += kCoarseBS) a[i] += prolong_node<T, true>(xc, i, C.N, Cc.N, dim);
     __syncthreads();
     for (int s = 0; s < I.nu_post; ++s) {
-      for (int i = tid; i < Lv.n; i += kCoarseBS)
-        c[i] = jacobi_node<T>(a, B, mh, i, Lv.N, I.dim, I.pde, Lv.h, I.eps, I.omega, false, tr);
+      for (int i = tid; i < C.n; i += kCoarseBS) {
+        int i1, i2, i3;
+        node_coords_small(i, C.N, dim, i1, i2, i3);
+        const T d = coarse_diag<T>(C, dim, pde, eps, i1, i2, ms[i]);
+        c[i] = a[i] + om * coarse_resid<T>(a, B, ms, i, i1, i2, i3, C, dim, pde, eps, tr) / d;
+      }
       __syncthreads();
       T* t = a; a = c; c = t;
       alt ^= 1u << l;
     }
   }
-  T* xg = (T*)LV[cl].x;
-  const T* xs = lds_level(lds, LV, cl, cl, (alt >> cl) & 1u);
-  for (int i = tid; i < LV[cl].n; i += kCoarseBS) xg[i] = xs[i];
+  const CoarseLevel C = LI[cl];
+  T* xg = (T*)I.lvd[cl].x;
+  const T* xs = lds + C.off + ((alt >> cl) & 1u) * C.n;
+  for (int i = tid; i < C.n; i += kCoarseBS) xg[i] = xs[i];
 }
+
+
+// Poisson 2D specialization of the single-workgroup coarse V-cycle.  Per
+// level the iterates are stored with a zero ring (pitch N+2), so sweeps need
+// no boundary tests, and the diagonal d = 4/h^2 + M_hat and 1/d are staged
+// once, so sweeps need no division:
+//   x <- x + omega (b - d x + h^-2 (sum of neighbours)) / d.
+// LDS per level: 2 (N+2)^2 + 3 N^2 elements (x, x2 padded; b, d, 1/d).
+__host__ __device__ inline int coarse_p2_elems(int N) { return 2 * (N + 2) * (N + 2) + 3 * N * N; }
+
+template <typename T>
+__global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_p2(Inst I, int guard) {
+  if (guard && I.ctrl->stop) return;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ int LN[kMaxLev], LOFF[kMaxLev];
+  __shared__ T LIH2[kMaxLev];
+  T* lds = (T*)lds_raw;
+  const int cl = I.coarse_lev, L = I.nlev;
+  const int tid = threadIdx.x;
+  const T om = (T)I.omega;
+  if (tid == 0) {
+    int off = 0;
+    for (int l = cl; l < L; ++l) {
+      const int N = I.lvd[l].N;
+      LN[l] = N;
+      LOFF[l] = off;
+      const double h = I.lvd[l].h;
+      LIH2[l] = (T)(1.0 / (h * h));
+      off += coarse_p2_elems(N);
+    }
+  }
+  __syncthreads();
+  // layout of level l at LOFF[l]: xa[(N+2)^2], xb[(N+2)^2], b[N^2], d[N^2], dinv[N^2]
+  for (int l = cl; l < L; ++l) {
+    const int N = LN[l], P = N + 2, n = N * N;
+    T* xa = lds + LOFF[l];
+    T* xb = xa + P * P;
+    T* d = xb + P * P + n;
+    T* dinv = d + n;
+    for (int k = tid; k < P * P; k += kCoarseBS) { xa[k] = 0; xb[k] = 0; }
+    const T* mg = (const T*)I.lvd[l].mh;
+    const T c0 = (T)4 * LIH2[l];
+    for (int i = tid; i < n; i += kCoarseBS) {
+      const T dv = c0 + mg[i];
+      d[i] = dv;
+      dinv[i] = (T)1 / dv;
+    }
+  }
+  {
+    const int n = LN[cl] * LN[cl];
+    T* b = lds + LOFF[cl] + 2 * (LN[cl] + 2) * (LN[cl] + 2);
+    const T* bg = (const T*)I.lvd[cl].b;
+    for (int i = tid; i < n; i += kCoarseBS) b[i] = bg[i];
+  }
+  __syncthreads();
+  unsigned alt = 0;  // bit l: level l's iterate sits in xb
+  for (int l = cl; l < L - 1; ++l) {
+    const int N = LN[l], P = N + 2, n = N * N;
+    const T ih2 = LIH2[l];
+    T* a = lds + LOFF[l];
+    T* c = a + P * P;
+    const T* b = c + P * P;
+    const T* d = b + n;
+    const T* dinv = d + n;
+    for (int s = 0; s < I.nu_pre; ++s) {
+      for (int i = tid; i < n; i += kCoarseBS) {
+        int i2, i1;
+        fast_divmod(i, N, i2, i1);
+        const int p = (i1 + 1) + P * (i2 + 1);
+        T v;
+        if (s == 0) v = om * b[i] * dinv[i];
+        else v = a[p] + om * (b[i] - d[i] * a[p] + ih2 * (a[p - 1] + a[p + 1] + a[p - P] + a[p + P])) * dinv[i];
+        c[p] = v;
+      }
+      __syncthreads();
+      T* t = a; a = c; c = t;
+      alt ^= 1u << l;
+    }
+    for (int i = tid; i < n; i += kCoarseBS) {
+      int i2, i1;
+      fast_divmod(i, N, i2, i1);
+      const int p = (i1 + 1) + P * (i2 + 1);
+      c[p] = b[i] - d[i] * a[p] + ih2 * (a[p - 1] + a[p + 1] + a[p - P] + a[p + P]);
+    }
+    __syncthreads();
+    const int Nc = LN[l + 1], nc = Nc * Nc;
+    T* bc = lds + LOFF[l + 1] + 2 * (Nc + 2) * (Nc + 2);
+    for (int ic = tid; ic < nc; ic += kCoarseBS) {
+      int j2, j1;
+      fast_divmod(ic, Nc, j2, j1);
+      const int p = (2 * j1 + 2) + P * (2 * j2 + 2);  // fine node 2j+1 (0-based) in padded coordinates
+      bc[ic] = (T)0.25 * c[p] + (T)0.125 * (c[p - 1] + c[p + 1] + c[p - P] + c[p + P]) +
+               (T)0.0625 * (c[p - 1 - P] + c[p + 1 - P] + c[p - 1 + P] + c[p + 1 + P]);
+    }
+    __syncthreads();
+  }
+  {
+    // coarsest grid (one node): exact solve
+    const int l = L - 1, N = LN[l], P = N + 2, n = N * N;
+    T* a = lds + LOFF[l];
+    const T* b = a + 2 * P * P;
+    const T* dinv = b + 2 * n;
+    for (int i = tid; i < n; i += kCoarseBS) {
+      int i2, i1;
+      fast_divmod(i, N, i2, i1);
+      a[(i1 + 1) + P * (i2 + 1)] = b[i] * dinv[i];
+    }
+    __syncthreads();
+  }
+  for (int l = L - 2; l >= cl; --l) {
+    const int N = LN[l], P = N + 2, n = N * N;
+    const int Nc = LN[l + 1], Pc = Nc + 2;
+    const T ih2 = LIH2[l];
+    T* base = lds + LOFF[l];
+    const int ca = (alt >> l) & 1u;
+    T* a = base + ca * P * P;
+    T* c = base + (1 - ca) * P * P;
+    const T* b = base + 2 * P * P;
+    const T* d = b + n;
+    const T* dinv = d + n;
+    const T* xc = lds + LOFF[l + 1] + ((alt >> (l + 1)) & 1u) * Pc * Pc;
+    for (int i = tid; i < n; i += kCoarseBS) {
+      int i2, i1;
+      fast_divmod(i, N, i2, i1);
+      // bilinear interpolation: fine 1-based F maps to coarse F/2 (even) or the two neighbours (odd);
+      // in padded coarse coordinates the boundary nodes are the zero ring
+      const int F1 = i1 + 1, F2 = i2 + 1;
+      const int lo1 = F1 >> 1, hi1 = (F1 + 1) >> 1, lo2 = F2 >> 1, hi2 = (F2 + 1) >> 1;
+      const T v = (T)0.25 * (xc[lo1 + Pc * lo2] + xc[hi1 + Pc * lo2] + xc[lo1 + Pc * hi2] + xc[hi1 + Pc * hi2]);
+      a[F1 + P * F2] += v;
+    }
+    __syncthreads();
+    for (int s = 0; s < I.nu_post; ++s) {
+      for (int i = tid; i < n; i += kCoarseBS) {
+        int i2, i1;
+        fast_divmod(i, N, i2, i1);
+        const int p = (i1 + 1) + P * (i2 + 1);
+        c[p] = a[p] + om * (b[i] - d[i] * a[p] + ih2 * (a[p - 1] + a[p + 1] + a[p - P] + a[p + P])) * dinv[i];
+      }
+      __syncthreads();
+      T* t = a; a = c; c = t;
+      alt ^= 1u << l;
+    }
+  }
+  {
+    const int N = LN[cl], P = N + 2, n = N * N;
+    const T* a = lds + LOFF[cl] + ((alt >> cl) & 1u) * P * P;
+    T* xg = (T*)I.lvd[cl].x;
+    for (int i = tid; i < n; i += kCoarseBS) {
+      int i2, i1;
+      fast_divmod(i, N, i2, i1);
+      xg[i] = a[(i1 + 1) + P * (i2 + 1)];
+    }
+  }
+}
+template __global__ void k_mg_coarse_p2<float>(Inst, int);
+template __global__ void k_mg_coarse_p2<double>(Inst, int);
 
 // b_0 = (1 + Theta_y) x between the two solves of S_hat^-1.
 template <typename T>
@@ -240,5 +469,204 @@ __global__ void __launch_bounds__(kBS) k_mg_scale_ty(Inst I, const T* __restrict
 IPM_MG_INST(float)
 IPM_MG_INST(double)
 #undef IPM_MG_INST
+
+
+// ---------------------------------------------------------------- fused 2D level kernels
+//
+// Descent at level l: nu damped-Jacobi sweeps from a zero iterate, the
+// residual, and its full-weighting restriction, for a tile of TC x TC coarse
+// nodes in one workgroup (temporal blocking in LDS: the sweeps run on a
+// region that shrinks by one node per sweep).  Writes the smoothed iterate
+// of the tile's own fine nodes and the coarse right-hand side.
+constexpr int kTC = 8;    // coarse nodes per tile side (down kernel)
+constexpr int kTF = 16;   // fine nodes per tile side (up kernel)
+
+__host__ __device__ constexpr int down_width(int nu) { return 2 * kTC + 1 + 2 * nu; }
+__host__ __device__ constexpr int up_width(int nu) { return kTF + 2 * nu; }
+
+template <typename T>
+__device__ __forceinline__ T jacobi_lds(const T* __restrict__ xa, const T* __restrict__ bs, const T* __restrict__ ms,
+                                        int li, int W, int g1, int g2, int N, int pde, double h, double eps,
+                                        double omega, bool tr) {
+  const T m = ms[li];
+  const T d = (T)op_diag(2, pde, h, eps, g1, g2) + m;
+  const T xi = xa[li];
+  const T Ax = apply_op_s<T>(xa, li, g1, g2, 0, N, W, 0, 2, pde, h, eps, tr) + m * xi;
+  return xi + (T)omega * (bs[li] - Ax) / d;
+}
+
+// bsrc: right-hand side of level l; if ty != nullptr the right-hand side is
+// (1 + Theta_y) bsrc (start of the second solve of S_hat^-1, level 0 only).
+template <typename T, int NU>
+__global__ void __launch_bounds__(kBS) k_mg_down2d(Inst I, int l, const T* __restrict__ bsrc,
+                                                   const double* __restrict__ ty, T* __restrict__ xout, int transpose,
+                                                   int guard) {
+  if (guard && I.ctrl->stop) return;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const Level& F = I.lv[l];
+  const Level& C = I.lv[l + 1];
+  const int N = F.N, Nc = C.N;
+  constexpr int nu = NU;
+  constexpr int W = down_width(NU);
+  T* bs = (T*)lds_raw;
+  T* ms = bs + W * W;
+  T* xa = ms + W * W;
+  T* xb = xa + W * W;
+  const int J1 = blockIdx.x * kTC, J2 = blockIdx.y * kTC;
+  const int o1 = 2 * J1 - nu, o2 = 2 * J2 - nu;  // global fine coords of LDS (0, 0)
+  const T* __restrict__ mh = (const T*)F.mh;
+  const double h = F.h, eps = I.eps, om = I.omega;
+  const int pde = I.pde;
+  const bool tr = transpose != 0;
+  const int tid = threadIdx.x;
+  for (int k = tid; k < W * W; k += kBS) {
+    const int g1 = o1 + k % W, g2 = o2 + k / W;
+    T bv = 0, mv = 0;
+    if (g1 >= 0 && g1 < N && g2 >= 0 && g2 < N) {
+      const int gi = g1 + N * g2;
+      bv = bsrc[gi];
+      if (ty) bv = (T)(1.0 + ty[gi]) * bv;
+      mv = mh[gi];
+    }
+    bs[k] = bv;
+    ms[k] = mv;
+  }
+  __syncthreads();
+  if (ty) {
+    // keep the scaled right-hand side for the ascent (the tile's own fine nodes)
+    for (int k = tid; k < 4 * kTC * kTC; k += kBS) {
+      const int q1 = nu + k % (2 * kTC), q2 = nu + k / (2 * kTC);
+      const int g1 = o1 + q1, g2 = o2 + q2;
+      if (g1 < N && g2 < N) ((T*)F.b)[g1 + N * g2] = bs[q1 + W * q2];
+    }
+  }
+  // first sweep from zero on the whole region
+  for (int k = tid; k < W * W; k += kBS) {
+    const int g1 = o1 + k % W, g2 = o2 + k / W;
+    T v = 0;
+    if (g1 >= 0 && g1 < N && g2 >= 0 && g2 < N) v = (T)om * bs[k] / ((T)op_diag(2, pde, h, eps, g1, g2) + ms[k]);
+    xa[k] = v;
+  }
+  __syncthreads();
+  T* a = xa;
+  T* c = xb;
+#pragma unroll
+  for (int s = 1; s < nu; ++s) {
+    const int lo = s, hi = W - s;  // region shrinks by one node per sweep
+    const int w = hi - lo;
+    for (int k = tid; k < w * w; k += kBS) {
+      const int q1 = lo + k % w, q2 = lo + k / w;
+      const int li = q1 + W * q2;
+      const int g1 = o1 + q1, g2 = o2 + q2;
+      T v = 0;
+      if (g1 >= 0 && g1 < N && g2 >= 0 && g2 < N) v = jacobi_lds<T>(a, bs, ms, li, W, g1, g2, N, pde, h, eps, om, tr);
+      c[li] = v;
+    }
+    __syncthreads();
+    T* t = a; a = c; c = t;
+  }
+  // write the tile's own fine nodes of the smoothed iterate
+  for (int k = tid; k < 4 * kTC * kTC; k += kBS) {
+    const int q1 = nu + k % (2 * kTC), q2 = nu + k / (2 * kTC);
+    const int g1 = o1 + q1, g2 = o2 + q2;
+    if (g1 < N && g2 < N) xout[g1 + N * g2] = a[q1 + W * q2];
+  }
+  // residual on the restriction stencil region [nu, W - nu) into c
+  {
+    const int lo = nu, w = 2 * kTC + 1;
+    for (int k = tid; k < w * w; k += kBS) {
+      const int q1 = lo + k % w, q2 = lo + k / w;
+      const int li = q1 + W * q2;
+      const int g1 = o1 + q1, g2 = o2 + q2;
+      T r = 0;
+      if (g1 >= 0 && g1 < N && g2 >= 0 && g2 < N)
+        r = bs[li] - (apply_op_s<T>(a, li, g1, g2, 0, N, W, 0, 2, pde, h, eps, tr) + ms[li] * a[li]);
+      c[li] = r;
+    }
+  }
+  __syncthreads();
+  // full weighting onto the tile's coarse nodes
+  {
+    const int j1 = tid % kTC, j2 = tid / kTC;
+    const int c1 = J1 + j1, c2 = J2 + j2;
+    if (tid < kTC * kTC && c1 < Nc && c2 < Nc) {
+      const int q1 = nu + 2 * j1 + 1, q2 = nu + 2 * j2 + 1;  // fine 2c+1 in LDS coordinates
+      const int li = q1 + W * q2;
+      const T v = (T)0.25 * c[li] + (T)0.125 * (c[li - 1] + c[li + 1] + c[li - W] + c[li + W]) +
+                  (T)0.0625 * (c[li - 1 - W] + c[li + 1 - W] + c[li - 1 + W] + c[li + 1 + W]);
+      ((T*)C.b)[c1 + Nc * c2] = v;
+    }
+  }
+}
+
+// Ascent at level l: x = xpre + P xc, then nu damped-Jacobi sweeps, for a
+// tile of TF x TF fine nodes (halo nu in LDS).
+template <typename T, int NU>
+__global__ void __launch_bounds__(kBS) k_mg_up2d(Inst I, int l, const T* __restrict__ xpre, const T* __restrict__ xc,
+                                                 T* __restrict__ xout, int transpose, int guard) {
+  if (guard && I.ctrl->stop) return;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const Level& F = I.lv[l];
+  const int N = F.N, Nc = I.lv[l + 1].N;
+  constexpr int nu = NU;
+  constexpr int W = up_width(NU);
+  T* bs = (T*)lds_raw;
+  T* ms = bs + W * W;
+  T* xa = ms + W * W;
+  T* xb = xa + W * W;
+  const int o1 = blockIdx.x * kTF - nu, o2 = blockIdx.y * kTF - nu;
+  const T* __restrict__ mh = (const T*)F.mh;
+  const T* __restrict__ b = (const T*)F.b;
+  const double h = F.h, eps = I.eps, om = I.omega;
+  const int pde = I.pde;
+  const bool tr = transpose != 0;
+  const int tid = threadIdx.x;
+  for (int k = tid; k < W * W; k += kBS) {
+    const int g1 = o1 + k % W, g2 = o2 + k / W;
+    T bv = 0, mv = 0, xv = 0;
+    if (g1 >= 0 && g1 < N && g2 >= 0 && g2 < N) {
+      const int gi = g1 + N * g2;
+      bv = b[gi];
+      mv = mh[gi];
+      xv = xpre[gi] + prolong_node<T>(xc, gi, N, Nc, 2);
+    }
+    bs[k] = bv;
+    ms[k] = mv;
+    xa[k] = xv;
+  }
+  __syncthreads();
+  T* a = xa;
+  T* c = xb;
+#pragma unroll
+  for (int s = 0; s < nu; ++s) {
+    const int lo = s + 1, hi = W - s - 1;
+    const int w = hi - lo;
+    for (int k = tid; k < w * w; k += kBS) {
+      const int q1 = lo + k % w, q2 = lo + k / w;
+      const int li = q1 + W * q2;
+      const int g1 = o1 + q1, g2 = o2 + q2;
+      T v = 0;
+      if (g1 >= 0 && g1 < N && g2 >= 0 && g2 < N) v = jacobi_lds<T>(a, bs, ms, li, W, g1, g2, N, pde, h, eps, om, tr);
+      c[li] = v;
+    }
+    __syncthreads();
+    T* t = a; a = c; c = t;
+  }
+  for (int k = tid; k < kTF * kTF; k += kBS) {
+    const int q1 = nu + k % kTF, q2 = nu + k / kTF;
+    const int g1 = o1 + q1, g2 = o2 + q2;
+    if (g1 < N && g2 < N) xout[g1 + N * g2] = a[q1 + W * q2];
+  }
+}
+
+#define IPM_MG2_INST(T, NU)                                                                              \
+  template __global__ void k_mg_down2d<T, NU>(Inst, int, const T*, const double*, T*, int, int);       \
+  template __global__ void k_mg_up2d<T, NU>(Inst, int, const T*, const T*, T*, int, int);
+#define IPM_MG2_INST_ALL(T) IPM_MG2_INST(T, 1) IPM_MG2_INST(T, 2) IPM_MG2_INST(T, 3) IPM_MG2_INST(T, 4) \
+  IPM_MG2_INST(T, 5) IPM_MG2_INST(T, 6)
+IPM_MG2_INST_ALL(float)
+IPM_MG2_INST_ALL(double)
+#undef IPM_MG2_INST_ALL
+#undef IPM_MG2_INST
 
 }  // namespace ipm

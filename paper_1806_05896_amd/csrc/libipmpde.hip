@@ -162,29 +162,52 @@ static int level_count(int N) {
 
 static size_t pow_dim(int N, int dim) { return dim == 2 ? (size_t)N * N : (size_t)N * N * N; }
 
-// LDS budget of the single-workgroup coarse kernel, and the largest grid it
-// takes (finer levels run as grid-wide kernels).
-static constexpr size_t kCoarseLds = 64 * 1024;
+// LDS budget of the single-workgroup coarse kernel (gfx950 has 160 KB of
+// LDS per CU), and the largest grid it takes; finer levels run as
+// grid-wide kernels.
+static constexpr size_t kCoarseLds = 150 * 1024;
 
-static int pick_coarse(const Level* lv, int nlev, size_t elem, int dim) {
-  const int nmax = dim == 2 ? 31 : 15;
+// p2: the Poisson 2D coarse kernel (padded layout), else the generic one.
+static size_t coarse_level_elems(const Level& L, bool p2) {
+  return p2 ? (size_t)coarse_p2_elems(L.N) : 4 * (size_t)L.n;
+}
+
+static int pick_coarse(const Level* lv, int nlev, size_t elem, int dim, bool p2) {
+  const int nmax = dim == 2 ? 63 : 15;
   int cl = nlev - 1;
   size_t need = 0;
   for (int l = nlev - 1; l >= 0; --l) {
-    need += 3 * (size_t)lv[l].n * elem;
+    need += coarse_level_elems(lv[l], p2) * elem;
     if (need > kCoarseLds || lv[l].N > nmax) break;
     cl = l;
   }
   return cl;
 }
 
-static size_t coarse_lds_bytes(const Level* lv, int nlev, int cl, size_t elem) {
+static size_t coarse_lds_bytes(const Level* lv, int nlev, int cl, size_t elem, bool p2) {
   size_t need = 0;
-  for (int l = cl; l < nlev; ++l) need += 3 * (size_t)lv[l].n * elem;
+  for (int l = cl; l < nlev; ++l) need += coarse_level_elems(lv[l], p2) * elem;
   return need;
 }
 
+// Allow the coarse kernel more than the default 64 KB of dynamic LDS.
+static int set_coarse_lds_limit() {
+  static bool done = false;
+  if (done) return IPMPDE_OK;
+  HIP_TRY(hipFuncSetAttribute((const void*)k_mg_coarse<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)kCoarseLds));
+  HIP_TRY(hipFuncSetAttribute((const void*)k_mg_coarse<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)kCoarseLds));
+  HIP_TRY(hipFuncSetAttribute((const void*)k_mg_coarse_p2<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)kCoarseLds));
+  HIP_TRY(hipFuncSetAttribute((const void*)k_mg_coarse_p2<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)kCoarseLds));
+  done = true;
+  return IPMPDE_OK;
+}
+
 static int ensure_mg(ipmpde_problem* P, bool fp32) {
+  TRY(set_coarse_lds_limit());
   bool& have = fp32 ? P->have32 : P->have64;
   Level* lv = fp32 ? P->lv32 : P->lv64;
   if (have) return IPMPDE_OK;
@@ -194,6 +217,7 @@ static int ensure_mg(ipmpde_problem* P, bool fp32) {
     lv[l].N = N;
     lv[l].n = (int)pow_dim(N, P->dim);
     lv[l].h = 1.0 / (N + 1);
+    lv[l].invN = 1.0f / (float)N;
     const size_t nb = (size_t)lv[l].n * el;
     TRY(dalloc(P, &lv[l].x, nb));
     TRY(dalloc(P, &lv[l].x2, nb));
@@ -205,7 +229,7 @@ static int ensure_mg(ipmpde_problem* P, bool fp32) {
     HIP_TRY(hipMemset(lv[l].mh, 0, nb));
     N = (N - 1) / 2;
   }
-  (fp32 ? P->coarse32 : P->coarse64) = pick_coarse(lv, P->nlev, el, P->dim);
+  (fp32 ? P->coarse32 : P->coarse64) = pick_coarse(lv, P->nlev, el, P->dim, P->dim == 2 && P->pde == IPMPDE_POISSON);
   Level*& lvd = fp32 ? P->lvd32 : P->lvd64;
   TRY(dalloc(P, (void**)&lvd, sizeof(Level) * kMaxLev));
   HIP_TRY(hipMemcpy(lvd, lv, sizeof(Level) * kMaxLev, hipMemcpyHostToDevice));
@@ -270,7 +294,7 @@ static int check_options(const ipmpde_problem* P, const ipmpde_options& o) {
   if (!(o.krylov_tol > 0 && o.krylov_tol < 1)) return fail(IPMPDE_EINVAL, "krylov_tol must be in (0,1)");
   if (o.krylov_maxit < 1) return fail(IPMPDE_EINVAL, "krylov_maxit must be >= 1");
   if (o.vcycles != 1) return fail(IPMPDE_EINVAL, "vcycles must be 1");
-  if (o.nu_pre < 1 || o.nu_pre > 8 || o.nu_post < 1 || o.nu_post > 8) return fail(IPMPDE_EINVAL, "nu out of [1,8]");
+  if (o.nu_pre < 1 || o.nu_pre > 6 || o.nu_post < 1 || o.nu_post > 6) return fail(IPMPDE_EINVAL, "nu out of [1,6]");
   if (o.krylov == IPMPDE_MINRES && o.nu_pre != o.nu_post)
     return fail(IPMPDE_EINVAL, "MINRES needs nu_pre == nu_post (symmetric preconditioner)");
   if (!(o.omega >= 0 && o.omega < 1.5)) return fail(IPMPDE_EINVAL, "omega out of range");
@@ -290,7 +314,16 @@ static int resolve_opts(const ipmpde_options* in, ipmpde_options* out) {
 // multigrid launch sequence
 
 template <typename T>
-static void mg_vcycle(ipmpde_problem* P, int transpose, int guard, hipStream_t s, T** out) {
+static void launch_coarse(ipmpde_problem* P, int transpose, int guard, hipStream_t s) {
+  const Inst& I = P->I;
+  const bool p2 = P->dim == 2 && P->pde == IPMPDE_POISSON;
+  const size_t lds = coarse_lds_bytes(I.lv, I.nlev, I.coarse_lev, sizeof(T), p2);
+  if (p2) hipLaunchKernelGGL(k_mg_coarse_p2<T>, dim3(1), dim3(kCoarseBS), lds, s, I, guard);
+  else hipLaunchKernelGGL(k_mg_coarse<T>, dim3(1), dim3(kCoarseBS), lds, s, I, transpose, guard);
+}
+
+template <typename T>
+static void mg_vcycle_generic(ipmpde_problem* P, int transpose, int guard, hipStream_t s, T** out) {
   const Inst& I = P->I;
   const int cl = I.coarse_lev;
   T* cur[kMaxLev];
@@ -305,8 +338,7 @@ static void mg_vcycle(ipmpde_problem* P, int transpose, int guard, hipStream_t s
     cur[l] = a;
     hipLaunchKernelGGL(k_mg_restrict<T>, dim3(nblk(I.lv[l + 1].n)), dim3(kBS), 0, s, I, l, a, transpose, guard);
   }
-  const size_t lds = coarse_lds_bytes(I.lv, I.nlev, cl, sizeof(T));
-  hipLaunchKernelGGL(k_mg_coarse<T>, dim3(1), dim3(kCoarseBS), lds, s, I, transpose, guard);
+  launch_coarse<T>(P, transpose, guard, s);
   cur[cl] = (T*)I.lv[cl].x;
   for (int l = cl - 1; l >= 0; --l) {
     const Level& L = I.lv[l];
@@ -322,14 +354,71 @@ static void mg_vcycle(ipmpde_problem* P, int transpose, int guard, hipStream_t s
   *out = cur[0];
 }
 
+template <typename T>
+static void launch_down2d(int nu, dim3 g, size_t lds, hipStream_t s, const Inst& I, int l, const T* bsrc,
+                          const double* ty, T* xout, int tr, int guard) {
+  switch (nu) {
+#define D_(NU) case NU: hipLaunchKernelGGL((k_mg_down2d<T, NU>), g, dim3(kBS), lds, s, I, l, bsrc, ty, xout, tr, guard); break;
+    D_(1) D_(2) D_(3) D_(4) D_(5) D_(6)
+#undef D_
+  }
+}
+template <typename T>
+static void launch_up2d(int nu, dim3 g, size_t lds, hipStream_t s, const Inst& I, int l, const T* xpre, const T* xc,
+                        T* xout, int tr, int guard) {
+  switch (nu) {
+#define U_(NU) case NU: hipLaunchKernelGGL((k_mg_up2d<T, NU>), g, dim3(kBS), lds, s, I, l, xpre, xc, xout, tr, guard); break;
+    U_(1) U_(2) U_(3) U_(4) U_(5) U_(6)
+#undef U_
+  }
+}
+
+// 2D V-cycle with the fused level kernels: per level one descent launch
+// (smoothing + residual + restriction) and one ascent launch (prolongation +
+// smoothing).  scaled_src != nullptr: the level-0 right-hand side is
+// (1 + Theta_y) scaled_src.  Output: level 0's x2.
+template <typename T>
+static void mg_vcycle_2d(ipmpde_problem* P, int transpose, int guard, const T* scaled_src, hipStream_t s, T** out) {
+  const Inst& I = P->I;
+  const int cl = I.coarse_lev;
+  const size_t ldd = 4 * (size_t)down_width(I.nu_pre) * down_width(I.nu_pre) * sizeof(T);
+  const size_t ldu = 4 * (size_t)up_width(I.nu_post) * up_width(I.nu_post) * sizeof(T);
+  for (int l = 0; l < cl; ++l) {
+    const Level& L = I.lv[l];
+    const int nt = div_up(I.lv[l + 1].N, kTC);
+    const T* bsrc = (l == 0 && scaled_src) ? scaled_src : (const T*)L.b;
+    const double* ty = (l == 0 && scaled_src) ? I.ty : nullptr;
+    launch_down2d<T>(I.nu_pre, dim3(nt, nt), ldd, s, I, l, bsrc, ty, (T*)L.x, transpose, guard);
+  }
+  launch_coarse<T>(P, transpose, guard, s);
+  for (int l = cl - 1; l >= 0; --l) {
+    const Level& L = I.lv[l];
+    const int nt = div_up(L.N, kTF);
+    const T* xc = (l + 1 == cl) ? (const T*)I.lv[cl].x : (const T*)I.lv[l + 1].x2;
+    launch_up2d<T>(I.nu_post, dim3(nt, nt), ldu, s, I, l, (const T*)L.x, xc, (T*)L.x2, transpose, guard);
+  }
+  *out = cl == 0 ? (T*)I.lv[0].x : (T*)I.lv[0].x2;
+}
+
+template <typename T>
+static void mg_vcycle(ipmpde_problem* P, int transpose, int guard, hipStream_t s, T** out) {
+  if (P->dim == 2) mg_vcycle_2d<T>(P, transpose, guard, nullptr, s, out);
+  else mg_vcycle_generic<T>(P, transpose, guard, s, out);
+}
+
 // S_hat^-1 applied to lv[0].b (Sec. 4.2): V-cycle on A + M_hat, scale by
 // 1 + Theta_y, V-cycle on (A + M_hat)^T.  Returns the level-0 output array.
 template <typename T>
 static T* schur_inv(ipmpde_problem* P, int guard, hipStream_t s) {
   T* x1;
+  T* x2;
+  if (P->dim == 2 && P->I.coarse_lev > 0) {
+    mg_vcycle_2d<T>(P, 0, guard, nullptr, s, &x1);
+    mg_vcycle_2d<T>(P, 1, guard, x1, s, &x2);
+    return x2;
+  }
   mg_vcycle<T>(P, 0, guard, s, &x1);
   hipLaunchKernelGGL(k_mg_scale_ty<T>, dim3(nblk(P->n)), dim3(kBS), 0, s, P->I, (const T*)x1, guard);
-  T* x2;
   mg_vcycle<T>(P, 1, guard, s, &x2);
   return x2;
 }
@@ -398,6 +487,11 @@ static int run_minres_chunk(ipmpde_problem* P, const ipmpde_options& o, int par,
   return IPMPDE_OK;
 }
 
+// Attainable accuracy: a relative residual below c eps |(|K||x| + |b|)| / |b|
+// cannot be resolved by evaluating b - K x in FP64; the Krylov solves accept
+// it as converged when the requested tolerance lies below that floor.
+static double floor_factor() { return 16.0 * 2.220446049250313e-16; }
+
 // Solve K X = rhs to |rhs - K X| <= tol |rhs|.  MINRES stops on its tracked
 // residual; the true residual is then checked, and a drift of the recurrence
 // (rare) restarts MINRES from the true residual.  Returns IPMPDE_OK or
@@ -435,7 +529,7 @@ static int minres_solve(ipmpde_problem* P, const ipmpde_options& o, hipStream_t 
     const double rel = P->ctrl_h->rnorm / bnorm;
     *its = total;
     *relres = rel;
-    if (rel <= tol) return IPMPDE_OK;
+    if (rel <= std::max(tol, floor_factor() * P->ctrl_h->rfloor / bnorm)) return IPMPDE_OK;
     if (!(rel == rel)) return fail(IPMPDE_EBREAKDOWN, "NaN in the Krylov iterate");
     if (P->ctrl_h->breakdown) return fail(IPMPDE_EKRYLOV, "MINRES breakdown (preconditioner not positive definite)");
     if (total >= o.krylov_maxit) return fail(IPMPDE_EKRYLOV, "Krylov iteration limit reached");
@@ -696,14 +790,14 @@ extern "C" int ipmpde_problem_create(const ipmpde_grid* grid, const ipmpde_pde* 
       (rc = dalloc_t(P, &P->Rt, n4)))
     return cleanup(rc);
   const size_t nparts = std::max<size_t>(4 * (size_t)nblk((long)n), 64 * kBS) + 64;
-  if ((rc = dalloc_t(P, &I.partials, nparts)) || (rc = dalloc_t(P, &I.counter, 64)) ||
+  if ((rc = dalloc_t(P, &I.partials, nparts)) || (rc = dalloc_t(P, &I.counter, kTicketStride * (kTicketGroups + 1))) ||
       (rc = dalloc(P, (void**)&I.ctrl, sizeof(KrylovCtrl))) || (rc = dalloc_t(P, &I.stat, 16)))
     return cleanup(rc);
   auto hip_fail = [&](hipError_t e, const char* what) {
     return cleanup(fail(IPMPDE_EDEVICE, std::string(what) + ": " + hipGetErrorString(e)));
   };
   hipError_t e;
-  if ((e = hipMemset(I.counter, 0, 64 * sizeof(unsigned))) != hipSuccess) return hip_fail(e, "hipMemset");
+  if ((e = hipMemset(I.counter, 0, kTicketStride * (kTicketGroups + 1) * sizeof(unsigned))) != hipSuccess) return hip_fail(e, "hipMemset");
   if ((e = hipMemset(I.ctrl, 0, sizeof(KrylovCtrl))) != hipSuccess) return hip_fail(e, "hipMemset");
   if ((e = hipMemset(I.stat, 0, 16 * sizeof(double))) != hipSuccess) return hip_fail(e, "hipMemset");
   for (int k = 0; k < nd; ++k)

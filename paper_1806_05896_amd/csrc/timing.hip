@@ -16,15 +16,32 @@ static double vcycle_bytes(const Inst& I) {
     b += (2 * n + nc) * e;                         // prolongation + correction
     b += I.nu_post * 4 * n * e;                    // post-smoothing
   }
-  for (int l = I.coarse_lev; l < I.nlev; ++l) b += I.lv[l].n * e;  // coarse diagonals
+  for (int l = I.coarse_lev; l < I.nlev; ++l) b += I.lv[l].n * e;  // coarse diagonals (M_hat)
   b += 2 * I.lv[I.coarse_lev].n * e;
   return b;
+}
+
+template <typename T>
+static void launch_down(ipmpde_problem* P, hipStream_t s) {
+  const Inst& I = P->I;
+  const size_t ldd = 4 * (size_t)down_width(I.nu_pre) * down_width(I.nu_pre) * sizeof(T);
+  const int nt = div_up(I.lv[1].N, kTC);
+  launch_down2d<T>(I.nu_pre, dim3(nt, nt), ldd, s, I, 0, (const T*)I.lv[0].b, (const double*)nullptr, (T*)I.lv[0].x, 0, 0);
+}
+template <typename T>
+static void launch_up(ipmpde_problem* P, hipStream_t s) {
+  const Inst& I = P->I;
+  const size_t ldu = 4 * (size_t)up_width(I.nu_post) * up_width(I.nu_post) * sizeof(T);
+  const int nt = div_up(I.lv[0].N, kTF);
+  launch_up2d<T>(I.nu_post, dim3(nt, nt), ldu, s, I, 0, (const T*)I.lv[0].x, (const T*)I.lv[1].x2, (T*)I.lv[0].x2, 0, 0);
 }
 
 extern "C" int ipmpde_time_kernel(ipmpde_problem* P, const ipmpde_options* opts, int kernel, int reps,
                                   ipmpde_stream stream, double* avg_ms, double* bytes) {
   if (!P || !avg_ms || !bytes) return fail(IPMPDE_EINVAL, "NULL argument");
   if (reps < 1 || reps > 100000) return fail(IPMPDE_EINVAL, "reps out of range");
+  if ((kernel == 4 || kernel == 5) && (P->dim != 2 || P->nlev < 2))
+    return fail(IPMPDE_EINVAL, "fused level kernels exist for 2D grids with at least two levels");
   ipmpde_options o;
   resolve_opts(opts, &o);
   TRY(check_options(P, o));
@@ -60,6 +77,14 @@ extern "C" int ipmpde_time_kernel(ipmpde_problem* P, const ipmpde_options* opts,
         if (f32) { float* x; mg_vcycle<float>(P, 0, 0, s, &x); }
         else { double* x; mg_vcycle<double>(P, 0, 0, s, &x); }
         break;
+      case 4:
+        if (f32) launch_down<float>(P, s);
+        else launch_down<double>(P, s);
+        break;
+      case 5:
+        if (f32) launch_up<float>(P, s);
+        else launch_up<double>(P, s);
+        break;
     }
   };
   switch (kernel) {
@@ -67,6 +92,9 @@ extern "C" int ipmpde_time_kernel(ipmpde_problem* P, const ipmpde_options* opts,
     case 1: *bytes = 4.0 * n * e; break;
     case 2: *bytes = 22.0 * n * 8 + n * e; break;
     case 3: *bytes = f32 ? vcycle_bytes<float>(I) : vcycle_bytes<double>(I); break;
+    case 4: *bytes = (3.0 * n + I.lv[1].n) * e; break;  // reads b, M_hat; writes x, coarse b
+    case 5: *bytes = (4.0 * n + I.lv[1].n) * e; break;  // reads x, b, M_hat, coarse x; writes x
+
     default: return fail(IPMPDE_EINVAL, "unknown kernel id");
   }
   // the timed K2 writes into R instead of a Lanczos vector: copy something bounded there first

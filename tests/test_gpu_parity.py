@@ -191,3 +191,37 @@ def test_ipm_parity_cases(case, krylov, precond):
     print(f"  rc={rc} nli={s.nli}/{ref.nli} its={s.krylov_its} rel u={_rel(u, ref.u):.2e} y={_rel(y, ref.y):.2e}")
     assert rc == 0 and s.nli == ref.nli
     assert _rel(u, ref.u) <= 1e-6 and _rel(y, ref.y) <= 1e-6
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", ["poisson_small", "poisson_box63", "convdiff_31", "poisson3d_15", "poisson_box255"])
+def test_schur_multigrid_quality(case, prec):
+    """The multigrid application of S_hat^-1 (Sec. 4.2, eq. (SchurApprox)) is close to the exact
+    S_hat^-1 = (A + M_hat)^-T (I + Theta_y) (A + M_hat)^-1 built here with SciPy: one V-cycle per
+    solve with 2+2 damped Jacobi sweeps must reduce the error below 0.35 (a V-cycle that is wrong
+    anywhere - restriction, prolongation, coarse solve - lands well above that)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    from oracle.ipm import barrier_diagonals
+    Options, Problem = _api()
+    print(f"[mg-quality] {case} {prec}", flush=True)
+    data = W.poisson2d_511(seed=0, N=255) if case == "poisson_box255" else CASES[case]()
+    disc, st = _generic_state(data, steps=3)
+    mu = st.mu * data.sigma
+    ty, tw, tv = barrier_diagonals(data, st)
+    a = data.alpha
+    mh = np.sqrt((tw + tv) / (a * (tw + tv) + tw * tv) * (1 + ty))
+    Am = (disc.A + sp.diags(mh)).tocsc()
+    lu = spla.splu(Am)
+    r = np.random.default_rng(7).normal(size=data.n)
+    exact = lu.solve((1 + ty) * lu.solve(r), trans="T")
+    opts = Options(mg_precision=prec)
+    x = np.zeros(4 * data.n)
+    x[3 * data.n:] = r
+    with Problem(data) as prob:
+        _load_state(prob, st, data.y_a is not None)
+        prob.newton_setup(mu, opts)
+        z = prob.apply_precond(torch.tensor(x, device="cuda", dtype=torch.float64), opts).cpu().numpy()
+    err = _rel(z[3 * data.n:], exact)
+    print(f"  rel err of S_hat^-1 by multigrid: {err:.3f}", flush=True)
+    assert err <= 0.35
