@@ -26,7 +26,8 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_NAMES = {0: "k_saddle (saddle matvec)", 1: "k_mg_jacobi (finest-level smoothing sweep)",
                 2: "k_minres_k2 (Lanczos + diagonal preconditioner)", 3: "one V-cycle",
                 4: "k_mg_down2d (finest level: smoothing + residual + restriction)",
-                5: "k_mg_up2d (finest level: prolongation + smoothing)"}
+                5: "k_mg_up2d (finest level: prolongation + smoothing)",
+                6: "k_minres_k1 (MINRES update + saddle matvec + dots)"}
 
 
 def log(*a):
@@ -93,7 +94,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 V-cycle variant")
-    ap.add_argument("--kernel", type=int, default=5, help="kernel id for the roofline figure")
+    ap.add_argument("--kernel", type=int, default=6, help="kernel id for the roofline figure")
     ap.add_argument("--N", type=int, default=511)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -151,7 +152,7 @@ def main():
                           "kernel": KERNEL_NAMES[args.kernel], "avg_us": ms * 1e3,
                           "algorithmic_bytes_per_launch": nbytes}
     kern = {}
-    for k in (0, 2, 3, 4, 5):
+    for k in (0, 2, 3, 4, 5, 6):
         ms_k, b_k = prob.time_kernel(k, reps=100, opts=opts, stream=torch.cuda.current_stream())
         kern[KERNEL_NAMES[k]] = {"avg_us": ms_k * 1e3, "GB/s": b_k / (ms_k * 1e-3) / 1e9}
     result["kernels"] = kern

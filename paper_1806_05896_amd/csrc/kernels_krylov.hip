@@ -197,11 +197,12 @@ __global__ void __launch_bounds__(kBS) k_minres_k1(Inst I, const double* __restr
                                                    const double* __restrict__ Zprev, double* __restrict__ Wsame,
                                                    const double* __restrict__ Wother, double* __restrict__ X,
                                                    double* __restrict__ Q, double* __restrict__ KWsame,
-                                                   const double* __restrict__ KWother, double* __restrict__ Rt) {
+                                                   const double* __restrict__ KWother, double* __restrict__ Rt,
+                                                   int timing) {
   __shared__ double smem[2 * kBS / 64];
   KrylovCtrl* C = I.ctrl;
-  if (C->stop) return;
-  const int pending = C->pending;
+  if (C->stop && !timing) return;
+  const int pending = timing ? 1 : C->pending;
   const int i = blockIdx.x * kBS + threadIdx.x;
   double acc[2] = {0.0, 0.0};
   if (i < I.n) {
@@ -232,7 +233,7 @@ __global__ void __launch_bounds__(kBS) k_minres_k1(Inst I, const double* __restr
   }
   if (grid_reduce<kSum, 2, kBS>(acc, I.partials, I.counter, gridDim.x, blockIdx.x, smem) && threadIdx.x == 0) {
     C->delta = acc[0];
-    if (pending) {
+    if (pending && !timing) {
       C->rtrack = sqrt(acc[1]);
       C->pending = 0;
       if (C->rtrack <= C->rtarget || !(acc[1] == acc[1])) C->stop = 1;

@@ -303,6 +303,21 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse(Inst I, int transpose, 
 // LDS per level: 2 (N+2)^2 + 3 N^2 elements (x, x2 padded; b, d, 1/d).
 __host__ __device__ inline int coarse_p2_elems(int N) { return 2 * (N + 2) * (N + 2) + 3 * N * N; }
 
+// Loop over the nodes (i1, i2) of an N x N level (N + 1 a power of two) with
+// a power-of-two thread layout: no division.  Defines i (compact index) and
+// p (index in the zero-ring padded layout of pitch P = N + 2).
+#define P2_FOR(NN)                                                                   \
+  {                                                                                  \
+    const int sh_ = 31 - __builtin_clz((NN) + 1), step_ = kCoarseBS >> sh_;          \
+    const int i1 = tid & ((1 << sh_) - 1);                                           \
+    for (int i2 = tid >> sh_; i2 < (NN) && i1 < (NN); i2 += step_) {                 \
+      const int i = i1 + (NN) * i2;                                                  \
+      const int p = (i1 + 1) + ((NN) + 2) * (i2 + 1);                                \
+      (void)i; (void)p;
+#define P2_END \
+    }          \
+  }
+
 template <typename T>
 __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_p2(Inst I, int guard) {
   if (guard && I.ctrl->stop) return;
@@ -358,34 +373,28 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_p2(Inst I, int guard) {
     const T* d = b + n;
     const T* dinv = d + n;
     for (int s = 0; s < I.nu_pre; ++s) {
-      for (int i = tid; i < n; i += kCoarseBS) {
-        int i2, i1;
-        fast_divmod(i, N, i2, i1);
-        const int p = (i1 + 1) + P * (i2 + 1);
-        T v;
-        if (s == 0) v = om * b[i] * dinv[i];
-        else v = a[p] + om * (b[i] - d[i] * a[p] + ih2 * (a[p - 1] + a[p + 1] + a[p - P] + a[p + P])) * dinv[i];
-        c[p] = v;
+      if (s == 0) {
+        P2_FOR(N) c[p] = om * b[i] * dinv[i]; P2_END
+      } else {
+        P2_FOR(N) c[p] = a[p] + om * (b[i] - d[i] * a[p] + ih2 * (a[p - 1] + a[p + 1] + a[p - P] + a[p + P])) * dinv[i]; P2_END
       }
       __syncthreads();
       T* t = a; a = c; c = t;
       alt ^= 1u << l;
     }
-    for (int i = tid; i < n; i += kCoarseBS) {
-      int i2, i1;
-      fast_divmod(i, N, i2, i1);
-      const int p = (i1 + 1) + P * (i2 + 1);
-      c[p] = b[i] - d[i] * a[p] + ih2 * (a[p - 1] + a[p + 1] + a[p - P] + a[p + P]);
-    }
+    P2_FOR(N) c[p] = b[i] - d[i] * a[p] + ih2 * (a[p - 1] + a[p + 1] + a[p - P] + a[p + P]); P2_END
     __syncthreads();
     const int Nc = LN[l + 1], nc = Nc * Nc;
     T* bc = lds + LOFF[l + 1] + 2 * (Nc + 2) * (Nc + 2);
-    for (int ic = tid; ic < nc; ic += kCoarseBS) {
-      int j2, j1;
-      fast_divmod(ic, Nc, j2, j1);
-      const int p = (2 * j1 + 2) + P * (2 * j2 + 2);  // fine node 2j+1 (0-based) in padded coordinates
-      bc[ic] = (T)0.25 * c[p] + (T)0.125 * (c[p - 1] + c[p + 1] + c[p - P] + c[p + P]) +
-               (T)0.0625 * (c[p - 1 - P] + c[p + 1 - P] + c[p - 1 + P] + c[p + 1 + P]);
+    {
+      const int sh = 31 - __builtin_clz(Nc + 1), msk = (1 << sh) - 1, step = kCoarseBS >> sh;
+      const int j1 = tid & msk;
+      for (int j2 = tid >> sh; j2 < Nc && j1 < Nc; j2 += step) {
+        const int ic = j1 + Nc * j2;
+        const int p = (2 * j1 + 2) + P * (2 * j2 + 2);  // fine node 2j+1 (0-based) in padded coordinates
+        bc[ic] = (T)0.25 * c[p] + (T)0.125 * (c[p - 1] + c[p + 1] + c[p - P] + c[p + P]) +
+                 (T)0.0625 * (c[p - 1 - P] + c[p + 1 - P] + c[p - 1 + P] + c[p + 1 + P]);
+      }
     }
     __syncthreads();
   }
@@ -395,11 +404,7 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_p2(Inst I, int guard) {
     T* a = lds + LOFF[l];
     const T* b = a + 2 * P * P;
     const T* dinv = b + 2 * n;
-    for (int i = tid; i < n; i += kCoarseBS) {
-      int i2, i1;
-      fast_divmod(i, N, i2, i1);
-      a[(i1 + 1) + P * (i2 + 1)] = b[i] * dinv[i];
-    }
+    P2_FOR(N) a[p] = b[i] * dinv[i]; P2_END
     __syncthreads();
   }
   for (int l = L - 2; l >= cl; --l) {
@@ -414,24 +419,17 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_p2(Inst I, int guard) {
     const T* d = b + n;
     const T* dinv = d + n;
     const T* xc = lds + LOFF[l + 1] + ((alt >> (l + 1)) & 1u) * Pc * Pc;
-    for (int i = tid; i < n; i += kCoarseBS) {
-      int i2, i1;
-      fast_divmod(i, N, i2, i1);
+    P2_FOR(N)
       // bilinear interpolation: fine 1-based F maps to coarse F/2 (even) or the two neighbours (odd);
       // in padded coarse coordinates the boundary nodes are the zero ring
       const int F1 = i1 + 1, F2 = i2 + 1;
       const int lo1 = F1 >> 1, hi1 = (F1 + 1) >> 1, lo2 = F2 >> 1, hi2 = (F2 + 1) >> 1;
       const T v = (T)0.25 * (xc[lo1 + Pc * lo2] + xc[hi1 + Pc * lo2] + xc[lo1 + Pc * hi2] + xc[hi1 + Pc * hi2]);
       a[F1 + P * F2] += v;
-    }
+    P2_END
     __syncthreads();
     for (int s = 0; s < I.nu_post; ++s) {
-      for (int i = tid; i < n; i += kCoarseBS) {
-        int i2, i1;
-        fast_divmod(i, N, i2, i1);
-        const int p = (i1 + 1) + P * (i2 + 1);
-        c[p] = a[p] + om * (b[i] - d[i] * a[p] + ih2 * (a[p - 1] + a[p + 1] + a[p - P] + a[p + P])) * dinv[i];
-      }
+      P2_FOR(N) c[p] = a[p] + om * (b[i] - d[i] * a[p] + ih2 * (a[p - 1] + a[p + 1] + a[p - P] + a[p + P])) * dinv[i]; P2_END
       __syncthreads();
       T* t = a; a = c; c = t;
       alt ^= 1u << l;
@@ -441,11 +439,7 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_p2(Inst I, int guard) {
     const int N = LN[cl], P = N + 2, n = N * N;
     const T* a = lds + LOFF[cl] + ((alt >> cl) & 1u) * P * P;
     T* xg = (T*)I.lvd[cl].x;
-    for (int i = tid; i < n; i += kCoarseBS) {
-      int i2, i1;
-      fast_divmod(i, N, i2, i1);
-      xg[i] = a[(i1 + 1) + P * (i2 + 1)];
-    }
+    P2_FOR(N) xg[i] = a[p]; P2_END
   }
 }
 template __global__ void k_mg_coarse_p2<float>(Inst, int);

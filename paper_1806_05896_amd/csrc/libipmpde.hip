@@ -435,7 +435,7 @@ static void minres_iteration(ipmpde_problem* P, int par, int maxit, hipStream_t 
   double* Vc = P->V[par];
   double* Vo = P->V[1 - par];
   hipLaunchKernelGGL(k_minres_k1, dim3(nb), dim3(kBS), 0, s, I, Zc, Zo, P->W[1 - par], P->W[par], P->X, P->Q,
-                     P->KW[1 - par], P->KW[par], P->Rt);
+                     P->KW[1 - par], P->KW[par], P->Rt, 0);
   hipLaunchKernelGGL(k_minres_k2<T>, dim3(nb), dim3(kBS), 0, s, I, P->Q, Vc, Vo, Zo);
   T* xs = schur_inv<T>(P, 1, s);
   hipLaunchKernelGGL(k_minres_k4<T>, dim3(nb), dim3(kBS), 0, s, I, (const T*)xs, Vo, Zo, 1, 0.0, maxit);

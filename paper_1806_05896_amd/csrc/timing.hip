@@ -77,6 +77,11 @@ extern "C" int ipmpde_time_kernel(ipmpde_problem* P, const ipmpde_options* opts,
         if (f32) { float* x; mg_vcycle<float>(P, 0, 0, s, &x); }
         else { double* x; mg_vcycle<double>(P, 0, 0, s, &x); }
         break;
+      case 6:
+        hipLaunchKernelGGL(k_minres_k1, dim3(nblk(P->n)), dim3(kBS), 0, s, I, (const double*)P->Z[1],
+                           (const double*)P->Z[0], P->W[0], (const double*)P->W[1], P->X, P->Q, P->KW[0],
+                           (const double*)P->KW[1], P->Rt, 1);
+        break;
       case 4:
         if (f32) launch_down<float>(P, s);
         else launch_down<double>(P, s);
@@ -94,6 +99,8 @@ extern "C" int ipmpde_time_kernel(ipmpde_problem* P, const ipmpde_options* opts,
     case 3: *bytes = f32 ? vcycle_bytes<float>(I) : vcycle_bytes<double>(I); break;
     case 4: *bytes = (3.0 * n + I.lv[1].n) * e; break;  // reads b, M_hat; writes x, coarse b
     case 5: *bytes = (4.0 * n + I.lv[1].n) * e; break;  // reads x, b, M_hat, coarse x; writes x
+    // K1: reads z_j, z_{j-1}, w x2, x, q, Kw x2, r (36n) and Theta_y,w,v (3n); writes w, x, Kw, r, q (20n)
+    case 6: *bytes = 59.0 * n * 8; break;
 
     default: return fail(IPMPDE_EINVAL, "unknown kernel id");
   }
