@@ -23,11 +23,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of the roofline kernel from rocprofv3 FETCH_SIZE/WRITE_SIZE
+# runs (profiles/k_minres_k1_poisson2d_511_pmc.md), valid while the kernel
+# sources hash to the value they were measured with.
+TRAFFIC = {"kernel": 6, "N": 511, "bytes": 140424333.4, "source_sha": "4c06722113282728"}
 KERNEL_NAMES = {0: "k_saddle (saddle matvec)", 1: "k_mg_jacobi (finest-level smoothing sweep)",
                 2: "k_minres_k2 (Lanczos + diagonal preconditioner)", 3: "one V-cycle",
                 4: "k_mg_down2d (finest level: smoothing + residual + restriction)",
                 5: "k_mg_up2d (finest level: prolongation + smoothing)",
                 6: "k_minres_k1 (MINRES update + saddle matvec + dots)"}
+
+
+def measured_traffic(args):
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1806_05896_amd", "csrc")
+    src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("kernels_krylov.hip", "common.h"))
+    sha = hashlib.sha256(src).hexdigest()[:16]
+    if args.kernel == TRAFFIC["kernel"] and args.N == TRAFFIC["N"] and sha == TRAFFIC["source_sha"]:
+        return TRAFFIC["bytes"]
+    return None
 
 
 def log(*a):
@@ -96,6 +110,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 V-cycle variant")
     ap.add_argument("--kernel", type=int, default=6, help="kernel id for the roofline figure")
     ap.add_argument("--N", type=int, default=511)
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="only launch the roofline kernel (20 times) and a 1 GiB device copy, for counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
@@ -115,6 +131,22 @@ def main():
     data = W.poisson2d_511(seed=0, N=args.N)
     prob = Problem(data)
     opts = Options(sigma=data.sigma, mg_precision="fp32")
+    if args.pmc_probe:
+        # the roofline kernel at a mid-solve Newton state, then a plain copy of known size
+        # (1 GiB, larger than the 256 MB Infinity Cache) that calibrates the byte counters
+        for k in range(6):
+            prob.ipm_step(opts.sigma ** (k + 1), opts)
+        prob.newton_setup(opts.sigma ** 7, opts)
+        ms, nbytes = prob.time_kernel(args.kernel, reps=20, opts=opts)
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"pmc_probe": KERNEL_NAMES[args.kernel], "algorithmic_bytes": nbytes,
+                          "copy_bytes_each_direction": src.numel() * 8}))
+        prob.close()
+        return
     log(f"workload poisson2d_511 N={data.N} n={data.n}")
     t, lat, its, st, rc = time_solves(prob, opts, args.steps, args.warmup, torch)
     u32 = prob.query("u")
@@ -148,7 +180,7 @@ def main():
     ms, nbytes = prob.time_kernel(args.kernel, reps=200, opts=opts, stream=torch.cuda.current_stream())
     achieved = nbytes / (ms * 1e-3) / 1e9
     result["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                          "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                          "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args),
                           "kernel": KERNEL_NAMES[args.kernel], "avg_us": ms * 1e3,
                           "algorithmic_bytes_per_launch": nbytes}
     kern = {}
