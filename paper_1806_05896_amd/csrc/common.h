@@ -46,14 +46,14 @@ struct KrylovCtrl {
   int stop;            // 0 running, 1 stopped (converged estimate, breakdown)
   int pending;         // a direction/solution update is pending
   int breakdown;       // 1: preconditioner indefinite or NaN
-  // FGMRES
+  int j;               // FGMRES: Arnoldi steps completed in this cycle
+  // FGMRES (not copied back to the host: everything above hcol is)
   double hcol[64];     // current Hessenberg column
   double g[64];        // rotated residual vector
   double cs[64], sn[64];
   double H[64 * 64];   // Hessenberg (column-major, restart+1 rows)
   double y[64];        // least-squares solution
   double hpass[64];    // coefficients of the current Gram-Schmidt pass
-  int j;               // Arnoldi steps completed in this cycle
 };
 
 // Everything a kernel needs to know about one problem instance.  Passed by
