@@ -212,11 +212,35 @@ int ipmpde_query_rhs(const ipmpde_problem* prob, double* host_out, size_t count)
 
 /* Time one hot-path kernel over `reps` back-to-back launches on `stream`
  * with HIP events; *avg_ms receives the mean duration per launch and
- * *bytes the algorithmic bytes one launch moves.  kernel ids:
- * 0 saddle matvec, 1 multigrid smoothing sweep (finest level),
- * 2 Lanczos update + diagonal preconditioner, 3 one V-cycle. */
+ * *bytes the algorithmic bytes one launch moves.  Requires a Newton setup
+ * (ipmpde_newton_setup or a solve) in the same multigrid precision.
+ * kernel ids: 0 saddle matvec, 2 Lanczos vector + exact (1,1)-block inverse,
+ * 3 one 2D V-cycle, 4 finest-level descent kernel (2D), 5 finest-level
+ * ascent kernel (2D), 6 MINRES update + saddle matvec + dot products. */
 int ipmpde_time_kernel(ipmpde_problem* prob, const ipmpde_options* opts, int kernel, int reps,
                        ipmpde_stream stream, double* avg_ms, double* bytes);
+
+/* ---- batches: many instances advanced by the same kernel launches ---- */
+
+/* A batch of `count` existing problems of the same dimension (sizes,
+ * operators and parameters may differ).  The batch references the
+ * problems; they must outlive it and must not be used concurrently with
+ * it.  Every kernel launch of a batched solve serves all instances (one
+ * grid z-slice per instance), so small and medium problems share the GPU
+ * instead of paying the launch latency one by one. */
+typedef struct ipmpde_batch ipmpde_batch;
+int ipmpde_batch_create(ipmpde_problem* const* probs, int count, ipmpde_batch** out);
+void ipmpde_batch_destroy(ipmpde_batch* batch);
+
+/* Run Algorithm A.1 on every problem of the batch in lockstep; each
+ * instance stops on its own test (then its blocks exit at once).  opts:
+ * NULL (defaults), one options struct (per_problem = 0), or an array of
+ * `count` structs (per_problem = 1) whose IPM fields (sigma, alpha0,
+ * tolerances, mu0, iteration limits) may differ while the Krylov and
+ * multigrid fields must agree (else IPMPDE_EINVAL).  Returns IPMPDE_OK
+ * once every instance has finished; each problem's outcome is in its
+ * stats (ipmpde_get_stats) and its iterates are queryable. */
+int ipmpde_batch_solve(ipmpde_batch* batch, const ipmpde_options* opts, int per_problem, ipmpde_stream stream);
 
 #ifdef __cplusplus
 }

@@ -91,6 +91,9 @@ SIGNATURES = {
     "ipmpde_query_rhs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "ipmpde_time_kernel": (C.c_int, [C.c_void_p, C.POINTER(COptions), C.c_int, C.c_int, C.c_void_p,
                                      C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "ipmpde_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_void_p)]),
+    "ipmpde_batch_destroy": (None, [C.c_void_p]),
+    "ipmpde_batch_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
 }
 
 _lib = None

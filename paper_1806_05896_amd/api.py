@@ -263,6 +263,49 @@ class Problem:
         return ms.value, nbytes.value
 
 
+class Batch:
+    """Several problems advanced by the same kernel launches (ipmpde_batch)."""
+
+    def __init__(self, problems):
+        self._lib = L.load()
+        self.problems = list(problems)
+        arr = (C.c_void_p * len(self.problems))(*[p._h.value for p in self.problems])
+        h = C.c_void_p()
+        L.check(self._lib.ipmpde_batch_create(arr, len(self.problems), C.byref(h)))
+        self._h = h
+
+    def solve(self, opts=None, stream=None):
+        """opts: None, one Options, or a list with one Options per problem."""
+        if opts is None:
+            ptr, per = None, 0
+        elif isinstance(opts, Options):
+            self._opts_keep = opts.to_c()
+            ptr, per = C.cast(C.byref(self._opts_keep), C.c_void_p), 0
+        else:
+            arr = (L.COptions * len(opts))(*[o.to_c() for o in opts])
+            self._opts_keep = arr
+            ptr, per = C.cast(arr, C.c_void_p), 1
+        L.check(self._lib.ipmpde_batch_solve(self._h, ptr, per, _stream_handle(stream)))
+        return [p.stats().status for p in self.problems]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ipmpde_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
 def footprint_bytes(dim: int, N: int, pde: str = "poisson", has_state_bounds: bool = False,
                     opts: Optional[Options] = None) -> int:
     lib = L.load()

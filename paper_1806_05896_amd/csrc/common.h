@@ -47,6 +47,10 @@ struct KrylovCtrl {
   int pending;         // a direction/solution update is pending
   int breakdown;       // 1: preconditioner indefinite or NaN
   int j;               // FGMRES: Arnoldi steps completed in this cycle
+  int want_restart;    // 1: the last cycle missed the tolerance; start another from the true residual
+  int its_total;       // Krylov iterations over all cycles of this solve
+  int failed;          // 1: iteration limit or breakdown
+  double relres;       // true relative residual after the last cycle
   // FGMRES (not copied back to the host: everything above hcol is)
   double hcol[64];     // current Hessenberg column
   double g[64];        // rotated residual vector
@@ -56,12 +60,17 @@ struct KrylovCtrl {
   double hpass[64];    // coefficients of the current Gram-Schmidt pass
 };
 
-// Everything a kernel needs to know about one problem instance.  Passed by
-// value as a kernel argument.
+// Everything a kernel needs to know about one problem instance.  Kernels
+// receive a device array of these and serve instance blockIdx.z, so one
+// launch can advance many (unevenly sized) instances; a single problem is a
+// batch of one.
 struct Inst {
   int dim, N, n, pde;  // pde: 0 Poisson, 1 convection-diffusion
   int has_y;
+  int active;          // 0: every kernel skips this instance
   double h, eps, alpha, beta;
+  double mu;           // barrier parameter of the current Newton system
+  double alpha0;       // fraction-to-boundary factor
   // data (FP64, n values)
   const double* ua;
   const double* ub;
@@ -73,6 +82,11 @@ struct Inst {
   double *y, *w, *v, *p, *lya, *lyb, *lwa, *lwb, *lva, *lvb;
   // barrier diagonals and preconditioner data
   double *ty, *tw, *tv, *mh;
+  // Newton system and Krylov workspace (4n each)
+  double *rhs, *X, *Q, *R, *Rt;
+  double *V[2], *Z[2], *W[2], *KW[2];
+  double *fV, *fZ;      // FGMRES basis (restart + 1 and restart vectors), or null
+  int nparts;           // capacity of `partials` in doubles
   // reductions
   double* partials;     // per-block partial results
   unsigned* counter;    // ticket for the last-block pattern (must be 0 between kernels)
@@ -81,6 +95,7 @@ struct Inst {
   // multigrid
   int nlev;             // number of levels (finest 0)
   int coarse_lev;       // first level handled by the single-workgroup kernel
+  int coarse_p2;        // 1: the coarse levels run in the padded 2D Poisson kernel
   int mg_fp32;          // 1: levels hold float
   int nu_pre, nu_post, vcycles;
   double omega;
@@ -304,5 +319,10 @@ __device__ __forceinline__ bool grid_reduce(double (&v)[K], double* __restrict__
 }
 
 inline int div_up(long a, long b) { return (int)((a + b - 1) / b); }
+
+// Start of every kernel: the instance of this block, skipped when inactive.
+#define INST_BEGIN                         \
+  const Inst& I = Dp[blockIdx.z];          \
+  if (!I.active) return;
 
 }  // namespace ipm

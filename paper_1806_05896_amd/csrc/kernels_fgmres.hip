@@ -2,37 +2,47 @@
 // block-triangular preconditioner P_T (Sec. 4) and for non-symmetric state
 // operators.  Arnoldi with classical Gram-Schmidt applied twice, all
 // reductions deterministic; the small Hessenberg least-squares problem is
-// updated with Givens rotations by one thread on the device.
+// updated with Givens rotations by one thread on the device.  Basis V_k and
+// preconditioned vectors Z_k live in the instance's fV / fZ (4n each); every
+// kernel serves instance blockIdx.z and each instance stops on its own.
 #include "common.h"
 
 namespace ipm {
 
-// w = K z (written to the next basis slot)
-__global__ void __launch_bounds__(kBS) k_fg_matvec(Inst I, const double* __restrict__ z, double* __restrict__ w) {
+__device__ __forceinline__ double* fg_v(const Inst& I, int k) { return I.fV + (size_t)k * 4 * I.n; }
+__device__ __forceinline__ double* fg_z(const Inst& I, int k) { return I.fZ + (size_t)k * 4 * I.n; }
+
+// V_{j+1} = K Z_j
+__global__ void __launch_bounds__(kBS) k_fg_matvec(const Inst* __restrict__ Dp, int j) {
+  INST_BEGIN
   if (I.ctrl->stop) return;
   const int i = blockIdx.x * kBS + threadIdx.x;
   if (i >= I.n) return;
   double o[4];
-  saddle_rows(I, z, i, 1.0, o);
+  saddle_rows(I, fg_z(I, j), i, 1.0, o);
   const int n = I.n;
+  double* w = fg_v(I, j + 1);
   w[i] = o[0]; w[n + i] = o[1]; w[2 * n + i] = o[2]; w[3 * n + i] = o[3];
 }
 
-// partials[k * nb + bx] = block part of <V_k, w>, k = blockIdx.y
-__global__ void __launch_bounds__(kBS) k_fg_multidot(Inst I, const double* __restrict__ V, const double* __restrict__ w,
-                                                     long n4) {
+// partials[k * nb + bx] = block part of <V_k, V_{j+1}>, k = blockIdx.y
+__global__ void __launch_bounds__(kBS) k_fg_multidot(const Inst* __restrict__ Dp, int j) {
+  INST_BEGIN
   if (I.ctrl->stop) return;
   __shared__ double smem[kBS / 64];
   const int k = blockIdx.y;
-  const double* v = V + (size_t)k * n4;
+  const long n4 = 4L * I.n;
+  const double* v = fg_v(I, k);
+  const double* w = fg_v(I, j + 1);
   double acc[1] = {0.0};
   for (long i = (long)blockIdx.x * kBS + threadIdx.x; i < n4; i += (long)gridDim.x * kBS) acc[0] += v[i] * w[i];
   block_reduce<kSum, 1, kBS>(acc, smem);
   if (threadIdx.x == 0) I.partials[(size_t)k * gridDim.x + blockIdx.x] = acc[0];
 }
 
-// hpass[k] = sum of partials (fixed order); hcol[k] += hpass[k]
-__global__ void __launch_bounds__(kBS) k_fg_multidot_final(Inst I, int nk, int nb, int first) {
+// hpass[k] = sum of partials (fixed order); hcol[k] (+)= hpass[k]
+__global__ void __launch_bounds__(kBS) k_fg_multidot_final(const Inst* __restrict__ Dp, int nk, int nb, int first) {
+  INST_BEGIN
   KrylovCtrl* C = I.ctrl;
   if (C->stop) return;
   __shared__ double smem[kBS / 64];
@@ -47,30 +57,35 @@ __global__ void __launch_bounds__(kBS) k_fg_multidot_final(Inst I, int nk, int n
   }
 }
 
-// w -= sum_k hpass[k] V_k
-__global__ void __launch_bounds__(kBS) k_fg_orth(Inst I, const double* __restrict__ V, double* __restrict__ w, int nk,
-                                                 long n4) {
+// V_{j+1} -= sum_{k<=j} hpass[k] V_k
+__global__ void __launch_bounds__(kBS) k_fg_orth(const Inst* __restrict__ Dp, int j) {
+  INST_BEGIN
   const KrylovCtrl* C = I.ctrl;
   if (C->stop) return;
+  const long n4 = 4L * I.n;
   const long i = (long)blockIdx.x * kBS + threadIdx.x;
   if (i >= n4) return;
+  double* w = fg_v(I, j + 1);
   double acc = w[i];
-  for (int k = 0; k < nk; ++k) acc -= C->hpass[k] * V[(size_t)k * n4 + i];
+  for (int k = 0; k <= j; ++k) acc -= C->hpass[k] * fg_v(I, k)[i];
   w[i] = acc;
 }
 
-// |w|^2 -> hcol[j+1] = |w|, then the Givens update of column j and the
-// residual estimate (last block, thread 0).
-__global__ void __launch_bounds__(kBS) k_fg_norm_givens(Inst I, const double* __restrict__ w, long n4, int j,
-                                                        double tol_abs) {
+// |V_{j+1}|^2 -> hcol[j+1], then the Givens update of column j and the
+// residual estimate (last block, thread 0); stop at tol |b|.
+__global__ void __launch_bounds__(kBS) k_fg_norm_givens(const Inst* __restrict__ Dp, int j, double tol, int maxit) {
+  INST_BEGIN
   KrylovCtrl* C = I.ctrl;
   if (C->stop) return;
   __shared__ double smem[kBS / 64];
+  const long n4 = 4L * I.n;
+  const double* w = fg_v(I, j + 1);
   double acc[1] = {0.0};
   for (long i = (long)blockIdx.x * kBS + threadIdx.x; i < n4; i += (long)gridDim.x * kBS) acc[0] += w[i] * w[i];
   if (!grid_reduce<kSum, 1, kBS>(acc, I.partials, I.counter, gridDim.x, blockIdx.x, smem) || threadIdx.x != 0) return;
   double* h = C->hcol;
   h[j + 1] = sqrt(acc[0]);
+  const double hn = h[j + 1];
   for (int i = 0; i < j; ++i) {
     const double t = C->cs[i] * h[i] + C->sn[i] * h[i + 1];
     h[i + 1] = -C->sn[i] * h[i] + C->cs[i] * h[i + 1];
@@ -80,36 +95,42 @@ __global__ void __launch_bounds__(kBS) k_fg_norm_givens(Inst I, const double* __
   const double cs = r > 0.0 ? h[j] / r : 1.0, sn = r > 0.0 ? h[j + 1] / r : 0.0;
   C->cs[j] = cs;
   C->sn[j] = sn;
-  const double hn = C->hcol[j + 1];
   h[j] = r;
   h[j + 1] = 0.0;
   for (int i = 0; i <= j; ++i) C->H[j * 64 + i] = h[i];
   C->g[j + 1] = -sn * C->g[j];
   C->g[j] = cs * C->g[j];
   C->j = j + 1;
-  C->iter += 1;
   C->est = fabs(C->g[j + 1]);
   C->hcol[63] = hn;  // |w| before the rotation, for the normalization kernel
   if (!(r > 0.0) || !isfinite(r)) C->breakdown = 1;
-  if (C->est <= tol_abs || !(hn > 0.0) || C->breakdown) C->stop = 1;
+  if (C->est <= tol * C->bnorm || !(hn > 0.0) || C->breakdown || C->its_total + C->j >= maxit) C->stop = 1;
 }
 
-// v_{j+1} = w / |w|
-__global__ void __launch_bounds__(kBS) k_fg_normalize(Inst I, double* __restrict__ w, long n4) {
+// V_{j+1} /= |V_{j+1}|
+__global__ void __launch_bounds__(kBS) k_fg_normalize(const Inst* __restrict__ Dp, int j) {
+  INST_BEGIN
   const KrylovCtrl* C = I.ctrl;
+  if (!C->want_restart) return;
+  const long n4 = 4L * I.n;
   const long i = (long)blockIdx.x * kBS + threadIdx.x;
   if (i >= n4) return;
   const double hn = C->hcol[63];
+  double* w = fg_v(I, j + 1);
   if (hn > 0.0) w[i] = w[i] / hn;
 }
 
-// start of a cycle: v_0 = r / |r|, g = (|r|, 0, ...)
-__global__ void __launch_bounds__(kBS) k_fg_start_norm(Inst I, const double* __restrict__ r, long n4) {
+// start of a cycle from the residual (src 0: rhs, 1: R): |r| -> g = (|r|, 0, ...)
+__global__ void __launch_bounds__(kBS) k_fg_start_norm(const Inst* __restrict__ Dp, int src) {
+  INST_BEGIN
+  KrylovCtrl* C = I.ctrl;
+  if (!C->want_restart) return;
   __shared__ double smem[kBS / 64];
+  const long n4 = 4L * I.n;
+  const double* r = src ? I.R : I.rhs;
   double acc[1] = {0.0};
   for (long i = (long)blockIdx.x * kBS + threadIdx.x; i < n4; i += (long)gridDim.x * kBS) acc[0] += r[i] * r[i];
   if (!grid_reduce<kSum, 1, kBS>(acc, I.partials, I.counter, gridDim.x, blockIdx.x, smem) || threadIdx.x != 0) return;
-  KrylovCtrl* C = I.ctrl;
   const double beta = sqrt(acc[0]);
   for (int k = 0; k < 64; ++k) C->g[k] = 0.0;
   C->g[0] = beta;
@@ -118,18 +139,25 @@ __global__ void __launch_bounds__(kBS) k_fg_start_norm(Inst I, const double* __r
   C->stop = beta > 0.0 ? 0 : 1;
   C->breakdown = 0;
 }
-__global__ void __launch_bounds__(kBS) k_fg_start_scale(Inst I, const double* __restrict__ r, double* __restrict__ v0,
-                                                        long n4) {
+
+// V_0 = r / |r|
+__global__ void __launch_bounds__(kBS) k_fg_start_scale(const Inst* __restrict__ Dp, int src) {
+  INST_BEGIN
   const KrylovCtrl* C = I.ctrl;
+  if (!C->want_restart) return;
+  const long n4 = 4L * I.n;
   const long i = (long)blockIdx.x * kBS + threadIdx.x;
   if (i >= n4) return;
+  const double* r = src ? I.R : I.rhs;
   const double b = C->hcol[63];
-  v0[i] = b > 0.0 ? r[i] / b : 0.0;
+  I.fV[i] = b > 0.0 ? r[i] / b : 0.0;
 }
 
-// back substitution H y = g over the k = ctrl->j completed steps (one thread)
-__global__ void k_fg_solve_small(Inst I) {
+// back substitution H y = g over the k = ctrl->j completed steps (one thread per instance)
+__global__ void k_fg_solve_small(const Inst* __restrict__ Dp) {
+  INST_BEGIN
   KrylovCtrl* C = I.ctrl;
+  if (!C->want_restart || threadIdx.x != 0 || blockIdx.x != 0) return;
   const int k = C->j;
   for (int i = k - 1; i >= 0; --i) {
     double s = C->g[i];
@@ -138,16 +166,18 @@ __global__ void k_fg_solve_small(Inst I) {
   }
 }
 
-// x += sum_{i<k} y_i Z_i
-__global__ void __launch_bounds__(kBS) k_fg_update_x(Inst I, const double* __restrict__ Z, double* __restrict__ X,
-                                                     long n4) {
+// X += sum_{i<k} y_i Z_i
+__global__ void __launch_bounds__(kBS) k_fg_update_x(const Inst* __restrict__ Dp) {
+  INST_BEGIN
   const KrylovCtrl* C = I.ctrl;
+  if (!C->want_restart) return;
+  const long n4 = 4L * I.n;
   const long i = (long)blockIdx.x * kBS + threadIdx.x;
   if (i >= n4) return;
   const int k = C->j;
-  double acc = X[i];
-  for (int c = 0; c < k; ++c) acc += C->y[c] * Z[(size_t)c * n4 + i];
-  X[i] = acc;
+  double acc = I.X[i];
+  for (int c = 0; c < k; ++c) acc += C->y[c] * fg_z(I, c)[i];
+  I.X[i] = acc;
 }
 
 }  // namespace ipm

@@ -5,13 +5,15 @@
 // Unit-mass finite-difference form: M = D = I, L = A.  Split bounds
 // (Sec. 2, eq. (split)) with u_a < 0 < u_b: z_a = 0, z_b = [u_b; -u_a], so
 // the gaps are w, u_b - w, v, -u_a - v (and y - y_a, y_b - y with state
-// bounds).
+// bounds).  Every kernel serves instance blockIdx.z of the descriptor array.
 #include "common.h"
 
 namespace ipm {
 
-// Starting point: box midpoints, p = 0, multipliers mu0 / gap.
-__global__ void __launch_bounds__(kBS) k_init_state(Inst I, double mu0) {
+// Starting point: box midpoints, p = 0, multipliers mu0 / gap with mu0 = I.mu.
+__global__ void __launch_bounds__(kBS) k_init_state(const Inst* __restrict__ Dp) {
+  INST_BEGIN
+  const double mu0 = I.mu;
   const int i = blockIdx.x * kBS + threadIdx.x;
   if (i >= I.n) return;
   const double ua = I.ua[i], ub = I.ub[i];
@@ -35,7 +37,8 @@ __global__ void __launch_bounds__(kBS) k_init_state(Inst I, double mu0) {
 
 // inf-norms of xi_p, xi_d (eq. (prdu)) and of the complementarity products
 // (eq. (gap) without the mu term) -> stat[0..2].
-__global__ void __launch_bounds__(kBS) k_measures(Inst I) {
+__global__ void __launch_bounds__(kBS) k_measures(const Inst* __restrict__ Dp) {
+  INST_BEGIN
   __shared__ double smem[3 * kBS / 64];
   const int i = blockIdx.x * kBS + threadIdx.x;
   double r[3] = {0.0, 0.0, 0.0};
@@ -72,11 +75,14 @@ __global__ void __launch_bounds__(kBS) k_measures(Inst I) {
 // (NewtonSystem)), the matching term M_hat = sqrt(Sigma (1 + Theta_y)) with
 // Sigma = (t_w + t_v) / (alpha (t_w + t_v) + t_w t_v) (eq. (Schur) and the
 // M_hat of Sec. 4.2 with M = D_M = I), and the right-hand side of eq.
-// (NewtonSystem) at barrier mu; |rhs|_2 -> ctrl->bnorm.
+// (NewtonSystem) at barrier I.mu; |rhs|_2 -> ctrl->bnorm.  M_hat is also
+// written, in the V-cycle precision T, to the finest multigrid level.
 template <typename T>
-__global__ void __launch_bounds__(kBS) k_newton_setup(Inst I, double mu, double* __restrict__ rhs, T* __restrict__ mh0) {
+__global__ void __launch_bounds__(kBS) k_newton_setup(const Inst* __restrict__ Dp) {
+  INST_BEGIN
   __shared__ double smem[kBS / 64];
   const int i = blockIdx.x * kBS + threadIdx.x;
+  const double mu = I.mu;
   double acc[1] = {0.0};
   if (i < I.n) {
     int i1, i2, i3;
@@ -98,7 +104,7 @@ __global__ void __launch_bounds__(kBS) k_newton_setup(Inst I, double mu, double*
     I.tw[i] = tw;
     I.tv[i] = tv;
     I.mh[i] = mh;
-    mh0[i] = (T)mh;
+    ((T*)I.lv[0].mh)[i] = (T)mh;
     const double u = w - v;
     const double Ay = apply_op<double>(I.y, i, i1, i2, i3, I.N, I.dim, I.pde, I.h, I.eps, false);
     const double ATp = apply_op<double>(I.p, i, i1, i2, i3, I.N, I.dim, I.pde, I.h, I.eps, true);
@@ -107,6 +113,7 @@ __global__ void __launch_bounds__(kBS) k_newton_setup(Inst I, double mu, double*
     const double rv = -(-I.alpha * u + I.beta + p - mu / v + mu / gvb);
     const double rp = -(Ay - u - I.fhat[i]);
     const int n = I.n;
+    double* rhs = I.rhs;
     rhs[i] = ry;
     rhs[n + i] = rw;
     rhs[2 * n + i] = rv;
@@ -116,18 +123,22 @@ __global__ void __launch_bounds__(kBS) k_newton_setup(Inst I, double mu, double*
   if (grid_reduce<kSum, 1, kBS>(acc, I.partials, I.counter, gridDim.x, blockIdx.x, smem) && threadIdx.x == 0)
     I.ctrl->bnorm = sqrt(acc[0]);
 }
-template __global__ void k_newton_setup<float>(Inst, double, double*, float*);
-template __global__ void k_newton_setup<double>(Inst, double, double*, double*);
+template __global__ void k_newton_setup<float>(const Inst*);
+template __global__ void k_newton_setup<double>(const Inst*);
 
-// Full-weighting restriction of the M_hat diagonal to the next coarser level
+// Full-weighting restriction of the M_hat diagonal from level l to level l+1
 // (tensor product of the weights 1/4, 1/2, 1/4); the coarse operator is the
 // rediscretized stencil plus this restricted reaction term.
 template <typename T>
-__global__ void __launch_bounds__(kBS) k_restrict_diag(const T* __restrict__ fine, T* __restrict__ coarse, int Nf,
-                                                       int Nc, int dim) {
-  const int nc = dim == 2 ? Nc * Nc : Nc * Nc * Nc;
+__global__ void __launch_bounds__(kBS) k_restrict_diag(const Inst* __restrict__ Dp, int l) {
+  INST_BEGIN
+  if (l + 1 >= I.nlev) return;
+  const Level& F = I.lv[l];
+  const Level& Cv = I.lv[l + 1];
   const int ic = blockIdx.x * kBS + threadIdx.x;
-  if (ic >= nc) return;
+  if (ic >= Cv.n) return;
+  const T* __restrict__ fine = (const T*)F.mh;
+  const int Nf = F.N, Nc = Cv.N, dim = I.dim;
   int j1, j2, j3;
   node_coords(ic, Nc, dim, j1, j2, j3);
   // coarse node J (1-based) sits on fine node 2J (1-based) -> 0-based 2j+1
@@ -144,10 +155,10 @@ __global__ void __launch_bounds__(kBS) k_restrict_diag(const T* __restrict__ fin
         for (int a = -1; a <= 1; ++a)
           acc += wt[a + 1] * wt[b + 1] * wt[c + 1] * (double)fine[(f1 + a) + Nf * ((f2 + b) + Nf * (f3 + c))];
   }
-  coarse[ic] = (T)acc;
+  ((T*)Cv.mh)[ic] = (T)acc;
 }
-template __global__ void k_restrict_diag<float>(const float*, float*, int, int, int);
-template __global__ void k_restrict_diag<double>(const double*, double*, int, int, int);
+template __global__ void k_restrict_diag<float>(const Inst*, int);
+template __global__ void k_restrict_diag<double>(const Inst*, int);
 
 // Multiplier steps of eqs. (zupdate1)-(zupdate4) for one bound pair.
 struct DL { double a, b; };
@@ -167,12 +178,15 @@ __device__ __forceinline__ double pos_step(double l, double dl) { return dl < 0.
 
 // Fraction-to-boundary step lengths (Algorithm A.1): alpha_P = alpha0 min(1, max
 // primal step), alpha_D likewise for the multipliers -> stat[3], stat[4].
-__global__ void __launch_bounds__(kBS) k_step_lengths(Inst I, const double* __restrict__ X, double mu, double alpha0) {
+__global__ void __launch_bounds__(kBS) k_step_lengths(const Inst* __restrict__ Dp) {
+  INST_BEGIN
   __shared__ double smem[2 * kBS / 64];
   const int i = blockIdx.x * kBS + threadIdx.x;
+  const double mu = I.mu;
   double r[2] = {INFINITY, INFINITY};
   if (i < I.n) {
     const int n = I.n;
+    const double* X = I.X;
     const double dy = X[i], dw = X[n + i], dv = X[2 * n + i];
     const double w = I.w[i], v = I.v[i], ua = I.ua[i], ub = I.ub[i];
     const double gwa = w, gwb = ub - w, gva = v, gvb = -ua - v;
@@ -193,18 +207,21 @@ __global__ void __launch_bounds__(kBS) k_step_lengths(Inst I, const double* __re
     r[1] = sd;
   }
   if (grid_reduce<kMin, 2, kBS>(r, I.partials, I.counter, gridDim.x, blockIdx.x, smem) && threadIdx.x == 0) {
-    I.stat[3] = alpha0 * nmin(1.0, r[0]);
-    I.stat[4] = alpha0 * nmin(1.0, r[1]);
+    I.stat[3] = I.alpha0 * nmin(1.0, r[0]);
+    I.stat[4] = I.alpha0 * nmin(1.0, r[1]);
   }
 }
 
 // Iterate update of Algorithm A.1: (y, w, v) += alpha_P (dy, dw, dv);
 // (p, lambdas) += alpha_D (dp, dlambdas).
-__global__ void __launch_bounds__(kBS) k_update(Inst I, const double* __restrict__ X, double mu) {
+__global__ void __launch_bounds__(kBS) k_update(const Inst* __restrict__ Dp) {
+  INST_BEGIN
   const int i = blockIdx.x * kBS + threadIdx.x;
   if (i >= I.n) return;
   const int n = I.n;
+  const double mu = I.mu;
   const double aP = I.stat[3], aD = I.stat[4];
+  const double* X = I.X;
   const double dy = X[i], dw = X[n + i], dv = X[2 * n + i], dp = X[3 * n + i];
   const double w = I.w[i], v = I.v[i], ua = I.ua[i], ub = I.ub[i];
   const double lwa = I.lwa[i], lwb = I.lwb[i], lva = I.lva[i], lvb = I.lvb[i];
@@ -226,13 +243,22 @@ __global__ void __launch_bounds__(kBS) k_update(Inst I, const double* __restrict
   I.lvb[i] = lvb + aD * lv.b;
 }
 
-// y = A x or A^T x (FP64).
-__global__ void __launch_bounds__(kBS) k_apply_op(Inst I, const double* __restrict__ x, double* __restrict__ y, int transpose) {
+// y = A x or A^T x (FP64), single instance.
+__global__ void __launch_bounds__(kBS) k_apply_op(const Inst* __restrict__ Dp, const double* __restrict__ x,
+                                                  double* __restrict__ y, int transpose) {
+  INST_BEGIN
   const int i = blockIdx.x * kBS + threadIdx.x;
   if (i >= I.n) return;
   int i1, i2, i3;
   node_coords(i, I.N, I.dim, i1, i2, i3);
   y[i] = apply_op<double>(x, i, i1, i2, i3, I.N, I.dim, I.pde, I.h, I.eps, transpose != 0);
+}
+
+// X = 0 (4n) for every active instance.
+__global__ void __launch_bounds__(kBS) k_zero_x(const Inst* __restrict__ Dp) {
+  INST_BEGIN
+  const long i = (long)blockIdx.x * kBS + threadIdx.x;
+  if (i < 4L * I.n) I.X[i] = 0.0;
 }
 
 }  // namespace ipm

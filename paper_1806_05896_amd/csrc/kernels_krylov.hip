@@ -9,7 +9,8 @@
 //
 // Preconditioned MINRES (Sec. 4: the Krylov method used with P_D) runs with
 // all scalars on the device.  One iteration is
-//   K1  pending direction/solution update of the previous iteration, then
+//   K1  pending direction/solution update of the previous iteration (and, by
+//       the same recurrence, K w and the residual r = b - K x), then
 //       q = K z_j / gamma_j and delta_j = <q, z_j / gamma_j>
 //   K2  Lanczos step v_{j+1} = q - (delta_j/gamma_j) v_j - (gamma_j/gamma_{j-1}) v_{j-1},
 //       exact (1,1)-block inverse of P_D on the y, w, v blocks and their part
@@ -17,6 +18,7 @@
 //   MG  z_{j+1,p} = S_hat^-1 v_{j+1,p}
 //   K4  rest of <v_{j+1}, z_{j+1}>, gamma_{j+1}, the Givens rotation and the
 //       coefficients of the next update, all in the last block.
+// Every kernel serves instance blockIdx.z; each instance stops on its own.
 #include "common.h"
 
 namespace ipm {
@@ -38,6 +40,23 @@ __device__ __forceinline__ void saddle_rows(const Inst& I, const double* __restr
   out[3] = s * (Axy - xw + xv);
 }
 
+// |K||x| row by row (all off-diagonal stencil entries are <= 0, so |A||x| = 2 diag |x| - A|x|).
+__device__ __forceinline__ void saddle_rows_abs(const Inst& I, const double* __restrict__ x, int i, double out[4]) {
+  int i1, i2, i3;
+  node_coords(i, I.N, I.dim, i1, i2, i3);
+  const int n = I.n;
+  const double xy = fabs(x[i]), xw = fabs(x[n + i]), xv = fabs(x[2 * n + i]), xp = fabs(x[3 * n + i]);
+  const double ty = I.ty[i], tw = I.tw[i], tv = I.tv[i], a = I.alpha;
+  const double d = op_diag(I.dim, I.pde, I.h, I.eps, i1, i2);
+  const int NN = I.N * I.N;
+  const double ATxp = 2.0 * d * xp - apply_op_s<double, true>(x + 3 * n, i, i1, i2, i3, I.N, I.N, NN, I.dim, I.pde, I.h, I.eps, true);
+  const double Axy = 2.0 * d * xy - apply_op_s<double, true>(x, i, i1, i2, i3, I.N, I.N, NN, I.dim, I.pde, I.h, I.eps, false);
+  out[0] = (1.0 + ty) * xy + ATxp;
+  out[1] = (a + tw) * xw + a * xv + xp;
+  out[2] = a * xw + (a + tv) * xv + xp;
+  out[3] = Axy + xw + xv;
+}
+
 // Exact inverse of the (1,1) block of P_D at node i: 1/(1+Th_y) on y and the
 // per-node 2x2 inverse of [a+t_w, -a; -a, a+t_v] (Sec. 4.1 with D_M = M = I).
 __device__ __forceinline__ void apply_A11_inv(const Inst& I, int i, double ry, double rw, double rv, double& zy,
@@ -49,8 +68,17 @@ __device__ __forceinline__ void apply_A11_inv(const Inst& I, int i, double ry, d
   zv = (a * rw + (a + tw) * rv) / det;
 }
 
-// y = K x
-__global__ void __launch_bounds__(kBS) k_saddle(Inst I, const double* __restrict__ x, double* __restrict__ y) {
+// Level-0 output array of the V-cycle: level 0's x when the whole hierarchy
+// runs in the single-workgroup kernel, else x (outsel = 0) or x2 (outsel = 1).
+template <typename T>
+__device__ __forceinline__ const T* mg_out(const Inst& I, int outsel) {
+  return (const T*)((I.coarse_lev == 0 || !outsel) ? I.lv[0].x : I.lv[0].x2);
+}
+
+// y = K x (single instance)
+__global__ void __launch_bounds__(kBS) k_saddle(const Inst* __restrict__ Dp, const double* __restrict__ x,
+                                                double* __restrict__ y) {
+  INST_BEGIN
   const int i = blockIdx.x * kBS + threadIdx.x;
   if (i >= I.n) return;
   double o[4];
@@ -59,40 +87,24 @@ __global__ void __launch_bounds__(kBS) k_saddle(Inst I, const double* __restrict
   y[i] = o[0]; y[n + i] = o[1]; y[2 * n + i] = o[2]; y[3 * n + i] = o[3];
 }
 
-// |K||x| row by row (all off-diagonal stencil entries are <= 0, so |A||x| = 2 diag |x| - A|x|).
-__device__ __forceinline__ void saddle_rows_abs(const Inst& I, const double* __restrict__ x, int i, double out[4]) {
-  int i1, i2, i3;
-  node_coords(i, I.N, I.dim, i1, i2, i3);
-  const int n = I.n;
-  const double xy = fabs(x[i]), xw = fabs(x[n + i]), xv = fabs(x[2 * n + i]), xp = fabs(x[3 * n + i]);
-  const double ty = I.ty[i], tw = I.tw[i], tv = I.tv[i], a = I.alpha;
-  const double d = op_diag(I.dim, I.pde, I.h, I.eps, i1, i2);
-  const double ATxp = 2.0 * d * xp - apply_op_s<double, true>(x + 3 * n, i, i1, i2, i3, I.N, I.N, I.N * I.N, I.dim, I.pde, I.h, I.eps, true);
-  const double Axy = 2.0 * d * xy - apply_op_s<double, true>(x, i, i1, i2, i3, I.N, I.N, I.N * I.N, I.dim, I.pde, I.h, I.eps, false);
-  out[0] = (1.0 + ty) * xy + ATxp;
-  out[1] = (a + tw) * xw + a * xv + xp;
-  out[2] = a * xw + (a + tv) * xv + xp;
-  out[3] = Axy + xw + xv;
-}
-
-// r = b - K x, |r|_2 -> ctrl->rnorm, and |(|K||x| + |b|)|_2 -> ctrl->rfloor: the
-// scale of the rounding error of evaluating r in FP64, which bounds the
-// attainable relative residual.
-__global__ void __launch_bounds__(kBS) k_true_residual(Inst I, const double* __restrict__ x,
-                                                       const double* __restrict__ b, double* __restrict__ r) {
+// R = rhs - K X, |R|_2 -> ctrl->rnorm, and |(|K||X| + |rhs|)|_2 -> ctrl->rfloor: the
+// scale of the rounding error of evaluating the residual in FP64, which
+// bounds the attainable relative residual.
+__global__ void __launch_bounds__(kBS) k_true_residual(const Inst* __restrict__ Dp) {
+  INST_BEGIN
   __shared__ double smem[2 * kBS / 64];
   const int i = blockIdx.x * kBS + threadIdx.x;
   double acc[2] = {0.0, 0.0};
   if (i < I.n) {
     double o[4], m[4];
-    saddle_rows(I, x, i, 1.0, o);
-    saddle_rows_abs(I, x, i, m);
+    saddle_rows(I, I.X, i, 1.0, o);
+    saddle_rows_abs(I, I.X, i, m);
     const int n = I.n;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const double bk = b[k * n + i];
+      const double bk = I.rhs[k * n + i];
       const double rk = bk - o[k];
-      r[k * n + i] = rk;
+      I.R[k * n + i] = rk;
       acc[0] += rk * rk;
       const double mk = m[k] + fabs(bk);
       acc[1] += mk * mk;
@@ -104,16 +116,57 @@ __global__ void __launch_bounds__(kBS) k_true_residual(Inst I, const double* __r
   }
 }
 
-// Diagonal part of the preconditioner for an arbitrary vector (used by the
-// stand-alone preconditioner entry point and FGMRES): z_{y,w,v} = A11^-1 r,
-// and b_0 = (T) r_p (or r_p - B z for P_T, see k_pt_rhs).
+// After a Krylov cycle and its true residual: converged when the relative
+// residual meets max(tol, ff * rfloor / bnorm) (ff: rounding factor); else
+// another cycle from the true residual unless the iteration budget is spent.
+// its_from_j: count FGMRES steps (ctrl->j) instead of MINRES iterations.
+__global__ void k_krylov_mark(const Inst* __restrict__ Dp, double tol, double ff, int maxit, int its_from_j) {
+  INST_BEGIN
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  KrylovCtrl* C = I.ctrl;
+  if (!C->want_restart) return;  // finished in an earlier cycle
+  C->its_total += its_from_j ? C->j : C->iter;
+  const double bn = C->bnorm;
+  const double rel = bn > 0.0 ? C->rnorm / bn : 0.0;
+  C->relres = rel;
+  const double lim = fmax(tol, bn > 0.0 ? ff * C->rfloor / bn : 0.0);
+  if (rel <= lim) { C->want_restart = 0; return; }
+  if (!(rel == rel) || C->breakdown || C->its_total >= maxit) { C->want_restart = 0; C->failed = 1; return; }
+  C->want_restart = 1;
+}
+
+// Start of a Krylov solve: X = 0, want_restart = 1 (so that the first cycle
+// runs), counters cleared.  bnorm comes from the Newton setup.
+__global__ void __launch_bounds__(kBS) k_krylov_begin(const Inst* __restrict__ Dp) {
+  INST_BEGIN
+  const long i = (long)blockIdx.x * kBS + threadIdx.x;
+  if (i < 4L * I.n) I.X[i] = 0.0;
+  if (i == 0) {
+    KrylovCtrl* C = I.ctrl;
+    C->want_restart = 1;
+    C->its_total = 0;
+    C->failed = 0;
+    C->relres = 0.0;
+    C->iter = 0;
+    C->j = 0;
+    C->stop = 0;
+    C->breakdown = 0;
+  }
+}
+
+// Diagonal part of the preconditioner: z_{y,w,v} = A11^-1 r, and the multigrid
+// right-hand side b_0 = (T) r_p (P_D) or, after k_pt_rhs, B z_A - r_p (P_T).
+// Operands: explicit pointers, or (when null) the FGMRES slots r = V_j, z = Z_j.
 template <typename T>
-__global__ void __launch_bounds__(kBS) k_precond_diag(Inst I, const double* __restrict__ r, double* __restrict__ z,
-                                                      int pt, int guard) {
+__global__ void __launch_bounds__(kBS) k_precond_diag(const Inst* __restrict__ Dp, const double* __restrict__ rx,
+                                                      double* __restrict__ zx, int j, int pt, int guard) {
+  INST_BEGIN
   if (guard && I.ctrl->stop) return;
   const int i = blockIdx.x * kBS + threadIdx.x;
   if (i >= I.n) return;
   const int n = I.n;
+  const double* r = rx ? rx : I.fV + (size_t)j * 4 * n;
+  double* z = zx ? zx : I.fZ + (size_t)j * 4 * n;
   double zy, zw, zv;
   apply_A11_inv(I, i, r[i], r[n + i], r[2 * n + i], zy, zw, zv);
   z[i] = zy; z[n + i] = zw; z[2 * n + i] = zv;
@@ -123,52 +176,60 @@ __global__ void __launch_bounds__(kBS) k_precond_diag(Inst I, const double* __re
 // P_T (Sec. 4, block lower triangular [A11 0; B -S_hat]): the p block solves
 // S_hat z_p = B z_A - r_p with B z_A = A z_y - z_w + z_v (M = I).
 template <typename T>
-__global__ void __launch_bounds__(kBS) k_pt_rhs(Inst I, const double* __restrict__ r, const double* __restrict__ z,
-                                                int guard) {
+__global__ void __launch_bounds__(kBS) k_pt_rhs(const Inst* __restrict__ Dp, const double* __restrict__ rx,
+                                                const double* __restrict__ zx, int j, int guard) {
+  INST_BEGIN
   if (guard && I.ctrl->stop) return;
   const int i = blockIdx.x * kBS + threadIdx.x;
   if (i >= I.n) return;
   int i1, i2, i3;
   node_coords(i, I.N, I.dim, i1, i2, i3);
   const int n = I.n;
+  const double* r = rx ? rx : I.fV + (size_t)j * 4 * n;
+  const double* z = zx ? zx : I.fZ + (size_t)j * 4 * n;
   const double Bz = apply_op<double>(z, i, i1, i2, i3, I.N, I.dim, I.pde, I.h, I.eps, false) - z[n + i] + z[2 * n + i];
   ((T*)I.lv[0].b)[i] = (T)(Bz - r[3 * n + i]);
 }
 
-// z_p = (double) x_mg
+// z_p = (double) multigrid output
 template <typename T>
-__global__ void __launch_bounds__(kBS) k_store_p(Inst I, const T* __restrict__ xmg, double* __restrict__ z, int guard) {
+__global__ void __launch_bounds__(kBS) k_store_p(const Inst* __restrict__ Dp, double* __restrict__ zx, int j, int outsel,
+                                                 int guard) {
+  INST_BEGIN
   if (guard && I.ctrl->stop) return;
   const int i = blockIdx.x * kBS + threadIdx.x;
   if (i >= I.n) return;
-  z[3 * I.n + i] = (double)xmg[i];
+  double* z = zx ? zx : I.fZ + (size_t)j * 4 * I.n;
+  z[3 * I.n + i] = (double)mg_out<T>(I, outsel)[i];
 }
 
 // ---------------------------------------------------------------- MINRES
 
-// Start of a MINRES cycle from residual r: v_1 = r, v_0 = 0, w = 0,
-// z_1 on the diagonal blocks, partial <v_1, z_1>; b_0 = (T) r_p.
+// Start of a MINRES cycle from the residual (src 0: rhs, 1: R): v_1 = r,
+// v_0 = 0, w = K w = 0, tracked r = source, z_1 on the diagonal blocks,
+// partial <v_1, z_1>; b_0 = (T) r_p.  Instances without a pending cycle skip.
 template <typename T>
-__global__ void __launch_bounds__(kBS) k_minres_init(Inst I, const double* __restrict__ r, double* __restrict__ V1,
-                                                     double* __restrict__ V0, double* __restrict__ Z1,
-                                                     double* __restrict__ W0, double* __restrict__ W1,
-                                                     double* __restrict__ KW0, double* __restrict__ KW1,
-                                                     double* __restrict__ Rt) {
+__global__ void __launch_bounds__(kBS) k_minres_init(const Inst* __restrict__ Dp, int src) {
+  INST_BEGIN
+  if (!I.ctrl->want_restart) return;
   __shared__ double smem[kBS / 64];
   const int i = blockIdx.x * kBS + threadIdx.x;
   double acc[1] = {0.0};
   if (i < I.n) {
     const int n = I.n;
+    const double* r = src ? I.R : I.rhs;
     const double ry = r[i], rw = r[n + i], rv = r[2 * n + i], rp = r[3 * n + i];
     double zy, zw, zv;
     apply_A11_inv(I, i, ry, rw, rv, zy, zw, zv);
+    double* V1 = I.V[1];
+    double* Z1 = I.Z[1];
     V1[i] = ry; V1[n + i] = rw; V1[2 * n + i] = rv; V1[3 * n + i] = rp;
     Z1[i] = zy; Z1[n + i] = zw; Z1[2 * n + i] = zv;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const int j = k * n + i;
-      V0[j] = 0.0; W0[j] = 0.0; W1[j] = 0.0; KW0[j] = 0.0; KW1[j] = 0.0;
-      Rt[j] = r[j];
+      const int q = k * n + i;
+      I.V[0][q] = 0.0; I.W[0][q] = 0.0; I.W[1][q] = 0.0; I.KW[0][q] = 0.0; I.KW[1][q] = 0.0;
+      I.Rt[q] = r[q];
     }
     ((T*)I.lv[0].b)[i] = (T)rp;
     acc[0] = ry * zy + rw * zw + rv * zv;
@@ -177,32 +238,27 @@ __global__ void __launch_bounds__(kBS) k_minres_init(Inst I, const double* __res
     I.ctrl->dot_tmp = acc[0];
 }
 
-// Apply the pending update of iteration i at node k:
-//   w_i = (z_i/gamma_i - a3 w_{i-2} - a2 w_{i-1}) / a1,  x += coef_x w_i
-__device__ __forceinline__ void minres_pending(const KrylovCtrl& C, const double* __restrict__ Zi,
-                                               double* __restrict__ Wsame, const double* __restrict__ Wother,
-                                               double* __restrict__ X, int k) {
-  const double wi = (Zi[k] / C.gamma_w - C.a3 * Wsame[k] - C.a2 * Wother[k]) / C.a1;
-  Wsame[k] = wi;
-  X[k] += C.coef_x * wi;
-}
-
 // K1: pending update of iteration j-1 (direction w, solution x, and by the
 // same recurrence K w and the residual r = b - K x, with |r|^2), then
 // q = K z_j / gamma_j and delta_j = <q, z_j/gamma_j>.  The last block stops
 // the solve once |r|_2 <= rtarget (the true residual is tracked exactly in
 // exact arithmetic whatever the preconditioner, so FP32 V-cycles cannot fake
-// convergence).
-__global__ void __launch_bounds__(kBS) k_minres_k1(Inst I, const double* __restrict__ Zc,
-                                                   const double* __restrict__ Zprev, double* __restrict__ Wsame,
-                                                   const double* __restrict__ Wother, double* __restrict__ X,
-                                                   double* __restrict__ Q, double* __restrict__ KWsame,
-                                                   const double* __restrict__ KWother, double* __restrict__ Rt,
-                                                   int timing) {
+// convergence).  par = parity of j; timing = 1 only for stand-alone timing.
+__global__ void __launch_bounds__(kBS) k_minres_k1(const Inst* __restrict__ Dp, int par, int timing) {
+  INST_BEGIN
   __shared__ double smem[2 * kBS / 64];
   KrylovCtrl* C = I.ctrl;
   if (C->stop && !timing) return;
   const int pending = timing ? 1 : C->pending;
+  const double* __restrict__ Zc = I.Z[par];
+  const double* __restrict__ Zprev = I.Z[1 - par];
+  double* __restrict__ Wsame = I.W[1 - par];
+  const double* __restrict__ Wother = I.W[par];
+  double* __restrict__ KWsame = I.KW[1 - par];
+  const double* __restrict__ KWother = I.KW[par];
+  double* __restrict__ X = I.X;
+  double* __restrict__ Q = I.Q;
+  double* __restrict__ Rt = I.Rt;
   const int i = blockIdx.x * kBS + threadIdx.x;
   double acc[2] = {0.0, 0.0};
   if (i < I.n) {
@@ -244,11 +300,15 @@ __global__ void __launch_bounds__(kBS) k_minres_k1(Inst I, const double* __restr
 // K2: Lanczos vector v_{j+1} (overwrites v_{j-1}), z_{j+1} on the diagonal
 // blocks, partial <v_{j+1}, z_{j+1}>, b_0 = (T) v_{j+1,p} for the multigrid.
 template <typename T>
-__global__ void __launch_bounds__(kBS) k_minres_k2(Inst I, const double* __restrict__ Q, const double* __restrict__ Vc,
-                                                   double* __restrict__ Vn, double* __restrict__ Zn) {
+__global__ void __launch_bounds__(kBS) k_minres_k2(const Inst* __restrict__ Dp, int par) {
+  INST_BEGIN
   __shared__ double smem[kBS / 64];
   const KrylovCtrl* C = I.ctrl;
   if (C->stop) return;
+  const double* __restrict__ Q = I.Q;
+  const double* __restrict__ Vc = I.V[par];
+  double* __restrict__ Vn = I.V[1 - par];
+  double* __restrict__ Zn = I.Z[1 - par];
   const int i = blockIdx.x * kBS + threadIdx.x;
   double acc[1] = {0.0};
   if (i < I.n) {
@@ -270,15 +330,19 @@ __global__ void __launch_bounds__(kBS) k_minres_k2(Inst I, const double* __restr
     I.ctrl->dot_tmp = acc[0];
 }
 
-// K4: z_{j+1,p} from the multigrid output, the rest of <v, z>, then the
-// scalar recurrence in the last block.  mode 0 starts a cycle (gamma_1),
-// mode 1 is an iteration.  rtarget: residual norm at which K1 stops (mode 0).
+// K4: z_{nb,p} from the multigrid output, the rest of <v, z>, then the scalar
+// recurrence in the last block.  mode 0 starts a cycle (gamma_1; nb = 1; the
+// stop target is tol |b|), mode 1 is an iteration (nb = 1 - parity).
 template <typename T>
-__global__ void __launch_bounds__(kBS) k_minres_k4(Inst I, const T* __restrict__ xmg, const double* __restrict__ Vn,
-                                                   double* __restrict__ Zn, int mode, double rtarget, int maxit) {
+__global__ void __launch_bounds__(kBS) k_minres_k4(const Inst* __restrict__ Dp, int nb, int mode, double tol, int maxit,
+                                                   int outsel) {
+  INST_BEGIN
   __shared__ double smem[kBS / 64];
   KrylovCtrl* C = I.ctrl;
-  if (mode != 0 && C->stop) return;
+  if (mode == 0 ? !C->want_restart : C->stop) return;
+  const double* __restrict__ Vn = I.V[nb];
+  double* __restrict__ Zn = I.Z[nb];
+  const T* __restrict__ xmg = mg_out<T>(I, outsel);
   const int i = blockIdx.x * kBS + threadIdx.x;
   double acc[1] = {0.0};
   if (i < I.n) {
@@ -293,7 +357,7 @@ __global__ void __launch_bounds__(kBS) k_minres_k4(Inst I, const T* __restrict__
     C->iter = 0;
     C->pending = 0;
     C->breakdown = 0;
-    C->rtarget = rtarget;
+    C->rtarget = tol * C->bnorm;
     C->rtrack = INFINITY;
     C->c_prev = C->c = 1.0;
     C->s_prev = C->s = 0.0;
@@ -336,28 +400,46 @@ __global__ void __launch_bounds__(kBS) k_minres_k4(Inst I, const T* __restrict__
   C->gamma_prev = g; C->gamma = gn;
   C->iter += 1;
   C->est = fabs(C->eta) / C->eta0;
-  if (gn == 0.0 || C->iter >= maxit || !isfinite(a1) || a1 == 0.0) C->stop = 1;
+  if (gn == 0.0 || C->its_total + C->iter >= maxit || !isfinite(a1) || a1 == 0.0) C->stop = 1;
 }
 
-// Pending update alone (after the loop stopped).
-__global__ void __launch_bounds__(kBS) k_minres_flush(Inst I, const double* __restrict__ Zi, double* __restrict__ Wsame,
-                                                      const double* __restrict__ Wother, double* __restrict__ X) {
+// Pending update alone (after the loop stopped), with the parity of the
+// instance's own last iteration.
+__global__ void __launch_bounds__(kBS) k_minres_flush(const Inst* __restrict__ Dp) {
+  INST_BEGIN
   const KrylovCtrl* C = I.ctrl;
-  if (!C->pending) return;
+  if (!C->want_restart || !C->pending) return;
   const int i = blockIdx.x * kBS + threadIdx.x;
   if (i >= I.n) return;
-  const int n = I.n;
+  const int it = C->iter, n = I.n;
+  const double* Zi = I.Z[it & 1];
+  double* Wsame = I.W[it & 1];
+  const double* Wother = I.W[(it + 1) & 1];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) minres_pending(*C, Zi, Wsame, Wother, X, k * n + i);
+  for (int k = 0; k < 4; ++k) {
+    const int q = k * n + i;
+    const double wi = (Zi[q] / C->gamma_w - C->a3 * Wsame[q] - C->a2 * Wother[q]) / C->a1;
+    Wsame[q] = wi;
+    I.X[q] += C->coef_x * wi;
+  }
 }
 
-#define IPM_KRY_INST(T)                                                                              \
-  template __global__ void k_precond_diag<T>(Inst, const double*, double*, int, int);               \
-  template __global__ void k_pt_rhs<T>(Inst, const double*, const double*, int);                    \
-  template __global__ void k_store_p<T>(Inst, const T*, double*, int);                              \
-  template __global__ void k_minres_init<T>(Inst, const double*, double*, double*, double*, double*, double*, double*, double*, double*); \
-  template __global__ void k_minres_k2<T>(Inst, const double*, const double*, double*, double*);    \
-  template __global__ void k_minres_k4<T>(Inst, const T*, const double*, double*, int, double, int);
+// Clear the stop flag (used before timing the iteration kernels in isolation).
+__global__ void k_ctrl_continue(const Inst* __restrict__ Dp) {
+  INST_BEGIN
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    I.ctrl->stop = 0;
+    I.ctrl->pending = 0;
+  }
+}
+
+#define IPM_KRY_INST(T)                                                                          \
+  template __global__ void k_precond_diag<T>(const Inst*, const double*, double*, int, int, int); \
+  template __global__ void k_pt_rhs<T>(const Inst*, const double*, const double*, int, int);      \
+  template __global__ void k_store_p<T>(const Inst*, double*, int, int, int);                     \
+  template __global__ void k_minres_init<T>(const Inst*, int);                                   \
+  template __global__ void k_minres_k2<T>(const Inst*, int);                                     \
+  template __global__ void k_minres_k4<T>(const Inst*, int, int, double, int, int);
 IPM_KRY_INST(float)
 IPM_KRY_INST(double)
 #undef IPM_KRY_INST

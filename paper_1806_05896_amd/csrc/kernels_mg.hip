@@ -108,35 +108,54 @@ __device__ __forceinline__ T prolong_node(const T* __restrict__ xc, int i, int N
 
 // ---------------------------------------------------------------- grid-wide kernels
 
+// guard 0: always run; 1: skip when the instance's Krylov loop stopped;
+// 2: skip when the instance has no pending Krylov cycle.
+__device__ __forceinline__ bool mg_skip(const Inst& I, int guard) {
+  return (guard == 1 && I.ctrl->stop) || (guard == 2 && !I.ctrl->want_restart);
+}
 template <typename T>
-__global__ void __launch_bounds__(kBS) k_mg_jacobi(Inst I, int l, const T* __restrict__ xin, T* __restrict__ xout,
-                                                   int first, int transpose, int guard) {
-  if (guard && I.ctrl->stop) return;
+__device__ __forceinline__ T* lvbuf(const Level& L, int sel) {
+  return (T*)(sel ? L.x2 : L.x);
+}
+
+// One damped Jacobi sweep at level l (3D path): x[dst] = sweep(x[src]).
+template <typename T>
+__global__ void __launch_bounds__(kBS) k_mg_jacobi(const Inst* __restrict__ Dp, int l, int src, int dst, int first,
+                                                   int transpose, int guard) {
+  INST_BEGIN
+  if (l >= I.coarse_lev || mg_skip(I, guard)) return;
   const Level& L = I.lv[l];
   const int i = blockIdx.x * kBS + threadIdx.x;
   if (i >= L.n) return;
-  xout[i] = jacobi_node<T>(xin, (const T*)L.b, (const T*)L.mh, i, L.N, I.dim, I.pde, L.h, I.eps, I.omega,
-                           first != 0, transpose != 0);
+  lvbuf<T>(L, dst)[i] = jacobi_node<T>(lvbuf<T>(L, src), (const T*)L.b, (const T*)L.mh, i, L.N, I.dim, I.pde, L.h,
+                                       I.eps, I.omega, first != 0, transpose != 0);
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBS) k_mg_restrict(Inst I, int l, const T* __restrict__ x, int transpose, int guard) {
-  if (guard && I.ctrl->stop) return;
+__global__ void __launch_bounds__(kBS) k_mg_restrict(const Inst* __restrict__ Dp, int l, int src, int transpose,
+                                                     int guard) {
+  INST_BEGIN
+  if (l >= I.coarse_lev || mg_skip(I, guard)) return;
   const Level& F = I.lv[l];
   const Level& C = I.lv[l + 1];
   const int ic = blockIdx.x * kBS + threadIdx.x;
   if (ic >= C.n) return;
-  ((T*)C.b)[ic] = restrict_resid_node<T>(x, (const T*)F.b, (const T*)F.mh, ic, F.N, C.N, I.dim, I.pde, F.h, I.eps,
-                                         transpose != 0);
+  ((T*)C.b)[ic] = restrict_resid_node<T>(lvbuf<T>(F, src), (const T*)F.b, (const T*)F.mh, ic, F.N, C.N, I.dim, I.pde,
+                                         F.h, I.eps, transpose != 0);
 }
 
+// x[dst] at level l += P (level l+1's current iterate: its x if it is the
+// coarse-kernel level, else x[csel]).
 template <typename T>
-__global__ void __launch_bounds__(kBS) k_mg_prolong(Inst I, int l, T* __restrict__ x, const T* __restrict__ xc, int guard) {
-  if (guard && I.ctrl->stop) return;
+__global__ void __launch_bounds__(kBS) k_mg_prolong(const Inst* __restrict__ Dp, int l, int dst, int csel, int guard) {
+  INST_BEGIN
+  if (l >= I.coarse_lev || mg_skip(I, guard)) return;
   const Level& F = I.lv[l];
+  const Level& C = I.lv[l + 1];
   const int i = blockIdx.x * kBS + threadIdx.x;
   if (i >= F.n) return;
-  x[i] += prolong_node<T>(xc, i, F.N, I.lv[l + 1].N, I.dim);
+  const T* xc = (l + 1 == I.coarse_lev) ? (const T*)C.x : lvbuf<T>(C, csel);
+  lvbuf<T>(F, dst)[i] += prolong_node<T>(xc, i, F.N, C.N, I.dim);
 }
 
 // All levels l >= coarse_lev in one workgroup: V-cycle from b at coarse_lev
@@ -163,8 +182,9 @@ __device__ __forceinline__ T coarse_resid(const T* __restrict__ x, const T* __re
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kCoarseBS) k_mg_coarse(Inst I, int transpose, int guard) {
-  if (guard && I.ctrl->stop) return;
+__global__ void __launch_bounds__(kCoarseBS) k_mg_coarse(const Inst* __restrict__ Dp, int transpose, int guard) {
+  INST_BEGIN
+  if (I.coarse_p2 || mg_skip(I, guard)) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ CoarseLevel LI[kMaxLev];
   T* lds = (T*)lds_raw;
@@ -319,8 +339,9 @@ __host__ __device__ inline int coarse_p2_elems(int N) { return 2 * (N + 2) * (N 
   }
 
 template <typename T>
-__global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_p2(Inst I, int guard) {
-  if (guard && I.ctrl->stop) return;
+__global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_p2(const Inst* __restrict__ Dp, int guard) {
+  INST_BEGIN
+  if (!I.coarse_p2 || mg_skip(I, guard)) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ int LN[kMaxLev], LOFF[kMaxLev];
   __shared__ T LIH2[kMaxLev];
@@ -442,24 +463,41 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_p2(Inst I, int guard) {
     P2_FOR(N) xg[i] = a[p]; P2_END
   }
 }
-template __global__ void k_mg_coarse_p2<float>(Inst, int);
-template __global__ void k_mg_coarse_p2<double>(Inst, int);
+template __global__ void k_mg_coarse_p2<float>(const Inst*, int);
+template __global__ void k_mg_coarse_p2<double>(const Inst*, int);
 
-// b_0 = (1 + Theta_y) x between the two solves of S_hat^-1.
+// b_0 = (1 + Theta_y) x between the two solves of S_hat^-1 (3D path); x is
+// the first solve's level-0 output (x or x2 by outsel, x when the whole
+// hierarchy ran in the coarse kernel).
 template <typename T>
-__global__ void __launch_bounds__(kBS) k_mg_scale_ty(Inst I, const T* __restrict__ x, int guard) {
-  if (guard && I.ctrl->stop) return;
+__global__ void __launch_bounds__(kBS) k_mg_scale_ty(const Inst* __restrict__ Dp, int outsel, int guard) {
+  INST_BEGIN
+  if (mg_skip(I, guard)) return;
   const int i = blockIdx.x * kBS + threadIdx.x;
   if (i >= I.n) return;
+  const T* x = (const T*)((I.coarse_lev == 0 || !outsel) ? I.lv[0].x : I.lv[0].x2);
   ((T*)I.lv[0].b)[i] = (T)(1.0 + I.ty[i]) * x[i];
 }
 
-#define IPM_MG_INST(T)                                                            \
-  template __global__ void k_mg_jacobi<T>(Inst, int, const T*, T*, int, int, int); \
-  template __global__ void k_mg_restrict<T>(Inst, int, const T*, int, int);        \
-  template __global__ void k_mg_prolong<T>(Inst, int, T*, const T*, int);          \
-  template __global__ void k_mg_coarse<T>(Inst, int, int);                         \
-  template __global__ void k_mg_scale_ty<T>(Inst, const T*, int);
+// b_0 = (1 + Theta_y) x for the instances of a 2D batch whose whole
+// hierarchy runs in the coarse kernel (the others scale inside their first
+// descent kernel).
+template <typename T>
+__global__ void __launch_bounds__(kBS) k_mg_scale_ty_small(const Inst* __restrict__ Dp, int guard) {
+  INST_BEGIN
+  if (I.coarse_lev != 0 || mg_skip(I, guard)) return;
+  const int i = blockIdx.x * kBS + threadIdx.x;
+  if (i >= I.n) return;
+  ((T*)I.lv[0].b)[i] = (T)(1.0 + I.ty[i]) * ((const T*)I.lv[0].x)[i];
+}
+
+#define IPM_MG_INST(T)                                                              \
+  template __global__ void k_mg_jacobi<T>(const Inst*, int, int, int, int, int, int); \
+  template __global__ void k_mg_restrict<T>(const Inst*, int, int, int, int);         \
+  template __global__ void k_mg_prolong<T>(const Inst*, int, int, int, int);          \
+  template __global__ void k_mg_coarse<T>(const Inst*, int, int);                     \
+  template __global__ void k_mg_scale_ty<T>(const Inst*, int, int);                   \
+  template __global__ void k_mg_scale_ty_small<T>(const Inst*, int);
 IPM_MG_INST(float)
 IPM_MG_INST(double)
 #undef IPM_MG_INST
@@ -492,13 +530,19 @@ __device__ __forceinline__ T jacobi_lds(const T* __restrict__ xa, const T* __res
 // bsrc: right-hand side of level l; if ty != nullptr the right-hand side is
 // (1 + Theta_y) bsrc (start of the second solve of S_hat^-1, level 0 only).
 template <typename T, int NU>
-__global__ void __launch_bounds__(kBS) k_mg_down2d(Inst I, int l, const T* __restrict__ bsrc,
-                                                   const double* __restrict__ ty, T* __restrict__ xout, int transpose,
+__global__ void __launch_bounds__(kBS) k_mg_down2d(const Inst* __restrict__ Dp, int l, int scaled, int transpose,
                                                    int guard) {
-  if (guard && I.ctrl->stop) return;
+  INST_BEGIN
+  if (l >= I.coarse_lev || mg_skip(I, guard)) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const Level& F = I.lv[l];
   const Level& C = I.lv[l + 1];
+  // scaled (level 0 only): the right-hand side is (1 + Theta_y) times the
+  // first solve's output (level 0's x2)
+  const T* __restrict__ bsrc = (const T*)(scaled ? F.x2 : F.b);
+  const double* __restrict__ ty = scaled ? I.ty : nullptr;
+  T* __restrict__ xout = (T*)F.x;
+  if ((int)(blockIdx.x * kTC) >= C.N || (int)(blockIdx.y * kTC) >= C.N) return;
   const int N = F.N, Nc = C.N;
   constexpr int nu = NU;
   constexpr int W = down_width(NU);
@@ -596,11 +640,15 @@ __global__ void __launch_bounds__(kBS) k_mg_down2d(Inst I, int l, const T* __res
 // Ascent at level l: x = xpre + P xc, then nu damped-Jacobi sweeps, for a
 // tile of TF x TF fine nodes (halo nu in LDS).
 template <typename T, int NU>
-__global__ void __launch_bounds__(kBS) k_mg_up2d(Inst I, int l, const T* __restrict__ xpre, const T* __restrict__ xc,
-                                                 T* __restrict__ xout, int transpose, int guard) {
-  if (guard && I.ctrl->stop) return;
+__global__ void __launch_bounds__(kBS) k_mg_up2d(const Inst* __restrict__ Dp, int l, int transpose, int guard) {
+  INST_BEGIN
+  if (l >= I.coarse_lev || mg_skip(I, guard)) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const Level& F = I.lv[l];
+  const T* __restrict__ xpre = (const T*)F.x;
+  const T* __restrict__ xc = (const T*)(l + 1 == I.coarse_lev ? I.lv[l + 1].x : I.lv[l + 1].x2);
+  T* __restrict__ xout = (T*)F.x2;
+  if ((int)(blockIdx.x * kTF) >= F.N || (int)(blockIdx.y * kTF) >= F.N) return;
   const int N = F.N, Nc = I.lv[l + 1].N;
   constexpr int nu = NU;
   constexpr int W = up_width(NU);
@@ -653,9 +701,9 @@ __global__ void __launch_bounds__(kBS) k_mg_up2d(Inst I, int l, const T* __restr
   }
 }
 
-#define IPM_MG2_INST(T, NU)                                                                              \
-  template __global__ void k_mg_down2d<T, NU>(Inst, int, const T*, const double*, T*, int, int);       \
-  template __global__ void k_mg_up2d<T, NU>(Inst, int, const T*, const T*, T*, int, int);
+#define IPM_MG2_INST(T, NU)                                                        \
+  template __global__ void k_mg_down2d<T, NU>(const Inst*, int, int, int, int);  \
+  template __global__ void k_mg_up2d<T, NU>(const Inst*, int, int, int);
 #define IPM_MG2_INST_ALL(T) IPM_MG2_INST(T, 1) IPM_MG2_INST(T, 2) IPM_MG2_INST(T, 3) IPM_MG2_INST(T, 4) \
   IPM_MG2_INST(T, 5) IPM_MG2_INST(T, 6)
 IPM_MG2_INST_ALL(float)

@@ -3,8 +3,11 @@
 // One translation unit: the kernel files are included here so that every
 // launch site sees its kernel.  The interior point loop (Appendix,
 // Algorithm A.1) runs on the host; every vector operation of it runs in the
-// kernels on the caller's stream.  The only device-to-host traffic is a few
-// scalars per IPM iteration (measures, step lengths) and per Krylov chunk.
+// kernels on the caller's stream.  Work is organised in groups: a device
+// array of instance descriptors that every kernel indexes with blockIdx.z,
+// so one launch advances all instances of a batch; a single problem is a
+// group of one.  The only device-to-host traffic is a few scalars per
+// instance per IPM iteration and per Krylov chunk.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -13,6 +16,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -43,9 +47,9 @@ static int fail(int code, const std::string& msg) {
       return fail(IPMPDE_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));              \
   } while (0)
 
-#define TRY(expr)                 \
-  do {                            \
-    int rc_ = (expr);             \
+#define TRY(expr)                     \
+  do {                                \
+    int rc_ = (expr);                 \
     if (rc_ != IPMPDE_OK) return rc_; \
   } while (0)
 
@@ -62,95 +66,98 @@ struct Alloc {
   void* ctx;
 };
 
-// ---------------------------------------------------------------------------
-// problem
-
-struct GraphKey {
-  int mg_fp32, nu_pre, nu_post, chunk, maxit, parity, krylov, precond, restart;
-  double omega;
-  bool operator<(const GraphKey& o) const {
-    return std::tie(mg_fp32, nu_pre, nu_post, chunk, maxit, parity, krylov, precond, restart, omega) <
-           std::tie(o.mg_fp32, o.nu_pre, o.nu_post, o.chunk, o.maxit, o.parity, o.krylov, o.precond, o.restart,
-                    o.omega);
+struct AllocList {
+  std::vector<Alloc> a;
+  int alloc(void** out, size_t bytes) {
+    void* p = nullptr;
+    bytes = std::max<size_t>(bytes, 256);
+    if (g_alloc) {
+      p = g_alloc(bytes, g_alloc_ctx);
+      if (!p) return fail(IPMPDE_ENOMEM, "allocator callback returned NULL");
+      a.push_back({p, g_free, g_alloc_ctx});
+    } else {
+      hipError_t e = hipMalloc(&p, bytes);
+      if (e != hipSuccess) return fail(IPMPDE_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+      a.push_back({p, nullptr, nullptr});
+    }
+    *out = p;
+    return IPMPDE_OK;
+  }
+  template <typename T>
+  int alloc_t(T** out, size_t count) {
+    return alloc((void**)out, count * sizeof(T));
+  }
+  void release() {
+    for (auto& x : a) {
+      if (x.fr) x.fr(x.p, x.ctx);
+      else (void)hipFree(x.p);
+    }
+    a.clear();
   }
 };
 
+// ---------------------------------------------------------------------------
+// groups
+
+struct GraphKey {
+  int mg_fp32, nu_pre, nu_post, chunk, maxit, count;
+  double omega, tol;
+  bool operator<(const GraphKey& o) const {
+    return std::tie(mg_fp32, nu_pre, nu_post, chunk, maxit, count, omega, tol) <
+           std::tie(o.mg_fp32, o.nu_pre, o.nu_post, o.chunk, o.maxit, o.count, o.omega, o.tol);
+  }
+};
+
+struct ipmpde_problem;
+
+// A set of instances advanced together.  Each descriptor is a copy of its
+// problem's template with the group's own scalar areas (ctrl, stat) and the
+// per-step fields (mu, active, multigrid selection) filled in.
+struct Group {
+  std::vector<ipmpde_problem*> probs;
+  int count = 0, dim = 0;
+  Inst* D = nullptr;             // device descriptors
+  Inst* H = nullptr;             // pinned host copies
+  KrylovCtrl* ctrl_d = nullptr;
+  KrylovCtrl* ctrl_h = nullptr;  // pinned (the prefix up to hcol is copied back)
+  double* stat_d = nullptr;
+  double* stat_h = nullptr;      // pinned, 16 per instance
+  hipStream_t cap_stream = nullptr;
+  std::map<GraphKey, hipGraphExec_t> graphs;
+  AllocList mem;
+  // grid sizes (maxima over instances) after group_select
+  int max_n = 0, max_nlev = 0, max_cl = 0;
+  int maxN[kMaxLev] = {0};
+  long maxn[kMaxLev] = {0};
+  size_t coarse_lds = 0;
+  bool p2 = false;   // some instance is 2D Poisson (padded coarse kernel)
+  bool gen = false;  // some instance uses the generic coarse kernel
+  bool any_small = false;  // 2D: some instance runs its whole hierarchy in the coarse kernel
+  int outsel = 1;    // level-0 output buffer of a V-cycle (x2 = 1)
+  int sel_pre = 0;   // 3D path: buffer holding the pre-smoothed iterate
+  bool fp32 = true;
+};
+
 struct ipmpde_problem {
-  Inst I;
+  Inst I;  // template descriptor (device pointers, problem data)
   int dim = 0, N = 0, n = 0, pde = 0;
   double eps = 1.0, alpha = 0.0, beta = 0.0;
   bool has_y = false;
-  std::vector<Alloc> allocs;
-  // Newton system and Krylov workspace (4n each)
-  double* rhs = nullptr;
-  double* X = nullptr;
-  double* V[2] = {nullptr, nullptr};
-  double* Z[2] = {nullptr, nullptr};
-  double* W[2] = {nullptr, nullptr};
-  double* Q = nullptr;
-  double* R = nullptr;
-  double* KW[2] = {nullptr, nullptr};  // K w for the two most recent MINRES directions
-  double* Rt = nullptr;                // tracked MINRES residual
-  // FGMRES basis (allocated on first use)
-  double* fV = nullptr;
-  double* fZ = nullptr;
-  int f_restart = 0;
-  // multigrid storage per precision
+  AllocList mem;
   int nlev = 0;
   Level lv32[kMaxLev];
   Level lv64[kMaxLev];
-  Level* lvd32 = nullptr;  // device copies of the level tables
+  Level* lvd32 = nullptr;
   Level* lvd64 = nullptr;
   bool have32 = false, have64 = false;
   int coarse32 = 0, coarse64 = 0;
-  // host mirrors (pinned)
-  KrylovCtrl* ctrl_h = nullptr;
-  double* stat_h = nullptr;
-  hipStream_t cap_stream = nullptr;
-  std::map<GraphKey, hipGraphExec_t> graphs;
+  int f_restart = 0;
+  Group* self = nullptr;  // the group of one used by the single-problem entry points
   ipmpde_stats stats;
   double mu = 1.0;
   bool setup_done = false;
   int setup_fp32 = -1;
-  double setup_mu = 0.0;
 };
-
-static int dalloc(ipmpde_problem* P, void** out, size_t bytes) {
-  void* p = nullptr;
-  bytes = std::max<size_t>(bytes, 256);
-  if (g_alloc) {
-    p = g_alloc(bytes, g_alloc_ctx);
-    if (!p) return fail(IPMPDE_ENOMEM, "allocator callback returned NULL");
-    P->allocs.push_back({p, g_free, g_alloc_ctx});
-  } else {
-    hipError_t e = hipMalloc(&p, bytes);
-    if (e != hipSuccess) return fail(IPMPDE_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
-    P->allocs.push_back({p, nullptr, nullptr});
-  }
-  *out = p;
-  return IPMPDE_OK;
-}
-
-template <typename T>
-static int dalloc_t(ipmpde_problem* P, T** out, size_t count) {
-  return dalloc(P, (void**)out, count * sizeof(T));
-}
-
-static void free_all(ipmpde_problem* P) {
-  for (auto& kv : P->graphs) hipGraphExecDestroy(kv.second);
-  P->graphs.clear();
-  for (auto& a : P->allocs) {
-    if (a.fr) a.fr(a.p, a.ctx);
-    else hipFree(a.p);
-  }
-  P->allocs.clear();
-  if (P->ctrl_h) hipHostFree(P->ctrl_h);
-  if (P->stat_h) hipHostFree(P->stat_h);
-  if (P->cap_stream) hipStreamDestroy(P->cap_stream);
-  P->ctrl_h = nullptr;
-  P->stat_h = nullptr;
-  P->cap_stream = nullptr;
-}
 
 static bool is_pow2m1(int N) { return N >= 3 && ((N + 1) & N) == 0; }
 
@@ -161,6 +168,8 @@ static int level_count(int N) {
 }
 
 static size_t pow_dim(int N, int dim) { return dim == 2 ? (size_t)N * N : (size_t)N * N * N; }
+
+static int nblk(long n) { return div_up(n, kBS); }
 
 // LDS budget of the single-workgroup coarse kernel (gfx950 has 160 KB of
 // LDS per CU), and the largest grid it takes; finer levels run as
@@ -190,21 +199,23 @@ static size_t coarse_lds_bytes(const Level* lv, int nlev, int cl, size_t elem, b
   return need;
 }
 
-// Allow the coarse kernel more than the default 64 KB of dynamic LDS.
+// Allow the coarse kernels more than the default 64 KB of dynamic LDS.
 static int set_coarse_lds_limit() {
-  static bool done = false;
-  if (done) return IPMPDE_OK;
-  HIP_TRY(hipFuncSetAttribute((const void*)k_mg_coarse<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)kCoarseLds));
-  HIP_TRY(hipFuncSetAttribute((const void*)k_mg_coarse<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)kCoarseLds));
-  HIP_TRY(hipFuncSetAttribute((const void*)k_mg_coarse_p2<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)kCoarseLds));
-  HIP_TRY(hipFuncSetAttribute((const void*)k_mg_coarse_p2<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)kCoarseLds));
-  done = true;
+  static std::once_flag once;
+  static hipError_t err = hipSuccess;
+  std::call_once(once, [] {
+    const void* fns[] = {(const void*)k_mg_coarse<float>, (const void*)k_mg_coarse<double>,
+                         (const void*)k_mg_coarse_p2<float>, (const void*)k_mg_coarse_p2<double>};
+    for (const void* f : fns) {
+      hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCoarseLds);
+      if (e != hipSuccess) err = e;
+    }
+  });
+  if (err != hipSuccess) return fail(IPMPDE_EDEVICE, std::string("hipFuncSetAttribute: ") + hipGetErrorString(err));
   return IPMPDE_OK;
 }
+
+static bool is_p2(const ipmpde_problem* P) { return P->dim == 2 && P->pde == IPMPDE_POISSON; }
 
 static int ensure_mg(ipmpde_problem* P, bool fp32) {
   TRY(set_coarse_lds_limit());
@@ -219,39 +230,169 @@ static int ensure_mg(ipmpde_problem* P, bool fp32) {
     lv[l].h = 1.0 / (N + 1);
     lv[l].invN = 1.0f / (float)N;
     const size_t nb = (size_t)lv[l].n * el;
-    TRY(dalloc(P, &lv[l].x, nb));
-    TRY(dalloc(P, &lv[l].x2, nb));
-    TRY(dalloc(P, &lv[l].b, nb));
-    TRY(dalloc(P, &lv[l].mh, nb));
+    TRY(P->mem.alloc(&lv[l].x, nb));
+    TRY(P->mem.alloc(&lv[l].x2, nb));
+    TRY(P->mem.alloc(&lv[l].b, nb));
+    TRY(P->mem.alloc(&lv[l].mh, nb));
     HIP_TRY(hipMemset(lv[l].x, 0, nb));
     HIP_TRY(hipMemset(lv[l].x2, 0, nb));
     HIP_TRY(hipMemset(lv[l].b, 0, nb));
     HIP_TRY(hipMemset(lv[l].mh, 0, nb));
     N = (N - 1) / 2;
   }
-  (fp32 ? P->coarse32 : P->coarse64) = pick_coarse(lv, P->nlev, el, P->dim, P->dim == 2 && P->pde == IPMPDE_POISSON);
+  (fp32 ? P->coarse32 : P->coarse64) = pick_coarse(lv, P->nlev, el, P->dim, is_p2(P));
   Level*& lvd = fp32 ? P->lvd32 : P->lvd64;
-  TRY(dalloc(P, (void**)&lvd, sizeof(Level) * kMaxLev));
+  TRY(P->mem.alloc_t(&lvd, kMaxLev));
   HIP_TRY(hipMemcpy(lvd, lv, sizeof(Level) * kMaxLev, hipMemcpyHostToDevice));
   have = true;
   return IPMPDE_OK;
 }
 
-static void select_mg(ipmpde_problem* P, const ipmpde_options& o) {
-  const bool fp32 = o.mg_precision == IPMPDE_FP32;
-  Level* lv = fp32 ? P->lv32 : P->lv64;
-  for (int l = 0; l < P->nlev; ++l) P->I.lv[l] = lv[l];
-  P->I.nlev = P->nlev;
-  P->I.coarse_lev = fp32 ? P->coarse32 : P->coarse64;
-  P->I.lvd = fp32 ? P->lvd32 : P->lvd64;
-  P->I.mg_fp32 = fp32 ? 1 : 0;
-  P->I.nu_pre = o.nu_pre;
-  P->I.nu_post = o.nu_post;
-  P->I.vcycles = o.vcycles;
-  P->I.omega = o.omega > 0 ? o.omega : (P->dim == 2 ? 0.8 : 6.0 / 7.0);
+static int ensure_fgmres(ipmpde_problem* P, int restart) {
+  if (P->I.fV && P->f_restart >= restart) return IPMPDE_OK;
+  const size_t n4 = 4 * (size_t)P->n;
+  TRY(P->mem.alloc_t(&P->I.fV, (size_t)(restart + 1) * n4));
+  TRY(P->mem.alloc_t(&P->I.fZ, (size_t)restart * n4));
+  P->f_restart = restart;
+  return IPMPDE_OK;
 }
 
-static int nblk(long n) { return div_up(n, kBS); }
+// partial-sum capacity for reductions over `blocks` blocks (3 values each)
+// and for the FGMRES block dot products (61 x 256)
+static int ensure_partials(ipmpde_problem* P, int blocks) {
+  const int need = std::max(4 * blocks, 64 * kBS) + 64;
+  if (P->I.nparts >= need) return IPMPDE_OK;
+  TRY(P->mem.alloc_t(&P->I.partials, (size_t)need));
+  P->I.nparts = need;
+  return IPMPDE_OK;
+}
+
+static void group_release(Group* G) {
+  if (!G) return;
+  for (auto& kv : G->graphs) (void)hipGraphExecDestroy(kv.second);
+  G->graphs.clear();
+  G->mem.release();
+  if (G->H) (void)hipHostFree(G->H);
+  if (G->ctrl_h) (void)hipHostFree(G->ctrl_h);
+  if (G->stat_h) (void)hipHostFree(G->stat_h);
+  if (G->cap_stream) (void)hipStreamDestroy(G->cap_stream);
+  delete G;
+}
+
+static int group_create(const std::vector<ipmpde_problem*>& probs, Group** out) {
+  Group* G = new Group();
+  G->probs = probs;
+  G->count = (int)probs.size();
+  G->dim = probs[0]->dim;
+  auto bail = [&](int rc) { group_release(G); return rc; };
+  int rc;
+  if ((rc = G->mem.alloc_t(&G->D, G->count))) return bail(rc);
+  if ((rc = G->mem.alloc_t(&G->ctrl_d, G->count))) return bail(rc);
+  if ((rc = G->mem.alloc_t(&G->stat_d, 16 * (size_t)G->count))) return bail(rc);
+  hipError_t e;
+  if ((e = hipMemset(G->ctrl_d, 0, sizeof(KrylovCtrl) * G->count)) != hipSuccess ||
+      (e = hipMemset(G->stat_d, 0, 16 * sizeof(double) * G->count)) != hipSuccess ||
+      (e = hipHostMalloc((void**)&G->H, sizeof(Inst) * G->count, hipHostMallocDefault)) != hipSuccess ||
+      (e = hipHostMalloc((void**)&G->ctrl_h, sizeof(KrylovCtrl) * G->count, hipHostMallocDefault)) != hipSuccess ||
+      (e = hipHostMalloc((void**)&G->stat_h, 16 * sizeof(double) * G->count, hipHostMallocDefault)) != hipSuccess ||
+      (e = hipStreamCreateWithFlags(&G->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+    return bail(fail(IPMPDE_EDEVICE, std::string("group setup: ") + hipGetErrorString(e)));
+  std::memset(G->ctrl_h, 0, sizeof(KrylovCtrl) * G->count);
+  for (int i = 0; i < G->count; ++i) {
+    G->H[i] = probs[i]->I;
+    G->H[i].ctrl = G->ctrl_d + i;
+    G->H[i].stat = G->stat_d + 16 * (size_t)i;
+    G->H[i].active = 1;
+    G->H[i].mu = 1.0;
+    G->H[i].alpha0 = 0.995;
+  }
+  *out = G;
+  return IPMPDE_OK;
+}
+
+// Refresh the descriptors from the problems' templates (keeping the
+// per-step fields) and select the multigrid precision and schedule.
+static int group_select(Group* G, const ipmpde_options& o) {
+  const bool fp32 = o.mg_precision == IPMPDE_FP32;
+  G->fp32 = fp32;
+  G->max_n = 0;
+  G->max_nlev = 0;
+  G->max_cl = 0;
+  G->coarse_lds = 0;
+  G->p2 = false;
+  G->gen = false;
+  G->any_small = false;
+  std::fill(G->maxN, G->maxN + kMaxLev, 0);
+  std::fill(G->maxn, G->maxn + kMaxLev, 0);
+  for (int i = 0; i < G->count; ++i) {
+    ipmpde_problem* P = G->probs[i];
+    TRY(ensure_mg(P, fp32));
+    if (o.krylov == IPMPDE_FGMRES) TRY(ensure_fgmres(P, o.restart));
+  }
+  for (int i = 0; i < G->count; ++i) TRY(ensure_partials(G->probs[i], nblk(std::max(G->max_n, G->probs[i]->n))));
+  for (int i = 0; i < G->count; ++i) G->max_n = std::max(G->max_n, G->probs[i]->n);
+  for (int i = 0; i < G->count; ++i) TRY(ensure_partials(G->probs[i], nblk(G->max_n)));
+  for (int i = 0; i < G->count; ++i) {
+    ipmpde_problem* P = G->probs[i];
+    Inst& d = G->H[i];
+    const int active = d.active;
+    const double mu = d.mu, a0 = d.alpha0;
+    d = P->I;
+    d.ctrl = G->ctrl_d + i;
+    d.stat = G->stat_d + 16 * (size_t)i;
+    d.active = active;
+    d.mu = mu;
+    d.alpha0 = a0;
+    const Level* lv = fp32 ? P->lv32 : P->lv64;
+    for (int l = 0; l < P->nlev; ++l) d.lv[l] = lv[l];
+    d.nlev = P->nlev;
+    d.coarse_lev = fp32 ? P->coarse32 : P->coarse64;
+    d.lvd = fp32 ? P->lvd32 : P->lvd64;
+    d.mg_fp32 = fp32 ? 1 : 0;
+    d.nu_pre = o.nu_pre;
+    d.nu_post = o.nu_post;
+    d.vcycles = o.vcycles;
+    d.omega = o.omega > 0 ? o.omega : (P->dim == 2 ? 0.8 : 6.0 / 7.0);
+    G->max_nlev = std::max(G->max_nlev, P->nlev);
+    G->max_cl = std::max(G->max_cl, d.coarse_lev);
+    G->any_small = G->any_small || d.coarse_lev == 0;
+    for (int l = 0; l < P->nlev; ++l) {
+      G->maxN[l] = std::max(G->maxN[l], lv[l].N);
+      G->maxn[l] = std::max(G->maxn[l], (long)lv[l].n);
+    }
+    d.coarse_p2 = is_p2(P) ? 1 : 0;
+    G->p2 = G->p2 || is_p2(P);
+    G->gen = G->gen || !is_p2(P);
+    G->coarse_lds = std::max(G->coarse_lds, coarse_lds_bytes(lv, P->nlev, d.coarse_lev, fp32 ? 4 : 8, is_p2(P)));
+  }
+  if (G->dim == 2) {
+    G->outsel = 1;
+  } else {
+    G->sel_pre = o.nu_pre & 1;
+    G->outsel = G->sel_pre ^ (o.nu_post & 1);
+  }
+  return IPMPDE_OK;
+}
+
+static int group_sync(Group* G, hipStream_t s) {
+  HIP_TRY(hipMemcpyAsync(G->D, G->H, sizeof(Inst) * G->count, hipMemcpyHostToDevice, s));
+  return IPMPDE_OK;
+}
+
+static dim3 gz(const Group* G, long nthreads, int y = 1) { return dim3(nblk(std::max(nthreads, 1L)), y, G->count); }
+
+static int read_ctrl(Group* G, hipStream_t s) {
+  HIP_TRY(hipMemcpy2DAsync(G->ctrl_h, sizeof(KrylovCtrl), G->ctrl_d, sizeof(KrylovCtrl), offsetof(KrylovCtrl, hcol),
+                           G->count, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return IPMPDE_OK;
+}
+
+static int read_stat(Group* G, hipStream_t s) {
+  HIP_TRY(hipMemcpyAsync(G->stat_h, G->stat_d, 16 * sizeof(double) * G->count, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return IPMPDE_OK;
+}
 
 // ---------------------------------------------------------------------------
 // options
@@ -279,7 +420,7 @@ extern "C" int ipmpde_default_options(ipmpde_options* o) {
   return IPMPDE_OK;
 }
 
-static int check_options(const ipmpde_problem* P, const ipmpde_options& o) {
+static int check_options(const ipmpde_options& o) {
   if (!(o.sigma > 0 && o.sigma < 1)) return fail(IPMPDE_EINVAL, "sigma must lie in (0,1)");
   if (!(o.alpha0 > 0 && o.alpha0 < 1)) return fail(IPMPDE_EINVAL, "alpha0 must lie in (0,1)");
   if (!(o.eps_p > 0 && o.eps_d > 0 && o.eps_c > 0)) return fail(IPMPDE_EINVAL, "tolerances must be positive");
@@ -300,74 +441,63 @@ static int check_options(const ipmpde_problem* P, const ipmpde_options& o) {
   if (!(o.omega >= 0 && o.omega < 1.5)) return fail(IPMPDE_EINVAL, "omega out of range");
   if (o.mg_precision != IPMPDE_FP32 && o.mg_precision != IPMPDE_FP64) return fail(IPMPDE_EINVAL, "bad mg_precision");
   if (o.chunk < 2 || o.chunk > 64 || (o.chunk & 1)) return fail(IPMPDE_EINVAL, "chunk must be even in [2,64]");
-  (void)P;
   return IPMPDE_OK;
 }
 
 static int resolve_opts(const ipmpde_options* in, ipmpde_options* out) {
   if (in) *out = *in;
   else ipmpde_default_options(out);
-  return IPMPDE_OK;
+  return check_options(*out);
 }
 
 // ---------------------------------------------------------------------------
-// multigrid launch sequence
+// multigrid launch sequence (all instances of the group)
 
 template <typename T>
-static void launch_coarse(ipmpde_problem* P, int transpose, int guard, hipStream_t s) {
-  const Inst& I = P->I;
-  const bool p2 = P->dim == 2 && P->pde == IPMPDE_POISSON;
-  const size_t lds = coarse_lds_bytes(I.lv, I.nlev, I.coarse_lev, sizeof(T), p2);
-  if (p2) hipLaunchKernelGGL(k_mg_coarse_p2<T>, dim3(1), dim3(kCoarseBS), lds, s, I, guard);
-  else hipLaunchKernelGGL(k_mg_coarse<T>, dim3(1), dim3(kCoarseBS), lds, s, I, transpose, guard);
+static void launch_coarse(Group* G, int transpose, int guard, hipStream_t s) {
+  // each instance takes the kernel it would take alone (the other one
+  // returns at once for it), so batched and solo solves round alike
+  if (G->p2) hipLaunchKernelGGL(k_mg_coarse_p2<T>, dim3(1, 1, G->count), dim3(kCoarseBS), G->coarse_lds, s, G->D, guard);
+  if (G->gen)
+    hipLaunchKernelGGL(k_mg_coarse<T>, dim3(1, 1, G->count), dim3(kCoarseBS), G->coarse_lds, s, G->D, transpose, guard);
+}
+
+// 3D (generic) V-cycle: per level nu_pre sweeps, residual + restriction,
+// coarse kernel, prolongation + nu_post sweeps.  Level-0 output: G->outsel.
+template <typename T>
+static void mg_vcycle_generic(Group* G, int transpose, int guard, hipStream_t s) {
+  const int nu_pre = G->H[0].nu_pre, nu_post = G->H[0].nu_post;
+  for (int l = 0; l < G->max_cl; ++l) {
+    int a = 0, c = 1;
+    for (int sw = 0; sw < nu_pre; ++sw) {
+      hipLaunchKernelGGL(k_mg_jacobi<T>, gz(G, G->maxn[l]), dim3(kBS), 0, s, G->D, l, a, c, sw == 0 ? 1 : 0, transpose, guard);
+      std::swap(a, c);
+    }
+    hipLaunchKernelGGL(k_mg_restrict<T>, gz(G, G->maxn[l + 1]), dim3(kBS), 0, s, G->D, l, a, transpose, guard);
+  }
+  launch_coarse<T>(G, transpose, guard, s);
+  for (int l = G->max_cl - 1; l >= 0; --l) {
+    int a = G->sel_pre, c = 1 - a;
+    hipLaunchKernelGGL(k_mg_prolong<T>, gz(G, G->maxn[l]), dim3(kBS), 0, s, G->D, l, a, G->outsel, guard);
+    for (int sw = 0; sw < nu_post; ++sw) {
+      hipLaunchKernelGGL(k_mg_jacobi<T>, gz(G, G->maxn[l]), dim3(kBS), 0, s, G->D, l, a, c, 0, transpose, guard);
+      std::swap(a, c);
+    }
+  }
 }
 
 template <typename T>
-static void mg_vcycle_generic(ipmpde_problem* P, int transpose, int guard, hipStream_t s, T** out) {
-  const Inst& I = P->I;
-  const int cl = I.coarse_lev;
-  T* cur[kMaxLev];
-  for (int l = 0; l < cl; ++l) {
-    const Level& L = I.lv[l];
-    T* a = (T*)L.x;
-    T* c = (T*)L.x2;
-    for (int sw = 0; sw < I.nu_pre; ++sw) {
-      hipLaunchKernelGGL(k_mg_jacobi<T>, dim3(nblk(L.n)), dim3(kBS), 0, s, I, l, a, c, sw == 0 ? 1 : 0, transpose, guard);
-      std::swap(a, c);
-    }
-    cur[l] = a;
-    hipLaunchKernelGGL(k_mg_restrict<T>, dim3(nblk(I.lv[l + 1].n)), dim3(kBS), 0, s, I, l, a, transpose, guard);
-  }
-  launch_coarse<T>(P, transpose, guard, s);
-  cur[cl] = (T*)I.lv[cl].x;
-  for (int l = cl - 1; l >= 0; --l) {
-    const Level& L = I.lv[l];
-    T* a = cur[l];
-    T* c = (a == (T*)L.x) ? (T*)L.x2 : (T*)L.x;
-    hipLaunchKernelGGL(k_mg_prolong<T>, dim3(nblk(L.n)), dim3(kBS), 0, s, I, l, a, cur[l + 1], guard);
-    for (int sw = 0; sw < I.nu_post; ++sw) {
-      hipLaunchKernelGGL(k_mg_jacobi<T>, dim3(nblk(L.n)), dim3(kBS), 0, s, I, l, a, c, 0, transpose, guard);
-      std::swap(a, c);
-    }
-    cur[l] = a;
-  }
-  *out = cur[0];
-}
-
-template <typename T>
-static void launch_down2d(int nu, dim3 g, size_t lds, hipStream_t s, const Inst& I, int l, const T* bsrc,
-                          const double* ty, T* xout, int tr, int guard) {
+static void launch_down2d(int nu, dim3 g, size_t lds, hipStream_t s, const Inst* D, int l, int scaled, int tr, int guard) {
   switch (nu) {
-#define D_(NU) case NU: hipLaunchKernelGGL((k_mg_down2d<T, NU>), g, dim3(kBS), lds, s, I, l, bsrc, ty, xout, tr, guard); break;
+#define D_(NU) case NU: hipLaunchKernelGGL((k_mg_down2d<T, NU>), g, dim3(kBS), lds, s, D, l, scaled, tr, guard); break;
     D_(1) D_(2) D_(3) D_(4) D_(5) D_(6)
 #undef D_
   }
 }
 template <typename T>
-static void launch_up2d(int nu, dim3 g, size_t lds, hipStream_t s, const Inst& I, int l, const T* xpre, const T* xc,
-                        T* xout, int tr, int guard) {
+static void launch_up2d(int nu, dim3 g, size_t lds, hipStream_t s, const Inst* D, int l, int tr, int guard) {
   switch (nu) {
-#define U_(NU) case NU: hipLaunchKernelGGL((k_mg_up2d<T, NU>), g, dim3(kBS), lds, s, I, l, xpre, xc, xout, tr, guard); break;
+#define U_(NU) case NU: hipLaunchKernelGGL((k_mg_up2d<T, NU>), g, dim3(kBS), lds, s, D, l, tr, guard); break;
     U_(1) U_(2) U_(3) U_(4) U_(5) U_(6)
 #undef U_
   }
@@ -375,283 +505,313 @@ static void launch_up2d(int nu, dim3 g, size_t lds, hipStream_t s, const Inst& I
 
 // 2D V-cycle with the fused level kernels: per level one descent launch
 // (smoothing + residual + restriction) and one ascent launch (prolongation +
-// smoothing).  scaled_src != nullptr: the level-0 right-hand side is
-// (1 + Theta_y) scaled_src.  Output: level 0's x2.
+// smoothing).  scaled: the level-0 right-hand side is (1 + Theta_y) times the
+// previous V-cycle's output.  Output: level 0's x2 (x for instances whose
+// whole hierarchy fits the coarse kernel).
 template <typename T>
-static void mg_vcycle_2d(ipmpde_problem* P, int transpose, int guard, const T* scaled_src, hipStream_t s, T** out) {
-  const Inst& I = P->I;
-  const int cl = I.coarse_lev;
-  const size_t ldd = 4 * (size_t)down_width(I.nu_pre) * down_width(I.nu_pre) * sizeof(T);
-  const size_t ldu = 4 * (size_t)up_width(I.nu_post) * up_width(I.nu_post) * sizeof(T);
-  for (int l = 0; l < cl; ++l) {
-    const Level& L = I.lv[l];
-    const int nt = div_up(I.lv[l + 1].N, kTC);
-    const T* bsrc = (l == 0 && scaled_src) ? scaled_src : (const T*)L.b;
-    const double* ty = (l == 0 && scaled_src) ? I.ty : nullptr;
-    launch_down2d<T>(I.nu_pre, dim3(nt, nt), ldd, s, I, l, bsrc, ty, (T*)L.x, transpose, guard);
+static void mg_vcycle_2d(Group* G, int transpose, int guard, int scaled, hipStream_t s) {
+  const int nu_pre = G->H[0].nu_pre, nu_post = G->H[0].nu_post;
+  const size_t ldd = 4 * (size_t)down_width(nu_pre) * down_width(nu_pre) * sizeof(T);
+  const size_t ldu = 4 * (size_t)up_width(nu_post) * up_width(nu_post) * sizeof(T);
+  for (int l = 0; l < G->max_cl; ++l) {
+    const int nt = div_up(G->maxN[l + 1], kTC);
+    launch_down2d<T>(nu_pre, dim3(nt, nt, G->count), ldd, s, G->D, l, (l == 0) ? scaled : 0, transpose, guard);
   }
-  launch_coarse<T>(P, transpose, guard, s);
-  for (int l = cl - 1; l >= 0; --l) {
-    const Level& L = I.lv[l];
-    const int nt = div_up(L.N, kTF);
-    const T* xc = (l + 1 == cl) ? (const T*)I.lv[cl].x : (const T*)I.lv[l + 1].x2;
-    launch_up2d<T>(I.nu_post, dim3(nt, nt), ldu, s, I, l, (const T*)L.x, xc, (T*)L.x2, transpose, guard);
+  launch_coarse<T>(G, transpose, guard, s);
+  for (int l = G->max_cl - 1; l >= 0; --l) {
+    const int nt = div_up(G->maxN[l], kTF);
+    launch_up2d<T>(nu_post, dim3(nt, nt, G->count), ldu, s, G->D, l, transpose, guard);
   }
-  *out = cl == 0 ? (T*)I.lv[0].x : (T*)I.lv[0].x2;
 }
 
+// S_hat^-1 applied to every instance's lv[0].b (Sec. 4.2): V-cycle on
+// A + M_hat, scale by 1 + Theta_y, V-cycle on (A + M_hat)^T.  The result is
+// the level-0 output array (selected in the kernels with G->outsel).
 template <typename T>
-static void mg_vcycle(ipmpde_problem* P, int transpose, int guard, hipStream_t s, T** out) {
-  if (P->dim == 2) mg_vcycle_2d<T>(P, transpose, guard, nullptr, s, out);
-  else mg_vcycle_generic<T>(P, transpose, guard, s, out);
-}
-
-// S_hat^-1 applied to lv[0].b (Sec. 4.2): V-cycle on A + M_hat, scale by
-// 1 + Theta_y, V-cycle on (A + M_hat)^T.  Returns the level-0 output array.
-template <typename T>
-static T* schur_inv(ipmpde_problem* P, int guard, hipStream_t s) {
-  T* x1;
-  T* x2;
-  if (P->dim == 2 && P->I.coarse_lev > 0) {
-    mg_vcycle_2d<T>(P, 0, guard, nullptr, s, &x1);
-    mg_vcycle_2d<T>(P, 1, guard, x1, s, &x2);
-    return x2;
+static void schur_inv(Group* G, int guard, hipStream_t s) {
+  if (G->dim == 2) {
+    mg_vcycle_2d<T>(G, 0, guard, 0, s);
+    // instances whose whole hierarchy is in the coarse kernel never run a
+    // descent kernel, so their scaled right-hand side is formed here; the
+    // others form it inside their first descent kernel
+    if (G->any_small) hipLaunchKernelGGL(k_mg_scale_ty_small<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, guard);
+    mg_vcycle_2d<T>(G, 1, guard, 1, s);
+    return;
   }
-  mg_vcycle<T>(P, 0, guard, s, &x1);
-  hipLaunchKernelGGL(k_mg_scale_ty<T>, dim3(nblk(P->n)), dim3(kBS), 0, s, P->I, (const T*)x1, guard);
-  mg_vcycle<T>(P, 1, guard, s, &x2);
-  return x2;
+  mg_vcycle_generic<T>(G, 0, guard, s);
+  hipLaunchKernelGGL(k_mg_scale_ty<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, G->outsel, guard);
+  mg_vcycle_generic<T>(G, 1, guard, s);
 }
 
 // ---------------------------------------------------------------------------
-// MINRES
-
-template <typename T>
-static void minres_iteration(ipmpde_problem* P, int par, int maxit, hipStream_t s) {
-  const Inst& I = P->I;
-  const int nb = nblk(P->n);
-  double* Zc = P->Z[par];
-  double* Zo = P->Z[1 - par];
-  double* Vc = P->V[par];
-  double* Vo = P->V[1 - par];
-  hipLaunchKernelGGL(k_minres_k1, dim3(nb), dim3(kBS), 0, s, I, Zc, Zo, P->W[1 - par], P->W[par], P->X, P->Q,
-                     P->KW[1 - par], P->KW[par], P->Rt, 0);
-  hipLaunchKernelGGL(k_minres_k2<T>, dim3(nb), dim3(kBS), 0, s, I, P->Q, Vc, Vo, Zo);
-  T* xs = schur_inv<T>(P, 1, s);
-  hipLaunchKernelGGL(k_minres_k4<T>, dim3(nb), dim3(kBS), 0, s, I, (const T*)xs, Vo, Zo, 1, 0.0, maxit);
-}
-
-template <typename T>
-static void minres_start(ipmpde_problem* P, const double* src, double rtarget, int maxit, hipStream_t s) {
-  const Inst& I = P->I;
-  const int nb = nblk(P->n);
-  hipLaunchKernelGGL(k_minres_init<T>, dim3(nb), dim3(kBS), 0, s, I, src, P->V[1], P->V[0], P->Z[1], P->W[0], P->W[1],
-                     P->KW[0], P->KW[1], P->Rt);
-  T* xs = schur_inv<T>(P, 0, s);
-  hipLaunchKernelGGL(k_minres_k4<T>, dim3(nb), dim3(kBS), 0, s, I, (const T*)xs, P->V[1], P->Z[1], 0, rtarget, maxit);
-}
-
-// Clear the stop flag (used before timing the iteration kernels in isolation).
-__global__ void k_ctrl_continue(KrylovCtrl* C, double unused) {
-  (void)unused;
-  C->stop = 0;
-  C->pending = 0;
-}
-
-static int read_ctrl(ipmpde_problem* P, hipStream_t s) {
-  HIP_TRY(hipMemcpyAsync(P->ctrl_h, P->I.ctrl, offsetof(KrylovCtrl, hcol), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  return IPMPDE_OK;
-}
-
-template <typename T>
-static int run_minres_chunk(ipmpde_problem* P, const ipmpde_options& o, int par, int maxit, hipStream_t s) {
-  if (!o.use_graphs) {
-    for (int t = 0; t < o.chunk; ++t) minres_iteration<T>(P, (par + t) & 1, maxit, s);
-    return IPMPDE_OK;
-  }
-  GraphKey key{P->I.mg_fp32, o.nu_pre, o.nu_post, o.chunk, maxit, par, IPMPDE_MINRES, IPMPDE_PD, 0, P->I.omega};
-  auto it = P->graphs.find(key);
-  if (it == P->graphs.end()) {
-    hipGraph_t g;
-    HIP_TRY(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
-    for (int t = 0; t < o.chunk; ++t) minres_iteration<T>(P, (par + t) & 1, maxit, P->cap_stream);
-    HIP_TRY(hipStreamEndCapture(P->cap_stream, &g));
-    hipGraphExec_t ge;
-    hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
-    if (e != hipSuccess) return fail(IPMPDE_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-    it = P->graphs.emplace(key, ge).first;
-  }
-  HIP_TRY(hipGraphLaunch(it->second, s));
-  return IPMPDE_OK;
-}
+// Krylov solves (all instances; each stops on its own)
 
 // Attainable accuracy: a relative residual below c eps |(|K||x| + |b|)| / |b|
 // cannot be resolved by evaluating b - K x in FP64; the Krylov solves accept
 // it as converged when the requested tolerance lies below that floor.
 static double floor_factor() { return 16.0 * 2.220446049250313e-16; }
 
-// Solve K X = rhs to |rhs - K X| <= tol |rhs|.  MINRES stops on its tracked
-// residual; the true residual is then checked, and a drift of the recurrence
-// (rare) restarts MINRES from the true residual.  Returns IPMPDE_OK or
-// IPMPDE_EKRYLOV; *its receives the iterations, *relres the true relative residual.
 template <typename T>
-static int minres_solve(ipmpde_problem* P, const ipmpde_options& o, hipStream_t s, int* its, double* relres) {
-  const int n4 = 4 * P->n;
-  HIP_TRY(hipMemsetAsync(P->X, 0, n4 * sizeof(double), s));
-  TRY(read_ctrl(P, s));
-  const double bnorm = P->ctrl_h->bnorm;
-  *its = 0;
-  *relres = 0.0;
-  if (!(bnorm > 0.0)) {
-    if (bnorm != bnorm) return fail(IPMPDE_EBREAKDOWN, "NaN in the Newton right-hand side");
+static void minres_iteration(Group* G, int par, int maxit, double tol, hipStream_t s) {
+  hipLaunchKernelGGL(k_minres_k1, gz(G, G->max_n), dim3(kBS), 0, s, G->D, par, 0);
+  hipLaunchKernelGGL(k_minres_k2<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, par);
+  schur_inv<T>(G, 1, s);
+  hipLaunchKernelGGL(k_minres_k4<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, 1 - par, 1, tol, maxit, G->outsel);
+}
+
+static bool any_running(const Group* G) {
+  for (int i = 0; i < G->count; ++i)
+    if (G->H[i].active && G->ctrl_h[i].want_restart && !G->ctrl_h[i].stop) return true;
+  return false;
+}
+static bool any_restart(const Group* G) {
+  for (int i = 0; i < G->count; ++i)
+    if (G->H[i].active && G->ctrl_h[i].want_restart) return true;
+  return false;
+}
+
+template <typename T>
+static int run_minres_chunk(Group* G, const ipmpde_options& o, hipStream_t s) {
+  if (!o.use_graphs) {
+    for (int t = 0; t < o.chunk; ++t) minres_iteration<T>(G, (1 + t) & 1, o.krylov_maxit, o.krylov_tol, s);
     return IPMPDE_OK;
   }
-  const double tol = o.krylov_tol;
-  const double* src = P->rhs;
-  int total = 0;
-  for (int cycle = 0; cycle < 16; ++cycle) {
-    const int left = o.krylov_maxit - total;
-    minres_start<T>(P, src, tol * bnorm, left, s);
-    TRY(read_ctrl(P, s));
-    while (!P->ctrl_h->stop && P->ctrl_h->iter < left) {
-      TRY(run_minres_chunk<T>(P, o, 1, left, s));
-      TRY(read_ctrl(P, s));
-    }
-    const int it = P->ctrl_h->iter;
-    // the pending update exists when the stop came from K4 (limit, breakdown)
-    hipLaunchKernelGGL(k_minres_flush, dim3(nblk(P->n)), dim3(kBS), 0, s, P->I, P->Z[it & 1], P->W[it & 1],
-                       P->W[(it + 1) & 1], P->X);
-    hipLaunchKernelGGL(k_true_residual, dim3(nblk(P->n)), dim3(kBS), 0, s, P->I, P->X, P->rhs, P->R);
-    TRY(read_ctrl(P, s));
-    total += it;
-    const double rel = P->ctrl_h->rnorm / bnorm;
-    *its = total;
-    *relres = rel;
-    if (rel <= std::max(tol, floor_factor() * P->ctrl_h->rfloor / bnorm)) return IPMPDE_OK;
-    if (!(rel == rel)) return fail(IPMPDE_EBREAKDOWN, "NaN in the Krylov iterate");
-    if (P->ctrl_h->breakdown) return fail(IPMPDE_EKRYLOV, "MINRES breakdown (preconditioner not positive definite)");
-    if (total >= o.krylov_maxit) return fail(IPMPDE_EKRYLOV, "Krylov iteration limit reached");
-    src = P->R;
+  GraphKey key{G->fp32 ? 1 : 0, o.nu_pre, o.nu_post, o.chunk, o.krylov_maxit, G->count, G->H[0].omega, o.krylov_tol};
+  auto it = G->graphs.find(key);
+  if (it == G->graphs.end()) {
+    hipGraph_t g;
+    HIP_TRY(hipStreamBeginCapture(G->cap_stream, hipStreamCaptureModeThreadLocal));
+    for (int t = 0; t < o.chunk; ++t) minres_iteration<T>(G, (1 + t) & 1, o.krylov_maxit, o.krylov_tol, G->cap_stream);
+    HIP_TRY(hipStreamEndCapture(G->cap_stream, &g));
+    hipGraphExec_t ge;
+    hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(IPMPDE_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    it = G->graphs.emplace(key, ge).first;
   }
-  return fail(IPMPDE_EKRYLOV, "Krylov solve did not converge within 16 restarts");
+  HIP_TRY(hipGraphLaunch(it->second, s));
+  return IPMPDE_OK;
+}
+
+// MINRES on every active instance: a cycle from the right-hand side, then
+// (for instances whose true residual missed the tolerance) cycles from the
+// true residual.  Per-instance results stay in the group's ctrl array.
+template <typename T>
+static int minres_group(Group* G, const ipmpde_options& o, hipStream_t s) {
+  const double tol = o.krylov_tol;
+  hipLaunchKernelGGL(k_krylov_begin, gz(G, 4L * G->max_n), dim3(kBS), 0, s, G->D);
+  for (int cycle = 0; cycle < 16; ++cycle) {
+    hipLaunchKernelGGL(k_minres_init<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, cycle == 0 ? 0 : 1);
+    schur_inv<T>(G, 2, s);
+    hipLaunchKernelGGL(k_minres_k4<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, 1, 0, tol, o.krylov_maxit, G->outsel);
+    HIP_TRY(hipGetLastError());
+    TRY(read_ctrl(G, s));
+    int chunks = 0;
+    while (any_running(G) && chunks++ < o.krylov_maxit / o.chunk + 2) {
+      TRY(run_minres_chunk<T>(G, o, s));
+      TRY(read_ctrl(G, s));
+    }
+    hipLaunchKernelGGL(k_minres_flush, gz(G, G->max_n), dim3(kBS), 0, s, G->D);
+    hipLaunchKernelGGL(k_true_residual, gz(G, G->max_n), dim3(kBS), 0, s, G->D);
+    hipLaunchKernelGGL(k_krylov_mark, dim3(1, 1, G->count), dim3(64), 0, s, G->D, tol, floor_factor(), o.krylov_maxit, 0);
+    HIP_TRY(hipGetLastError());
+    TRY(read_ctrl(G, s));
+    if (!any_restart(G)) return IPMPDE_OK;
+  }
+  return IPMPDE_OK;
+}
+
+template <typename T>
+static void precond_apply(Group* G, int pt, const double* x, double* y, int j, int guard, hipStream_t s) {
+  hipLaunchKernelGGL(k_precond_diag<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, x, y, j, pt, guard);
+  if (pt) hipLaunchKernelGGL(k_pt_rhs<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, x, (const double*)y, j, guard);
+  schur_inv<T>(G, guard, s);
+  hipLaunchKernelGGL(k_store_p<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, y, j, G->outsel, guard);
+}
+
+static int fg_multidot_blocks(long n4) { return std::min(nblk(n4), 256); }
+
+template <typename T>
+static void fgmres_step(Group* G, int pt, int j, double tol, int maxit, hipStream_t s) {
+  const long n4 = 4L * G->max_n;
+  precond_apply<T>(G, pt, nullptr, nullptr, j, 1, s);
+  hipLaunchKernelGGL(k_fg_matvec, gz(G, G->max_n), dim3(kBS), 0, s, G->D, j);
+  const int nbm = fg_multidot_blocks(n4);
+  for (int pass = 0; pass < 2; ++pass) {
+    hipLaunchKernelGGL(k_fg_multidot, dim3(nbm, j + 1, G->count), dim3(kBS), 0, s, G->D, j);
+    hipLaunchKernelGGL(k_fg_multidot_final, dim3(1, 1, G->count), dim3(kBS), 0, s, G->D, j + 1, nbm, pass == 0 ? 1 : 0);
+    hipLaunchKernelGGL(k_fg_orth, gz(G, n4), dim3(kBS), 0, s, G->D, j);
+  }
+  hipLaunchKernelGGL(k_fg_norm_givens, dim3(nbm, 1, G->count), dim3(kBS), 0, s, G->D, j, tol, maxit);
+  hipLaunchKernelGGL(k_fg_normalize, gz(G, n4), dim3(kBS), 0, s, G->D, j);
+}
+
+template <typename T>
+static int fgmres_group(Group* G, const ipmpde_options& o, hipStream_t s) {
+  const long n4 = 4L * G->max_n;
+  const int pt = o.precond == IPMPDE_PT;
+  const int nbm = fg_multidot_blocks(n4);
+  const int step = 4;
+  hipLaunchKernelGGL(k_krylov_begin, gz(G, n4), dim3(kBS), 0, s, G->D);
+  for (int cycle = 0; cycle < 1000; ++cycle) {
+    const int src = cycle == 0 ? 0 : 1;
+    hipLaunchKernelGGL(k_fg_start_norm, dim3(nbm, 1, G->count), dim3(kBS), 0, s, G->D, src);
+    hipLaunchKernelGGL(k_fg_start_scale, gz(G, n4), dim3(kBS), 0, s, G->D, src);
+    TRY(read_ctrl(G, s));
+    for (int j0 = 0; j0 < o.restart && any_running(G); j0 += step) {
+      for (int j = j0; j < std::min(j0 + step, o.restart); ++j) fgmres_step<T>(G, pt, j, o.krylov_tol, o.krylov_maxit, s);
+      HIP_TRY(hipGetLastError());
+      TRY(read_ctrl(G, s));
+    }
+    hipLaunchKernelGGL(k_fg_solve_small, dim3(1, 1, G->count), dim3(64), 0, s, G->D);
+    hipLaunchKernelGGL(k_fg_update_x, gz(G, n4), dim3(kBS), 0, s, G->D);
+    hipLaunchKernelGGL(k_true_residual, gz(G, G->max_n), dim3(kBS), 0, s, G->D);
+    hipLaunchKernelGGL(k_krylov_mark, dim3(1, 1, G->count), dim3(64), 0, s, G->D, o.krylov_tol, floor_factor(),
+                       o.krylov_maxit, 1);
+    HIP_TRY(hipGetLastError());
+    TRY(read_ctrl(G, s));
+    if (!any_restart(G)) return IPMPDE_OK;
+  }
+  return IPMPDE_OK;
+}
+
+static int krylov_group(Group* G, const ipmpde_options& o, hipStream_t s) {
+  if (o.krylov == IPMPDE_MINRES) return G->fp32 ? minres_group<float>(G, o, s) : minres_group<double>(G, o, s);
+  return G->fp32 ? fgmres_group<float>(G, o, s) : fgmres_group<double>(G, o, s);
+}
+
+// per-instance Krylov outcome after krylov_group
+static int krylov_status(const Group* G, int i) {
+  const KrylovCtrl& C = G->ctrl_h[i];
+  if (!(C.relres == C.relres)) return IPMPDE_EBREAKDOWN;
+  return C.failed ? IPMPDE_EKRYLOV : IPMPDE_OK;
 }
 
 // ---------------------------------------------------------------------------
-// Newton setup and IPM step
+// Newton setup and IPM steps (all instances)
 
-template <typename T>
-static int newton_setup_t(ipmpde_problem* P, double mu, hipStream_t s) {
-  const Inst& I = P->I;
-  hipLaunchKernelGGL(k_newton_setup<T>, dim3(nblk(P->n)), dim3(kBS), 0, s, I, mu, P->rhs, (T*)I.lv[0].mh);
-  for (int l = 0; l + 1 < I.nlev; ++l)
-    hipLaunchKernelGGL(k_restrict_diag<T>, dim3(nblk(I.lv[l + 1].n)), dim3(kBS), 0, s, (const T*)I.lv[l].mh,
-                       (T*)I.lv[l + 1].mh, I.lv[l].N, I.lv[l + 1].N, P->dim);
-  return IPMPDE_OK;
-}
-
-static int newton_setup(ipmpde_problem* P, const ipmpde_options& o, double mu, hipStream_t s) {
-  TRY(ensure_mg(P, o.mg_precision == IPMPDE_FP32));
-  select_mg(P, o);
-  if (o.mg_precision == IPMPDE_FP32) TRY(newton_setup_t<float>(P, mu, s));
-  else TRY(newton_setup_t<double>(P, mu, s));
-  HIP_TRY(hipGetLastError());
-  P->setup_done = true;
-  P->setup_fp32 = o.mg_precision == IPMPDE_FP32;
-  P->setup_mu = mu;
-  return IPMPDE_OK;
-}
-
-static int ensure_fgmres(ipmpde_problem* P, int restart);
-template <typename T>
-static int fgmres_solve(ipmpde_problem* P, const ipmpde_options& o, hipStream_t s, int* its, double* relres);
-
-static int krylov_solve(ipmpde_problem* P, const ipmpde_options& o, hipStream_t s, int* its, double* relres) {
-  const bool f32 = o.mg_precision == IPMPDE_FP32;
-  if (o.krylov == IPMPDE_MINRES) return f32 ? minres_solve<float>(P, o, s, its, relres) : minres_solve<double>(P, o, s, its, relres);
-  TRY(ensure_fgmres(P, o.restart));
-  return f32 ? fgmres_solve<float>(P, o, s, its, relres) : fgmres_solve<double>(P, o, s, its, relres);
-}
-
-static int read_stat(ipmpde_problem* P, hipStream_t s) {
-  HIP_TRY(hipMemcpyAsync(P->stat_h, P->I.stat, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  return IPMPDE_OK;
-}
-
-static int measures(ipmpde_problem* P, hipStream_t s, double* xp, double* xd, double* xc) {
-  hipLaunchKernelGGL(k_measures, dim3(nblk(P->n)), dim3(kBS), 0, s, P->I);
-  HIP_TRY(hipGetLastError());
-  TRY(read_stat(P, s));
-  *xp = P->stat_h[0];
-  *xd = P->stat_h[1];
-  *xc = P->stat_h[2];
-  return IPMPDE_OK;
-}
-
-// One pass of the loop body of Algorithm A.1 at barrier mu_new.
-static int ipm_step_impl(ipmpde_problem* P, const ipmpde_options& o, double mu_new, hipStream_t s, double* aP,
-                         double* aD, int* its, double* relres) {
-  TRY(newton_setup(P, o, mu_new, s));
-  int krc = krylov_solve(P, o, s, its, relres);
-  if (krc != IPMPDE_OK && krc != IPMPDE_EKRYLOV) return krc;
-  hipLaunchKernelGGL(k_step_lengths, dim3(nblk(P->n)), dim3(kBS), 0, s, P->I, P->X, mu_new, o.alpha0);
-  hipLaunchKernelGGL(k_update, dim3(nblk(P->n)), dim3(kBS), 0, s, P->I, P->X, mu_new);
-  HIP_TRY(hipGetLastError());
-  TRY(read_stat(P, s));
-  *aP = P->stat_h[3];
-  *aD = P->stat_h[4];
-  P->mu = mu_new;
-  return krc;
-}
-
-static void reset_state(ipmpde_problem* P, double mu0, hipStream_t s) {
-  hipLaunchKernelGGL(k_init_state, dim3(nblk(P->n)), dim3(kBS), 0, s, P->I, mu0);
-  P->mu = mu0;
-}
-
-static int solve_impl(ipmpde_problem* P, const ipmpde_options& o, hipStream_t s) {
-  auto t0 = std::chrono::steady_clock::now();
-  ipmpde_stats& st = P->stats;
-  std::memset(&st, 0, sizeof(st));
-  reset_state(P, o.mu0, s);
-  HIP_TRY(hipGetLastError());
-  int status = IPMPDE_ENOTCONVERGED;
-  double aP = 0, aD = 0;
-  for (int k = 0;; ++k) {
-    double xp, xd, xc;
-    TRY(measures(P, s, &xp, &xd, &xc));
-    st.hist_mu[k] = P->mu;
-    st.hist_xi_p[k] = xp;
-    st.hist_xi_d[k] = xd;
-    st.hist_xi_c[k] = xc;
-    st.hist_len = k + 1;
-    st.nli = k;
-    st.xi_p = xp; st.xi_d = xd; st.xi_c = xc; st.mu = P->mu;
-    if (!(xp == xp && xd == xd && xc == xc)) { status = fail(IPMPDE_EBREAKDOWN, "NaN in the IPM iterates"); break; }
-    if (o.fixed_nli > 0) {
-      if (k >= o.fixed_nli) { status = IPMPDE_OK; break; }
-    } else if (xp <= o.eps_p && xd <= o.eps_d && xc <= o.eps_c) {
-      status = IPMPDE_OK;
-      break;
-    }
-    if (k >= o.ipm_maxit) { status = fail(IPMPDE_ENOTCONVERGED, "IPM iteration limit reached"); break; }
-    int its = 0;
-    double rel = 0;
-    int rc = ipm_step_impl(P, o, o.sigma * P->mu, s, &aP, &aD, &its, &rel);
-    st.hist_krylov[k] = its;
-    st.hist_krylov_relres[k] = rel;
-    st.hist_alpha_p[k] = aP;
-    st.hist_alpha_d[k] = aD;
-    st.krylov_its += its;
-    if (rc == IPMPDE_EKRYLOV) st.krylov_fail += 1;
-    else if (rc != IPMPDE_OK) { status = rc; break; }
-    if (!(aP > 1e-10 && aD > 1e-10)) { status = fail(IPMPDE_EBREAKDOWN, "step length collapsed"); break; }
+static int newton_setup_group(Group* G, const ipmpde_options& o, hipStream_t s) {
+  TRY(group_select(G, o));
+  TRY(group_sync(G, s));
+  if (G->fp32) {
+    hipLaunchKernelGGL(k_newton_setup<float>, gz(G, G->max_n), dim3(kBS), 0, s, G->D);
+    for (int l = 0; l + 1 < G->max_nlev; ++l)
+      hipLaunchKernelGGL(k_restrict_diag<float>, gz(G, G->maxn[l + 1]), dim3(kBS), 0, s, G->D, l);
+  } else {
+    hipLaunchKernelGGL(k_newton_setup<double>, gz(G, G->max_n), dim3(kBS), 0, s, G->D);
+    for (int l = 0; l + 1 < G->max_nlev; ++l)
+      hipLaunchKernelGGL(k_restrict_diag<double>, gz(G, G->maxn[l + 1]), dim3(kBS), 0, s, G->D, l);
   }
-  st.status = status;
-  st.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  return status;
+  HIP_TRY(hipGetLastError());
+  for (int i = 0; i < G->count; ++i) {
+    G->probs[i]->setup_done = true;
+    G->probs[i]->setup_fp32 = G->fp32 ? 1 : 0;
+  }
+  return IPMPDE_OK;
+}
+
+static int group_step(Group* G, const ipmpde_options& o, hipStream_t s) {
+  TRY(newton_setup_group(G, o, s));
+  TRY(krylov_group(G, o, s));
+  hipLaunchKernelGGL(k_step_lengths, gz(G, G->max_n), dim3(kBS), 0, s, G->D);
+  hipLaunchKernelGGL(k_update, gz(G, G->max_n), dim3(kBS), 0, s, G->D);
+  HIP_TRY(hipGetLastError());
+  TRY(read_stat(G, s));
+  return IPMPDE_OK;
+}
+
+static int group_measures(Group* G, hipStream_t s) {
+  TRY(group_sync(G, s));
+  hipLaunchKernelGGL(k_measures, gz(G, G->max_n), dim3(kBS), 0, s, G->D);
+  HIP_TRY(hipGetLastError());
+  TRY(read_stat(G, s));
+  return IPMPDE_OK;
+}
+
+// Starting point of every instance with its own mu0.
+static int group_reset(Group* G, const std::vector<ipmpde_options>& po, hipStream_t s) {
+  for (int i = 0; i < G->count; ++i) {
+    G->H[i].active = 1;
+    G->H[i].mu = po[i].mu0;
+    G->H[i].alpha0 = po[i].alpha0;
+    G->probs[i]->mu = po[i].mu0;
+  }
+  TRY(group_sync(G, s));
+  hipLaunchKernelGGL(k_init_state, gz(G, G->max_n), dim3(kBS), 0, s, G->D);
+  HIP_TRY(hipGetLastError());
+  return IPMPDE_OK;
+}
+
+// Algorithm A.1 on every instance of the group, in lockstep; each instance
+// leaves the loop (and every later launch) when its own test is met.  po:
+// per-instance options (IPM fields may differ; Krylov/multigrid fields must
+// match).  Per-instance status goes to the problems' stats.
+static int solve_group(Group* G, const std::vector<ipmpde_options>& po, hipStream_t s) {
+  auto t0 = std::chrono::steady_clock::now();
+  const ipmpde_options& o = po[0];
+  for (int i = 0; i < G->count; ++i) {
+    ipmpde_stats& st = G->probs[i]->stats;
+    std::memset(&st, 0, sizeof(st));
+    st.status = IPMPDE_ENOTCONVERGED;
+  }
+  TRY(group_select(G, o));
+  TRY(group_reset(G, po, s));
+  std::vector<int> done(G->count, 0);
+  for (int k = 0;; ++k) {
+    TRY(group_measures(G, s));
+    int alive = 0;
+    for (int i = 0; i < G->count; ++i) {
+      if (done[i]) continue;
+      ipmpde_problem* P = G->probs[i];
+      ipmpde_stats& st = P->stats;
+      const double xp = G->stat_h[16 * i], xd = G->stat_h[16 * i + 1], xc = G->stat_h[16 * i + 2];
+      st.hist_mu[k] = P->mu;
+      st.hist_xi_p[k] = xp;
+      st.hist_xi_d[k] = xd;
+      st.hist_xi_c[k] = xc;
+      st.hist_len = k + 1;
+      st.nli = k;
+      st.xi_p = xp; st.xi_d = xd; st.xi_c = xc; st.mu = P->mu;
+      const ipmpde_options& oi = po[i];
+      int finish = -1;
+      if (!(xp == xp && xd == xd && xc == xc)) finish = IPMPDE_EBREAKDOWN;
+      else if (oi.fixed_nli > 0 ? k >= oi.fixed_nli : (xp <= oi.eps_p && xd <= oi.eps_d && xc <= oi.eps_c))
+        finish = IPMPDE_OK;
+      else if (k >= oi.ipm_maxit) finish = IPMPDE_ENOTCONVERGED;
+      if (finish >= 0) {
+        st.status = finish;
+        done[i] = 1;
+        G->H[i].active = 0;
+      } else {
+        ++alive;
+        P->mu *= oi.sigma;
+        G->H[i].mu = P->mu;
+      }
+    }
+    if (!alive) break;
+    TRY(group_step(G, o, s));
+    for (int i = 0; i < G->count; ++i) {
+      if (done[i]) continue;
+      ipmpde_stats& st = G->probs[i]->stats;
+      const double aP = G->stat_h[16 * i + 3], aD = G->stat_h[16 * i + 4];
+      const KrylovCtrl& C = G->ctrl_h[i];
+      st.hist_krylov[k] = C.its_total;
+      st.hist_krylov_relres[k] = C.relres;
+      st.hist_alpha_p[k] = aP;
+      st.hist_alpha_d[k] = aD;
+      st.krylov_its += C.its_total;
+      const int kst = krylov_status(G, i);
+      if (kst == IPMPDE_EKRYLOV) st.krylov_fail += 1;
+      if (kst == IPMPDE_EBREAKDOWN || !(aP > 1e-10 && aD > 1e-10)) {
+        st.status = IPMPDE_EBREAKDOWN;
+        done[i] = 1;
+        G->H[i].active = 0;
+      }
+    }
+  }
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  for (int i = 0; i < G->count; ++i) G->probs[i]->stats.solve_ms = ms;
+  return IPMPDE_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -671,7 +831,6 @@ static void fold_boundary(int dim, int N, int pde, double eps, const double* g, 
   const size_t n = pow_dim(N, dim);
   for (size_t idx = 0; idx < n; ++idx) {
     int i1 = idx % N, i2 = (idx / N) % N, i3 = dim == 3 ? (int)(idx / ((size_t)N * N)) : 0;
-    // 1-based full-grid coordinates
     int c[3] = {i1 + 1, i2 + 1, dim == 3 ? i3 + 1 : 0};
     double acc = 0.0;
     for (int ax = 0; ax < dim; ++ax) {
@@ -696,7 +855,7 @@ static void fold_boundary(int dim, int N, int pde, double eps, const double* g, 
   }
 }
 
-extern "C" const char* ipmpde_version(void) { return "libipmpde 0.1 (gfx950)"; }
+extern "C" const char* ipmpde_version(void) { return "libipmpde 0.2 (gfx950)"; }
 extern "C" const char* ipmpde_last_error(void) { return g_err.c_str(); }
 
 extern "C" int ipmpde_set_allocator(ipmpde_alloc_fn a, ipmpde_free_fn f, void* ctx) {
@@ -711,14 +870,21 @@ extern "C" size_t ipmpde_footprint_bytes(const ipmpde_grid* grid, const ipmpde_p
                                          const ipmpde_options* opts) {
   if (!grid || !pde) return 0;
   ipmpde_options o;
-  resolve_opts(opts, &o);
+  if (opts) o = *opts;
+  else ipmpde_default_options(&o);
   const size_t n = pow_dim(grid->n, grid->dim);
   size_t fields = 6 + 8 + 4 + (has_y ? 4 : 0);  // data, iterates, diagonals
-  size_t words = fields * n + 4 * n * 11;        // Newton rhs, X, V, Z, W, Q, R
+  size_t words = fields * n + 4 * n * 14;        // Newton rhs and the Krylov vectors
   if (o.krylov == IPMPDE_FGMRES) words += 4 * n * (2 * (size_t)o.restart + 1);
   const size_t el = o.mg_precision == IPMPDE_FP32 ? 4 : 8;
   const double lvl = grid->dim == 2 ? 4.0 / 3.0 : 8.0 / 7.0;
   return words * 8 + (size_t)(4 * el * n * lvl) + (1 << 20);
+}
+
+static void problem_free(ipmpde_problem* P) {
+  if (P->self) group_release(P->self);
+  P->self = nullptr;
+  P->mem.release();
 }
 
 extern "C" int ipmpde_problem_create(const ipmpde_grid* grid, const ipmpde_pde* pde, double alpha, double beta,
@@ -768,11 +934,15 @@ extern "C" int ipmpde_problem_create(const ipmpde_grid* grid, const ipmpde_pde* 
   std::memset(&I, 0, sizeof(I));
   I.dim = dim; I.N = N; I.n = (int)n; I.pde = P->pde; I.has_y = P->has_y ? 1 : 0;
   I.h = 1.0 / (N + 1); I.eps = P->eps; I.alpha = alpha; I.beta = beta;
-  auto cleanup = [&](int rc) { free_all(P); delete P; return rc; };
+  I.active = 1;
+  I.mu = 1.0;
+  I.alpha0 = 0.995;
+  auto cleanup = [&](int rc) { problem_free(P); delete P; return rc; };
   int rc = IPMPDE_OK;
   double* dev[32];
   int nd = 0;
-  auto A = [&](double** p) -> int { int r = dalloc_t(P, p, n); if (r == IPMPDE_OK) dev[nd++] = *p; return r; };
+  AllocList& M = P->mem;
+  auto A = [&](double** p) -> int { int r = M.alloc_t(p, n); if (r == IPMPDE_OK) dev[nd++] = *p; return r; };
   double *ua, *ub, *ya = nullptr, *yb = nullptr, *yd, *fh;
   if ((rc = A(&ua)) || (rc = A(&ub)) || (rc = A(&yd)) || (rc = A(&fh))) return cleanup(rc);
   if (P->has_y && ((rc = A(&ya)) || (rc = A(&yb)))) return cleanup(rc);
@@ -783,26 +953,22 @@ extern "C" int ipmpde_problem_create(const ipmpde_grid* grid, const ipmpde_pde* 
   if (P->has_y && ((rc = A(&I.lya)) || (rc = A(&I.lyb)))) return cleanup(rc);
   I.ua = ua; I.ub = ub; I.ya = ya; I.yb = yb; I.yd = yd; I.fhat = fh;
   const size_t n4 = 4 * n;
-  if ((rc = dalloc_t(P, &P->rhs, n4)) || (rc = dalloc_t(P, &P->X, n4)) || (rc = dalloc_t(P, &P->V[0], n4)) ||
-      (rc = dalloc_t(P, &P->V[1], n4)) || (rc = dalloc_t(P, &P->Z[0], n4)) || (rc = dalloc_t(P, &P->Z[1], n4)) ||
-      (rc = dalloc_t(P, &P->W[0], n4)) || (rc = dalloc_t(P, &P->W[1], n4)) || (rc = dalloc_t(P, &P->Q, n4)) ||
-      (rc = dalloc_t(P, &P->R, n4)) || (rc = dalloc_t(P, &P->KW[0], n4)) || (rc = dalloc_t(P, &P->KW[1], n4)) ||
-      (rc = dalloc_t(P, &P->Rt, n4)))
-    return cleanup(rc);
-  const size_t nparts = std::max<size_t>(4 * (size_t)nblk((long)n), 64 * kBS) + 64;
-  if ((rc = dalloc_t(P, &I.partials, nparts)) || (rc = dalloc_t(P, &I.counter, kTicketStride * (kTicketGroups + 1))) ||
-      (rc = dalloc(P, (void**)&I.ctrl, sizeof(KrylovCtrl))) || (rc = dalloc_t(P, &I.stat, 16)))
+  double** vecs[] = {&I.rhs, &I.X, &I.Q, &I.R, &I.Rt, &I.V[0], &I.V[1], &I.Z[0], &I.Z[1], &I.W[0], &I.W[1],
+                     &I.KW[0], &I.KW[1]};
+  for (double** v : vecs)
+    if ((rc = M.alloc_t(v, n4))) return cleanup(rc);
+  if ((rc = ensure_partials(P, nblk((long)n))) || (rc = M.alloc_t(&I.counter, kTicketStride * (kTicketGroups + 1))))
     return cleanup(rc);
   auto hip_fail = [&](hipError_t e, const char* what) {
     return cleanup(fail(IPMPDE_EDEVICE, std::string(what) + ": " + hipGetErrorString(e)));
   };
   hipError_t e;
-  if ((e = hipMemset(I.counter, 0, kTicketStride * (kTicketGroups + 1) * sizeof(unsigned))) != hipSuccess) return hip_fail(e, "hipMemset");
-  if ((e = hipMemset(I.ctrl, 0, sizeof(KrylovCtrl))) != hipSuccess) return hip_fail(e, "hipMemset");
-  if ((e = hipMemset(I.stat, 0, 16 * sizeof(double))) != hipSuccess) return hip_fail(e, "hipMemset");
+  if ((e = hipMemset(I.counter, 0, kTicketStride * (kTicketGroups + 1) * sizeof(unsigned))) != hipSuccess)
+    return hip_fail(e, "hipMemset");
   for (int k = 0; k < nd; ++k)
     if ((e = hipMemset(dev[k], 0, n * sizeof(double))) != hipSuccess) return hip_fail(e, "hipMemset");
-  if ((e = hipMemset(P->X, 0, n4 * sizeof(double))) != hipSuccess) return hip_fail(e, "hipMemset");
+  for (double** v : vecs)
+    if ((e = hipMemset(*v, 0, n4 * sizeof(double))) != hipSuccess) return hip_fail(e, "hipMemset");
   if ((e = hipMemcpy(ua, u_a, n * 8, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(e, "hipMemcpy");
   if ((e = hipMemcpy(ub, u_b, n * 8, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(e, "hipMemcpy");
   if ((e = hipMemcpy(yd, y_d, n * 8, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(e, "hipMemcpy");
@@ -811,17 +977,12 @@ extern "C" int ipmpde_problem_create(const ipmpde_grid* grid, const ipmpde_pde* 
     if ((e = hipMemcpy(ya, y_a, n * 8, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(e, "hipMemcpy");
     if ((e = hipMemcpy(yb, y_b, n * 8, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(e, "hipMemcpy");
   }
-  if ((e = hipHostMalloc((void**)&P->ctrl_h, sizeof(KrylovCtrl), hipHostMallocDefault)) != hipSuccess)
-    return hip_fail(e, "hipHostMalloc");
-  if ((e = hipHostMalloc((void**)&P->stat_h, 16 * sizeof(double), hipHostMallocDefault)) != hipSuccess)
-    return hip_fail(e, "hipHostMalloc");
-  if ((e = hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking)) != hipSuccess)
-    return hip_fail(e, "hipStreamCreate");
+  if ((rc = ensure_mg(P, true)) != IPMPDE_OK) return cleanup(rc);
+  if ((rc = group_create({P}, &P->self)) != IPMPDE_OK) return cleanup(rc);
   ipmpde_options o;
   ipmpde_default_options(&o);
-  if ((rc = ensure_mg(P, true)) != IPMPDE_OK) return cleanup(rc);
-  select_mg(P, o);
-  reset_state(P, o.mu0, nullptr);
+  if ((rc = group_select(P->self, o)) != IPMPDE_OK) return cleanup(rc);
+  if ((rc = group_reset(P->self, {o}, nullptr)) != IPMPDE_OK) return cleanup(rc);
   if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "init");
   *out = P;
   return IPMPDE_OK;
@@ -829,8 +990,8 @@ extern "C" int ipmpde_problem_create(const ipmpde_grid* grid, const ipmpde_pde* 
 
 extern "C" void ipmpde_problem_destroy(ipmpde_problem* P) {
   if (!P) return;
-  hipDeviceSynchronize();
-  free_all(P);
+  (void)hipDeviceSynchronize();
+  problem_free(P);
   delete P;
 }
 
@@ -839,22 +1000,40 @@ extern "C" void ipmpde_problem_destroy(ipmpde_problem* P) {
 
 static hipStream_t S(ipmpde_stream s) { return (hipStream_t)s; }
 
+static int status_error(int st) {
+  if (st == IPMPDE_ENOTCONVERGED) return fail(st, "IPM iteration limit reached");
+  if (st == IPMPDE_EBREAKDOWN) return fail(st, "breakdown: NaN in the iterates or a collapsed step length");
+  return st;
+}
+
 extern "C" int ipmpde_solve(ipmpde_problem* P, const ipmpde_options* opts, ipmpde_stream stream) {
   if (!P) return fail(IPMPDE_EINVAL, "problem is NULL");
   ipmpde_options o;
-  resolve_opts(opts, &o);
-  TRY(check_options(P, o));
-  return solve_impl(P, o, S(stream));
+  TRY(resolve_opts(opts, &o));
+  TRY(solve_group(P->self, {o}, S(stream)));
+  return status_error(P->stats.status);
 }
 
 extern "C" int ipmpde_reset(ipmpde_problem* P, const ipmpde_options* opts, ipmpde_stream stream) {
   if (!P) return fail(IPMPDE_EINVAL, "problem is NULL");
   ipmpde_options o;
-  resolve_opts(opts, &o);
-  TRY(check_options(P, o));
-  reset_state(P, o.mu0, S(stream));
-  HIP_TRY(hipGetLastError());
-  return IPMPDE_OK;
+  TRY(resolve_opts(opts, &o));
+  TRY(group_select(P->self, o));
+  return group_reset(P->self, {o}, S(stream));
+}
+
+// One Newton setup + Krylov solve of the single-problem group at barrier mu_new.
+static int single_newton(ipmpde_problem* P, const ipmpde_options& o, double mu_new, hipStream_t s, int* its,
+                         double* relres) {
+  Group* G = P->self;
+  G->H[0].active = 1;
+  G->H[0].mu = mu_new;
+  G->H[0].alpha0 = o.alpha0;
+  TRY(newton_setup_group(G, o, s));
+  TRY(krylov_group(G, o, s));
+  if (its) *its = G->ctrl_h[0].its_total;
+  if (relres) *relres = G->ctrl_h[0].relres;
+  return krylov_status(G, 0);
 }
 
 extern "C" int ipmpde_ipm_step(ipmpde_problem* P, const ipmpde_options* opts, double mu_new, ipmpde_stream stream,
@@ -862,25 +1041,35 @@ extern "C" int ipmpde_ipm_step(ipmpde_problem* P, const ipmpde_options* opts, do
   if (!P) return fail(IPMPDE_EINVAL, "problem is NULL");
   if (!(mu_new > 0)) return fail(IPMPDE_EINVAL, "mu_new must be positive");
   ipmpde_options o;
-  resolve_opts(opts, &o);
-  TRY(check_options(P, o));
-  double aP = 0, aD = 0, rel = 0;
+  TRY(resolve_opts(opts, &o));
+  hipStream_t s = S(stream);
   int its = 0;
-  int rc = ipm_step_impl(P, o, mu_new, S(stream), &aP, &aD, &its, &rel);
-  if (alpha_p) *alpha_p = aP;
-  if (alpha_d) *alpha_d = aD;
+  double rel = 0;
+  const int krc = single_newton(P, o, mu_new, s, &its, &rel);
+  if (krc != IPMPDE_OK && krc != IPMPDE_EKRYLOV) return fail(krc, "Newton solve broke down");
+  Group* G = P->self;
+  hipLaunchKernelGGL(k_step_lengths, gz(G, G->max_n), dim3(kBS), 0, s, G->D);
+  hipLaunchKernelGGL(k_update, gz(G, G->max_n), dim3(kBS), 0, s, G->D);
+  HIP_TRY(hipGetLastError());
+  TRY(read_stat(G, s));
+  P->mu = mu_new;
+  if (alpha_p) *alpha_p = G->stat_h[3];
+  if (alpha_d) *alpha_d = G->stat_h[4];
   if (krylov_its) *krylov_its = its;
   if (relres) *relres = rel;
-  return rc;
+  if (krc == IPMPDE_EKRYLOV) return fail(krc, "Krylov tolerance not reached");
+  return IPMPDE_OK;
 }
 
 extern "C" int ipmpde_newton_setup(ipmpde_problem* P, const ipmpde_options* opts, double mu_new, ipmpde_stream stream) {
   if (!P) return fail(IPMPDE_EINVAL, "problem is NULL");
   if (!(mu_new > 0)) return fail(IPMPDE_EINVAL, "mu_new must be positive");
   ipmpde_options o;
-  resolve_opts(opts, &o);
-  TRY(check_options(P, o));
-  TRY(newton_setup(P, o, mu_new, S(stream)));
+  TRY(resolve_opts(opts, &o));
+  Group* G = P->self;
+  G->H[0].active = 1;
+  G->H[0].mu = mu_new;
+  TRY(newton_setup_group(G, o, S(stream)));
   HIP_TRY(hipStreamSynchronize(S(stream)));
   return IPMPDE_OK;
 }
@@ -890,20 +1079,22 @@ extern "C" int ipmpde_newton_direction(ipmpde_problem* P, const ipmpde_options* 
   if (!P) return fail(IPMPDE_EINVAL, "problem is NULL");
   if (!(mu_new > 0)) return fail(IPMPDE_EINVAL, "mu_new must be positive");
   ipmpde_options o;
-  resolve_opts(opts, &o);
-  TRY(check_options(P, o));
-  TRY(newton_setup(P, o, mu_new, S(stream)));
-  int its = 0;
-  double rel = 0;
-  int rc = krylov_solve(P, o, S(stream), &its, &rel);
-  if (krylov_its) *krylov_its = its;
-  if (relres) *relres = rel;
-  return rc;
+  TRY(resolve_opts(opts, &o));
+  const int rc = single_newton(P, o, mu_new, S(stream), krylov_its, relres);
+  if (rc == IPMPDE_EKRYLOV) return fail(rc, "Krylov tolerance not reached");
+  if (rc != IPMPDE_OK) return fail(rc, "Newton solve broke down");
+  return IPMPDE_OK;
 }
 
 extern "C" int ipmpde_measures(ipmpde_problem* P, ipmpde_stream stream, double* xp, double* xd, double* xc) {
   if (!P || !xp || !xd || !xc) return fail(IPMPDE_EINVAL, "NULL argument");
-  return measures(P, S(stream), xp, xd, xc);
+  Group* G = P->self;
+  G->H[0].active = 1;
+  TRY(group_measures(G, S(stream)));
+  *xp = G->stat_h[0];
+  *xd = G->stat_h[1];
+  *xc = G->stat_h[2];
+  return IPMPDE_OK;
 }
 
 extern "C" int ipmpde_get_stats(const ipmpde_problem* P, ipmpde_stats* out) {
@@ -927,10 +1118,10 @@ static const double* field_ptr(const ipmpde_problem* P, int field, int* kind) {
     case IPMPDE_FIELD_LAM_WB: return I.lwb;
     case IPMPDE_FIELD_LAM_VA: return I.lva;
     case IPMPDE_FIELD_LAM_VB: return I.lvb;
-    case IPMPDE_FIELD_DY: return P->X;
-    case IPMPDE_FIELD_DW: return P->X + n;
-    case IPMPDE_FIELD_DV: return P->X + 2 * n;
-    case IPMPDE_FIELD_DP: return P->X + 3 * n;
+    case IPMPDE_FIELD_DY: return I.X;
+    case IPMPDE_FIELD_DW: return I.X + n;
+    case IPMPDE_FIELD_DV: return I.X + 2 * n;
+    case IPMPDE_FIELD_DP: return I.X + 3 * n;
     case IPMPDE_FIELD_THETA_Y: return I.ty;
     case IPMPDE_FIELD_THETA_W: return I.tw;
     case IPMPDE_FIELD_THETA_V: return I.tv;
@@ -978,14 +1169,17 @@ extern "C" int ipmpde_query_rhs(const ipmpde_problem* P, double* out, size_t cou
   if (!P || !out) return fail(IPMPDE_EINVAL, "NULL argument");
   if (count != 4 * (size_t)P->n) return fail(IPMPDE_EINVAL, "count must equal 4 n");
   HIP_TRY(hipDeviceSynchronize());
-  HIP_TRY(hipMemcpy(out, P->rhs, count * 8, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(out, P->I.rhs, count * 8, hipMemcpyDeviceToHost));
   return IPMPDE_OK;
 }
 
 extern "C" int ipmpde_apply_operator(const ipmpde_problem* P, int transpose, const double* x, double* y,
                                      ipmpde_stream stream) {
   if (!P || !x || !y) return fail(IPMPDE_EINVAL, "NULL argument");
-  hipLaunchKernelGGL(k_apply_op, dim3(nblk(P->n)), dim3(kBS), 0, S(stream), P->I, x, y, transpose);
+  Group* G = P->self;
+  G->H[0].active = 1;
+  TRY(group_sync(G, S(stream)));
+  hipLaunchKernelGGL(k_apply_op, gz(G, P->n), dim3(kBS), 0, S(stream), G->D, x, y, transpose);
   HIP_TRY(hipGetLastError());
   return IPMPDE_OK;
 }
@@ -993,34 +1187,74 @@ extern "C" int ipmpde_apply_operator(const ipmpde_problem* P, int transpose, con
 extern "C" int ipmpde_apply_saddle(ipmpde_problem* P, const double* x, double* y, ipmpde_stream stream) {
   if (!P || !x || !y) return fail(IPMPDE_EINVAL, "NULL argument");
   if (!P->setup_done) return fail(IPMPDE_EINVAL, "no Newton setup yet");
-  hipLaunchKernelGGL(k_saddle, dim3(nblk(P->n)), dim3(kBS), 0, S(stream), P->I, x, y);
+  Group* G = P->self;
+  hipLaunchKernelGGL(k_saddle, gz(G, P->n), dim3(kBS), 0, S(stream), G->D, x, y);
   HIP_TRY(hipGetLastError());
   return IPMPDE_OK;
-}
-
-template <typename T>
-static void precond_apply_t(ipmpde_problem* P, int pt, const double* x, double* y, int guard, hipStream_t s) {
-  hipLaunchKernelGGL(k_precond_diag<T>, dim3(nblk(P->n)), dim3(kBS), 0, s, P->I, x, y, pt, guard);
-  if (pt) hipLaunchKernelGGL(k_pt_rhs<T>, dim3(nblk(P->n)), dim3(kBS), 0, s, P->I, x, (const double*)y, guard);
-  T* xs = schur_inv<T>(P, guard, s);
-  hipLaunchKernelGGL(k_store_p<T>, dim3(nblk(P->n)), dim3(kBS), 0, s, P->I, (const T*)xs, y, guard);
 }
 
 extern "C" int ipmpde_apply_precond(ipmpde_problem* P, const ipmpde_options* opts, const double* x, double* y,
                                     ipmpde_stream stream) {
   if (!P || !x || !y) return fail(IPMPDE_EINVAL, "NULL argument");
   ipmpde_options o;
-  resolve_opts(opts, &o);
-  TRY(check_options(P, o));
+  TRY(resolve_opts(opts, &o));
   if (!P->setup_done || P->setup_fp32 != (o.mg_precision == IPMPDE_FP32))
     return fail(IPMPDE_EINVAL, "no Newton setup for this multigrid precision");
-  select_mg(P, o);
+  Group* G = P->self;
+  TRY(group_select(G, o));
+  TRY(group_sync(G, S(stream)));
   const int pt = o.precond == IPMPDE_PT;
-  if (o.mg_precision == IPMPDE_FP32) precond_apply_t<float>(P, pt, x, y, 0, S(stream));
-  else precond_apply_t<double>(P, pt, x, y, 0, S(stream));
+  if (G->fp32) precond_apply<float>(G, pt, x, y, 0, 0, S(stream));
+  else precond_apply<double>(G, pt, x, y, 0, 0, S(stream));
   HIP_TRY(hipGetLastError());
   return IPMPDE_OK;
 }
 
-#include "fgmres_host.hip"
+// ---------------------------------------------------------------------------
+// batches
+
+struct ipmpde_batch {
+  Group* G = nullptr;
+};
+
+extern "C" int ipmpde_batch_create(ipmpde_problem* const* probs, int count, ipmpde_batch** out) {
+  if (!out) return fail(IPMPDE_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!probs || count < 1 || count > 65535) return fail(IPMPDE_EINVAL, "count must be in [1, 65535]");
+  std::vector<ipmpde_problem*> v(probs, probs + count);
+  for (int i = 0; i < count; ++i) {
+    if (!v[i]) return fail(IPMPDE_EINVAL, "NULL problem in batch");
+    if (v[i]->dim != v[0]->dim) return fail(IPMPDE_EINVAL, "all problems of a batch must have the same dimension");
+    for (int j = 0; j < i; ++j)
+      if (v[j] == v[i]) return fail(IPMPDE_EINVAL, "a problem appears twice in the batch");
+  }
+  ipmpde_batch* B = new ipmpde_batch();
+  const int rc = group_create(v, &B->G);
+  if (rc != IPMPDE_OK) { delete B; return rc; }
+  *out = B;
+  return IPMPDE_OK;
+}
+
+extern "C" void ipmpde_batch_destroy(ipmpde_batch* B) {
+  if (!B) return;
+  (void)hipDeviceSynchronize();
+  group_release(B->G);
+  delete B;
+}
+
+extern "C" int ipmpde_batch_solve(ipmpde_batch* B, const ipmpde_options* opts, int per_problem, ipmpde_stream stream) {
+  if (!B) return fail(IPMPDE_EINVAL, "batch is NULL");
+  Group* G = B->G;
+  std::vector<ipmpde_options> po(G->count);
+  for (int i = 0; i < G->count; ++i) TRY(resolve_opts(opts ? (per_problem ? &opts[i] : opts) : nullptr, &po[i]));
+  for (int i = 1; i < G->count; ++i) {
+    const ipmpde_options &a = po[0], &b = po[i];
+    if (a.krylov != b.krylov || a.precond != b.precond || a.restart != b.restart || a.krylov_tol != b.krylov_tol ||
+        a.krylov_maxit != b.krylov_maxit || a.nu_pre != b.nu_pre || a.nu_post != b.nu_post || a.omega != b.omega ||
+        a.mg_precision != b.mg_precision || a.chunk != b.chunk || a.use_graphs != b.use_graphs || a.vcycles != b.vcycles)
+      return fail(IPMPDE_EINVAL, "Krylov and multigrid options must agree across a batch");
+  }
+  return solve_group(G, po, S(stream));
+}
+
 #include "timing.hip"

@@ -1,0 +1,66 @@
+"""Batched solves: several unevenly sized problems advanced by the same
+kernel launches give each problem the result of its solo solve."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import workloads as W  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def _mixed(seed=0):
+    reqs = W.served_requests(n_requests=12, seed=seed, sizes=(31, 63, 127))
+    return [d for _, d in reqs]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_equals_solo(prec):
+    from paper_1806_05896_amd import Batch, Options, Problem
+    datas = _mixed()
+    print("[batch] sizes", [d.N for d in datas], "pdes", [d.pde for d in datas], flush=True)
+    opts = [Options(sigma=d.sigma, mg_precision=prec) for d in datas]
+    solo = []
+    for d, o in zip(datas, opts):
+        with Problem(d) as p:
+            rc = p.solve(o)
+            solo.append((rc, p.query("u"), p.query("y"), p.stats()))
+    probs = [Problem(d) for d in datas]
+    with Batch(probs) as b:
+        st = b.solve(opts)
+    for k, (p, (rc, u, y, s)) in enumerate(zip(probs, solo)):
+        ub, yb, sb = p.query("u"), p.query("y"), p.stats()
+        print(f"  {k}: N={p.N} rc={rc}/{st[k]} nli={s.nli}/{sb.nli} its={s.krylov_its}/{sb.krylov_its} "
+              f"max|du|={np.abs(ub - u).max():.1e}", flush=True)
+        assert st[k] == rc == 0
+        assert sb.nli == s.nli and sb.krylov_its == s.krylov_its
+        np.testing.assert_array_equal(ub, u)
+        np.testing.assert_array_equal(yb, y)
+        p.close()
+
+
+def test_batch_member_limits_do_not_leak():
+    """One member with an IPM iteration limit of 2 stops early (ENOTCONVERGED);
+    its batch-mates converge exactly as they would alone."""
+    from paper_1806_05896_amd import Batch, Options, Problem
+    datas = _mixed(seed=1)[:5]
+    opts = [Options(sigma=d.sigma) for d in datas]
+    opts[2] = Options(sigma=datas[2].sigma, ipm_maxit=2)
+    probs = [Problem(d) for d in datas]
+    with Batch(probs) as b:
+        st = b.solve(opts)
+    assert st[2] == 4 and probs[2].stats().nli == 2
+    for k in (0, 1, 3, 4):
+        with Problem(datas[k]) as p:
+            p.solve(opts[k])
+            np.testing.assert_array_equal(p.query("u"), probs[k].query("u"))
+        assert st[k] == 0
+    for p in probs:
+        p.close()
