@@ -101,6 +101,122 @@ def cpu_baseline(data, nli):
                       + (f"; OMP_NUM_THREADS={threads}" if threads else "")}
 
 
+def solver_options(d, Options, prec="fp32"):
+    """Per-request solver choice: MINRES + P_D for Poisson, FGMRES(30) + P_T
+    for convection-diffusion, multigrid in the given precision."""
+    if d.pde == "convdiff":
+        return Options(sigma=d.sigma, krylov="fgmres", precond="pt", mg_precision=prec)
+    return Options(sigma=d.sigma, krylov="minres", precond="pd", mg_precision=prec)
+
+
+def bench_batched(W, torch, B, reps):
+    """B instances of the 511^2 workload (seeds 0..B-1) advanced by the same
+    launches (ipmpde_batch), FP32 V-cycles against plain FP64 V-cycles."""
+    import numpy as np
+    from paper_1806_05896_amd import Batch, Options, Problem
+    datas = [W.poisson2d_511(seed=s) for s in range(B)]
+    probs = [Problem(d) for d in datas]
+    out = {"instances": B, "workload": "poisson2d_511 seeds 0..%d" % (B - 1)}
+    us = {}
+    stream = torch.cuda.current_stream()
+    with Batch(probs) as b:
+        for prec in ("fp32", "fp64"):
+            opts = [Options(sigma=d.sigma, mg_precision=prec) for d in datas]
+            b.solve(opts, stream=stream)  # warm-up (graph capture, workspace)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                st = b.solve(opts, stream=stream)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / reps
+            its = sum(p.stats().krylov_its for p in probs)
+            us[prec] = [p.query("u") for p in probs]
+            out[prec] = {"solves_per_s": B / t, "ms_per_batch": t * 1e3, "krylov_its_per_s": its / t,
+                         "status": st, "nli": [p.stats().nli for p in probs]}
+            log(f"batched x{B} {prec}: {B / t:.2f} solves/s ({t * 1e3:.1f} ms per batch)")
+    out["max_rel_l2_u_fp32_vs_fp64"] = max(float(np.linalg.norm(a - c) / np.linalg.norm(c))
+                                           for a, c in zip(us["fp32"], us["fp64"]))
+    out["fp32_over_fp64"] = out["fp32"]["solves_per_s"] / out["fp64"]["solves_per_s"]
+    for p in probs:
+        p.close()
+    return out
+
+
+def serve_run(reqs, times, torch, slots, budget, prec="fp32"):
+    """Drive the request stream through the serving engine: request i is
+    created (its data uploaded) and submitted at times[i] seconds after the
+    start; the loop steps the engine while work is in flight and returns each
+    request's control to the host when it finishes.  Latency = completion
+    (result on the host) minus arrival."""
+    import numpy as np  # noqa: F401
+    from paper_1806_05896_amd import Engine, Options, Problem
+    stream = torch.cuda.current_stream()
+    n = len(reqs)
+    lat = [None] * n
+    status = [None] * n
+    its = 0
+    probs, tickets = [None] * n, [None] * n
+    pending = []
+    nxt = 0
+    steps = 0
+    with Engine(budget, slots) as eng:
+        t0 = time.perf_counter()
+        while nxt < n or pending:
+            now = time.perf_counter() - t0
+            while nxt < n and times[nxt] <= now:
+                d = reqs[nxt]
+                probs[nxt] = Problem(d)
+                tickets[nxt] = eng.submit(probs[nxt], solver_options(d, Options, prec))
+                pending.append(nxt)
+                nxt += 1
+            if not pending:
+                time.sleep(max(0.0, times[nxt] - (time.perf_counter() - t0)))
+                continue
+            eng.step(stream)
+            steps += 1
+            still = []
+            for i in pending:
+                info = eng.poll(tickets[i])
+                if info["state"] != 2:
+                    still.append(i)
+                    continue
+                probs[i].query("u")  # the response
+                lat[i] = (time.perf_counter() - t0 - times[i]) * 1e3
+                status[i] = info["status"]
+                its += info["krylov_its"]
+                eng.release(tickets[i])
+                probs[i].close()
+            pending = still
+        makespan = time.perf_counter() - t0
+        peak = eng.info()["peak_bytes"]
+    return {"requests": n, "makespan_s": makespan, "solves_per_s": n / makespan, "krylov_its_per_s": its / makespan,
+            "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99), "max": max(lat)},
+            "engine_steps": steps, "peak_admitted_bytes": peak,
+            "ok": sum(1 for s in status if s == 0), "status_counts": {str(k): status.count(k) for k in set(status)}}
+
+
+def bench_serving(W, torch, n_requests, slots, budget_gib, loads):
+    """Served mix: saturation throughput with every request present at the
+    start, then Poisson arrivals at the given fractions of it."""
+    reqs = W.served_requests(n_requests=n_requests, seed=0)
+    datas = [d for _, d in reqs]
+    unit_times = [t for t, _ in reqs]  # arrival times of a unit-rate Poisson process
+    budget = int(budget_gib * (1 << 30))
+    out = {"workload": f"served_mix: {n_requests} requests, 50% Poisson / 25% CD eps=1/50 / 25% CD eps=1/200, "
+                       "N in {31,63,127,255}, alpha logU[1e-6,1e-2], beta logU[1e-5,1e-2], bounds U[1,10]",
+           "slots": slots, "hbm_budget_gib": budget_gib}
+    sat = serve_run(datas, [0.0] * len(datas), torch, slots, budget)
+    log(f"serving saturation: {sat['solves_per_s']:.2f} req/s, p50 {sat['latency_ms']['p50']:.0f} ms")
+    out["saturation"] = sat
+    for load in loads:
+        rate = load * sat["solves_per_s"]
+        r = serve_run(datas, [t / rate for t in unit_times], torch, slots, budget)
+        r["arrival_rate_per_s"] = rate
+        log(f"serving load {load}: p50 {r['latency_ms']['p50']:.0f} ms p99 {r['latency_ms']['p99']:.0f} ms")
+        out[f"load_{load}"] = r
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +226,12 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 V-cycle variant")
     ap.add_argument("--kernel", type=int, default=6, help="kernel id for the roofline figure")
     ap.add_argument("--N", type=int, default=511)
+    ap.add_argument("--batch", type=int, default=8, help="instances of the batched FP32-vs-FP64 run (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=256, help="requests of the served mix (0: skip)")
+    ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-budget-gib", type=float, default=32.0)
+    ap.add_argument("--serve-loads", type=str, default="0.8", help="arrival rates as fractions of saturation")
+    ap.add_argument("--only", choices=["serve", "batch"], default=None, help="run one extra section alone")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only launch the roofline kernel (20 times) and a 1 GiB device copy, for counter runs")
     args = ap.parse_args()
@@ -128,6 +250,14 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    loads = [float(x) for x in args.serve_loads.split(",") if x]
+    if args.only == "serve":
+        print(json.dumps({"serving": bench_serving(W, torch, args.serve_requests, args.serve_slots,
+                                                   args.serve_budget_gib, loads)}), flush=True)
+        return
+    if args.only == "batch":
+        print(json.dumps({"batched": bench_batched(W, torch, args.batch, 2)}), flush=True)
+        return
     data = W.poisson2d_511(seed=0, N=args.N)
     prob = Problem(data)
     opts = Options(sigma=data.sigma, mg_precision="fp32")
@@ -197,6 +327,15 @@ def main():
         result["fp64_vcycles"] = {"solves_per_s": n64 / t64, "krylov_its_per_solve": its64 / n64,
                                   "nli": st64.nli, "status": rc64,
                                   "rel_l2_u_vs_fp32_path": float(np.linalg.norm(u32 - u64) / np.linalg.norm(u64))}
+
+    if args.batch > 0:
+        result["batched"] = bench_batched(W, torch, args.batch, 2)
+    if args.serve_requests > 0:
+        result["serving"] = bench_serving(W, torch, args.serve_requests, args.serve_slots, args.serve_budget_gib,
+                                          loads)
+        result["served_latency_ms"] = {"p50": result["serving"][f"load_{loads[0]}"]["latency_ms"]["p50"],
+                                       "p99": result["serving"][f"load_{loads[0]}"]["latency_ms"]["p99"],
+                                       "load": loads[0]} if loads else None
 
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample ...")

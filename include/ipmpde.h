@@ -149,7 +149,11 @@ int ipmpde_problem_create(const ipmpde_grid* grid, const ipmpde_pde* pde, double
 
 void ipmpde_problem_destroy(ipmpde_problem* prob);
 
-/* Bytes of device memory a problem of this shape uses with these options. */
+/* Bytes of device memory a problem of this shape holds while it is solved
+ * with these options (opts NULL = defaults): data, iterates and barrier
+ * diagonals (allocated at create) plus the Newton/Krylov/multigrid
+ * workspace (allocated at the first solve, or on admission to an engine).
+ * 0 for an invalid grid. */
 size_t ipmpde_footprint_bytes(const ipmpde_grid* grid, const ipmpde_pde* pde, int has_state_bounds,
                               const ipmpde_options* opts);
 
@@ -241,6 +245,67 @@ void ipmpde_batch_destroy(ipmpde_batch* batch);
  * once every instance has finished; each problem's outcome is in its
  * stats (ipmpde_get_stats) and its iterates are queryable. */
 int ipmpde_batch_solve(ipmpde_batch* batch, const ipmpde_options* opts, int per_problem, ipmpde_stream stream);
+
+/* ---- serving engine: continuous batching of solves ----------------------
+ *
+ * A request is a problem (created as above) plus options.  Requests queue in
+ * arrival order and are admitted while fewer than max_slots run and the sum
+ * of the admitted requests' ipmpde_footprint_bytes stays within
+ * hbm_budget_bytes; admission allocates the problem's Newton/Krylov/multigrid
+ * workspace (from the registered allocator) and retirement frees it, while
+ * the problem's data and iterates stay on the device.  Each
+ * ipmpde_engine_step advances every admitted request by one iteration of
+ * Algorithm A.1 (Appendix); requests with equal Krylov and multigrid options
+ * (and dimension) share the same kernel launches, each at its own IPM
+ * iteration, and requests admitted at a step join at that step.  A
+ * request's arithmetic is that of its solo ipmpde_solve, so its result does
+ * not depend on the other requests in flight.  Once a request is done its
+ * problem can be queried and reused (its stats hold the outcome).  While a
+ * problem is queued or running, every other entry point on it fails with
+ * IPMPDE_EINVAL; destroying it then is undefined.  An engine is not
+ * thread-safe; it issues all work on the stream passed to
+ * ipmpde_engine_step and synchronises that stream before returning. */
+typedef struct ipmpde_engine ipmpde_engine;
+
+enum { IPMPDE_REQ_QUEUED = 0, IPMPDE_REQ_RUNNING = 1, IPMPDE_REQ_DONE = 2 };
+
+typedef struct {
+  int state;              /* IPMPDE_REQ_* */
+  int status;             /* the solve's result code once done, else -1 */
+  int nli;                /* IPM iterations so far */
+  int krylov_its;         /* Krylov iterations so far */
+  double queue_ms;        /* submission to admission (to now while queued) */
+  double latency_ms;      /* submission to completion (to now while not done) */
+  size_t footprint_bytes; /* HBM bytes accounted for the request */
+} ipmpde_request_info;
+
+typedef struct {
+  int running, queued, groups;
+  size_t bytes_in_use, peak_bytes, budget_bytes;
+  long steps;
+} ipmpde_engine_info;
+
+/* hbm_budget_bytes > 0, 1 <= max_slots <= 4096; EINVAL otherwise. */
+int ipmpde_engine_create(size_t hbm_budget_bytes, int max_slots, ipmpde_engine** out);
+/* Frees the engine; requests still queued or running are dropped (their
+ * workspace freed, their problems usable again). */
+void ipmpde_engine_destroy(ipmpde_engine* engine);
+/* Queues a request; *ticket identifies it.  opts NULL = defaults.  ENOMEM
+ * when the request alone exceeds the budget; EINVAL for bad options or a
+ * problem already in an engine. */
+int ipmpde_engine_submit(ipmpde_engine* engine, ipmpde_problem* problem, const ipmpde_options* opts,
+                         uint64_t* ticket);
+/* Admits what fits, then runs one IPM iteration of every admitted request
+ * and retires the finished ones.  running/queued (may be NULL) receive the
+ * counts after the step.  A request's own failure (breakdown, iteration
+ * limit) is its status, not the step's; the step fails only on EDEVICE or
+ * ENOMEM for engine structures. */
+int ipmpde_engine_step(ipmpde_engine* engine, ipmpde_stream stream, int* running, int* queued);
+/* State of a request; EINVAL for an unknown ticket. */
+int ipmpde_engine_poll(const ipmpde_engine* engine, uint64_t ticket, ipmpde_request_info* info);
+/* Forgets a finished request (its ticket becomes unknown). */
+int ipmpde_engine_release(ipmpde_engine* engine, uint64_t ticket);
+int ipmpde_engine_get_info(const ipmpde_engine* engine, ipmpde_engine_info* info);
 
 #ifdef __cplusplus
 }

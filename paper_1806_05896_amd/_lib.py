@@ -59,6 +59,19 @@ class CStats(C.Structure):
     ]
 
 
+class RequestInfo(C.Structure):
+    _fields_ = [("state", C.c_int), ("status", C.c_int), ("nli", C.c_int), ("krylov_its", C.c_int),
+                ("queue_ms", C.c_double), ("latency_ms", C.c_double), ("footprint_bytes", C.c_size_t)]
+
+
+class EngineInfo(C.Structure):
+    _fields_ = [("running", C.c_int), ("queued", C.c_int), ("groups", C.c_int),
+                ("bytes_in_use", C.c_size_t), ("peak_bytes", C.c_size_t), ("budget_bytes", C.c_size_t),
+                ("steps", C.c_long)]
+
+
+REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2
+
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
@@ -94,6 +107,13 @@ SIGNATURES = {
     "ipmpde_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_void_p)]),
     "ipmpde_batch_destroy": (None, [C.c_void_p]),
     "ipmpde_batch_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
+    "ipmpde_engine_create": (C.c_int, [C.c_size_t, C.c_int, C.POINTER(C.c_void_p)]),
+    "ipmpde_engine_destroy": (None, [C.c_void_p]),
+    "ipmpde_engine_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(COptions), C.POINTER(C.c_uint64)]),
+    "ipmpde_engine_step": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "ipmpde_engine_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(RequestInfo)]),
+    "ipmpde_engine_release": (C.c_int, [C.c_void_p, C.c_uint64]),
+    "ipmpde_engine_get_info": (C.c_int, [C.c_void_p, C.POINTER(EngineInfo)]),
 }
 
 _lib = None

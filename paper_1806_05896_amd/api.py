@@ -306,6 +306,72 @@ class Batch:
         self.close()
 
 
+class Engine:
+    """Serving engine (ipmpde_engine): continuous batching of solves with
+    admission by HBM footprint.  The Python side only marshals arguments;
+    queueing, admission, stepping and retirement run in the library."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int):
+        self._lib = L.load()
+        h = C.c_void_p()
+        L.check(self._lib.ipmpde_engine_create(int(hbm_budget_bytes), int(max_slots), C.byref(h)))
+        self._h = h
+        self._problems = {}  # ticket -> Problem (kept alive while queued or running)
+
+    def submit(self, problem: "Problem", opts: Optional[Options] = None) -> int:
+        t = C.c_uint64()
+        o = Problem._opts(opts)
+        L.check(self._lib.ipmpde_engine_submit(self._h, problem._h, o, C.byref(t)))
+        self._problems[t.value] = problem
+        return t.value
+
+    def step(self, stream=None):
+        """One IPM iteration of every admitted request; returns (running, queued)."""
+        r, q = C.c_int(), C.c_int()
+        L.check(self._lib.ipmpde_engine_step(self._h, _stream_handle(stream), C.byref(r), C.byref(q)))
+        return r.value, q.value
+
+    def poll(self, ticket: int) -> dict:
+        info = L.RequestInfo()
+        L.check(self._lib.ipmpde_engine_poll(self._h, C.c_uint64(ticket), C.byref(info)))
+        return {k: getattr(info, k) for k, _ in info._fields_}
+
+    def release(self, ticket: int):
+        L.check(self._lib.ipmpde_engine_release(self._h, C.c_uint64(ticket)))
+        self._problems.pop(ticket, None)
+
+    def info(self) -> dict:
+        info = L.EngineInfo()
+        L.check(self._lib.ipmpde_engine_get_info(self._h, C.byref(info)))
+        return {k: getattr(info, k) for k, _ in info._fields_}
+
+    def run(self, stream=None, max_steps: int = 100000):
+        """Step until nothing is queued or running."""
+        for _ in range(max_steps):
+            r, q = self.step(stream)
+            if r == 0 and q == 0:
+                return
+        raise RuntimeError("engine did not drain")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ipmpde_engine_destroy(self._h)
+            self._h = None
+            self._problems.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
 def footprint_bytes(dim: int, N: int, pde: str = "poisson", has_state_bounds: bool = False,
                     opts: Optional[Options] = None) -> int:
     lib = L.load()

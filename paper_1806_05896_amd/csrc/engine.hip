@@ -1,0 +1,279 @@
+// Serving engine: continuous batching of IPM solves.
+//
+// Requests (a problem plus its options) wait in a FIFO queue and are
+// admitted while a slot is free and the sum of the admitted problems' HBM
+// footprints stays within the budget; admission allocates a problem's
+// Newton/Krylov/multigrid workspace and retirement frees it, while the
+// problem data and iterates stay on the device for the caller to query.
+// Every engine step advances each admitted request by one iteration of
+// Algorithm A.1 (Appendix): requests that share the Krylov and multigrid
+// options form one group, whose kernels advance all its members in the same
+// launches.  A request that arrives while others run joins at the next
+// step, starting from its own initial point, so requests at different IPM
+// iterations share every launch.  Each request takes exactly the arithmetic
+// of a solo solve (per-instance reductions and kernel choices), so its
+// result does not depend on what else is in flight.
+
+using Clock = std::chrono::steady_clock;
+
+struct EngineReq {
+  uint64_t ticket = 0;
+  ipmpde_problem* P = nullptr;
+  ipmpde_options o;
+  size_t bytes = 0;
+  Clock::time_point t_submit, t_admit, t_done;
+  int state = IPMPDE_REQ_QUEUED;
+  int k = 0;           // IPM iteration whose measures come next
+  bool fresh = true;   // still to be put at the starting point
+};
+
+struct EngineClass {
+  ipmpde_options o;  // Krylov and multigrid options of every member
+  int dim = 0;
+  Group* G = nullptr;
+  std::vector<EngineReq*> members;
+};
+
+struct ipmpde_engine {
+  size_t budget = 0, in_use = 0, peak = 0;
+  int max_slots = 0, running = 0;
+  uint64_t next_ticket = 1;
+  long steps = 0;
+  std::deque<EngineReq*> queue;
+  std::vector<EngineClass*> classes;
+  std::map<uint64_t, EngineReq*> reqs;
+};
+
+static bool same_solver(const ipmpde_options& a, const ipmpde_options& b) {
+  return a.krylov == b.krylov && a.precond == b.precond && a.restart == b.restart && a.krylov_tol == b.krylov_tol &&
+         a.krylov_maxit == b.krylov_maxit && a.nu_pre == b.nu_pre && a.nu_post == b.nu_post && a.omega == b.omega &&
+         a.mg_precision == b.mg_precision && a.chunk == b.chunk && a.use_graphs == b.use_graphs &&
+         a.vcycles == b.vcycles;
+}
+
+static int next_pow2(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+extern "C" int ipmpde_engine_create(size_t hbm_budget_bytes, int max_slots, ipmpde_engine** out) {
+  if (!out) return fail(IPMPDE_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (hbm_budget_bytes == 0) return fail(IPMPDE_EINVAL, "hbm_budget_bytes must be positive");
+  if (max_slots < 1 || max_slots > 4096) return fail(IPMPDE_EINVAL, "max_slots must be in [1, 4096]");
+  ipmpde_engine* E = new ipmpde_engine();
+  E->budget = hbm_budget_bytes;
+  E->max_slots = max_slots;
+  *out = E;
+  return IPMPDE_OK;
+}
+
+static void engine_retire(ipmpde_engine* E, EngineReq* R, int status) {
+  R->P->stats.status = status;
+  R->t_done = Clock::now();
+  R->P->stats.solve_ms = std::chrono::duration<double, std::milli>(R->t_done - R->t_admit).count();
+  R->state = IPMPDE_REQ_DONE;
+  release_work(R->P);
+  R->P->in_engine = false;
+  E->in_use -= R->bytes;
+  E->running -= 1;
+}
+
+extern "C" void ipmpde_engine_destroy(ipmpde_engine* E) {
+  if (!E) return;
+  (void)hipDeviceSynchronize();
+  for (auto& kv : E->reqs) {
+    EngineReq* R = kv.second;
+    if (R->state == IPMPDE_REQ_RUNNING) release_work(R->P);
+    if (R->state != IPMPDE_REQ_DONE) R->P->in_engine = false;
+    delete R;
+  }
+  for (EngineClass* C : E->classes) {
+    group_release(C->G);
+    delete C;
+  }
+  delete E;
+}
+
+extern "C" int ipmpde_engine_submit(ipmpde_engine* E, ipmpde_problem* P, const ipmpde_options* opts,
+                                    uint64_t* ticket) {
+  if (!E || !P || !ticket) return fail(IPMPDE_EINVAL, "NULL argument");
+  if (P->in_engine) return fail(IPMPDE_EINVAL, "problem is already queued or running in an engine");
+  ipmpde_options o;
+  TRY(resolve_opts(opts, &o));
+  ipmpde_grid g{P->dim, P->N};
+  ipmpde_pde d{P->pde, P->eps};
+  const size_t bytes = ipmpde_footprint_bytes(&g, &d, P->has_y ? 1 : 0, &o);
+  if (bytes > E->budget) return fail(IPMPDE_ENOMEM, "the request's footprint exceeds the engine's HBM budget");
+  EngineReq* R = new EngineReq();
+  R->ticket = E->next_ticket++;
+  R->P = P;
+  R->o = o;
+  R->bytes = bytes;
+  R->t_submit = Clock::now();
+  P->in_engine = true;
+  E->queue.push_back(R);
+  E->reqs[R->ticket] = R;
+  *ticket = R->ticket;
+  return IPMPDE_OK;
+}
+
+// Move queued requests into free slots, in arrival order, while the budget
+// allows (the head of the queue is never overtaken).
+static int engine_admit(ipmpde_engine* E) {
+  while (!E->queue.empty() && E->running < E->max_slots) {
+    EngineReq* R = E->queue.front();
+    if (E->in_use + R->bytes > E->budget) break;
+    E->queue.pop_front();
+    EngineClass* C = nullptr;
+    for (EngineClass* c : E->classes)
+      if (c->dim == R->P->dim && same_solver(c->o, R->o)) C = c;
+    if (!C) {
+      C = new EngineClass();
+      C->o = R->o;
+      C->dim = R->P->dim;
+      const int rc = group_create({}, E->max_slots, C->dim, &C->G);
+      if (rc != IPMPDE_OK) {
+        delete C;
+        E->queue.push_front(R);
+        return rc;
+      }
+      E->classes.push_back(C);
+    }
+    R->t_admit = Clock::now();
+    R->state = IPMPDE_REQ_RUNNING;
+    R->fresh = true;
+    R->k = 0;
+    ipm_begin(R->P);
+    E->in_use += R->bytes;
+    E->peak = std::max(E->peak, E->in_use);
+    E->running += 1;
+    const int rc = ensure_work(R->P);
+    if (rc != IPMPDE_OK) {
+      engine_retire(E, R, rc);
+      continue;
+    }
+    C->members.push_back(R);
+  }
+  return IPMPDE_OK;
+}
+
+// One IPM iteration of every member of one class.
+static int engine_class_step(ipmpde_engine* E, EngineClass* C, hipStream_t s) {
+  Group* G = C->G;
+  const int m = (int)C->members.size();
+  G->probs.resize(m);
+  G->count = m;
+  G->zc = std::min(next_pow2(m), G->cap);
+  bool any_fresh = false;
+  for (int i = 0; i < m; ++i) {
+    EngineReq* R = C->members[i];
+    G->probs[i] = R->P;
+    G->H[i].active = 1;
+    G->H[i].mu = R->P->mu;
+    G->H[i].alpha0 = R->o.alpha0;
+    any_fresh = any_fresh || R->fresh;
+  }
+  TRY(group_select(G, C->o));
+  if (any_fresh) {
+    // the starting point of the new members only
+    for (int i = 0; i < m; ++i) {
+      EngineReq* R = C->members[i];
+      G->H[i].active = R->fresh ? 1 : 0;
+      if (R->fresh) {
+        R->P->mu = R->o.mu0;
+        G->H[i].mu = R->o.mu0;
+      }
+    }
+    TRY(group_sync(G, s));
+    hipLaunchKernelGGL(k_init_state, gz(G, G->max_n), dim3(kBS), 0, s, G->D);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));  // the upload above has read the flags
+    for (int i = 0; i < m; ++i) {
+      C->members[i]->fresh = false;
+      C->members[i]->P->need_init = false;
+      G->H[i].active = 1;
+    }
+  }
+  TRY(group_measures(G, s));
+  std::vector<int> fin(m, -1);
+  int alive = 0;
+  for (int i = 0; i < m; ++i) {
+    fin[i] = ipm_check(G, i, C->members[i]->k, C->members[i]->o);
+    if (fin[i] < 0) ++alive;
+  }
+  if (alive) {
+    TRY(group_step(G, C->o, s));
+    for (int i = 0; i < m; ++i) {
+      if (fin[i] >= 0) continue;
+      fin[i] = ipm_after_step(G, i, C->members[i]->k);
+      C->members[i]->k += 1;
+    }
+  }
+  // the stream is idle here (group_step and group_measures end with a
+  // read-back), so finished members' workspace can go
+  std::vector<EngineReq*> keep;
+  for (int i = 0; i < m; ++i) {
+    if (fin[i] >= 0) engine_retire(E, C->members[i], fin[i]);
+    else keep.push_back(C->members[i]);
+  }
+  C->members.swap(keep);
+  return IPMPDE_OK;
+}
+
+extern "C" int ipmpde_engine_step(ipmpde_engine* E, ipmpde_stream stream, int* running, int* queued) {
+  if (!E) return fail(IPMPDE_EINVAL, "engine is NULL");
+  hipStream_t s = S(stream);
+  TRY(engine_admit(E));
+  for (EngineClass* C : E->classes)
+    if (!C->members.empty()) TRY(engine_class_step(E, C, s));
+  E->steps += 1;
+  if (running) *running = E->running;
+  if (queued) *queued = (int)E->queue.size();
+  return IPMPDE_OK;
+}
+
+extern "C" int ipmpde_engine_poll(const ipmpde_engine* E, uint64_t ticket, ipmpde_request_info* info) {
+  if (!E || !info) return fail(IPMPDE_EINVAL, "NULL argument");
+  auto it = E->reqs.find(ticket);
+  if (it == E->reqs.end()) return fail(IPMPDE_EINVAL, "unknown ticket");
+  const EngineReq* R = it->second;
+  const auto ms = [](Clock::time_point a, Clock::time_point b) {
+    return std::chrono::duration<double, std::milli>(b - a).count();
+  };
+  const Clock::time_point now = Clock::now();
+  std::memset(info, 0, sizeof(*info));
+  info->state = R->state;
+  info->status = R->state == IPMPDE_REQ_DONE ? R->P->stats.status : -1;
+  info->nli = R->state == IPMPDE_REQ_QUEUED ? 0 : R->P->stats.nli;
+  info->krylov_its = R->state == IPMPDE_REQ_QUEUED ? 0 : R->P->stats.krylov_its;
+  info->queue_ms = ms(R->t_submit, R->state == IPMPDE_REQ_QUEUED ? now : R->t_admit);
+  info->latency_ms = ms(R->t_submit, R->state == IPMPDE_REQ_DONE ? R->t_done : now);
+  info->footprint_bytes = R->bytes;
+  return IPMPDE_OK;
+}
+
+extern "C" int ipmpde_engine_release(ipmpde_engine* E, uint64_t ticket) {
+  if (!E) return fail(IPMPDE_EINVAL, "engine is NULL");
+  auto it = E->reqs.find(ticket);
+  if (it == E->reqs.end()) return fail(IPMPDE_EINVAL, "unknown ticket");
+  if (it->second->state != IPMPDE_REQ_DONE) return fail(IPMPDE_EINVAL, "request has not finished");
+  delete it->second;
+  E->reqs.erase(it);
+  return IPMPDE_OK;
+}
+
+extern "C" int ipmpde_engine_get_info(const ipmpde_engine* E, ipmpde_engine_info* info) {
+  if (!E || !info) return fail(IPMPDE_EINVAL, "NULL argument");
+  std::memset(info, 0, sizeof(*info));
+  info->running = E->running;
+  info->queued = (int)E->queue.size();
+  info->groups = 0;
+  for (const EngineClass* C : E->classes) info->groups += C->members.empty() ? 0 : 1;
+  info->bytes_in_use = E->in_use;
+  info->peak_bytes = E->peak;
+  info->budget_bytes = E->budget;
+  info->steps = E->steps;
+  return IPMPDE_OK;
+}

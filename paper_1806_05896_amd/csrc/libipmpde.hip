@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <mutex>
 #include <string>
@@ -99,14 +100,19 @@ struct AllocList {
 // ---------------------------------------------------------------------------
 // groups
 
+// A captured chunk of Krylov iterations is valid for one launch geometry:
+// the options, the descriptor count and the group's size maxima.
 struct GraphKey {
-  int mg_fp32, nu_pre, nu_post, chunk, maxit, count;
+  int mg_fp32, nu_pre, nu_post, chunk, maxit, zc, max_n, max_nlev, max_cl, flags;
+  size_t coarse_lds;
   double omega, tol;
   bool operator<(const GraphKey& o) const {
-    return std::tie(mg_fp32, nu_pre, nu_post, chunk, maxit, count, omega, tol) <
-           std::tie(o.mg_fp32, o.nu_pre, o.nu_post, o.chunk, o.maxit, o.count, o.omega, o.tol);
+    return std::tie(mg_fp32, nu_pre, nu_post, chunk, maxit, zc, max_n, max_nlev, max_cl, flags, coarse_lds, omega, tol) <
+           std::tie(o.mg_fp32, o.nu_pre, o.nu_post, o.chunk, o.maxit, o.zc, o.max_n, o.max_nlev, o.max_cl, o.flags,
+                    o.coarse_lds, o.omega, o.tol);
   }
 };
+static constexpr size_t kMaxGraphs = 64;
 
 struct ipmpde_problem;
 
@@ -116,6 +122,8 @@ struct ipmpde_problem;
 struct Group {
   std::vector<ipmpde_problem*> probs;
   int count = 0, dim = 0;
+  int cap = 0;  // descriptor capacity
+  int zc = 0;   // descriptors per launch (blockIdx.z extent); [count, zc) are inactive
   Inst* D = nullptr;             // device descriptors
   Inst* H = nullptr;             // pinned host copies
   KrylovCtrl* ctrl_d = nullptr;
@@ -143,7 +151,11 @@ struct ipmpde_problem {
   int dim = 0, N = 0, n = 0, pde = 0;
   double eps = 1.0, alpha = 0.0, beta = 0.0;
   bool has_y = false;
-  AllocList mem;
+  AllocList mem;   // problem data, iterates, barrier diagonals (lifetime of the handle)
+  AllocList work;  // Newton/Krylov vectors, multigrid levels, reduction partials
+  bool have_work = false;
+  bool need_init = true;   // iterates not yet at the starting point
+  bool in_engine = false;  // queued or running in a serving engine
   int nlev = 0;
   Level lv32[kMaxLev];
   Level lv64[kMaxLev];
@@ -157,6 +169,7 @@ struct ipmpde_problem {
   double mu = 1.0;
   bool setup_done = false;
   int setup_fp32 = -1;
+  const Group* setup_group = nullptr;  // group whose descriptors hold the last Newton setup
 };
 
 static bool is_pow2m1(int N) { return N >= 3 && ((N + 1) & N) == 0; }
@@ -230,10 +243,10 @@ static int ensure_mg(ipmpde_problem* P, bool fp32) {
     lv[l].h = 1.0 / (N + 1);
     lv[l].invN = 1.0f / (float)N;
     const size_t nb = (size_t)lv[l].n * el;
-    TRY(P->mem.alloc(&lv[l].x, nb));
-    TRY(P->mem.alloc(&lv[l].x2, nb));
-    TRY(P->mem.alloc(&lv[l].b, nb));
-    TRY(P->mem.alloc(&lv[l].mh, nb));
+    TRY(P->work.alloc(&lv[l].x, nb));
+    TRY(P->work.alloc(&lv[l].x2, nb));
+    TRY(P->work.alloc(&lv[l].b, nb));
+    TRY(P->work.alloc(&lv[l].mh, nb));
     HIP_TRY(hipMemset(lv[l].x, 0, nb));
     HIP_TRY(hipMemset(lv[l].x2, 0, nb));
     HIP_TRY(hipMemset(lv[l].b, 0, nb));
@@ -242,7 +255,7 @@ static int ensure_mg(ipmpde_problem* P, bool fp32) {
   }
   (fp32 ? P->coarse32 : P->coarse64) = pick_coarse(lv, P->nlev, el, P->dim, is_p2(P));
   Level*& lvd = fp32 ? P->lvd32 : P->lvd64;
-  TRY(P->mem.alloc_t(&lvd, kMaxLev));
+  TRY(P->work.alloc_t(&lvd, kMaxLev));
   HIP_TRY(hipMemcpy(lvd, lv, sizeof(Level) * kMaxLev, hipMemcpyHostToDevice));
   have = true;
   return IPMPDE_OK;
@@ -251,20 +264,60 @@ static int ensure_mg(ipmpde_problem* P, bool fp32) {
 static int ensure_fgmres(ipmpde_problem* P, int restart) {
   if (P->I.fV && P->f_restart >= restart) return IPMPDE_OK;
   const size_t n4 = 4 * (size_t)P->n;
-  TRY(P->mem.alloc_t(&P->I.fV, (size_t)(restart + 1) * n4));
-  TRY(P->mem.alloc_t(&P->I.fZ, (size_t)restart * n4));
+  TRY(P->work.alloc_t(&P->I.fV, (size_t)(restart + 1) * n4));
+  TRY(P->work.alloc_t(&P->I.fZ, (size_t)restart * n4));
   P->f_restart = restart;
   return IPMPDE_OK;
 }
 
 // partial-sum capacity for reductions over `blocks` blocks (3 values each)
 // and for the FGMRES block dot products (61 x 256)
+static int partials_words(int blocks) { return std::max(4 * blocks, 64 * kBS) + 64; }
 static int ensure_partials(ipmpde_problem* P, int blocks) {
-  const int need = std::max(4 * blocks, 64 * kBS) + 64;
+  const int need = partials_words(blocks);
   if (P->I.nparts >= need) return IPMPDE_OK;
-  TRY(P->mem.alloc_t(&P->I.partials, (size_t)need));
+  TRY(P->work.alloc_t(&P->I.partials, (size_t)need));
   P->I.nparts = need;
   return IPMPDE_OK;
+}
+
+// The Newton right-hand side, direction and Krylov vectors (4n each).
+static constexpr int kKrylovVecs = 13;
+static void krylov_vecs(Inst& I, double** v[kKrylovVecs]) {
+  double** all[kKrylovVecs] = {&I.rhs, &I.X, &I.Q, &I.R, &I.Rt, &I.V[0], &I.V[1], &I.Z[0], &I.Z[1],
+                               &I.W[0], &I.W[1], &I.KW[0], &I.KW[1]};
+  std::copy(all, all + kKrylovVecs, v);
+}
+
+// Workspace of the Newton solves; allocated on first use (or admission to a
+// serving engine) and released when the problem leaves the engine.
+static int ensure_work(ipmpde_problem* P) {
+  if (P->have_work) return IPMPDE_OK;
+  const size_t n4 = 4 * (size_t)P->n;
+  double** v[kKrylovVecs];
+  krylov_vecs(P->I, v);
+  for (double** p : v) TRY(P->work.alloc_t(p, n4));
+  for (double** p : v) HIP_TRY(hipMemset(*p, 0, n4 * sizeof(double)));
+  TRY(ensure_partials(P, nblk((long)P->n)));
+  P->have_work = true;
+  return IPMPDE_OK;
+}
+
+static void release_work(ipmpde_problem* P) {
+  P->work.release();
+  Inst& I = P->I;
+  double** v[kKrylovVecs];
+  krylov_vecs(I, v);
+  for (double** p : v) *p = nullptr;
+  I.fV = I.fZ = nullptr;
+  I.partials = nullptr;
+  I.nparts = 0;
+  P->f_restart = 0;
+  P->have32 = P->have64 = false;
+  P->lvd32 = P->lvd64 = nullptr;
+  for (int l = 0; l < kMaxLev; ++l) P->lv32[l] = P->lv64[l] = Level{};
+  P->have_work = false;
+  P->setup_done = false;
 }
 
 static void group_release(Group* G) {
@@ -279,25 +332,30 @@ static void group_release(Group* G) {
   delete G;
 }
 
-static int group_create(const std::vector<ipmpde_problem*>& probs, Group** out) {
+// A group with room for `cap` descriptors holding `probs` (cap >= size).
+static int group_create(const std::vector<ipmpde_problem*>& probs, int cap, int dim, Group** out) {
   Group* G = new Group();
   G->probs = probs;
   G->count = (int)probs.size();
-  G->dim = probs[0]->dim;
+  G->cap = cap;
+  G->zc = G->count;
+  G->dim = dim;
   auto bail = [&](int rc) { group_release(G); return rc; };
   int rc;
-  if ((rc = G->mem.alloc_t(&G->D, G->count))) return bail(rc);
-  if ((rc = G->mem.alloc_t(&G->ctrl_d, G->count))) return bail(rc);
-  if ((rc = G->mem.alloc_t(&G->stat_d, 16 * (size_t)G->count))) return bail(rc);
+  if ((rc = G->mem.alloc_t(&G->D, cap))) return bail(rc);
+  if ((rc = G->mem.alloc_t(&G->ctrl_d, cap))) return bail(rc);
+  if ((rc = G->mem.alloc_t(&G->stat_d, 16 * (size_t)cap))) return bail(rc);
   hipError_t e;
-  if ((e = hipMemset(G->ctrl_d, 0, sizeof(KrylovCtrl) * G->count)) != hipSuccess ||
-      (e = hipMemset(G->stat_d, 0, 16 * sizeof(double) * G->count)) != hipSuccess ||
-      (e = hipHostMalloc((void**)&G->H, sizeof(Inst) * G->count, hipHostMallocDefault)) != hipSuccess ||
-      (e = hipHostMalloc((void**)&G->ctrl_h, sizeof(KrylovCtrl) * G->count, hipHostMallocDefault)) != hipSuccess ||
-      (e = hipHostMalloc((void**)&G->stat_h, 16 * sizeof(double) * G->count, hipHostMallocDefault)) != hipSuccess ||
+  if ((e = hipMemset(G->ctrl_d, 0, sizeof(KrylovCtrl) * cap)) != hipSuccess ||
+      (e = hipMemset(G->stat_d, 0, 16 * sizeof(double) * cap)) != hipSuccess ||
+      (e = hipHostMalloc((void**)&G->H, sizeof(Inst) * cap, hipHostMallocDefault)) != hipSuccess ||
+      (e = hipHostMalloc((void**)&G->ctrl_h, sizeof(KrylovCtrl) * cap, hipHostMallocDefault)) != hipSuccess ||
+      (e = hipHostMalloc((void**)&G->stat_h, 16 * sizeof(double) * cap, hipHostMallocDefault)) != hipSuccess ||
       (e = hipStreamCreateWithFlags(&G->cap_stream, hipStreamNonBlocking)) != hipSuccess)
     return bail(fail(IPMPDE_EDEVICE, std::string("group setup: ") + hipGetErrorString(e)));
-  std::memset(G->ctrl_h, 0, sizeof(KrylovCtrl) * G->count);
+  std::memset(G->ctrl_h, 0, sizeof(KrylovCtrl) * cap);
+  std::memset(G->stat_h, 0, 16 * sizeof(double) * cap);
+  std::memset((void*)G->H, 0, sizeof(Inst) * cap);  // active = 0
   for (int i = 0; i < G->count; ++i) {
     G->H[i] = probs[i]->I;
     G->H[i].ctrl = G->ctrl_d + i;
@@ -326,6 +384,7 @@ static int group_select(Group* G, const ipmpde_options& o) {
   std::fill(G->maxn, G->maxn + kMaxLev, 0);
   for (int i = 0; i < G->count; ++i) {
     ipmpde_problem* P = G->probs[i];
+    TRY(ensure_work(P));
     TRY(ensure_mg(P, fp32));
     if (o.krylov == IPMPDE_FGMRES) TRY(ensure_fgmres(P, o.restart));
   }
@@ -374,12 +433,17 @@ static int group_select(Group* G, const ipmpde_options& o) {
   return IPMPDE_OK;
 }
 
+// Upload the descriptors.  The copy reads the pinned host array when it
+// executes, not when it is enqueued: the host copies must not be edited
+// again until the stream has been synchronised past it (every caller's next
+// edit follows a read-back that does so, or an explicit wait).
 static int group_sync(Group* G, hipStream_t s) {
-  HIP_TRY(hipMemcpyAsync(G->D, G->H, sizeof(Inst) * G->count, hipMemcpyHostToDevice, s));
+  for (int i = G->count; i < G->zc; ++i) G->H[i].active = 0;
+  HIP_TRY(hipMemcpyAsync(G->D, G->H, sizeof(Inst) * G->zc, hipMemcpyHostToDevice, s));
   return IPMPDE_OK;
 }
 
-static dim3 gz(const Group* G, long nthreads, int y = 1) { return dim3(nblk(std::max(nthreads, 1L)), y, G->count); }
+static dim3 gz(const Group* G, long nthreads, int y = 1) { return dim3(nblk(std::max(nthreads, 1L)), y, G->zc); }
 
 static int read_ctrl(Group* G, hipStream_t s) {
   HIP_TRY(hipMemcpy2DAsync(G->ctrl_h, sizeof(KrylovCtrl), G->ctrl_d, sizeof(KrylovCtrl), offsetof(KrylovCtrl, hcol),
@@ -457,9 +521,9 @@ template <typename T>
 static void launch_coarse(Group* G, int transpose, int guard, hipStream_t s) {
   // each instance takes the kernel it would take alone (the other one
   // returns at once for it), so batched and solo solves round alike
-  if (G->p2) hipLaunchKernelGGL(k_mg_coarse_p2<T>, dim3(1, 1, G->count), dim3(kCoarseBS), G->coarse_lds, s, G->D, guard);
+  if (G->p2) hipLaunchKernelGGL(k_mg_coarse_p2<T>, dim3(1, 1, G->zc), dim3(kCoarseBS), G->coarse_lds, s, G->D, guard);
   if (G->gen)
-    hipLaunchKernelGGL(k_mg_coarse<T>, dim3(1, 1, G->count), dim3(kCoarseBS), G->coarse_lds, s, G->D, transpose, guard);
+    hipLaunchKernelGGL(k_mg_coarse<T>, dim3(1, 1, G->zc), dim3(kCoarseBS), G->coarse_lds, s, G->D, transpose, guard);
 }
 
 // 3D (generic) V-cycle: per level nu_pre sweeps, residual + restriction,
@@ -515,12 +579,12 @@ static void mg_vcycle_2d(Group* G, int transpose, int guard, int scaled, hipStre
   const size_t ldu = 4 * (size_t)up_width(nu_post) * up_width(nu_post) * sizeof(T);
   for (int l = 0; l < G->max_cl; ++l) {
     const int nt = div_up(G->maxN[l + 1], kTC);
-    launch_down2d<T>(nu_pre, dim3(nt, nt, G->count), ldd, s, G->D, l, (l == 0) ? scaled : 0, transpose, guard);
+    launch_down2d<T>(nu_pre, dim3(nt, nt, G->zc), ldd, s, G->D, l, (l == 0) ? scaled : 0, transpose, guard);
   }
   launch_coarse<T>(G, transpose, guard, s);
   for (int l = G->max_cl - 1; l >= 0; --l) {
     const int nt = div_up(G->maxN[l], kTF);
-    launch_up2d<T>(nu_post, dim3(nt, nt, G->count), ldu, s, G->D, l, transpose, guard);
+    launch_up2d<T>(nu_post, dim3(nt, nt, G->zc), ldu, s, G->D, l, transpose, guard);
   }
 }
 
@@ -576,9 +640,15 @@ static int run_minres_chunk(Group* G, const ipmpde_options& o, hipStream_t s) {
     for (int t = 0; t < o.chunk; ++t) minres_iteration<T>(G, (1 + t) & 1, o.krylov_maxit, o.krylov_tol, s);
     return IPMPDE_OK;
   }
-  GraphKey key{G->fp32 ? 1 : 0, o.nu_pre, o.nu_post, o.chunk, o.krylov_maxit, G->count, G->H[0].omega, o.krylov_tol};
+  const int flags = (G->p2 ? 1 : 0) | (G->gen ? 2 : 0) | (G->any_small ? 4 : 0) | (G->outsel << 3);
+  GraphKey key{G->fp32 ? 1 : 0, o.nu_pre, o.nu_post, o.chunk, o.krylov_maxit, G->zc, G->max_n, G->max_nlev,
+               G->max_cl, flags, G->coarse_lds, G->H[0].omega, o.krylov_tol};
   auto it = G->graphs.find(key);
   if (it == G->graphs.end()) {
+    if (G->graphs.size() >= kMaxGraphs) {
+      for (auto& kv : G->graphs) (void)hipGraphExecDestroy(kv.second);
+      G->graphs.clear();
+    }
     hipGraph_t g;
     HIP_TRY(hipStreamBeginCapture(G->cap_stream, hipStreamCaptureModeThreadLocal));
     for (int t = 0; t < o.chunk; ++t) minres_iteration<T>(G, (1 + t) & 1, o.krylov_maxit, o.krylov_tol, G->cap_stream);
@@ -613,7 +683,7 @@ static int minres_group(Group* G, const ipmpde_options& o, hipStream_t s) {
     }
     hipLaunchKernelGGL(k_minres_flush, gz(G, G->max_n), dim3(kBS), 0, s, G->D);
     hipLaunchKernelGGL(k_true_residual, gz(G, G->max_n), dim3(kBS), 0, s, G->D);
-    hipLaunchKernelGGL(k_krylov_mark, dim3(1, 1, G->count), dim3(64), 0, s, G->D, tol, floor_factor(), o.krylov_maxit, 0);
+    hipLaunchKernelGGL(k_krylov_mark, dim3(1, 1, G->zc), dim3(64), 0, s, G->D, tol, floor_factor(), o.krylov_maxit, 0);
     HIP_TRY(hipGetLastError());
     TRY(read_ctrl(G, s));
     if (!any_restart(G)) return IPMPDE_OK;
@@ -638,11 +708,11 @@ static void fgmres_step(Group* G, int pt, int j, double tol, int maxit, hipStrea
   hipLaunchKernelGGL(k_fg_matvec, gz(G, G->max_n), dim3(kBS), 0, s, G->D, j);
   const int nbm = fg_multidot_blocks(n4);
   for (int pass = 0; pass < 2; ++pass) {
-    hipLaunchKernelGGL(k_fg_multidot, dim3(nbm, j + 1, G->count), dim3(kBS), 0, s, G->D, j);
-    hipLaunchKernelGGL(k_fg_multidot_final, dim3(1, 1, G->count), dim3(kBS), 0, s, G->D, j + 1, nbm, pass == 0 ? 1 : 0);
+    hipLaunchKernelGGL(k_fg_multidot, dim3(nbm, j + 1, G->zc), dim3(kBS), 0, s, G->D, j);
+    hipLaunchKernelGGL(k_fg_multidot_final, dim3(1, 1, G->zc), dim3(kBS), 0, s, G->D, j + 1, nbm, pass == 0 ? 1 : 0);
     hipLaunchKernelGGL(k_fg_orth, gz(G, n4), dim3(kBS), 0, s, G->D, j);
   }
-  hipLaunchKernelGGL(k_fg_norm_givens, dim3(nbm, 1, G->count), dim3(kBS), 0, s, G->D, j, tol, maxit);
+  hipLaunchKernelGGL(k_fg_norm_givens, dim3(nbm, 1, G->zc), dim3(kBS), 0, s, G->D, j, tol, maxit);
   hipLaunchKernelGGL(k_fg_normalize, gz(G, n4), dim3(kBS), 0, s, G->D, j);
 }
 
@@ -655,7 +725,7 @@ static int fgmres_group(Group* G, const ipmpde_options& o, hipStream_t s) {
   hipLaunchKernelGGL(k_krylov_begin, gz(G, n4), dim3(kBS), 0, s, G->D);
   for (int cycle = 0; cycle < 1000; ++cycle) {
     const int src = cycle == 0 ? 0 : 1;
-    hipLaunchKernelGGL(k_fg_start_norm, dim3(nbm, 1, G->count), dim3(kBS), 0, s, G->D, src);
+    hipLaunchKernelGGL(k_fg_start_norm, dim3(nbm, 1, G->zc), dim3(kBS), 0, s, G->D, src);
     hipLaunchKernelGGL(k_fg_start_scale, gz(G, n4), dim3(kBS), 0, s, G->D, src);
     TRY(read_ctrl(G, s));
     for (int j0 = 0; j0 < o.restart && any_running(G); j0 += step) {
@@ -663,10 +733,10 @@ static int fgmres_group(Group* G, const ipmpde_options& o, hipStream_t s) {
       HIP_TRY(hipGetLastError());
       TRY(read_ctrl(G, s));
     }
-    hipLaunchKernelGGL(k_fg_solve_small, dim3(1, 1, G->count), dim3(64), 0, s, G->D);
+    hipLaunchKernelGGL(k_fg_solve_small, dim3(1, 1, G->zc), dim3(64), 0, s, G->D);
     hipLaunchKernelGGL(k_fg_update_x, gz(G, n4), dim3(kBS), 0, s, G->D);
     hipLaunchKernelGGL(k_true_residual, gz(G, G->max_n), dim3(kBS), 0, s, G->D);
-    hipLaunchKernelGGL(k_krylov_mark, dim3(1, 1, G->count), dim3(64), 0, s, G->D, o.krylov_tol, floor_factor(),
+    hipLaunchKernelGGL(k_krylov_mark, dim3(1, 1, G->zc), dim3(64), 0, s, G->D, o.krylov_tol, floor_factor(),
                        o.krylov_maxit, 1);
     HIP_TRY(hipGetLastError());
     TRY(read_ctrl(G, s));
@@ -706,6 +776,7 @@ static int newton_setup_group(Group* G, const ipmpde_options& o, hipStream_t s) 
   for (int i = 0; i < G->count; ++i) {
     G->probs[i]->setup_done = true;
     G->probs[i]->setup_fp32 = G->fp32 ? 1 : 0;
+    G->probs[i]->setup_group = G;
   }
   return IPMPDE_OK;
 }
@@ -735,11 +806,73 @@ static int group_reset(Group* G, const std::vector<ipmpde_options>& po, hipStrea
     G->H[i].mu = po[i].mu0;
     G->H[i].alpha0 = po[i].alpha0;
     G->probs[i]->mu = po[i].mu0;
+    G->probs[i]->need_init = false;
   }
   TRY(group_sync(G, s));
   hipLaunchKernelGGL(k_init_state, gz(G, G->max_n), dim3(kBS), 0, s, G->D);
   HIP_TRY(hipGetLastError());
   return IPMPDE_OK;
+}
+
+// Per-instance bookkeeping of Algorithm A.1, shared by the lockstep batch
+// solve and the serving engine so that both take identical decisions.
+
+static void ipm_begin(ipmpde_problem* P) {
+  std::memset(&P->stats, 0, sizeof(P->stats));
+  P->stats.status = IPMPDE_ENOTCONVERGED;
+}
+
+// After the measures of iterate k (slot i of G): record them and return the
+// final status, or -1 to go on (mu is then reduced for the next step).
+static int ipm_check(Group* G, int i, int k, const ipmpde_options& oi) {
+  ipmpde_problem* P = G->probs[i];
+  ipmpde_stats& st = P->stats;
+  const double xp = G->stat_h[16 * i], xd = G->stat_h[16 * i + 1], xc = G->stat_h[16 * i + 2];
+  if (k < IPMPDE_MAX_HIST) {
+    st.hist_mu[k] = P->mu;
+    st.hist_xi_p[k] = xp;
+    st.hist_xi_d[k] = xd;
+    st.hist_xi_c[k] = xc;
+    st.hist_len = k + 1;
+  }
+  st.nli = k;
+  st.xi_p = xp; st.xi_d = xd; st.xi_c = xc; st.mu = P->mu;
+  int finish = -1;
+  if (!(xp == xp && xd == xd && xc == xc)) finish = IPMPDE_EBREAKDOWN;
+  else if (oi.fixed_nli > 0 ? k >= oi.fixed_nli : (xp <= oi.eps_p && xd <= oi.eps_d && xc <= oi.eps_c))
+    finish = IPMPDE_OK;
+  else if (k >= oi.ipm_maxit) finish = IPMPDE_ENOTCONVERGED;
+  if (finish >= 0) {
+    st.status = finish;
+    G->H[i].active = 0;
+  } else {
+    P->mu *= oi.sigma;
+    G->H[i].mu = P->mu;
+  }
+  return finish;
+}
+
+// After Newton step k of slot i: record it; returns the final status on a
+// breakdown (NaN or collapsed step), else -1.
+static int ipm_after_step(Group* G, int i, int k) {
+  ipmpde_stats& st = G->probs[i]->stats;
+  const double aP = G->stat_h[16 * i + 3], aD = G->stat_h[16 * i + 4];
+  const KrylovCtrl& C = G->ctrl_h[i];
+  if (k < IPMPDE_MAX_HIST) {
+    st.hist_krylov[k] = C.its_total;
+    st.hist_krylov_relres[k] = C.relres;
+    st.hist_alpha_p[k] = aP;
+    st.hist_alpha_d[k] = aD;
+  }
+  st.krylov_its += C.its_total;
+  const int kst = krylov_status(G, i);
+  if (kst == IPMPDE_EKRYLOV) st.krylov_fail += 1;
+  if (kst == IPMPDE_EBREAKDOWN || !(aP > 1e-10 && aD > 1e-10)) {
+    st.status = IPMPDE_EBREAKDOWN;
+    G->H[i].active = 0;
+    return IPMPDE_EBREAKDOWN;
+  }
+  return -1;
 }
 
 // Algorithm A.1 on every instance of the group, in lockstep; each instance
@@ -749,11 +882,7 @@ static int group_reset(Group* G, const std::vector<ipmpde_options>& po, hipStrea
 static int solve_group(Group* G, const std::vector<ipmpde_options>& po, hipStream_t s) {
   auto t0 = std::chrono::steady_clock::now();
   const ipmpde_options& o = po[0];
-  for (int i = 0; i < G->count; ++i) {
-    ipmpde_stats& st = G->probs[i]->stats;
-    std::memset(&st, 0, sizeof(st));
-    st.status = IPMPDE_ENOTCONVERGED;
-  }
+  for (int i = 0; i < G->count; ++i) ipm_begin(G->probs[i]);
   TRY(group_select(G, o));
   TRY(group_reset(G, po, s));
   std::vector<int> done(G->count, 0);
@@ -762,52 +891,13 @@ static int solve_group(Group* G, const std::vector<ipmpde_options>& po, hipStrea
     int alive = 0;
     for (int i = 0; i < G->count; ++i) {
       if (done[i]) continue;
-      ipmpde_problem* P = G->probs[i];
-      ipmpde_stats& st = P->stats;
-      const double xp = G->stat_h[16 * i], xd = G->stat_h[16 * i + 1], xc = G->stat_h[16 * i + 2];
-      st.hist_mu[k] = P->mu;
-      st.hist_xi_p[k] = xp;
-      st.hist_xi_d[k] = xd;
-      st.hist_xi_c[k] = xc;
-      st.hist_len = k + 1;
-      st.nli = k;
-      st.xi_p = xp; st.xi_d = xd; st.xi_c = xc; st.mu = P->mu;
-      const ipmpde_options& oi = po[i];
-      int finish = -1;
-      if (!(xp == xp && xd == xd && xc == xc)) finish = IPMPDE_EBREAKDOWN;
-      else if (oi.fixed_nli > 0 ? k >= oi.fixed_nli : (xp <= oi.eps_p && xd <= oi.eps_d && xc <= oi.eps_c))
-        finish = IPMPDE_OK;
-      else if (k >= oi.ipm_maxit) finish = IPMPDE_ENOTCONVERGED;
-      if (finish >= 0) {
-        st.status = finish;
-        done[i] = 1;
-        G->H[i].active = 0;
-      } else {
-        ++alive;
-        P->mu *= oi.sigma;
-        G->H[i].mu = P->mu;
-      }
+      if (ipm_check(G, i, k, po[i]) >= 0) done[i] = 1;
+      else ++alive;
     }
     if (!alive) break;
     TRY(group_step(G, o, s));
-    for (int i = 0; i < G->count; ++i) {
-      if (done[i]) continue;
-      ipmpde_stats& st = G->probs[i]->stats;
-      const double aP = G->stat_h[16 * i + 3], aD = G->stat_h[16 * i + 4];
-      const KrylovCtrl& C = G->ctrl_h[i];
-      st.hist_krylov[k] = C.its_total;
-      st.hist_krylov_relres[k] = C.relres;
-      st.hist_alpha_p[k] = aP;
-      st.hist_alpha_d[k] = aD;
-      st.krylov_its += C.its_total;
-      const int kst = krylov_status(G, i);
-      if (kst == IPMPDE_EKRYLOV) st.krylov_fail += 1;
-      if (kst == IPMPDE_EBREAKDOWN || !(aP > 1e-10 && aD > 1e-10)) {
-        st.status = IPMPDE_EBREAKDOWN;
-        done[i] = 1;
-        G->H[i].active = 0;
-      }
-    }
+    for (int i = 0; i < G->count; ++i)
+      if (!done[i] && ipm_after_step(G, i, k) >= 0) done[i] = 1;
   }
   const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   for (int i = 0; i < G->count; ++i) G->probs[i]->stats.solve_ms = ms;
@@ -866,19 +956,29 @@ extern "C" int ipmpde_set_allocator(ipmpde_alloc_fn a, ipmpde_free_fn f, void* c
   return IPMPDE_OK;
 }
 
+// Device bytes a problem holds while it is solved: its data, iterates and
+// barrier diagonals for the handle's lifetime, plus the workspace of the
+// Newton solves (Krylov vectors, multigrid levels of the chosen precision,
+// FGMRES basis, reduction partials).  Mirrors the allocations one by one.
 extern "C" size_t ipmpde_footprint_bytes(const ipmpde_grid* grid, const ipmpde_pde* pde, int has_y,
                                          const ipmpde_options* opts) {
-  if (!grid || !pde) return 0;
+  if (!grid || !pde || (grid->dim != 2 && grid->dim != 3) || !is_pow2m1(grid->n)) return 0;
   ipmpde_options o;
   if (opts) o = *opts;
   else ipmpde_default_options(&o);
-  const size_t n = pow_dim(grid->n, grid->dim);
-  size_t fields = 6 + 8 + 4 + (has_y ? 4 : 0);  // data, iterates, diagonals
-  size_t words = fields * n + 4 * n * 14;        // Newton rhs and the Krylov vectors
-  if (o.krylov == IPMPDE_FGMRES) words += 4 * n * (2 * (size_t)o.restart + 1);
+  const size_t n = pow_dim(grid->n, grid->dim), n4 = 4 * n;
+  auto A = [](size_t b) { return std::max<size_t>(b, 256); };
+  const size_t arrays = 16 + (has_y ? 4 : 0);  // bounds, y_d, f_hat, iterates, multipliers, diagonals
+  size_t bytes = arrays * A(n * 8) + A(kTicketStride * (kTicketGroups + 1) * sizeof(unsigned));
+  bytes += kKrylovVecs * A(n4 * 8) + A((size_t)partials_words(nblk((long)n)) * 8);
   const size_t el = o.mg_precision == IPMPDE_FP32 ? 4 : 8;
-  const double lvl = grid->dim == 2 ? 4.0 / 3.0 : 8.0 / 7.0;
-  return words * 8 + (size_t)(4 * el * n * lvl) + (1 << 20);
+  for (int N = grid->n;; N = (N - 1) / 2) {
+    bytes += 4 * A(pow_dim(N, grid->dim) * el);
+    if (N <= 1) break;
+  }
+  bytes += A(kMaxLev * sizeof(Level));
+  if (o.krylov == IPMPDE_FGMRES) bytes += A((size_t)(o.restart + 1) * n4 * 8) + A((size_t)o.restart * n4 * 8);
+  return bytes;
 }
 
 static void problem_free(ipmpde_problem* P) {
@@ -952,13 +1052,7 @@ extern "C" int ipmpde_problem_create(const ipmpde_grid* grid, const ipmpde_pde* 
     return cleanup(rc);
   if (P->has_y && ((rc = A(&I.lya)) || (rc = A(&I.lyb)))) return cleanup(rc);
   I.ua = ua; I.ub = ub; I.ya = ya; I.yb = yb; I.yd = yd; I.fhat = fh;
-  const size_t n4 = 4 * n;
-  double** vecs[] = {&I.rhs, &I.X, &I.Q, &I.R, &I.Rt, &I.V[0], &I.V[1], &I.Z[0], &I.Z[1], &I.W[0], &I.W[1],
-                     &I.KW[0], &I.KW[1]};
-  for (double** v : vecs)
-    if ((rc = M.alloc_t(v, n4))) return cleanup(rc);
-  if ((rc = ensure_partials(P, nblk((long)n))) || (rc = M.alloc_t(&I.counter, kTicketStride * (kTicketGroups + 1))))
-    return cleanup(rc);
+  if ((rc = M.alloc_t(&I.counter, kTicketStride * (kTicketGroups + 1)))) return cleanup(rc);
   auto hip_fail = [&](hipError_t e, const char* what) {
     return cleanup(fail(IPMPDE_EDEVICE, std::string(what) + ": " + hipGetErrorString(e)));
   };
@@ -967,8 +1061,6 @@ extern "C" int ipmpde_problem_create(const ipmpde_grid* grid, const ipmpde_pde* 
     return hip_fail(e, "hipMemset");
   for (int k = 0; k < nd; ++k)
     if ((e = hipMemset(dev[k], 0, n * sizeof(double))) != hipSuccess) return hip_fail(e, "hipMemset");
-  for (double** v : vecs)
-    if ((e = hipMemset(*v, 0, n4 * sizeof(double))) != hipSuccess) return hip_fail(e, "hipMemset");
   if ((e = hipMemcpy(ua, u_a, n * 8, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(e, "hipMemcpy");
   if ((e = hipMemcpy(ub, u_b, n * 8, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(e, "hipMemcpy");
   if ((e = hipMemcpy(yd, y_d, n * 8, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(e, "hipMemcpy");
@@ -977,12 +1069,6 @@ extern "C" int ipmpde_problem_create(const ipmpde_grid* grid, const ipmpde_pde* 
     if ((e = hipMemcpy(ya, y_a, n * 8, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(e, "hipMemcpy");
     if ((e = hipMemcpy(yb, y_b, n * 8, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(e, "hipMemcpy");
   }
-  if ((rc = ensure_mg(P, true)) != IPMPDE_OK) return cleanup(rc);
-  if ((rc = group_create({P}, &P->self)) != IPMPDE_OK) return cleanup(rc);
-  ipmpde_options o;
-  ipmpde_default_options(&o);
-  if ((rc = group_select(P->self, o)) != IPMPDE_OK) return cleanup(rc);
-  if ((rc = group_reset(P->self, {o}, nullptr)) != IPMPDE_OK) return cleanup(rc);
   if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "init");
   *out = P;
   return IPMPDE_OK;
@@ -1000,6 +1086,22 @@ extern "C" void ipmpde_problem_destroy(ipmpde_problem* P) {
 
 static hipStream_t S(ipmpde_stream s) { return (hipStream_t)s; }
 
+// The group of one behind the single-problem entry points, created on first
+// use; a problem that has not been solved or reset yet is put at the
+// starting point first (default options).
+static int ensure_self(ipmpde_problem* P, hipStream_t s) {
+  if (P->in_engine) return fail(IPMPDE_EINVAL, "problem is queued or running in an engine");
+  if (!P->self) TRY(group_create({P}, 1, P->dim, &P->self));
+  if (P->need_init) {
+    ipmpde_options o;
+    ipmpde_default_options(&o);
+    TRY(group_select(P->self, o));
+    TRY(group_reset(P->self, {o}, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  return IPMPDE_OK;
+}
+
 static int status_error(int st) {
   if (st == IPMPDE_ENOTCONVERGED) return fail(st, "IPM iteration limit reached");
   if (st == IPMPDE_EBREAKDOWN) return fail(st, "breakdown: NaN in the iterates or a collapsed step length");
@@ -1010,6 +1112,7 @@ extern "C" int ipmpde_solve(ipmpde_problem* P, const ipmpde_options* opts, ipmpd
   if (!P) return fail(IPMPDE_EINVAL, "problem is NULL");
   ipmpde_options o;
   TRY(resolve_opts(opts, &o));
+  TRY(ensure_self(P, S(stream)));
   TRY(solve_group(P->self, {o}, S(stream)));
   return status_error(P->stats.status);
 }
@@ -1018,6 +1121,7 @@ extern "C" int ipmpde_reset(ipmpde_problem* P, const ipmpde_options* opts, ipmpd
   if (!P) return fail(IPMPDE_EINVAL, "problem is NULL");
   ipmpde_options o;
   TRY(resolve_opts(opts, &o));
+  TRY(ensure_self(P, S(stream)));
   TRY(group_select(P->self, o));
   return group_reset(P->self, {o}, S(stream));
 }
@@ -1025,6 +1129,7 @@ extern "C" int ipmpde_reset(ipmpde_problem* P, const ipmpde_options* opts, ipmpd
 // One Newton setup + Krylov solve of the single-problem group at barrier mu_new.
 static int single_newton(ipmpde_problem* P, const ipmpde_options& o, double mu_new, hipStream_t s, int* its,
                          double* relres) {
+  TRY(ensure_self(P, s));
   Group* G = P->self;
   G->H[0].active = 1;
   G->H[0].mu = mu_new;
@@ -1066,6 +1171,7 @@ extern "C" int ipmpde_newton_setup(ipmpde_problem* P, const ipmpde_options* opts
   if (!(mu_new > 0)) return fail(IPMPDE_EINVAL, "mu_new must be positive");
   ipmpde_options o;
   TRY(resolve_opts(opts, &o));
+  TRY(ensure_self(P, S(stream)));
   Group* G = P->self;
   G->H[0].active = 1;
   G->H[0].mu = mu_new;
@@ -1088,6 +1194,7 @@ extern "C" int ipmpde_newton_direction(ipmpde_problem* P, const ipmpde_options* 
 
 extern "C" int ipmpde_measures(ipmpde_problem* P, ipmpde_stream stream, double* xp, double* xd, double* xc) {
   if (!P || !xp || !xd || !xc) return fail(IPMPDE_EINVAL, "NULL argument");
+  TRY(ensure_self(P, S(stream)));
   Group* G = P->self;
   G->H[0].active = 1;
   TRY(group_measures(G, S(stream)));
@@ -1137,6 +1244,11 @@ extern "C" int ipmpde_query(const ipmpde_problem* P, int field, double* out, siz
   int kind;
   const double* src = field_ptr(P, field, &kind);
   if (kind < 0) return fail(IPMPDE_EINVAL, "unknown field");
+  if (P->in_engine) return fail(IPMPDE_EINVAL, "problem is queued or running in an engine");
+  if (P->need_init) TRY(ensure_self((ipmpde_problem*)P, nullptr));
+  src = field_ptr(P, field, &kind);
+  if (field >= IPMPDE_FIELD_DY && field <= IPMPDE_FIELD_DP && !src)
+    return fail(IPMPDE_EINVAL, "no Newton direction (workspace released)");
   HIP_TRY(hipDeviceSynchronize());
   if (kind == 1) {
     std::vector<double> v(count);
@@ -1157,6 +1269,7 @@ extern "C" int ipmpde_set_field(ipmpde_problem* P, int field, const double* in, 
         (field >= IPMPDE_FIELD_LAM_YA && field <= IPMPDE_FIELD_LAM_VB)))
     return fail(IPMPDE_EINVAL, "field is not an iterate");
   TRY(validate_array(in, count, "field"));
+  TRY(ensure_self(P, nullptr));
   int kind;
   double* dst = (double*)field_ptr(P, field, &kind);
   if (!dst) return fail(IPMPDE_EINVAL, "field not present (no state bounds)");
@@ -1168,6 +1281,7 @@ extern "C" int ipmpde_set_field(ipmpde_problem* P, int field, const double* in, 
 extern "C" int ipmpde_query_rhs(const ipmpde_problem* P, double* out, size_t count) {
   if (!P || !out) return fail(IPMPDE_EINVAL, "NULL argument");
   if (count != 4 * (size_t)P->n) return fail(IPMPDE_EINVAL, "count must equal 4 n");
+  if (!P->I.rhs) return fail(IPMPDE_EINVAL, "no Newton right-hand side (workspace not allocated)");
   HIP_TRY(hipDeviceSynchronize());
   HIP_TRY(hipMemcpy(out, P->I.rhs, count * 8, hipMemcpyDeviceToHost));
   return IPMPDE_OK;
@@ -1176,6 +1290,7 @@ extern "C" int ipmpde_query_rhs(const ipmpde_problem* P, double* out, size_t cou
 extern "C" int ipmpde_apply_operator(const ipmpde_problem* P, int transpose, const double* x, double* y,
                                      ipmpde_stream stream) {
   if (!P || !x || !y) return fail(IPMPDE_EINVAL, "NULL argument");
+  TRY(ensure_self((ipmpde_problem*)P, S(stream)));
   Group* G = P->self;
   G->H[0].active = 1;
   TRY(group_sync(G, S(stream)));
@@ -1186,7 +1301,7 @@ extern "C" int ipmpde_apply_operator(const ipmpde_problem* P, int transpose, con
 
 extern "C" int ipmpde_apply_saddle(ipmpde_problem* P, const double* x, double* y, ipmpde_stream stream) {
   if (!P || !x || !y) return fail(IPMPDE_EINVAL, "NULL argument");
-  if (!P->setup_done) return fail(IPMPDE_EINVAL, "no Newton setup yet");
+  if (!P->setup_done || !P->self || P->setup_group != P->self) return fail(IPMPDE_EINVAL, "no Newton setup yet");
   Group* G = P->self;
   hipLaunchKernelGGL(k_saddle, gz(G, P->n), dim3(kBS), 0, S(stream), G->D, x, y);
   HIP_TRY(hipGetLastError());
@@ -1198,7 +1313,7 @@ extern "C" int ipmpde_apply_precond(ipmpde_problem* P, const ipmpde_options* opt
   if (!P || !x || !y) return fail(IPMPDE_EINVAL, "NULL argument");
   ipmpde_options o;
   TRY(resolve_opts(opts, &o));
-  if (!P->setup_done || P->setup_fp32 != (o.mg_precision == IPMPDE_FP32))
+  if (!P->setup_done || !P->self || P->setup_group != P->self || P->setup_fp32 != (o.mg_precision == IPMPDE_FP32))
     return fail(IPMPDE_EINVAL, "no Newton setup for this multigrid precision");
   Group* G = P->self;
   TRY(group_select(G, o));
@@ -1228,8 +1343,10 @@ extern "C" int ipmpde_batch_create(ipmpde_problem* const* probs, int count, ipmp
     for (int j = 0; j < i; ++j)
       if (v[j] == v[i]) return fail(IPMPDE_EINVAL, "a problem appears twice in the batch");
   }
+  for (int i = 0; i < count; ++i)
+    if (v[i]->in_engine) return fail(IPMPDE_EINVAL, "a problem of the batch is queued or running in an engine");
   ipmpde_batch* B = new ipmpde_batch();
-  const int rc = group_create(v, &B->G);
+  const int rc = group_create(v, count, v[0]->dim, &B->G);
   if (rc != IPMPDE_OK) { delete B; return rc; }
   *out = B;
   return IPMPDE_OK;
@@ -1257,4 +1374,5 @@ extern "C" int ipmpde_batch_solve(ipmpde_batch* B, const ipmpde_options* opts, i
   return solve_group(G, po, S(stream));
 }
 
+#include "engine.hip"
 #include "timing.hip"

@@ -24,7 +24,7 @@ extern "C" int ipmpde_time_kernel(ipmpde_problem* P, const ipmpde_options* opts,
   if (reps < 1 || reps > 100000) return fail(IPMPDE_EINVAL, "reps out of range");
   ipmpde_options o;
   TRY(resolve_opts(opts, &o));
-  if (!P->setup_done || P->setup_fp32 != (o.mg_precision == IPMPDE_FP32))
+  if (!P->setup_done || !P->self || P->setup_group != P->self || P->setup_fp32 != (o.mg_precision == IPMPDE_FP32))
     return fail(IPMPDE_EINVAL, "no Newton setup for this multigrid precision");
   if ((kernel == 3 || kernel == 4 || kernel == 5) && (P->dim != 2 || P->nlev < 2))
     return fail(IPMPDE_EINVAL, "the fused level kernels exist for 2D grids with at least two levels");

@@ -103,3 +103,39 @@ def test_footprint_grows_with_grid(lib):
     lib.ipmpde_default_options(C.byref(o))
     f = lambda N: lib.ipmpde_footprint_bytes(C.byref(L.Grid(2, N)), C.byref(L.Pde(L.POISSON, 1.0)), 1, C.byref(o))
     assert f(511) > 3.5 * f(255) > 0
+
+
+def test_engine_argument_checks(lib):
+    h = C.c_void_p()
+    assert lib.ipmpde_engine_create(0, 4, C.byref(h)) == L.EINVAL
+    assert lib.ipmpde_engine_create(1 << 30, 0, C.byref(h)) == L.EINVAL
+    assert lib.ipmpde_engine_create(1 << 30, 5000, C.byref(h)) == L.EINVAL
+    assert lib.ipmpde_engine_create(1 << 30, 4, None) == L.EINVAL
+    assert lib.ipmpde_engine_create(1 << 30, 4, C.byref(h)) == L.OK and h.value
+    info = L.RequestInfo()
+    assert lib.ipmpde_engine_poll(h, C.c_uint64(7), C.byref(info)) == L.EINVAL
+    assert lib.ipmpde_engine_release(h, C.c_uint64(7)) == L.EINVAL
+    ei = L.EngineInfo()
+    assert lib.ipmpde_engine_get_info(h, C.byref(ei)) == L.OK
+    assert (ei.running, ei.queued, ei.bytes_in_use, ei.budget_bytes) == (0, 0, 0, 1 << 30)
+    t = C.c_uint64()
+    assert lib.ipmpde_engine_submit(h, None, None, C.byref(t)) == L.EINVAL
+    assert lib.ipmpde_engine_step(None, None, None, None) == L.EINVAL
+    lib.ipmpde_engine_destroy(h)
+    lib.ipmpde_engine_destroy(None)
+
+
+def test_footprint_counts_fgmres_basis_and_precision(lib):
+    o = L.COptions()
+    lib.ipmpde_default_options(C.byref(o))
+    g, pd = L.Grid(2, 255), L.Pde(L.CONVDIFF, 0.005)
+    base = lib.ipmpde_footprint_bytes(C.byref(g), C.byref(pd), 0, C.byref(o))
+    o.krylov = L.FGMRES
+    fg = lib.ipmpde_footprint_bytes(C.byref(g), C.byref(pd), 0, C.byref(o))
+    n4 = 4 * 255 * 255
+    assert fg - base == 8 * n4 * (2 * o.restart + 1)
+    o.krylov = L.MINRES
+    o.mg_precision = L.FP64
+    f64 = lib.ipmpde_footprint_bytes(C.byref(g), C.byref(pd), 0, C.byref(o))
+    assert f64 > base
+    assert lib.ipmpde_footprint_bytes(C.byref(L.Grid(2, 100)), C.byref(pd), 0, None) == 0
