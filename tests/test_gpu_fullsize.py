@@ -9,7 +9,7 @@ pytestmark = pytest.mark.gpu
 
 import workloads as W  # noqa: E402
 from oracle.fd import discretize  # noqa: E402
-from oracle.ipm import IPMOptions, IPMState, ipm_step, measures  # noqa: E402
+from oracle.ipm import IPMOptions, IPMState, ipm_step, measures, newton_matrix, newton_rhs  # noqa: E402
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -35,6 +35,10 @@ def _rel(a, b):
     ("poisson2d_511", {}, {}),
     ("convdiff2d_255", {}, {"krylov": "fgmres", "precond": "pt"}),
     ("poisson3d_127", {"N": 63}, {}),
+    ("poisson3d_127", {"beta": 1e-4}, {}),
+    ("poisson3d_127", {"beta": 1e-3}, {}),
+    ("poisson3d_127", {"beta": 1e-2}, {}),
+    ("poisson3d_127", {"beta": 1e-1}, {}),
 ])
 def test_final_iterate_kkt_certificate(name, kw, opts_kw):
     """The GPU's final iterate satisfies the stopping test (Algorithm A.1, inf-norms of
@@ -81,3 +85,63 @@ def test_ipm_step_parity_at_511():
     for f in ("y", "w", "v", "p", "lwa", "lwb", "lva", "lvb", "lya", "lyb"):
         a, b = getattr(st1, f), getattr(ref, f)
         assert _rel(a, b) <= 1e-6, (f, _rel(a, b))
+
+
+@pytest.mark.parametrize("name,opts_kw", [
+    ("poisson2d_511", {}),
+    ("poisson2d_511", {"krylov": "fgmres", "precond": "pt"}),
+    ("convdiff2d_255", {"krylov": "fgmres", "precond": "pt"}),
+    ("convdiff2d_255", {}),
+    ("poisson3d_127", {}),
+])
+def test_newton_direction_solves_oracle_system(name, opts_kw):
+    """At the full sizes, from a mid-solve GPU state: the GPU Newton direction
+    solves the oracle's own sparse FP64 system (eq. (NewtonSystem), assembled on
+    the CPU from the same state) to the Krylov tolerance 1e-10, or to the FP64
+    attainable-accuracy floor 16 eps |(|K||x| + |b|)| / |b| where that is larger."""
+    from paper_1806_05896_amd import Options, Problem
+    data = W.by_name(name, seed=0)
+    opts = Options(sigma=data.sigma, **opts_kw)
+    print(f"[newton-full] {name} {opts_kw}", flush=True)
+    with Problem(data) as prob:
+        mu = 1.0
+        for _ in range(3):
+            mu *= data.sigma
+            prob.ipm_step(mu, opts)
+        st = _state_from_gpu(prob, data.y_a is not None, mu)
+        mu *= data.sigma
+        info = prob.newton_direction(mu, opts)
+        dx = np.concatenate([prob.query(f) for f in ("dy", "dw", "dv", "dp")])
+    disc = discretize(data)
+    K = newton_matrix(data, disc, st).tocsr()
+    b = newton_rhs(data, disc, st, mu)
+    res = np.linalg.norm(b - K @ dx) / np.linalg.norm(b)
+    floor = 16 * np.finfo(float).eps * np.linalg.norm(abs(K) @ np.abs(dx) + np.abs(b)) / np.linalg.norm(b)
+    print(f"  its={info['krylov_its']} rel residual {res:.2e} (gpu {info['relres']:.2e}, floor {floor:.2e})",
+          flush=True)
+    assert res <= max(1e-10, floor) * 1.01
+
+
+def test_ipm_step_parity_convdiff_255():
+    """One IPM step of the convection-diffusion workload (FGMRES + P_T) from a
+    mid-solve GPU state against the oracle's step (SuperLU) from the same state."""
+    from paper_1806_05896_amd import Options, Problem
+    data = W.convdiff2d_255(seed=0)
+    opts = Options(sigma=data.sigma, krylov="fgmres", precond="pt")
+    print("[step255cd] GPU steps", flush=True)
+    with Problem(data) as prob:
+        mu = 1.0
+        for _ in range(5):
+            mu *= data.sigma
+            prob.ipm_step(mu, opts)
+        st0 = _state_from_gpu(prob, False, mu)
+        mu *= data.sigma
+        info = prob.ipm_step(mu, opts)
+        st1 = _state_from_gpu(prob, False, mu)
+    disc = discretize(data)
+    ref, rinfo = ipm_step(data, disc, st0, IPMOptions(sigma=data.sigma), mu, "schur")
+    print(f"  gpu alpha_P={info['alpha_P']:.6f} oracle {rinfo['alpha_P']:.6f}", flush=True)
+    assert abs(info["alpha_P"] - rinfo["alpha_P"]) <= 1e-6 and abs(info["alpha_D"] - rinfo["alpha_D"]) <= 1e-6
+    for f in ("y", "w", "v", "p", "lwa", "lwb", "lva", "lvb"):
+        a, r = getattr(st1, f), getattr(ref, f)
+        assert _rel(a, r) <= 1e-6, (f, _rel(a, r))
