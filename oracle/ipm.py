@@ -35,6 +35,16 @@ Readings taken where the paper is silent, garbled or ambiguous:
   R7  primal variables (y, z) move with alpha_P, dual ones (p, lambdas) with
       alpha_D, as Algorithm A.1 states.
   R8  "no state bounds" means the lambda_y blocks are absent and Theta_y = 0.
+
+Option beyond the paper (off by default): mu_rule = "central" takes the
+barrier target from the current iterate, mu^{k+1} = sigma * (mean of the
+complementarity products of eq. (gap) at mu = 0), the duality measure of the
+path-following scheme Algorithm A.1 cites, instead of sigma mu^k.  On the
+central path (all products equal mu^k) the two coincide; when the step
+lengths collapse the fixed geometric decrease runs ahead of the iterate and
+the method can stall or lose interiority, which the iterate-based target
+avoids.  A breakdown (a bound gap or product that is no longer positive and
+finite, or a singular Newton matrix) ends solve() with status "breakdown".
 """
 from __future__ import annotations
 
@@ -59,6 +69,7 @@ class IPMOptions:
     maxit: int = 200
     fixed_nli: int = 0          # > 0: take exactly this many Newton steps
     newton: str = "auto"        # "full" (4n system) | "schur" (eliminated, SPD in dp) | "auto"
+    mu_rule: str = "paper"      # "paper": mu^{k+1} = sigma mu^k | "central": sigma * mean product
 
 
 @dataclass
@@ -145,6 +156,22 @@ def residuals(prob, disc: Discretization, st: IPMState):
 def measures(prob, disc, st):
     xp, xd, xc = residuals(prob, disc, st)
     return float(np.abs(xp).max()), float(np.abs(xd).max()), float(np.abs(xc).max())
+
+
+def complementarity_mean(prob, disc, st) -> float:
+    """Mean of the complementarity products (eq. (gap) with mu = 0) over every
+    finite bound: the duality measure of the iterate."""
+    return float(residuals(prob, disc, st)[2].mean())
+
+
+def next_mu(prob, disc, st, opts: "IPMOptions") -> float:
+    """Barrier target of the next Newton step (Algorithm A.1, or the
+    iterate-based target of mu_rule = "central")."""
+    if opts.mu_rule == "central":
+        return opts.sigma * complementarity_mean(prob, disc, st)
+    if opts.mu_rule != "paper":
+        raise ValueError(opts.mu_rule)
+    return opts.sigma * st.mu
 
 
 def barrier_diagonals(prob, st: IPMState):
@@ -312,8 +339,18 @@ def solve(prob, opts: Optional[IPMOptions] = None) -> IPMResult:
         if k >= opts.maxit:
             hist.append(rec)
             break
-        mu_new = opts.sigma * st.mu
-        st, info = ipm_step(prob, disc, st, opts, mu_new, opts.newton)
+        prods = residuals(prob, disc, st)[2]
+        if not (np.isfinite(xp) and np.isfinite(xd) and np.all(np.isfinite(prods)) and prods.min() > 0):
+            hist.append(rec)
+            status = "breakdown"
+            break
+        mu_new = next_mu(prob, disc, st, opts)
+        try:
+            st, info = ipm_step(prob, disc, st, opts, mu_new, opts.newton)
+        except RuntimeError:  # singular Newton matrix
+            hist.append(rec)
+            status = "breakdown"
+            break
         rec.update(alpha_P=info["alpha_P"], alpha_D=info["alpha_D"])
         hist.append(rec)
         k += 1

@@ -206,8 +206,9 @@ def test_beta_zero_single_mode_closed_form():
     np.testing.assert_allclose(r.p, p.alpha * lam * y, rtol=0, atol=1e-8 * np.abs(lam * y).max())
 
 
+@pytest.mark.parametrize("mu_rule", ["paper", "central"])
 @pytest.mark.parametrize("pde", ["poisson", "convdiff"])
-def test_matches_proximal_gradient_on_small_grid(pde):
+def test_matches_proximal_gradient_on_small_grid(pde, mu_rule):
     """The IPM optimum equals an independent FISTA solution of the reduced problem in u."""
     N = 7
     p = W.poisson2d_small(seed=4, N=N)
@@ -220,7 +221,7 @@ def test_matches_proximal_gradient_on_small_grid(pde):
     p.u_a[:] = -1.5; p.u_b[:] = 1.0
     A = I.dense_operator(2, N, p.pde, p.eps)
     u_ref, y_ref = I.fista(A, p.y_d, np.zeros(p.n), p.alpha, p.beta, p.u_a, p.u_b)
-    r = oracle.solve(p, IPMOptions(eps_p=1e-12, eps_d=1e-12, eps_c=1e-12))
+    r = oracle.solve(p, IPMOptions(eps_p=1e-12, eps_d=1e-12, eps_c=1e-12, mu_rule=mu_rule))
     assert r.status == "converged"
     assert (np.abs(u_ref) < 1e-12).sum() > 0 and (np.abs(u_ref - 1.0) < 1e-12).sum() > 0
     assert (np.abs(u_ref + 1.5) < 1e-12).sum() > 0
@@ -228,8 +229,9 @@ def test_matches_proximal_gradient_on_small_grid(pde):
     np.testing.assert_allclose(r.y, y_ref, rtol=0, atol=1e-8)
 
 
+@pytest.mark.parametrize("mu_rule", ["paper", "central"])
 @pytest.mark.parametrize("state_bounds", [False, True])
-def test_matches_exhaustive_active_set(state_bounds):
+def test_matches_exhaustive_active_set(state_bounds, mu_rule):
     """Brute force over all active sets of a 2x2 grid (with and without state bounds)."""
     N = 2
     p = W.poisson2d_small(seed=5, N=N)
@@ -244,7 +246,7 @@ def test_matches_exhaustive_active_set(state_bounds):
     A = I.dense_operator(2, N)
     ref = I.active_set_qp(A, p.y_d, p.f, p.alpha, p.beta, p.u_a, p.u_b, p.y_a, p.y_b)
     assert ref is not None
-    r = oracle.solve(p, IPMOptions(eps_p=1e-12, eps_d=1e-12, eps_c=1e-12))
+    r = oracle.solve(p, IPMOptions(eps_p=1e-12, eps_d=1e-12, eps_c=1e-12, mu_rule=mu_rule))
     assert r.status == "converged"
     np.testing.assert_allclose(r.u, ref[1], rtol=0, atol=1e-7)
     np.testing.assert_allclose(r.y, ref[0], rtol=0, atol=1e-8)
@@ -308,3 +310,33 @@ def test_nli_at_sigma_02_and_final_mu():
     r = oracle.solve(p, IPMOptions(sigma=0.2))
     assert r.nli == 9
     assert r.state.mu == pytest.approx(5.12e-7, rel=1e-12)
+
+
+def test_central_mu_rule_starts_on_the_path():
+    """At the starting point every complementarity product equals mu_0 (R3), so
+    the iterate-based target of mu_rule="central" equals sigma mu_0."""
+    from oracle.fd import discretize
+    from oracle.ipm import complementarity_mean, initial_state, next_mu, residuals
+    p = W.poisson2d_511(seed=3, N=15)
+    for mu0 in (1.0, 0.37):
+        opts = IPMOptions(sigma=0.2, mu0=mu0, mu_rule="central")
+        disc = discretize(p)
+        st = initial_state(p, opts)
+        prods = residuals(p, disc, st)[2]
+        np.testing.assert_allclose(prods, mu0, rtol=1e-15)
+        assert abs(next_mu(p, disc, st, opts) - 0.2 * mu0) <= 1e-15 * mu0
+        assert abs(complementarity_mean(p, disc, st) - mu0) <= 1e-15 * mu0
+
+
+def test_fixed_decrease_breakdown_and_central_rule():
+    """The state-constrained workload with seed 10 at 63^2: Algorithm A.1's fixed
+    decrease mu^{k+1} = sigma mu^k loses interiority (reported as a breakdown),
+    while the iterate-based target converges to the stopping test."""
+    from oracle.fd import discretize
+    from oracle.ipm import measures
+    p = W.poisson2d_511(seed=10, N=63)
+    r = oracle.solve(p, IPMOptions(sigma=p.sigma, maxit=60))
+    assert r.status == "breakdown"
+    r = oracle.solve(p, IPMOptions(sigma=p.sigma, maxit=60, mu_rule="central"))
+    assert r.status == "converged"
+    assert max(measures(p, discretize(p), r.state)) <= 1e-6
