@@ -63,6 +63,7 @@ enum { IPMPDE_POISSON = 0, IPMPDE_CONVDIFF = 1 };
 enum { IPMPDE_MINRES = 0, IPMPDE_FGMRES = 1 };
 enum { IPMPDE_PD = 0, IPMPDE_PT = 1 };
 enum { IPMPDE_FP64 = 0, IPMPDE_FP32 = 1 };
+enum { IPMPDE_MU_PAPER = 0, IPMPDE_MU_CENTRAL = 1 };
 
 /* Fields for ipmpde_query / ipmpde_set_field (each n doubles). */
 enum {
@@ -96,6 +97,11 @@ typedef struct {
   int mg_precision;    /* IPMPDE_FP64 | IPMPDE_FP32 (default): precision of the V-cycles */
   int chunk;           /* Krylov iterations per device-side batch between host checks; default 8 */
   int use_graphs;      /* capture Krylov chunks in HIP graphs; default 1 */
+  int mu_rule;         /* barrier target of the next step: IPMPDE_MU_PAPER (default),
+                          mu^{k+1} = sigma mu^k as in Algorithm A.1, or IPMPDE_MU_CENTRAL,
+                          sigma times the mean complementarity product of the iterate
+                          (the duality measure; equal on the central path, and robust when
+                          step lengths collapse) */
 } ipmpde_options;
 
 #define IPMPDE_MAX_HIST 256
@@ -220,7 +226,8 @@ int ipmpde_query_rhs(const ipmpde_problem* prob, double* host_out, size_t count)
  * (ipmpde_newton_setup or a solve) in the same multigrid precision.
  * kernel ids: 0 saddle matvec, 2 Lanczos vector + exact (1,1)-block inverse,
  * 3 one 2D V-cycle, 4 finest-level descent kernel (2D), 5 finest-level
- * ascent kernel (2D), 6 MINRES update + saddle matvec + dot products. */
+ * ascent kernel (2D), 6 MINRES update + saddle matvec + dot products,
+ * 7 the single-workgroup coarse-grid kernel. */
 int ipmpde_time_kernel(ipmpde_problem* prob, const ipmpde_options* opts, int kernel, int reps,
                        ipmpde_stream stream, double* avg_ms, double* bytes);
 

@@ -15,6 +15,7 @@ POISSON, CONVDIFF = 0, 1
 MINRES, FGMRES = 0, 1
 PD, PT = 0, 1
 FP64, FP32 = 0, 1
+MU_PAPER, MU_CENTRAL = 0, 1
 MAX_HIST = 256
 
 FIELDS = {
@@ -42,6 +43,7 @@ class COptions(C.Structure):
         ("krylov", C.c_int), ("precond", C.c_int), ("restart", C.c_int), ("krylov_tol", C.c_double),
         ("krylov_maxit", C.c_int), ("vcycles", C.c_int), ("nu_pre", C.c_int), ("nu_post", C.c_int),
         ("omega", C.c_double), ("mg_precision", C.c_int), ("chunk", C.c_int), ("use_graphs", C.c_int),
+        ("mu_rule", C.c_int),
     ]
 
 

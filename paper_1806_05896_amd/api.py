@@ -15,8 +15,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "csrc", "libipmpde.hip")
 _INC = os.path.join(os.path.dirname(_HERE), "include")
 
+# -amdgpu-kernarg-preload-count: the first kernel arguments arrive in SGPRs
+# (gfx950), which takes one memory round trip off every launch.
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-shared", "-std=c++17", "-Wno-unused-value",
-               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+               "-mllvm", "-amdgpu-kernarg-preload-count=8"]
 
 
 def library_path() -> str:
@@ -60,6 +63,7 @@ class Options:
     mg_precision: str = "fp32"      # "fp32" | "fp64"
     chunk: int = 8
     use_graphs: bool = True
+    mu_rule: str = "paper"          # "paper" (sigma mu^k) | "central" (sigma x mean complementarity)
 
     def to_c(self) -> L.COptions:
         o = L.COptions()
@@ -73,6 +77,8 @@ class Options:
                 v = {"fp64": L.FP64, "fp32": L.FP32}[v]
             elif f.name == "use_graphs":
                 v = int(bool(v))
+            elif f.name == "mu_rule":
+                v = {"paper": L.MU_PAPER, "central": L.MU_CENTRAL}[v]
             setattr(o, f.name, v)
         return o
 

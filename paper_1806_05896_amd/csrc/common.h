@@ -41,11 +41,13 @@ struct KrylovCtrl {
   double rnorm;        // |b - K x|_2 from the last true-residual check
   double rtarget;      // stop when the tracked residual norm falls to this value
   double rtrack;       // tracked residual norm |r_j|_2 (recurrence)
+  double rs2, rc;      // r_j = rs2 r_{j-1} + rc v_{j+1} (applied with the next Lanczos step)
   double rfloor;       // |(|K||x| + |b|)|_2 from the last true-residual check (rounding floor scale)
   int iter;            // iterations completed
   int stop;            // 0 running, 1 stopped (converged estimate, breakdown)
   int pending;         // a direction/solution update is pending
   int breakdown;       // 1: preconditioner indefinite or NaN
+  int rpend;           // a residual update (rs2, rc) is pending
   int j;               // FGMRES: Arnoldi steps completed in this cycle
   int want_restart;    // 1: the last cycle missed the tolerance; start another from the true residual
   int its_total;       // Krylov iterations over all cycles of this solve
@@ -84,7 +86,7 @@ struct Inst {
   double *ty, *tw, *tv, *mh;
   // Newton system and Krylov workspace (4n each)
   double *rhs, *X, *Q, *R, *Rt;
-  double *V[2], *Z[2], *W[2], *KW[2];
+  double *V[2], *Z[2], *W[2];
   double *fV, *fZ;      // FGMRES basis (restart + 1 and restart vectors), or null
   int nparts;           // capacity of `partials` in doubles
   // reductions
@@ -96,6 +98,10 @@ struct Inst {
   int nlev;             // number of levels (finest 0)
   int coarse_lev;       // first level handled by the single-workgroup kernel
   int coarse_p2;        // 1: the coarse levels run in the padded 2D Poisson kernel
+  void* cpack;          // Poisson 2D: the coarse levels' LDS image (zero iterates, d, 1/d), built per Newton setup
+  void* kc_b0;          // k-cycle solves (vcycles > 1): the solve's level-0 right-hand side
+  void* kc_s[2];        // and its accumulated iterate (ping-pong)
+  int cpack_elems;      // its length in elements of the multigrid type
   int mg_fp32;          // 1: levels hold float
   int nu_pre, nu_post, vcycles;
   double omega;
@@ -319,6 +325,14 @@ __device__ __forceinline__ bool grid_reduce(double (&v)[K], double* __restrict__
 }
 
 inline int div_up(long a, long b) { return (int)((a + b - 1) / b); }
+
+// Level-0 output array of the V-cycle: level 0's x when the whole hierarchy
+// runs in the single-workgroup kernel, else x (outsel = 0) or x2 (outsel = 1).
+template <typename T>
+__device__ __forceinline__ const T* mg_out(const Inst& I, int outsel) {
+  return (const T*)((I.coarse_lev == 0 || !outsel) ? I.lv[0].x : I.lv[0].x2);
+}
+
 
 // Start of every kernel: the instance of this block, skipped when inactive.
 #define INST_BEGIN                         \

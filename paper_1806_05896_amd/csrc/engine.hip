@@ -196,7 +196,9 @@ static int engine_class_step(ipmpde_engine* E, EngineClass* C, hipStream_t s) {
       G->H[i].active = 1;
     }
   }
-  TRY(group_measures(G, s));
+  bool mean = false;
+  for (const EngineReq* R : C->members) mean = mean || R->o.mu_rule == IPMPDE_MU_CENTRAL;
+  TRY(group_measures(G, s, mean));
   std::vector<int> fin(m, -1);
   int alive = 0;
   for (int i = 0; i < m; ++i) {

@@ -71,6 +71,26 @@ __global__ void __launch_bounds__(kBS) k_measures(const Inst* __restrict__ Dp) {
   }
 }
 
+// Mean of the complementarity products (eq. (gap) with mu = 0) over every
+// finite bound, the duality measure of the iterate -> stat[5] (the barrier
+// target of the iterate-based rule is sigma times it).
+__global__ void __launch_bounds__(kBS) k_compl_mean(const Inst* __restrict__ Dp) {
+  INST_BEGIN
+  __shared__ double smem[kBS / 64];
+  const int i = blockIdx.x * kBS + threadIdx.x;
+  double acc[1] = {0.0};
+  if (i < I.n) {
+    const double w = I.w[i], v = I.v[i];
+    acc[0] = (w * I.lwa[i] + (I.ub[i] - w) * I.lwb[i]) + (v * I.lva[i] + (-I.ua[i] - v) * I.lvb[i]);
+    if (I.has_y) {
+      const double y = I.y[i];
+      acc[0] += (y - I.ya[i]) * I.lya[i] + (I.yb[i] - y) * I.lyb[i];
+    }
+  }
+  if (grid_reduce<kSum, 1, kBS>(acc, I.partials, I.counter, gridDim.x, blockIdx.x, smem) && threadIdx.x == 0)
+    I.stat[5] = acc[0] / ((I.has_y ? 6.0 : 4.0) * I.n);
+}
+
 // Barrier diagonals Theta_y, Theta_w, Theta_v (Sec. 3, below eq.
 // (NewtonSystem)), the matching term M_hat = sqrt(Sigma (1 + Theta_y)) with
 // Sigma = (t_w + t_v) / (alpha (t_w + t_v) + t_w t_v) (eq. (Schur) and the

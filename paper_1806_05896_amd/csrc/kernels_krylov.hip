@@ -9,12 +9,17 @@
 //
 // Preconditioned MINRES (Sec. 4: the Krylov method used with P_D) runs with
 // all scalars on the device.  One iteration is
-//   K1  pending direction/solution update of the previous iteration (and, by
-//       the same recurrence, K w and the residual r = b - K x), then
+//   K1  pending direction/solution update of the previous iteration, then
 //       q = K z_j / gamma_j and delta_j = <q, z_j / gamma_j>
 //   K2  Lanczos step v_{j+1} = q - (delta_j/gamma_j) v_j - (gamma_j/gamma_{j-1}) v_{j-1},
 //       exact (1,1)-block inverse of P_D on the y, w, v blocks and their part
-//       of <v_{j+1}, z_{j+1}>; the p block is handed to the multigrid
+//       of <v_{j+1}, z_{j+1}>; the p block is handed to the multigrid.  It
+//       also advances the unpreconditioned residual of the previous iterate,
+//       r_{j-1} = s^2 r_{j-2} + (phi c / gamma_j) v_j (the residual in the
+//       Lanczos basis is phi times the last column of the transposed QR
+//       rotations; the identity needs only the computed three-term relation,
+//       so it holds with an inexact FP32 preconditioner), and stops the solve
+//       once |r|_2 <= tol |b|_2
 //   MG  z_{j+1,p} = S_hat^-1 v_{j+1,p}
 //   K4  rest of <v_{j+1}, z_{j+1}>, gamma_{j+1}, the Givens rotation and the
 //       coefficients of the next update, all in the last block.
@@ -66,13 +71,6 @@ __device__ __forceinline__ void apply_A11_inv(const Inst& I, int i, double ry, d
   const double det = a * (tw + tv) + tw * tv;
   zw = ((a + tv) * rw + a * rv) / det;
   zv = (a * rw + (a + tw) * rv) / det;
-}
-
-// Level-0 output array of the V-cycle: level 0's x when the whole hierarchy
-// runs in the single-workgroup kernel, else x (outsel = 0) or x2 (outsel = 1).
-template <typename T>
-__device__ __forceinline__ const T* mg_out(const Inst& I, int outsel) {
-  return (const T*)((I.coarse_lev == 0 || !outsel) ? I.lv[0].x : I.lv[0].x2);
 }
 
 // y = K x (single instance)
@@ -228,7 +226,7 @@ __global__ void __launch_bounds__(kBS) k_minres_init(const Inst* __restrict__ Dp
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int q = k * n + i;
-      I.V[0][q] = 0.0; I.W[0][q] = 0.0; I.W[1][q] = 0.0; I.KW[0][q] = 0.0; I.KW[1][q] = 0.0;
+      I.V[0][q] = 0.0; I.W[0][q] = 0.0; I.W[1][q] = 0.0;
       I.Rt[q] = r[q];
     }
     ((T*)I.lv[0].b)[i] = (T)rp;
@@ -238,15 +236,12 @@ __global__ void __launch_bounds__(kBS) k_minres_init(const Inst* __restrict__ Dp
     I.ctrl->dot_tmp = acc[0];
 }
 
-// K1: pending update of iteration j-1 (direction w, solution x, and by the
-// same recurrence K w and the residual r = b - K x, with |r|^2), then
-// q = K z_j / gamma_j and delta_j = <q, z_j/gamma_j>.  The last block stops
-// the solve once |r|_2 <= rtarget (the true residual is tracked exactly in
-// exact arithmetic whatever the preconditioner, so FP32 V-cycles cannot fake
-// convergence).  par = parity of j; timing = 1 only for stand-alone timing.
+// K1: pending update of iteration j-1 (direction w, solution x), then
+// q = K z_j / gamma_j and delta_j = <q, z_j/gamma_j>.  par = parity of j;
+// timing = 1 only for stand-alone timing.
 __global__ void __launch_bounds__(kBS) k_minres_k1(const Inst* __restrict__ Dp, int par, int timing) {
   INST_BEGIN
-  __shared__ double smem[2 * kBS / 64];
+  __shared__ double smem[kBS / 64];
   KrylovCtrl* C = I.ctrl;
   if (C->stop && !timing) return;
   const int pending = timing ? 1 : C->pending;
@@ -254,13 +249,10 @@ __global__ void __launch_bounds__(kBS) k_minres_k1(const Inst* __restrict__ Dp, 
   const double* __restrict__ Zprev = I.Z[1 - par];
   double* __restrict__ Wsame = I.W[1 - par];
   const double* __restrict__ Wother = I.W[par];
-  double* __restrict__ KWsame = I.KW[1 - par];
-  const double* __restrict__ KWother = I.KW[par];
   double* __restrict__ X = I.X;
   double* __restrict__ Q = I.Q;
-  double* __restrict__ Rt = I.Rt;
   const int i = blockIdx.x * kBS + threadIdx.x;
-  double acc[2] = {0.0, 0.0};
+  double acc[1] = {0.0};
   if (i < I.n) {
     const int n = I.n;
     if (pending) {
@@ -271,11 +263,6 @@ __global__ void __launch_bounds__(kBS) k_minres_k1(const Inst* __restrict__ Dp, 
         const double wi = (Zprev[j] / g - a3 * Wsame[j] - a2 * Wother[j]) / a1;
         Wsame[j] = wi;
         X[j] += cx * wi;
-        const double kwi = (Q[j] - a3 * KWsame[j] - a2 * KWother[j]) / a1;
-        KWsame[j] = kwi;
-        const double r = Rt[j] - cx * kwi;
-        Rt[j] = r;
-        acc[1] += r * r;
       }
     }
     const double s = 1.0 / C->gamma;
@@ -287,38 +274,45 @@ __global__ void __launch_bounds__(kBS) k_minres_k1(const Inst* __restrict__ Dp, 
       acc[0] += o[k] * (Zc[k * n + i] * s);
     }
   }
-  if (grid_reduce<kSum, 2, kBS>(acc, I.partials, I.counter, gridDim.x, blockIdx.x, smem) && threadIdx.x == 0) {
+  if (grid_reduce<kSum, 1, kBS>(acc, I.partials, I.counter, gridDim.x, blockIdx.x, smem) && threadIdx.x == 0) {
     C->delta = acc[0];
-    if (pending && !timing) {
-      C->rtrack = sqrt(acc[1]);
-      C->pending = 0;
-      if (C->rtrack <= C->rtarget || !(acc[1] == acc[1])) C->stop = 1;
-    }
+    if (pending && !timing) C->pending = 0;
   }
 }
 
 // K2: Lanczos vector v_{j+1} (overwrites v_{j-1}), z_{j+1} on the diagonal
-// blocks, partial <v_{j+1}, z_{j+1}>, b_0 = (T) v_{j+1,p} for the multigrid.
+// blocks, partial <v_{j+1}, z_{j+1}>, b_0 = (T) v_{j+1,p} for the multigrid;
+// the pending residual update with v_j and, in the last block, the stop test
+// on |r_{j-1}|_2.  timing = 1 only for stand-alone timing.
 template <typename T>
-__global__ void __launch_bounds__(kBS) k_minres_k2(const Inst* __restrict__ Dp, int par) {
+__global__ void __launch_bounds__(kBS) k_minres_k2(const Inst* __restrict__ Dp, int par, int timing) {
   INST_BEGIN
-  __shared__ double smem[kBS / 64];
-  const KrylovCtrl* C = I.ctrl;
-  if (C->stop) return;
+  __shared__ double smem[2 * kBS / 64];
+  KrylovCtrl* C = I.ctrl;
+  if (C->stop && !timing) return;
+  const int rpend = timing ? 1 : C->rpend;
   const double* __restrict__ Q = I.Q;
   const double* __restrict__ Vc = I.V[par];
   double* __restrict__ Vn = I.V[1 - par];
   double* __restrict__ Zn = I.Z[1 - par];
+  double* __restrict__ Rt = I.Rt;
   const int i = blockIdx.x * kBS + threadIdx.x;
-  double acc[1] = {0.0};
+  double acc[2] = {0.0, 0.0};
   if (i < I.n) {
     const int n = I.n;
     const double c1 = C->delta / C->gamma, c2 = C->gamma / C->gamma_prev;
+    const double rs2 = C->rs2, rc = C->rc;
     double v[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      v[k] = Q[k * n + i] - c1 * Vc[k * n + i] - c2 * Vn[k * n + i];
+      const double vc = Vc[k * n + i];
+      v[k] = Q[k * n + i] - c1 * vc - c2 * Vn[k * n + i];
       Vn[k * n + i] = v[k];
+      if (rpend) {
+        const double r = rs2 * Rt[k * n + i] + rc * vc;
+        Rt[k * n + i] = r;
+        acc[1] += r * r;
+      }
     }
     double zy, zw, zv;
     apply_A11_inv(I, i, v[0], v[1], v[2], zy, zw, zv);
@@ -326,8 +320,14 @@ __global__ void __launch_bounds__(kBS) k_minres_k2(const Inst* __restrict__ Dp, 
     ((T*)I.lv[0].b)[i] = (T)v[3];
     acc[0] = v[0] * zy + v[1] * zw + v[2] * zv;
   }
-  if (grid_reduce<kSum, 1, kBS>(acc, I.partials, I.counter, gridDim.x, blockIdx.x, smem) && threadIdx.x == 0)
-    I.ctrl->dot_tmp = acc[0];
+  if (grid_reduce<kSum, 2, kBS>(acc, I.partials, I.counter, gridDim.x, blockIdx.x, smem) && threadIdx.x == 0) {
+    C->dot_tmp = acc[0];
+    if (rpend && !timing) {
+      C->rpend = 0;
+      C->rtrack = sqrt(acc[1]);
+      if (C->rtrack <= C->rtarget || !(acc[1] == acc[1])) C->stop = 1;
+    }
+  }
 }
 
 // K4: z_{nb,p} from the multigrid output, the rest of <v, z>, then the scalar
@@ -356,6 +356,7 @@ __global__ void __launch_bounds__(kBS) k_minres_k4(const Inst* __restrict__ Dp, 
   if (mode == 0) {
     C->iter = 0;
     C->pending = 0;
+    C->rpend = 0;
     C->breakdown = 0;
     C->rtarget = tol * C->bnorm;
     C->rtrack = INFINITY;
@@ -395,6 +396,9 @@ __global__ void __launch_bounds__(kBS) k_minres_k4(const Inst* __restrict__ Dp, 
   C->gamma_w = g;
   C->pending = 1;
   C->eta = -sn * C->eta;
+  C->rs2 = sn * sn;
+  C->rc = gn > 0.0 ? C->eta * cn / gn : 0.0;
+  C->rpend = 1;
   C->c_prev = C->c; C->c = cn;
   C->s_prev = C->s; C->s = sn;
   C->gamma_prev = g; C->gamma = gn;
@@ -438,7 +442,7 @@ __global__ void k_ctrl_continue(const Inst* __restrict__ Dp) {
   template __global__ void k_pt_rhs<T>(const Inst*, const double*, const double*, int, int);      \
   template __global__ void k_store_p<T>(const Inst*, double*, int, int, int);                     \
   template __global__ void k_minres_init<T>(const Inst*, int);                                   \
-  template __global__ void k_minres_k2<T>(const Inst*, int);                                     \
+  template __global__ void k_minres_k2<T>(const Inst*, int, int);                                     \
   template __global__ void k_minres_k4<T>(const Inst*, int, int, double, int, int);
 IPM_KRY_INST(float)
 IPM_KRY_INST(double)

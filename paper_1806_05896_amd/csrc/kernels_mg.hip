@@ -338,6 +338,52 @@ __host__ __device__ inline int coarse_p2_elems(int N) { return 2 * (N + 2) * (N 
     }          \
   }
 
+// Largest coarse grid of the Poisson kernel (2D) and its nodes per thread.
+constexpr int kCoarseP2MaxN = 63;
+constexpr int kCoarseP2PerThread = (kCoarseP2MaxN * kCoarseP2MaxN + kCoarseBS - 1) / kCoarseBS;
+
+// Level l (0 = the first coarse-kernel level) of the LDS image of the
+// Poisson coarse kernel holding element k of the image, or -1 past its end;
+// widths halve from N0 (N_{l+1} = (N_l - 1) / 2).
+__device__ __forceinline__ int coarse_p2_level(int k, int N0, int nl, int& N, int& off) {
+  off = 0;
+  N = N0;
+  for (int l = 0; l < nl; ++l) {
+    const int e = coarse_p2_elems(N);
+    if (k < off + e) return l;
+    off += e;
+    N = (N - 1) / 2;
+  }
+  return -1;
+}
+
+// The LDS image of every instance's coarse levels after a Newton setup:
+// per level zero iterates, a zero right-hand side, d = 4/h^2 + m and 1/d.
+template <typename T>
+__global__ void __launch_bounds__(kBS) k_coarse_pack(const Inst* __restrict__ Dp) {
+  INST_BEGIN
+  if (!I.coarse_p2) return;
+  const int k = blockIdx.x * kBS + threadIdx.x;
+  if (k >= I.cpack_elems) return;
+  const int cl = I.coarse_lev;
+  int N, off;
+  const int l = coarse_p2_level(k, I.lv[cl].N, I.nlev - cl, N, off);
+  T v = 0;
+  if (l >= 0) {
+    const int P = N + 2, n = N * N;
+    const int r = k - off - 2 * P * P - n;  // index in [d | dinv]
+    if (r >= 0) {
+      const Level& Lv = I.lv[cl + l];
+      const int i = r < n ? r : r - n;
+      const T dv = (T)4 * (T)(1.0 / (Lv.h * Lv.h)) + ((const T*)Lv.mh)[i];
+      v = r < n ? dv : (T)1 / dv;
+    }
+  }
+  ((T*)I.cpack)[k] = v;
+}
+template __global__ void k_coarse_pack<float>(const Inst*);
+template __global__ void k_coarse_pack<double>(const Inst*);
+
 template <typename T>
 __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_p2(const Inst* __restrict__ Dp, int guard) {
   INST_BEGIN
@@ -349,39 +395,49 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_p2(const Inst* __restri
   const int cl = I.coarse_lev, L = I.nlev;
   const int tid = threadIdx.x;
   const T om = (T)I.omega;
+  const int N0 = I.lv[cl].N, n0 = N0 * N0;
+  // the top level's right-hand side, in flight while the image is copied
+  const T* __restrict__ bg = (const T*)I.lv[cl].b;
+  T breg[kCoarseP2PerThread];
+#pragma unroll
+  for (int j = 0; j < kCoarseP2PerThread; ++j) {
+    const int i = tid + j * kCoarseBS;
+    breg[j] = i < n0 ? bg[i] : (T)0;
+  }
   if (tid == 0) {
-    int off = 0;
+    // level widths, offsets and 1/h^2 from the top width (h = 1 / (N + 1))
+    int off = 0, N = N0;
     for (int l = cl; l < L; ++l) {
-      const int N = I.lvd[l].N;
       LN[l] = N;
       LOFF[l] = off;
-      const double h = I.lvd[l].h;
+      const double h = 1.0 / (N + 1);
       LIH2[l] = (T)(1.0 / (h * h));
       off += coarse_p2_elems(N);
+      N = (N - 1) / 2;
     }
+  }
+  // layout of level l at LOFF[l]: xa[(N+2)^2], xb[(N+2)^2], b[N^2], d[N^2], dinv[N^2]
+  {
+    const T* __restrict__ pk = (const T*)I.cpack;
+    const int total = I.cpack_elems;
+    int k = tid;
+    for (; k + 3 * kCoarseBS < total; k += 4 * kCoarseBS) {
+      const T v0 = pk[k], v1 = pk[k + kCoarseBS], v2 = pk[k + 2 * kCoarseBS], v3 = pk[k + 3 * kCoarseBS];
+      lds[k] = v0;
+      lds[k + kCoarseBS] = v1;
+      lds[k + 2 * kCoarseBS] = v2;
+      lds[k + 3 * kCoarseBS] = v3;
+    }
+    for (; k < total; k += kCoarseBS) lds[k] = pk[k];
   }
   __syncthreads();
-  // layout of level l at LOFF[l]: xa[(N+2)^2], xb[(N+2)^2], b[N^2], d[N^2], dinv[N^2]
-  for (int l = cl; l < L; ++l) {
-    const int N = LN[l], P = N + 2, n = N * N;
-    T* xa = lds + LOFF[l];
-    T* xb = xa + P * P;
-    T* d = xb + P * P + n;
-    T* dinv = d + n;
-    for (int k = tid; k < P * P; k += kCoarseBS) { xa[k] = 0; xb[k] = 0; }
-    const T* mg = (const T*)I.lvd[l].mh;
-    const T c0 = (T)4 * LIH2[l];
-    for (int i = tid; i < n; i += kCoarseBS) {
-      const T dv = c0 + mg[i];
-      d[i] = dv;
-      dinv[i] = (T)1 / dv;
-    }
-  }
   {
-    const int n = LN[cl] * LN[cl];
-    T* b = lds + LOFF[cl] + 2 * (LN[cl] + 2) * (LN[cl] + 2);
-    const T* bg = (const T*)I.lvd[cl].b;
-    for (int i = tid; i < n; i += kCoarseBS) b[i] = bg[i];
+    T* b = lds + LOFF[cl] + 2 * (N0 + 2) * (N0 + 2);
+#pragma unroll
+    for (int j = 0; j < kCoarseP2PerThread; ++j) {
+      const int i = tid + j * kCoarseBS;
+      if (i < n0) b[i] = breg[j];
+    }
   }
   __syncthreads();
   unsigned alt = 0;  // bit l: level l's iterate sits in xb
@@ -491,7 +547,59 @@ __global__ void __launch_bounds__(kBS) k_mg_scale_ty_small(const Inst* __restric
   ((T*)I.lv[0].b)[i] = (T)(1.0 + I.ty[i]) * ((const T*)I.lv[0].x)[i];
 }
 
+// k-cycle multigrid solve of (A + M_hat) x = b at level 0 (vcycles = k > 1):
+// x_1 = V b, x_{j+1} = x_j + V (b - (A + M_hat) x_j), V the V-cycle from a
+// zero guess (symmetric, so the k-cycle operator is too).  After V-cycle j
+// (output: the solution for j = 1, else a correction) this kernel forms
+// s_j = s_{j-1} + output (s_0 = 0) in kc_s[j & 1] and the next right-hand
+// side b - (A + M_hat) s_j into level 0's b (the solve's own right-hand side
+// is kept in kc_b0 at j = 1).
+template <typename T>
+__global__ void __launch_bounds__(kBS) k_mg_kc_resid(const Inst* __restrict__ Dp, int outsel, int transpose, int j,
+                                                     int guard) {
+  INST_BEGIN
+  if (mg_skip(I, guard)) return;
+  const int i = blockIdx.x * kBS + threadIdx.x;
+  if (i >= I.n) return;
+  const Level& L0 = I.lv[0];
+  const T* __restrict__ out = mg_out<T>(I, outsel);
+  const T* __restrict__ sp = (const T*)I.kc_s[(j + 1) & 1];
+  T* __restrict__ sn = (T*)I.kc_s[j & 1];
+  T* __restrict__ b = (T*)L0.b;
+  T* __restrict__ b0 = (T*)I.kc_b0;
+  int i1, i2, i3;
+  node_coords(i, L0.N, I.dim, i1, i2, i3);
+  const bool tr = transpose != 0;
+  T bo, si, ax;
+  if (j == 1) {
+    bo = b[i];
+    b0[i] = bo;
+    si = out[i];
+    ax = apply_op<T>(out, i, i1, i2, i3, L0.N, I.dim, I.pde, L0.h, I.eps, tr);
+  } else {
+    bo = b0[i];
+    si = sp[i] + out[i];
+    ax = apply_op<T>(sp, i, i1, i2, i3, L0.N, I.dim, I.pde, L0.h, I.eps, tr) +
+         apply_op<T>(out, i, i1, i2, i3, L0.N, I.dim, I.pde, L0.h, I.eps, tr);
+  }
+  sn[i] = si;
+  b[i] = bo - (ax + ((const T*)L0.mh)[i] * si);
+}
+
+// End of a k-cycle solve: output = s_{k-1} + output (the last correction).
+template <typename T>
+__global__ void __launch_bounds__(kBS) k_mg_kc_final(const Inst* __restrict__ Dp, int outsel, int k, int guard) {
+  INST_BEGIN
+  if (mg_skip(I, guard)) return;
+  const int i = blockIdx.x * kBS + threadIdx.x;
+  if (i >= I.n) return;
+  T* __restrict__ out = (T*)mg_out<T>(I, outsel);
+  out[i] += ((const T*)I.kc_s[(k - 1) & 1])[i];
+}
+
 #define IPM_MG_INST(T)                                                              \
+  template __global__ void k_mg_kc_resid<T>(const Inst*, int, int, int, int);         \
+  template __global__ void k_mg_kc_final<T>(const Inst*, int, int, int);              \
   template __global__ void k_mg_jacobi<T>(const Inst*, int, int, int, int, int, int); \
   template __global__ void k_mg_restrict<T>(const Inst*, int, int, int, int);         \
   template __global__ void k_mg_prolong<T>(const Inst*, int, int, int, int);          \
@@ -505,8 +613,10 @@ IPM_MG_INST(double)
 
 // ---------------------------------------------------------------- fused 2D level kernels
 //
-// Descent at level l: nu damped-Jacobi sweeps from a zero iterate, the
-// residual, and its full-weighting restriction, for a tile of TC x TC coarse
+// Generic 2D operator (convection-diffusion; the Poisson instances take the
+// kernels specialised for the constant stencil).  Descent at level l: nu
+// damped-Jacobi sweeps from a zero iterate, the residual, and its
+// full-weighting restriction, for a tile of TC x TC coarse
 // nodes in one workgroup (temporal blocking in LDS: the sweeps run on a
 // region that shrinks by one node per sweep).  Writes the smoothed iterate
 // of the tile's own fine nodes and the coarse right-hand side.
@@ -533,7 +643,7 @@ template <typename T, int NU>
 __global__ void __launch_bounds__(kBS) k_mg_down2d(const Inst* __restrict__ Dp, int l, int scaled, int transpose,
                                                    int guard) {
   INST_BEGIN
-  if (l >= I.coarse_lev || mg_skip(I, guard)) return;
+  if (I.coarse_p2 || l >= I.coarse_lev || mg_skip(I, guard)) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const Level& F = I.lv[l];
   const Level& C = I.lv[l + 1];
@@ -642,7 +752,7 @@ __global__ void __launch_bounds__(kBS) k_mg_down2d(const Inst* __restrict__ Dp, 
 template <typename T, int NU>
 __global__ void __launch_bounds__(kBS) k_mg_up2d(const Inst* __restrict__ Dp, int l, int transpose, int guard) {
   INST_BEGIN
-  if (l >= I.coarse_lev || mg_skip(I, guard)) return;
+  if (I.coarse_p2 || l >= I.coarse_lev || mg_skip(I, guard)) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const Level& F = I.lv[l];
   const T* __restrict__ xpre = (const T*)F.x;

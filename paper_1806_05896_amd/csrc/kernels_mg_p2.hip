@@ -1,0 +1,202 @@
+// Fused V-cycle level kernels for 2D Poisson (constant 5-point stencil), the
+// multigrid of S_hat^-1 (Sec. 4.2) for the Poisson problems.
+//
+// Per node the kernels stage in LDS the diagonal d = 4/h^2 + m of A + M_hat
+// (m = the level's M_hat entry) and w = omega / d, so a damped-Jacobi sweep is
+//   x <- (1 - omega) x + w (b + h^-2 (sum of the four neighbours)),
+// and the residual is b + h^-2 (sum of the neighbours) - d x.  Nodes of the
+// LDS region outside the grid hold b = w = x = 0, which keeps the homogeneous
+// Dirichlet condition with no tests in the sweeps.  The tile size is a
+// template parameter (a launch choice); it changes no node's arithmetic, only
+// how much halo is recomputed.
+#include "common.h"
+
+namespace ipm {
+
+__host__ __device__ constexpr int p2_down_width(int nu, int tc) { return 2 * tc + 1 + 2 * nu; }
+__host__ __device__ constexpr int p2_up_width(int nu, int tf) { return tf + 2 * nu; }
+__host__ __device__ constexpr int p2_up_coarse_width(int nu, int tf) { return p2_up_width(nu, tf) / 2 + 2; }
+template <typename T, int NU, int TC>
+constexpr size_t p2_down_lds() { return 5 * sizeof(T) * p2_down_width(NU, TC) * p2_down_width(NU, TC); }
+template <typename T, int NU, int TF>
+constexpr size_t p2_up_lds() {
+  return sizeof(T) * (4 * p2_up_width(NU, TF) * p2_up_width(NU, TF) +
+                      p2_up_coarse_width(NU, TF) * p2_up_coarse_width(NU, TF));
+}
+constexpr size_t kStaticLdsMax = 65536;
+
+// Descent at level l for a tile of TC x TC coarse nodes: NU sweeps from a
+// zero iterate (the first is x = w b), the smoothed iterate of the tile's own
+// 2TC x 2TC fine nodes, the residual and its full-weighting restriction.
+// scaled (level 0 only): the right-hand side is (1 + Theta_y) times level 0's
+// x2 (the first solve's output); it is also stored as level 0's b for the
+// ascent.
+template <typename T, int NU, int TC>
+__global__ void __launch_bounds__(kBS) k_mg_down_p2(const Inst* __restrict__ Dp, int l, int scaled, int guard) {
+  INST_BEGIN
+  if (!I.coarse_p2 || l >= I.coarse_lev || mg_skip(I, guard)) return;
+  const Level& F = I.lv[l];
+  const Level& C = I.lv[l + 1];
+  const int N = F.N, Nc = C.N;
+  const int J1 = blockIdx.x * TC, J2 = blockIdx.y * TC;
+  if (J1 >= Nc || J2 >= Nc) return;
+  constexpr int W = p2_down_width(NU, TC);
+  __shared__ T bs[W * W], ds[W * W], ws[W * W], xa[W * W], xb[W * W];
+  const int o1 = 2 * J1 - NU, o2 = 2 * J2 - NU;  // fine coordinates of LDS (0, 0)
+  const T* __restrict__ bsrc = (const T*)(scaled ? F.x2 : F.b);
+  const double* __restrict__ ty = scaled ? I.ty : nullptr;
+  const T* __restrict__ mh = (const T*)F.mh;
+  const T ih2 = (T)(1.0 / (F.h * F.h));
+  const T om = (T)I.omega, om1 = (T)1 - om;
+  const int tid = threadIdx.x;
+  for (int k = tid; k < W * W; k += kBS) {
+    const int q2 = k / W, q1 = k - q2 * W;
+    const int g1 = o1 + q1, g2 = o2 + q2;
+    T bv = 0, dv = 0, wv = 0;
+    if ((unsigned)g1 < (unsigned)N && (unsigned)g2 < (unsigned)N) {
+      const int gi = g1 + N * g2;
+      bv = bsrc[gi];
+      if (ty) bv = (T)(1.0 + ty[gi]) * bv;
+      dv = (T)4 * ih2 + mh[gi];
+      wv = om / dv;
+    }
+    bs[k] = bv;
+    ds[k] = dv;
+    ws[k] = wv;
+    xa[k] = wv * bv;
+  }
+  __syncthreads();
+  if (ty) {
+    T* __restrict__ bout = (T*)F.b;
+    for (int k = tid; k < 4 * TC * TC; k += kBS) {
+      const int r2 = k / (2 * TC), r1 = k - r2 * (2 * TC);
+      const int g1 = 2 * J1 + r1, g2 = 2 * J2 + r2;
+      if (g1 < N && g2 < N) bout[g1 + N * g2] = bs[(NU + r1) + W * (NU + r2)];
+    }
+  }
+  T* a = xa;
+  T* c = xb;
+#pragma unroll
+  for (int s = 1; s < NU; ++s) {
+    const int w = W - 2 * s;  // the region shrinks by one node per sweep
+    for (int k = tid; k < w * w; k += kBS) {
+      const int r2 = k / w, r1 = k - r2 * w;
+      const int li = (r1 + s) + W * (r2 + s);
+      c[li] = om1 * a[li] + ws[li] * (bs[li] + ih2 * ((a[li - 1] + a[li + 1]) + (a[li - W] + a[li + W])));
+    }
+    __syncthreads();
+    T* t = a; a = c; c = t;
+  }
+  {
+    T* __restrict__ xout = (T*)F.x;
+    for (int k = tid; k < 4 * TC * TC; k += kBS) {
+      const int r2 = k / (2 * TC), r1 = k - r2 * (2 * TC);
+      const int g1 = 2 * J1 + r1, g2 = 2 * J2 + r2;
+      if (g1 < N && g2 < N) xout[g1 + N * g2] = a[(NU + r1) + W * (NU + r2)];
+    }
+  }
+  {
+    constexpr int w = 2 * TC + 1;
+    for (int k = tid; k < w * w; k += kBS) {
+      const int r2 = k / w, r1 = k - r2 * w;
+      const int li = (r1 + NU) + W * (r2 + NU);
+      c[li] = bs[li] + ih2 * ((a[li - 1] + a[li + 1]) + (a[li - W] + a[li + W])) - ds[li] * a[li];
+    }
+  }
+  __syncthreads();
+  for (int k = tid; k < TC * TC; k += kBS) {
+    const int j2 = k / TC, j1 = k - j2 * TC;
+    const int c1 = J1 + j1, c2 = J2 + j2;
+    if (c1 < Nc && c2 < Nc) {
+      const int li = (NU + 2 * j1 + 1) + W * (NU + 2 * j2 + 1);  // fine node 2c + 1
+      const T v = (T)0.25 * c[li] + (T)0.125 * ((c[li - 1] + c[li + 1]) + (c[li - W] + c[li + W])) +
+                  (T)0.0625 * ((c[li - 1 - W] + c[li + 1 - W]) + (c[li - 1 + W] + c[li + 1 + W]));
+      ((T*)C.b)[c1 + Nc * c2] = v;
+    }
+  }
+}
+
+// Ascent at level l for a tile of TF x TF fine nodes: x = x_pre + P x_c
+// (bilinear prolongation from a coarse patch staged in LDS), then NU sweeps;
+// writes the tile's own nodes to level l's x2.
+template <typename T, int NU, int TF>
+__global__ void __launch_bounds__(kBS) k_mg_up_p2(const Inst* __restrict__ Dp, int l, int guard) {
+  INST_BEGIN
+  if (!I.coarse_p2 || l >= I.coarse_lev || mg_skip(I, guard)) return;
+  const Level& F = I.lv[l];
+  const int N = F.N, Nc = I.lv[l + 1].N;
+  if ((int)(blockIdx.x * TF) >= N || (int)(blockIdx.y * TF) >= N) return;
+  constexpr int W = p2_up_width(NU, TF);
+  constexpr int WC = p2_up_coarse_width(NU, TF);
+  __shared__ T bs[W * W], ws[W * W], xa[W * W], xb[W * W], cs[WC * WC];
+  const int o1 = blockIdx.x * TF - NU, o2 = blockIdx.y * TF - NU;
+  // coarse 1-based index of the patch's first column/row: the lower coarse
+  // neighbour of the region's first fine node (fine 1-based index o + 1)
+  const int cb1 = (o1 + 1) >> 1, cb2 = (o2 + 1) >> 1;
+  const T* __restrict__ xc = (const T*)(l + 1 == I.coarse_lev ? I.lv[l + 1].x : I.lv[l + 1].x2);
+  const T* __restrict__ xpre = (const T*)F.x;
+  const T* __restrict__ b = (const T*)F.b;
+  const T* __restrict__ mh = (const T*)F.mh;
+  const T ih2 = (T)(1.0 / (F.h * F.h));
+  const T om = (T)I.omega, om1 = (T)1 - om;
+  const int tid = threadIdx.x;
+  for (int k = tid; k < WC * WC; k += kBS) {
+    const int p2 = k / WC, p1 = k - p2 * WC;
+    const int c1 = cb1 + p1 - 1, c2 = cb2 + p2 - 1;  // 0-based coarse node
+    cs[k] = ((unsigned)c1 < (unsigned)Nc && (unsigned)c2 < (unsigned)Nc) ? xc[c1 + Nc * c2] : (T)0;
+  }
+  for (int k = tid; k < W * W; k += kBS) {
+    const int q2 = k / W, q1 = k - q2 * W;
+    const int g1 = o1 + q1, g2 = o2 + q2;
+    T bv = 0, wv = 0, xv = 0;
+    if ((unsigned)g1 < (unsigned)N && (unsigned)g2 < (unsigned)N) {
+      const int gi = g1 + N * g2;
+      bv = b[gi];
+      wv = om / ((T)4 * ih2 + mh[gi]);
+      xv = xpre[gi];
+    }
+    bs[k] = bv;
+    ws[k] = wv;
+    xa[k] = xv;
+  }
+  __syncthreads();
+  for (int k = tid; k < W * W; k += kBS) {
+    const int q2 = k / W, q1 = k - q2 * W;
+    const int g1 = o1 + q1, g2 = o2 + q2;
+    if ((unsigned)g1 < (unsigned)N && (unsigned)g2 < (unsigned)N) {
+      // fine 1-based F: even -> coarse F/2; odd -> (F-1)/2 and (F+1)/2, 1/2 each
+      const int F1 = g1 + 1, F2 = g2 + 1;
+      const int pi = ((F1 >> 1) - cb1) + WC * ((F2 >> 1) - cb2);
+      T v;
+      if (F1 & 1) {
+        v = (F2 & 1) ? (T)0.25 * ((cs[pi] + cs[pi + 1]) + (cs[pi + WC] + cs[pi + WC + 1]))
+                     : (T)0.5 * (cs[pi] + cs[pi + 1]);
+      } else {
+        v = (F2 & 1) ? (T)0.5 * (cs[pi] + cs[pi + WC]) : cs[pi];
+      }
+      xa[k] += v;
+    }
+  }
+  __syncthreads();
+  T* a = xa;
+  T* c = xb;
+#pragma unroll
+  for (int s = 1; s <= NU; ++s) {
+    const int w = W - 2 * s;
+    for (int k = tid; k < w * w; k += kBS) {
+      const int r2 = k / w, r1 = k - r2 * w;
+      const int li = (r1 + s) + W * (r2 + s);
+      c[li] = om1 * a[li] + ws[li] * (bs[li] + ih2 * ((a[li - 1] + a[li + 1]) + (a[li - W] + a[li + W])));
+    }
+    __syncthreads();
+    T* t = a; a = c; c = t;
+  }
+  T* __restrict__ xout = (T*)F.x2;
+  for (int k = tid; k < TF * TF; k += kBS) {
+    const int r2 = k / TF, r1 = k - r2 * TF;
+    const int g1 = blockIdx.x * TF + r1, g2 = blockIdx.y * TF + r2;
+    if (g1 < N && g2 < N) xout[g1 + N * g2] = a[(NU + r1) + W * (NU + r2)];
+  }
+}
+
+}  // namespace ipm

@@ -27,6 +27,7 @@
 #include "kernels_ipm.hip"
 #include "kernels_krylov.hip"
 #include "kernels_mg.hip"
+#include "kernels_mg_p2.hip"
 #include "kernels_fgmres.hip"
 
 using namespace ipm;
@@ -140,6 +141,7 @@ struct Group {
   size_t coarse_lds = 0;
   bool p2 = false;   // some instance is 2D Poisson (padded coarse kernel)
   bool gen = false;  // some instance uses the generic coarse kernel
+  int max_cpack = 0; // longest coarse LDS image (Poisson instances)
   bool any_small = false;  // 2D: some instance runs its whole hierarchy in the coarse kernel
   int outsel = 1;    // level-0 output buffer of a V-cycle (x2 = 1)
   int sel_pre = 0;   // 3D path: buffer holding the pre-smoothed iterate
@@ -163,6 +165,11 @@ struct ipmpde_problem {
   Level* lvd64 = nullptr;
   bool have32 = false, have64 = false;
   int coarse32 = 0, coarse64 = 0;
+  void* cpack32 = nullptr;  // LDS image of the Poisson coarse levels (per precision)
+  void* cpack64 = nullptr;
+  void* kc32[3] = {nullptr, nullptr, nullptr};  // k-cycle level-0 arrays: b0, s[0], s[1]
+  void* kc64[3] = {nullptr, nullptr, nullptr};
+  int cpack_elems32 = 0, cpack_elems64 = 0;
   int f_restart = 0;
   Group* self = nullptr;  // the group of one used by the single-problem entry points
   ipmpde_stats stats;
@@ -195,7 +202,7 @@ static size_t coarse_level_elems(const Level& L, bool p2) {
 }
 
 static int pick_coarse(const Level* lv, int nlev, size_t elem, int dim, bool p2) {
-  const int nmax = dim == 2 ? 63 : 15;
+  const int nmax = dim == 2 ? kCoarseP2MaxN : 15;
   int cl = nlev - 1;
   size_t need = 0;
   for (int l = nlev - 1; l >= 0; --l) {
@@ -253,7 +260,16 @@ static int ensure_mg(ipmpde_problem* P, bool fp32) {
     HIP_TRY(hipMemset(lv[l].mh, 0, nb));
     N = (N - 1) / 2;
   }
-  (fp32 ? P->coarse32 : P->coarse64) = pick_coarse(lv, P->nlev, el, P->dim, is_p2(P));
+  for (void*& a : (fp32 ? P->kc32 : P->kc64)) TRY(P->work.alloc(&a, (size_t)lv[0].n * el));
+  const int cl = pick_coarse(lv, P->nlev, el, P->dim, is_p2(P));
+  (fp32 ? P->coarse32 : P->coarse64) = cl;
+  if (is_p2(P)) {
+    int elems = 0;
+    for (int l = cl; l < P->nlev; ++l) elems += coarse_p2_elems(lv[l].N);
+    void*& pk = fp32 ? P->cpack32 : P->cpack64;
+    TRY(P->work.alloc(&pk, (size_t)elems * el));
+    (fp32 ? P->cpack_elems32 : P->cpack_elems64) = elems;
+  }
   Level*& lvd = fp32 ? P->lvd32 : P->lvd64;
   TRY(P->work.alloc_t(&lvd, kMaxLev));
   HIP_TRY(hipMemcpy(lvd, lv, sizeof(Level) * kMaxLev, hipMemcpyHostToDevice));
@@ -282,10 +298,10 @@ static int ensure_partials(ipmpde_problem* P, int blocks) {
 }
 
 // The Newton right-hand side, direction and Krylov vectors (4n each).
-static constexpr int kKrylovVecs = 13;
+static constexpr int kKrylovVecs = 11;
 static void krylov_vecs(Inst& I, double** v[kKrylovVecs]) {
   double** all[kKrylovVecs] = {&I.rhs, &I.X, &I.Q, &I.R, &I.Rt, &I.V[0], &I.V[1], &I.Z[0], &I.Z[1],
-                               &I.W[0], &I.W[1], &I.KW[0], &I.KW[1]};
+                               &I.W[0], &I.W[1]};
   std::copy(all, all + kKrylovVecs, v);
 }
 
@@ -315,6 +331,9 @@ static void release_work(ipmpde_problem* P) {
   P->f_restart = 0;
   P->have32 = P->have64 = false;
   P->lvd32 = P->lvd64 = nullptr;
+  P->cpack32 = P->cpack64 = nullptr;
+  for (int k = 0; k < 3; ++k) P->kc32[k] = P->kc64[k] = nullptr;
+  P->cpack_elems32 = P->cpack_elems64 = 0;
   for (int l = 0; l < kMaxLev; ++l) P->lv32[l] = P->lv64[l] = Level{};
   P->have_work = false;
   P->setup_done = false;
@@ -380,6 +399,7 @@ static int group_select(Group* G, const ipmpde_options& o) {
   G->p2 = false;
   G->gen = false;
   G->any_small = false;
+  G->max_cpack = 0;
   std::fill(G->maxN, G->maxN + kMaxLev, 0);
   std::fill(G->maxn, G->maxn + kMaxLev, 0);
   for (int i = 0; i < G->count; ++i) {
@@ -420,6 +440,13 @@ static int group_select(Group* G, const ipmpde_options& o) {
       G->maxn[l] = std::max(G->maxn[l], (long)lv[l].n);
     }
     d.coarse_p2 = is_p2(P) ? 1 : 0;
+    d.cpack = fp32 ? P->cpack32 : P->cpack64;
+    void* const* kc = fp32 ? P->kc32 : P->kc64;
+    d.kc_b0 = kc[0];
+    d.kc_s[0] = kc[1];
+    d.kc_s[1] = kc[2];
+    d.cpack_elems = fp32 ? P->cpack_elems32 : P->cpack_elems64;
+    G->max_cpack = std::max(G->max_cpack, d.cpack_elems);
     G->p2 = G->p2 || is_p2(P);
     G->gen = G->gen || !is_p2(P);
     G->coarse_lds = std::max(G->coarse_lds, coarse_lds_bytes(lv, P->nlev, d.coarse_lev, fp32 ? 4 : 8, is_p2(P)));
@@ -481,6 +508,7 @@ extern "C" int ipmpde_default_options(ipmpde_options* o) {
   o->mg_precision = IPMPDE_FP32;
   o->chunk = 8;
   o->use_graphs = 1;
+  o->mu_rule = IPMPDE_MU_PAPER;
   return IPMPDE_OK;
 }
 
@@ -498,13 +526,14 @@ static int check_options(const ipmpde_options& o) {
   if (o.restart < 1 || o.restart > 60) return fail(IPMPDE_EINVAL, "restart must be in [1,60]");
   if (!(o.krylov_tol > 0 && o.krylov_tol < 1)) return fail(IPMPDE_EINVAL, "krylov_tol must be in (0,1)");
   if (o.krylov_maxit < 1) return fail(IPMPDE_EINVAL, "krylov_maxit must be >= 1");
-  if (o.vcycles != 1) return fail(IPMPDE_EINVAL, "vcycles must be 1");
+  if (o.vcycles < 1 || o.vcycles > 8) return fail(IPMPDE_EINVAL, "vcycles must be in [1, 8]");
   if (o.nu_pre < 1 || o.nu_pre > 6 || o.nu_post < 1 || o.nu_post > 6) return fail(IPMPDE_EINVAL, "nu out of [1,6]");
   if (o.krylov == IPMPDE_MINRES && o.nu_pre != o.nu_post)
     return fail(IPMPDE_EINVAL, "MINRES needs nu_pre == nu_post (symmetric preconditioner)");
   if (!(o.omega >= 0 && o.omega < 1.5)) return fail(IPMPDE_EINVAL, "omega out of range");
   if (o.mg_precision != IPMPDE_FP32 && o.mg_precision != IPMPDE_FP64) return fail(IPMPDE_EINVAL, "bad mg_precision");
   if (o.chunk < 2 || o.chunk > 64 || (o.chunk & 1)) return fail(IPMPDE_EINVAL, "chunk must be even in [2,64]");
+  if (o.mu_rule != IPMPDE_MU_PAPER && o.mu_rule != IPMPDE_MU_CENTRAL) return fail(IPMPDE_EINVAL, "bad mu_rule");
   return IPMPDE_OK;
 }
 
@@ -567,6 +596,77 @@ static void launch_up2d(int nu, dim3 g, size_t lds, hipStream_t s, const Inst* D
   }
 }
 
+// Tile choice of the Poisson level kernels: the large tiles recompute less
+// halo but make fewer workgroups, so they are taken when the launch still
+// has at least this many.
+static constexpr long kBigTileMinGroups = 2048;
+
+template <typename T, int NU>
+static void launch_down_p2_nu(const Group* G, int l, int scaled, int guard, hipStream_t s) {
+  const int Nc = G->maxN[l + 1];
+  if constexpr (p2_down_lds<T, NU, 16>() <= kStaticLdsMax) {
+    const int nt = div_up(Nc, 16);
+    if ((long)nt * nt * G->zc >= kBigTileMinGroups) {
+      hipLaunchKernelGGL((k_mg_down_p2<T, NU, 16>), dim3(nt, nt, G->zc), dim3(kBS), 0, s, G->D, l, scaled, guard);
+      return;
+    }
+  }
+  const int nt = div_up(Nc, 8);
+  hipLaunchKernelGGL((k_mg_down_p2<T, NU, 8>), dim3(nt, nt, G->zc), dim3(kBS), 0, s, G->D, l, scaled, guard);
+}
+
+template <typename T, int NU>
+static void launch_up_p2_nu(const Group* G, int l, int guard, hipStream_t s) {
+  const int N = G->maxN[l];
+  if constexpr (p2_up_lds<T, NU, 32>() <= kStaticLdsMax) {
+    const int nt = div_up(N, 32);
+    if ((long)nt * nt * G->zc >= kBigTileMinGroups) {
+      hipLaunchKernelGGL((k_mg_up_p2<T, NU, 32>), dim3(nt, nt, G->zc), dim3(kBS), 0, s, G->D, l, guard);
+      return;
+    }
+  }
+  const int nt = div_up(N, 16);
+  hipLaunchKernelGGL((k_mg_up_p2<T, NU, 16>), dim3(nt, nt, G->zc), dim3(kBS), 0, s, G->D, l, guard);
+}
+
+// One descent (smoothing + residual + restriction) of level l for every
+// instance: the Poisson kernels for the Poisson instances, the generic ones
+// for the others (each kernel returns at once for the other kind).
+template <typename T>
+static void launch_down_level(const Group* G, int l, int scaled, int transpose, int guard, hipStream_t s) {
+  const int nu = G->H[0].nu_pre;
+  if (G->gen) {
+    const size_t ldd = 4 * (size_t)down_width(nu) * down_width(nu) * sizeof(T);
+    const int nt = div_up(G->maxN[l + 1], kTC);
+    launch_down2d<T>(nu, dim3(nt, nt, G->zc), ldd, s, G->D, l, scaled, transpose, guard);
+  }
+  if (G->p2) {
+    switch (nu) {
+#define D_(NU) case NU: launch_down_p2_nu<T, NU>(G, l, scaled, guard, s); break;
+      D_(1) D_(2) D_(3) D_(4) D_(5) D_(6)
+#undef D_
+    }
+  }
+}
+
+// One ascent (prolongation + smoothing) of level l for every instance.
+template <typename T>
+static void launch_up_level(const Group* G, int l, int transpose, int guard, hipStream_t s) {
+  const int nu = G->H[0].nu_post;
+  if (G->gen) {
+    const size_t ldu = 4 * (size_t)up_width(nu) * up_width(nu) * sizeof(T);
+    const int nt = div_up(G->maxN[l], kTF);
+    launch_up2d<T>(nu, dim3(nt, nt, G->zc), ldu, s, G->D, l, transpose, guard);
+  }
+  if (G->p2) {
+    switch (nu) {
+#define U_(NU) case NU: launch_up_p2_nu<T, NU>(G, l, guard, s); break;
+      U_(1) U_(2) U_(3) U_(4) U_(5) U_(6)
+#undef U_
+    }
+  }
+}
+
 // 2D V-cycle with the fused level kernels: per level one descent launch
 // (smoothing + residual + restriction) and one ascent launch (prolongation +
 // smoothing).  scaled: the level-0 right-hand side is (1 + Theta_y) times the
@@ -574,37 +674,43 @@ static void launch_up2d(int nu, dim3 g, size_t lds, hipStream_t s, const Inst* D
 // whole hierarchy fits the coarse kernel).
 template <typename T>
 static void mg_vcycle_2d(Group* G, int transpose, int guard, int scaled, hipStream_t s) {
-  const int nu_pre = G->H[0].nu_pre, nu_post = G->H[0].nu_post;
-  const size_t ldd = 4 * (size_t)down_width(nu_pre) * down_width(nu_pre) * sizeof(T);
-  const size_t ldu = 4 * (size_t)up_width(nu_post) * up_width(nu_post) * sizeof(T);
-  for (int l = 0; l < G->max_cl; ++l) {
-    const int nt = div_up(G->maxN[l + 1], kTC);
-    launch_down2d<T>(nu_pre, dim3(nt, nt, G->zc), ldd, s, G->D, l, (l == 0) ? scaled : 0, transpose, guard);
-  }
+  for (int l = 0; l < G->max_cl; ++l) launch_down_level<T>(G, l, (l == 0) ? scaled : 0, transpose, guard, s);
   launch_coarse<T>(G, transpose, guard, s);
-  for (int l = G->max_cl - 1; l >= 0; --l) {
-    const int nt = div_up(G->maxN[l], kTF);
-    launch_up2d<T>(nu_post, dim3(nt, nt, G->zc), ldu, s, G->D, l, transpose, guard);
-  }
+  for (int l = G->max_cl - 1; l >= 0; --l) launch_up_level<T>(G, l, transpose, guard, s);
 }
 
-// S_hat^-1 applied to every instance's lv[0].b (Sec. 4.2): V-cycle on
-// A + M_hat, scale by 1 + Theta_y, V-cycle on (A + M_hat)^T.  The result is
+// One multigrid solve with A + M_hat (transpose: its transpose) from level
+// 0's b: vcycles V-cycles as a k-cycle iteration (the first may take the
+// scaled right-hand side, 2D path).  Output: the level-0 output array.
+template <typename T>
+static void mg_solve(Group* G, int transpose, int guard, int scaled, hipStream_t s) {
+  const int k = G->H[0].vcycles;
+  for (int j = 1; j <= k; ++j) {
+    if (j > 1)
+      hipLaunchKernelGGL(k_mg_kc_resid<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, G->outsel, transpose, j - 1, guard);
+    if (G->dim == 2) mg_vcycle_2d<T>(G, transpose, guard, j == 1 ? scaled : 0, s);
+    else mg_vcycle_generic<T>(G, transpose, guard, s);
+  }
+  if (k > 1) hipLaunchKernelGGL(k_mg_kc_final<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, G->outsel, k, guard);
+}
+
+// S_hat^-1 applied to every instance's lv[0].b (Sec. 4.2): solve with
+// A + M_hat, scale by 1 + Theta_y, solve with (A + M_hat)^T.  The result is
 // the level-0 output array (selected in the kernels with G->outsel).
 template <typename T>
 static void schur_inv(Group* G, int guard, hipStream_t s) {
   if (G->dim == 2) {
-    mg_vcycle_2d<T>(G, 0, guard, 0, s);
+    mg_solve<T>(G, 0, guard, 0, s);
     // instances whose whole hierarchy is in the coarse kernel never run a
     // descent kernel, so their scaled right-hand side is formed here; the
     // others form it inside their first descent kernel
     if (G->any_small) hipLaunchKernelGGL(k_mg_scale_ty_small<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, guard);
-    mg_vcycle_2d<T>(G, 1, guard, 1, s);
+    mg_solve<T>(G, 1, guard, 1, s);
     return;
   }
-  mg_vcycle_generic<T>(G, 0, guard, s);
+  mg_solve<T>(G, 0, guard, 0, s);
   hipLaunchKernelGGL(k_mg_scale_ty<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, G->outsel, guard);
-  mg_vcycle_generic<T>(G, 1, guard, s);
+  mg_solve<T>(G, 1, guard, 0, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -618,7 +724,7 @@ static double floor_factor() { return 16.0 * 2.220446049250313e-16; }
 template <typename T>
 static void minres_iteration(Group* G, int par, int maxit, double tol, hipStream_t s) {
   hipLaunchKernelGGL(k_minres_k1, gz(G, G->max_n), dim3(kBS), 0, s, G->D, par, 0);
-  hipLaunchKernelGGL(k_minres_k2<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, par);
+  hipLaunchKernelGGL(k_minres_k2<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, par, 0);
   schur_inv<T>(G, 1, s);
   hipLaunchKernelGGL(k_minres_k4<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, 1 - par, 1, tol, maxit, G->outsel);
 }
@@ -767,10 +873,12 @@ static int newton_setup_group(Group* G, const ipmpde_options& o, hipStream_t s) 
     hipLaunchKernelGGL(k_newton_setup<float>, gz(G, G->max_n), dim3(kBS), 0, s, G->D);
     for (int l = 0; l + 1 < G->max_nlev; ++l)
       hipLaunchKernelGGL(k_restrict_diag<float>, gz(G, G->maxn[l + 1]), dim3(kBS), 0, s, G->D, l);
+    if (G->p2) hipLaunchKernelGGL(k_coarse_pack<float>, gz(G, G->max_cpack), dim3(kBS), 0, s, G->D);
   } else {
     hipLaunchKernelGGL(k_newton_setup<double>, gz(G, G->max_n), dim3(kBS), 0, s, G->D);
     for (int l = 0; l + 1 < G->max_nlev; ++l)
       hipLaunchKernelGGL(k_restrict_diag<double>, gz(G, G->maxn[l + 1]), dim3(kBS), 0, s, G->D, l);
+    if (G->p2) hipLaunchKernelGGL(k_coarse_pack<double>, gz(G, G->max_cpack), dim3(kBS), 0, s, G->D);
   }
   HIP_TRY(hipGetLastError());
   for (int i = 0; i < G->count; ++i) {
@@ -791,9 +899,12 @@ static int group_step(Group* G, const ipmpde_options& o, hipStream_t s) {
   return IPMPDE_OK;
 }
 
-static int group_measures(Group* G, hipStream_t s) {
+// Measures of every active instance -> stat[0..2]; with `mean`, also the
+// mean complementarity product -> stat[5].
+static int group_measures(Group* G, hipStream_t s, bool mean = false) {
   TRY(group_sync(G, s));
   hipLaunchKernelGGL(k_measures, gz(G, G->max_n), dim3(kBS), 0, s, G->D);
+  if (mean) hipLaunchKernelGGL(k_compl_mean, gz(G, G->max_n), dim3(kBS), 0, s, G->D);
   HIP_TRY(hipGetLastError());
   TRY(read_stat(G, s));
   return IPMPDE_OK;
@@ -846,7 +957,7 @@ static int ipm_check(Group* G, int i, int k, const ipmpde_options& oi) {
     st.status = finish;
     G->H[i].active = 0;
   } else {
-    P->mu *= oi.sigma;
+    P->mu = oi.sigma * (oi.mu_rule == IPMPDE_MU_CENTRAL ? G->stat_h[16 * i + 5] : P->mu);
     G->H[i].mu = P->mu;
   }
   return finish;
@@ -886,8 +997,10 @@ static int solve_group(Group* G, const std::vector<ipmpde_options>& po, hipStrea
   TRY(group_select(G, o));
   TRY(group_reset(G, po, s));
   std::vector<int> done(G->count, 0);
+  bool mean = false;
+  for (const ipmpde_options& oi : po) mean = mean || oi.mu_rule == IPMPDE_MU_CENTRAL;
   for (int k = 0;; ++k) {
-    TRY(group_measures(G, s));
+    TRY(group_measures(G, s, mean));
     int alive = 0;
     for (int i = 0; i < G->count; ++i) {
       if (done[i]) continue;
@@ -976,7 +1089,19 @@ extern "C" size_t ipmpde_footprint_bytes(const ipmpde_grid* grid, const ipmpde_p
     bytes += 4 * A(pow_dim(N, grid->dim) * el);
     if (N <= 1) break;
   }
+  bytes += 3 * A(n * el);  // k-cycle level-0 arrays
   bytes += A(kMaxLev * sizeof(Level));
+  if (grid->dim == 2 && pde->kind == IPMPDE_POISSON) {  // the coarse levels' LDS image
+    Level lv[kMaxLev];
+    int nlev = 0;
+    for (int N = grid->n;; N = (N - 1) / 2) {
+      lv[nlev].N = N;
+      lv[nlev].n = N * N;
+      ++nlev;
+      if (N <= 1) break;
+    }
+    bytes += A(coarse_lds_bytes(lv, nlev, pick_coarse(lv, nlev, el, 2, true), el, true));
+  }
   if (o.krylov == IPMPDE_FGMRES) bytes += A((size_t)(o.restart + 1) * n4 * 8) + A((size_t)o.restart * n4 * 8);
   return bytes;
 }

@@ -38,47 +38,53 @@ extern "C" int ipmpde_time_kernel(ipmpde_problem* P, const ipmpde_options* opts,
   const bool f32 = G->fp32;
   const double e = f32 ? 4.0 : 8.0;
   hipLaunchKernelGGL(k_ctrl_continue, dim3(1, 1, 1), dim3(64), 0, s, G->D);
-  const int nu_pre = o.nu_pre, nu_post = o.nu_post;
   auto launch = [&]() {
     switch (kernel) {
       case 0:
         hipLaunchKernelGGL(k_saddle, gz(G, P->n), dim3(kBS), 0, s, G->D, (const double*)I.Z[0], I.Q);
         break;
       case 2:
-        if (f32) hipLaunchKernelGGL(k_minres_k2<float>, gz(G, P->n), dim3(kBS), 0, s, G->D, 1);
-        else hipLaunchKernelGGL(k_minres_k2<double>, gz(G, P->n), dim3(kBS), 0, s, G->D, 1);
+        if (f32) hipLaunchKernelGGL(k_minres_k2<float>, gz(G, P->n), dim3(kBS), 0, s, G->D, 1, 1);
+        else hipLaunchKernelGGL(k_minres_k2<double>, gz(G, P->n), dim3(kBS), 0, s, G->D, 1, 1);
         break;
       case 3:
         if (f32) mg_vcycle_2d<float>(G, 0, 0, 0, s);
         else mg_vcycle_2d<double>(G, 0, 0, 0, s);
         break;
-      case 4: {
-        const size_t ldd = 4 * (size_t)down_width(nu_pre) * down_width(nu_pre) * e;
-        const int nt = div_up(I.lv[1].N, kTC);
-        if (f32) launch_down2d<float>(nu_pre, dim3(nt, nt, 1), ldd, s, G->D, 0, 0, 0, 0);
-        else launch_down2d<double>(nu_pre, dim3(nt, nt, 1), ldd, s, G->D, 0, 0, 0, 0);
+      case 4:
+        if (f32) launch_down_level<float>(G, 0, 0, 0, 0, s);
+        else launch_down_level<double>(G, 0, 0, 0, 0, s);
         break;
-      }
-      case 5: {
-        const size_t ldu = 4 * (size_t)up_width(nu_post) * up_width(nu_post) * e;
-        const int nt = div_up(I.lv[0].N, kTF);
-        if (f32) launch_up2d<float>(nu_post, dim3(nt, nt, 1), ldu, s, G->D, 0, 0, 0);
-        else launch_up2d<double>(nu_post, dim3(nt, nt, 1), ldu, s, G->D, 0, 0, 0);
+      case 5:
+        if (f32) launch_up_level<float>(G, 0, 0, 0, s);
+        else launch_up_level<double>(G, 0, 0, 0, s);
         break;
-      }
       case 6:
         hipLaunchKernelGGL(k_minres_k1, gz(G, P->n), dim3(kBS), 0, s, G->D, 1, 1);
+        break;
+      case 7:
+        if (f32) launch_coarse<float>(G, 0, 0, s);
+        else launch_coarse<double>(G, 0, 0, s);
         break;
     }
   };
   switch (kernel) {
     case 0: *bytes = 11.0 * n * 8; break;
-    case 2: *bytes = 22.0 * n * 8 + n * e; break;  // reads q, v_j, v_{j-1}, Theta x3; writes v, z x3, b_0
+    // K2: reads q, v_j, v_{j-1}, r (16n) and Theta_y,w,v (3n); writes v, r (8n), z_y,w,v (3n), b_0
+    case 2: *bytes = 30.0 * n * 8 + n * e; break;
     case 3: *bytes = f32 ? vcycle_bytes<float>(I) : vcycle_bytes<double>(I); break;
     case 4: *bytes = (3.0 * n + I.lv[1].n) * e; break;  // reads b, M_hat; writes x, coarse b
     case 5: *bytes = (4.0 * n + I.lv[1].n) * e; break;  // reads x, b, M_hat, coarse x; writes x2
-    // K1: reads z_j, z_{j-1}, w x2, x, q, Kw x2, r (36n) and Theta_y,w,v (3n); writes w, x, Kw, r, q (20n)
-    case 6: *bytes = 59.0 * n * 8; break;
+    // K1: reads z_j, z_{j-1}, w x2, x (20n) and Theta_y,w,v (3n); writes w, x, q (12n)
+    case 6: *bytes = 35.0 * n * 8; break;
+    // single-workgroup coarse kernel: its LDS image (Poisson) or the levels' M_hat, the top b and x
+    case 7: {
+      const int cl = I.coarse_lev;
+      double img = 0;
+      for (int l = cl; l < I.nlev; ++l) img += I.coarse_p2 ? coarse_p2_elems(I.lv[l].N) : I.lv[l].n;
+      *bytes = (img + 2.0 * I.lv[cl].n) * e;
+      break;
+    }
     default: return fail(IPMPDE_EINVAL, "unknown kernel id");
   }
   launch();  // warm-up

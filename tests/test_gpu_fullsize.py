@@ -61,6 +61,25 @@ def test_final_iterate_kkt_certificate(name, kw, opts_kw):
     assert s.xi_p <= 1e-6 and s.xi_d <= 1e-6
 
 
+def test_hard_instance_reports_breakdown_at_511():
+    """The 511^2 state-constrained instance with seed 10, on which Algorithm A.1's
+    fixed decrease of mu outruns the iterate (the oracle loses interiority on the
+    same data at 63^2): the solve ends with a clean EBREAKDOWN status, every
+    recorded measure is finite up to the failure, and the iterates stay
+    queryable."""
+    from paper_1806_05896_amd import Options, Problem
+    from paper_1806_05896_amd import _lib as L
+    data = W.poisson2d_511(seed=10)
+    print("[hard511] seed 10, paper rule", flush=True)
+    with Problem(data) as prob:
+        rc = prob.solve(Options(sigma=data.sigma))
+        s = prob.stats()
+        u = prob.query("u")
+    print(f"  rc={rc} nli={s.nli} its={s.krylov_its}", flush=True)
+    assert rc == L.EBREAKDOWN and s.status == L.EBREAKDOWN
+    assert np.all(np.isfinite(s.hist_xi_p[:5])) and u.shape == (data.n,)
+
+
 def test_ipm_step_parity_at_511():
     """One IPM step (Newton solve + multiplier steps + step lengths + update) from a
     mid-solve GPU state, against the oracle's step (SuperLU) from the same state."""

@@ -112,16 +112,18 @@ def test_saddle_matvec_parity(case):
         assert _rel(y, K @ x) <= 1e-13
 
 
+@pytest.mark.parametrize("vcycles", [1, 3])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("case", ["poisson_small", "convdiff_31", "poisson3d_15"])
-def test_pd_preconditioner_symmetric_positive(case, prec):
-    """P_D^-1 must be symmetric positive definite for MINRES (exactly so in FP64)."""
+def test_pd_preconditioner_symmetric_positive(case, prec, vcycles):
+    """P_D^-1 must be symmetric positive definite for MINRES (exactly so in FP64),
+    also with k-cycle multigrid solves."""
     Options, Problem = _api()
-    print(f"[precond] {case} {prec}", flush=True)
+    print(f"[precond] {case} {prec} vcycles={vcycles}", flush=True)
     data = CASES[case]()
     disc, st = _generic_state(data)
     mu = st.mu * data.sigma
-    opts = Options(mg_precision=prec)
+    opts = Options(mg_precision=prec, vcycles=vcycles)
     rng = np.random.default_rng(3)
     with Problem(data) as prob:
         _load_state(prob, st, data.y_a is not None)
@@ -193,6 +195,25 @@ def test_ipm_parity_cases(case, krylov, precond):
     assert _rel(u, ref.u) <= 1e-6 and _rel(y, ref.y) <= 1e-6
 
 
+@pytest.mark.parametrize("seed,N", [(10, 31), (0, 63)])
+def test_ipm_parity_central_mu_rule(seed, N):
+    """The iterate-based barrier target (mu_rule="central") against the oracle
+    running the same rule, on the state-constrained workload shape; seed 10 is
+    the instance on which the fixed decrease of Algorithm A.1 breaks down at 63^2."""
+    Options, Problem = _api()
+    print(f"[ipm-central] poisson2d seed={seed} N={N}", flush=True)
+    data = W.poisson2d_511(seed=seed, N=N)
+    ref = oracle.solve(data, IPMOptions(sigma=data.sigma, mu_rule="central"))
+    assert ref.status == "converged"
+    with Problem(data) as prob:
+        rc = prob.solve(Options(sigma=data.sigma, mu_rule="central"))
+        u, y = prob.query("u"), prob.query("y")
+        s = prob.stats()
+    print(f"  rc={rc} nli={s.nli}/{ref.nli} its={s.krylov_its} rel u={_rel(u, ref.u):.2e} y={_rel(y, ref.y):.2e}")
+    assert rc == 0 and s.nli == ref.nli
+    assert _rel(u, ref.u) <= 1e-6 and _rel(y, ref.y) <= 1e-6
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("case", ["poisson_small", "poisson_box63", "convdiff_31", "poisson3d_15", "poisson_box255"])
 def test_schur_multigrid_quality(case, prec):
@@ -225,3 +246,62 @@ def test_schur_multigrid_quality(case, prec):
     err = _rel(z[3 * data.n:], exact)
     print(f"  rel err of S_hat^-1 by multigrid: {err:.3f}", flush=True)
     assert err <= 0.35
+
+
+@pytest.mark.parametrize("case", ["poisson_small", "convdiff_31", "poisson3d_15", "poisson_box255"])
+def test_kcycle_multigrid_contracts(case):
+    """k V-cycles per multigrid solve (x_{j+1} = x_j + V(b - (A + M_hat) x_j)) approach the
+    exact S_hat^-1 geometrically: each doubling of k at least halves the error (FP64)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    from oracle.ipm import barrier_diagonals
+    Options, Problem = _api()
+    print(f"[kcycle] {case}", flush=True)
+    data = W.poisson2d_511(seed=0, N=255) if case == "poisson_box255" else CASES[case]()
+    disc, st = _generic_state(data, steps=3)
+    mu = st.mu * data.sigma
+    ty, tw, tv = barrier_diagonals(data, st)
+    a = data.alpha
+    mh = np.sqrt((tw + tv) / (a * (tw + tv) + tw * tv) * (1 + ty))
+    lu = spla.splu((disc.A + sp.diags(mh)).tocsc())
+    r = np.random.default_rng(7).normal(size=data.n)
+    exact = lu.solve((1 + ty) * lu.solve(r), trans="T")
+    x = np.zeros(4 * data.n)
+    x[3 * data.n:] = r
+    errs = {}
+    with Problem(data) as prob:
+        _load_state(prob, st, data.y_a is not None)
+        for k in (1, 2, 4):
+            opts = Options(mg_precision="fp64", vcycles=k)
+            prob.newton_setup(mu, opts)
+            z = prob.apply_precond(torch.tensor(x, device="cuda", dtype=torch.float64), opts).cpu().numpy()
+            errs[k] = _rel(z[3 * data.n:], exact)
+    print("  rel err by k:", {k: f"{e:.2e}" for k, e in errs.items()}, flush=True)
+    assert errs[2] <= 0.5 * errs[1] and errs[4] <= 0.5 * errs[2]
+
+
+def test_hard_instance_central_rule_kcycles():
+    """Seed 10 at 63^2: the instance on which the fixed decrease breaks down.  With the
+    iterate-based target and 3 V-cycles of 3+3 sweeps per multigrid solve (the lean
+    1-cycle preconditioner needs more than the Krylov limit late in this solve) the GPU
+    follows the oracle's trajectory: same iteration count, stopping test met (independent
+    CPU measures), control and state within 1e-6."""
+    from oracle.ipm import measures
+    Options, Problem = _api()
+    data = W.poisson2d_511(seed=10, N=63)
+    print("[hard] seed 10 N=63 central vcycles=3", flush=True)
+    ref = oracle.solve(data, IPMOptions(sigma=data.sigma, mu_rule="central"))
+    with Problem(data) as prob:
+        rc = prob.solve(Options(sigma=data.sigma, mu_rule="central", vcycles=3, nu_pre=3, nu_post=3,
+                                krylov_maxit=2000))
+        s = prob.stats()
+        u = prob.query("u")
+        q = prob.query
+        from oracle.ipm import IPMState
+        st = IPMState(q("y"), q("w"), q("v"), q("p"), q("lam_wa"), q("lam_wb"), q("lam_va"), q("lam_vb"), mu=s.mu)
+        st.lya, st.lyb = q("lam_ya"), q("lam_yb")
+    xs = measures(data, discretize(data), st)
+    print(f"  rc={rc} nli={s.nli}/{ref.nli} its={s.krylov_its} max/step={max(s.hist_krylov[:s.nli])} "
+          f"measures={xs} rel u vs oracle={_rel(u, ref.u):.2e}", flush=True)
+    assert rc == 0 and max(xs) <= 1e-6 and s.nli == ref.nli
+    assert _rel(u, ref.u) <= 1e-6
