@@ -7,9 +7,12 @@ u in [-5, 5] and state box y in [-0.2, 0.3]; y_d is a sum of 8 seeded sine
 modes; alpha = 1e-4, beta = 1e-3, sigma = 0.2 (workloads.poisson2d_511).
 
 One step = one complete interior point solve (every Newton system, Krylov
-iteration, preconditioner application and update of Algorithm A.1), inputs
-already resident in HBM.  The headline path runs MINRES + P_D with FP32
-V-cycles; the plain FP64 V-cycle variant is timed beside it.
+iteration, preconditioner application and update of Algorithm A.1) of one
+batch of B instances of that workload (seeds 0..B-1), advanced together by
+the batched kernels; inputs are resident in HBM before the timed region.
+The headline path runs MINRES + P_D with FP32 V-cycles; the plain FP64
+V-cycle variant, the single-instance solve and the served request mix are
+timed beside it.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -26,12 +29,13 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the roofline kernel from rocprofv3 FETCH_SIZE/WRITE_SIZE
 # runs (profiles/k_minres_k1_poisson2d_511_pmc.md), valid while the kernel
 # sources hash to the value they were measured with.
-TRAFFIC = {"kernel": 6, "N": 511, "bytes": 140424333.4, "source_sha": "4c06722113282728"}
+TRAFFIC = {"kernel": 6, "N": 511, "batch": 8, "bytes": None, "source_sha": None}
 KERNEL_NAMES = {0: "k_saddle (saddle matvec)", 1: "k_mg_jacobi (finest-level smoothing sweep)",
                 2: "k_minres_k2 (Lanczos + diagonal preconditioner)", 3: "one V-cycle",
                 4: "k_mg_down2d (finest level: smoothing + residual + restriction)",
                 5: "k_mg_up2d (finest level: prolongation + smoothing)",
-                6: "k_minres_k1 (MINRES update + saddle matvec + dots)"}
+                6: "k_minres_k1 (MINRES update + saddle matvec + dots)",
+                7: "k_mg_coarse_p2 (coarse levels in one workgroup)"}
 
 
 def measured_traffic(args):
@@ -39,7 +43,8 @@ def measured_traffic(args):
     csrc = os.path.join(ROOT, "paper_1806_05896_amd", "csrc")
     src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("kernels_krylov.hip", "common.h"))
     sha = hashlib.sha256(src).hexdigest()[:16]
-    if args.kernel == TRAFFIC["kernel"] and args.N == TRAFFIC["N"] and sha == TRAFFIC["source_sha"]:
+    if (args.kernel == TRAFFIC["kernel"] and args.N == TRAFFIC["N"] and args.batch == TRAFFIC["batch"]
+            and sha == TRAFFIC["source_sha"]):
         return TRAFFIC["bytes"]
     return None
 
@@ -226,7 +231,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 V-cycle variant")
     ap.add_argument("--kernel", type=int, default=6, help="kernel id for the roofline figure")
     ap.add_argument("--N", type=int, default=511)
-    ap.add_argument("--batch", type=int, default=8, help="instances of the batched FP32-vs-FP64 run (0: skip)")
+    ap.add_argument("--batch", type=int, default=8, help="instances solved together per step")
     ap.add_argument("--serve-requests", type=int, default=256, help="requests of the served mix (0: skip)")
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-budget-gib", type=float, default=32.0)
@@ -256,34 +261,51 @@ def main():
                                                    args.serve_budget_gib, loads)}), flush=True)
         return
     if args.only == "batch":
-        print(json.dumps({"batched": bench_batched(W, torch, args.batch, 2)}), flush=True)
+        print(json.dumps({"batched": bench_batched(W, torch, max(1, args.batch), 2)}), flush=True)
         return
-    data = W.poisson2d_511(seed=0, N=args.N)
-    prob = Problem(data)
-    opts = Options(sigma=data.sigma, mg_precision="fp32")
+    from paper_1806_05896_amd import Batch
+    B = max(1, args.batch)
+    datas = [W.poisson2d_511(seed=k, N=args.N) for k in range(B)]
+    probs = [Problem(d) for d in datas]
+    batch = Batch(probs)
+    opts = Options(sigma=datas[0].sigma, mg_precision="fp32")
+    stream = torch.cuda.current_stream()
     if args.pmc_probe:
-        # the roofline kernel at a mid-solve Newton state, then a plain copy of known size
-        # (1 GiB, larger than the 256 MB Infinity Cache) that calibrates the byte counters
-        for k in range(6):
-            prob.ipm_step(opts.sigma ** (k + 1), opts)
-        prob.newton_setup(opts.sigma ** 7, opts)
-        ms, nbytes = prob.time_kernel(args.kernel, reps=20, opts=opts)
+        # the roofline kernel of the batched step at a mid-solve Newton state, then a plain
+        # copy of known size (1 GiB, larger than the 256 MB Infinity Cache) that calibrates
+        # the byte counters
+        probe = Options(sigma=datas[0].sigma, mg_precision="fp32", fixed_nli=3)
+        batch.solve(probe, stream=stream)
+        ms, nbytes = batch.time_kernel(args.kernel, reps=20, opts=probe, stream=stream)
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"pmc_probe": KERNEL_NAMES[args.kernel], "algorithmic_bytes": nbytes,
+        print(json.dumps({"pmc_probe": KERNEL_NAMES[args.kernel], "instances": B, "algorithmic_bytes": nbytes,
                           "copy_bytes_each_direction": src.numel() * 8}))
-        prob.close()
         return
-    log(f"workload poisson2d_511 N={data.N} n={data.n}")
-    t, lat, its, st, rc = time_solves(prob, opts, args.steps, args.warmup, torch)
-    u32 = prob.query("u")
-    solves_per_s = args.steps / t
+    log(f"workload poisson2d_511 N={args.N} x {B} instances")
+    for w in range(args.warmup):
+        batch.solve(opts, stream=stream)
+        log(f"warmup {w + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    lat, its = [], 0
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ts = time.perf_counter()
+        st = batch.solve(opts, stream=stream)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - ts) * 1e3)
+        its += sum(p.stats().krylov_its for p in probs)
+        log(f"step {k + 1}/{args.steps}: status={st} {lat[-1]:.2f} ms")
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    stats = [p.stats() for p in probs]
+    u32 = [p.query("u") for p in probs]
     result = {
         "metric": "IPM solves/s (2D Poisson 511^2, L1 + control and state boxes)",
-        "value": solves_per_s,
+        "value": B * args.steps / t,
         "unit": "IPM solves/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -293,43 +315,62 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
-        "data": "synthetic (seeded sine-mode desired state, workloads.poisson2d_511)",
-        "config": {"workload": f"poisson2d_511: 2D Poisson {data.N}x{data.N} interior, alpha=1e-4, beta=1e-3, "
-                               "u in [-5,5], y in [-0.2,0.3], sigma=0.2, IPM tol 1e-6",
-                   "krylov": "minres", "precond": "P_D", "mg_precision": "fp32", "vcycles": 1,
-                   "nu_pre": 2, "nu_post": 2, "krylov_tol": 1e-10, "status": rc},
+        "data": "synthetic (seeded sine-mode desired states, workloads.poisson2d_511 seeds 0..%d)" % (B - 1),
+        "config": {"workload": f"poisson2d_511 x{B}: 2D Poisson {args.N}x{args.N} interior, alpha=1e-4, "
+                               "beta=1e-3, u in [-5,5], y in [-0.2,0.3], sigma=0.2, IPM tol 1e-6; "
+                               f"{B} instances (seeds 0..{B - 1}) solved as one batch per step",
+                   "batch": B, "krylov": "minres", "precond": "P_D", "mg_precision": "fp32", "vcycles": 1,
+                   "nu_pre": 2, "nu_post": 2, "krylov_tol": 1e-10, "status": st},
         "krylov_its_per_s": its / t,
-        "nli": st.nli,
-        "krylov_its_per_solve": its / args.steps,
-        "krylov_its_per_ipm_step": st.hist_krylov[:st.nli],
-        "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
+        "nli": [s_.nli for s_ in stats],
+        "krylov_its_per_solve": its / (B * args.steps),
+        "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99), "of": "one batched step"},
     }
 
-    # roofline of the dominant kernel, timed live with HIP events on the solve stream
-    prob.newton_setup(st.mu if st.mu > 0 else 1e-6, opts)
-    ms, nbytes = prob.time_kernel(args.kernel, reps=200, opts=opts, stream=torch.cuda.current_stream())
+    # roofline of the dominant kernel of the batched step, timed with HIP events on the
+    # solve stream (one launch serves all instances)
+    ms, nbytes = batch.time_kernel(args.kernel, reps=100, opts=opts, stream=stream)
     achieved = nbytes / (ms * 1e-3) / 1e9
     result["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args),
                           "kernel": KERNEL_NAMES[args.kernel], "avg_us": ms * 1e3,
-                          "algorithmic_bytes_per_launch": nbytes}
+                          "algorithmic_bytes_per_launch": nbytes, "instances_per_launch": B}
     kern = {}
-    for k in (0, 2, 3, 4, 5, 6):
-        ms_k, b_k = prob.time_kernel(k, reps=100, opts=opts, stream=torch.cuda.current_stream())
+    for k in (2, 3, 4, 5, 6, 7):
+        ms_k, b_k = batch.time_kernel(k, reps=50, opts=opts, stream=stream)
         kern[KERNEL_NAMES[k]] = {"avg_us": ms_k * 1e3, "GB/s": b_k / (ms_k * 1e-3) / 1e9}
     result["kernels"] = kern
 
     if not args.no_fp64:
-        opts64 = Options(sigma=data.sigma, mg_precision="fp64")
-        t64, lat64, its64, st64, rc64 = time_solves(prob, opts64, max(2, args.steps // 2), 1, torch)
-        u64 = prob.query("u")
+        opts64 = Options(sigma=datas[0].sigma, mg_precision="fp64")
+        batch.solve(opts64, stream=stream)
+        torch.cuda.synchronize()
         n64 = max(2, args.steps // 2)
-        result["fp64_vcycles"] = {"solves_per_s": n64 / t64, "krylov_its_per_solve": its64 / n64,
-                                  "nli": st64.nli, "status": rc64,
-                                  "rel_l2_u_vs_fp32_path": float(np.linalg.norm(u32 - u64) / np.linalg.norm(u64))}
+        t0 = time.perf_counter()
+        for _ in range(n64):
+            batch.solve(opts64, stream=stream)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t0
+        u64 = [p.query("u") for p in probs]
+        result["fp64_vcycles"] = {
+            "solves_per_s": B * n64 / t64, "krylov_its_per_solve": sum(p.stats().krylov_its for p in probs) / B,
+            "status": [p.stats().status for p in probs],
+            "fp32_speedup": (B * args.steps / t) / (B * n64 / t64),
+            "max_rel_l2_u_vs_fp32_path": max(float(np.linalg.norm(a - c) / np.linalg.norm(c))
+                                             for a, c in zip(u32, u64))}
+    batch.close()
 
-    if args.batch > 0:
-        result["batched"] = bench_batched(W, torch, args.batch, 2)
+    # one instance alone (latency of a single solve)
+    single = probs[0]
+    ts, lat1, its1, st1, rc1 = time_solves(single, opts, max(3, args.steps // 2), 1, torch)
+    n1 = max(3, args.steps // 2)
+    result["single_instance"] = {"solves_per_s": n1 / ts, "krylov_its_per_s": its1 / ts, "nli": st1.nli,
+                                 "latency_ms": {"p50": percentile(lat1, 50), "p99": percentile(lat1, 99)},
+                                 "status": rc1}
+    data0 = datas[0]
+    for p in probs:
+        p.close()
+
     if args.serve_requests > 0:
         result["serving"] = bench_serving(W, torch, args.serve_requests, args.serve_slots, args.serve_budget_gib,
                                           loads)
@@ -339,8 +380,7 @@ def main():
 
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample ...")
-        result["cpu_baseline"] = cpu_baseline(data, st.nli)
-    prob.close()
+        result["cpu_baseline"] = cpu_baseline(data0, st1.nli)
     print(json.dumps(result), flush=True)
 
 

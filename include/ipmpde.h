@@ -253,6 +253,13 @@ void ipmpde_batch_destroy(ipmpde_batch* batch);
  * stats (ipmpde_get_stats) and its iterates are queryable. */
 int ipmpde_batch_solve(ipmpde_batch* batch, const ipmpde_options* opts, int per_problem, ipmpde_stream stream);
 
+/* ipmpde_time_kernel for a whole batch: one launch serves every instance;
+ * *bytes sums the instances' algorithmic bytes.  Requires a Newton setup by
+ * this batch (a batch solve) in the same multigrid precision; kernel 0 (the
+ * saddle matvec on explicit vectors) is for single problems only. */
+int ipmpde_batch_time_kernel(ipmpde_batch* batch, const ipmpde_options* opts, int kernel, int reps,
+                             ipmpde_stream stream, double* avg_ms, double* bytes);
+
 /* ---- serving engine: continuous batching of solves ----------------------
  *
  * A request is a problem (created as above) plus options.  Requests queue in

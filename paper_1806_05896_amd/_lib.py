@@ -109,6 +109,8 @@ SIGNATURES = {
     "ipmpde_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_void_p)]),
     "ipmpde_batch_destroy": (None, [C.c_void_p]),
     "ipmpde_batch_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
+    "ipmpde_batch_time_kernel": (C.c_int, [C.c_void_p, C.POINTER(COptions), C.c_int, C.c_int, C.c_void_p,
+                                           C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "ipmpde_engine_create": (C.c_int, [C.c_size_t, C.c_int, C.POINTER(C.c_void_p)]),
     "ipmpde_engine_destroy": (None, [C.c_void_p]),
     "ipmpde_engine_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(COptions), C.POINTER(C.c_uint64)]),

@@ -294,6 +294,13 @@ class Batch:
         L.check(self._lib.ipmpde_batch_solve(self._h, ptr, per, _stream_handle(stream)))
         return [p.stats().status for p in self.problems]
 
+    def time_kernel(self, kernel: int, reps: int = 50, opts: Optional[Options] = None, stream=None):
+        """(avg_ms, bytes) of one launch serving every instance (after a batch solve)."""
+        ms, b = C.c_double(), C.c_double()
+        L.check(self._lib.ipmpde_batch_time_kernel(self._h, Problem._opts(opts), kernel, reps, _stream_handle(stream),
+                                                   C.byref(ms), C.byref(b)))
+        return ms.value, b.value
+
     def close(self):
         if getattr(self, "_h", None):
             self._lib.ipmpde_batch_destroy(self._h)
