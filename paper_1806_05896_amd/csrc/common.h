@@ -334,6 +334,21 @@ __device__ __forceinline__ const T* mg_out(const Inst& I, int outsel) {
 }
 
 
+// Node of this thread in a stencil kernel.  The workgroups of a launch are
+// dispatched round-robin over the 8 XCDs, each with its own L2; the hardware
+// block index is remapped so that XCD x sweeps the x-th contiguous eighth of
+// the instance's blocks, which keeps the stencil's rows above and below a
+// block mostly in the same L2 instead of fetching them again.  The instance's
+// block count is rounded up to a multiple of 8, as every launch grid is
+// (nodes >= n mean "no node").  The map depends only on n, so an instance
+// computes the same partial sums alone and in a batch.
+__device__ __forceinline__ int xcd_node(int n) {
+  const int nb = ((n + kBS - 1) / kBS + 7) & ~7;
+  const int b = blockIdx.x;
+  if (b >= nb) return n;
+  return ((b & 7) * (nb >> 3) + (b >> 3)) * kBS + threadIdx.x;
+}
+
 // Start of every kernel: the instance of this block, skipped when inactive.
 #define INST_BEGIN                         \
   const Inst& I = Dp[blockIdx.z];          \

@@ -16,7 +16,7 @@ __device__ __forceinline__ double* fg_z(const Inst& I, int k) { return I.fZ + (s
 __global__ void __launch_bounds__(kBS) k_fg_matvec(const Inst* __restrict__ Dp, int j) {
   INST_BEGIN
   if (I.ctrl->stop) return;
-  const int i = blockIdx.x * kBS + threadIdx.x;
+  const int i = xcd_node(I.n);
   if (i >= I.n) return;
   double o[4];
   saddle_rows(I, fg_z(I, j), i, 1.0, o);

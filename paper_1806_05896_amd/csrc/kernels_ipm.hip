@@ -40,7 +40,7 @@ __global__ void __launch_bounds__(kBS) k_init_state(const Inst* __restrict__ Dp)
 __global__ void __launch_bounds__(kBS) k_measures(const Inst* __restrict__ Dp) {
   INST_BEGIN
   __shared__ double smem[3 * kBS / 64];
-  const int i = blockIdx.x * kBS + threadIdx.x;
+  const int i = xcd_node(I.n);
   double r[3] = {0.0, 0.0, 0.0};
   if (i < I.n) {
     int i1, i2, i3;
@@ -101,7 +101,7 @@ template <typename T>
 __global__ void __launch_bounds__(kBS) k_newton_setup(const Inst* __restrict__ Dp) {
   INST_BEGIN
   __shared__ double smem[kBS / 64];
-  const int i = blockIdx.x * kBS + threadIdx.x;
+  const int i = xcd_node(I.n);
   const double mu = I.mu;
   double acc[1] = {0.0};
   if (i < I.n) {
@@ -267,7 +267,7 @@ __global__ void __launch_bounds__(kBS) k_update(const Inst* __restrict__ Dp) {
 __global__ void __launch_bounds__(kBS) k_apply_op(const Inst* __restrict__ Dp, const double* __restrict__ x,
                                                   double* __restrict__ y, int transpose) {
   INST_BEGIN
-  const int i = blockIdx.x * kBS + threadIdx.x;
+  const int i = xcd_node(I.n);
   if (i >= I.n) return;
   int i1, i2, i3;
   node_coords(i, I.N, I.dim, i1, i2, i3);

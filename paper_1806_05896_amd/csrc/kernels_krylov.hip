@@ -77,7 +77,7 @@ __device__ __forceinline__ void apply_A11_inv(const Inst& I, int i, double ry, d
 __global__ void __launch_bounds__(kBS) k_saddle(const Inst* __restrict__ Dp, const double* __restrict__ x,
                                                 double* __restrict__ y) {
   INST_BEGIN
-  const int i = blockIdx.x * kBS + threadIdx.x;
+  const int i = xcd_node(I.n);
   if (i >= I.n) return;
   double o[4];
   saddle_rows(I, x, i, 1.0, o);
@@ -91,7 +91,7 @@ __global__ void __launch_bounds__(kBS) k_saddle(const Inst* __restrict__ Dp, con
 __global__ void __launch_bounds__(kBS) k_true_residual(const Inst* __restrict__ Dp) {
   INST_BEGIN
   __shared__ double smem[2 * kBS / 64];
-  const int i = blockIdx.x * kBS + threadIdx.x;
+  const int i = xcd_node(I.n);
   double acc[2] = {0.0, 0.0};
   if (i < I.n) {
     double o[4], m[4];
@@ -251,7 +251,7 @@ __global__ void __launch_bounds__(kBS) k_minres_k1(const Inst* __restrict__ Dp, 
   const double* __restrict__ Wother = I.W[par];
   double* __restrict__ X = I.X;
   double* __restrict__ Q = I.Q;
-  const int i = blockIdx.x * kBS + threadIdx.x;
+  const int i = xcd_node(I.n);
   double acc[1] = {0.0};
   if (i < I.n) {
     const int n = I.n;

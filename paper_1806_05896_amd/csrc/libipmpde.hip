@@ -189,7 +189,8 @@ static int level_count(int N) {
 
 static size_t pow_dim(int N, int dim) { return dim == 2 ? (size_t)N * N : (size_t)N * N * N; }
 
-static int nblk(long n) { return div_up(n, kBS); }
+// Blocks of a node-parallel launch, a multiple of 8 (one per XCD; see xcd_node).
+static int nblk(long n) { return (div_up(n, kBS) + 7) & ~7; }
 
 // LDS budget of the single-workgroup coarse kernel (gfx950 has 160 KB of
 // LDS per CU), and the largest grid it takes; finer levels run as
