@@ -2,13 +2,14 @@
 // multigrid of S_hat^-1 (Sec. 4.2) for the Poisson problems.
 //
 // Per node the kernels stage in LDS the diagonal d = 4/h^2 + m of A + M_hat
-// (m = the level's M_hat entry) and w = omega / d, so a damped-Jacobi sweep is
+// (m = the level's M_hat entry; the descent, which also needs d for the
+// residual) or w = omega / d (the ascent), so a damped-Jacobi sweep is
 //   x <- (1 - omega) x + w (b + h^-2 (sum of the four neighbours)),
 // and the residual is b + h^-2 (sum of the neighbours) - d x.  Nodes of the
-// LDS region outside the grid hold b = w = x = 0, which keeps the homogeneous
-// Dirichlet condition with no tests in the sweeps.  The tile size is a
-// template parameter (a launch choice); it changes no node's arithmetic, only
-// how much halo is recomputed.
+// LDS region outside the grid hold b = d = w = x = 0, which keeps the
+// homogeneous Dirichlet condition with no tests in the sweeps.  The tile size
+// is a template parameter (a launch choice); it changes no node's arithmetic,
+// only how much halo is recomputed.
 #include "common.h"
 
 namespace ipm {
@@ -17,13 +18,32 @@ __host__ __device__ constexpr int p2_down_width(int nu, int tc) { return 2 * tc 
 __host__ __device__ constexpr int p2_up_width(int nu, int tf) { return tf + 2 * nu; }
 __host__ __device__ constexpr int p2_up_coarse_width(int nu, int tf) { return p2_up_width(nu, tf) / 2 + 2; }
 template <typename T, int NU, int TC>
-constexpr size_t p2_down_lds() { return 5 * sizeof(T) * p2_down_width(NU, TC) * p2_down_width(NU, TC); }
+constexpr size_t p2_down_lds() { return 4 * sizeof(T) * p2_down_width(NU, TC) * p2_down_width(NU, TC); }
 template <typename T, int NU, int TF>
 constexpr size_t p2_up_lds() {
   return sizeof(T) * (4 * p2_up_width(NU, TF) * p2_up_width(NU, TF) +
                       p2_up_coarse_width(NU, TF) * p2_up_coarse_width(NU, TF));
 }
 constexpr size_t kStaticLdsMax = 65536;
+
+// Tile of this workgroup.  The tiles of a launch are dispatched round-robin
+// over the 8 XCDs; when an instance has a multiple of 8 tiles, XCD x takes
+// the x-th contiguous eighth of them (a band of tile rows), so the halo rows
+// a tile shares with the tiles above and below are mostly in the same L2.
+// The order of the tiles changes no node's arithmetic.
+__device__ __forceinline__ void xcd_tile(int& tx, int& ty) {
+  const int nx = gridDim.x, nt = nx * gridDim.y;
+  int t = blockIdx.x + nx * blockIdx.y;
+  if ((nt & 7) == 0) t = (t & 7) * (nt >> 3) + (t >> 3);
+  ty = t / nx;
+  tx = t - ty * nx;
+}
+
+// omega / d in the multigrid type (a hardware reciprocal in FP32).
+template <typename T>
+__device__ __forceinline__ T omega_over(T om, T d) { return om / d; }
+template <>
+__device__ __forceinline__ float omega_over<float>(float om, float d) { return om * __builtin_amdgcn_rcpf(d); }
 
 // Descent at level l for a tile of TC x TC coarse nodes: NU sweeps from a
 // zero iterate (the first is x = w b), the smoothed iterate of the tile's own
@@ -38,13 +58,15 @@ __global__ void __launch_bounds__(kBS) k_mg_down_p2(const Inst* __restrict__ Dp,
   const Level& F = I.lv[l];
   const Level& C = I.lv[l + 1];
   const int N = F.N, Nc = C.N;
-  const int J1 = blockIdx.x * TC, J2 = blockIdx.y * TC;
+  int tx, ty;
+  xcd_tile(tx, ty);
+  const int J1 = tx * TC, J2 = ty * TC;
   if (J1 >= Nc || J2 >= Nc) return;
   constexpr int W = p2_down_width(NU, TC);
-  __shared__ T bs[W * W], ds[W * W], ws[W * W], xa[W * W], xb[W * W];
+  __shared__ T bs[W * W], ds[W * W], xa[W * W], xb[W * W];
   const int o1 = 2 * J1 - NU, o2 = 2 * J2 - NU;  // fine coordinates of LDS (0, 0)
   const T* __restrict__ bsrc = (const T*)(scaled ? F.x2 : F.b);
-  const double* __restrict__ ty = scaled ? I.ty : nullptr;
+  const double* __restrict__ tyv = scaled ? I.ty : nullptr;
   const T* __restrict__ mh = (const T*)F.mh;
   const T ih2 = (T)(1.0 / (F.h * F.h));
   const T om = (T)I.omega, om1 = (T)1 - om;
@@ -56,17 +78,16 @@ __global__ void __launch_bounds__(kBS) k_mg_down_p2(const Inst* __restrict__ Dp,
     if ((unsigned)g1 < (unsigned)N && (unsigned)g2 < (unsigned)N) {
       const int gi = g1 + N * g2;
       bv = bsrc[gi];
-      if (ty) bv = (T)(1.0 + ty[gi]) * bv;
+      if (tyv) bv = (T)(1.0 + tyv[gi]) * bv;
       dv = (T)4 * ih2 + mh[gi];
-      wv = om / dv;
+      wv = omega_over<T>(om, dv);
     }
     bs[k] = bv;
     ds[k] = dv;
-    ws[k] = wv;
     xa[k] = wv * bv;
   }
   __syncthreads();
-  if (ty) {
+  if (tyv) {
     T* __restrict__ bout = (T*)F.b;
     for (int k = tid; k < 4 * TC * TC; k += kBS) {
       const int r2 = k / (2 * TC), r1 = k - r2 * (2 * TC);
@@ -82,7 +103,9 @@ __global__ void __launch_bounds__(kBS) k_mg_down_p2(const Inst* __restrict__ Dp,
     for (int k = tid; k < w * w; k += kBS) {
       const int r2 = k / w, r1 = k - r2 * w;
       const int li = (r1 + s) + W * (r2 + s);
-      c[li] = om1 * a[li] + ws[li] * (bs[li] + ih2 * ((a[li - 1] + a[li + 1]) + (a[li - W] + a[li + W])));
+      const T d = ds[li];
+      const T wv = d > (T)0 ? omega_over<T>(om, d) : (T)0;
+      c[li] = om1 * a[li] + wv * (bs[li] + ih2 * ((a[li - 1] + a[li + 1]) + (a[li - W] + a[li + W])));
     }
     __syncthreads();
     T* t = a; a = c; c = t;
@@ -125,11 +148,13 @@ __global__ void __launch_bounds__(kBS) k_mg_up_p2(const Inst* __restrict__ Dp, i
   if (!I.coarse_p2 || l >= I.coarse_lev || mg_skip(I, guard)) return;
   const Level& F = I.lv[l];
   const int N = F.N, Nc = I.lv[l + 1].N;
-  if ((int)(blockIdx.x * TF) >= N || (int)(blockIdx.y * TF) >= N) return;
+  int tx, ty;
+  xcd_tile(tx, ty);
+  if (tx * TF >= N || ty * TF >= N) return;
   constexpr int W = p2_up_width(NU, TF);
   constexpr int WC = p2_up_coarse_width(NU, TF);
   __shared__ T bs[W * W], ws[W * W], xa[W * W], xb[W * W], cs[WC * WC];
-  const int o1 = blockIdx.x * TF - NU, o2 = blockIdx.y * TF - NU;
+  const int o1 = tx * TF - NU, o2 = ty * TF - NU;
   // coarse 1-based index of the patch's first column/row: the lower coarse
   // neighbour of the region's first fine node (fine 1-based index o + 1)
   const int cb1 = (o1 + 1) >> 1, cb2 = (o2 + 1) >> 1;
@@ -152,7 +177,7 @@ __global__ void __launch_bounds__(kBS) k_mg_up_p2(const Inst* __restrict__ Dp, i
     if ((unsigned)g1 < (unsigned)N && (unsigned)g2 < (unsigned)N) {
       const int gi = g1 + N * g2;
       bv = b[gi];
-      wv = om / ((T)4 * ih2 + mh[gi]);
+      wv = omega_over<T>(om, (T)4 * ih2 + mh[gi]);
       xv = xpre[gi];
     }
     bs[k] = bv;
@@ -194,7 +219,7 @@ __global__ void __launch_bounds__(kBS) k_mg_up_p2(const Inst* __restrict__ Dp, i
   T* __restrict__ xout = (T*)F.x2;
   for (int k = tid; k < TF * TF; k += kBS) {
     const int r2 = k / TF, r1 = k - r2 * TF;
-    const int g1 = blockIdx.x * TF + r1, g2 = blockIdx.y * TF + r2;
+    const int g1 = tx * TF + r1, g2 = ty * TF + r2;
     if (g1 < N && g2 < N) xout[g1 + N * g2] = a[(NU + r1) + W * (NU + r2)];
   }
 }
