@@ -106,6 +106,24 @@ def cpu_baseline(data, nli):
                       + (f"; OMP_NUM_THREADS={threads}" if threads else "")}
 
 
+def copy_ceiling(torch, reps=10):
+    """Device-to-device copy of 1 GiB (larger than the 256 MB Infinity Cache):
+    the attainable HBM bandwidth on this machine, read + write bytes over time."""
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    gbs = 2 * src.numel() * 8 / (ms * 1e-3) / 1e9
+    del src, dst
+    return gbs
+
+
 def solver_options(d, Options, prec="fp32"):
     """Per-request solver choice: MINRES + P_D for Poisson, FGMRES(30) + P_T
     for convection-diffusion, multigrid in the given precision."""
@@ -335,6 +353,9 @@ def main():
                           "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args),
                           "kernel": KERNEL_NAMES[args.kernel], "avg_us": ms * 1e3,
                           "algorithmic_bytes_per_launch": nbytes, "instances_per_launch": B}
+    ceiling = copy_ceiling(torch)
+    result["roofline"]["copy_ceiling_GBps"] = ceiling
+    result["roofline"]["frac_of_copy_ceiling"] = achieved / ceiling
     kern = {}
     for k in (2, 3, 4, 5, 6, 7):
         ms_k, b_k = batch.time_kernel(k, reps=50, opts=opts, stream=stream)
