@@ -35,6 +35,12 @@ Readings taken where the paper is silent, garbled or ambiguous:
   R7  primal variables (y, z) move with alpha_P, dual ones (p, lambdas) with
       alpha_D, as Algorithm A.1 states.
   R8  "no state bounds" means the lambda_y blocks are absent and Theta_y = 0.
+  R9  partial observation (Sec. 4.3): the tracking term is taken over the
+      observed nodes only, 1/2 (y - y_d)^T O (y - y_d) with O = diag(obs)
+      (the unit-mass form of the mass matrix of the observation region), so
+      O replaces M = I in the (1,1) block and in the first row of eq.
+      (prdu); O + Theta_y is singular where a node is unobserved and has no
+      state bound, and only the full 4n system is solved directly.
 
 Option beyond the paper (off by default): mu_rule = "central" takes the
 barrier target from the current iterate, mu^{k+1} = sigma * (mean of the
@@ -119,6 +125,12 @@ class _Bounds:
             self.yb = np.asarray(prob.y_b, dtype=np.float64)
 
 
+def _obs(prob) -> np.ndarray:
+    """Observation weights O (R9): ones when the whole domain is observed."""
+    o = getattr(prob, "obs", None)
+    return np.ones(prob.n) if o is None else np.asarray(o, dtype=np.float64)
+
+
 def initial_state(prob, opts: IPMOptions) -> IPMState:
     """Starting point (reading R3)."""
     bd = _Bounds(prob)
@@ -141,7 +153,7 @@ def residuals(prob, disc: Discretization, st: IPMState):
     A, a, b = disc.A, prob.alpha, prob.beta
     u = st.w - st.v
     xi_p = A @ st.y - u - disc.f_hat
-    dy = st.y - prob.y_d + A.T @ st.p
+    dy = _obs(prob) * (st.y - prob.y_d) + A.T @ st.p
     if bd.has_y:
         dy = dy - st.lya + st.lyb
     dw = a * u + b - st.p - st.lwa + st.lwb
@@ -195,7 +207,7 @@ def newton_matrix(prob, disc: Discretization, st: IPMState) -> sp.csc_matrix:
     Z = None
     A = disc.A
     K = sp.bmat([
-        [sp.diags(1.0 + ty), Z, Z, A.T],
+        [sp.diags(_obs(prob) + ty), Z, Z, A.T],
         [Z, sp.diags(a + tw), -a * I, -I],
         [Z, -a * I, sp.diags(a + tv), I],
         [A, -I, I, Z],
@@ -208,7 +220,7 @@ def newton_rhs(prob, disc: Discretization, st: IPMState, mu: float) -> np.ndarra
     bd = _Bounds(prob)
     A, a, b = disc.A, prob.alpha, prob.beta
     u = st.w - st.v
-    ry = st.y - prob.y_d + A.T @ st.p
+    ry = _obs(prob) * (st.y - prob.y_d) + A.T @ st.p
     if bd.has_y:
         ry = ry - mu / (st.y - bd.ya) + mu / (bd.yb - st.y)
     rw = a * u + b - st.p - mu / (st.w - bd.zaw) + mu / (bd.zbw - st.w)
@@ -230,8 +242,11 @@ def newton_solve(prob, disc: Discretization, st: IPMState, mu: float, mode: str 
     with Sigma = (theta_w + theta_v) / (alpha (theta_w + theta_v) + theta_w theta_v),
     the diagonal form that eq. (Schur) takes for M = I."""
     n = prob.n
+    ty, tw, tv = barrier_diagonals(prob, st)
     if mode == "auto":
         mode = "full" if (prob.dim == 2 and prob.N <= 127) or (prob.dim == 3 and prob.N <= 31) else "schur"
+        if not np.all(_obs(prob) + ty > 0):  # (1,1) block singular (R9): no elimination of dy
+            mode = "full"
     rhs = newton_rhs(prob, disc, st, mu)
     if mode == "full":
         K = newton_matrix(prob, disc, st)
@@ -240,10 +255,9 @@ def newton_solve(prob, disc: Discretization, st: IPMState, mu: float, mode: str 
     if mode != "schur":
         raise ValueError(mode)
     a = prob.alpha
-    ty, tw, tv = barrier_diagonals(prob, st)
     by, bw, bv, bp = rhs[:n], rhs[n:2 * n], rhs[2 * n:3 * n], rhs[3 * n:]
     A = disc.A
-    dyinv = 1.0 / (1.0 + ty)
+    dyinv = 1.0 / (_obs(prob) + ty)
     det = a * (tw + tv) + tw * tv
     sigma_d = (tw + tv) / det
     S = (A @ sp.diags(dyinv) @ A.T + sp.diags(sigma_d)).tocsc()

@@ -71,12 +71,14 @@ def sine_eigenvalue(dim, N, ks):
     return sum(4.0 / h ** 2 * math.sin(k * math.pi * h / 2) ** 2 for k in ks)
 
 
-def fista(A, yd, fhat, alpha, beta, ua, ub, iters=20000, tol=1e-15):
-    """min_u 1/2|A^-1(u+fhat) - yd|^2 + alpha/2|u|^2 + beta|u|_1, ua <= u <= ub."""
+def fista(A, yd, fhat, alpha, beta, ua, ub, iters=20000, tol=1e-15, obs=None):
+    """min_u 1/2 (y - yd)^T O (y - yd) + alpha/2|u|^2 + beta|u|_1 with
+    y = A^-1 (u + fhat), ua <= u <= ub, O = diag(obs) (identity if None)."""
     Ainv = np.linalg.inv(A)
-    G = Ainv.T @ Ainv
+    O = np.eye(A.shape[0]) if obs is None else np.diag(obs)
+    G = Ainv.T @ O @ Ainv
     L = np.linalg.eigvalsh(G).max() + alpha
-    c = Ainv.T @ (Ainv @ fhat - yd)
+    c = Ainv.T @ O @ (Ainv @ fhat - yd)
     u = np.zeros(A.shape[0]); z = u.copy(); t = 1.0
     for _ in range(iters):
         grad = G @ z + c + alpha * z

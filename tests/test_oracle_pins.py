@@ -340,3 +340,77 @@ def test_fixed_decrease_breakdown_and_central_rule():
     r = oracle.solve(p, IPMOptions(sigma=p.sigma, maxit=60, mu_rule="central"))
     assert r.status == "converged"
     assert max(measures(p, discretize(p), r.state)) <= 1e-6
+
+
+def test_partial_observation_matches_weighted_fista():
+    """Partial observation (Sec. 4.3, reading R9): the IPM optimum equals an
+    independent FISTA solution of the reduced problem in u with the tracking
+    term taken over the observed nodes only."""
+    N = 7
+    p = W.poisson2d_small(seed=6, N=N)
+    x1, x2 = W.interior_coords(2, N)
+    p.obs = ((x1 < 0.55) & (x2 > 0.3)).astype(float)  # an observed corner region
+    rng = np.random.default_rng(13)  # zero, free and both bound-active controls all occur
+    p.y_d = W.sine_modes(rng, 2, N, 4, 3)[0] * 2.0
+    p.beta = 2e-3
+    p.u_a[:] = -1.5; p.u_b[:] = 1.0
+    A = I.dense_operator(2, N)
+    u_ref, y_ref = I.fista(A, p.y_d, np.zeros(p.n), p.alpha, p.beta, p.u_a, p.u_b, obs=p.obs)
+    r = oracle.solve(p, IPMOptions(eps_p=1e-12, eps_d=1e-12, eps_c=1e-12))
+    assert r.status == "converged"
+    assert 0 < p.obs.sum() < p.n
+    assert (np.abs(u_ref) < 1e-12).sum() > 0 and (np.abs(u_ref - p.u_b) < 1e-12).sum() > 0
+    assert (np.abs(u_ref - p.u_a) < 1e-12).sum() > 0
+    np.testing.assert_allclose(r.u, u_ref, rtol=0, atol=1e-7)
+    np.testing.assert_allclose(r.y, y_ref, rtol=0, atol=1e-8)
+
+
+def test_full_observation_weights_change_nothing():
+    """obs = 1 everywhere is the problem without observation weights."""
+    p = W.poisson2d_small(seed=1, N=15)
+    q = p.copy()
+    q.obs = np.ones(p.n)
+    a = oracle.solve(p, IPMOptions(sigma=0.2))
+    b = oracle.solve(q, IPMOptions(sigma=0.2))
+    assert a.nli == b.nli
+    np.testing.assert_array_equal(a.u, b.u)
+
+
+def test_partial_observation_preconditioner_with_exact_blocks():
+    """The preconditioner P_Pi of Sec. 4.3 (eq. (eq:prec1)), built with exact
+    L^-1, (alpha M~ + Theta_z)^-1 and the exact Schur complement S_Pi of the
+    permuted system, makes P_Pi^-1 K an involution (block triangular with
+    identity diagonal blocks up to sign), so GMRES needs two iterations; and
+    the paper's three-step application v2 = (alpha M~ + Theta_z)^-1 w2,
+    v1 = L^-1 (Mbar v2 + w3), v3 = S^-1 ((M + Theta_y) v1 - w1) equals the
+    dense inverse of eq. (eq:prec1)."""
+    from oracle.fd import discretize
+    from oracle.ipm import barrier_diagonals, initial_state, ipm_step, newton_matrix
+    p = W.poisson2d_partial(seed=0, N=5)
+    opts = IPMOptions(sigma=p.sigma)
+    disc = discretize(p)
+    st = initial_state(p, opts)
+    for _ in range(3):
+        st, _ = ipm_step(p, disc, st, opts, st.mu * opts.sigma)
+    n, a = p.n, p.alpha
+    K = newton_matrix(p, disc, st).toarray()
+    ty, tw, tv = barrier_diagonals(p, st)
+    L = disc.A.toarray()
+    Mo = np.diag(p.obs + ty)                      # M + Theta_y (observation form)
+    Az = np.block([[np.diag(a + tw), -a * np.eye(n)], [-a * np.eye(n), np.diag(a + tv)]])
+    Mbar = np.hstack([np.eye(n), -np.eye(n)])     # u = w - v
+    Li, Azi = np.linalg.inv(L), np.linalg.inv(Az)
+    S = L.T + Mo @ Li @ Mbar @ Azi @ Mbar.T
+    Si = np.linalg.inv(S)
+    # eq. (eq:prec1), unknown order [y; z; p]
+    Pinv = np.block([[np.zeros((n, n)), Li @ Mbar @ Azi, Li],
+                     [np.zeros((2 * n, n)), Azi, np.zeros((2 * n, n))],
+                     [-Si, Si @ Mo @ Li @ Mbar @ Azi, Si @ Mo @ Li]])
+    T = Pinv @ K
+    assert np.abs(T @ T - np.eye(4 * n)).max() <= 1e-8 * np.abs(T).max() ** 2
+    w = np.random.default_rng(2).normal(size=4 * n)
+    w1, w2, w3 = w[:n], w[n:3 * n], w[3 * n:]
+    v2 = Azi @ w2
+    v1 = Li @ (Mbar @ v2 + w3)
+    v3 = Si @ (Mo @ v1 - w1)
+    np.testing.assert_allclose(np.concatenate([v1, v2, v3]), Pinv @ w, rtol=1e-10, atol=1e-12)

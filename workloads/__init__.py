@@ -38,6 +38,7 @@ CONFIG_IDS = {
     "poisson3d_127": 2,
     "convdiff2d_255": 3,
     "served_mix": 4,
+    "poisson2d_partial": 5,
 }
 
 
@@ -61,6 +62,9 @@ class ProblemData:
     sigma: float = 0.2  # recommended barrier reduction factor for this class
     name: str = ""
     meta: dict = field(default_factory=dict)
+    # observation weights (1 where the state is observed, 0 elsewhere); None:
+    # the whole domain is observed
+    obs: Optional[np.ndarray] = None
 
     @property
     def n(self) -> int:
@@ -76,7 +80,7 @@ class ProblemData:
 
         return ProblemData(self.dim, self.N, self.pde, self.eps, self.alpha, self.beta,
                            c(self.u_a), c(self.u_b), c(self.y_a), c(self.y_b), c(self.y_d),
-                           c(self.f), c(self.g), self.sigma, self.name, dict(self.meta))
+                           c(self.f), c(self.g), self.sigma, self.name, dict(self.meta), c(self.obs))
 
 
 def rng_for(config: str, instance: int = 0, seed: int = 0) -> np.random.Generator:
@@ -158,6 +162,19 @@ def convdiff2d_255(seed: int = 0, N: int = 255, eps: float = 1.0 / 200.0, instan
                        None, None, y_d, None, None, 0.4, "convdiff2d_255", {"modes": modes})
 
 
+def poisson2d_partial(seed: int = 0, N: int = 255, instance: int = 0) -> ProblemData:
+    """Partial observation: the state is observed on the central square
+    (0.25, 0.75)^2 only (weights 1 there, 0 elsewhere), 8 sine modes for y_d,
+    alpha = 1e-4, beta = 1e-3, u in [-5, 5], no state bounds, sigma = 0.25."""
+    rng = rng_for("poisson2d_partial", instance, seed)
+    y_d, modes = sine_modes(rng, 2, N)
+    x1, x2 = interior_coords(2, N)
+    obs = ((x1 > 0.25) & (x1 < 0.75) & (x2 > 0.25) & (x2 < 0.75)).astype(np.float64)
+    n = N * N
+    return ProblemData(2, N, "poisson", 1.0, 1e-4, 1e-3, _const(n, -5.0), _const(n, 5.0), None, None,
+                       y_d, None, None, 0.25, "poisson2d_partial", {"modes": modes}, obs)
+
+
 def served_requests(n_requests: int = 256, seed: int = 0, sizes=(31, 63, 127, 255), rate: float = 1.0):
     """Request stream for the serving workload: (arrival_time, ProblemData) pairs.
 
@@ -192,4 +209,5 @@ def served_requests(n_requests: int = 256, seed: int = 0, sizes=(31, 63, 127, 25
 
 def by_name(name: str, seed: int = 0, **kw) -> ProblemData:
     return {"poisson2d_small": poisson2d_small, "poisson2d_511": poisson2d_511,
-            "poisson3d_127": poisson3d_127, "convdiff2d_255": convdiff2d_255}[name](seed=seed, **kw)
+            "poisson3d_127": poisson3d_127, "convdiff2d_255": convdiff2d_255,
+            "poisson2d_partial": poisson2d_partial}[name](seed=seed, **kw)
