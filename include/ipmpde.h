@@ -61,7 +61,7 @@ enum {
 
 enum { IPMPDE_POISSON = 0, IPMPDE_CONVDIFF = 1 };
 enum { IPMPDE_MINRES = 0, IPMPDE_FGMRES = 1 };
-enum { IPMPDE_PD = 0, IPMPDE_PT = 1 };
+enum { IPMPDE_PD = 0, IPMPDE_PT = 1, IPMPDE_PPI = 2 };
 enum { IPMPDE_FP64 = 0, IPMPDE_FP32 = 1 };
 enum { IPMPDE_MU_PAPER = 0, IPMPDE_MU_CENTRAL = 1 };
 
@@ -87,7 +87,9 @@ typedef struct {
   int ipm_maxit;       /* default 200 */
   int fixed_nli;       /* > 0: take exactly this many IPM steps (parity runs); default 0 */
   int krylov;          /* IPMPDE_MINRES (default) | IPMPDE_FGMRES */
-  int precond;         /* IPMPDE_PD (default) | IPMPDE_PT (requires FGMRES) */
+  int precond;         /* IPMPDE_PD (default) | IPMPDE_PT (requires FGMRES) |
+                          IPMPDE_PPI, the partial-observation preconditioner of
+                          Sec. 4.3 (requires FGMRES) */
   int restart;         /* FGMRES restart length; default 30 */
   double krylov_tol;   /* relative unpreconditioned residual |b - K x| / |b|; default 1e-10 (Sec. 6) */
   int krylov_maxit;    /* default 500 */
@@ -154,6 +156,15 @@ int ipmpde_problem_create(const ipmpde_grid* grid, const ipmpde_pde* pde, double
                           const double* y_d, const double* f, const double* g, ipmpde_problem** out);
 
 void ipmpde_problem_destroy(ipmpde_problem* prob);
+
+/* Partial observation (Sec. 4.3): the tracking term becomes
+ * 1/2 (y - y_d)^T O (y - y_d) with O = diag(weights) (n values, finite and
+ * >= 0; 1 = observed), replacing the identity in the (1,1) block of the
+ * Newton system.  weights NULL restores full observation.  When some weight
+ * is 0 and the problem has no state bounds the (1,1) block is singular and
+ * only IPMPDE_PPI (with FGMRES) may be used (other preconditioners give
+ * IPMPDE_EINVAL at solve).  Adds n doubles of device memory. */
+int ipmpde_set_observation(ipmpde_problem* prob, const double* weights, size_t count);
 
 /* Bytes of device memory a problem of this shape holds while it is solved
  * with these options (opts NULL = defaults): data, iterates and barrier

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(_HERE, "libipmpde.so")
 OK, EINVAL, ENOMEM, EDEVICE, ENOTCONVERGED, EKRYLOV, EBREAKDOWN = range(7)
 POISSON, CONVDIFF = 0, 1
 MINRES, FGMRES = 0, 1
-PD, PT = 0, 1
+PD, PT, PPI = 0, 1, 2
 FP64, FP32 = 0, 1
 MU_PAPER, MU_CENTRAL = 0, 1
 MAX_HIST = 256
@@ -89,6 +89,7 @@ SIGNATURES = {
     "ipmpde_footprint_bytes": (C.c_size_t, [C.POINTER(Grid), C.POINTER(Pde), C.c_int, C.POINTER(COptions)]),
     "ipmpde_solve": (C.c_int, [C.c_void_p, C.POINTER(COptions), C.c_void_p]),
     "ipmpde_query": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_size_t]),
+    "ipmpde_set_observation": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "ipmpde_set_field": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_size_t]),
     "ipmpde_reset": (C.c_int, [C.c_void_p, C.POINTER(COptions), C.c_void_p]),
     "ipmpde_ipm_step": (C.c_int, [C.c_void_p, C.POINTER(COptions), C.c_double, C.c_void_p,

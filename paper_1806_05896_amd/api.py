@@ -52,7 +52,7 @@ class Options:
     ipm_maxit: int = 200
     fixed_nli: int = 0
     krylov: str = "minres"          # "minres" | "fgmres"
-    precond: str = "pd"             # "pd" | "pt"
+    precond: str = "pd"             # "pd" | "pt" | "ppi" (partial observation, FGMRES)
     restart: int = 30
     krylov_tol: float = 1e-10
     krylov_maxit: int = 500
@@ -72,7 +72,7 @@ class Options:
             if f.name == "krylov":
                 v = {"minres": L.MINRES, "fgmres": L.FGMRES}[v]
             elif f.name == "precond":
-                v = {"pd": L.PD, "pt": L.PT}[v]
+                v = {"pd": L.PD, "pt": L.PT, "ppi": L.PPI}[v]
             elif f.name == "mg_precision":
                 v = {"fp64": L.FP64, "fp32": L.FP32}[v]
             elif f.name == "use_graphs":
@@ -135,11 +135,12 @@ class Problem:
     """One problem instance resident on the GPU (ipmpde_problem)."""
 
     def __init__(self, data=None, *, dim=None, N=None, pde="poisson", eps=1.0, alpha=None, beta=None,
-                 u_a=None, u_b=None, y_a=None, y_b=None, y_d=None, f=None, g=None):
+                 u_a=None, u_b=None, y_a=None, y_b=None, y_d=None, f=None, g=None, obs=None):
         if data is not None:
             dim, N, pde, eps = data.dim, data.N, data.pde, data.eps
             alpha, beta = data.alpha, data.beta
             u_a, u_b, y_a, y_b, y_d, f, g = data.u_a, data.u_b, data.y_a, data.y_b, data.y_d, data.f, data.g
+            obs = getattr(data, "obs", None)
         self._lib = L.load()
         self.dim, self.N = int(dim), int(N)
         self.n = self.N ** self.dim
@@ -155,6 +156,16 @@ class Problem:
         self._h = h
         self.has_state_bounds = y_a is not None
         self._keep = None
+        if obs is not None:
+            self.set_observation(obs)
+
+    def set_observation(self, weights):
+        """Observation weights O (Sec. 4.3); None: the whole domain."""
+        if weights is None:
+            L.check(self._lib.ipmpde_set_observation(self._h, None, 0))
+            return
+        w = _f64(weights, self.n, "obs")
+        L.check(self._lib.ipmpde_set_observation(self._h, _ptr(w), self.n))
 
     def close(self):
         if getattr(self, "_h", None):

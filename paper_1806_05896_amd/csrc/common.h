@@ -24,7 +24,8 @@ struct Level {
   void* x;    // iterate
   void* x2;   // second iterate buffer (Jacobi ping-pong)
   void* b;    // right-hand side
-  void* mh;   // diagonal reaction term M_hat restricted to this level
+  void* mh;   // diagonal reaction term of the operator being solved with (M_hat restricted to this level)
+  void* mhb;  // base of the level's reaction-term slots (n each): 0 M_hat (P_Pi: Sigma), 1 O + Theta_y, 2 zero
 };
 
 // Scalars of one Krylov solve, in device memory.
@@ -99,6 +100,10 @@ struct Inst {
   int coarse_lev;       // first level handled by the single-workgroup kernel
   int coarse_p2;        // 1: the coarse levels run in the padded 2D Poisson kernel
   void* cpack;          // Poisson 2D: the coarse levels' LDS image (zero iterates, d, 1/d), built per Newton setup
+  void* cpackb;         // base of the coarse LDS images of the three reaction-term slots
+  int cpack_slot;       // elements between two slots' images
+  const double* obs;    // observation weights O (nullptr: the whole domain, O = I)
+  int ppi;              // 1: the partial-observation preconditioner P_Pi (three multigrid operators)
   void* kc_b0;          // k-cycle solves (vcycles > 1): the solve's level-0 right-hand side
   void* kc_s[2];        // and its accumulated iterate (ping-pong)
   int cpack_elems;      // its length in elements of the multigrid type
@@ -333,6 +338,9 @@ __device__ __forceinline__ const T* mg_out(const Inst& I, int outsel) {
   return (const T*)((I.coarse_lev == 0 || !outsel) ? I.lv[0].x : I.lv[0].x2);
 }
 
+
+// Observation weight of node i (the (1,1) block is O + Theta_y).
+__device__ __forceinline__ double obs_w(const Inst& I, int i) { return I.obs ? I.obs[i] : 1.0; }
 
 // Node of this thread in a stencil kernel.  The workgroups of a launch are
 // dispatched round-robin over the 8 XCDs, each with its own L2; the hardware

@@ -52,7 +52,7 @@ __global__ void __launch_bounds__(kBS) k_measures(const Inst* __restrict__ Dp) {
     const double ua = I.ua[i], ub = I.ub[i];
     const double lwa = I.lwa[i], lwb = I.lwb[i], lva = I.lva[i], lvb = I.lvb[i];
     r[0] = fabs(Ay - u - I.fhat[i]);
-    double dy = y - I.yd[i] + ATp;
+    double dy = obs_w(I, i) * (y - I.yd[i]) + ATp;
     double pc = nmax(nmax(w * lwa, (ub - w) * lwb), nmax(v * lva, (-ua - v) * lvb));
     if (I.has_y) {
       const double lya = I.lya[i], lyb = I.lyb[i];
@@ -92,11 +92,13 @@ __global__ void __launch_bounds__(kBS) k_compl_mean(const Inst* __restrict__ Dp)
 }
 
 // Barrier diagonals Theta_y, Theta_w, Theta_v (Sec. 3, below eq.
-// (NewtonSystem)), the matching term M_hat = sqrt(Sigma (1 + Theta_y)) with
+// (NewtonSystem)), the matching term M_hat = sqrt(Sigma (O + Theta_y)) with
 // Sigma = (t_w + t_v) / (alpha (t_w + t_v) + t_w t_v) (eq. (Schur) and the
-// M_hat of Sec. 4.2 with M = D_M = I), and the right-hand side of eq.
-// (NewtonSystem) at barrier I.mu; |rhs|_2 -> ctrl->bnorm.  M_hat is also
-// written, in the V-cycle precision T, to the finest multigrid level.
+// M_hat of Sec. 4.2 with M = D_M = I, O the observation weights), and the
+// right-hand side of eq. (NewtonSystem) at barrier I.mu; |rhs|_2 ->
+// ctrl->bnorm.  The reaction term of the multigrid operator is written, in
+// the V-cycle precision T, to the finest level: M_hat, or for P_Pi (Sec. 4.3)
+// M_r = Sigma in slot 0 and M_l = O + Theta_y in slot 1.
 template <typename T>
 __global__ void __launch_bounds__(kBS) k_newton_setup(const Inst* __restrict__ Dp) {
   INST_BEGIN
@@ -119,16 +121,18 @@ __global__ void __launch_bounds__(kBS) k_newton_setup(const Inst* __restrict__ D
       by = -mu / gya + mu / gyb;
     }
     const double sig = (tw + tv) / (I.alpha * (tw + tv) + tw * tv);
-    const double mh = sqrt(sig * (1.0 + ty));
+    const double ow = obs_w(I, i);
+    const double mh = I.ppi ? sig : sqrt(sig * (ow + ty));
     I.ty[i] = ty;
     I.tw[i] = tw;
     I.tv[i] = tv;
     I.mh[i] = mh;
     ((T*)I.lv[0].mh)[i] = (T)mh;
+    if (I.ppi) ((T*)I.lv[0].mhb)[I.n + i] = (T)(ow + ty);
     const double u = w - v;
     const double Ay = apply_op<double>(I.y, i, i1, i2, i3, I.N, I.dim, I.pde, I.h, I.eps, false);
     const double ATp = apply_op<double>(I.p, i, i1, i2, i3, I.N, I.dim, I.pde, I.h, I.eps, true);
-    const double ry = -(y - I.yd[i] + ATp + by);
+    const double ry = -(ow * (y - I.yd[i]) + ATp + by);
     const double rw = -(I.alpha * u + I.beta - p - mu / w + mu / gwb);
     const double rv = -(-I.alpha * u + I.beta + p - mu / v + mu / gvb);
     const double rp = -(Ay - u - I.fhat[i]);

@@ -39,7 +39,7 @@ __device__ __forceinline__ void saddle_rows(const Inst& I, const double* __restr
   const double ATxp = apply_op<double>(x + 3 * n, i, i1, i2, i3, I.N, I.dim, I.pde, I.h, I.eps, true);
   const double Axy = apply_op<double>(x, i, i1, i2, i3, I.N, I.dim, I.pde, I.h, I.eps, false);
   const double xp = x[3 * n + i];
-  out[0] = s * ((1.0 + ty) * xy + ATxp);
+  out[0] = s * ((obs_w(I, i) + ty) * xy + ATxp);
   out[1] = s * ((a + tw) * xw - a * xv - xp);
   out[2] = s * (-a * xw + (a + tv) * xv + xp);
   out[3] = s * (Axy - xw + xv);
@@ -56,21 +56,27 @@ __device__ __forceinline__ void saddle_rows_abs(const Inst& I, const double* __r
   const int NN = I.N * I.N;
   const double ATxp = 2.0 * d * xp - apply_op_s<double, true>(x + 3 * n, i, i1, i2, i3, I.N, I.N, NN, I.dim, I.pde, I.h, I.eps, true);
   const double Axy = 2.0 * d * xy - apply_op_s<double, true>(x, i, i1, i2, i3, I.N, I.N, NN, I.dim, I.pde, I.h, I.eps, false);
-  out[0] = (1.0 + ty) * xy + ATxp;
+  out[0] = (obs_w(I, i) + ty) * xy + ATxp;
   out[1] = (a + tw) * xw + a * xv + xp;
   out[2] = a * xw + (a + tv) * xv + xp;
   out[3] = Axy + xw + xv;
 }
 
-// Exact inverse of the (1,1) block of P_D at node i: 1/(1+Th_y) on y and the
-// per-node 2x2 inverse of [a+t_w, -a; -a, a+t_v] (Sec. 4.1 with D_M = M = I).
-__device__ __forceinline__ void apply_A11_inv(const Inst& I, int i, double ry, double rw, double rv, double& zy,
-                                              double& zw, double& zv) {
-  const double ty = I.ty[i], tw = I.tw[i], tv = I.tv[i], a = I.alpha;
-  zy = ry / (1.0 + ty);
+// Per-node inverse of the z block [a+t_w, -a; -a, a+t_v] (alpha M~ + Theta_z
+// with M = I; Sec. 4.1).
+__device__ __forceinline__ void apply_z_inv(const Inst& I, int i, double rw, double rv, double& zw, double& zv) {
+  const double tw = I.tw[i], tv = I.tv[i], a = I.alpha;
   const double det = a * (tw + tv) + tw * tv;
   zw = ((a + tv) * rw + a * rv) / det;
   zv = (a * rw + (a + tw) * rv) / det;
+}
+
+// Exact inverse of the (1,1) block of P_D at node i: 1/(O+Th_y) on y and the
+// per-node 2x2 inverse on (w, v) (Sec. 4.1 with D_M = M = I).
+__device__ __forceinline__ void apply_A11_inv(const Inst& I, int i, double ry, double rw, double rv, double& zy,
+                                              double& zw, double& zv) {
+  zy = ry / (obs_w(I, i) + I.ty[i]);
+  apply_z_inv(I, i, rw, rv, zw, zv);
 }
 
 // y = K x (single instance)
@@ -187,6 +193,60 @@ __global__ void __launch_bounds__(kBS) k_pt_rhs(const Inst* __restrict__ Dp, con
   const double* z = zx ? zx : I.fZ + (size_t)j * 4 * n;
   const double Bz = apply_op<double>(z, i, i1, i2, i3, I.N, I.dim, I.pde, I.h, I.eps, false) - z[n + i] + z[2 * n + i];
   ((T*)I.lv[0].b)[i] = (T)(Bz - r[3 * n + i]);
+}
+
+// Partial-observation preconditioner P_Pi (Sec. 4.3, eq. (eq:prec1)), applied
+// as v2 = (alpha M~ + Theta_z)^-1 r_z, v1 = L^-1 (Mbar v2 + r_p),
+// v3 = S_Pi^-1 ((O + Theta_y) v1 - r_y), with S_Pi approximated by
+// (L^T + M_l) L^-1 (L + M_r), M_l = O + Theta_y and M_r = Sigma (the
+// diagonal of Mbar (alpha M~ + Theta_z)^-1 Mbar^T), every solve by multigrid.
+// Step a: z_w, z_v and the right-hand side Mbar v2 + r_p of the L solve.
+template <typename T>
+__global__ void __launch_bounds__(kBS) k_ppi_a(const Inst* __restrict__ Dp, const double* __restrict__ rx,
+                                               double* __restrict__ zx, int j, int guard) {
+  INST_BEGIN
+  if (guard && I.ctrl->stop) return;
+  const int i = blockIdx.x * kBS + threadIdx.x;
+  if (i >= I.n) return;
+  const int n = I.n;
+  const double* r = rx ? rx : I.fV + (size_t)j * 4 * n;
+  double* z = zx ? zx : I.fZ + (size_t)j * 4 * n;
+  double zw, zv;
+  apply_z_inv(I, i, r[n + i], r[2 * n + i], zw, zv);
+  z[n + i] = zw;
+  z[2 * n + i] = zv;
+  ((T*)I.lv[0].b)[i] = (T)(zw - zv + r[3 * n + i]);
+}
+
+// Step b: z_y = v1 (the L solve's output) and the right-hand side
+// (O + Theta_y) v1 - r_y of the solve with L^T + M_l.
+template <typename T>
+__global__ void __launch_bounds__(kBS) k_ppi_b(const Inst* __restrict__ Dp, const double* __restrict__ rx,
+                                               double* __restrict__ zx, int j, int outsel, int guard) {
+  INST_BEGIN
+  if (guard && I.ctrl->stop) return;
+  const int i = blockIdx.x * kBS + threadIdx.x;
+  if (i >= I.n) return;
+  const int n = I.n;
+  const double* r = rx ? rx : I.fV + (size_t)j * 4 * n;
+  double* z = zx ? zx : I.fZ + (size_t)j * 4 * n;
+  const double v1 = (double)mg_out<T>(I, outsel)[i];
+  z[i] = v1;
+  ((T*)I.lv[0].b)[i] = (T)((obs_w(I, i) + I.ty[i]) * v1 - r[i]);
+}
+
+// Step c: the right-hand side L s of the solve with L + M_r (s: the previous
+// solve's output).
+template <typename T>
+__global__ void __launch_bounds__(kBS) k_ppi_c(const Inst* __restrict__ Dp, int outsel, int guard) {
+  INST_BEGIN
+  if (guard && I.ctrl->stop) return;
+  const int i = xcd_node(I.n);
+  if (i >= I.n) return;
+  int i1, i2, i3;
+  node_coords(i, I.N, I.dim, i1, i2, i3);
+  const T* s = mg_out<T>(I, outsel);
+  ((T*)I.lv[0].b)[i] = apply_op<T>(s, i, i1, i2, i3, I.N, I.dim, I.pde, I.h, I.eps, false);
 }
 
 // z_p = (double) multigrid output
@@ -441,6 +501,9 @@ __global__ void k_ctrl_continue(const Inst* __restrict__ Dp) {
   template __global__ void k_precond_diag<T>(const Inst*, const double*, double*, int, int, int); \
   template __global__ void k_pt_rhs<T>(const Inst*, const double*, const double*, int, int);      \
   template __global__ void k_store_p<T>(const Inst*, double*, int, int, int);                     \
+  template __global__ void k_ppi_a<T>(const Inst*, const double*, double*, int, int);              \
+  template __global__ void k_ppi_b<T>(const Inst*, const double*, double*, int, int, int);         \
+  template __global__ void k_ppi_c<T>(const Inst*, int, int);                                      \
   template __global__ void k_minres_init<T>(const Inst*, int);                                   \
   template __global__ void k_minres_k2<T>(const Inst*, int, int);                                     \
   template __global__ void k_minres_k4<T>(const Inst*, int, int, double, int, int);

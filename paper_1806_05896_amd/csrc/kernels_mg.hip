@@ -196,7 +196,7 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse(const Inst* __restrict_
   if (tid == 0) {
     int off = 0;
     for (int l = cl; l < L; ++l) {
-      const Level& Lv = I.lvd[l];
+      const Level& Lv = I.lv[l];
       LI[l].N = Lv.N;
       LI[l].n = Lv.n;
       LI[l].off = off;
@@ -209,13 +209,13 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse(const Inst* __restrict_
   // stage b at the top level and M_hat at every level
   for (int l = cl; l < L; ++l) {
     const CoarseLevel C = LI[l];
-    const T* mg = (const T*)I.lvd[l].mh;
+    const T* mg = (const T*)I.lv[l].mh;
     T* ms = lds + C.off + 3 * C.n;
     for (int i = tid; i < C.n; i += kCoarseBS) ms[i] = mg[i];
   }
   {
     const CoarseLevel C = LI[cl];
-    const T* bg = (const T*)I.lvd[cl].b;
+    const T* bg = (const T*)I.lv[cl].b;
     T* B = lds + C.off + 2 * C.n;
     for (int i = tid; i < C.n; i += kCoarseBS) B[i] = bg[i];
   }
@@ -309,7 +309,7 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse(const Inst* __restrict_
     }
   }
   const CoarseLevel C = LI[cl];
-  T* xg = (T*)I.lvd[cl].x;
+  T* xg = (T*)I.lv[cl].x;
   const T* xs = lds + C.off + ((alt >> cl) & 1u) * C.n;
   for (int i = tid; i < C.n; i += kCoarseBS) xg[i] = xs[i];
 }
@@ -515,7 +515,7 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_p2(const Inst* __restri
   {
     const int N = LN[cl], P = N + 2, n = N * N;
     const T* a = lds + LOFF[cl] + ((alt >> cl) & 1u) * P * P;
-    T* xg = (T*)I.lvd[cl].x;
+    T* xg = (T*)I.lv[cl].x;
     P2_FOR(N) xg[i] = a[p]; P2_END
   }
 }
@@ -532,7 +532,7 @@ __global__ void __launch_bounds__(kBS) k_mg_scale_ty(const Inst* __restrict__ Dp
   const int i = blockIdx.x * kBS + threadIdx.x;
   if (i >= I.n) return;
   const T* x = (const T*)((I.coarse_lev == 0 || !outsel) ? I.lv[0].x : I.lv[0].x2);
-  ((T*)I.lv[0].b)[i] = (T)(1.0 + I.ty[i]) * x[i];
+  ((T*)I.lv[0].b)[i] = (T)(obs_w(I, i) + I.ty[i]) * x[i];
 }
 
 // b_0 = (1 + Theta_y) x for the instances of a 2D batch whose whole
@@ -544,7 +544,23 @@ __global__ void __launch_bounds__(kBS) k_mg_scale_ty_small(const Inst* __restric
   if (I.coarse_lev != 0 || mg_skip(I, guard)) return;
   const int i = blockIdx.x * kBS + threadIdx.x;
   if (i >= I.n) return;
-  ((T*)I.lv[0].b)[i] = (T)(1.0 + I.ty[i]) * ((const T*)I.lv[0].x)[i];
+  ((T*)I.lv[0].b)[i] = (T)(obs_w(I, i) + I.ty[i]) * ((const T*)I.lv[0].x)[i];
+}
+
+// Reaction term of the multigrid operator for the next solves (slot 0:
+// M_hat, or M_r for P_Pi; 1: M_l = O + Theta_y; 2: zero, the operator L
+// alone): the descriptors' level and coarse-image pointers move to the slot
+// (stream ordered, so it also works inside captured graphs).  Slot 0 is the
+// state the host copies of the descriptors assume.
+__global__ void k_mg_select(Inst* __restrict__ Dp, int slot) {
+  Inst& I = Dp[blockIdx.z];
+  const int l = threadIdx.x;
+  if (l < I.nlev) {
+    Level& L = I.lv[l];
+    L.mh = (char*)L.mhb + (size_t)slot * L.n * (I.mg_fp32 ? 4 : 8);
+  }
+  if (l == 0 && I.cpackb)
+    I.cpack = (char*)I.cpackb + (size_t)slot * I.cpack_slot * (I.mg_fp32 ? 4 : 8);
 }
 
 // k-cycle multigrid solve of (A + M_hat) x = b at level 0 (vcycles = k > 1):
@@ -673,7 +689,7 @@ __global__ void __launch_bounds__(kBS) k_mg_down2d(const Inst* __restrict__ Dp, 
     if (g1 >= 0 && g1 < N && g2 >= 0 && g2 < N) {
       const int gi = g1 + N * g2;
       bv = bsrc[gi];
-      if (ty) bv = (T)(1.0 + ty[gi]) * bv;
+      if (ty) bv = (T)(obs_w(I, gi) + ty[gi]) * bv;
       mv = mh[gi];
     }
     bs[k] = bv;

@@ -78,7 +78,7 @@ __global__ void __launch_bounds__(kBS) k_mg_down_p2(const Inst* __restrict__ Dp,
     if ((unsigned)g1 < (unsigned)N && (unsigned)g2 < (unsigned)N) {
       const int gi = g1 + N * g2;
       bv = bsrc[gi];
-      if (tyv) bv = (T)(1.0 + tyv[gi]) * bv;
+      if (tyv) bv = (T)(obs_w(I, gi) + tyv[gi]) * bv;
       dv = (T)4 * ih2 + mh[gi];
       wv = omega_over<T>(om, dv);
     }

@@ -158,6 +158,8 @@ struct ipmpde_problem {
   bool have_work = false;
   bool need_init = true;   // iterates not yet at the starting point
   bool in_engine = false;  // queued or running in a serving engine
+  double* obs = nullptr;   // observation weights (device), nullptr: observed everywhere
+  bool obs_zero = false;   // some node is unobserved
   int nlev = 0;
   Level lv32[kMaxLev];
   Level lv64[kMaxLev];
@@ -238,6 +240,10 @@ static int set_coarse_lds_limit() {
 
 static bool is_p2(const ipmpde_problem* P) { return P->dim == 2 && P->pde == IPMPDE_POISSON; }
 
+// Reaction-term slots of every multigrid level (see k_mg_select): the
+// Schur-approximation operator's, and the two extra operators of P_Pi.
+static constexpr int kReactionSlots = 3;
+
 static int ensure_mg(ipmpde_problem* P, bool fp32) {
   TRY(set_coarse_lds_limit());
   bool& have = fp32 ? P->have32 : P->have64;
@@ -254,11 +260,12 @@ static int ensure_mg(ipmpde_problem* P, bool fp32) {
     TRY(P->work.alloc(&lv[l].x, nb));
     TRY(P->work.alloc(&lv[l].x2, nb));
     TRY(P->work.alloc(&lv[l].b, nb));
-    TRY(P->work.alloc(&lv[l].mh, nb));
+    TRY(P->work.alloc(&lv[l].mh, kReactionSlots * nb));  // slot 2 stays zero
+    lv[l].mhb = lv[l].mh;
     HIP_TRY(hipMemset(lv[l].x, 0, nb));
     HIP_TRY(hipMemset(lv[l].x2, 0, nb));
     HIP_TRY(hipMemset(lv[l].b, 0, nb));
-    HIP_TRY(hipMemset(lv[l].mh, 0, nb));
+    HIP_TRY(hipMemset(lv[l].mh, 0, kReactionSlots * nb));
     N = (N - 1) / 2;
   }
   for (void*& a : (fp32 ? P->kc32 : P->kc64)) TRY(P->work.alloc(&a, (size_t)lv[0].n * el));
@@ -268,7 +275,7 @@ static int ensure_mg(ipmpde_problem* P, bool fp32) {
     int elems = 0;
     for (int l = cl; l < P->nlev; ++l) elems += coarse_p2_elems(lv[l].N);
     void*& pk = fp32 ? P->cpack32 : P->cpack64;
-    TRY(P->work.alloc(&pk, (size_t)elems * el));
+    TRY(P->work.alloc(&pk, (size_t)kReactionSlots * elems * el));
     (fp32 ? P->cpack_elems32 : P->cpack_elems64) = elems;
   }
   Level*& lvd = fp32 ? P->lvd32 : P->lvd64;
@@ -442,6 +449,10 @@ static int group_select(Group* G, const ipmpde_options& o) {
     }
     d.coarse_p2 = is_p2(P) ? 1 : 0;
     d.cpack = fp32 ? P->cpack32 : P->cpack64;
+    d.cpackb = d.cpack;
+    d.cpack_slot = fp32 ? P->cpack_elems32 : P->cpack_elems64;
+    d.obs = P->obs;
+    d.ppi = o.precond == IPMPDE_PPI ? 1 : 0;
     void* const* kc = fp32 ? P->kc32 : P->kc64;
     d.kc_b0 = kc[0];
     d.kc_s[0] = kc[1];
@@ -521,7 +532,10 @@ static int check_options(const ipmpde_options& o) {
   if (o.ipm_maxit < 1 || o.ipm_maxit > IPMPDE_MAX_HIST - 1) return fail(IPMPDE_EINVAL, "ipm_maxit out of range");
   if (o.fixed_nli < 0 || o.fixed_nli > IPMPDE_MAX_HIST - 1) return fail(IPMPDE_EINVAL, "fixed_nli out of range");
   if (o.krylov != IPMPDE_MINRES && o.krylov != IPMPDE_FGMRES) return fail(IPMPDE_EINVAL, "unknown krylov");
-  if (o.precond != IPMPDE_PD && o.precond != IPMPDE_PT) return fail(IPMPDE_EINVAL, "unknown precond");
+  if (o.precond != IPMPDE_PD && o.precond != IPMPDE_PT && o.precond != IPMPDE_PPI)
+    return fail(IPMPDE_EINVAL, "unknown precond");
+  if (o.precond == IPMPDE_PPI && o.krylov != IPMPDE_FGMRES)
+    return fail(IPMPDE_EINVAL, "P_Pi is not symmetric: it requires FGMRES");
   if (o.precond == IPMPDE_PT && o.krylov != IPMPDE_FGMRES)
     return fail(IPMPDE_EINVAL, "the block-triangular preconditioner needs FGMRES");
   if (o.restart < 1 || o.restart > 60) return fail(IPMPDE_EINVAL, "restart must be in [1,60]");
@@ -798,8 +812,29 @@ static int minres_group(Group* G, const ipmpde_options& o, hipStream_t s) {
   return IPMPDE_OK;
 }
 
+static void mg_select(Group* G, int slot, hipStream_t s) {
+  hipLaunchKernelGGL(k_mg_select, dim3(1, 1, G->zc), dim3(64), 0, s, G->D, slot);
+}
+
+// z = P^-1 r for every instance (pt: IPMPDE_PD, IPMPDE_PT or IPMPDE_PPI);
+// explicit operands, or the FGMRES slots r = V_j, z = Z_j when null.
 template <typename T>
 static void precond_apply(Group* G, int pt, const double* x, double* y, int j, int guard, hipStream_t s) {
+  if (pt == IPMPDE_PPI) {
+    // Sec. 4.3: v2 (z block), v1 = L^-1 (Mbar v2 + r_p), then
+    // v3 = (L + M_r)^-1 L (L^T + M_l)^-1 ((O + Theta_y) v1 - r_y)
+    hipLaunchKernelGGL(k_ppi_a<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, x, y, j, guard);
+    mg_select(G, 2, s);
+    mg_solve<T>(G, 0, guard, 0, s);
+    hipLaunchKernelGGL(k_ppi_b<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, x, y, j, G->outsel, guard);
+    mg_select(G, 1, s);
+    mg_solve<T>(G, 1, guard, 0, s);
+    hipLaunchKernelGGL(k_ppi_c<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, G->outsel, guard);
+    mg_select(G, 0, s);
+    mg_solve<T>(G, 0, guard, 0, s);
+    hipLaunchKernelGGL(k_store_p<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, y, j, G->outsel, guard);
+    return;
+  }
   hipLaunchKernelGGL(k_precond_diag<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, x, y, j, pt, guard);
   if (pt) hipLaunchKernelGGL(k_pt_rhs<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, x, (const double*)y, j, guard);
   schur_inv<T>(G, guard, s);
@@ -826,7 +861,7 @@ static void fgmres_step(Group* G, int pt, int j, double tol, int maxit, hipStrea
 template <typename T>
 static int fgmres_group(Group* G, const ipmpde_options& o, hipStream_t s) {
   const long n4 = 4L * G->max_n;
-  const int pt = o.precond == IPMPDE_PT;
+  const int pt = o.precond;  // IPMPDE_PD, IPMPDE_PT or IPMPDE_PPI
   const int nbm = fg_multidot_blocks(n4);
   const int step = 4;
   hipLaunchKernelGGL(k_krylov_begin, gz(G, n4), dim3(kBS), 0, s, G->D);
@@ -867,7 +902,26 @@ static int krylov_status(const Group* G, int i) {
 // ---------------------------------------------------------------------------
 // Newton setup and IPM steps (all instances)
 
+// P_Pi's extra operators: M_l (slot 1, written at level 0 by the Newton setup)
+// restricted to every level and its coarse image; the coarse image of the
+// zero slot (L alone); back to slot 0.
+template <typename T>
+static void ppi_setup(Group* G, hipStream_t s) {
+  mg_select(G, 1, s);
+  for (int l = 0; l + 1 < G->max_nlev; ++l)
+    hipLaunchKernelGGL(k_restrict_diag<T>, gz(G, G->maxn[l + 1]), dim3(kBS), 0, s, G->D, l);
+  if (G->p2) hipLaunchKernelGGL(k_coarse_pack<T>, gz(G, G->max_cpack), dim3(kBS), 0, s, G->D);
+  mg_select(G, 2, s);
+  if (G->p2) hipLaunchKernelGGL(k_coarse_pack<T>, gz(G, G->max_cpack), dim3(kBS), 0, s, G->D);
+  mg_select(G, 0, s);
+}
+
 static int newton_setup_group(Group* G, const ipmpde_options& o, hipStream_t s) {
+  for (int i = 0; i < G->count; ++i) {
+    const ipmpde_problem* P = G->probs[i];
+    if (o.precond != IPMPDE_PPI && P->obs_zero && !P->has_y)
+      return fail(IPMPDE_EINVAL, "unobserved nodes without state bounds make the (1,1) block singular: use P_Pi");
+  }
   TRY(group_select(G, o));
   TRY(group_sync(G, s));
   if (G->fp32) {
@@ -875,11 +929,13 @@ static int newton_setup_group(Group* G, const ipmpde_options& o, hipStream_t s) 
     for (int l = 0; l + 1 < G->max_nlev; ++l)
       hipLaunchKernelGGL(k_restrict_diag<float>, gz(G, G->maxn[l + 1]), dim3(kBS), 0, s, G->D, l);
     if (G->p2) hipLaunchKernelGGL(k_coarse_pack<float>, gz(G, G->max_cpack), dim3(kBS), 0, s, G->D);
+    if (o.precond == IPMPDE_PPI) ppi_setup<float>(G, s);
   } else {
     hipLaunchKernelGGL(k_newton_setup<double>, gz(G, G->max_n), dim3(kBS), 0, s, G->D);
     for (int l = 0; l + 1 < G->max_nlev; ++l)
       hipLaunchKernelGGL(k_restrict_diag<double>, gz(G, G->maxn[l + 1]), dim3(kBS), 0, s, G->D, l);
     if (G->p2) hipLaunchKernelGGL(k_coarse_pack<double>, gz(G, G->max_cpack), dim3(kBS), 0, s, G->D);
+    if (o.precond == IPMPDE_PPI) ppi_setup<double>(G, s);
   }
   HIP_TRY(hipGetLastError());
   for (int i = 0; i < G->count; ++i) {
@@ -1086,8 +1142,8 @@ extern "C" size_t ipmpde_footprint_bytes(const ipmpde_grid* grid, const ipmpde_p
   size_t bytes = arrays * A(n * 8) + A(kTicketStride * (kTicketGroups + 1) * sizeof(unsigned));
   bytes += kKrylovVecs * A(n4 * 8) + A((size_t)partials_words(nblk((long)n)) * 8);
   const size_t el = o.mg_precision == IPMPDE_FP32 ? 4 : 8;
-  for (int N = grid->n;; N = (N - 1) / 2) {
-    bytes += 4 * A(pow_dim(N, grid->dim) * el);
+  for (int N = grid->n;; N = (N - 1) / 2) {  // x, x2, b and the reaction-term slots
+    bytes += 3 * A(pow_dim(N, grid->dim) * el) + A(kReactionSlots * pow_dim(N, grid->dim) * el);
     if (N <= 1) break;
   }
   bytes += 3 * A(n * el);  // k-cycle level-0 arrays
@@ -1101,7 +1157,7 @@ extern "C" size_t ipmpde_footprint_bytes(const ipmpde_grid* grid, const ipmpde_p
       ++nlev;
       if (N <= 1) break;
     }
-    bytes += A(coarse_lds_bytes(lv, nlev, pick_coarse(lv, nlev, el, 2, true), el, true));
+    bytes += A(kReactionSlots * coarse_lds_bytes(lv, nlev, pick_coarse(lv, nlev, el, 2, true), el, true));
   }
   if (o.krylov == IPMPDE_FGMRES) bytes += A((size_t)(o.restart + 1) * n4 * 8) + A((size_t)o.restart * n4 * 8);
   return bytes;
@@ -1364,6 +1420,28 @@ static const double* field_ptr(const ipmpde_problem* P, int field, int* kind) {
   }
 }
 
+extern "C" int ipmpde_set_observation(ipmpde_problem* P, const double* weights, size_t count) {
+  if (!P) return fail(IPMPDE_EINVAL, "problem is NULL");
+  if (P->in_engine) return fail(IPMPDE_EINVAL, "problem is queued or running in an engine");
+  if (!weights) {
+    P->I.obs = P->obs = nullptr;
+    P->obs_zero = false;
+    return IPMPDE_OK;
+  }
+  if (count != (size_t)P->n) return fail(IPMPDE_EINVAL, "count must equal the number of nodes");
+  bool zero = false;
+  for (size_t i = 0; i < count; ++i) {
+    if (!(weights[i] >= 0.0 && std::isfinite(weights[i]))) return fail(IPMPDE_EINVAL, "weights must be finite and >= 0");
+    zero = zero || weights[i] == 0.0;
+  }
+  if (!P->obs) TRY(P->mem.alloc_t(&P->obs, count));
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(P->obs, weights, count * sizeof(double), hipMemcpyHostToDevice));
+  P->I.obs = P->obs;
+  P->obs_zero = zero;
+  return IPMPDE_OK;
+}
+
 extern "C" int ipmpde_query(const ipmpde_problem* P, int field, double* out, size_t count) {
   if (!P || !out) return fail(IPMPDE_EINVAL, "NULL argument");
   if (count != (size_t)P->n) return fail(IPMPDE_EINVAL, "count must equal the number of nodes");
@@ -1444,7 +1522,7 @@ extern "C" int ipmpde_apply_precond(ipmpde_problem* P, const ipmpde_options* opt
   Group* G = P->self;
   TRY(group_select(G, o));
   TRY(group_sync(G, S(stream)));
-  const int pt = o.precond == IPMPDE_PT;
+  const int pt = o.precond;  // IPMPDE_PD, IPMPDE_PT or IPMPDE_PPI
   if (G->fp32) precond_apply<float>(G, pt, x, y, 0, 0, S(stream));
   else precond_apply<double>(G, pt, x, y, 0, 0, S(stream));
   HIP_TRY(hipGetLastError());
