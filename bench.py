@@ -124,6 +124,29 @@ def copy_ceiling(torch, reps=10):
     return gbs
 
 
+def bench_partial(W, torch, N, reps):
+    """Partial observation (observed on the central square, no state bounds):
+    FGMRES(30) + P_Pi, FP32 V-cycles, one instance of N^2."""
+    from paper_1806_05896_amd import Options, Problem
+    d = W.poisson2d_partial(seed=0, N=N)
+    o = Options(sigma=d.sigma, krylov="fgmres", precond="ppi", mg_precision="fp32")
+    stream = torch.cuda.current_stream()
+    with Problem(d) as p:
+        p.solve(o, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            rc = p.solve(o, stream=stream)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / reps
+        s = p.stats()
+    log(f"partial observation {N}^2: {1 / t:.2f} solves/s")
+    return {"workload": f"poisson2d_partial: 2D Poisson {N}x{N}, observed on (0.25,0.75)^2, alpha=1e-4, "
+                        "beta=1e-3, u in [-5,5], sigma=0.25", "krylov": "fgmres(30)", "precond": "P_Pi",
+            "solves_per_s": 1 / t, "ms_per_solve": t * 1e3, "nli": s.nli, "krylov_its_per_solve": s.krylov_its,
+            "krylov_its_per_s": s.krylov_its / t, "status": rc}
+
+
 def solver_options(d, Options, prec="fp32"):
     """Per-request solver choice: MINRES + P_D for Poisson, FGMRES(30) + P_T
     for convection-diffusion, multigrid in the given precision."""
@@ -254,7 +277,9 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-budget-gib", type=float, default=32.0)
     ap.add_argument("--serve-loads", type=str, default="0.8", help="arrival rates as fractions of saturation")
-    ap.add_argument("--only", choices=["serve", "batch"], default=None, help="run one extra section alone")
+    ap.add_argument("--partial-N", type=int, default=255, help="grid of the partial-observation run (0: skip)")
+    ap.add_argument("--only", choices=["serve", "batch", "partial"], default=None,
+                    help="run one extra section alone")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only launch the roofline kernel (20 times) and a 1 GiB device copy, for counter runs")
     args = ap.parse_args()
@@ -277,6 +302,9 @@ def main():
     if args.only == "serve":
         print(json.dumps({"serving": bench_serving(W, torch, args.serve_requests, args.serve_slots,
                                                    args.serve_budget_gib, loads)}), flush=True)
+        return
+    if args.only == "partial":
+        print(json.dumps({"partial_observation": bench_partial(W, torch, args.partial_N, 3)}), flush=True)
         return
     if args.only == "batch":
         print(json.dumps({"batched": bench_batched(W, torch, max(1, args.batch), 2)}), flush=True)
@@ -391,6 +419,9 @@ def main():
     data0 = datas[0]
     for p in probs:
         p.close()
+
+    if args.partial_N > 0:
+        result["partial_observation"] = bench_partial(W, torch, args.partial_N, 2)
 
     if args.serve_requests > 0:
         result["serving"] = bench_serving(W, torch, args.serve_requests, args.serve_slots, args.serve_budget_gib,
