@@ -11,7 +11,7 @@
  *
  * where A is the 5-point (2D) or 7-point (3D) Laplacian, or (2D) the
  * upwinded convection-diffusion operator -eps Lap + w.grad with the wind
- * w = (2 x2 (1 - x1^2), -2 x1 (1 - x2^2)) of Sec. 6.3; f_hat = f minus the
+ * w = (2 x2 (1 - x1^2), -2 x1 (1 - x2^2)) of Sec. 5.2; f_hat = f minus the
  * boundary columns of A applied to the Dirichlet data g.
  *
  * The solver is the path-following method of the Appendix (Algorithm A.1)
@@ -80,9 +80,9 @@ typedef struct { int kind; double eps; } ipmpde_pde;     /* kind IPMPDE_POISSON 
 
 /* Solver options.  ipmpde_default_options fills the defaults named here. */
 typedef struct {
-  double sigma;        /* barrier reduction factor (0,1); default 0.2 (Sec. 6.1) */
-  double alpha0;       /* fraction to the boundary; default 0.995 (Sec. 6) */
-  double eps_p, eps_d, eps_c; /* stopping tolerances on inf-norms; default 1e-6 (Sec. 6) */
+  double sigma;        /* barrier reduction factor (0,1); default 0.2 (Sec. 5.1) */
+  double alpha0;       /* fraction to the boundary; default 0.995 (Sec. 5) */
+  double eps_p, eps_d, eps_c; /* stopping tolerances on inf-norms; default 1e-6 (Sec. 5) */
   double mu0;          /* initial barrier parameter; default 1 */
   int ipm_maxit;       /* default 200 */
   int fixed_nli;       /* > 0: take exactly this many IPM steps (parity runs); default 0 */
@@ -91,7 +91,7 @@ typedef struct {
                           IPMPDE_PPI, the partial-observation preconditioner of
                           Sec. 4.3 (requires FGMRES) */
   int restart;         /* FGMRES restart length; default 30 */
-  double krylov_tol;   /* relative unpreconditioned residual |b - K x| / |b|; default 1e-10 (Sec. 6) */
+  double krylov_tol;   /* relative unpreconditioned residual |b - K x| / |b|; default 1e-10 (Sec. 5) */
   int krylov_maxit;    /* default 500 */
   int vcycles;         /* V-cycles per multigrid solve; default 1 */
   int nu_pre, nu_post; /* Jacobi sweeps; default 2, 2 (MINRES needs nu_pre == nu_post) */

@@ -1,11 +1,11 @@
 """Finite-difference discretization of the state equation (oracle).
 
-The paper discretizes with Q1 finite elements (Sec. 2 and Sec. 6); this
+The paper discretizes with Q1 finite elements (Sec. 2 and Sec. 5); this
 oracle follows the finite-difference reading used throughout the build:
 
 * grid: N interior points per axis on (0,1)^d, h = 1/(N+1), x_i = i h;
 * Poisson (eq. (eq:lap)): (A y)_i = h^-2 (2d y_i - sum of the 2d neighbours);
-* convection-diffusion (Sec. 6.3, -eps Lap y + w.grad y = u): A = eps A_Poisson + C
+* convection-diffusion (Sec. 5.2, -eps Lap y + w.grad y = u): A = eps A_Poisson + C
   with first-order upwinding at node values,
       (C y)_i = sum_a [max(w_a,0)(y_i - y_{i-e_a}) + min(w_a,0)(y_{i+e_a} - y_i)] / h,
   wind w = (2 x2 (1 - x1^2), -2 x1 (1 - x2^2));
@@ -25,7 +25,7 @@ import scipy.sparse as sp
 
 
 def _wind(x1: np.ndarray, x2: np.ndarray):
-    """Wind of the convection-diffusion example, Sec. 6.3."""
+    """Wind of the convection-diffusion example, Sec. 5.2."""
     return 2.0 * x2 * (1.0 - x1 * x1), -2.0 * x1 * (1.0 - x2 * x2)
 
 

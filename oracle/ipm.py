@@ -20,7 +20,7 @@ Readings taken where the paper is silent, garbled or ambiguous:
       (eq. (prdu)) and of the complementarity products of eq. (gap) taken
       with mu = 0 (with mu^k subtracted the central path would satisfy the
       test trivially).  This reproduces NLI = 9 at sigma = 0.2 and a final
-      mu of 0.2^9 = 5.1e-7, as Sec. 6.1 reports.
+      mu of 0.2^9 = 5.1e-7, as Sec. 5.1 reports.
   R2  mu_0 = 1 (Fig. convh starts at mu = 1).
   R3  starting point: box midpoints (y = 0 without state bounds),
       w = z_b,w / 2, v = z_b,v / 2, p = 0 and lambda = mu_0 / gap for every

@@ -117,7 +117,7 @@ struct Inst {
 // ---------------------------------------------------------------------------
 // stencils
 
-// Convection-diffusion wind of Sec. 6.3 at x = (x1, x2).
+// Convection-diffusion wind of Sec. 5.2 at x = (x1, x2).
 __device__ __forceinline__ void wind(double x1, double x2, double& w1, double& w2) {
   w1 = 2.0 * x2 * (1.0 - x1 * x1);
   w2 = -2.0 * x1 * (1.0 - x2 * x2);

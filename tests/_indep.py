@@ -12,7 +12,7 @@ import numpy as np
 
 
 def wind(x1, x2):
-    # wind field of the convection-diffusion example (Sec. 6.3)
+    # wind field of the convection-diffusion example (Sec. 5.2)
     return 2.0 * x2 * (1.0 - x1 ** 2), -2.0 * x1 * (1.0 - x2 ** 2)
 
 

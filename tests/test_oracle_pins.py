@@ -41,7 +41,7 @@ def test_poisson_stencil_exact_on_cubics(dim, N):
 
 @pytest.mark.parametrize("N", [7, 31])
 def test_convdiff_upwind_exact_on_linears(N):
-    """Upwind differences are exact on linear functions: A q = w . grad q (Sec. 6.3 wind)."""
+    """Upwind differences are exact on linear functions: A q = w . grad q (Sec. 5.2 wind)."""
     eps = 1.0 / 200
     q = lambda x: 1.0 + 2.0 * x[0] - 3.0 * x[1]
     A = operator_matrix(2, N, "convdiff", eps)
@@ -277,7 +277,7 @@ def test_paper_convergence_history_fixture():
     np.testing.assert_allclose(mu, 0.25 ** (k - 1), rtol=2e-3)
     np.testing.assert_allclose(xip[1:5] / xip[:4], 0.005, rtol=2e-3)
     p = W.poisson2d_small(seed=0, N=15)
-    p.u_a[:] = -2.0; p.u_b[:] = 1.5           # the paper's box (Sec. 6.1): u^0 != 0, xi_p^0 != 0
+    p.u_a[:] = -2.0; p.u_b[:] = 1.5           # the paper's box (Sec. 5.1): u^0 != 0, xi_p^0 != 0
     r = oracle.solve(p, IPMOptions(sigma=0.25))
     mus = np.array([h["mu"] for h in r.history])
     np.testing.assert_allclose(mus, 0.25 ** np.arange(len(mus)), rtol=1e-14)
@@ -301,7 +301,7 @@ def test_sign_symmetry():
 
 
 def test_nli_at_sigma_02_and_final_mu():
-    """Sec. 6.1 (Table caption): sigma = 0.2 gives 9 IPM iterations ending at mu = 5e-7
+    """Sec. 5.1 (Table caption): sigma = 0.2 gives 9 IPM iterations ending at mu = 5e-7
     when the iterates stay centred; the reading R1 stops exactly there when
     every step is a full (alpha_0-scaled) step."""
     p = W.poisson2d_small(seed=0, N=15)

@@ -13,14 +13,14 @@ Boundary data g lives on the (N+2)^d nodes including the boundary, same
 ordering with 0-based indices 0..N+1.
 
 Workload recipes (the paper prints no data files; these stand in for its
-analytic desired states, Sec. 6):
+analytic desired states, Sec. 5):
   * ``poisson2d_small``: N=31, y_d = A sin(pi x1) sin(pi x2), A ~ N(1, 0.1),
     alpha=1e-2, beta=1e-3, u in [-2, 2], no state bounds.
   * ``poisson2d_511``: N=511, y_d = 8 random sine modes, alpha=1e-4,
     beta=1e-3, u in [-5, 5], y in [-0.2, 0.3].
   * ``poisson3d_127``: N=127 in 3D, 8 sine modes, alpha=1e-5,
     beta from {1e-4, 1e-3, 1e-2, 1e-1}, u in [-10, 10].
-  * ``convdiff2d_255``: eps=1/200, wind of Sec. 6.3, N=255, 8 sine modes,
+  * ``convdiff2d_255``: eps=1/200, wind of Sec. 5.2, N=255, 8 sine modes,
     alpha=beta=1e-3, u in [-3, 3].
   * ``served_mix``: a stream of mixed requests (see ``served_requests``).
 """
