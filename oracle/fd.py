@@ -15,6 +15,19 @@ oracle follows the finite-difference reading used throughout the build:
 
 Dirichlet data g (eq. (eq:lap), y = g on the boundary) enters through the
 boundary columns of the full operator: A_II y_I = f - A_IB g_B =: f_hat.
+
+Heat equation y_t - Lap y = u + f (Sec. 4.4), all at once: backward Euler
+with step tau on nt steps gives the block lower bidiagonal matrix of Sec.
+4.4 (M + tau L on the diagonal, -M below it) acting on the states at
+t_1..t_nt.  With M = I and the whole constraint divided by tau (the time
+counterpart of the unit mass scaling; the objective's rectangle-rule weight
+tau is divided out likewise, which again leaves the minimizer unchanged),
+the state operator is
+
+    A = blocks I/tau + A_h on the diagonal, -I/tau below it,
+
+A_h the 2D Poisson matrix, and the initial state y0 moves to the right-hand
+side of the first step: f_hat_1 = f_1 - A_IB g_B + y0 / tau.
 """
 from __future__ import annotations
 
@@ -86,7 +99,7 @@ class Discretization:
 
     @property
     def n(self):
-        return self.N ** self.dim
+        return self.A.shape[0]
 
 
 def operator_matrix(dim: int, N: int, pde: str = "poisson", eps: float = 1.0) -> sp.csr_matrix:
@@ -105,8 +118,35 @@ def rhs_offset(dim: int, N: int, pde: str, eps: float, g) -> np.ndarray:
     return -(full @ gg)
 
 
+def heat_operator(N: int, nt: int, tau: float) -> sp.csr_matrix:
+    """All-at-once backward Euler matrix of Sec. 4.4 with M = I, divided by tau."""
+    Ah = operator_matrix(2, N, "poisson")
+    Id = sp.identity(N * N, format="csr")
+    diag_blocks = sp.kron(sp.identity(nt), Id / tau + Ah)
+    sub_blocks = sp.kron(sp.eye(nt, k=-1), Id / tau)
+    return (diag_blocks - sub_blocks).tocsr()
+
+
+def discretize_heat(prob) -> Discretization:
+    """Heat equation (Sec. 4.4): the operator above and f_hat with the
+    boundary data folded into every step and y0 / tau into the first."""
+    N, nt, tau = prob.N, prob.nt, prob.tau
+    if prob.dim != 2 or nt < 1 or not tau > 0:
+        raise ValueError("the heat equation takes dim 2, nt >= 1 and tau > 0")
+    A = heat_operator(N, nt, tau)
+    n2 = N * N
+    f_hat = np.zeros(n2 * nt) if prob.f is None else np.array(prob.f, dtype=np.float64, copy=True)
+    step = rhs_offset(2, N, "poisson", 1.0, prob.g)
+    f_hat += np.tile(step, nt)
+    if prob.y0 is not None:
+        f_hat[:n2] += np.asarray(prob.y0, dtype=np.float64) / tau
+    return Discretization(2, N, A, f_hat)
+
+
 def discretize(prob) -> Discretization:
     """Operator and folded right-hand side for a workloads.ProblemData."""
+    if prob.pde == "heat":
+        return discretize_heat(prob)
     full, rows_full = _full_operator(prob.dim, prob.N, prob.pde, prob.eps)
     A = full[:, rows_full].tocsr()
     f = np.zeros(rows_full.size) if prob.f is None else np.asarray(prob.f, dtype=np.float64)

@@ -244,7 +244,10 @@ def newton_solve(prob, disc: Discretization, st: IPMState, mu: float, mode: str 
     n = prob.n
     ty, tw, tv = barrier_diagonals(prob, st)
     if mode == "auto":
-        mode = "full" if (prob.dim == 2 and prob.N <= 127) or (prob.dim == 3 and prob.N <= 31) else "schur"
+        if prob.pde == "heat":
+            mode = "full" if prob.n <= 30000 else "schur"
+        else:
+            mode = "full" if (prob.dim == 2 and prob.N <= 127) or (prob.dim == 3 and prob.N <= 31) else "schur"
         if not np.all(_obs(prob) + ty > 0):  # (1,1) block singular (R9): no elimination of dy
             mode = "full"
     rhs = newton_rhs(prob, disc, st, mu)

@@ -161,3 +161,20 @@ def active_set_qp(A, yd, fhat, alpha, beta, ua, ub, ya=None, yb=None):
                     raise AssertionError("two KKT points found for a strongly convex QP")
                 best = (y, u)
     return best
+
+
+def dense_heat_operator(N, nt, tau):
+    """Backward Euler space-time operator (Sec. 4.4, M = I, divided by tau) as
+    a dense matrix, one row at a time: row (t, i) carries
+    (y[t, i] - y[t-1, i]) / tau + (Poisson stencil of y[t])_i."""
+    n2 = N * N
+    Ah = dense_operator(2, N, "poisson")
+    A = np.zeros((n2 * nt, n2 * nt))
+    for t in range(nt):
+        for i in range(n2):
+            r = t * n2 + i
+            A[r, t * n2:(t + 1) * n2] += Ah[i]
+            A[r, r] += 1.0 / tau
+            if t > 0:
+                A[r, r - n2] -= 1.0 / tau
+    return A

@@ -414,3 +414,98 @@ def test_partial_observation_preconditioner_with_exact_blocks():
     v1 = Li @ (Mbar @ v2 + w3)
     v3 = Si @ (Mo @ v1 - w1)
     np.testing.assert_allclose(np.concatenate([v1, v2, v3]), Pinv @ w, rtol=1e-10, atol=1e-12)
+
+
+# ---------------------------------------------------------------- heat equation (Sec. 4.4)
+
+def _heat(N, nt, tau=None, seed=0):
+    p = W.heat2d(seed=seed, N=N, nt=nt)
+    if tau is not None:
+        p.tau = tau
+    return p
+
+
+def test_heat_operator_matches_row_by_row_assembly():
+    N, nt, tau = 3, 4, 0.125
+    A = discretize(_heat(N, nt, tau)).A.toarray()
+    np.testing.assert_array_equal(A, I.dense_heat_operator(N, nt, tau))
+
+
+def test_heat_operator_exact_on_separable_polynomial():
+    """y = q(x) (a + b t) with q = x1(1-x1)x2(1-x2): the five-point stencil is
+    exact on q (quadratic along each axis) and backward Euler on a linear
+    function of t, so A y = f_hat with f = y_t - Lap y at the nodes and the
+    initial state y(., 0) entering the first step."""
+    N, nt = 7, 5
+    tau = 1.0 / nt
+    a, b = 0.7, -1.3
+    x1, x2 = W.interior_coords(2, N)
+    q = x1 * (1 - x1) * x2 * (1 - x2)
+    lap_q = -2 * x2 * (1 - x2) - 2 * x1 * (1 - x1)
+    ts = tau * np.arange(1, nt + 1)
+    y = np.concatenate([q * (a + b * t) for t in ts])
+    f = np.concatenate([q * b - lap_q * (a + b * t) for t in ts])
+    p = _heat(N, nt, tau)
+    p.f = f
+    p.y0 = q * a
+    d = discretize(p)
+    np.testing.assert_allclose(d.A @ y, d.f_hat, rtol=0, atol=1e-11)
+
+
+def test_heat_single_mode_matches_time_kkt():
+    """beta = 0, inactive bounds, y_d and y0 multiples of the sine mode phi:
+    the optimum is phi times the solution of the 3 nt x 3 nt optimality
+    system of the mode's scalar heat equation c' + lam c = d (backward Euler),
+    solved densely."""
+    N, nt = 7, 6
+    tau = 1.0 / nt
+    p = _heat(N, nt, tau, seed=3)
+    amp = p.meta["amplitude"]
+    p.beta = 0.0
+    p.alpha = 1e-2
+    p.u_a[:] = -1e3; p.u_b[:] = 1e3
+    c0 = 0.4
+    phi = I.sine_mode(2, N, (1, 1))
+    p.y0 = c0 * phi
+    lam = I.sine_eigenvalue(2, N, (1, 1))
+    T = np.diag(np.full(nt, 1.0 / tau + lam)) - np.diag(np.full(nt - 1, 1.0 / tau), -1)
+    K = np.zeros((3 * nt, 3 * nt)); r = np.zeros(3 * nt)
+    E = np.eye(nt)
+    # [c; d; q]: c - amp + T^T q = 0, alpha d - q = 0, T c - d = c0 / tau e_1
+    K[:nt, :nt] = E; K[:nt, 2 * nt:] = T.T; r[:nt] = amp
+    K[nt:2 * nt, nt:2 * nt] = p.alpha * E; K[nt:2 * nt, 2 * nt:] = -E
+    K[2 * nt:, :nt] = T; K[2 * nt:, nt:2 * nt] = -E; r[2 * nt] = c0 / tau
+    sol = np.linalg.solve(K, r)
+    c, dd = sol[:nt], sol[nt:2 * nt]
+    res = oracle.solve(p, IPMOptions(sigma=p.sigma, eps_p=1e-11, eps_d=1e-11, eps_c=1e-11))
+    assert res.status == "converged"
+    y_ref = np.concatenate([ck * phi for ck in c])
+    u_ref = np.concatenate([dk * phi for dk in dd])
+    np.testing.assert_allclose(res.y, y_ref, rtol=0, atol=1e-8 * np.abs(y_ref).max())
+    np.testing.assert_allclose(res.u, u_ref, rtol=0, atol=1e-8 * np.abs(u_ref).max())
+
+
+@pytest.mark.parametrize("mu_rule", ["paper", "central"])
+def test_heat_matches_proximal_gradient(mu_rule):
+    """The IPM optimum of a small heat problem equals an independent FISTA
+    solution of the reduced problem in u (all four control regimes present)."""
+    N, nt = 3, 4
+    tau = 1.0 / nt
+    p = _heat(N, nt, tau, seed=1)
+    p.alpha = 1e-2
+    p.beta = 5e-3
+    p.u_a[:] = -0.5; p.u_b[:] = 1.2
+    rng = np.random.default_rng(5)
+    p.y_d = rng.uniform(-0.6, 0.8, p.n)
+    p.y0 = rng.uniform(-0.2, 0.2, N * N)
+    A = I.dense_heat_operator(N, nt, tau)
+    fhat = np.zeros(p.n)
+    fhat[:N * N] = p.y0 / tau
+    u_ref, y_ref = I.fista(A, p.y_d, fhat, p.alpha, p.beta, p.u_a, p.u_b, iters=200000)
+    r = oracle.solve(p, IPMOptions(sigma=p.sigma, eps_p=1e-12, eps_d=1e-12, eps_c=1e-12, mu_rule=mu_rule))
+    assert r.status == "converged"
+    assert (np.abs(u_ref) < 1e-12).sum() > 0
+    assert (np.abs(u_ref - 1.2) < 1e-12).sum() > 0 and (np.abs(u_ref + 0.5) < 1e-12).sum() > 0
+    assert ((np.abs(u_ref) > 1e-6) & (u_ref < 1.2 - 1e-6) & (u_ref > -0.5 + 1e-6)).sum() > 0
+    np.testing.assert_allclose(r.u, u_ref, rtol=0, atol=1e-7)
+    np.testing.assert_allclose(r.y, y_ref, rtol=0, atol=1e-8)

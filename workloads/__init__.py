@@ -23,6 +23,15 @@ analytic desired states, Sec. 5):
   * ``convdiff2d_255``: eps=1/200, wind of Sec. 5.2, N=255, 8 sine modes,
     alpha=beta=1e-3, u in [-3, 3].
   * ``served_mix``: a stream of mixed requests (see ``served_requests``).
+  * ``heat2d``: the heat equation on (0,1)^2 x (0,1] (Sec. 5.3), N=63,
+    nt=100 backward Euler steps (tau=0.01), y_d = A sin(pi x1) sin(pi x2) at
+    every time step, A ~ N(1, 0.1), y(0) = 0, alpha=1e-4, beta=1e-2,
+    u in [-15, 15], no state bounds, sigma=0.25.
+
+Heat-equation fields live on the space-time nodes (x_i, t_k), t_k = k tau,
+k = 1..nt: nt consecutive blocks of N^2 values (block k-1 holds time t_k),
+each in the layout above.  The initial state y0 has N^2 values; g is
+time-independent.
 """
 from __future__ import annotations
 
@@ -39,6 +48,7 @@ CONFIG_IDS = {
     "convdiff2d_255": 3,
     "served_mix": 4,
     "poisson2d_partial": 5,
+    "heat2d": 6,
 }
 
 
@@ -65,10 +75,15 @@ class ProblemData:
     # observation weights (1 where the state is observed, 0 elsewhere); None:
     # the whole domain is observed
     obs: Optional[np.ndarray] = None
+    # heat equation (pde "heat", dim 2): nt time steps of length tau, initial
+    # state y0 (N^2 values; None: zero); every other field then has nt N^2 values
+    nt: int = 1
+    tau: float = 0.0
+    y0: Optional[np.ndarray] = None
 
     @property
     def n(self) -> int:
-        return self.N ** self.dim
+        return self.N ** self.dim * self.nt
 
     @property
     def h(self) -> float:
@@ -80,7 +95,8 @@ class ProblemData:
 
         return ProblemData(self.dim, self.N, self.pde, self.eps, self.alpha, self.beta,
                            c(self.u_a), c(self.u_b), c(self.y_a), c(self.y_b), c(self.y_d),
-                           c(self.f), c(self.g), self.sigma, self.name, dict(self.meta), c(self.obs))
+                           c(self.f), c(self.g), self.sigma, self.name, dict(self.meta), c(self.obs),
+                           self.nt, self.tau, c(self.y0))
 
 
 def rng_for(config: str, instance: int = 0, seed: int = 0) -> np.random.Generator:
@@ -175,6 +191,20 @@ def poisson2d_partial(seed: int = 0, N: int = 255, instance: int = 0) -> Problem
                        y_d, None, None, 0.25, "poisson2d_partial", {"modes": modes}, obs)
 
 
+def heat2d(seed: int = 0, N: int = 63, nt: int = 100, alpha: float = 1e-4, instance: int = 0) -> ProblemData:
+    """Heat equation, time-independent desired state A sin(pi x1) sin(pi x2)
+    (Sec. 5.3), T = 1 split into nt backward Euler steps, y(0) = 0,
+    beta = 1e-2, u in [-15, 15], no state bounds, sigma = 0.25."""
+    rng = rng_for("heat2d", instance, seed)
+    amp = rng.normal(1.0, 0.1)
+    x1, x2 = interior_coords(2, N)
+    frame = amp * np.sin(math.pi * x1) * np.sin(math.pi * x2)
+    n = N * N * nt
+    return ProblemData(2, N, "heat", 1.0, alpha, 1e-2, _const(n, -15.0), _const(n, 15.0), None, None,
+                       np.tile(frame, nt), None, None, 0.25, "heat2d", {"amplitude": amp},
+                       None, nt, 1.0 / nt, None)
+
+
 def served_requests(n_requests: int = 256, seed: int = 0, sizes=(31, 63, 127, 255), rate: float = 1.0):
     """Request stream for the serving workload: (arrival_time, ProblemData) pairs.
 
@@ -210,4 +240,4 @@ def served_requests(n_requests: int = 256, seed: int = 0, sizes=(31, 63, 127, 25
 def by_name(name: str, seed: int = 0, **kw) -> ProblemData:
     return {"poisson2d_small": poisson2d_small, "poisson2d_511": poisson2d_511,
             "poisson3d_127": poisson3d_127, "convdiff2d_255": convdiff2d_255,
-            "poisson2d_partial": poisson2d_partial}[name](seed=seed, **kw)
+            "poisson2d_partial": poisson2d_partial, "heat2d": heat2d}[name](seed=seed, **kw)
