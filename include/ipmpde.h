@@ -59,7 +59,7 @@ enum {
   IPMPDE_EBREAKDOWN = 6     /* NaN/Inf in the iterates or a collapsed step length */
 };
 
-enum { IPMPDE_POISSON = 0, IPMPDE_CONVDIFF = 1 };
+enum { IPMPDE_POISSON = 0, IPMPDE_CONVDIFF = 1, IPMPDE_HEAT = 2 /* ipmpde_heat_create only */ };
 enum { IPMPDE_MINRES = 0, IPMPDE_FGMRES = 1 };
 enum { IPMPDE_PD = 0, IPMPDE_PT = 1, IPMPDE_PPI = 2 };
 enum { IPMPDE_FP64 = 0, IPMPDE_FP32 = 1 };
@@ -154,6 +154,32 @@ int ipmpde_set_allocator(ipmpde_alloc_fn alloc, ipmpde_free_fn free_, void* ctx)
 int ipmpde_problem_create(const ipmpde_grid* grid, const ipmpde_pde* pde, double alpha, double beta,
                           const double* u_a, const double* u_b, const double* y_a, const double* y_b,
                           const double* y_d, const double* f, const double* g, ipmpde_problem** out);
+
+/* Heat equation y_t - Lap y = u + f on (0,1)^2 x (0, T], T = nt tau, all
+ * time steps at once (Sec. 4.4, eq. (TimeDeptSystem)): backward Euler with
+ * step tau gives the block lower bidiagonal state matrix (M + tau L on the
+ * diagonal, -M below it).  In the unit-mass form used throughout (M = I, the
+ * constraint divided by tau and the objective's rectangle-rule weight tau
+ * divided out, which leaves the minimizer unchanged) the problem is the one
+ * above with n = N^2 nt space-time unknowns per field and
+ *   A = blocks I/tau + A_h on the diagonal, -I/tau below it,
+ * A_h the 2D 5-point Laplacian, f_hat = f - A_IB g in every step plus
+ * y0/tau in the first.
+ * Layout: nt consecutive blocks of N^2 values, block k-1 the time t_k = k tau
+ * (k = 1..nt), each block in the 2D layout.  u_a, u_b, y_d (required), y_a,
+ * y_b, f (optional) take N^2 nt values; g (optional) (N+2)^2 values, the
+ * same at every time step; y0 (optional, zero if NULL) the initial state,
+ * N^2 values.  grid->dim must be 2, 1 <= nt <= 65535, tau > 0, N^2 nt <= 1e8;
+ * otherwise as ipmpde_problem_create.  The Schur block's solves with
+ * L + M_hat (and the transpose) are block forward (backward) substitutions
+ * over the time steps with one multigrid solve per step.  P_D and P_T only
+ * (P_Pi: IPMPDE_EINVAL at solve); such a problem is solved alone
+ * (ipmpde_solve and the single-problem entry points), not in a batch or an
+ * engine (IPMPDE_EINVAL). */
+int ipmpde_heat_create(const ipmpde_grid* grid, int nt, double tau, double alpha, double beta,
+                       const double* u_a, const double* u_b, const double* y_a, const double* y_b,
+                       const double* y_d, const double* f, const double* g, const double* y0,
+                       ipmpde_problem** out);
 
 void ipmpde_problem_destroy(ipmpde_problem* prob);
 

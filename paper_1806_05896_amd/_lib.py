@@ -11,7 +11,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libipmpde.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOTCONVERGED, EKRYLOV, EBREAKDOWN = range(7)
-POISSON, CONVDIFF = 0, 1
+POISSON, CONVDIFF, HEAT = 0, 1, 2
 MINRES, FGMRES = 0, 1
 PD, PT, PPI = 0, 1, 2
 FP64, FP32 = 0, 1
@@ -85,6 +85,8 @@ SIGNATURES = {
     "ipmpde_set_allocator": (C.c_int, [ALLOC_FN, FREE_FN, C.c_void_p]),
     "ipmpde_problem_create": (C.c_int, [C.POINTER(Grid), C.POINTER(Pde), C.c_double, C.c_double]
                               + [C.c_void_p] * 7 + [C.POINTER(C.c_void_p)]),
+    "ipmpde_heat_create": (C.c_int, [C.POINTER(Grid), C.c_int, C.c_double, C.c_double, C.c_double]
+                           + [C.c_void_p] * 8 + [C.POINTER(C.c_void_p)]),
     "ipmpde_problem_destroy": (None, [C.c_void_p]),
     "ipmpde_footprint_bytes": (C.c_size_t, [C.POINTER(Grid), C.POINTER(Pde), C.c_int, C.POINTER(COptions)]),
     "ipmpde_solve": (C.c_int, [C.c_void_p, C.POINTER(COptions), C.c_void_p]),

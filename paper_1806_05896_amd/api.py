@@ -135,24 +135,33 @@ class Problem:
     """One problem instance resident on the GPU (ipmpde_problem)."""
 
     def __init__(self, data=None, *, dim=None, N=None, pde="poisson", eps=1.0, alpha=None, beta=None,
-                 u_a=None, u_b=None, y_a=None, y_b=None, y_d=None, f=None, g=None, obs=None):
+                 u_a=None, u_b=None, y_a=None, y_b=None, y_d=None, f=None, g=None, obs=None,
+                 nt=1, tau=0.0, y0=None):
         if data is not None:
             dim, N, pde, eps = data.dim, data.N, data.pde, data.eps
             alpha, beta = data.alpha, data.beta
             u_a, u_b, y_a, y_b, y_d, f, g = data.u_a, data.u_b, data.y_a, data.y_b, data.y_d, data.f, data.g
             obs = getattr(data, "obs", None)
+            nt, tau, y0 = getattr(data, "nt", 1), getattr(data, "tau", 0.0), getattr(data, "y0", None)
         self._lib = L.load()
         self.dim, self.N = int(dim), int(N)
-        self.n = self.N ** self.dim
+        self.nt = int(nt) if pde == "heat" else 1
+        self.n = self.N ** self.dim * self.nt
         n = self.n
         self._keep = [_f64(u_a, n, "u_a"), _f64(u_b, n, "u_b"), _f64(y_a, n, "y_a"), _f64(y_b, n, "y_b"),
                       _f64(y_d, n, "y_d"), _f64(f, n, "f"), _f64(g, (self.N + 2) ** self.dim, "g")]
         grid = L.Grid(self.dim, self.N)
-        kind = {"poisson": L.POISSON, "convdiff": L.CONVDIFF}[pde]
-        pdes = L.Pde(kind, float(eps))
         h = C.c_void_p()
-        L.check(self._lib.ipmpde_problem_create(C.byref(grid), C.byref(pdes), float(alpha), float(beta),
-                                                *[_ptr(a) for a in self._keep], C.byref(h)))
+        if pde == "heat":
+            # the heat equation (Sec. 4.4): nt backward Euler steps of length tau
+            self._keep.append(_f64(y0, self.N ** self.dim, "y0"))
+            L.check(self._lib.ipmpde_heat_create(C.byref(grid), self.nt, float(tau), float(alpha), float(beta),
+                                                 *[_ptr(a) for a in self._keep], C.byref(h)))
+        else:
+            kind = {"poisson": L.POISSON, "convdiff": L.CONVDIFF}[pde]
+            pdes = L.Pde(kind, float(eps))
+            L.check(self._lib.ipmpde_problem_create(C.byref(grid), C.byref(pdes), float(alpha), float(beta),
+                                                    *[_ptr(a) for a in self._keep], C.byref(h)))
         self._h = h
         self.has_state_bounds = y_a is not None
         self._keep = None

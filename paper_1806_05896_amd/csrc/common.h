@@ -68,7 +68,9 @@ struct KrylovCtrl {
 // launch can advance many (unevenly sized) instances; a single problem is a
 // batch of one.
 struct Inst {
-  int dim, N, n, pde;  // pde: 0 Poisson, 1 convection-diffusion
+  int dim, N, n, pde;  // pde: 0 Poisson, 1 convection-diffusion, 2 heat (n = N^2 nt space-time nodes)
+  int nt;              // heat: time steps (1 otherwise)
+  double tau;          // heat: time step
   int has_y;
   int active;          // 0: every kernel skips this instance
   double h, eps, alpha, beta;
@@ -207,6 +209,53 @@ __device__ __forceinline__ void node_coords(int idx, int N, int dim, int& i1, in
   int t = idx / N;
   if (dim == 2) { i2 = t; i3 = 0; }
   else { i2 = t % N; i3 = t / N; }
+}
+
+// Coordinates of node idx of an instance's state vector: for the heat
+// equation (time steps stacked after the N^2 nodes of each step) i3 is the
+// time step.
+__device__ __forceinline__ void inst_coords(int pde, int idx, int N, int dim, int& i1, int& i2, int& i3) {
+  node_coords(idx, N, pde == 2 ? 3 : dim, i1, i2, i3);
+}
+
+// (A x)_idx or (A^T x)_idx of the instance's state operator.  Heat equation
+// (Sec. 4.4, divided by tau with M = I): blocks I/tau + A_h on the diagonal,
+// -I/tau on the block subdiagonal, so A couples step i3 to step i3 - 1 and
+// A^T to step i3 + 1.
+template <typename T>
+__device__ __forceinline__ T inst_op(const Inst& I, const T* __restrict__ x, int idx, int i1, int i2, int i3,
+                                     bool transpose) {
+  if (I.pde != 2) return apply_op<T>(x, idx, i1, i2, i3, I.N, I.dim, I.pde, I.h, I.eps, transpose);
+  const double it = 1.0 / I.tau;
+  const int nn = I.N * I.N;
+  double r = (double)apply_op_s<T>(x, idx, i1, i2, 0, I.N, I.N, nn, 2, 0, I.h, 0.0, false) + it * (double)x[idx];
+  if (!transpose) {
+    if (i3 > 0) r -= it * (double)x[idx - nn];
+  } else {
+    if (i3 < I.nt - 1) r -= it * (double)x[idx + nn];
+  }
+  return (T)r;
+}
+
+// (|A| |x|)_idx (or with |A^T|) for rounding-error bounds.  Every
+// off-diagonal entry of the operators is <= 0, so |A||x| = 2 diag |x| - A|x|.
+__device__ __forceinline__ double inst_op_abs(const Inst& I, const double* __restrict__ x, int idx, int i1, int i2,
+                                              int i3, bool transpose) {
+  if (I.pde != 2) {
+    const double d = op_diag(I.dim, I.pde, I.h, I.eps, i1, i2);
+    return 2.0 * d * fabs(x[idx]) -
+           apply_op_s<double, true>(x, idx, i1, i2, i3, I.N, I.N, I.N * I.N, I.dim, I.pde, I.h, I.eps, transpose);
+  }
+  const double it = 1.0 / I.tau, d = 4.0 / (I.h * I.h);
+  const int nn = I.N * I.N;
+  double r = 2.0 * d * fabs(x[idx]) - apply_op_s<double, true>(x, idx, i1, i2, 0, I.N, I.N, nn, 2, 0, I.h, 0.0, false);
+  r += it * fabs(x[idx]);
+  if (!transpose) {
+    if (i3 > 0) r += it * fabs(x[idx - nn]);
+  } else {
+    if (i3 < I.nt - 1) r += it * fabs(x[idx + nn]);
+  }
+  return r;
 }
 
 // ---------------------------------------------------------------------------

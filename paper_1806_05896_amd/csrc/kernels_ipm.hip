@@ -44,11 +44,11 @@ __global__ void __launch_bounds__(kBS) k_measures(const Inst* __restrict__ Dp) {
   double r[3] = {0.0, 0.0, 0.0};
   if (i < I.n) {
     int i1, i2, i3;
-    node_coords(i, I.N, I.dim, i1, i2, i3);
+    inst_coords(I.pde, i, I.N, I.dim, i1, i2, i3);
     const double y = I.y[i], w = I.w[i], v = I.v[i], p = I.p[i];
     const double u = w - v;
-    const double Ay = apply_op<double>(I.y, i, i1, i2, i3, I.N, I.dim, I.pde, I.h, I.eps, false);
-    const double ATp = apply_op<double>(I.p, i, i1, i2, i3, I.N, I.dim, I.pde, I.h, I.eps, true);
+    const double Ay = inst_op<double>(I, I.y, i, i1, i2, i3, false);
+    const double ATp = inst_op<double>(I, I.p, i, i1, i2, i3, true);
     const double ua = I.ua[i], ub = I.ub[i];
     const double lwa = I.lwa[i], lwb = I.lwb[i], lva = I.lva[i], lvb = I.lvb[i];
     r[0] = fabs(Ay - u - I.fhat[i]);
@@ -108,7 +108,7 @@ __global__ void __launch_bounds__(kBS) k_newton_setup(const Inst* __restrict__ D
   double acc[1] = {0.0};
   if (i < I.n) {
     int i1, i2, i3;
-    node_coords(i, I.N, I.dim, i1, i2, i3);
+    inst_coords(I.pde, i, I.N, I.dim, i1, i2, i3);
     const double y = I.y[i], w = I.w[i], v = I.v[i], p = I.p[i];
     const double ua = I.ua[i], ub = I.ub[i];
     const double gwb = ub - w, gvb = -ua - v;
@@ -127,11 +127,12 @@ __global__ void __launch_bounds__(kBS) k_newton_setup(const Inst* __restrict__ D
     I.tw[i] = tw;
     I.tv[i] = tv;
     I.mh[i] = mh;
-    ((T*)I.lv[0].mh)[i] = (T)mh;
+    // heat equation: every time step's multigrid operator is I/tau + A_h + M_hat
+    ((T*)I.lv[0].mh)[i] = (T)(I.pde == 2 ? mh + 1.0 / I.tau : mh);
     if (I.ppi) ((T*)I.lv[0].mhb)[I.n + i] = (T)(ow + ty);
     const double u = w - v;
-    const double Ay = apply_op<double>(I.y, i, i1, i2, i3, I.N, I.dim, I.pde, I.h, I.eps, false);
-    const double ATp = apply_op<double>(I.p, i, i1, i2, i3, I.N, I.dim, I.pde, I.h, I.eps, true);
+    const double Ay = inst_op<double>(I, I.y, i, i1, i2, i3, false);
+    const double ATp = inst_op<double>(I, I.p, i, i1, i2, i3, true);
     const double ry = -(ow * (y - I.yd[i]) + ATp + by);
     const double rw = -(I.alpha * u + I.beta - p - mu / w + mu / gwb);
     const double rv = -(-I.alpha * u + I.beta + p - mu / v + mu / gvb);
@@ -274,8 +275,8 @@ __global__ void __launch_bounds__(kBS) k_apply_op(const Inst* __restrict__ Dp, c
   const int i = xcd_node(I.n);
   if (i >= I.n) return;
   int i1, i2, i3;
-  node_coords(i, I.N, I.dim, i1, i2, i3);
-  y[i] = apply_op<double>(x, i, i1, i2, i3, I.N, I.dim, I.pde, I.h, I.eps, transpose != 0);
+  inst_coords(I.pde, i, I.N, I.dim, i1, i2, i3);
+  y[i] = inst_op<double>(I, x, i, i1, i2, i3, transpose != 0);
 }
 
 // X = 0 (4n) for every active instance.

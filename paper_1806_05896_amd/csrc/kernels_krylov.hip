@@ -32,12 +32,12 @@ namespace ipm {
 __device__ __forceinline__ void saddle_rows(const Inst& I, const double* __restrict__ x, int i, double s,
                                             double out[4]) {
   int i1, i2, i3;
-  node_coords(i, I.N, I.dim, i1, i2, i3);
+  inst_coords(I.pde, i, I.N, I.dim, i1, i2, i3);
   const int n = I.n;
   const double xy = x[i], xw = x[n + i], xv = x[2 * n + i];
   const double ty = I.ty[i], tw = I.tw[i], tv = I.tv[i], a = I.alpha;
-  const double ATxp = apply_op<double>(x + 3 * n, i, i1, i2, i3, I.N, I.dim, I.pde, I.h, I.eps, true);
-  const double Axy = apply_op<double>(x, i, i1, i2, i3, I.N, I.dim, I.pde, I.h, I.eps, false);
+  const double ATxp = inst_op<double>(I, x + 3 * n, i, i1, i2, i3, true);
+  const double Axy = inst_op<double>(I, x, i, i1, i2, i3, false);
   const double xp = x[3 * n + i];
   out[0] = s * ((obs_w(I, i) + ty) * xy + ATxp);
   out[1] = s * ((a + tw) * xw - a * xv - xp);
@@ -48,14 +48,12 @@ __device__ __forceinline__ void saddle_rows(const Inst& I, const double* __restr
 // |K||x| row by row (all off-diagonal stencil entries are <= 0, so |A||x| = 2 diag |x| - A|x|).
 __device__ __forceinline__ void saddle_rows_abs(const Inst& I, const double* __restrict__ x, int i, double out[4]) {
   int i1, i2, i3;
-  node_coords(i, I.N, I.dim, i1, i2, i3);
+  inst_coords(I.pde, i, I.N, I.dim, i1, i2, i3);
   const int n = I.n;
   const double xy = fabs(x[i]), xw = fabs(x[n + i]), xv = fabs(x[2 * n + i]), xp = fabs(x[3 * n + i]);
   const double ty = I.ty[i], tw = I.tw[i], tv = I.tv[i], a = I.alpha;
-  const double d = op_diag(I.dim, I.pde, I.h, I.eps, i1, i2);
-  const int NN = I.N * I.N;
-  const double ATxp = 2.0 * d * xp - apply_op_s<double, true>(x + 3 * n, i, i1, i2, i3, I.N, I.N, NN, I.dim, I.pde, I.h, I.eps, true);
-  const double Axy = 2.0 * d * xy - apply_op_s<double, true>(x, i, i1, i2, i3, I.N, I.N, NN, I.dim, I.pde, I.h, I.eps, false);
+  const double ATxp = inst_op_abs(I, x + 3 * n, i, i1, i2, i3, true);
+  const double Axy = inst_op_abs(I, x, i, i1, i2, i3, false);
   out[0] = (obs_w(I, i) + ty) * xy + ATxp;
   out[1] = (a + tw) * xw + a * xv + xp;
   out[2] = a * xw + (a + tv) * xv + xp;
@@ -187,11 +185,11 @@ __global__ void __launch_bounds__(kBS) k_pt_rhs(const Inst* __restrict__ Dp, con
   const int i = blockIdx.x * kBS + threadIdx.x;
   if (i >= I.n) return;
   int i1, i2, i3;
-  node_coords(i, I.N, I.dim, i1, i2, i3);
+  inst_coords(I.pde, i, I.N, I.dim, i1, i2, i3);
   const int n = I.n;
   const double* r = rx ? rx : I.fV + (size_t)j * 4 * n;
   const double* z = zx ? zx : I.fZ + (size_t)j * 4 * n;
-  const double Bz = apply_op<double>(z, i, i1, i2, i3, I.N, I.dim, I.pde, I.h, I.eps, false) - z[n + i] + z[2 * n + i];
+  const double Bz = inst_op<double>(I, z, i, i1, i2, i3, false) - z[n + i] + z[2 * n + i];
   ((T*)I.lv[0].b)[i] = (T)(Bz - r[3 * n + i]);
 }
 

@@ -535,6 +535,22 @@ __global__ void __launch_bounds__(kBS) k_mg_scale_ty(const Inst* __restrict__ Dp
   ((T*)I.lv[0].b)[i] = (T)(obs_w(I, i) + I.ty[i]) * x[i];
 }
 
+// Block substitution of the heat equation's L + M_hat (Sec. 4.4; the block
+// below the diagonal is -I/tau): before the multigrid solve of time step t
+// (descriptor of that step) its right-hand side takes the neighbouring
+// step's solution, b_t += x_{t-dir} / tau, dir = 1 forward (L + M_hat),
+// dir = -1 backward (the transpose).  Consecutive steps' arrays are n apart.
+template <typename T>
+__global__ void __launch_bounds__(kBS) k_heat_couple(const Inst* __restrict__ Dp, int dir, int outsel, int guard) {
+  INST_BEGIN
+  if (mg_skip(I, guard)) return;
+  const int i = blockIdx.x * kBS + threadIdx.x;
+  if (i >= I.n) return;
+  const T* __restrict__ nb = mg_out<T>(I, outsel) - (ptrdiff_t)dir * I.n;
+  T* __restrict__ b = (T*)I.lv[0].b;
+  b[i] = (T)((double)b[i] + (double)nb[i] / I.tau);
+}
+
 // b_0 = (1 + Theta_y) x for the instances of a 2D batch whose whole
 // hierarchy runs in the coarse kernel (the others scale inside their first
 // descent kernel).
@@ -621,7 +637,8 @@ __global__ void __launch_bounds__(kBS) k_mg_kc_final(const Inst* __restrict__ Dp
   template __global__ void k_mg_prolong<T>(const Inst*, int, int, int, int);          \
   template __global__ void k_mg_coarse<T>(const Inst*, int, int);                     \
   template __global__ void k_mg_scale_ty<T>(const Inst*, int, int);                   \
-  template __global__ void k_mg_scale_ty_small<T>(const Inst*, int);
+  template __global__ void k_mg_scale_ty_small<T>(const Inst*, int);                   \
+  template __global__ void k_heat_couple<T>(const Inst*, int, int, int);
 IPM_MG_INST(float)
 IPM_MG_INST(double)
 #undef IPM_MG_INST

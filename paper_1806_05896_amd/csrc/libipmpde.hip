@@ -144,6 +144,7 @@ struct Group {
   int max_cpack = 0; // longest coarse LDS image (Poisson instances)
   bool any_small = false;  // 2D: some instance runs its whole hierarchy in the coarse kernel
   int outsel = 1;    // level-0 output buffer of a V-cycle (x2 = 1)
+  bool heat = false; // a heat-equation problem (always a group of one)
   int sel_pre = 0;   // 3D path: buffer holding the pre-smoothed iterate
   bool fp32 = true;
 };
@@ -174,6 +175,14 @@ struct ipmpde_problem {
   int cpack_elems32 = 0, cpack_elems64 = 0;
   int f_restart = 0;
   Group* self = nullptr;  // the group of one used by the single-problem entry points
+  // heat equation: nt time steps of length tau; every multigrid solve runs
+  // step by step on per-step descriptors (a 2D Poisson-type instance each,
+  // pointing into the space-time arrays), launched through hview
+  int nt = 1;
+  double tau = 0.0;
+  Inst* hs_h = nullptr;  // pinned host copies of the per-step descriptors
+  Inst* hs_d = nullptr;
+  Group hview;           // D = hs_d + t (one step, zc = 1) or hs_d (all steps, zc = nt)
   ipmpde_stats stats;
   double mu = 1.0;
   bool setup_done = false;
@@ -244,8 +253,47 @@ static bool is_p2(const ipmpde_problem* P) { return P->dim == 2 && P->pde == IPM
 // Schur-approximation operator's, and the two extra operators of P_Pi.
 static constexpr int kReactionSlots = 3;
 
+// Heat equation: every level array holds all nt time steps (step t at
+// offset t n_l); one reaction-term slot (I/tau + M_hat restricted); the
+// coarse LDS image once per step.
+static int ensure_mg_heat(ipmpde_problem* P, bool fp32) {
+  bool& have = fp32 ? P->have32 : P->have64;
+  Level* lv = fp32 ? P->lv32 : P->lv64;
+  if (have) return IPMPDE_OK;
+  const size_t el = fp32 ? 4 : 8, nt = (size_t)P->nt;
+  int N = P->N;
+  for (int l = 0; l < P->nlev; ++l) {
+    lv[l].N = N;
+    lv[l].n = N * N;
+    lv[l].h = 1.0 / (N + 1);
+    lv[l].invN = 1.0f / (float)N;
+    const size_t nb = (size_t)lv[l].n * el * nt;
+    TRY(P->work.alloc(&lv[l].x, nb));
+    TRY(P->work.alloc(&lv[l].x2, nb));
+    TRY(P->work.alloc(&lv[l].b, nb));
+    TRY(P->work.alloc(&lv[l].mh, nb));
+    lv[l].mhb = lv[l].mh;
+    for (void* a : {lv[l].x, lv[l].x2, lv[l].b, lv[l].mh}) HIP_TRY(hipMemset(a, 0, nb));
+    N = (N - 1) / 2;
+  }
+  for (void*& a : (fp32 ? P->kc32 : P->kc64)) TRY(P->work.alloc(&a, (size_t)lv[0].n * el * nt));
+  const int cl = pick_coarse(lv, P->nlev, el, 2, true);
+  (fp32 ? P->coarse32 : P->coarse64) = cl;
+  int elems = 0;
+  for (int l = cl; l < P->nlev; ++l) elems += coarse_p2_elems(lv[l].N);
+  void*& pk = fp32 ? P->cpack32 : P->cpack64;
+  TRY(P->work.alloc(&pk, nt * elems * el));
+  (fp32 ? P->cpack_elems32 : P->cpack_elems64) = elems;
+  Level*& lvd = fp32 ? P->lvd32 : P->lvd64;
+  TRY(P->work.alloc_t(&lvd, kMaxLev));
+  HIP_TRY(hipMemcpy(lvd, lv, sizeof(Level) * kMaxLev, hipMemcpyHostToDevice));
+  have = true;
+  return IPMPDE_OK;
+}
+
 static int ensure_mg(ipmpde_problem* P, bool fp32) {
   TRY(set_coarse_lds_limit());
+  if (P->pde == IPMPDE_HEAT) return ensure_mg_heat(P, fp32);
   bool& have = fp32 ? P->have32 : P->have64;
   Level* lv = fp32 ? P->lv32 : P->lv64;
   if (have) return IPMPDE_OK;
@@ -367,6 +415,7 @@ static int group_create(const std::vector<ipmpde_problem*>& probs, int cap, int 
   G->cap = cap;
   G->zc = G->count;
   G->dim = dim;
+  G->heat = probs.size() == 1 && probs[0]->pde == IPMPDE_HEAT;
   auto bail = [&](int rc) { group_release(G); return rc; };
   int rc;
   if ((rc = G->mem.alloc_t(&G->D, cap))) return bail(rc);
@@ -393,6 +442,73 @@ static int group_create(const std::vector<ipmpde_problem*>& probs, int cap, int 
   }
   *out = G;
   return IPMPDE_OK;
+}
+
+// Heat equation: the per-time-step descriptors (from the problem's filled
+// descriptor d) and the launch view over them.  Step t is a 2D Poisson-type
+// instance with operator I/tau + A_h + M_hat_t whose arrays are the t-th
+// slices of the space-time arrays.
+static void heat_steps(ipmpde_problem* P, const Inst& d, bool fp32) {
+  const Level* lv = fp32 ? P->lv32 : P->lv64;
+  const size_t el = fp32 ? 4 : 8;
+  const int n2 = P->N * P->N;
+  void* const* kc = fp32 ? P->kc32 : P->kc64;
+  char* pk = (char*)(fp32 ? P->cpack32 : P->cpack64);
+  const int pe = fp32 ? P->cpack_elems32 : P->cpack_elems64;
+  auto at = [](void* base, size_t off) { return (void*)((char*)base + off); };
+  for (int t = 0; t < P->nt; ++t) {
+    Inst& S = P->hs_h[t];
+    S = d;
+    S.pde = IPMPDE_POISSON;
+    S.n = n2;
+    S.nt = 1;
+    for (int l = 0; l < P->nlev; ++l) {
+      const size_t off = (size_t)t * lv[l].n * el;
+      S.lv[l] = lv[l];
+      S.lv[l].x = at(lv[l].x, off);
+      S.lv[l].x2 = at(lv[l].x2, off);
+      S.lv[l].b = at(lv[l].b, off);
+      S.lv[l].mh = at(lv[l].mh, off);
+      S.lv[l].mhb = S.lv[l].mh;
+    }
+    const size_t o2 = (size_t)t * n2;
+    S.ty = d.ty + o2;
+    S.tw = d.tw + o2;
+    S.tv = d.tv + o2;
+    S.obs = d.obs ? d.obs + o2 : nullptr;
+    S.kc_b0 = at(kc[0], o2 * el);
+    S.kc_s[0] = at(kc[1], o2 * el);
+    S.kc_s[1] = at(kc[2], o2 * el);
+    S.coarse_p2 = 1;
+    S.cpack = pk + (size_t)t * pe * el;
+    S.cpackb = S.cpack;
+    S.cpack_slot = pe;
+    S.cpack_elems = pe;
+    S.ppi = 0;
+    S.lvd = nullptr;
+  }
+  Group& V = P->hview;
+  V.count = 1;
+  V.dim = 2;
+  V.zc = 1;
+  V.D = P->hs_d;
+  V.H = P->hs_h;
+  V.fp32 = fp32;
+  V.max_n = n2;
+  V.max_nlev = P->nlev;
+  V.max_cl = d.coarse_lev;
+  std::fill(V.maxN, V.maxN + kMaxLev, 0);
+  std::fill(V.maxn, V.maxn + kMaxLev, 0);
+  for (int l = 0; l < P->nlev; ++l) {
+    V.maxN[l] = lv[l].N;
+    V.maxn[l] = lv[l].n;
+  }
+  V.coarse_lds = coarse_lds_bytes(lv, P->nlev, d.coarse_lev, el, true);
+  V.p2 = true;
+  V.gen = false;
+  V.max_cpack = pe;
+  V.any_small = d.coarse_lev == 0;
+  V.outsel = 1;
 }
 
 // Refresh the descriptors from the problems' templates (keeping the
@@ -463,6 +579,7 @@ static int group_select(Group* G, const ipmpde_options& o) {
     G->gen = G->gen || !is_p2(P);
     G->coarse_lds = std::max(G->coarse_lds, coarse_lds_bytes(lv, P->nlev, d.coarse_lev, fp32 ? 4 : 8, is_p2(P)));
   }
+  if (G->heat) heat_steps(G->probs[0], G->H[0], fp32);
   if (G->dim == 2) {
     G->outsel = 1;
   } else {
@@ -479,6 +596,10 @@ static int group_select(Group* G, const ipmpde_options& o) {
 static int group_sync(Group* G, hipStream_t s) {
   for (int i = G->count; i < G->zc; ++i) G->H[i].active = 0;
   HIP_TRY(hipMemcpyAsync(G->D, G->H, sizeof(Inst) * G->zc, hipMemcpyHostToDevice, s));
+  if (G->heat) {
+    const ipmpde_problem* P = G->probs[0];
+    HIP_TRY(hipMemcpyAsync(P->hs_d, P->hs_h, sizeof(Inst) * P->nt, hipMemcpyHostToDevice, s));
+  }
   return IPMPDE_OK;
 }
 
@@ -709,11 +830,39 @@ static void mg_solve(Group* G, int transpose, int guard, int scaled, hipStream_t
   if (k > 1) hipLaunchKernelGGL(k_mg_kc_final<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, G->outsel, k, guard);
 }
 
+// Heat equation (Sec. 4.4): S_hat^-1 = (L + M_hat)^-T (O + Theta_y)
+// (L + M_hat)^-1 with the block lower bidiagonal L + M_hat solved by block
+// forward substitution, each diagonal block I/tau + A_h + M_hat_t by the
+// multigrid solve of its time step, and the transpose by block backward
+// substitution with the same per-step solves.
+template <typename T>
+static void heat_schur_inv(Group* G, int guard, hipStream_t s) {
+  ipmpde_problem* P = G->probs[0];
+  Group* V = &P->hview;
+  V->zc = 1;
+  for (int t = 0; t < P->nt; ++t) {
+    V->D = P->hs_d + t;
+    if (t > 0) hipLaunchKernelGGL(k_heat_couple<T>, gz(V, V->max_n), dim3(kBS), 0, s, V->D, 1, G->outsel, guard);
+    mg_solve<T>(V, 0, guard, 0, s);
+  }
+  hipLaunchKernelGGL(k_mg_scale_ty<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, G->outsel, guard);
+  for (int t = P->nt - 1; t >= 0; --t) {
+    V->D = P->hs_d + t;
+    if (t < P->nt - 1) hipLaunchKernelGGL(k_heat_couple<T>, gz(V, V->max_n), dim3(kBS), 0, s, V->D, -1, G->outsel, guard);
+    mg_solve<T>(V, 1, guard, 0, s);
+  }
+  V->D = P->hs_d;
+}
+
 // S_hat^-1 applied to every instance's lv[0].b (Sec. 4.2): solve with
 // A + M_hat, scale by 1 + Theta_y, solve with (A + M_hat)^T.  The result is
 // the level-0 output array (selected in the kernels with G->outsel).
 template <typename T>
 static void schur_inv(Group* G, int guard, hipStream_t s) {
+  if (G->heat) {
+    heat_schur_inv<T>(G, guard, s);
+    return;
+  }
   if (G->dim == 2) {
     mg_solve<T>(G, 0, guard, 0, s);
     // instances whose whole hierarchy is in the coarse kernel never run a
@@ -916,7 +1065,25 @@ static void ppi_setup(Group* G, hipStream_t s) {
   mg_select(G, 0, s);
 }
 
+// Heat equation: the reaction term of every time step (written at level 0
+// by the Newton setup) restricted to all levels and each step's coarse
+// image, all steps in one launch per level.
+template <typename T>
+static void heat_setup(Group* G, hipStream_t s) {
+  ipmpde_problem* P = G->probs[0];
+  Group* V = &P->hview;
+  V->D = P->hs_d;
+  V->zc = P->nt;
+  hipLaunchKernelGGL(k_newton_setup<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D);
+  for (int l = 0; l + 1 < V->max_nlev; ++l)
+    hipLaunchKernelGGL(k_restrict_diag<T>, gz(V, V->maxn[l + 1]), dim3(kBS), 0, s, V->D, l);
+  hipLaunchKernelGGL(k_coarse_pack<T>, gz(V, V->max_cpack), dim3(kBS), 0, s, V->D);
+  V->zc = 1;
+}
+
 static int newton_setup_group(Group* G, const ipmpde_options& o, hipStream_t s) {
+  if (G->heat && o.precond == IPMPDE_PPI)
+    return fail(IPMPDE_EINVAL, "P_Pi is not available for the heat equation");
   for (int i = 0; i < G->count; ++i) {
     const ipmpde_problem* P = G->probs[i];
     if (o.precond != IPMPDE_PPI && P->obs_zero && !P->has_y)
@@ -924,7 +1091,10 @@ static int newton_setup_group(Group* G, const ipmpde_options& o, hipStream_t s) 
   }
   TRY(group_select(G, o));
   TRY(group_sync(G, s));
-  if (G->fp32) {
+  if (G->heat) {
+    if (G->fp32) heat_setup<float>(G, s);
+    else heat_setup<double>(G, s);
+  } else if (G->fp32) {
     hipLaunchKernelGGL(k_newton_setup<float>, gz(G, G->max_n), dim3(kBS), 0, s, G->D);
     for (int l = 0; l + 1 < G->max_nlev; ++l)
       hipLaunchKernelGGL(k_restrict_diag<float>, gz(G, G->maxn[l + 1]), dim3(kBS), 0, s, G->D, l);
@@ -1166,28 +1336,24 @@ extern "C" size_t ipmpde_footprint_bytes(const ipmpde_grid* grid, const ipmpde_p
 static void problem_free(ipmpde_problem* P) {
   if (P->self) group_release(P->self);
   P->self = nullptr;
+  if (P->hs_h) (void)hipHostFree(P->hs_h);
+  P->hs_h = nullptr;
   P->mem.release();
 }
 
-extern "C" int ipmpde_problem_create(const ipmpde_grid* grid, const ipmpde_pde* pde, double alpha, double beta,
-                                     const double* u_a, const double* u_b, const double* y_a, const double* y_b,
-                                     const double* y_d, const double* f, const double* g, ipmpde_problem** out) {
-  if (!out) return fail(IPMPDE_EINVAL, "out is NULL");
-  *out = nullptr;
-  if (!grid || !pde) return fail(IPMPDE_EINVAL, "grid and pde are required");
-  if (grid->dim != 2 && grid->dim != 3) return fail(IPMPDE_EINVAL, "dim must be 2 or 3");
-  if (!is_pow2m1(grid->n)) return fail(IPMPDE_EINVAL, "n must be 2^k - 1 with k >= 2");
-  if (grid->n > (grid->dim == 2 ? 8191 : 511)) return fail(IPMPDE_EINVAL, "grid too large");
-  if (pde->kind != IPMPDE_POISSON && pde->kind != IPMPDE_CONVDIFF) return fail(IPMPDE_EINVAL, "unknown pde kind");
-  if (pde->kind == IPMPDE_CONVDIFF && grid->dim != 2) return fail(IPMPDE_EINVAL, "convection-diffusion is 2D only");
-  if (pde->kind == IPMPDE_CONVDIFF && !(pde->eps > 0 && std::isfinite(pde->eps)))
-    return fail(IPMPDE_EINVAL, "eps must be positive");
+// Shared by the steady and the heat-equation constructors (kind, grid and
+// time steps already validated): copies the data, folds boundary data (and
+// for the heat equation the initial state) into f_hat.
+static int problem_create_impl(int dim, int N, int kind, double eps, int nt, double tau, double alpha, double beta,
+                               const double* u_a, const double* u_b, const double* y_a, const double* y_b,
+                               const double* y_d, const double* f, const double* g, const double* y0,
+                               ipmpde_problem** out) {
   if (!(alpha > 0 && std::isfinite(alpha))) return fail(IPMPDE_EINVAL, "alpha must be positive");
   if (!(beta >= 0 && std::isfinite(beta))) return fail(IPMPDE_EINVAL, "beta must be non-negative");
   if (!u_a || !u_b || !y_d) return fail(IPMPDE_EINVAL, "u_a, u_b and y_d are required");
   if ((y_a == nullptr) != (y_b == nullptr)) return fail(IPMPDE_EINVAL, "y_a and y_b must both be given or both NULL");
-  const int dim = grid->dim, N = grid->n;
-  const size_t n = pow_dim(N, dim);
+  const bool heat = kind == IPMPDE_HEAT;
+  const size_t n = pow_dim(N, dim) * (size_t)nt;
   TRY(validate_array(u_a, n, "u_a"));
   TRY(validate_array(u_b, n, "u_b"));
   TRY(validate_array(y_d, n, "y_d"));
@@ -1201,14 +1367,27 @@ extern "C" int ipmpde_problem_create(const ipmpde_grid* grid, const ipmpde_pde* 
   }
   if (f) TRY(validate_array(f, n, "f"));
   if (g) TRY(validate_array(g, pow_dim(N + 2, dim), "g"));
+  if (y0) TRY(validate_array(y0, pow_dim(N, dim), "y0"));
 
   std::vector<double> fhat(n, 0.0);
   if (f) std::copy(f, f + n, fhat.begin());
-  if (g) fold_boundary(dim, N, pde->kind, pde->kind == IPMPDE_POISSON ? 1.0 : pde->eps, g, fhat);
+  if (heat) {
+    // every time step sees the same boundary data; y0 / tau enters the first step
+    const size_t n2 = pow_dim(N, dim);
+    std::vector<double> step(n2, 0.0);
+    if (g) fold_boundary(dim, N, IPMPDE_POISSON, 1.0, g, step);
+    for (int t = 0; t < nt; ++t)
+      for (size_t i = 0; i < n2; ++i) fhat[(size_t)t * n2 + i] += step[i];
+    if (y0)
+      for (size_t i = 0; i < n2; ++i) fhat[i] += y0[i] / tau;
+  } else if (g) {
+    fold_boundary(dim, N, kind, kind == IPMPDE_POISSON ? 1.0 : eps, g, fhat);
+  }
 
   ipmpde_problem* P = new ipmpde_problem();
-  P->dim = dim; P->N = N; P->n = (int)n; P->pde = pde->kind;
-  P->eps = pde->kind == IPMPDE_POISSON ? 1.0 : pde->eps;
+  P->dim = dim; P->N = N; P->n = (int)n; P->pde = kind;
+  P->eps = kind == IPMPDE_CONVDIFF ? eps : 1.0;
+  P->nt = nt; P->tau = tau;
   P->alpha = alpha; P->beta = beta; P->has_y = y_a != nullptr;
   P->nlev = level_count(N);
   std::memset(&P->stats, 0, sizeof(P->stats));
@@ -1216,6 +1395,7 @@ extern "C" int ipmpde_problem_create(const ipmpde_grid* grid, const ipmpde_pde* 
   std::memset(&I, 0, sizeof(I));
   I.dim = dim; I.N = N; I.n = (int)n; I.pde = P->pde; I.has_y = P->has_y ? 1 : 0;
   I.h = 1.0 / (N + 1); I.eps = P->eps; I.alpha = alpha; I.beta = beta;
+  I.nt = nt; I.tau = tau;
   I.active = 1;
   I.mu = 1.0;
   I.alpha0 = 0.995;
@@ -1251,9 +1431,50 @@ extern "C" int ipmpde_problem_create(const ipmpde_grid* grid, const ipmpde_pde* 
     if ((e = hipMemcpy(ya, y_a, n * 8, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(e, "hipMemcpy");
     if ((e = hipMemcpy(yb, y_b, n * 8, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(e, "hipMemcpy");
   }
+  if (heat) {
+    if ((rc = M.alloc_t(&P->hs_d, (size_t)nt))) return cleanup(rc);
+    if ((e = hipHostMalloc((void**)&P->hs_h, sizeof(Inst) * nt, hipHostMallocDefault)) != hipSuccess)
+      return hip_fail(e, "hipHostMalloc");
+    std::memset((void*)P->hs_h, 0, sizeof(Inst) * nt);
+  }
   if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "init");
   *out = P;
   return IPMPDE_OK;
+}
+
+extern "C" int ipmpde_problem_create(const ipmpde_grid* grid, const ipmpde_pde* pde, double alpha, double beta,
+                                     const double* u_a, const double* u_b, const double* y_a, const double* y_b,
+                                     const double* y_d, const double* f, const double* g, ipmpde_problem** out) {
+  if (!out) return fail(IPMPDE_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!grid || !pde) return fail(IPMPDE_EINVAL, "grid and pde are required");
+  if (grid->dim != 2 && grid->dim != 3) return fail(IPMPDE_EINVAL, "dim must be 2 or 3");
+  if (!is_pow2m1(grid->n)) return fail(IPMPDE_EINVAL, "n must be 2^k - 1 with k >= 2");
+  if (grid->n > (grid->dim == 2 ? 8191 : 511)) return fail(IPMPDE_EINVAL, "grid too large");
+  if (pde->kind == IPMPDE_HEAT) return fail(IPMPDE_EINVAL, "heat-equation problems are made by ipmpde_heat_create");
+  if (pde->kind != IPMPDE_POISSON && pde->kind != IPMPDE_CONVDIFF) return fail(IPMPDE_EINVAL, "unknown pde kind");
+  if (pde->kind == IPMPDE_CONVDIFF && grid->dim != 2) return fail(IPMPDE_EINVAL, "convection-diffusion is 2D only");
+  if (pde->kind == IPMPDE_CONVDIFF && !(pde->eps > 0 && std::isfinite(pde->eps)))
+    return fail(IPMPDE_EINVAL, "eps must be positive");
+  return problem_create_impl(grid->dim, grid->n, pde->kind, pde->eps, 1, 0.0, alpha, beta, u_a, u_b, y_a, y_b, y_d,
+                             f, g, nullptr, out);
+}
+
+extern "C" int ipmpde_heat_create(const ipmpde_grid* grid, int nt, double tau, double alpha, double beta,
+                                  const double* u_a, const double* u_b, const double* y_a, const double* y_b,
+                                  const double* y_d, const double* f, const double* g, const double* y0,
+                                  ipmpde_problem** out) {
+  if (!out) return fail(IPMPDE_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!grid) return fail(IPMPDE_EINVAL, "grid is required");
+  if (grid->dim != 2) return fail(IPMPDE_EINVAL, "the heat equation is posed on a 2D grid");
+  if (!is_pow2m1(grid->n)) return fail(IPMPDE_EINVAL, "n must be 2^k - 1 with k >= 2");
+  if (grid->n > 2047) return fail(IPMPDE_EINVAL, "grid too large");
+  if (nt < 1 || nt > 65535) return fail(IPMPDE_EINVAL, "nt must be in [1, 65535]");
+  if (!(tau > 0 && std::isfinite(tau))) return fail(IPMPDE_EINVAL, "tau must be positive");
+  if ((double)grid->n * grid->n * nt > 1.0e8) return fail(IPMPDE_EINVAL, "too many space-time nodes");
+  return problem_create_impl(2, grid->n, IPMPDE_HEAT, 1.0, nt, tau, alpha, beta, u_a, u_b, y_a, y_b, y_d, f, g, y0,
+                             out);
 }
 
 extern "C" void ipmpde_problem_destroy(ipmpde_problem* P) {
@@ -1544,6 +1765,7 @@ extern "C" int ipmpde_batch_create(ipmpde_problem* const* probs, int count, ipmp
   for (int i = 0; i < count; ++i) {
     if (!v[i]) return fail(IPMPDE_EINVAL, "NULL problem in batch");
     if (v[i]->dim != v[0]->dim) return fail(IPMPDE_EINVAL, "all problems of a batch must have the same dimension");
+    if (v[i]->pde == IPMPDE_HEAT) return fail(IPMPDE_EINVAL, "heat-equation problems are solved one at a time");
     for (int j = 0; j < i; ++j)
       if (v[j] == v[i]) return fail(IPMPDE_EINVAL, "a problem appears twice in the batch");
   }
