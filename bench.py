@@ -147,6 +147,33 @@ def bench_partial(W, torch, N, reps):
             "krylov_its_per_s": s.krylov_its / t, "status": rc}
 
 
+def bench_heat(W, torch, N, nt, reps):
+    """Heat equation, all nt time steps at once (tau = 1/nt), one instance:
+    FGMRES(30) + P_T (the paper's choice for this problem) and MINRES + P_D,
+    FP32 V-cycles; the Schur solves are block substitutions over the steps."""
+    from paper_1806_05896_amd import Options, Problem
+    d = W.heat2d(seed=0, N=N, nt=nt)
+    stream = torch.cuda.current_stream()
+    out = {"workload": f"heat2d: heat equation {N}x{N} x {nt} backward Euler steps (tau={1.0 / nt:g}), "
+                       f"y_d = A sin(pi x1) sin(pi x2), alpha=1e-4, beta=1e-2, u in [-15,15], sigma=0.25",
+           "space_time_nodes": d.n}
+    with Problem(d) as p:
+        for name, kry, pre in (("fgmres_pt", "fgmres", "pt"), ("minres_pd", "minres", "pd")):
+            o = Options(sigma=d.sigma, krylov=kry, precond=pre, mg_precision="fp32")
+            p.solve(o, stream=stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                rc = p.solve(o, stream=stream)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / reps
+            s = p.stats()
+            log(f"heat {N}^2 x {nt} {name}: {1 / t:.2f} solves/s, nli {s.nli}, its {s.krylov_its}")
+            out[name] = {"solves_per_s": 1 / t, "ms_per_solve": t * 1e3, "nli": s.nli,
+                         "krylov_its_per_solve": s.krylov_its, "krylov_its_per_s": s.krylov_its / t, "status": rc}
+    return out
+
+
 def solver_options(d, Options, prec="fp32"):
     """Per-request solver choice: MINRES + P_D for Poisson, FGMRES(30) + P_T
     for convection-diffusion, multigrid in the given precision."""
@@ -278,7 +305,9 @@ def main():
     ap.add_argument("--serve-budget-gib", type=float, default=32.0)
     ap.add_argument("--serve-loads", type=str, default="0.8", help="arrival rates as fractions of saturation")
     ap.add_argument("--partial-N", type=int, default=255, help="grid of the partial-observation run (0: skip)")
-    ap.add_argument("--only", choices=["serve", "batch", "partial"], default=None,
+    ap.add_argument("--heat-N", type=int, default=63, help="grid of the heat-equation run (0: skip)")
+    ap.add_argument("--heat-nt", type=int, default=100, help="time steps of the heat-equation run")
+    ap.add_argument("--only", choices=["serve", "batch", "partial", "heat"], default=None,
                     help="run one extra section alone")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only launch the roofline kernel (20 times) and a 1 GiB device copy, for counter runs")
@@ -305,6 +334,9 @@ def main():
         return
     if args.only == "partial":
         print(json.dumps({"partial_observation": bench_partial(W, torch, args.partial_N, 3)}), flush=True)
+        return
+    if args.only == "heat":
+        print(json.dumps({"heat": bench_heat(W, torch, args.heat_N, args.heat_nt, 3)}), flush=True)
         return
     if args.only == "batch":
         print(json.dumps({"batched": bench_batched(W, torch, max(1, args.batch), 2)}), flush=True)
@@ -422,6 +454,8 @@ def main():
 
     if args.partial_N > 0:
         result["partial_observation"] = bench_partial(W, torch, args.partial_N, 2)
+    if args.heat_N > 0:
+        result["heat"] = bench_heat(W, torch, args.heat_N, args.heat_nt, 2)
 
     if args.serve_requests > 0:
         result["serving"] = bench_serving(W, torch, args.serve_requests, args.serve_slots, args.serve_budget_gib,

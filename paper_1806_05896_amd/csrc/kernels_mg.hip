@@ -384,6 +384,115 @@ __global__ void __launch_bounds__(kBS) k_coarse_pack(const Inst* __restrict__ Dp
 template __global__ void k_coarse_pack<float>(const Inst*);
 template __global__ void k_coarse_pack<double>(const Inst*);
 
+// Loop over the nodes of an N x N level with NT threads (thread t), as P2_FOR.
+#define P2_FOR_T(NN, T_, NT_)                                                        \
+  {                                                                                  \
+    const int sh_ = 31 - __builtin_clz((NN) + 1), step_ = (NT_) >> sh_;             \
+    const int i1 = (T_) & ((1 << sh_) - 1);                                          \
+    for (int i2 = (T_) >> sh_; i2 < (NN) && i1 < (NN); i2 += step_) {                \
+      const int i = i1 + (NN) * i2;                                                  \
+      const int p = (i1 + 1) + ((NN) + 2) * (i2 + 1);                                \
+      (void)i; (void)p;
+
+// Descent at level l: nu_pre damped-Jacobi sweeps from zero, the residual and
+// its full-weighting restriction to level l + 1's right-hand side.
+template <typename T, int NT>
+__device__ __forceinline__ void p2_down(const Inst& I, T* lds, const int* LN, const int* LOFF, const T* LIH2, int l,
+                                        int tid, T om, unsigned& alt) {
+  const int N = LN[l], P = N + 2, n = N * N;
+  const T ih2 = LIH2[l];
+  T* a = lds + LOFF[l];
+  T* c = a + P * P;
+  const T* b = c + P * P;
+  const T* d = b + n;
+  const T* dinv = d + n;
+  for (int s = 0; s < I.nu_pre; ++s) {
+    if (s == 0) {
+      P2_FOR_T(N, tid, NT) c[p] = om * b[i] * dinv[i]; P2_END
+    } else {
+      P2_FOR_T(N, tid, NT) c[p] = a[p] + om * (b[i] - d[i] * a[p] + ih2 * (a[p - 1] + a[p + 1] + a[p - P] + a[p + P])) * dinv[i]; P2_END
+    }
+    __syncthreads();
+    T* t = a; a = c; c = t;
+    alt ^= 1u << l;
+  }
+  P2_FOR_T(N, tid, NT) c[p] = b[i] - d[i] * a[p] + ih2 * (a[p - 1] + a[p + 1] + a[p - P] + a[p + P]); P2_END
+  __syncthreads();
+  const int Nc = LN[l + 1];
+  T* bc = lds + LOFF[l + 1] + 2 * (Nc + 2) * (Nc + 2);
+  {
+    const int sh = 31 - __builtin_clz(Nc + 1), msk = (1 << sh) - 1, step = NT >> sh;
+    const int j1 = tid & msk;
+    for (int j2 = tid >> sh; j2 < Nc && j1 < Nc; j2 += step) {
+      const int ic = j1 + Nc * j2;
+      const int p = (2 * j1 + 2) + P * (2 * j2 + 2);  // fine node 2j+1 (0-based) in padded coordinates
+      bc[ic] = (T)0.25 * c[p] + (T)0.125 * (c[p - 1] + c[p + 1] + c[p - P] + c[p + P]) +
+               (T)0.0625 * (c[p - 1 - P] + c[p + 1 - P] + c[p - 1 + P] + c[p + 1 + P]);
+    }
+  }
+  __syncthreads();
+}
+
+// Ascent at level l: bilinear prolongation of level l + 1's iterate (in xb
+// when bit l + 1 of alt is set) added to the iterate, nu_post sweeps.
+template <typename T, int NT>
+__device__ __forceinline__ void p2_up(const Inst& I, T* lds, const int* LN, const int* LOFF, const T* LIH2, int l,
+                                      int tid, T om, unsigned& alt) {
+  const int N = LN[l], P = N + 2, n = N * N;
+  const int Nc = LN[l + 1], Pc = Nc + 2;
+  const T ih2 = LIH2[l];
+  T* base = lds + LOFF[l];
+  const int ca = (alt >> l) & 1u;
+  T* a = base + ca * P * P;
+  T* c = base + (1 - ca) * P * P;
+  const T* b = base + 2 * P * P;
+  const T* d = b + n;
+  const T* dinv = d + n;
+  const T* xc = lds + LOFF[l + 1] + ((alt >> (l + 1)) & 1u) * Pc * Pc;
+  P2_FOR_T(N, tid, NT)
+    // bilinear interpolation: fine 1-based F maps to coarse F/2 (even) or the two neighbours (odd);
+    // in padded coarse coordinates the boundary nodes are the zero ring
+    const int F1 = i1 + 1, F2 = i2 + 1;
+    const int lo1 = F1 >> 1, hi1 = (F1 + 1) >> 1, lo2 = F2 >> 1, hi2 = (F2 + 1) >> 1;
+    const T v = (T)0.25 * (xc[lo1 + Pc * lo2] + xc[hi1 + Pc * lo2] + xc[lo1 + Pc * hi2] + xc[hi1 + Pc * hi2]);
+    a[F1 + P * F2] += v;
+  P2_END
+  __syncthreads();
+  for (int s = 0; s < I.nu_post; ++s) {
+    P2_FOR_T(N, tid, NT) c[p] = a[p] + om * (b[i] - d[i] * a[p] + ih2 * (a[p - 1] + a[p + 1] + a[p - P] + a[p + P])) * dinv[i]; P2_END
+    __syncthreads();
+    T* t = a; a = c; c = t;
+    alt ^= 1u << l;
+  }
+}
+
+// The V-cycle of the Poisson coarse kernel on the LDS image (level tables
+// LN, LOFF, LIH2 set, top-level right-hand side in place): pre-smoothing,
+// residual and restriction down to the single-node grid, its exact solve,
+// prolongation and post-smoothing back up.  Returns the top level's final
+// iterate (padded layout) in LDS.
+template <typename T>
+__device__ __forceinline__ const T* coarse_p2_cycle(const Inst& I, T* lds, const int* LN, const int* LOFF,
+                                                    const T* LIH2) {
+  const int cl = I.coarse_lev, L = I.nlev;
+  const int tid = threadIdx.x;
+  const T om = (T)I.omega;
+  unsigned alt = 0;  // bit l: level l's iterate sits in xb
+  for (int l = cl; l < L - 1; ++l) p2_down<T, kCoarseBS>(I, lds, LN, LOFF, LIH2, l, tid, om, alt);
+  {
+    // coarsest grid (one node): exact solve
+    const int l = L - 1, N = LN[l], P = N + 2, n = N * N;
+    T* a = lds + LOFF[l];
+    const T* b = a + 2 * P * P;
+    const T* dinv = b + 2 * n;
+    P2_FOR_T(N, tid, kCoarseBS) a[p] = b[i] * dinv[i]; P2_END
+    __syncthreads();
+  }
+  for (int l = L - 2; l >= cl; --l) p2_up<T, kCoarseBS>(I, lds, LN, LOFF, LIH2, l, tid, om, alt);
+  const int N = LN[cl], P = N + 2;
+  return lds + LOFF[cl] + ((alt >> cl) & 1u) * P * P;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_p2(const Inst* __restrict__ Dp, int guard) {
   INST_BEGIN
@@ -394,7 +503,6 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_p2(const Inst* __restri
   T* lds = (T*)lds_raw;
   const int cl = I.coarse_lev, L = I.nlev;
   const int tid = threadIdx.x;
-  const T om = (T)I.omega;
   const int N0 = I.lv[cl].N, n0 = N0 * N0;
   // the top level's right-hand side, in flight while the image is copied
   const T* __restrict__ bg = (const T*)I.lv[cl].b;
@@ -440,87 +548,126 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_p2(const Inst* __restri
     }
   }
   __syncthreads();
-  unsigned alt = 0;  // bit l: level l's iterate sits in xb
-  for (int l = cl; l < L - 1; ++l) {
-    const int N = LN[l], P = N + 2, n = N * N;
-    const T ih2 = LIH2[l];
-    T* a = lds + LOFF[l];
-    T* c = a + P * P;
-    const T* b = c + P * P;
-    const T* d = b + n;
-    const T* dinv = d + n;
-    for (int s = 0; s < I.nu_pre; ++s) {
-      if (s == 0) {
-        P2_FOR(N) c[p] = om * b[i] * dinv[i]; P2_END
-      } else {
-        P2_FOR(N) c[p] = a[p] + om * (b[i] - d[i] * a[p] + ih2 * (a[p - 1] + a[p + 1] + a[p - P] + a[p + P])) * dinv[i]; P2_END
-      }
-      __syncthreads();
-      T* t = a; a = c; c = t;
-      alt ^= 1u << l;
-    }
-    P2_FOR(N) c[p] = b[i] - d[i] * a[p] + ih2 * (a[p - 1] + a[p + 1] + a[p - P] + a[p + P]); P2_END
-    __syncthreads();
-    const int Nc = LN[l + 1], nc = Nc * Nc;
-    T* bc = lds + LOFF[l + 1] + 2 * (Nc + 2) * (Nc + 2);
-    {
-      const int sh = 31 - __builtin_clz(Nc + 1), msk = (1 << sh) - 1, step = kCoarseBS >> sh;
-      const int j1 = tid & msk;
-      for (int j2 = tid >> sh; j2 < Nc && j1 < Nc; j2 += step) {
-        const int ic = j1 + Nc * j2;
-        const int p = (2 * j1 + 2) + P * (2 * j2 + 2);  // fine node 2j+1 (0-based) in padded coordinates
-        bc[ic] = (T)0.25 * c[p] + (T)0.125 * (c[p - 1] + c[p + 1] + c[p - P] + c[p + P]) +
-                 (T)0.0625 * (c[p - 1 - P] + c[p + 1 - P] + c[p - 1 + P] + c[p + 1 + P]);
-      }
-    }
-    __syncthreads();
-  }
+  const T* a = coarse_p2_cycle<T>(I, lds, LN, LOFF, LIH2);
   {
-    // coarsest grid (one node): exact solve
-    const int l = L - 1, N = LN[l], P = N + 2, n = N * N;
-    T* a = lds + LOFF[l];
-    const T* b = a + 2 * P * P;
-    const T* dinv = b + 2 * n;
-    P2_FOR(N) a[p] = b[i] * dinv[i]; P2_END
-    __syncthreads();
-  }
-  for (int l = L - 2; l >= cl; --l) {
-    const int N = LN[l], P = N + 2, n = N * N;
-    const int Nc = LN[l + 1], Pc = Nc + 2;
-    const T ih2 = LIH2[l];
-    T* base = lds + LOFF[l];
-    const int ca = (alt >> l) & 1u;
-    T* a = base + ca * P * P;
-    T* c = base + (1 - ca) * P * P;
-    const T* b = base + 2 * P * P;
-    const T* d = b + n;
-    const T* dinv = d + n;
-    const T* xc = lds + LOFF[l + 1] + ((alt >> (l + 1)) & 1u) * Pc * Pc;
-    P2_FOR(N)
-      // bilinear interpolation: fine 1-based F maps to coarse F/2 (even) or the two neighbours (odd);
-      // in padded coarse coordinates the boundary nodes are the zero ring
-      const int F1 = i1 + 1, F2 = i2 + 1;
-      const int lo1 = F1 >> 1, hi1 = (F1 + 1) >> 1, lo2 = F2 >> 1, hi2 = (F2 + 1) >> 1;
-      const T v = (T)0.25 * (xc[lo1 + Pc * lo2] + xc[hi1 + Pc * lo2] + xc[lo1 + Pc * hi2] + xc[hi1 + Pc * hi2]);
-      a[F1 + P * F2] += v;
-    P2_END
-    __syncthreads();
-    for (int s = 0; s < I.nu_post; ++s) {
-      P2_FOR(N) c[p] = a[p] + om * (b[i] - d[i] * a[p] + ih2 * (a[p - 1] + a[p + 1] + a[p - P] + a[p + P])) * dinv[i]; P2_END
-      __syncthreads();
-      T* t = a; a = c; c = t;
-      alt ^= 1u << l;
-    }
-  }
-  {
-    const int N = LN[cl], P = N + 2, n = N * N;
-    const T* a = lds + LOFF[cl] + ((alt >> cl) & 1u) * P * P;
+    const int N = LN[cl];
     T* xg = (T*)I.lv[cl].x;
     P2_FOR(N) xg[i] = a[p]; P2_END
   }
 }
 template __global__ void k_mg_coarse_p2<float>(const Inst*, int);
 template __global__ void k_mg_coarse_p2<double>(const Inst*, int);
+
+// Heat equation, whole hierarchy in one workgroup (every step's coarse_lev
+// is 0, one V-cycle per step): a whole block substitution of L + M_hat
+// (dir = 1: steps 0..nt-1) or of its transpose (dir = -1: nt-1..0) in one
+// launch.  Step t's right-hand side takes the previous step's solution / tau
+// (held in registers), its V-cycle runs on its LDS image, and its solution
+// goes to its level-0 x; the arithmetic is that of k_heat_couple followed by
+// k_mg_coarse_p2 per step.  The iterate areas of the image are copied once:
+// every V-cycle writes each interior iterate value before reading it (the
+// first pre-smoothing sweep starts from zero) and never writes the zero
+// rings, so later steps copy only d and 1/d of each level.
+// d and 1/d of every level of the largest image, and per thread.
+constexpr int kHeatDD = 2 * (63 * 63 + 31 * 31 + 15 * 15 + 7 * 7 + 3 * 3 + 1);
+constexpr int kHeatDDPerThread = (kHeatDD + kCoarseBS - 1) / kCoarseBS;
+
+template <typename T>
+__global__ void __launch_bounds__(kCoarseBS) k_heat_sweep_p2(const Inst* __restrict__ steps, int nt, int dir,
+                                                             int guard) {
+  const Inst& I0 = steps[0];
+  if (!I0.active || !I0.coarse_p2 || I0.coarse_lev != 0 || mg_skip(I0, guard)) return;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ int LN[kMaxLev], LOFF[kMaxLev];
+  __shared__ T LIH2[kMaxLev];
+  T* lds = (T*)lds_raw;
+  const int L = I0.nlev;
+  const int tid = threadIdx.x;
+  const int N0 = I0.lv[0].N, n0 = N0 * N0;
+  if (tid == 0) {
+    int off = 0, N = N0;
+    for (int l = 0; l < L; ++l) {
+      LN[l] = N;
+      LOFF[l] = off;
+      const double h = 1.0 / (N + 1);
+      LIH2[l] = (T)(1.0 / (h * h));
+      off += coarse_p2_elems(N);
+      N = (N - 1) / 2;
+    }
+  }
+  __syncthreads();
+  // image offsets of this thread's share of the levels' d and 1/d (-1: none),
+  // so that each step issues all its loads at once
+  int ddo[kHeatDDPerThread];
+#pragma unroll
+  for (int j = 0; j < kHeatDDPerThread; ++j) {
+    int e = tid + j * kCoarseBS, o = -1;
+    for (int l = 0; l < L; ++l) {
+      const int N = LN[l], m = 2 * N * N;
+      if (e < m) {
+        o = LOFF[l] + 2 * (N + 2) * (N + 2) + N * N + e;
+        break;
+      }
+      e -= m;
+    }
+    ddo[j] = o;
+  }
+  T xreg[kCoarseP2PerThread];
+  for (int k = 0; k < nt; ++k) {
+    const int t = dir > 0 ? k : nt - 1 - k;
+    const Inst& I = steps[t];
+    const T* __restrict__ bg = (const T*)I.lv[0].b;
+    T breg[kCoarseP2PerThread];
+#pragma unroll
+    for (int j = 0; j < kCoarseP2PerThread; ++j) {
+      const int i = tid + j * kCoarseBS;
+      T v = i < n0 ? bg[i] : (T)0;
+      if (k > 0) v = (T)((double)v + (double)xreg[j] / I0.tau);
+      breg[j] = v;
+    }
+    const T* __restrict__ pk = (const T*)I.cpack;
+    if (k == 0) {
+      for (int e = tid; e < I.cpack_elems; e += kCoarseBS) lds[e] = pk[e];
+    } else {
+      T ddv[kHeatDDPerThread];
+#pragma unroll
+      for (int j = 0; j < kHeatDDPerThread; ++j) ddv[j] = ddo[j] >= 0 ? pk[ddo[j]] : (T)0;
+#pragma unroll
+      for (int j = 0; j < kHeatDDPerThread; ++j)
+        if (ddo[j] >= 0) lds[ddo[j]] = ddv[j];
+    }
+    __syncthreads();
+    {
+      T* b = lds + 2 * (N0 + 2) * (N0 + 2);
+#pragma unroll
+      for (int j = 0; j < kCoarseP2PerThread; ++j) {
+        const int i = tid + j * kCoarseBS;
+        if (i < n0) b[i] = breg[j];
+      }
+    }
+    __syncthreads();
+    // the cycle's scalars (levels, sweeps, omega) are the same for every step
+    const T* a = coarse_p2_cycle<T>(I0, lds, LN, LOFF, LIH2);
+    T* xg = (T*)I.lv[0].x;
+    {
+      const int P = N0 + 2;
+#pragma unroll
+      for (int j = 0; j < kCoarseP2PerThread; ++j) {
+        const int i = tid + j * kCoarseBS;
+        T v = 0;
+        if (i < n0) {
+          const int i2 = i / N0, i1 = i - i2 * N0;
+          v = a[(i1 + 1) + P * (i2 + 1)];
+          xg[i] = v;
+        }
+        xreg[j] = v;
+      }
+    }
+    __syncthreads();
+  }
+}
+template __global__ void k_heat_sweep_p2<float>(const Inst*, int, int, int);
+template __global__ void k_heat_sweep_p2<double>(const Inst*, int, int, int);
 
 // b_0 = (1 + Theta_y) x between the two solves of S_hat^-1 (3D path); x is
 // the first solve's level-0 output (x or x2 by outsel, x when the whole

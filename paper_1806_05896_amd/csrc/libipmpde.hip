@@ -237,7 +237,8 @@ static int set_coarse_lds_limit() {
   static hipError_t err = hipSuccess;
   std::call_once(once, [] {
     const void* fns[] = {(const void*)k_mg_coarse<float>, (const void*)k_mg_coarse<double>,
-                         (const void*)k_mg_coarse_p2<float>, (const void*)k_mg_coarse_p2<double>};
+                         (const void*)k_mg_coarse_p2<float>, (const void*)k_mg_coarse_p2<double>,
+                         (const void*)k_heat_sweep_p2<float>, (const void*)k_heat_sweep_p2<double>};
     for (const void* f : fns) {
       hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCoarseLds);
       if (e != hipSuccess) err = e;
@@ -840,6 +841,13 @@ static void heat_schur_inv(Group* G, int guard, hipStream_t s) {
   ipmpde_problem* P = G->probs[0];
   Group* V = &P->hview;
   V->zc = 1;
+  if (V->any_small && V->H[0].vcycles == 1) {
+    // whole hierarchy in one workgroup: each substitution is one launch
+    hipLaunchKernelGGL(k_heat_sweep_p2<T>, dim3(1), dim3(kCoarseBS), V->coarse_lds, s, P->hs_d, P->nt, 1, guard);
+    hipLaunchKernelGGL(k_mg_scale_ty<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, G->outsel, guard);
+    hipLaunchKernelGGL(k_heat_sweep_p2<T>, dim3(1), dim3(kCoarseBS), V->coarse_lds, s, P->hs_d, P->nt, -1, guard);
+    return;
+  }
   for (int t = 0; t < P->nt; ++t) {
     V->D = P->hs_d + t;
     if (t > 0) hipLaunchKernelGGL(k_heat_couple<T>, gz(V, V->max_n), dim3(kBS), 0, s, V->D, 1, G->outsel, guard);

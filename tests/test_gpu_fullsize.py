@@ -112,6 +112,8 @@ def test_ipm_step_parity_at_511():
     ("convdiff2d_255", {"krylov": "fgmres", "precond": "pt"}),
     ("convdiff2d_255", {}),
     ("poisson3d_127", {}),
+    ("heat2d", {"krylov": "fgmres", "precond": "pt"}),
+    ("heat2d", {}),
 ])
 def test_newton_direction_solves_oracle_system(name, opts_kw):
     """At the full sizes, from a mid-solve GPU state: the GPU Newton direction
@@ -164,3 +166,24 @@ def test_ipm_step_parity_convdiff_255():
     for f in ("y", "w", "v", "p", "lwa", "lwb", "lva", "lvb"):
         a, r = getattr(st1, f), getattr(ref, f)
         assert _rel(a, r) <= 1e-6, (f, _rel(a, r))
+
+
+@pytest.mark.parametrize("krylov,precond", [("fgmres", "pt"), ("minres", "pd")])
+def test_heat_full_size_kkt(krylov, precond):
+    """Heat equation at 63^2 x 100 time steps (tau = 0.01): the final iterate
+    meets the IPM tolerance on the oracle's own residuals (eqs. (prdu), (gap))
+    evaluated from the queried fields, and the reported measures agree."""
+    from paper_1806_05896_amd import Options, Problem
+    data = W.heat2d(seed=0)
+    print(f"[heat full] {krylov} {precond} n={data.n}", flush=True)
+    with Problem(data) as prob:
+        rc = prob.solve(Options(sigma=data.sigma, krylov=krylov, precond=precond, mg_precision="fp32"))
+        s = prob.stats()
+        st = _state_from_gpu(prob, False, s.mu)
+    xp, xd, xc = measures(data, discretize(data), st)
+    print(f"  rc={rc} nli={s.nli} its={s.krylov_its} measures {xp:.2e} {xd:.2e} {xc:.2e}", flush=True)
+    assert rc == 0 and s.krylov_fail == 0
+    assert max(xp, xd, xc) <= 1e-6
+    # the residual entries are differences of terms of size |A||y| ~ 3e4 (h = 1/64,
+    # 1/tau = 100), so evaluation order alone moves them by ~1e-12
+    np.testing.assert_allclose([xp, xd, xc], [s.xi_p, s.xi_d, s.xi_c], rtol=1e-6, atol=1e-10)

@@ -205,3 +205,26 @@ def test_heat_refusals():
         assert rc == L.OK
         with pytest.raises(Exception):
             prob.time_kernel(3, reps=1)
+
+
+@pytest.mark.parametrize("prec,vcycles", [("fp64", 1), ("fp32", 2)])
+def test_heat_direction_per_step_launches(prec, vcycles):
+    """63^2 x 7 steps with FP64 V-cycles (the finest level runs outside the
+    single-workgroup kernel) or k-cycle solves: the substitution takes one
+    multigrid launch sequence per time step.  The Newton direction must solve
+    the oracle's sparse system to the Krylov tolerance."""
+    _, Options, Problem = _api()
+    print(f"[heat per-step] {prec} vcycles={vcycles}", flush=True)
+    data = W.heat2d(seed=4, N=63, nt=7)
+    disc, st = _generic_state(data, steps=3)
+    mu = st.mu * data.sigma
+    K = newton_matrix(data, disc, st)
+    b = newton_rhs(data, disc, st, mu)
+    opts = Options(krylov="fgmres", precond="pt", mg_precision=prec, vcycles=vcycles)
+    with Problem(data) as prob:
+        _load_state(prob, st, False)
+        info = prob.newton_direction(mu, opts)
+        d = np.concatenate([prob.query(f) for f in ("dy", "dw", "dv", "dp")])
+    res = np.linalg.norm(b - K @ d) / np.linalg.norm(b)
+    print(f"  its={info['krylov_its']} relres(oracle K)={res:.2e}", flush=True)
+    assert info["rc"] == 0 and res <= 1e-9
