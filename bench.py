@@ -174,6 +174,34 @@ def bench_heat(W, torch, N, nt, reps):
     return out
 
 
+def bench_heat_batch(W, torch, N, nt, B, reps):
+    """B heat instances (seeds 0..B-1) solved as one batch: the substitution
+    kernel runs one workgroup per instance, every other launch serves all."""
+    from paper_1806_05896_amd import Batch, Options, Problem
+    datas = [W.heat2d(seed=k, N=N, nt=nt) for k in range(B)]
+    probs = [Problem(d) for d in datas]
+    stream = torch.cuda.current_stream()
+    out = {"instances": B, "workload": f"heat2d seeds 0..{B - 1}, {N}x{N} x {nt} steps"}
+    try:
+        batch = Batch(probs)
+        for name, kry, pre in (("fgmres_pt", "fgmres", "pt"), ("minres_pd", "minres", "pd")):
+            o = Options(sigma=datas[0].sigma, krylov=kry, precond=pre, mg_precision="fp32")
+            batch.solve(o, stream=stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                st = batch.solve(o, stream=stream)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / reps
+            log(f"heat batch {B} x {N}^2 x {nt} {name}: {B / t:.2f} solves/s")
+            out[name] = {"solves_per_s": B / t, "ms_per_batched_solve": t * 1e3, "status": st,
+                         "krylov_its": [p.stats().krylov_its for p in probs]}
+    finally:
+        for p in probs:
+            p.close()
+    return out
+
+
 def solver_options(d, Options, prec="fp32"):
     """Per-request solver choice: MINRES + P_D for Poisson, FGMRES(30) + P_T
     for convection-diffusion, multigrid in the given precision."""
@@ -307,6 +335,7 @@ def main():
     ap.add_argument("--partial-N", type=int, default=255, help="grid of the partial-observation run (0: skip)")
     ap.add_argument("--heat-N", type=int, default=63, help="grid of the heat-equation run (0: skip)")
     ap.add_argument("--heat-nt", type=int, default=100, help="time steps of the heat-equation run")
+    ap.add_argument("--heat-batch", type=int, default=16, help="instances of the batched heat run (0: skip)")
     ap.add_argument("--only", choices=["serve", "batch", "partial", "heat"], default=None,
                     help="run one extra section alone")
     ap.add_argument("--pmc-probe", action="store_true",
@@ -336,7 +365,10 @@ def main():
         print(json.dumps({"partial_observation": bench_partial(W, torch, args.partial_N, 3)}), flush=True)
         return
     if args.only == "heat":
-        print(json.dumps({"heat": bench_heat(W, torch, args.heat_N, args.heat_nt, 3)}), flush=True)
+        out = bench_heat(W, torch, args.heat_N, args.heat_nt, 3)
+        if args.heat_batch > 0:
+            out["batched"] = bench_heat_batch(W, torch, args.heat_N, args.heat_nt, args.heat_batch, 2)
+        print(json.dumps({"heat": out}), flush=True)
         return
     if args.only == "batch":
         print(json.dumps({"batched": bench_batched(W, torch, max(1, args.batch), 2)}), flush=True)
@@ -456,6 +488,8 @@ def main():
         result["partial_observation"] = bench_partial(W, torch, args.partial_N, 2)
     if args.heat_N > 0:
         result["heat"] = bench_heat(W, torch, args.heat_N, args.heat_nt, 2)
+        if args.heat_batch > 0:
+            result["heat"]["batched"] = bench_heat_batch(W, torch, args.heat_N, args.heat_nt, args.heat_batch, 1)
 
     if args.serve_requests > 0:
         result["serving"] = bench_serving(W, torch, args.serve_requests, args.serve_slots, args.serve_budget_gib,

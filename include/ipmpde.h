@@ -173,9 +173,11 @@ int ipmpde_problem_create(const ipmpde_grid* grid, const ipmpde_pde* pde, double
  * otherwise as ipmpde_problem_create.  The Schur block's solves with
  * L + M_hat (and the transpose) are block forward (backward) substitutions
  * over the time steps with one multigrid solve per step.  P_D and P_T only
- * (P_Pi: IPMPDE_EINVAL at solve); such a problem is solved alone
- * (ipmpde_solve and the single-problem entry points), not in a batch or an
- * engine (IPMPDE_EINVAL). */
+ * (P_Pi: IPMPDE_EINVAL at solve).  Heat problems may be batched with other
+ * heat problems only (ipmpde_batch_create: IPMPDE_EINVAL for a mix); a batch
+ * of more than one needs every time step's hierarchy in the single-workgroup
+ * kernel (N <= 63 with FP32, N <= 31 with FP64 V-cycles) and vcycles = 1,
+ * else IPMPDE_EINVAL at solve.  Not admitted to an engine (IPMPDE_EINVAL). */
 int ipmpde_heat_create(const ipmpde_grid* grid, int nt, double tau, double alpha, double beta,
                        const double* u_a, const double* u_b, const double* y_a, const double* y_b,
                        const double* y_d, const double* f, const double* g, const double* y0,

@@ -114,6 +114,7 @@ struct Inst {
   double omega;
   Level lv[kMaxLev];
   const Level* lvd;     // the same level table in device memory (for loops over levels)
+  const Inst* hsteps;   // heat equation: the nt per-time-step multigrid descriptors (device)
 };
 
 // ---------------------------------------------------------------------------

@@ -573,10 +573,13 @@ constexpr int kHeatDD = 2 * (63 * 63 + 31 * 31 + 15 * 15 + 7 * 7 + 3 * 3 + 1);
 constexpr int kHeatDDPerThread = (kHeatDD + kCoarseBS - 1) / kCoarseBS;
 
 template <typename T>
-__global__ void __launch_bounds__(kCoarseBS) k_heat_sweep_p2(const Inst* __restrict__ steps, int nt, int dir,
-                                                             int guard) {
+__global__ void __launch_bounds__(kCoarseBS) k_heat_sweep_p2(const Inst* __restrict__ Dp, int dir, int guard) {
+  INST_BEGIN
+  if (mg_skip(I, guard)) return;
+  const Inst* __restrict__ steps = I.hsteps;
+  const int nt = I.nt;
   const Inst& I0 = steps[0];
-  if (!I0.active || !I0.coarse_p2 || I0.coarse_lev != 0 || mg_skip(I0, guard)) return;
+  if (!I0.coarse_p2 || I0.coarse_lev != 0) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ int LN[kMaxLev], LOFF[kMaxLev];
   __shared__ T LIH2[kMaxLev];
@@ -615,8 +618,8 @@ __global__ void __launch_bounds__(kCoarseBS) k_heat_sweep_p2(const Inst* __restr
   T xreg[kCoarseP2PerThread];
   for (int k = 0; k < nt; ++k) {
     const int t = dir > 0 ? k : nt - 1 - k;
-    const Inst& I = steps[t];
-    const T* __restrict__ bg = (const T*)I.lv[0].b;
+    const Inst& St = steps[t];
+    const T* __restrict__ bg = (const T*)St.lv[0].b;
     T breg[kCoarseP2PerThread];
 #pragma unroll
     for (int j = 0; j < kCoarseP2PerThread; ++j) {
@@ -625,9 +628,9 @@ __global__ void __launch_bounds__(kCoarseBS) k_heat_sweep_p2(const Inst* __restr
       if (k > 0) v = (T)((double)v + (double)xreg[j] / I0.tau);
       breg[j] = v;
     }
-    const T* __restrict__ pk = (const T*)I.cpack;
+    const T* __restrict__ pk = (const T*)St.cpack;
     if (k == 0) {
-      for (int e = tid; e < I.cpack_elems; e += kCoarseBS) lds[e] = pk[e];
+      for (int e = tid; e < St.cpack_elems; e += kCoarseBS) lds[e] = pk[e];
     } else {
       T ddv[kHeatDDPerThread];
 #pragma unroll
@@ -648,7 +651,7 @@ __global__ void __launch_bounds__(kCoarseBS) k_heat_sweep_p2(const Inst* __restr
     __syncthreads();
     // the cycle's scalars (levels, sweeps, omega) are the same for every step
     const T* a = coarse_p2_cycle<T>(I0, lds, LN, LOFF, LIH2);
-    T* xg = (T*)I.lv[0].x;
+    T* xg = (T*)St.lv[0].x;
     {
       const int P = N0 + 2;
 #pragma unroll
@@ -666,8 +669,8 @@ __global__ void __launch_bounds__(kCoarseBS) k_heat_sweep_p2(const Inst* __restr
     __syncthreads();
   }
 }
-template __global__ void k_heat_sweep_p2<float>(const Inst*, int, int, int);
-template __global__ void k_heat_sweep_p2<double>(const Inst*, int, int, int);
+template __global__ void k_heat_sweep_p2<float>(const Inst*, int, int);
+template __global__ void k_heat_sweep_p2<double>(const Inst*, int, int);
 
 // b_0 = (1 + Theta_y) x between the two solves of S_hat^-1 (3D path); x is
 // the first solve's level-0 output (x or x2 by outsel, x when the whole

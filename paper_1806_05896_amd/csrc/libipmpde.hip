@@ -144,7 +144,7 @@ struct Group {
   int max_cpack = 0; // longest coarse LDS image (Poisson instances)
   bool any_small = false;  // 2D: some instance runs its whole hierarchy in the coarse kernel
   int outsel = 1;    // level-0 output buffer of a V-cycle (x2 = 1)
-  bool heat = false; // a heat-equation problem (always a group of one)
+  bool heat = false; // heat-equation problems (a group holds only heat problems or none)
   int sel_pre = 0;   // 3D path: buffer holding the pre-smoothed iterate
   bool fp32 = true;
 };
@@ -416,7 +416,7 @@ static int group_create(const std::vector<ipmpde_problem*>& probs, int cap, int 
   G->cap = cap;
   G->zc = G->count;
   G->dim = dim;
-  G->heat = probs.size() == 1 && probs[0]->pde == IPMPDE_HEAT;
+  G->heat = !probs.empty() && probs[0]->pde == IPMPDE_HEAT;
   auto bail = [&](int rc) { group_release(G); return rc; };
   int rc;
   if ((rc = G->mem.alloc_t(&G->D, cap))) return bail(rc);
@@ -580,7 +580,11 @@ static int group_select(Group* G, const ipmpde_options& o) {
     G->gen = G->gen || !is_p2(P);
     G->coarse_lds = std::max(G->coarse_lds, coarse_lds_bytes(lv, P->nlev, d.coarse_lev, fp32 ? 4 : 8, is_p2(P)));
   }
-  if (G->heat) heat_steps(G->probs[0], G->H[0], fp32);
+  if (G->heat)
+    for (int i = 0; i < G->count; ++i) {
+      heat_steps(G->probs[i], G->H[i], fp32);
+      G->H[i].hsteps = G->probs[i]->hs_d;
+    }
   if (G->dim == 2) {
     G->outsel = 1;
   } else {
@@ -597,10 +601,11 @@ static int group_select(Group* G, const ipmpde_options& o) {
 static int group_sync(Group* G, hipStream_t s) {
   for (int i = G->count; i < G->zc; ++i) G->H[i].active = 0;
   HIP_TRY(hipMemcpyAsync(G->D, G->H, sizeof(Inst) * G->zc, hipMemcpyHostToDevice, s));
-  if (G->heat) {
-    const ipmpde_problem* P = G->probs[0];
-    HIP_TRY(hipMemcpyAsync(P->hs_d, P->hs_h, sizeof(Inst) * P->nt, hipMemcpyHostToDevice, s));
-  }
+  if (G->heat)
+    for (int i = 0; i < G->count; ++i) {
+      const ipmpde_problem* P = G->probs[i];
+      HIP_TRY(hipMemcpyAsync(P->hs_d, P->hs_h, sizeof(Inst) * P->nt, hipMemcpyHostToDevice, s));
+    }
   return IPMPDE_OK;
 }
 
@@ -836,18 +841,31 @@ static void mg_solve(Group* G, int transpose, int guard, int scaled, hipStream_t
 // forward substitution, each diagonal block I/tau + A_h + M_hat_t by the
 // multigrid solve of its time step, and the transpose by block backward
 // substitution with the same per-step solves.
+// Heat groups whose every step hierarchy fits one workgroup, one V-cycle per
+// step: each substitution is one launch, one workgroup per instance.
+static bool heat_one_launch(const Group* G) {
+  for (int i = 0; i < G->count; ++i) {
+    const Group& V = G->probs[i]->hview;
+    if (!V.any_small || G->H[i].vcycles != 1) return false;
+  }
+  return true;
+}
+
 template <typename T>
 static void heat_schur_inv(Group* G, int guard, hipStream_t s) {
+  if (heat_one_launch(G)) {
+    size_t lds = 0;
+    for (int i = 0; i < G->count; ++i) lds = std::max(lds, G->probs[i]->hview.coarse_lds);
+    const dim3 grid(1, 1, G->zc);
+    hipLaunchKernelGGL(k_heat_sweep_p2<T>, grid, dim3(kCoarseBS), lds, s, G->D, 1, guard);
+    hipLaunchKernelGGL(k_mg_scale_ty<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, G->outsel, guard);
+    hipLaunchKernelGGL(k_heat_sweep_p2<T>, grid, dim3(kCoarseBS), lds, s, G->D, -1, guard);
+    return;
+  }
+  // per-step launches (a group of one: the checks at Newton setup)
   ipmpde_problem* P = G->probs[0];
   Group* V = &P->hview;
   V->zc = 1;
-  if (V->any_small && V->H[0].vcycles == 1) {
-    // whole hierarchy in one workgroup: each substitution is one launch
-    hipLaunchKernelGGL(k_heat_sweep_p2<T>, dim3(1), dim3(kCoarseBS), V->coarse_lds, s, P->hs_d, P->nt, 1, guard);
-    hipLaunchKernelGGL(k_mg_scale_ty<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, G->outsel, guard);
-    hipLaunchKernelGGL(k_heat_sweep_p2<T>, dim3(1), dim3(kCoarseBS), V->coarse_lds, s, P->hs_d, P->nt, -1, guard);
-    return;
-  }
   for (int t = 0; t < P->nt; ++t) {
     V->D = P->hs_d + t;
     if (t > 0) hipLaunchKernelGGL(k_heat_couple<T>, gz(V, V->max_n), dim3(kBS), 0, s, V->D, 1, G->outsel, guard);
@@ -1078,15 +1096,17 @@ static void ppi_setup(Group* G, hipStream_t s) {
 // image, all steps in one launch per level.
 template <typename T>
 static void heat_setup(Group* G, hipStream_t s) {
-  ipmpde_problem* P = G->probs[0];
-  Group* V = &P->hview;
-  V->D = P->hs_d;
-  V->zc = P->nt;
   hipLaunchKernelGGL(k_newton_setup<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D);
-  for (int l = 0; l + 1 < V->max_nlev; ++l)
-    hipLaunchKernelGGL(k_restrict_diag<T>, gz(V, V->maxn[l + 1]), dim3(kBS), 0, s, V->D, l);
-  hipLaunchKernelGGL(k_coarse_pack<T>, gz(V, V->max_cpack), dim3(kBS), 0, s, V->D);
-  V->zc = 1;
+  for (int i = 0; i < G->count; ++i) {
+    ipmpde_problem* P = G->probs[i];
+    Group* V = &P->hview;
+    V->D = P->hs_d;
+    V->zc = P->nt;
+    for (int l = 0; l + 1 < V->max_nlev; ++l)
+      hipLaunchKernelGGL(k_restrict_diag<T>, gz(V, V->maxn[l + 1]), dim3(kBS), 0, s, V->D, l);
+    hipLaunchKernelGGL(k_coarse_pack<T>, gz(V, V->max_cpack), dim3(kBS), 0, s, V->D);
+    V->zc = 1;
+  }
 }
 
 static int newton_setup_group(Group* G, const ipmpde_options& o, hipStream_t s) {
@@ -1098,6 +1118,9 @@ static int newton_setup_group(Group* G, const ipmpde_options& o, hipStream_t s) 
       return fail(IPMPDE_EINVAL, "unobserved nodes without state bounds make the (1,1) block singular: use P_Pi");
   }
   TRY(group_select(G, o));
+  if (G->heat && G->count > 1 && !heat_one_launch(G))
+    return fail(IPMPDE_EINVAL, "a batch of heat-equation problems needs every time step's hierarchy in one "
+                               "workgroup (N <= 63 with FP32 or N <= 31 with FP64 V-cycles) and vcycles = 1");
   TRY(group_sync(G, s));
   if (G->heat) {
     if (G->fp32) heat_setup<float>(G, s);
@@ -1773,7 +1796,8 @@ extern "C" int ipmpde_batch_create(ipmpde_problem* const* probs, int count, ipmp
   for (int i = 0; i < count; ++i) {
     if (!v[i]) return fail(IPMPDE_EINVAL, "NULL problem in batch");
     if (v[i]->dim != v[0]->dim) return fail(IPMPDE_EINVAL, "all problems of a batch must have the same dimension");
-    if (v[i]->pde == IPMPDE_HEAT) return fail(IPMPDE_EINVAL, "heat-equation problems are solved one at a time");
+    if ((v[i]->pde == IPMPDE_HEAT) != (v[0]->pde == IPMPDE_HEAT))
+      return fail(IPMPDE_EINVAL, "a batch holds only heat-equation problems or none");
     for (int j = 0; j < i; ++j)
       if (v[j] == v[i]) return fail(IPMPDE_EINVAL, "a problem appears twice in the batch");
   }

@@ -192,19 +192,50 @@ def test_heat_ipm_parity(case, krylov, precond, prec):
 
 
 def test_heat_refusals():
-    """P_Pi, batches and the per-level timers are refused for the heat equation."""
+    """P_Pi, batches mixing heat and steady problems, heat batches outside the
+    one-launch substitution, and the per-level timers are refused."""
     Batch, Options, Problem = _api()
     from paper_1806_05896_amd import _lib as L
     data = CASES["heat_7x10"]()
-    with Problem(data) as prob:
+    with Problem(data) as prob, Problem(W.poisson2d_small(N=15)) as steady, \
+            Problem(W.heat2d(seed=5, N=63, nt=3)) as big:
         with pytest.raises(Exception):
             prob.solve(Options(krylov="fgmres", precond="ppi"), raise_on_error=True)
         with pytest.raises(Exception):
-            Batch([prob])
+            Batch([prob, steady])
+        with pytest.raises(Exception):  # FP64 V-cycles at 63^2 need per-step launches
+            Batch([prob, big]).solve(Options(sigma=data.sigma, mg_precision="fp64"))
         rc = prob.solve(Options(sigma=data.sigma))
         assert rc == L.OK
         with pytest.raises(Exception):
             prob.time_kernel(3, reps=1)
+
+
+@pytest.mark.parametrize("krylov,precond", [("fgmres", "pt"), ("minres", "pd")])
+def test_heat_batch_equals_solo(krylov, precond):
+    """Heat problems of different sizes and step counts solved as one batch
+    (one workgroup per instance in the substitution kernel) give bit-identical
+    iterates and the same iteration counts as solo solves."""
+    Batch, Options, Problem = _api()
+    datas = [W.heat2d(seed=1, N=15, nt=25), W.heat2d(seed=2, N=31, nt=10), W.heat2d(seed=0, N=7, nt=12)]
+    opts = Options(sigma=0.25, krylov=krylov, precond=precond, mg_precision="fp32")
+    solo = []
+    for d in datas:
+        with Problem(d) as p:
+            assert p.solve(opts) == 0
+            solo.append((p.query("u"), p.query("y"), p.stats()))
+    probs = [Problem(d) for d in datas]
+    try:
+        b = Batch(probs)
+        b.solve(opts)
+        for p, (u, y, st) in zip(probs, solo):
+            s = p.stats()
+            assert s.status == 0 and s.nli == st.nli and s.krylov_its == st.krylov_its
+            np.testing.assert_array_equal(p.query("u"), u)
+            np.testing.assert_array_equal(p.query("y"), y)
+    finally:
+        for p in probs:
+            p.close()
 
 
 @pytest.mark.parametrize("prec,vcycles", [("fp64", 1), ("fp32", 2)])
