@@ -397,7 +397,7 @@ template __global__ void k_coarse_pack<double>(const Inst*);
 // Descent at level l: nu_pre damped-Jacobi sweeps from zero, the residual and
 // its full-weighting restriction to level l + 1's right-hand side.
 template <typename T, int NT>
-__device__ __forceinline__ void p2_down(const Inst& I, T* lds, const int* LN, const int* LOFF, const T* LIH2, int l,
+__device__ __forceinline__ void p2_down(int nu_pre, T* lds, const int* LN, const int* LOFF, const T* LIH2, int l,
                                         int tid, T om, unsigned& alt) {
   const int N = LN[l], P = N + 2, n = N * N;
   const T ih2 = LIH2[l];
@@ -406,7 +406,7 @@ __device__ __forceinline__ void p2_down(const Inst& I, T* lds, const int* LN, co
   const T* b = c + P * P;
   const T* d = b + n;
   const T* dinv = d + n;
-  for (int s = 0; s < I.nu_pre; ++s) {
+  for (int s = 0; s < nu_pre; ++s) {
     if (s == 0) {
       P2_FOR_T(N, tid, NT) c[p] = om * b[i] * dinv[i]; P2_END
     } else {
@@ -436,7 +436,7 @@ __device__ __forceinline__ void p2_down(const Inst& I, T* lds, const int* LN, co
 // Ascent at level l: bilinear prolongation of level l + 1's iterate (in xb
 // when bit l + 1 of alt is set) added to the iterate, nu_post sweeps.
 template <typename T, int NT>
-__device__ __forceinline__ void p2_up(const Inst& I, T* lds, const int* LN, const int* LOFF, const T* LIH2, int l,
+__device__ __forceinline__ void p2_up(int nu_post, T* lds, const int* LN, const int* LOFF, const T* LIH2, int l,
                                       int tid, T om, unsigned& alt) {
   const int N = LN[l], P = N + 2, n = N * N;
   const int Nc = LN[l + 1], Pc = Nc + 2;
@@ -458,7 +458,7 @@ __device__ __forceinline__ void p2_up(const Inst& I, T* lds, const int* LN, cons
     a[F1 + P * F2] += v;
   P2_END
   __syncthreads();
-  for (int s = 0; s < I.nu_post; ++s) {
+  for (int s = 0; s < nu_post; ++s) {
     P2_FOR_T(N, tid, NT) c[p] = a[p] + om * (b[i] - d[i] * a[p] + ih2 * (a[p - 1] + a[p + 1] + a[p - P] + a[p + P])) * dinv[i]; P2_END
     __syncthreads();
     T* t = a; a = c; c = t;
@@ -472,13 +472,11 @@ __device__ __forceinline__ void p2_up(const Inst& I, T* lds, const int* LN, cons
 // prolongation and post-smoothing back up.  Returns the top level's final
 // iterate (padded layout) in LDS.
 template <typename T>
-__device__ __forceinline__ const T* coarse_p2_cycle(const Inst& I, T* lds, const int* LN, const int* LOFF,
-                                                    const T* LIH2) {
-  const int cl = I.coarse_lev, L = I.nlev;
+__device__ __forceinline__ const T* coarse_p2_cycle(T* lds, const int* LN, const int* LOFF, const T* LIH2, int cl,
+                                                    int L, T om, int nu_pre, int nu_post) {
   const int tid = threadIdx.x;
-  const T om = (T)I.omega;
   unsigned alt = 0;  // bit l: level l's iterate sits in xb
-  for (int l = cl; l < L - 1; ++l) p2_down<T, kCoarseBS>(I, lds, LN, LOFF, LIH2, l, tid, om, alt);
+  for (int l = cl; l < L - 1; ++l) p2_down<T, kCoarseBS>(nu_pre, lds, LN, LOFF, LIH2, l, tid, om, alt);
   {
     // coarsest grid (one node): exact solve
     const int l = L - 1, N = LN[l], P = N + 2, n = N * N;
@@ -488,7 +486,7 @@ __device__ __forceinline__ const T* coarse_p2_cycle(const Inst& I, T* lds, const
     P2_FOR_T(N, tid, kCoarseBS) a[p] = b[i] * dinv[i]; P2_END
     __syncthreads();
   }
-  for (int l = L - 2; l >= cl; --l) p2_up<T, kCoarseBS>(I, lds, LN, LOFF, LIH2, l, tid, om, alt);
+  for (int l = L - 2; l >= cl; --l) p2_up<T, kCoarseBS>(nu_post, lds, LN, LOFF, LIH2, l, tid, om, alt);
   const int N = LN[cl], P = N + 2;
   return lds + LOFF[cl] + ((alt >> cl) & 1u) * P * P;
 }
@@ -548,7 +546,7 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_p2(const Inst* __restri
     }
   }
   __syncthreads();
-  const T* a = coarse_p2_cycle<T>(I, lds, LN, LOFF, LIH2);
+  const T* a = coarse_p2_cycle<T>(lds, LN, LOFF, LIH2, cl, L, (T)I.omega, I.nu_pre, I.nu_post);
   {
     const int N = LN[cl];
     T* xg = (T*)I.lv[cl].x;
@@ -576,15 +574,21 @@ template <typename T>
 __global__ void __launch_bounds__(kCoarseBS) k_heat_sweep_p2(const Inst* __restrict__ Dp, int dir, int guard) {
   INST_BEGIN
   if (mg_skip(I, guard)) return;
-  const Inst* __restrict__ steps = I.hsteps;
+  // the step descriptors are read-only during the kernel: reading them
+  // through the constant address space keeps their loads scalar (the
+  // kernel's global stores would otherwise force vector reloads)
+  typedef const __attribute__((address_space(4))) Inst CInst;
+  CInst* steps = (CInst*)I.hsteps;
   const int nt = I.nt;
-  const Inst& I0 = steps[0];
+  CInst& I0 = steps[0];
   if (!I0.coarse_p2 || I0.coarse_lev != 0) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ int LN[kMaxLev], LOFF[kMaxLev];
   __shared__ T LIH2[kMaxLev];
   T* lds = (T*)lds_raw;
-  const int L = I0.nlev;
+  const int L = I0.nlev, nu_pre = I0.nu_pre, nu_post = I0.nu_post;
+  const T om = (T)I0.omega;
+  const double tau = I0.tau;
   const int tid = threadIdx.x;
   const int N0 = I0.lv[0].N, n0 = N0 * N0;
   if (tid == 0) {
@@ -615,29 +619,38 @@ __global__ void __launch_bounds__(kCoarseBS) k_heat_sweep_p2(const Inst* __restr
     }
     ddo[j] = o;
   }
-  T xreg[kCoarseP2PerThread];
-  for (int k = 0; k < nt; ++k) {
-    const int t = dir > 0 ? k : nt - 1 - k;
-    const Inst& St = steps[t];
-    const T* __restrict__ bg = (const T*)St.lv[0].b;
-    T breg[kCoarseP2PerThread];
+  // the next step's right-hand side and d, 1/d are loaded while the current
+  // step's V-cycle runs (the barriers wait for LDS operations only)
+  T xreg[kCoarseP2PerThread], bnext[kCoarseP2PerThread], ddnext[kHeatDDPerThread];
+  auto prefetch = [&](CInst& Sn) {
+    const T* __restrict__ bg = (const T*)Sn.lv[0].b;
+    const T* __restrict__ pk = (const T*)Sn.cpack;
 #pragma unroll
     for (int j = 0; j < kCoarseP2PerThread; ++j) {
       const int i = tid + j * kCoarseBS;
-      T v = i < n0 ? bg[i] : (T)0;
-      if (k > 0) v = (T)((double)v + (double)xreg[j] / I0.tau);
+      bnext[j] = i < n0 ? bg[i] : (T)0;
+    }
+#pragma unroll
+    for (int j = 0; j < kHeatDDPerThread; ++j) ddnext[j] = ddo[j] >= 0 ? pk[ddo[j]] : (T)0;
+  };
+  prefetch(steps[dir > 0 ? 0 : nt - 1]);
+  for (int k = 0; k < nt; ++k) {
+    const int t = dir > 0 ? k : nt - 1 - k;
+    CInst& St = steps[t];
+    T breg[kCoarseP2PerThread];
+#pragma unroll
+    for (int j = 0; j < kCoarseP2PerThread; ++j) {
+      T v = bnext[j];
+      if (k > 0) v = (T)((double)v + (double)xreg[j] / tau);
       breg[j] = v;
     }
-    const T* __restrict__ pk = (const T*)St.cpack;
     if (k == 0) {
+      const T* __restrict__ pk = (const T*)St.cpack;
       for (int e = tid; e < St.cpack_elems; e += kCoarseBS) lds[e] = pk[e];
     } else {
-      T ddv[kHeatDDPerThread];
-#pragma unroll
-      for (int j = 0; j < kHeatDDPerThread; ++j) ddv[j] = ddo[j] >= 0 ? pk[ddo[j]] : (T)0;
 #pragma unroll
       for (int j = 0; j < kHeatDDPerThread; ++j)
-        if (ddo[j] >= 0) lds[ddo[j]] = ddv[j];
+        if (ddo[j] >= 0) lds[ddo[j]] = ddnext[j];
     }
     __syncthreads();
     {
@@ -649,8 +662,8 @@ __global__ void __launch_bounds__(kCoarseBS) k_heat_sweep_p2(const Inst* __restr
       }
     }
     __syncthreads();
-    // the cycle's scalars (levels, sweeps, omega) are the same for every step
-    const T* a = coarse_p2_cycle<T>(I0, lds, LN, LOFF, LIH2);
+    if (k + 1 < nt) prefetch(steps[dir > 0 ? t + 1 : t - 1]);
+    const T* a = coarse_p2_cycle<T>(lds, LN, LOFF, LIH2, 0, L, om, nu_pre, nu_post);
     T* xg = (T*)St.lv[0].x;
     {
       const int P = N0 + 2;
