@@ -46,8 +46,17 @@ def _with_data(N, nt, seed=2):
     return d
 
 
+def _state_bounded(N, nt):
+    """State bounds y in [-0.1, 0.5]: the upper bound is active on about 10% of the nodes."""
+    d = W.heat2d(seed=6, N=N, nt=nt)
+    d.y_a = np.full(d.n, -0.1)
+    d.y_b = np.full(d.n, 0.5)
+    return d
+
+
 CASES = {
     "heat_7x10": lambda: W.heat2d(seed=0, N=7, nt=10),
+    "heat_sb_7x8": lambda: _state_bounded(7, 8),
     "heat_15x25": lambda: W.heat2d(seed=1, N=15, nt=25),
     "heat_data_7x6": lambda: _with_data(7, 6),
     "heat_31x1": lambda: W.heat2d(seed=3, N=31, nt=1),
@@ -75,7 +84,7 @@ def test_heat_operator_parity(N, nt):
             assert _rel(y, ref) <= 1e-13, (tr, _rel(y, ref))
 
 
-@pytest.mark.parametrize("case", ["heat_7x10", "heat_data_7x6", "heat_31x1"])
+@pytest.mark.parametrize("case", ["heat_7x10", "heat_data_7x6", "heat_31x1", "heat_sb_7x8"])
 def test_heat_rhs_and_saddle_matvec(case):
     """Newton right-hand side (with y0, g and f folded into f_hat) and the saddle matvec."""
     _, Options, Problem = _api()
@@ -175,7 +184,9 @@ def test_heat_newton_direction_parity(case, krylov, precond, prec):
                                                       ("heat_data_7x6", "fgmres", "pt", "fp32"),
                                                       ("heat_15x25", "fgmres", "pt", "fp32"),
                                                       ("heat_15x25", "minres", "pd", "fp64"),
-                                                      ("heat_31x1", "minres", "pd", "fp32")])
+                                                      ("heat_31x1", "minres", "pd", "fp32"),
+                                                      ("heat_sb_7x8", "minres", "pd", "fp32"),
+                                                      ("heat_sb_7x8", "fgmres", "pt", "fp64")])
 def test_heat_ipm_parity(case, krylov, precond, prec):
     _, Options, Problem = _api()
     print(f"[heat ipm] {case} {krylov} {precond} {prec}", flush=True)

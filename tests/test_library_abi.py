@@ -139,3 +139,30 @@ def test_footprint_counts_fgmres_basis_and_precision(lib):
     f64 = lib.ipmpde_footprint_bytes(C.byref(g), C.byref(pd), 0, C.byref(o))
     assert f64 > base
     assert lib.ipmpde_footprint_bytes(C.byref(L.Grid(2, 100)), C.byref(pd), 0, None) == 0
+
+
+@pytest.mark.parametrize("dim,N,nt,tau,msg", [
+    (3, 7, 4, 0.25, "2D grid"),
+    (2, 8, 4, 0.25, "2^k - 1"),
+    (2, 7, 0, 0.25, "nt must be"),
+    (2, 7, 70000, 0.25, "nt must be"),
+    (2, 7, 4, 0.0, "tau must be positive"),
+    (2, 7, 4, float("nan"), "tau must be positive"),
+    (2, 2047, 65535, 0.01, "too many space-time nodes"),
+])
+def test_heat_create_rejects_bad_shapes_on_the_host(lib, dim, N, nt, tau, msg):
+    """ipmpde_heat_create validates the grid and the time axis before it
+    touches the device."""
+    h = C.c_void_p()
+    rc = lib.ipmpde_heat_create(C.byref(L.Grid(dim, N)), nt, tau, 1e-2, 1e-3, None, None, None, None, None, None,
+                                None, None, C.byref(h))
+    assert rc == L.EINVAL
+    assert msg in lib.ipmpde_last_error().decode()
+    assert not h.value
+
+
+def test_problem_create_refuses_the_heat_kind(lib):
+    h = C.c_void_p()
+    rc = lib.ipmpde_problem_create(C.byref(L.Grid(2, 7)), C.byref(L.Pde(L.HEAT, 1.0)), 1e-2, 1e-3, None, None,
+                                   None, None, None, None, None, C.byref(h))
+    assert rc == L.EINVAL and "ipmpde_heat_create" in lib.ipmpde_last_error().decode()
