@@ -321,7 +321,7 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse(const Inst* __restrict_
 // once, so sweeps need no division:
 //   x <- x + omega (b - d x + h^-2 (sum of neighbours)) / d.
 // LDS per level: 2 (N+2)^2 + 3 N^2 elements (x, x2 padded; b, d, 1/d).
-__host__ __device__ inline int coarse_p2_elems(int N) { return 2 * (N + 2) * (N + 2) + 3 * N * N; }
+__host__ __device__ constexpr int coarse_p2_elems(int N) { return 2 * (N + 2) * (N + 2) + 3 * N * N; }
 
 // Loop over the nodes (i1, i2) of an N x N level (N + 1 a power of two) with
 // a power-of-two thread layout: no division.  Defines i (compact index) and
@@ -341,6 +341,11 @@ __host__ __device__ inline int coarse_p2_elems(int N) { return 2 * (N + 2) * (N 
 // Largest coarse grid of the Poisson kernel (2D) and its nodes per thread.
 constexpr int kCoarseP2MaxN = 63;
 constexpr int kCoarseP2PerThread = (kCoarseP2MaxN * kCoarseP2MaxN + kCoarseBS - 1) / kCoarseBS;
+// Nodes per thread of the widest coarse-kernel level in precision T: in FP64
+// a 63 x 63 level's image (163 KB) exceeds the LDS budget, so the widest is
+// 31 x 31 (961 nodes, one per thread).
+template <typename T>
+__host__ __device__ constexpr int p2_per_thread() { return sizeof(T) == 8 ? 1 : kCoarseP2PerThread; }
 
 // Level l (0 = the first coarse-kernel level) of the LDS image of the
 // Poisson coarse kernel holding element k of the image, or -1 past its end;
@@ -504,9 +509,9 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_p2(const Inst* __restri
   const int N0 = I.lv[cl].N, n0 = N0 * N0;
   // the top level's right-hand side, in flight while the image is copied
   const T* __restrict__ bg = (const T*)I.lv[cl].b;
-  T breg[kCoarseP2PerThread];
+  T breg[p2_per_thread<T>()];
 #pragma unroll
-  for (int j = 0; j < kCoarseP2PerThread; ++j) {
+  for (int j = 0; j < p2_per_thread<T>(); ++j) {
     const int i = tid + j * kCoarseBS;
     breg[j] = i < n0 ? bg[i] : (T)0;
   }
@@ -540,7 +545,7 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_p2(const Inst* __restri
   {
     T* b = lds + LOFF[cl] + 2 * (N0 + 2) * (N0 + 2);
 #pragma unroll
-    for (int j = 0; j < kCoarseP2PerThread; ++j) {
+    for (int j = 0; j < p2_per_thread<T>(); ++j) {
       const int i = tid + j * kCoarseBS;
       if (i < n0) b[i] = breg[j];
     }
@@ -568,7 +573,9 @@ template __global__ void k_mg_coarse_p2<double>(const Inst*, int);
 // rings, so later steps copy only d and 1/d of each level.
 // d and 1/d of every level of the largest image, and per thread.
 constexpr int kHeatDD = 2 * (63 * 63 + 31 * 31 + 15 * 15 + 7 * 7 + 3 * 3 + 1);
-constexpr int kHeatDDPerThread = (kHeatDD + kCoarseBS - 1) / kCoarseBS;
+constexpr int kHeatDD64 = 2 * (31 * 31 + 15 * 15 + 7 * 7 + 3 * 3 + 1);  // FP64: widest 31 (p2_per_thread)
+template <typename T>
+constexpr int heat_dd_per_thread() { return ((sizeof(T) == 8 ? kHeatDD64 : kHeatDD) + kCoarseBS - 1) / kCoarseBS; }
 
 template <typename T>
 __global__ void __launch_bounds__(kCoarseBS) k_heat_sweep_p2(const Inst* __restrict__ Dp, int dir, int guard) {
@@ -605,9 +612,9 @@ __global__ void __launch_bounds__(kCoarseBS) k_heat_sweep_p2(const Inst* __restr
   __syncthreads();
   // image offsets of this thread's share of the levels' d and 1/d (-1: none),
   // so that each step issues all its loads at once
-  int ddo[kHeatDDPerThread];
+  int ddo[heat_dd_per_thread<T>()];
 #pragma unroll
-  for (int j = 0; j < kHeatDDPerThread; ++j) {
+  for (int j = 0; j < heat_dd_per_thread<T>(); ++j) {
     int e = tid + j * kCoarseBS, o = -1;
     for (int l = 0; l < L; ++l) {
       const int N = LN[l], m = 2 * N * N;
@@ -621,25 +628,25 @@ __global__ void __launch_bounds__(kCoarseBS) k_heat_sweep_p2(const Inst* __restr
   }
   // the next step's right-hand side and d, 1/d are loaded while the current
   // step's V-cycle runs (the barriers wait for LDS operations only)
-  T xreg[kCoarseP2PerThread], bnext[kCoarseP2PerThread], ddnext[kHeatDDPerThread];
+  T xreg[p2_per_thread<T>()], bnext[p2_per_thread<T>()], ddnext[heat_dd_per_thread<T>()];
   auto prefetch = [&](CInst& Sn) {
     const T* __restrict__ bg = (const T*)Sn.lv[0].b;
     const T* __restrict__ pk = (const T*)Sn.cpack;
 #pragma unroll
-    for (int j = 0; j < kCoarseP2PerThread; ++j) {
+    for (int j = 0; j < p2_per_thread<T>(); ++j) {
       const int i = tid + j * kCoarseBS;
       bnext[j] = i < n0 ? bg[i] : (T)0;
     }
 #pragma unroll
-    for (int j = 0; j < kHeatDDPerThread; ++j) ddnext[j] = ddo[j] >= 0 ? pk[ddo[j]] : (T)0;
+    for (int j = 0; j < heat_dd_per_thread<T>(); ++j) ddnext[j] = ddo[j] >= 0 ? pk[ddo[j]] : (T)0;
   };
   prefetch(steps[dir > 0 ? 0 : nt - 1]);
   for (int k = 0; k < nt; ++k) {
     const int t = dir > 0 ? k : nt - 1 - k;
     CInst& St = steps[t];
-    T breg[kCoarseP2PerThread];
+    T breg[p2_per_thread<T>()];
 #pragma unroll
-    for (int j = 0; j < kCoarseP2PerThread; ++j) {
+    for (int j = 0; j < p2_per_thread<T>(); ++j) {
       T v = bnext[j];
       if (k > 0) v = (T)((double)v + (double)xreg[j] / tau);
       breg[j] = v;
@@ -649,14 +656,14 @@ __global__ void __launch_bounds__(kCoarseBS) k_heat_sweep_p2(const Inst* __restr
       for (int e = tid; e < St.cpack_elems; e += kCoarseBS) lds[e] = pk[e];
     } else {
 #pragma unroll
-      for (int j = 0; j < kHeatDDPerThread; ++j)
+      for (int j = 0; j < heat_dd_per_thread<T>(); ++j)
         if (ddo[j] >= 0) lds[ddo[j]] = ddnext[j];
     }
     __syncthreads();
     {
       T* b = lds + 2 * (N0 + 2) * (N0 + 2);
 #pragma unroll
-      for (int j = 0; j < kCoarseP2PerThread; ++j) {
+      for (int j = 0; j < p2_per_thread<T>(); ++j) {
         const int i = tid + j * kCoarseBS;
         if (i < n0) b[i] = breg[j];
       }
@@ -668,7 +675,7 @@ __global__ void __launch_bounds__(kCoarseBS) k_heat_sweep_p2(const Inst* __restr
     {
       const int P = N0 + 2;
 #pragma unroll
-      for (int j = 0; j < kCoarseP2PerThread; ++j) {
+      for (int j = 0; j < p2_per_thread<T>(); ++j) {
         const int i = tid + j * kCoarseBS;
         T v = 0;
         if (i < n0) {

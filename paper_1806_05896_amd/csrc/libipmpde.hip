@@ -207,6 +207,8 @@ static int nblk(long n) { return (div_up(n, kBS) + 7) & ~7; }
 // LDS per CU), and the largest grid it takes; finer levels run as
 // grid-wide kernels.
 static constexpr size_t kCoarseLds = 150 * 1024;
+// the FP64 kernels size their per-thread arrays for coarse levels of at most 31 x 31
+static_assert((size_t)coarse_p2_elems(63) * 8 > kCoarseLds, "an FP64 63 x 63 level must not fit the coarse kernel");
 
 // p2: the Poisson 2D coarse kernel (padded layout), else the generic one.
 static size_t coarse_level_elems(const Level& L, bool p2) {
