@@ -96,6 +96,11 @@ class Discretization:
     N: int
     A: sp.csr_matrix       # interior operator A_II (n x n)
     f_hat: np.ndarray      # f - A_IB g_B
+    # finite elements (fem.py): tracking mass, control mass (regularization
+    # and the coupling L y - M u), L1 quadrature weights; None: unit mass
+    Mt: object = None
+    Mc: object = None
+    dl: object = None
 
     @property
     def n(self):
@@ -147,6 +152,9 @@ def discretize(prob) -> Discretization:
     """Operator and folded right-hand side for a workloads.ProblemData."""
     if prob.pde == "heat":
         return discretize_heat(prob)
+    if prob.pde == "poisson_q1":
+        from .fem import discretize_q1
+        return discretize_q1(prob)
     full, rows_full = _full_operator(prob.dim, prob.N, prob.pde, prob.eps)
     A = full[:, rows_full].tocsr()
     f = np.zeros(rows_full.size) if prob.f is None else np.asarray(prob.f, dtype=np.float64)

@@ -147,17 +147,31 @@ def initial_state(prob, opts: IPMOptions) -> IPMState:
     return st
 
 
+def _fem(disc) -> bool:
+    """Finite-element masses present (fem.py): M in the tracking term, the
+    regularization and the coupling, D in the L1 term (eq. (pb_fe_lin))."""
+    return disc.Mc is not None
+
+
 def residuals(prob, disc: Discretization, st: IPMState):
     """xi_p, xi_d (eq. (prdu)) and the complementarity products (eq. (gap), mu = 0)."""
     bd = _Bounds(prob)
     A, a, b = disc.A, prob.alpha, prob.beta
     u = st.w - st.v
-    xi_p = A @ st.y - u - disc.f_hat
-    dy = _obs(prob) * (st.y - prob.y_d) + A.T @ st.p
+    if _fem(disc):
+        Mc, Mu, Mp = disc.Mc, disc.Mc @ u, disc.Mc @ st.p
+        xi_p = A @ st.y - Mu - disc.f_hat
+        dy = disc.Mt @ (st.y - prob.y_d) + A.T @ st.p
+        bd_ = b * disc.dl
+        dw = a * Mu + bd_ - Mp - st.lwa + st.lwb
+        dv = -a * Mu + bd_ + Mp - st.lva + st.lvb
+    else:
+        xi_p = A @ st.y - u - disc.f_hat
+        dy = _obs(prob) * (st.y - prob.y_d) + A.T @ st.p
+        dw = a * u + b - st.p - st.lwa + st.lwb
+        dv = -a * u + b + st.p - st.lva + st.lvb
     if bd.has_y:
         dy = dy - st.lya + st.lyb
-    dw = a * u + b - st.p - st.lwa + st.lwb
-    dv = -a * u + b + st.p - st.lva + st.lvb
     prods = [(st.w - bd.zaw) * st.lwa, (bd.zbw - st.w) * st.lwb,
              (st.v - bd.zav) * st.lva, (bd.zbv - st.v) * st.lvb]
     if bd.has_y:
@@ -206,6 +220,14 @@ def newton_matrix(prob, disc: Discretization, st: IPMState) -> sp.csc_matrix:
     I = sp.identity(n, format="csr")
     Z = None
     A = disc.A
+    if _fem(disc):
+        M, Mt = disc.Mc, disc.Mt
+        return sp.bmat([
+            [Mt + sp.diags(ty), Z, Z, A.T],
+            [Z, a * M + sp.diags(tw), -a * M, -M],
+            [Z, -a * M, a * M + sp.diags(tv), M],
+            [A, -M, M, Z],
+        ], format="csc")
     K = sp.bmat([
         [sp.diags(_obs(prob) + ty), Z, Z, A.T],
         [Z, sp.diags(a + tw), -a * I, -I],
@@ -220,12 +242,21 @@ def newton_rhs(prob, disc: Discretization, st: IPMState, mu: float) -> np.ndarra
     bd = _Bounds(prob)
     A, a, b = disc.A, prob.alpha, prob.beta
     u = st.w - st.v
-    ry = _obs(prob) * (st.y - prob.y_d) + A.T @ st.p
+    if _fem(disc):
+        Mu, Mp, bd_ = disc.Mc @ u, disc.Mc @ st.p, b * disc.dl
+        ry = disc.Mt @ (st.y - prob.y_d) + A.T @ st.p
+        rw = a * Mu + bd_ - Mp
+        rv = -a * Mu + bd_ + Mp
+        rp = A @ st.y - Mu - disc.f_hat
+    else:
+        ry = _obs(prob) * (st.y - prob.y_d) + A.T @ st.p
+        rw = a * u + b - st.p
+        rv = -a * u + b + st.p
+        rp = A @ st.y - u - disc.f_hat
     if bd.has_y:
         ry = ry - mu / (st.y - bd.ya) + mu / (bd.yb - st.y)
-    rw = a * u + b - st.p - mu / (st.w - bd.zaw) + mu / (bd.zbw - st.w)
-    rv = -a * u + b + st.p - mu / (st.v - bd.zav) + mu / (bd.zbv - st.v)
-    rp = A @ st.y - u - disc.f_hat
+    rw = rw - mu / (st.w - bd.zaw) + mu / (bd.zbw - st.w)
+    rv = rv - mu / (st.v - bd.zav) + mu / (bd.zbv - st.v)
     return -np.concatenate([ry, rw, rv, rp])
 
 
@@ -249,6 +280,8 @@ def newton_solve(prob, disc: Discretization, st: IPMState, mu: float, mode: str 
         else:
             mode = "full" if (prob.dim == 2 and prob.N <= 127) or (prob.dim == 3 and prob.N <= 31) else "schur"
         if not np.all(_obs(prob) + ty > 0):  # (1,1) block singular (R9): no elimination of dy
+            mode = "full"
+        if _fem(disc):  # non-diagonal masses: no per-node elimination
             mode = "full"
     rhs = newton_rhs(prob, disc, st, mu)
     if mode == "full":

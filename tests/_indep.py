@@ -178,3 +178,51 @@ def dense_heat_operator(N, nt, tau):
             if t > 0:
                 A[r, r - n2] -= 1.0 / tau
     return A
+
+
+def dense_q1(N):
+    """Q1 stiffness and consistent mass on the interior nodes from their
+    nine-point stencils (interior node: 8/3 and -1/3 for the stiffness,
+    h^2/36 times 16, 4 (edge neighbours), 1 (corner neighbours) for the mass),
+    one row at a time; neighbours on the boundary are dropped."""
+    h = 1.0 / (N + 1)
+    n = N * N
+    K = np.zeros((n, n)); M = np.zeros((n, n))
+    for i2 in range(N):
+        for i1 in range(N):
+            r = i1 + N * i2
+            for b in (-1, 0, 1):
+                for a in (-1, 0, 1):
+                    j1, j2 = i1 + a, i2 + b
+                    if not (0 <= j1 < N and 0 <= j2 < N):
+                        continue
+                    c = j1 + N * j2
+                    if a == 0 and b == 0:
+                        K[r, c] += 8.0 / 3.0; M[r, c] += 16.0 * h * h / 36.0
+                    elif a == 0 or b == 0:
+                        K[r, c] -= 1.0 / 3.0; M[r, c] += 4.0 * h * h / 36.0
+                    else:
+                        K[r, c] -= 1.0 / 3.0; M[r, c] += 1.0 * h * h / 36.0
+    return K, M
+
+
+def fista_weighted(K, M, dl, yd, fhat, alpha, beta, ua, ub, iters=200000, tol=1e-15):
+    """min_u 1/2 (y - yd)^T M (y - yd) + alpha/2 u^T M u + beta sum_i dl_i |u_i|
+    with K y = M u + fhat and ua <= u <= ub (the finite-element problem),
+    by FISTA on u with a per-node weighted soft threshold."""
+    Kinv = np.linalg.inv(K)
+    G = Kinv @ M                       # y = G u + Kinv fhat
+    H = G.T @ M @ G + alpha * M        # Hessian in u
+    c = G.T @ M @ (Kinv @ fhat - yd)
+    L = np.linalg.eigvalsh(H).max()
+    u = np.zeros(K.shape[0]); z = u.copy(); t = 1.0
+    for _ in range(iters):
+        q = z - (H @ z + c) / L
+        un = np.clip(np.sign(q) * np.maximum(np.abs(q) - beta * dl / L, 0.0), ua, ub)
+        tn = 0.5 * (1 + math.sqrt(1 + 4 * t * t))
+        z = un + ((t - 1) / tn) * (un - u)
+        if np.abs(un - u).max() < tol:
+            u = un
+            break
+        u, t = un, tn
+    return u, G @ u + Kinv @ fhat

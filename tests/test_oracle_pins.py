@@ -509,3 +509,77 @@ def test_heat_matches_proximal_gradient(mu_rule):
     assert ((np.abs(u_ref) > 1e-6) & (u_ref < 1.2 - 1e-6) & (u_ref > -0.5 + 1e-6)).sum() > 0
     np.testing.assert_allclose(r.u, u_ref, rtol=0, atol=1e-7)
     np.testing.assert_allclose(r.y, y_ref, rtol=0, atol=1e-8)
+
+
+# ---------------------------------------------------------------- Q1 finite elements (Sec. 2, Sec. 5)
+
+def test_q1_element_assembly_matches_stencils():
+    from oracle.fem import q1_matrices
+    N = 7
+    L, M, D = q1_matrices(N)
+    Kd, Md = I.dense_q1(N)
+    np.testing.assert_allclose(L.toarray(), Kd, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(M.toarray(), Md, rtol=0, atol=1e-18)
+    np.testing.assert_allclose(D, np.full(N * N, 1.0 / 64), rtol=0, atol=0)
+
+
+def test_q1_stiffness_exact_on_cubics_and_mass_on_linears():
+    """On the uniform grid the Q1 stiffness stencil gives h^2 (-Lap u) for any
+    cubic u, and the mass stencil h^2 u for any linear u (boundary included)."""
+    from oracle.fem import _full_matrices, _interior_index
+    N = 15
+    h = 1.0 / (N + 1)
+    Lf, Mf = _full_matrices(N)
+    x1, x2 = W.all_coords(2, N)
+    Iidx = _interior_index(N)
+    u = 0.3 * x1 ** 3 - x1 ** 2 * x2 + 0.7 * x1 * x2 + 2 * x2 ** 2 - x2 + 0.2
+    lap = 1.8 * x1 - 2 * x2 + 4
+    np.testing.assert_allclose((Lf @ u)[Iidx], -h * h * lap[Iidx], rtol=0, atol=1e-13)
+    lin = 0.4 * x1 - 1.1 * x2 + 0.3
+    np.testing.assert_allclose((Mf @ lin)[Iidx], h * h * lin[Iidx], rtol=0, atol=1e-16)
+
+
+def test_q1_mass_diagonal_bounds_of_sec_4_1():
+    """lambda(D_M^-1 M) of the Q1 mass lies in [1/4, 9/4] (Wathen's bound the
+    paper relies on), and the eigenvalues of (alpha D~_M + Theta_z)^-1
+    (alpha M~ + Theta_z) lie in [min(lambda_min, 1), max(lambda_max, 1)]
+    (the theorem of Sec. 4.1)."""
+    from oracle.fem import q1_matrices
+    import scipy.linalg as sla
+    N = 7
+    _, M, _ = q1_matrices(N)
+    M = M.toarray()
+    DM = np.diag(np.diag(M))
+    lam = sla.eigh(M, DM, eigvals_only=True)
+    assert lam.min() >= 0.25 - 1e-12 and lam.max() <= 2.25 + 1e-12
+    rng = np.random.default_rng(2)
+    n = N * N
+    a = 1e-2
+    tw, tv = rng.uniform(0.01, 10, n), rng.uniform(0.01, 10, n)
+    full = np.block([[a * M + np.diag(tw), -a * M], [-a * M, a * M + np.diag(tv)]])
+    diag = np.block([[a * DM + np.diag(tw), -a * DM], [-a * DM, a * DM + np.diag(tv)]])
+    mu = sla.eigh(full, diag, eigvals_only=True)
+    assert mu.min() >= min(lam.min(), 1) - 1e-10 and mu.max() <= max(lam.max(), 1) + 1e-10
+
+
+@pytest.mark.parametrize("mu_rule", ["paper", "central"])
+def test_q1_ipm_matches_weighted_fista(mu_rule):
+    """The Q1 problem of eq. (pb_fe): the IPM optimum equals FISTA on the
+    reduced problem in u with the consistent masses and the lumped L1 weights."""
+    N = 7
+    p = W.poisson2d_q1(seed=1, N=N)
+    rng = np.random.default_rng(4)
+    p.y_d = W.sine_modes(rng, 2, N, 4, 3)[0] * 4.0
+    p.alpha, p.beta = 1e-2, 3e-3
+    p.u_a[:] = -1.5; p.u_b[:] = 1.0
+    p.y_a = p.y_b = None
+    K, M = I.dense_q1(N)
+    dl = np.full(p.n, 1.0 / (N + 1) ** 2)
+    u_ref, y_ref = I.fista_weighted(K, M, dl, p.y_d, np.zeros(p.n), p.alpha, p.beta, p.u_a, p.u_b)
+    r = oracle.solve(p, IPMOptions(sigma=p.sigma, eps_p=1e-13, eps_d=1e-13, eps_c=1e-13, mu_rule=mu_rule))
+    assert r.status == "converged"
+    assert (np.abs(u_ref) < 1e-12).sum() > 0 and (np.abs(u_ref - 1.0) < 1e-12).sum() > 0
+    assert (np.abs(u_ref + 1.5) < 1e-12).sum() > 0
+    assert ((np.abs(u_ref) > 1e-6) & (u_ref < 1.0 - 1e-6) & (u_ref > -1.5 + 1e-6)).sum() > 0
+    np.testing.assert_allclose(r.u, u_ref, rtol=0, atol=1e-7)
+    np.testing.assert_allclose(r.y, y_ref, rtol=0, atol=1e-8)
