@@ -15,6 +15,13 @@ assembled here element by element from the 4 x 4 element matrices of a
 square of side h.  Dirichlet data g enter through the boundary columns of L
 and the source through M: f_hat = M_II f_I - L_IB g_B (the boundary part of
 M f is dropped with f given at interior nodes only).
+
+The problem handed to the interior point method is eq. (pb_fe_lin) divided
+by h^2, the lumped mass of a node (the finite-element counterpart of the
+unit-mass form of fd.py): L / h^2, M / h^2 (rows summing to 1 away from the
+boundary), D / h^2 = I and f_hat / h^2.  The minimizer is unchanged, and the
+barrier parameter and the stopping tolerances keep the meaning they have
+for the finite-difference problems, independent of the mesh.
 """
 from __future__ import annotations
 
@@ -79,11 +86,13 @@ def discretize_q1(prob) -> Discretization:
     N = prob.N
     Lf, Mf = _full_matrices(N)
     I = _interior_index(N)
+    h = 1.0 / (N + 1)
     L, M = Lf[I][:, I].tocsr(), Mf[I][:, I].tocsr()
     f_hat = np.zeros(N * N) if prob.f is None else M @ np.asarray(prob.f, dtype=np.float64)
     if prob.g is not None:
         gg = np.array(prob.g, dtype=np.float64, copy=True)
         gg[I] = 0.0
         f_hat = f_hat - (Lf @ gg)[I]
-    h = 1.0 / (N + 1)
-    return Discretization(2, N, L, f_hat, Mt=M, Mc=M, dl=np.full(N * N, h * h))
+    s = 1.0 / (h * h)
+    return Discretization(2, N, (L * s).tocsr(), f_hat * s, Mt=(M * s).tocsr(), Mc=(M * s).tocsr(),
+                          dl=np.ones(N * N))
