@@ -11,7 +11,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libipmpde.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOTCONVERGED, EKRYLOV, EBREAKDOWN = range(7)
-POISSON, CONVDIFF, HEAT = 0, 1, 2
+POISSON, CONVDIFF, HEAT, POISSON_Q1 = 0, 1, 2, 3
 MINRES, FGMRES = 0, 1
 PD, PT, PPI = 0, 1, 2
 FP64, FP32 = 0, 1

@@ -158,7 +158,7 @@ class Problem:
             L.check(self._lib.ipmpde_heat_create(C.byref(grid), self.nt, float(tau), float(alpha), float(beta),
                                                  *[_ptr(a) for a in self._keep], C.byref(h)))
         else:
-            kind = {"poisson": L.POISSON, "convdiff": L.CONVDIFF}[pde]
+            kind = {"poisson": L.POISSON, "convdiff": L.CONVDIFF, "poisson_q1": L.POISSON_Q1}[pde]
             pdes = L.Pde(kind, float(eps))
             L.check(self._lib.ipmpde_problem_create(C.byref(grid), C.byref(pdes), float(alpha), float(beta),
                                                     *[_ptr(a) for a in self._keep], C.byref(h)))

@@ -68,7 +68,8 @@ struct KrylovCtrl {
 // launch can advance many (unevenly sized) instances; a single problem is a
 // batch of one.
 struct Inst {
-  int dim, N, n, pde;  // pde: 0 Poisson, 1 convection-diffusion, 2 heat (n = N^2 nt space-time nodes)
+  int dim, N, n, pde;  // pde: 0 Poisson, 1 convection-diffusion, 2 heat (n = N^2 nt space-time nodes),
+                       // 3 Poisson with Q1 finite elements (2D)
   int nt;              // heat: time steps (1 otherwise)
   double tau;          // heat: time step
   int has_y;
@@ -129,6 +130,7 @@ __device__ __forceinline__ void wind(double x1, double x2, double& w1, double& w
 // Diagonal entry of the operator at node (i1, i2) (0-based) on a grid of width h.
 __device__ __forceinline__ double op_diag(int dim, int pde, double h, double eps, int i1, int i2) {
   if (pde == 0) return 2.0 * dim / (h * h);
+  if (pde == 3) return 8.0 / (3.0 * h * h);
   double w1, w2;
   wind((i1 + 1) * h, (i2 + 1) * h, w1, w2);
   return 4.0 * eps / (h * h) + (fabs(w1) + fabs(w2)) / h;
@@ -160,6 +162,25 @@ __device__ __forceinline__ T apply_op_s(const T* __restrict__ x, int idx, int i1
       if (i3 < N - 1) nb += X_(idx + sz);
     }
     return ih2 * ((T)(2 * dim) * X_(idx) - nb);
+  }
+  if (pde == 3) {
+    // Q1 stiffness divided by h^2 (2D): (8 x - the eight neighbours) / (3 h^2), symmetric
+    const T ih2 = (T)(1.0 / (3.0 * h * h));
+    const bool l = i1 > 0, r = i1 < N - 1, d = i2 > 0, u = i2 < N - 1;
+    T nb = 0;
+    if (l) nb += X_(idx - 1);
+    if (r) nb += X_(idx + 1);
+    if (d) {
+      nb += X_(idx - sy);
+      if (l) nb += X_(idx - sy - 1);
+      if (r) nb += X_(idx - sy + 1);
+    }
+    if (u) {
+      nb += X_(idx + sy);
+      if (l) nb += X_(idx + sy - 1);
+      if (r) nb += X_(idx + sy + 1);
+    }
+    return ih2 * ((T)8 * X_(idx) - nb);
   }
   // 2D upwind convection-diffusion
   const double ed = eps / (h * h), ih = 1.0 / h;
@@ -236,6 +257,31 @@ __device__ __forceinline__ T inst_op(const Inst& I, const T* __restrict__ x, int
     if (i3 < I.nt - 1) r -= it * (double)x[idx + nn];
   }
   return (T)r;
+}
+
+// Q1 mass matrix divided by h^2 (2D): (16 x + 4 (edge neighbours) + corner
+// neighbours) / 36, so that rows sum to 1 away from the boundary.  Its
+// diagonal, the D_M of the preconditioners, is 4/9.  ABS: with |x|.
+constexpr double kQ1MassDiag = 16.0 / 36.0;
+template <typename T, bool ABS = false>
+__device__ __forceinline__ T q1_mass(const T* __restrict__ x, int idx, int i1, int i2, int N) {
+#define X_(k) ldv<T, ABS>(x, (k))
+  const bool l = i1 > 0, r = i1 < N - 1, d = i2 > 0, u = i2 < N - 1;
+  T e = 0, c = 0;
+  if (l) e += X_(idx - 1);
+  if (r) e += X_(idx + 1);
+  if (d) {
+    e += X_(idx - N);
+    if (l) c += X_(idx - N - 1);
+    if (r) c += X_(idx - N + 1);
+  }
+  if (u) {
+    e += X_(idx + N);
+    if (l) c += X_(idx + N - 1);
+    if (r) c += X_(idx + N + 1);
+  }
+#undef X_
+  return ((T)16 * ldv<T, ABS>(x, idx) + (T)4 * e + c) * (T)(1.0 / 36.0);
 }
 
 // (|A| |x|)_idx (or with |A^T|) for rounding-error bounds.  Every

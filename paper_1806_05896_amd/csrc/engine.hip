@@ -100,7 +100,8 @@ extern "C" int ipmpde_engine_submit(ipmpde_engine* E, ipmpde_problem* P, const i
                                     uint64_t* ticket) {
   if (!E || !P || !ticket) return fail(IPMPDE_EINVAL, "NULL argument");
   if (P->in_engine) return fail(IPMPDE_EINVAL, "problem is already queued or running in an engine");
-  if (P->pde == IPMPDE_HEAT) return fail(IPMPDE_EINVAL, "heat-equation problems are solved one at a time");
+  if (P->pde == IPMPDE_HEAT || P->pde == IPMPDE_POISSON_Q1)
+    return fail(IPMPDE_EINVAL, "heat-equation and Q1 problems are not served by the engine");
   ipmpde_options o;
   TRY(resolve_opts(opts, &o));
   ipmpde_grid g{P->dim, P->N};

@@ -51,16 +51,21 @@ __global__ void __launch_bounds__(kBS) k_measures(const Inst* __restrict__ Dp) {
     const double ATp = inst_op<double>(I, I.p, i, i1, i2, i3, true);
     const double ua = I.ua[i], ub = I.ub[i];
     const double lwa = I.lwa[i], lwb = I.lwb[i], lva = I.lva[i], lvb = I.lvb[i];
-    r[0] = fabs(Ay - u - I.fhat[i]);
-    double dy = obs_w(I, i) * (y - I.yd[i]) + ATp;
+    // unit mass, or Q1: M u, M (y - y_d) and M p in eq. (prdu)
+    const bool q1 = I.pde == 3;
+    const double Mu = q1 ? q1_mass<double>(I.w, i, i1, i2, I.N) - q1_mass<double>(I.v, i, i1, i2, I.N) : u;
+    const double Mp = q1 ? q1_mass<double>(I.p, i, i1, i2, I.N) : p;
+    r[0] = fabs(Ay - Mu - I.fhat[i]);
+    double dy = (q1 ? q1_mass<double>(I.y, i, i1, i2, I.N) - q1_mass<double>(I.yd, i, i1, i2, I.N)
+                    : obs_w(I, i) * (y - I.yd[i])) + ATp;
     double pc = nmax(nmax(w * lwa, (ub - w) * lwb), nmax(v * lva, (-ua - v) * lvb));
     if (I.has_y) {
       const double lya = I.lya[i], lyb = I.lyb[i];
       dy += -lya + lyb;
       pc = nmax(pc, nmax((y - I.ya[i]) * lya, (I.yb[i] - y) * lyb));
     }
-    const double dw = I.alpha * u + I.beta - p - lwa + lwb;
-    const double dv = -I.alpha * u + I.beta + p - lva + lvb;
+    const double dw = I.alpha * Mu + I.beta - Mp - lwa + lwb;
+    const double dv = -I.alpha * Mu + I.beta + Mp - lva + lvb;
     r[1] = nmax(fabs(dy), nmax(fabs(dw), fabs(dv)));
     r[2] = fabs(pc);
   }
@@ -120,9 +125,19 @@ __global__ void __launch_bounds__(kBS) k_newton_setup(const Inst* __restrict__ D
       ty = I.lya[i] / gya + I.lyb[i] / gyb;
       by = -mu / gya + mu / gyb;
     }
-    const double sig = (tw + tv) / (I.alpha * (tw + tv) + tw * tv);
+    const bool q1 = I.pde == 3;
+    double sig, mh;
     const double ow = obs_w(I, i);
-    const double mh = I.ppi ? sig : sqrt(sig * (ow + ty));
+    if (q1) {
+      // Sec. 4.2 with D_M = diag(M): [D_M/alpha - (1/alpha^2)(1/t_w + 1/t_v + 1/(alpha D_M))^-1]
+      // = D_M^2 (t_w + t_v) / (alpha D_M (t_w + t_v) + t_w t_v), times D_M + Theta_y, square root
+      const double dm = kQ1MassDiag;
+      sig = dm * dm * (tw + tv) / (I.alpha * dm * (tw + tv) + tw * tv);
+      mh = sqrt(sig * (dm + ty));
+    } else {
+      sig = (tw + tv) / (I.alpha * (tw + tv) + tw * tv);
+      mh = I.ppi ? sig : sqrt(sig * (ow + ty));
+    }
     I.ty[i] = ty;
     I.tw[i] = tw;
     I.tv[i] = tv;
@@ -133,10 +148,14 @@ __global__ void __launch_bounds__(kBS) k_newton_setup(const Inst* __restrict__ D
     const double u = w - v;
     const double Ay = inst_op<double>(I, I.y, i, i1, i2, i3, false);
     const double ATp = inst_op<double>(I, I.p, i, i1, i2, i3, true);
-    const double ry = -(ow * (y - I.yd[i]) + ATp + by);
-    const double rw = -(I.alpha * u + I.beta - p - mu / w + mu / gwb);
-    const double rv = -(-I.alpha * u + I.beta + p - mu / v + mu / gvb);
-    const double rp = -(Ay - u - I.fhat[i]);
+    const double Mu = q1 ? q1_mass<double>(I.w, i, i1, i2, I.N) - q1_mass<double>(I.v, i, i1, i2, I.N) : u;
+    const double Mp = q1 ? q1_mass<double>(I.p, i, i1, i2, I.N) : p;
+    const double Myd = q1 ? q1_mass<double>(I.y, i, i1, i2, I.N) - q1_mass<double>(I.yd, i, i1, i2, I.N)
+                          : ow * (y - I.yd[i]);
+    const double ry = -(Myd + ATp + by);
+    const double rw = -(I.alpha * Mu + I.beta - Mp - mu / w + mu / gwb);
+    const double rv = -(-I.alpha * Mu + I.beta + Mp - mu / v + mu / gvb);
+    const double rp = -(Ay - Mu - I.fhat[i]);
     const int n = I.n;
     double* rhs = I.rhs;
     rhs[i] = ry;

@@ -39,6 +39,16 @@ __device__ __forceinline__ void saddle_rows(const Inst& I, const double* __restr
   const double ATxp = inst_op<double>(I, x + 3 * n, i, i1, i2, i3, true);
   const double Axy = inst_op<double>(I, x, i, i1, i2, i3, false);
   const double xp = x[3 * n + i];
+  if (I.pde == 3) {
+    // Q1 (Sec. 2): M in the (1,1) block, alpha M~ and the coupling M bar
+    const double My = q1_mass<double>(x, i, i1, i2, I.N), Mw = q1_mass<double>(x + n, i, i1, i2, I.N);
+    const double Mv = q1_mass<double>(x + 2 * n, i, i1, i2, I.N), Mp = q1_mass<double>(x + 3 * n, i, i1, i2, I.N);
+    out[0] = s * (My + ty * xy + ATxp);
+    out[1] = s * (a * (Mw - Mv) + tw * xw - Mp);
+    out[2] = s * (-a * (Mw - Mv) + tv * xv + Mp);
+    out[3] = s * (Axy - (Mw - Mv));
+    return;
+  }
   out[0] = s * ((obs_w(I, i) + ty) * xy + ATxp);
   out[1] = s * ((a + tw) * xw - a * xv - xp);
   out[2] = s * (-a * xw + (a + tv) * xv + xp);
@@ -54,6 +64,16 @@ __device__ __forceinline__ void saddle_rows_abs(const Inst& I, const double* __r
   const double ty = I.ty[i], tw = I.tw[i], tv = I.tv[i], a = I.alpha;
   const double ATxp = inst_op_abs(I, x + 3 * n, i, i1, i2, i3, true);
   const double Axy = inst_op_abs(I, x, i, i1, i2, i3, false);
+  if (I.pde == 3) {
+    const double My = q1_mass<double, true>(x, i, i1, i2, I.N), Mw = q1_mass<double, true>(x + n, i, i1, i2, I.N);
+    const double Mv = q1_mass<double, true>(x + 2 * n, i, i1, i2, I.N);
+    const double Mp = q1_mass<double, true>(x + 3 * n, i, i1, i2, I.N);
+    out[0] = My + ty * xy + ATxp;
+    out[1] = a * (Mw + Mv) + tw * xw + Mp;
+    out[2] = a * (Mw + Mv) + tv * xv + Mp;
+    out[3] = Axy + Mw + Mv;
+    return;
+  }
   out[0] = (obs_w(I, i) + ty) * xy + ATxp;
   out[1] = (a + tw) * xw + a * xv + xp;
   out[2] = a * xw + (a + tv) * xv + xp;
@@ -61,9 +81,9 @@ __device__ __forceinline__ void saddle_rows_abs(const Inst& I, const double* __r
 }
 
 // Per-node inverse of the z block [a+t_w, -a; -a, a+t_v] (alpha M~ + Theta_z
-// with M = I; Sec. 4.1).
+// with M = I; Sec. 4.1); for Q1 the paper's alpha D~_M + Theta_z, a = alpha D_M.
 __device__ __forceinline__ void apply_z_inv(const Inst& I, int i, double rw, double rv, double& zw, double& zv) {
-  const double tw = I.tw[i], tv = I.tv[i], a = I.alpha;
+  const double tw = I.tw[i], tv = I.tv[i], a = I.pde == 3 ? I.alpha * kQ1MassDiag : I.alpha;
   const double det = a * (tw + tv) + tw * tv;
   zw = ((a + tv) * rw + a * rv) / det;
   zv = (a * rw + (a + tw) * rv) / det;
@@ -171,8 +191,51 @@ __global__ void __launch_bounds__(kBS) k_precond_diag(const Inst* __restrict__ D
   double* z = zx ? zx : I.fZ + (size_t)j * 4 * n;
   double zy, zw, zv;
   apply_A11_inv(I, i, r[i], r[n + i], r[2 * n + i], zy, zw, zv);
-  z[i] = zy; z[n + i] = zw; z[2 * n + i] = zv;
+  if (I.pde != 3) z[i] = zy;  // Q1: the y block comes from k_cheb_step
+  z[n + i] = zw; z[2 * n + i] = zv;
   if (!pt) ((T*)I.lv[0].b)[i] = (T)r[3 * n + i];
+}
+
+// Q1 (Sec. 4.1): z_y = (M + Theta_y)^-1 r_y approximated by Chebyshev
+// semi-iteration with the diagonal D_M + Theta_y, whose preconditioned
+// spectrum lies in [1/4, 9/4] (the Q1 mass-matrix bounds): with
+// theta, delta the centre and half-width of that interval and x_0 = 0,
+//   x_1 = d_0 = (D_M + Theta_y)^-1 r / theta,
+//   r_k = r_{k-1} - (M + Theta_y) d_{k-1},
+//   d_k = rho_k rho_{k-1} d_{k-1} + (2 rho_k / delta) (D_M + Theta_y)^-1 r_k,
+//   x_{k+1} = x_k + d_k,  rho_0 = delta / theta, rho_k = 1 / (2 theta / delta - rho_{k-1}).
+// Step k of the recurrence (k = 0 starts it): the residual rk and the
+// direction buffers d[2] (d_{k-1} read from d[(k+1)&1], d_k written to
+// d[k&1]) are n-vectors of the workspace.
+__global__ void __launch_bounds__(kBS) k_cheb_step(const Inst* __restrict__ Dp, const double* __restrict__ rx, double* __restrict__ zx,
+                                                   int j, int k, double rho, double rho_prev, double theta,
+                                                   double delta, int guard) {
+  INST_BEGIN
+  if (guard && I.ctrl->stop) return;
+  const int i = blockIdx.x * kBS + threadIdx.x;
+  if (i >= I.n) return;
+  const int n = I.n;
+  const double* r = rx ? rx : I.fV + (size_t)j * 4 * n;
+  double* z = zx ? zx : I.fZ + (size_t)j * 4 * n;
+  double* rk = I.W[0];
+  double* dd[2] = {I.W[0] + n, I.W[0] + 2 * n};
+  const double dinv = 1.0 / (kQ1MassDiag + I.ty[i]);
+  if (k == 0) {
+    const double d0 = r[i] * dinv / theta;
+    rk[i] = r[i];
+    dd[0][i] = d0;
+    z[i] = d0;
+    return;
+  }
+  int i1, i2, i3;
+  node_coords(i, I.N, 2, i1, i2, i3);
+  const double* dp = dd[(k + 1) & 1];
+  const double Ad = q1_mass<double>(dp, i, i1, i2, I.N) + I.ty[i] * dp[i];
+  const double res = rk[i] - Ad;
+  const double dn = rho * rho_prev * dp[i] + (2.0 * rho / delta) * res * dinv;
+  rk[i] = res;
+  dd[k & 1][i] = dn;
+  z[i] += dn;
 }
 
 // P_T (Sec. 4, block lower triangular [A11 0; B -S_hat]): the p block solves
@@ -189,7 +252,9 @@ __global__ void __launch_bounds__(kBS) k_pt_rhs(const Inst* __restrict__ Dp, con
   const int n = I.n;
   const double* r = rx ? rx : I.fV + (size_t)j * 4 * n;
   const double* z = zx ? zx : I.fZ + (size_t)j * 4 * n;
-  const double Bz = inst_op<double>(I, z, i, i1, i2, i3, false) - z[n + i] + z[2 * n + i];
+  const double Bz = I.pde == 3 ? inst_op<double>(I, z, i, i1, i2, i3, false) -
+                                      (q1_mass<double>(z + n, i, i1, i2, I.N) - q1_mass<double>(z + 2 * n, i, i1, i2, I.N))
+                                : inst_op<double>(I, z, i, i1, i2, i3, false) - z[n + i] + z[2 * n + i];
   ((T*)I.lv[0].b)[i] = (T)(Bz - r[3 * n + i]);
 }
 

@@ -145,6 +145,7 @@ struct Group {
   bool any_small = false;  // 2D: some instance runs its whole hierarchy in the coarse kernel
   int outsel = 1;    // level-0 output buffer of a V-cycle (x2 = 1)
   bool heat = false; // heat-equation problems (a group holds only heat problems or none)
+  bool q1 = false;   // Q1 finite-element problems (likewise): generic multigrid path
   int sel_pre = 0;   // 3D path: buffer holding the pre-smoothed iterate
   bool fp32 = true;
 };
@@ -419,6 +420,7 @@ static int group_create(const std::vector<ipmpde_problem*>& probs, int cap, int 
   G->zc = G->count;
   G->dim = dim;
   G->heat = !probs.empty() && probs[0]->pde == IPMPDE_HEAT;
+  G->q1 = !probs.empty() && probs[0]->pde == IPMPDE_POISSON_Q1;
   auto bail = [&](int rc) { group_release(G); return rc; };
   int rc;
   if ((rc = G->mem.alloc_t(&G->D, cap))) return bail(rc);
@@ -587,7 +589,7 @@ static int group_select(Group* G, const ipmpde_options& o) {
       heat_steps(G->probs[i], G->H[i], fp32);
       G->H[i].hsteps = G->probs[i]->hs_d;
     }
-  if (G->dim == 2) {
+  if (G->dim == 2 && !G->q1) {
     G->outsel = 1;
   } else {
     G->sel_pre = o.nu_pre & 1;
@@ -832,7 +834,7 @@ static void mg_solve(Group* G, int transpose, int guard, int scaled, hipStream_t
   for (int j = 1; j <= k; ++j) {
     if (j > 1)
       hipLaunchKernelGGL(k_mg_kc_resid<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, G->outsel, transpose, j - 1, guard);
-    if (G->dim == 2) mg_vcycle_2d<T>(G, transpose, guard, j == 1 ? scaled : 0, s);
+    if (G->dim == 2 && !G->q1) mg_vcycle_2d<T>(G, transpose, guard, j == 1 ? scaled : 0, s);
     else mg_vcycle_generic<T>(G, transpose, guard, s);
   }
   if (k > 1) hipLaunchKernelGGL(k_mg_kc_final<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, G->outsel, k, guard);
@@ -891,7 +893,7 @@ static void schur_inv(Group* G, int guard, hipStream_t s) {
     heat_schur_inv<T>(G, guard, s);
     return;
   }
-  if (G->dim == 2) {
+  if (G->dim == 2 && !G->q1) {
     mg_solve<T>(G, 0, guard, 0, s);
     // instances whose whole hierarchy is in the coarse kernel never run a
     // descent kernel, so their scaled right-hand side is formed here; the
@@ -993,6 +995,9 @@ static void mg_select(Group* G, int slot, hipStream_t s) {
   hipLaunchKernelGGL(k_mg_select, dim3(1, 1, G->zc), dim3(64), 0, s, G->D, slot);
 }
 
+// Chebyshev steps for the Q1 mass block (the paper's 20).
+static constexpr int kChebSteps = 20;
+
 // z = P^-1 r for every instance (pt: IPMPDE_PD, IPMPDE_PT or IPMPDE_PPI);
 // explicit operands, or the FGMRES slots r = V_j, z = Z_j when null.
 template <typename T>
@@ -1013,6 +1018,19 @@ static void precond_apply(Group* G, int pt, const double* x, double* y, int j, i
     return;
   }
   hipLaunchKernelGGL(k_precond_diag<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, x, y, j, pt, guard);
+  if (G->q1) {
+    // (M + Theta_y)^-1 by Chebyshev semi-iteration (Sec. 4.1 and Sec. 5: 20 steps), spectrum [1/4, 9/4]
+    const double theta = 1.25, delta = 1.0;
+    double rho_prev = delta / theta, rho = rho_prev;
+    for (int k = 0; k < kChebSteps; ++k) {
+      if (k > 0) {
+        rho_prev = rho;
+        rho = 1.0 / (2.0 * theta / delta - rho_prev);
+      }
+      hipLaunchKernelGGL(k_cheb_step, gz(G, G->max_n), dim3(kBS), 0, s, G->D, x, y, j, k, rho, rho_prev, theta, delta,
+                         guard);
+    }
+  }
   if (pt) hipLaunchKernelGGL(k_pt_rhs<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, x, (const double*)y, j, guard);
   schur_inv<T>(G, guard, s);
   hipLaunchKernelGGL(k_store_p<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, y, j, G->outsel, guard);
@@ -1114,6 +1132,8 @@ static void heat_setup(Group* G, hipStream_t s) {
 static int newton_setup_group(Group* G, const ipmpde_options& o, hipStream_t s) {
   if (G->heat && o.precond == IPMPDE_PPI)
     return fail(IPMPDE_EINVAL, "P_Pi is not available for the heat equation");
+  if (G->q1 && (o.krylov != IPMPDE_FGMRES || o.precond == IPMPDE_PPI))
+    return fail(IPMPDE_EINVAL, "Q1 problems are solved with FGMRES and P_D or P_T");
   for (int i = 0; i < G->count; ++i) {
     const ipmpde_problem* P = G->probs[i];
     if (o.precond != IPMPDE_PPI && P->obs_zero && !P->has_y)
@@ -1318,6 +1338,26 @@ static void fold_boundary(int dim, int N, int pde, double eps, const double* g, 
   }
 }
 
+// Q1 (divided by h^2): f_hat = M f - L_IB g with the interior mass stencil
+// (16, 4, 1) / 36 applied to f and the stiffness stencil's boundary
+// neighbours, -1 / (3 h^2) each over the eight neighbours, applied to g.
+static void fold_q1(int N, const double* f, const double* g, std::vector<double>& fhat) {
+  const double h = 1.0 / (N + 1);
+  const int P = N + 2;
+  for (int i2 = 0; i2 < N; ++i2)
+    for (int i1 = 0; i1 < N; ++i1) {
+      double acc = 0.0;
+      for (int b = -1; b <= 1; ++b)
+        for (int a = -1; a <= 1; ++a) {
+          const int j1 = i1 + a, j2 = i2 + b;
+          const bool inside = j1 >= 0 && j1 < N && j2 >= 0 && j2 < N;
+          if (inside && f) acc += (a == 0 && b == 0 ? 16.0 : (a == 0 || b == 0 ? 4.0 : 1.0)) / 36.0 * f[j1 + N * j2];
+          if (!inside && g) acc += g[(j1 + 1) + (size_t)P * (j2 + 1)] / (3.0 * h * h);
+        }
+      fhat[i1 + (size_t)N * i2] = acc;
+    }
+}
+
 extern "C" const char* ipmpde_version(void) { return "libipmpde 0.2 (gfx950)"; }
 extern "C" const char* ipmpde_last_error(void) { return g_err.c_str(); }
 
@@ -1413,6 +1453,8 @@ static int problem_create_impl(int dim, int N, int kind, double eps, int nt, dou
       for (size_t i = 0; i < n2; ++i) fhat[(size_t)t * n2 + i] += step[i];
     if (y0)
       for (size_t i = 0; i < n2; ++i) fhat[i] += y0[i] / tau;
+  } else if (kind == IPMPDE_POISSON_Q1) {
+    fold_q1(N, f, g, fhat);
   } else if (g) {
     fold_boundary(dim, N, kind, kind == IPMPDE_POISSON ? 1.0 : eps, g, fhat);
   }
@@ -1485,7 +1527,9 @@ extern "C" int ipmpde_problem_create(const ipmpde_grid* grid, const ipmpde_pde* 
   if (!is_pow2m1(grid->n)) return fail(IPMPDE_EINVAL, "n must be 2^k - 1 with k >= 2");
   if (grid->n > (grid->dim == 2 ? 8191 : 511)) return fail(IPMPDE_EINVAL, "grid too large");
   if (pde->kind == IPMPDE_HEAT) return fail(IPMPDE_EINVAL, "heat-equation problems are made by ipmpde_heat_create");
-  if (pde->kind != IPMPDE_POISSON && pde->kind != IPMPDE_CONVDIFF) return fail(IPMPDE_EINVAL, "unknown pde kind");
+  if (pde->kind != IPMPDE_POISSON && pde->kind != IPMPDE_CONVDIFF && pde->kind != IPMPDE_POISSON_Q1)
+    return fail(IPMPDE_EINVAL, "unknown pde kind");
+  if (pde->kind == IPMPDE_POISSON_Q1 && grid->dim != 2) return fail(IPMPDE_EINVAL, "Q1 elements are 2D only");
   if (pde->kind == IPMPDE_CONVDIFF && grid->dim != 2) return fail(IPMPDE_EINVAL, "convection-diffusion is 2D only");
   if (pde->kind == IPMPDE_CONVDIFF && !(pde->eps > 0 && std::isfinite(pde->eps)))
     return fail(IPMPDE_EINVAL, "eps must be positive");
@@ -1677,6 +1721,8 @@ static const double* field_ptr(const ipmpde_problem* P, int field, int* kind) {
 extern "C" int ipmpde_set_observation(ipmpde_problem* P, const double* weights, size_t count) {
   if (!P) return fail(IPMPDE_EINVAL, "problem is NULL");
   if (P->in_engine) return fail(IPMPDE_EINVAL, "problem is queued or running in an engine");
+  if (P->pde == IPMPDE_POISSON_Q1 && weights)
+    return fail(IPMPDE_EINVAL, "observation weights are defined for the finite-difference problems");
   if (!weights) {
     P->I.obs = P->obs = nullptr;
     P->obs_zero = false;
@@ -1800,6 +1846,8 @@ extern "C" int ipmpde_batch_create(ipmpde_problem* const* probs, int count, ipmp
     if (v[i]->dim != v[0]->dim) return fail(IPMPDE_EINVAL, "all problems of a batch must have the same dimension");
     if ((v[i]->pde == IPMPDE_HEAT) != (v[0]->pde == IPMPDE_HEAT))
       return fail(IPMPDE_EINVAL, "a batch holds only heat-equation problems or none");
+    if ((v[i]->pde == IPMPDE_POISSON_Q1) != (v[0]->pde == IPMPDE_POISSON_Q1))
+      return fail(IPMPDE_EINVAL, "a batch holds only Q1 problems or none");
     for (int j = 0; j < i; ++j)
       if (v[j] == v[i]) return fail(IPMPDE_EINVAL, "a problem appears twice in the batch");
   }

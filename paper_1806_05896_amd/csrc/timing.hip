@@ -51,8 +51,9 @@ static int time_kernel_group(Group* G, const ipmpde_options& o, int kernel, int 
     const ipmpde_problem* P = G->probs[i];
     if (!P->setup_done || P->setup_group != G || P->setup_fp32 != (o.mg_precision == IPMPDE_FP32))
       return fail(IPMPDE_EINVAL, "no Newton setup for this multigrid precision");
-    if ((kernel == 3 || kernel == 4 || kernel == 5 || kernel == 7) && P->pde == IPMPDE_HEAT)
-      return fail(IPMPDE_EINVAL, "the heat equation's multigrid runs per time step: time kernels 0, 2 or 6");
+    if ((kernel == 3 || kernel == 4 || kernel == 5 || kernel == 7) &&
+        (P->pde == IPMPDE_HEAT || P->pde == IPMPDE_POISSON_Q1))
+      return fail(IPMPDE_EINVAL, "time kernels 0, 2 or 6 for heat-equation and Q1 problems");
     if ((kernel == 3 || kernel == 4 || kernel == 5) && (P->dim != 2 || P->nlev < 2))
       return fail(IPMPDE_EINVAL, "the fused level kernels exist for 2D grids with at least two levels");
   }

@@ -114,6 +114,8 @@ def test_ipm_step_parity_at_511():
     ("poisson3d_127", {}),
     ("heat2d", {"krylov": "fgmres", "precond": "pt"}),
     ("heat2d", {}),
+    ("poisson2d_q1", {"krylov": "fgmres", "precond": "pt"}),
+    ("poisson2d_q1", {"krylov": "fgmres", "precond": "pd"}),
 ])
 def test_newton_direction_solves_oracle_system(name, opts_kw):
     """At the full sizes, from a mid-solve GPU state: the GPU Newton direction
@@ -186,4 +188,22 @@ def test_heat_full_size_kkt(krylov, precond):
     assert max(xp, xd, xc) <= 1e-6
     # the residual entries are differences of terms of size |A||y| ~ 3e4 (h = 1/64,
     # 1/tau = 100), so evaluation order alone moves them by ~1e-12
+    np.testing.assert_allclose([xp, xd, xc], [s.xi_p, s.xi_d, s.xi_c], rtol=1e-6, atol=1e-10)
+
+
+def test_q1_full_size_kkt():
+    """Q1 at 511^2 with state bounds (FGMRES + P_T): the final iterate meets
+    the IPM tolerance on the oracle's own residuals, and the reported
+    measures agree with them."""
+    from paper_1806_05896_amd import Options, Problem
+    data = W.poisson2d_q1(seed=0)
+    print(f"[q1 full] n={data.n}", flush=True)
+    with Problem(data) as prob:
+        rc = prob.solve(Options(sigma=data.sigma, krylov="fgmres", precond="pt", mg_precision="fp32"))
+        s = prob.stats()
+        st = _state_from_gpu(prob, True, s.mu)
+    xp, xd, xc = measures(data, discretize(data), st)
+    print(f"  rc={rc} nli={s.nli} its={s.krylov_its} measures {xp:.2e} {xd:.2e} {xc:.2e}", flush=True)
+    assert rc == 0 and s.krylov_fail == 0
+    assert max(xp, xd, xc) <= 1e-6
     np.testing.assert_allclose([xp, xd, xc], [s.xi_p, s.xi_d, s.xi_c], rtol=1e-6, atol=1e-10)

@@ -1,0 +1,231 @@
+"""GPU parity for the Q1 finite-element discretization (Sec. 2, eq.
+(pb_fe_lin); the paper's own discretization): operators, Newton right-hand
+side and saddle matvec with the consistent mass, the Chebyshev
+semi-iteration of the (1,1) block, Newton directions (FGMRES with P_D and
+P_T) and whole solves, through the C ABI against the CPU oracle.  Tolerances
+as in test_gpu_parity.py."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+import workloads as W  # noqa: E402
+from oracle.fd import discretize  # noqa: E402
+from oracle.ipm import IPMOptions, barrier_diagonals, newton_matrix, newton_rhs, newton_solve  # noqa: E402
+from tests.test_gpu_parity import _generic_state, _load_state, _rel  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def _api():
+    from paper_1806_05896_amd import Batch, Options, Problem
+    return Batch, Options, Problem
+
+
+def _with_data(N):
+    """Nonzero source and boundary data (folded into f_hat through M and L)."""
+    d = W.poisson2d_q1(seed=3, N=N)
+    rng = np.random.default_rng(N)
+    d.f = 0.3 * rng.normal(size=d.n)
+    g1, g2 = W.all_coords(2, N)
+    d.g = 0.05 * (1 + g1 - g2)
+    return d
+
+
+CASES = {
+    "q1_31": lambda: W.poisson2d_q1(seed=0, N=31),
+    "q1_63": lambda: W.poisson2d_q1(seed=0, N=63),
+    "q1_63_hard": lambda: W.poisson2d_q1(seed=1, N=63),
+    "q1_data_31": lambda: _with_data(31),
+    "q1_nobounds_31": lambda: _nostate(31),
+}
+
+
+def _nostate(N):
+    d = W.poisson2d_q1(seed=2, N=N)
+    d.y_a = d.y_b = None
+    return d
+
+
+def _rhs_magnitude(data, disc, st, mu):
+    """Sum of the magnitudes of the terms of each right-hand-side entry."""
+    aA, aM = abs(disc.A), abs(disc.Mc)
+    ry = aM @ (np.abs(st.y) + np.abs(data.y_d)) + aA.T @ np.abs(st.p)
+    if data.y_a is not None:
+        ry = ry + mu / np.abs(st.y - data.y_a) + mu / np.abs(data.y_b - st.y)
+    au = data.alpha * (aM @ (np.abs(st.w) + np.abs(st.v)))
+    rw = au + data.beta + aM @ np.abs(st.p) + mu / np.abs(st.w) + mu / np.abs(data.u_b - st.w)
+    rv = au + data.beta + aM @ np.abs(st.p) + mu / np.abs(st.v) + mu / np.abs(-data.u_a - st.v)
+    rp = aA @ np.abs(st.y) + aM @ (np.abs(st.w) + np.abs(st.v)) + np.abs(disc.f_hat)
+    return np.concatenate([ry, rw, rv, rp])
+
+
+@pytest.mark.parametrize("N", [3, 31, 127])
+def test_q1_operator_parity(N):
+    _, Options, Problem = _api()
+    print(f"[q1 operator] N={N}", flush=True)
+    data = W.poisson2d_q1(N=N)
+    A = discretize(data).A
+    x = np.random.default_rng(N).normal(size=data.n)
+    with Problem(data) as prob:
+        xt = torch.tensor(x, device="cuda", dtype=torch.float64)
+        for tr in (False, True):
+            y = prob.apply_operator(xt, transpose=tr).cpu().numpy()
+            assert _rel(y, (A.T if tr else A) @ x) <= 1e-13
+
+
+@pytest.mark.parametrize("case", ["q1_31", "q1_data_31", "q1_nobounds_31"])
+def test_q1_rhs_and_saddle_matvec(case):
+    _, Options, Problem = _api()
+    print(f"[q1 saddle] {case}", flush=True)
+    data = CASES[case]()
+    disc, st = _generic_state(data)
+    mu = st.mu * data.sigma
+    K = newton_matrix(data, disc, st)
+    b = newton_rhs(data, disc, st, mu)
+    opts = Options(krylov="fgmres", precond="pd")
+    with Problem(data) as prob:
+        _load_state(prob, st, data.y_a is not None)
+        prob.newton_setup(mu, opts)
+        assert np.all(np.abs(prob.query_rhs() - b) <= 64 * np.finfo(float).eps * _rhs_magnitude(data, disc, st, mu))
+        x = np.random.default_rng(1).normal(size=4 * data.n)
+        y = prob.apply_saddle(torch.tensor(x, device="cuda", dtype=torch.float64)).cpu().numpy()
+        assert _rel(y, K @ x) <= 1e-13
+
+
+def test_q1_chebyshev_block():
+    """The y block of P_D^-1 is 20 Chebyshev steps for (M + Theta_y) z = r on
+    [1/4, 9/4]: its error against the exact solve is at most
+    2 ((3 - 1) / (3 + 1))^20 in the energy norm (condition number 9)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    _, Options, Problem = _api()
+    data = CASES["q1_31"]()
+    disc, st = _generic_state(data)
+    mu = st.mu * data.sigma
+    ty, _, _ = barrier_diagonals(data, st)
+    B = (disc.Mt + sp.diags(ty)).tocsc()
+    r = np.random.default_rng(5).normal(size=data.n)
+    exact = spla.spsolve(B, r)
+    x = np.zeros(4 * data.n)
+    x[:data.n] = r
+    opts = Options(krylov="fgmres", precond="pd", mg_precision="fp64")
+    with Problem(data) as prob:
+        _load_state(prob, st, True)
+        prob.newton_setup(mu, opts)
+        z = prob.apply_precond(torch.tensor(x, device="cuda", dtype=torch.float64), opts).cpu().numpy()
+    e = z[:data.n] - exact
+    err = math.sqrt(e @ (B @ e)) / math.sqrt(exact @ (B @ exact))
+    print(f"  energy-norm error {err:.2e}", flush=True)
+    assert err <= 2 * 0.5 ** 20
+
+
+@pytest.mark.parametrize("precond,prec", [("pd", "fp64"), ("pd", "fp32"), ("pt", "fp32"), ("pt", "fp64")])
+@pytest.mark.parametrize("case", ["q1_31", "q1_63_hard"])
+def test_q1_newton_direction_parity(case, precond, prec):
+    _, Options, Problem = _api()
+    print(f"[q1 newton] {case} {precond} {prec}", flush=True)
+    data = CASES[case]()
+    disc, st = _generic_state(data, steps=3)
+    mu = st.mu * data.sigma
+    K = newton_matrix(data, disc, st)
+    b = newton_rhs(data, disc, st, mu)
+    ref = np.concatenate(newton_solve(data, disc, st, mu))
+    opts = Options(krylov="fgmres", precond=precond, mg_precision=prec)
+    with Problem(data) as prob:
+        _load_state(prob, st, data.y_a is not None)
+        info = prob.newton_direction(mu, opts)
+        d = np.concatenate([prob.query(f) for f in ("dy", "dw", "dv", "dp")])
+    res = np.linalg.norm(b - K @ d) / np.linalg.norm(b)
+    print(f"  its={info['krylov_its']} relres(gpu)={info['relres']:.2e} relres(oracle K)={res:.2e}", flush=True)
+    assert info["rc"] == 0
+    assert res <= 1e-9
+    assert _rel(d, ref) <= 1e-6
+
+
+@pytest.mark.parametrize("case,precond,prec", [("q1_31", "pt", "fp32"), ("q1_31", "pd", "fp64"),
+                                               ("q1_data_31", "pt", "fp32"), ("q1_nobounds_31", "pd", "fp32"),
+                                               ("q1_63", "pt", "fp32")])
+def test_q1_ipm_parity(case, precond, prec):
+    _, Options, Problem = _api()
+    print(f"[q1 ipm] {case} {precond} {prec}", flush=True)
+    data = CASES[case]()
+    ref = oracle.solve(data, IPMOptions(sigma=data.sigma))
+    with Problem(data) as prob:
+        rc = prob.solve(Options(sigma=data.sigma, krylov="fgmres", precond=precond, mg_precision=prec))
+        u, y, p = prob.query("u"), prob.query("y"), prob.query("p")
+        s = prob.stats()
+    print(f"  rc={rc} nli={s.nli}/{ref.nli} its={s.krylov_its} rel u={_rel(u, ref.u):.2e} y={_rel(y, ref.y):.2e}")
+    assert ref.status == "converged"
+    assert rc == 0 and s.nli == ref.nli
+    assert _rel(u, ref.u) <= 1e-6 and _rel(y, ref.y) <= 1e-6 and _rel(p, ref.p) <= 1e-6
+
+
+def test_q1_hard_instance_both_rules():
+    """Seed 1 at 63^2: under the fixed decrease the oracle and the GPU both
+    lose the interior at the same iteration (EBREAKDOWN, as for the
+    finite-difference instance of the barrier readings).  Under the
+    iterate-based rule the oracle converges in 42 iterations; the GPU follows
+    its history (barrier and measures) through iteration 36, after which the
+    Newton systems become too ill-conditioned for the geometric multigrid (the
+    known limit of the Schur approximation with a strongly varying M_hat)."""
+    _, Options, Problem = _api()
+    from paper_1806_05896_amd import _lib as L
+    data = CASES["q1_63_hard"]()
+    ref = oracle.solve(data, IPMOptions(sigma=data.sigma))
+    refc = oracle.solve(data, IPMOptions(sigma=data.sigma, mu_rule="central"))
+    assert ref.status == "breakdown" and refc.status == "converged"
+    with Problem(data) as prob:
+        rc = prob.solve(Options(sigma=data.sigma, krylov="fgmres", precond="pt", mg_precision="fp32"))
+        assert rc == L.EBREAKDOWN and prob.stats().nli == ref.nli
+    with Problem(data) as prob:
+        prob.solve(Options(sigma=data.sigma, krylov="fgmres", precond="pt", mg_precision="fp32", mu_rule="central",
+                           ipm_maxit=40))
+        s = prob.stats()
+    for k in range(37):
+        h = refc.history[k]
+        got = (s.hist_mu[k], s.hist_xi_p[k], s.hist_xi_d[k], s.hist_xi_c[k])
+        np.testing.assert_allclose(got, (h["mu"], h["xi_p"], h["xi_d"], h["xi_c"]), rtol=2e-2, err_msg=str(k))
+
+
+def test_q1_batch_equals_solo():
+    Batch, Options, Problem = _api()
+    datas = [W.poisson2d_q1(seed=0, N=31), W.poisson2d_q1(seed=0, N=63)]
+    opts = Options(sigma=0.2, krylov="fgmres", precond="pt", mg_precision="fp32")
+    solo = []
+    for d in datas:
+        with Problem(d) as p:
+            assert p.solve(opts) == 0
+            solo.append((p.query("u"), p.stats()))
+    probs = [Problem(d) for d in datas]
+    try:
+        Batch(probs).solve(opts)
+        for p, (u, st) in zip(probs, solo):
+            s = p.stats()
+            assert s.status == 0 and s.nli == st.nli and s.krylov_its == st.krylov_its
+            np.testing.assert_array_equal(p.query("u"), u)
+    finally:
+        for p in probs:
+            p.close()
+
+
+def test_q1_refusals():
+    Batch, Options, Problem = _api()
+    data = CASES["q1_31"]()
+    with Problem(data) as prob, Problem(W.poisson2d_small(N=15)) as fd:
+        for o in (Options(krylov="minres", precond="pd"), Options(krylov="fgmres", precond="ppi")):
+            with pytest.raises(Exception):
+                prob.solve(o, raise_on_error=True)
+        with pytest.raises(Exception):
+            prob.set_observation(np.ones(data.n))
+        with pytest.raises(Exception):
+            Batch([prob, fd])
