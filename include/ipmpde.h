@@ -159,8 +159,8 @@ int ipmpde_set_allocator(ipmpde_alloc_fn alloc, ipmpde_free_fn free_, void* ctx)
  *   minimize 1/2 (y - y_d)^T M (y - y_d) + alpha/2 u^T M u + beta |u|_1
  *   s.t. L y - M u = f_hat,  f_hat = M f - L_IB g,
  * with L = (8, -1 x 8) / (3 h^2) and M = (16, 4 x 4, 1 x 4) / 36 as nine-point
- * stencils.  Solved with FGMRES and P_D or P_T only (IPMPDE_EINVAL otherwise
- * at solve): (M + Theta_y)^-1 by 20 steps of Chebyshev semi-iteration with
+ * stencils.  MINRES + P_D, FGMRES + P_D or P_T (P_Pi: IPMPDE_EINVAL at
+ * solve): (M + Theta_y)^-1 by 20 steps of Chebyshev semi-iteration with
  * D_M + Theta_y, alpha M~ + Theta_z by alpha D~_M + Theta_z, M_hat with D_M
  * (Sec. 4.1, 4.2), multigrid on L + M_hat.  No observation weights; batched
  * only with other Q1 problems; not admitted to an engine. */

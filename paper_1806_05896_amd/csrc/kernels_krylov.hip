@@ -206,19 +206,22 @@ __global__ void __launch_bounds__(kBS) k_precond_diag(const Inst* __restrict__ D
 //   x_{k+1} = x_k + d_k,  rho_0 = delta / theta, rho_k = 1 / (2 theta / delta - rho_{k-1}).
 // Step k of the recurrence (k = 0 starts it): the residual rk and the
 // direction buffers d[2] (d_{k-1} read from d[(k+1)&1], d_k written to
-// d[k&1]) are n-vectors of the workspace.
+// d[k&1]) are n-vectors of the q workspace (free outside the MINRES matvec).
+// Operands: MINRES (mpar >= 0) the Lanczos vector v = V[1-mpar] and its
+// image Z[1-mpar]; otherwise rx, zx or the FGMRES slots V_j, Z_j.  guard 1:
+// skip a stopped solve; 2: skip an instance without a pending cycle.
 __global__ void __launch_bounds__(kBS) k_cheb_step(const Inst* __restrict__ Dp, const double* __restrict__ rx, double* __restrict__ zx,
-                                                   int j, int k, double rho, double rho_prev, double theta,
+                                                   int j, int mpar, int k, double rho, double rho_prev, double theta,
                                                    double delta, int guard) {
   INST_BEGIN
-  if (guard && I.ctrl->stop) return;
+  if ((guard == 1 && I.ctrl->stop) || (guard == 2 && !I.ctrl->want_restart)) return;
   const int i = blockIdx.x * kBS + threadIdx.x;
   if (i >= I.n) return;
   const int n = I.n;
-  const double* r = rx ? rx : I.fV + (size_t)j * 4 * n;
-  double* z = zx ? zx : I.fZ + (size_t)j * 4 * n;
-  double* rk = I.W[0];
-  double* dd[2] = {I.W[0] + n, I.W[0] + 2 * n};
+  const double* r = mpar >= 0 ? I.V[1 - mpar] : (rx ? rx : I.fV + (size_t)j * 4 * n);
+  double* z = mpar >= 0 ? I.Z[1 - mpar] : (zx ? zx : I.fZ + (size_t)j * 4 * n);
+  double* rk = I.Q;
+  double* dd[2] = {I.Q + n, I.Q + 2 * n};
   const double dinv = 1.0 / (kQ1MassDiag + I.ty[i]);
   if (k == 0) {
     const double d0 = r[i] * dinv / theta;
@@ -345,7 +348,9 @@ __global__ void __launch_bounds__(kBS) k_minres_init(const Inst* __restrict__ Dp
     double* V1 = I.V[1];
     double* Z1 = I.Z[1];
     V1[i] = ry; V1[n + i] = rw; V1[2 * n + i] = rv; V1[3 * n + i] = rp;
-    Z1[i] = zy; Z1[n + i] = zw; Z1[2 * n + i] = zv;
+    const bool q1 = I.pde == 3;  // Q1: z_y from k_cheb_step, its part of <v, z> in K4
+    if (!q1) Z1[i] = zy;
+    Z1[n + i] = zw; Z1[2 * n + i] = zv;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int q = k * n + i;
@@ -353,7 +358,7 @@ __global__ void __launch_bounds__(kBS) k_minres_init(const Inst* __restrict__ Dp
       I.Rt[q] = r[q];
     }
     ((T*)I.lv[0].b)[i] = (T)rp;
-    acc[0] = ry * zy + rw * zw + rv * zv;
+    acc[0] = (q1 ? 0.0 : ry * zy) + rw * zw + rv * zv;
   }
   if (grid_reduce<kSum, 1, kBS>(acc, I.partials, I.counter, gridDim.x, blockIdx.x, smem) && threadIdx.x == 0)
     I.ctrl->dot_tmp = acc[0];
@@ -439,9 +444,11 @@ __global__ void __launch_bounds__(kBS) k_minres_k2(const Inst* __restrict__ Dp, 
     }
     double zy, zw, zv;
     apply_A11_inv(I, i, v[0], v[1], v[2], zy, zw, zv);
-    Zn[i] = zy; Zn[n + i] = zw; Zn[2 * n + i] = zv;
+    const bool q1 = I.pde == 3;  // Q1: z_y from k_cheb_step, its part of <v, z> in K4
+    if (!q1) Zn[i] = zy;
+    Zn[n + i] = zw; Zn[2 * n + i] = zv;
     ((T*)I.lv[0].b)[i] = (T)v[3];
-    acc[0] = v[0] * zy + v[1] * zw + v[2] * zv;
+    acc[0] = (q1 ? 0.0 : v[0] * zy) + v[1] * zw + v[2] * zv;
   }
   if (grid_reduce<kSum, 2, kBS>(acc, I.partials, I.counter, gridDim.x, blockIdx.x, smem) && threadIdx.x == 0) {
     C->dot_tmp = acc[0];
@@ -473,6 +480,7 @@ __global__ void __launch_bounds__(kBS) k_minres_k4(const Inst* __restrict__ Dp, 
     const double z = (double)xmg[i];
     Zn[3 * n + i] = z;
     acc[0] = Vn[3 * n + i] * z;
+    if (I.pde == 3) acc[0] += Vn[i] * Zn[i];
   }
   if (!grid_reduce<kSum, 1, kBS>(acc, I.partials, I.counter, gridDim.x, blockIdx.x, smem) || threadIdx.x != 0) return;
   const double dot = C->dot_tmp + acc[0];

@@ -915,10 +915,30 @@ static void schur_inv(Group* G, int guard, hipStream_t s) {
 // it as converged when the requested tolerance lies below that floor.
 static double floor_factor() { return 16.0 * 2.220446049250313e-16; }
 
+// Chebyshev steps for the Q1 mass block (the paper's 20).
+static constexpr int kChebSteps = 20;
+
+// z_y = (M + Theta_y)^-1 r_y for every Q1 instance by Chebyshev
+// semi-iteration (Sec. 4.1) on the spectrum [1/4, 9/4] of the diagonally
+// scaled Q1 mass; operands as k_cheb_step takes them.
+static void cheb_apply(Group* G, const double* x, double* y, int j, int mpar, int guard, hipStream_t s) {
+  const double theta = 1.25, delta = 1.0;
+  double rho_prev = delta / theta, rho = rho_prev;
+  for (int k = 0; k < kChebSteps; ++k) {
+    if (k > 0) {
+      rho_prev = rho;
+      rho = 1.0 / (2.0 * theta / delta - rho_prev);
+    }
+    hipLaunchKernelGGL(k_cheb_step, gz(G, G->max_n), dim3(kBS), 0, s, G->D, x, y, j, mpar, k, rho, rho_prev, theta,
+                       delta, guard);
+  }
+}
+
 template <typename T>
 static void minres_iteration(Group* G, int par, int maxit, double tol, hipStream_t s) {
   hipLaunchKernelGGL(k_minres_k1, gz(G, G->max_n), dim3(kBS), 0, s, G->D, par, 0);
   hipLaunchKernelGGL(k_minres_k2<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, par, 0);
+  if (G->q1) cheb_apply(G, nullptr, nullptr, 0, par, 1, s);
   schur_inv<T>(G, 1, s);
   hipLaunchKernelGGL(k_minres_k4<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, 1 - par, 1, tol, maxit, G->outsel);
 }
@@ -972,6 +992,7 @@ static int minres_group(Group* G, const ipmpde_options& o, hipStream_t s) {
   hipLaunchKernelGGL(k_krylov_begin, gz(G, 4L * G->max_n), dim3(kBS), 0, s, G->D);
   for (int cycle = 0; cycle < 16; ++cycle) {
     hipLaunchKernelGGL(k_minres_init<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, cycle == 0 ? 0 : 1);
+    if (G->q1) cheb_apply(G, nullptr, nullptr, 0, 0, 2, s);
     schur_inv<T>(G, 2, s);
     hipLaunchKernelGGL(k_minres_k4<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, 1, 0, tol, o.krylov_maxit, G->outsel);
     HIP_TRY(hipGetLastError());
@@ -995,9 +1016,6 @@ static void mg_select(Group* G, int slot, hipStream_t s) {
   hipLaunchKernelGGL(k_mg_select, dim3(1, 1, G->zc), dim3(64), 0, s, G->D, slot);
 }
 
-// Chebyshev steps for the Q1 mass block (the paper's 20).
-static constexpr int kChebSteps = 20;
-
 // z = P^-1 r for every instance (pt: IPMPDE_PD, IPMPDE_PT or IPMPDE_PPI);
 // explicit operands, or the FGMRES slots r = V_j, z = Z_j when null.
 template <typename T>
@@ -1018,19 +1036,7 @@ static void precond_apply(Group* G, int pt, const double* x, double* y, int j, i
     return;
   }
   hipLaunchKernelGGL(k_precond_diag<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, x, y, j, pt, guard);
-  if (G->q1) {
-    // (M + Theta_y)^-1 by Chebyshev semi-iteration (Sec. 4.1 and Sec. 5: 20 steps), spectrum [1/4, 9/4]
-    const double theta = 1.25, delta = 1.0;
-    double rho_prev = delta / theta, rho = rho_prev;
-    for (int k = 0; k < kChebSteps; ++k) {
-      if (k > 0) {
-        rho_prev = rho;
-        rho = 1.0 / (2.0 * theta / delta - rho_prev);
-      }
-      hipLaunchKernelGGL(k_cheb_step, gz(G, G->max_n), dim3(kBS), 0, s, G->D, x, y, j, k, rho, rho_prev, theta, delta,
-                         guard);
-    }
-  }
+  if (G->q1) cheb_apply(G, x, y, j, -1, guard, s);
   if (pt) hipLaunchKernelGGL(k_pt_rhs<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, x, (const double*)y, j, guard);
   schur_inv<T>(G, guard, s);
   hipLaunchKernelGGL(k_store_p<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, y, j, G->outsel, guard);
@@ -1132,8 +1138,7 @@ static void heat_setup(Group* G, hipStream_t s) {
 static int newton_setup_group(Group* G, const ipmpde_options& o, hipStream_t s) {
   if (G->heat && o.precond == IPMPDE_PPI)
     return fail(IPMPDE_EINVAL, "P_Pi is not available for the heat equation");
-  if (G->q1 && (o.krylov != IPMPDE_FGMRES || o.precond == IPMPDE_PPI))
-    return fail(IPMPDE_EINVAL, "Q1 problems are solved with FGMRES and P_D or P_T");
+  if (G->q1 && o.precond == IPMPDE_PPI) return fail(IPMPDE_EINVAL, "P_Pi is not available for Q1 problems");
   for (int i = 0; i < G->count; ++i) {
     const ipmpde_problem* P = G->probs[i];
     if (o.precond != IPMPDE_PPI && P->obs_zero && !P->has_y)
