@@ -174,6 +174,32 @@ def bench_heat(W, torch, N, nt, reps):
     return out
 
 
+def bench_q1(W, torch, N, reps):
+    """The 511^2 Poisson workload with Q1 finite elements (the paper's own
+    discretization), one instance: MINRES + P_D and FGMRES(30) + P_T, FP32
+    V-cycles, 20 Chebyshev steps for the mass block."""
+    from paper_1806_05896_amd import Options, Problem
+    d = W.poisson2d_q1(seed=0, N=N)
+    stream = torch.cuda.current_stream()
+    out = {"workload": f"poisson2d_q1: 2D Poisson {N}x{N}, Q1 elements, alpha=1e-4, beta=1e-3, u in [-5,5], "
+                       "y in [-0.2,0.3], sigma=0.2"}
+    with Problem(d) as p:
+        for name, kry, pre in (("minres_pd", "minres", "pd"), ("fgmres_pt", "fgmres", "pt")):
+            o = Options(sigma=d.sigma, krylov=kry, precond=pre, mg_precision="fp32")
+            p.solve(o, stream=stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                rc = p.solve(o, stream=stream)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / reps
+            s = p.stats()
+            log(f"q1 {N}^2 {name}: {1 / t:.2f} solves/s, nli {s.nli}, its {s.krylov_its}")
+            out[name] = {"solves_per_s": 1 / t, "ms_per_solve": t * 1e3, "nli": s.nli,
+                         "krylov_its_per_solve": s.krylov_its, "krylov_its_per_s": s.krylov_its / t, "status": rc}
+    return out
+
+
 def bench_heat_batch(W, torch, N, nt, B, reps):
     """B heat instances (seeds 0..B-1) solved as one batch: the substitution
     kernel runs one workgroup per instance, every other launch serves all."""
@@ -336,7 +362,8 @@ def main():
     ap.add_argument("--heat-N", type=int, default=63, help="grid of the heat-equation run (0: skip)")
     ap.add_argument("--heat-nt", type=int, default=100, help="time steps of the heat-equation run")
     ap.add_argument("--heat-batch", type=int, default=16, help="instances of the batched heat run (0: skip)")
-    ap.add_argument("--only", choices=["serve", "batch", "partial", "heat"], default=None,
+    ap.add_argument("--q1-N", type=int, default=511, help="grid of the Q1 finite-element run (0: skip)")
+    ap.add_argument("--only", choices=["serve", "batch", "partial", "heat", "q1"], default=None,
                     help="run one extra section alone")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only launch the roofline kernel (20 times) and a 1 GiB device copy, for counter runs")
@@ -363,6 +390,9 @@ def main():
         return
     if args.only == "partial":
         print(json.dumps({"partial_observation": bench_partial(W, torch, args.partial_N, 3)}), flush=True)
+        return
+    if args.only == "q1":
+        print(json.dumps({"q1": bench_q1(W, torch, args.q1_N, 3)}), flush=True)
         return
     if args.only == "heat":
         out = bench_heat(W, torch, args.heat_N, args.heat_nt, 3)
@@ -486,6 +516,8 @@ def main():
 
     if args.partial_N > 0:
         result["partial_observation"] = bench_partial(W, torch, args.partial_N, 2)
+    if args.q1_N > 0:
+        result["q1"] = bench_q1(W, torch, args.q1_N, 2)
     if args.heat_N > 0:
         result["heat"] = bench_heat(W, torch, args.heat_N, args.heat_nt, 2)
         if args.heat_batch > 0:

@@ -116,6 +116,7 @@ def test_ipm_step_parity_at_511():
     ("heat2d", {}),
     ("poisson2d_q1", {"krylov": "fgmres", "precond": "pt"}),
     ("poisson2d_q1", {"krylov": "fgmres", "precond": "pd"}),
+    ("poisson2d_q1", {}),
 ])
 def test_newton_direction_solves_oracle_system(name, opts_kw):
     """At the full sizes, from a mid-solve GPU state: the GPU Newton direction
