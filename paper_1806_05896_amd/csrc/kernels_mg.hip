@@ -380,7 +380,9 @@ __global__ void __launch_bounds__(kBS) k_coarse_pack(const Inst* __restrict__ Dp
     if (r >= 0) {
       const Level& Lv = I.lv[cl + l];
       const int i = r < n ? r : r - n;
-      const T dv = (T)4 * (T)(1.0 / (Lv.h * Lv.h)) + ((const T*)Lv.mh)[i];
+      // the operator's diagonal: 4/h^2 (five-point) or 8/(3 h^2) (Q1), plus the reaction term
+      const T dv = (I.coarse_p2 == 2 ? (T)(8.0 / (3.0 * Lv.h * Lv.h)) : (T)4 * (T)(1.0 / (Lv.h * Lv.h))) +
+                   ((const T*)Lv.mh)[i];
       v = r < n ? dv : (T)1 / dv;
     }
   }
@@ -399,13 +401,27 @@ template __global__ void k_coarse_pack<double>(const Inst*);
       const int p = (i1 + 1) + ((NN) + 2) * (i2 + 1);                                \
       (void)i; (void)p;
 
+// Off-diagonal part of the level operator at padded node p, with the sign
+// flipped: (sum of the four neighbours) / h^2 for the five-point stencil
+// (ST = 5), (sum of the eight neighbours) / (3 h^2) for the Q1 stiffness
+// (ST = 9); ihs is 1/h^2 or 1/(3 h^2).
+template <typename T, int ST>
+__device__ __forceinline__ T p2_nb(const T* __restrict__ a, int p, int P, T ihs) {
+  if constexpr (ST == 5) {
+    return ihs * (a[p - 1] + a[p + 1] + a[p - P] + a[p + P]);
+  } else {
+    return ihs * ((a[p - 1] + a[p + 1] + a[p - P] + a[p + P]) +
+                  (a[p - P - 1] + a[p - P + 1] + a[p + P - 1] + a[p + P + 1]));
+  }
+}
+
 // Descent at level l: nu_pre damped-Jacobi sweeps from zero, the residual and
 // its full-weighting restriction to level l + 1's right-hand side.
-template <typename T, int NT>
+template <typename T, int NT, int ST = 5>
 __device__ __forceinline__ void p2_down(int nu_pre, T* lds, const int* LN, const int* LOFF, const T* LIH2, int l,
                                         int tid, T om, unsigned& alt) {
   const int N = LN[l], P = N + 2, n = N * N;
-  const T ih2 = LIH2[l];
+  const T ih2 = ST == 5 ? LIH2[l] : LIH2[l] * (T)(1.0 / 3.0);
   T* a = lds + LOFF[l];
   T* c = a + P * P;
   const T* b = c + P * P;
@@ -415,13 +431,13 @@ __device__ __forceinline__ void p2_down(int nu_pre, T* lds, const int* LN, const
     if (s == 0) {
       P2_FOR_T(N, tid, NT) c[p] = om * b[i] * dinv[i]; P2_END
     } else {
-      P2_FOR_T(N, tid, NT) c[p] = a[p] + om * (b[i] - d[i] * a[p] + ih2 * (a[p - 1] + a[p + 1] + a[p - P] + a[p + P])) * dinv[i]; P2_END
+      P2_FOR_T(N, tid, NT) c[p] = a[p] + om * (b[i] - d[i] * a[p] + p2_nb<T, ST>(a, p, P, ih2)) * dinv[i]; P2_END
     }
     __syncthreads();
     T* t = a; a = c; c = t;
     alt ^= 1u << l;
   }
-  P2_FOR_T(N, tid, NT) c[p] = b[i] - d[i] * a[p] + ih2 * (a[p - 1] + a[p + 1] + a[p - P] + a[p + P]); P2_END
+  P2_FOR_T(N, tid, NT) c[p] = b[i] - d[i] * a[p] + p2_nb<T, ST>(a, p, P, ih2); P2_END
   __syncthreads();
   const int Nc = LN[l + 1];
   T* bc = lds + LOFF[l + 1] + 2 * (Nc + 2) * (Nc + 2);
@@ -440,12 +456,12 @@ __device__ __forceinline__ void p2_down(int nu_pre, T* lds, const int* LN, const
 
 // Ascent at level l: bilinear prolongation of level l + 1's iterate (in xb
 // when bit l + 1 of alt is set) added to the iterate, nu_post sweeps.
-template <typename T, int NT>
+template <typename T, int NT, int ST = 5>
 __device__ __forceinline__ void p2_up(int nu_post, T* lds, const int* LN, const int* LOFF, const T* LIH2, int l,
                                       int tid, T om, unsigned& alt) {
   const int N = LN[l], P = N + 2, n = N * N;
   const int Nc = LN[l + 1], Pc = Nc + 2;
-  const T ih2 = LIH2[l];
+  const T ih2 = ST == 5 ? LIH2[l] : LIH2[l] * (T)(1.0 / 3.0);
   T* base = lds + LOFF[l];
   const int ca = (alt >> l) & 1u;
   T* a = base + ca * P * P;
@@ -464,7 +480,7 @@ __device__ __forceinline__ void p2_up(int nu_post, T* lds, const int* LN, const 
   P2_END
   __syncthreads();
   for (int s = 0; s < nu_post; ++s) {
-    P2_FOR_T(N, tid, NT) c[p] = a[p] + om * (b[i] - d[i] * a[p] + ih2 * (a[p - 1] + a[p + 1] + a[p - P] + a[p + P])) * dinv[i]; P2_END
+    P2_FOR_T(N, tid, NT) c[p] = a[p] + om * (b[i] - d[i] * a[p] + p2_nb<T, ST>(a, p, P, ih2)) * dinv[i]; P2_END
     __syncthreads();
     T* t = a; a = c; c = t;
     alt ^= 1u << l;
@@ -476,12 +492,12 @@ __device__ __forceinline__ void p2_up(int nu_post, T* lds, const int* LN, const 
 // residual and restriction down to the single-node grid, its exact solve,
 // prolongation and post-smoothing back up.  Returns the top level's final
 // iterate (padded layout) in LDS.
-template <typename T>
+template <typename T, int ST = 5>
 __device__ __forceinline__ const T* coarse_p2_cycle(T* lds, const int* LN, const int* LOFF, const T* LIH2, int cl,
                                                     int L, T om, int nu_pre, int nu_post) {
   const int tid = threadIdx.x;
   unsigned alt = 0;  // bit l: level l's iterate sits in xb
-  for (int l = cl; l < L - 1; ++l) p2_down<T, kCoarseBS>(nu_pre, lds, LN, LOFF, LIH2, l, tid, om, alt);
+  for (int l = cl; l < L - 1; ++l) p2_down<T, kCoarseBS, ST>(nu_pre, lds, LN, LOFF, LIH2, l, tid, om, alt);
   {
     // coarsest grid (one node): exact solve
     const int l = L - 1, N = LN[l], P = N + 2, n = N * N;
@@ -491,7 +507,7 @@ __device__ __forceinline__ const T* coarse_p2_cycle(T* lds, const int* LN, const
     P2_FOR_T(N, tid, kCoarseBS) a[p] = b[i] * dinv[i]; P2_END
     __syncthreads();
   }
-  for (int l = L - 2; l >= cl; --l) p2_up<T, kCoarseBS>(nu_post, lds, LN, LOFF, LIH2, l, tid, om, alt);
+  for (int l = L - 2; l >= cl; --l) p2_up<T, kCoarseBS, ST>(nu_post, lds, LN, LOFF, LIH2, l, tid, om, alt);
   const int N = LN[cl], P = N + 2;
   return lds + LOFF[cl] + ((alt >> cl) & 1u) * P * P;
 }
@@ -551,7 +567,9 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_p2(const Inst* __restri
     }
   }
   __syncthreads();
-  const T* a = coarse_p2_cycle<T>(lds, LN, LOFF, LIH2, cl, L, (T)I.omega, I.nu_pre, I.nu_post);
+  // coarse_p2 2: the Q1 nine-point stiffness
+  const T* a = I.coarse_p2 == 2 ? coarse_p2_cycle<T, 9>(lds, LN, LOFF, LIH2, cl, L, (T)I.omega, I.nu_pre, I.nu_post)
+                                : coarse_p2_cycle<T, 5>(lds, LN, LOFF, LIH2, cl, L, (T)I.omega, I.nu_pre, I.nu_post);
   {
     const int N = LN[cl];
     T* xg = (T*)I.lv[cl].x;

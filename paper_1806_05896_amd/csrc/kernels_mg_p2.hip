@@ -54,7 +54,7 @@ __device__ __forceinline__ float omega_over<float>(float om, float d) { return o
 template <typename T, int NU, int TC>
 __global__ void __launch_bounds__(kBS) k_mg_down_p2(const Inst* __restrict__ Dp, int l, int scaled, int guard) {
   INST_BEGIN
-  if (!I.coarse_p2 || l >= I.coarse_lev || mg_skip(I, guard)) return;
+  if (I.coarse_p2 != 1 || l >= I.coarse_lev || mg_skip(I, guard)) return;
   const Level& F = I.lv[l];
   const Level& C = I.lv[l + 1];
   const int N = F.N, Nc = C.N;
@@ -145,7 +145,7 @@ __global__ void __launch_bounds__(kBS) k_mg_down_p2(const Inst* __restrict__ Dp,
 template <typename T, int NU, int TF>
 __global__ void __launch_bounds__(kBS) k_mg_up_p2(const Inst* __restrict__ Dp, int l, int guard) {
   INST_BEGIN
-  if (!I.coarse_p2 || l >= I.coarse_lev || mg_skip(I, guard)) return;
+  if (I.coarse_p2 != 1 || l >= I.coarse_lev || mg_skip(I, guard)) return;
   const Level& F = I.lv[l];
   const int N = F.N, Nc = I.lv[l + 1].N;
   int tx, ty;

@@ -252,6 +252,8 @@ static int set_coarse_lds_limit() {
 }
 
 static bool is_p2(const ipmpde_problem* P) { return P->dim == 2 && P->pde == IPMPDE_POISSON; }
+// The padded single-workgroup coarse kernel: 2D Poisson (five-point) and Q1 (nine-point).
+static bool padded_coarse(const ipmpde_problem* P) { return is_p2(P) || P->pde == IPMPDE_POISSON_Q1; }
 
 // Reaction-term slots of every multigrid level (see k_mg_select): the
 // Schur-approximation operator's, and the two extra operators of P_Pi.
@@ -321,9 +323,9 @@ static int ensure_mg(ipmpde_problem* P, bool fp32) {
     N = (N - 1) / 2;
   }
   for (void*& a : (fp32 ? P->kc32 : P->kc64)) TRY(P->work.alloc(&a, (size_t)lv[0].n * el));
-  const int cl = pick_coarse(lv, P->nlev, el, P->dim, is_p2(P));
+  const int cl = pick_coarse(lv, P->nlev, el, P->dim, padded_coarse(P));
   (fp32 ? P->coarse32 : P->coarse64) = cl;
-  if (is_p2(P)) {
+  if (padded_coarse(P)) {
     int elems = 0;
     for (int l = cl; l < P->nlev; ++l) elems += coarse_p2_elems(lv[l].N);
     void*& pk = fp32 ? P->cpack32 : P->cpack64;
@@ -568,7 +570,7 @@ static int group_select(Group* G, const ipmpde_options& o) {
       G->maxN[l] = std::max(G->maxN[l], lv[l].N);
       G->maxn[l] = std::max(G->maxn[l], (long)lv[l].n);
     }
-    d.coarse_p2 = is_p2(P) ? 1 : 0;
+    d.coarse_p2 = is_p2(P) ? 1 : (padded_coarse(P) ? 2 : 0);
     d.cpack = fp32 ? P->cpack32 : P->cpack64;
     d.cpackb = d.cpack;
     d.cpack_slot = fp32 ? P->cpack_elems32 : P->cpack_elems64;
@@ -580,9 +582,9 @@ static int group_select(Group* G, const ipmpde_options& o) {
     d.kc_s[1] = kc[2];
     d.cpack_elems = fp32 ? P->cpack_elems32 : P->cpack_elems64;
     G->max_cpack = std::max(G->max_cpack, d.cpack_elems);
-    G->p2 = G->p2 || is_p2(P);
-    G->gen = G->gen || !is_p2(P);
-    G->coarse_lds = std::max(G->coarse_lds, coarse_lds_bytes(lv, P->nlev, d.coarse_lev, fp32 ? 4 : 8, is_p2(P)));
+    G->p2 = G->p2 || padded_coarse(P);
+    G->gen = G->gen || !padded_coarse(P);
+    G->coarse_lds = std::max(G->coarse_lds, coarse_lds_bytes(lv, P->nlev, d.coarse_lev, fp32 ? 4 : 8, padded_coarse(P)));
   }
   if (G->heat)
     for (int i = 0; i < G->count; ++i) {
@@ -1396,7 +1398,7 @@ extern "C" size_t ipmpde_footprint_bytes(const ipmpde_grid* grid, const ipmpde_p
   }
   bytes += 3 * A(n * el);  // k-cycle level-0 arrays
   bytes += A(kMaxLev * sizeof(Level));
-  if (grid->dim == 2 && pde->kind == IPMPDE_POISSON) {  // the coarse levels' LDS image
+  if (grid->dim == 2 && (pde->kind == IPMPDE_POISSON || pde->kind == IPMPDE_POISSON_Q1)) {  // coarse LDS image
     Level lv[kMaxLev];
     int nlev = 0;
     for (int N = grid->n;; N = (N - 1) / 2) {
