@@ -1,11 +1,14 @@
-// Fused V-cycle level kernels for 2D Poisson (constant 5-point stencil), the
-// multigrid of S_hat^-1 (Sec. 4.2) for the Poisson problems.
+// Fused V-cycle level kernels for 2D Poisson (constant 5-point stencil, ST =
+// 5, or the Q1 nine-point stiffness divided by h^2, ST = 9), the multigrid of
+// S_hat^-1 (Sec. 4.2) for the Poisson problems.
 //
-// Per node the kernels stage in LDS the diagonal d = 4/h^2 + m of A + M_hat
-// (m = the level's M_hat entry; the descent, which also needs d for the
-// residual) or w = omega / d (the ascent), so a damped-Jacobi sweep is
-//   x <- (1 - omega) x + w (b + h^-2 (sum of the four neighbours)),
-// and the residual is b + h^-2 (sum of the neighbours) - d x.  Nodes of the
+// Per node the kernels stage in LDS the diagonal d = 4/h^2 + m (ST = 5) or
+// 8/(3 h^2) + m (ST = 9) of A + M_hat (m = the level's M_hat entry; the
+// descent, which also needs d for the residual) or w = omega / d (the
+// ascent), so a damped-Jacobi sweep is
+//   x <- (1 - omega) x + w (b + s (sum of the neighbours)),
+// s = 1/h^2 over the four neighbours or 1/(3 h^2) over the eight, and the
+// residual is b + s (sum of the neighbours) - d x.  Nodes of the
 // LDS region outside the grid hold b = d = w = x = 0, which keeps the
 // homogeneous Dirichlet condition with no tests in the sweeps.  The tile size
 // is a template parameter (a launch choice); it changes no node's arithmetic,
@@ -39,6 +42,22 @@ __device__ __forceinline__ void xcd_tile(int& tx, int& ty) {
   tx = t - ty * nx;
 }
 
+// Neighbour sum of LDS node li (row pitch W) scaled by s, for stencil ST.
+template <typename T, int ST>
+__device__ __forceinline__ T p2l_nb(const T* __restrict__ a, int li, int W, T s) {
+  if constexpr (ST == 5) {
+    return s * ((a[li - 1] + a[li + 1]) + (a[li - W] + a[li + W]));
+  } else {
+    return s * (((a[li - 1] + a[li + 1]) + (a[li - W] + a[li + W])) +
+                ((a[li - W - 1] + a[li - W + 1]) + (a[li + W - 1] + a[li + W + 1])));
+  }
+}
+// The stencil's diagonal and neighbour scale at mesh width h.
+template <typename T, int ST>
+__device__ __forceinline__ T p2l_diag(double h) { return ST == 5 ? (T)4 * (T)(1.0 / (h * h)) : (T)(8.0 / (3.0 * h * h)); }
+template <typename T, int ST>
+__device__ __forceinline__ T p2l_scale(double h) { return ST == 5 ? (T)(1.0 / (h * h)) : (T)(1.0 / (3.0 * h * h)); }
+
 // omega / d in the multigrid type (a hardware reciprocal in FP32).
 template <typename T>
 __device__ __forceinline__ T omega_over(T om, T d) { return om / d; }
@@ -51,10 +70,10 @@ __device__ __forceinline__ float omega_over<float>(float om, float d) { return o
 // scaled (level 0 only): the right-hand side is (1 + Theta_y) times level 0's
 // x2 (the first solve's output); it is also stored as level 0's b for the
 // ascent.
-template <typename T, int NU, int TC>
+template <typename T, int NU, int TC, int ST = 5>
 __global__ void __launch_bounds__(kBS) k_mg_down_p2(const Inst* __restrict__ Dp, int l, int scaled, int guard) {
   INST_BEGIN
-  if (I.coarse_p2 != 1 || l >= I.coarse_lev || mg_skip(I, guard)) return;
+  if (I.coarse_p2 != (ST == 5 ? 1 : 2) || l >= I.coarse_lev || mg_skip(I, guard)) return;
   const Level& F = I.lv[l];
   const Level& C = I.lv[l + 1];
   const int N = F.N, Nc = C.N;
@@ -68,7 +87,7 @@ __global__ void __launch_bounds__(kBS) k_mg_down_p2(const Inst* __restrict__ Dp,
   const T* __restrict__ bsrc = (const T*)(scaled ? F.x2 : F.b);
   const double* __restrict__ tyv = scaled ? I.ty : nullptr;
   const T* __restrict__ mh = (const T*)F.mh;
-  const T ih2 = (T)(1.0 / (F.h * F.h));
+  const T ih2 = p2l_scale<T, ST>(F.h), dg = p2l_diag<T, ST>(F.h);
   const T om = (T)I.omega, om1 = (T)1 - om;
   const int tid = threadIdx.x;
   for (int k = tid; k < W * W; k += kBS) {
@@ -79,7 +98,7 @@ __global__ void __launch_bounds__(kBS) k_mg_down_p2(const Inst* __restrict__ Dp,
       const int gi = g1 + N * g2;
       bv = bsrc[gi];
       if (tyv) bv = (T)(obs_w(I, gi) + tyv[gi]) * bv;
-      dv = (T)4 * ih2 + mh[gi];
+      dv = dg + mh[gi];
       wv = omega_over<T>(om, dv);
     }
     bs[k] = bv;
@@ -105,7 +124,7 @@ __global__ void __launch_bounds__(kBS) k_mg_down_p2(const Inst* __restrict__ Dp,
       const int li = (r1 + s) + W * (r2 + s);
       const T d = ds[li];
       const T wv = d > (T)0 ? omega_over<T>(om, d) : (T)0;
-      c[li] = om1 * a[li] + wv * (bs[li] + ih2 * ((a[li - 1] + a[li + 1]) + (a[li - W] + a[li + W])));
+      c[li] = om1 * a[li] + wv * (bs[li] + p2l_nb<T, ST>(a, li, W, ih2));
     }
     __syncthreads();
     T* t = a; a = c; c = t;
@@ -123,7 +142,7 @@ __global__ void __launch_bounds__(kBS) k_mg_down_p2(const Inst* __restrict__ Dp,
     for (int k = tid; k < w * w; k += kBS) {
       const int r2 = k / w, r1 = k - r2 * w;
       const int li = (r1 + NU) + W * (r2 + NU);
-      c[li] = bs[li] + ih2 * ((a[li - 1] + a[li + 1]) + (a[li - W] + a[li + W])) - ds[li] * a[li];
+      c[li] = bs[li] + p2l_nb<T, ST>(a, li, W, ih2) - ds[li] * a[li];
     }
   }
   __syncthreads();
@@ -142,10 +161,10 @@ __global__ void __launch_bounds__(kBS) k_mg_down_p2(const Inst* __restrict__ Dp,
 // Ascent at level l for a tile of TF x TF fine nodes: x = x_pre + P x_c
 // (bilinear prolongation from a coarse patch staged in LDS), then NU sweeps;
 // writes the tile's own nodes to level l's x2.
-template <typename T, int NU, int TF>
+template <typename T, int NU, int TF, int ST = 5>
 __global__ void __launch_bounds__(kBS) k_mg_up_p2(const Inst* __restrict__ Dp, int l, int guard) {
   INST_BEGIN
-  if (I.coarse_p2 != 1 || l >= I.coarse_lev || mg_skip(I, guard)) return;
+  if (I.coarse_p2 != (ST == 5 ? 1 : 2) || l >= I.coarse_lev || mg_skip(I, guard)) return;
   const Level& F = I.lv[l];
   const int N = F.N, Nc = I.lv[l + 1].N;
   int tx, ty;
@@ -162,7 +181,7 @@ __global__ void __launch_bounds__(kBS) k_mg_up_p2(const Inst* __restrict__ Dp, i
   const T* __restrict__ xpre = (const T*)F.x;
   const T* __restrict__ b = (const T*)F.b;
   const T* __restrict__ mh = (const T*)F.mh;
-  const T ih2 = (T)(1.0 / (F.h * F.h));
+  const T ih2 = p2l_scale<T, ST>(F.h), dg = p2l_diag<T, ST>(F.h);
   const T om = (T)I.omega, om1 = (T)1 - om;
   const int tid = threadIdx.x;
   for (int k = tid; k < WC * WC; k += kBS) {
@@ -177,7 +196,7 @@ __global__ void __launch_bounds__(kBS) k_mg_up_p2(const Inst* __restrict__ Dp, i
     if ((unsigned)g1 < (unsigned)N && (unsigned)g2 < (unsigned)N) {
       const int gi = g1 + N * g2;
       bv = b[gi];
-      wv = omega_over<T>(om, (T)4 * ih2 + mh[gi]);
+      wv = omega_over<T>(om, dg + mh[gi]);
       xv = xpre[gi];
     }
     bs[k] = bv;
@@ -211,7 +230,7 @@ __global__ void __launch_bounds__(kBS) k_mg_up_p2(const Inst* __restrict__ Dp, i
     for (int k = tid; k < w * w; k += kBS) {
       const int r2 = k / w, r1 = k - r2 * w;
       const int li = (r1 + s) + W * (r2 + s);
-      c[li] = om1 * a[li] + ws[li] * (bs[li] + ih2 * ((a[li - 1] + a[li + 1]) + (a[li - W] + a[li + W])));
+      c[li] = om1 * a[li] + ws[li] * (bs[li] + p2l_nb<T, ST>(a, li, W, ih2));
     }
     __syncthreads();
     T* t = a; a = c; c = t;

@@ -591,7 +591,7 @@ static int group_select(Group* G, const ipmpde_options& o) {
       heat_steps(G->probs[i], G->H[i], fp32);
       G->H[i].hsteps = G->probs[i]->hs_d;
     }
-  if (G->dim == 2 && !G->q1) {
+  if (G->dim == 2) {
     G->outsel = 1;
   } else {
     G->sel_pre = o.nu_pre & 1;
@@ -749,32 +749,32 @@ static void launch_up2d(int nu, dim3 g, size_t lds, hipStream_t s, const Inst* D
 // has at least this many.
 static constexpr long kBigTileMinGroups = 2048;
 
-template <typename T, int NU>
+template <typename T, int NU, int ST>
 static void launch_down_p2_nu(const Group* G, int l, int scaled, int guard, hipStream_t s) {
   const int Nc = G->maxN[l + 1];
   if constexpr (p2_down_lds<T, NU, 16>() <= kStaticLdsMax) {
     const int nt = div_up(Nc, 16);
     if ((long)nt * nt * G->zc >= kBigTileMinGroups) {
-      hipLaunchKernelGGL((k_mg_down_p2<T, NU, 16>), dim3(nt, nt, G->zc), dim3(kBS), 0, s, G->D, l, scaled, guard);
+      hipLaunchKernelGGL((k_mg_down_p2<T, NU, 16, ST>), dim3(nt, nt, G->zc), dim3(kBS), 0, s, G->D, l, scaled, guard);
       return;
     }
   }
   const int nt = div_up(Nc, 8);
-  hipLaunchKernelGGL((k_mg_down_p2<T, NU, 8>), dim3(nt, nt, G->zc), dim3(kBS), 0, s, G->D, l, scaled, guard);
+  hipLaunchKernelGGL((k_mg_down_p2<T, NU, 8, ST>), dim3(nt, nt, G->zc), dim3(kBS), 0, s, G->D, l, scaled, guard);
 }
 
-template <typename T, int NU>
+template <typename T, int NU, int ST>
 static void launch_up_p2_nu(const Group* G, int l, int guard, hipStream_t s) {
   const int N = G->maxN[l];
   if constexpr (p2_up_lds<T, NU, 32>() <= kStaticLdsMax) {
     const int nt = div_up(N, 32);
     if ((long)nt * nt * G->zc >= kBigTileMinGroups) {
-      hipLaunchKernelGGL((k_mg_up_p2<T, NU, 32>), dim3(nt, nt, G->zc), dim3(kBS), 0, s, G->D, l, guard);
+      hipLaunchKernelGGL((k_mg_up_p2<T, NU, 32, ST>), dim3(nt, nt, G->zc), dim3(kBS), 0, s, G->D, l, guard);
       return;
     }
   }
   const int nt = div_up(N, 16);
-  hipLaunchKernelGGL((k_mg_up_p2<T, NU, 16>), dim3(nt, nt, G->zc), dim3(kBS), 0, s, G->D, l, guard);
+  hipLaunchKernelGGL((k_mg_up_p2<T, NU, 16, ST>), dim3(nt, nt, G->zc), dim3(kBS), 0, s, G->D, l, guard);
 }
 
 // One descent (smoothing + residual + restriction) of level l for every
@@ -790,7 +790,11 @@ static void launch_down_level(const Group* G, int l, int scaled, int transpose, 
   }
   if (G->p2) {
     switch (nu) {
-#define D_(NU) case NU: launch_down_p2_nu<T, NU>(G, l, scaled, guard, s); break;
+#define D_(NU)                                                      \
+  case NU:                                                          \
+    if (G->q1) launch_down_p2_nu<T, NU, 9>(G, l, scaled, guard, s); \
+    else launch_down_p2_nu<T, NU, 5>(G, l, scaled, guard, s);       \
+    break;
       D_(1) D_(2) D_(3) D_(4) D_(5) D_(6)
 #undef D_
     }
@@ -808,7 +812,11 @@ static void launch_up_level(const Group* G, int l, int transpose, int guard, hip
   }
   if (G->p2) {
     switch (nu) {
-#define U_(NU) case NU: launch_up_p2_nu<T, NU>(G, l, guard, s); break;
+#define U_(NU)                                              \
+  case NU:                                                  \
+    if (G->q1) launch_up_p2_nu<T, NU, 9>(G, l, guard, s);   \
+    else launch_up_p2_nu<T, NU, 5>(G, l, guard, s);         \
+    break;
       U_(1) U_(2) U_(3) U_(4) U_(5) U_(6)
 #undef U_
     }
@@ -836,7 +844,7 @@ static void mg_solve(Group* G, int transpose, int guard, int scaled, hipStream_t
   for (int j = 1; j <= k; ++j) {
     if (j > 1)
       hipLaunchKernelGGL(k_mg_kc_resid<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, G->outsel, transpose, j - 1, guard);
-    if (G->dim == 2 && !G->q1) mg_vcycle_2d<T>(G, transpose, guard, j == 1 ? scaled : 0, s);
+    if (G->dim == 2) mg_vcycle_2d<T>(G, transpose, guard, j == 1 ? scaled : 0, s);
     else mg_vcycle_generic<T>(G, transpose, guard, s);
   }
   if (k > 1) hipLaunchKernelGGL(k_mg_kc_final<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, G->outsel, k, guard);
@@ -895,7 +903,7 @@ static void schur_inv(Group* G, int guard, hipStream_t s) {
     heat_schur_inv<T>(G, guard, s);
     return;
   }
-  if (G->dim == 2 && !G->q1) {
+  if (G->dim == 2 && !G->q1) {  // Q1: the middle factor M + Theta_y is a stencil, applied below
     mg_solve<T>(G, 0, guard, 0, s);
     // instances whose whole hierarchy is in the coarse kernel never run a
     // descent kernel, so their scaled right-hand side is formed here; the
