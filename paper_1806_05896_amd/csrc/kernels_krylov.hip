@@ -191,7 +191,7 @@ __global__ void __launch_bounds__(kBS) k_precond_diag(const Inst* __restrict__ D
   double* z = zx ? zx : I.fZ + (size_t)j * 4 * n;
   double zy, zw, zv;
   apply_A11_inv(I, i, r[i], r[n + i], r[2 * n + i], zy, zw, zv);
-  if (I.pde != 3) z[i] = zy;  // Q1: the y block comes from k_cheb_step
+  if (I.pde != 3) z[i] = zy;  // Q1: the y block comes from k_cheb_block
   z[n + i] = zw; z[2 * n + i] = zv;
   if (!pt) ((T*)I.lv[0].b)[i] = (T)r[3 * n + i];
 }
@@ -204,41 +204,110 @@ __global__ void __launch_bounds__(kBS) k_precond_diag(const Inst* __restrict__ D
 //   r_k = r_{k-1} - (M + Theta_y) d_{k-1},
 //   d_k = rho_k rho_{k-1} d_{k-1} + (2 rho_k / delta) (D_M + Theta_y)^-1 r_k,
 //   x_{k+1} = x_k + d_k,  rho_0 = delta / theta, rho_k = 1 / (2 theta / delta - rho_{k-1}).
-// Step k of the recurrence (k = 0 starts it): the residual rk and the
-// direction buffers d[2] (d_{k-1} read from d[(k+1)&1], d_k written to
-// d[k&1]) are n-vectors of the q workspace (free outside the MINRES matvec).
+// The steps run S per launch (temporal blocking): a workgroup takes a TT x TT
+// tile of nodes with a halo of S nodes, holds r, d (two buffers), the
+// diagonal and Theta_y of the region in LDS and runs steps k0 .. k0+S-1
+// there; every step that reads neighbours shrinks the valid region by one
+// node, so the tile's own nodes stay exact (values outside the grid are zero,
+// which drops those neighbours as the mass stencil does).  Between launches
+// r and d live in the q workspace (free outside the MINRES matvec), two
+// buffers each by launch parity (in: launch & 1, out: the other), so no
+// workgroup overwrites values another still reads as its halo; x is the
+// output's y block, read and written at the tile's own nodes only.
 // Operands: MINRES (mpar >= 0) the Lanczos vector v = V[1-mpar] and its
 // image Z[1-mpar]; otherwise rx, zx or the FGMRES slots V_j, Z_j.  guard 1:
 // skip a stopped solve; 2: skip an instance without a pending cycle.
-__global__ void __launch_bounds__(kBS) k_cheb_step(const Inst* __restrict__ Dp, const double* __restrict__ rx, double* __restrict__ zx,
-                                                   int j, int mpar, int k, double rho, double rho_prev, double theta,
-                                                   double delta, int guard) {
+struct ChebCoef {
+  double rho[24];  // rho_k
+  double theta, delta;
+};
+
+template <int TT, int S>
+__global__ void __launch_bounds__(kBS) k_cheb_block(const Inst* __restrict__ Dp, const double* __restrict__ rx,
+                                                    double* __restrict__ zx, int j, int mpar, int k0, int launch,
+                                                    ChebCoef cf, int guard) {
   INST_BEGIN
   if ((guard == 1 && I.ctrl->stop) || (guard == 2 && !I.ctrl->want_restart)) return;
-  const int i = blockIdx.x * kBS + threadIdx.x;
-  if (i >= I.n) return;
-  const int n = I.n;
+  const int N = I.N, n = I.n;
+  const int t1 = blockIdx.x * TT, t2 = blockIdx.y * TT;
+  if (t1 >= N || t2 >= N) return;
+  constexpr int W = TT + 2 * S;
+  __shared__ double R[W * W], D0[W * W], D1[W * W], DI[W * W], TY[W * W];
   const double* r = mpar >= 0 ? I.V[1 - mpar] : (rx ? rx : I.fV + (size_t)j * 4 * n);
   double* z = mpar >= 0 ? I.Z[1 - mpar] : (zx ? zx : I.fZ + (size_t)j * 4 * n);
-  double* rk = I.Q;
-  double* dd[2] = {I.Q + n, I.Q + 2 * n};
-  const double dinv = 1.0 / (kQ1MassDiag + I.ty[i]);
-  if (k == 0) {
-    const double d0 = r[i] * dinv / theta;
-    rk[i] = r[i];
-    dd[0][i] = d0;
-    z[i] = d0;
-    return;
+  const int in = launch & 1, out = 1 - in;
+  const double* rin = k0 == 0 ? r : I.Q + (size_t)in * n;
+  const double* din = I.Q + (size_t)(2 + in) * n;
+  double* rout = I.Q + (size_t)out * n;
+  double* dout = I.Q + (size_t)(2 + out) * n;
+  const int o1 = t1 - S, o2 = t2 - S;
+  const int tid = threadIdx.x;
+  for (int k = tid; k < W * W; k += kBS) {
+    const int q2 = k / W, q1 = k - q2 * W;
+    const int g1 = o1 + q1, g2 = o2 + q2;
+    double rv = 0, dv = 0, iv = 0, tv = 0;
+    if ((unsigned)g1 < (unsigned)N && (unsigned)g2 < (unsigned)N) {
+      const int gi = g1 + N * g2;
+      tv = I.ty[gi];
+      iv = 1.0 / (kQ1MassDiag + tv);
+      rv = rin[gi];
+      dv = k0 == 0 ? 0.0 : din[gi];
+    }
+    R[k] = rv; D0[k] = dv; DI[k] = iv; TY[k] = tv;
   }
-  int i1, i2, i3;
-  node_coords(i, I.N, 2, i1, i2, i3);
-  const double* dp = dd[(k + 1) & 1];
-  const double Ad = q1_mass<double>(dp, i, i1, i2, I.N) + I.ty[i] * dp[i];
-  const double res = rk[i] - Ad;
-  const double dn = rho * rho_prev * dp[i] + (2.0 * rho / delta) * res * dinv;
-  rk[i] = res;
-  dd[k & 1][i] = dn;
-  z[i] += dn;
+  __syncthreads();
+  // own-node iterate x (read only where this workgroup writes it)
+  double xo[(TT * TT + kBS - 1) / kBS];
+#pragma unroll
+  for (int u = 0; u < (TT * TT + kBS - 1) / kBS; ++u) {
+    const int k = tid + u * kBS;
+    const int r2 = k / TT, r1 = k - r2 * TT;
+    const int g1 = t1 + r1, g2 = t2 + r2;
+    xo[u] = (k < TT * TT && g1 < N && g2 < N && k0 > 0) ? z[g1 + N * g2] : 0.0;
+  }
+  double* dp = D0;
+  double* dn = D1;
+  int m = 0;  // nodes lost at each side of the region so far
+  for (int s2 = 0; s2 < S; ++s2) {
+    const int k = k0 + s2;
+    if (k == 0) {
+      for (int q = tid; q < W * W; q += kBS) dn[q] = R[q] * DI[q] / cf.theta;
+    } else {
+      ++m;
+      const int w = W - 2 * m;
+      const double rho = cf.rho[k], rho_prev = cf.rho[k - 1], c2 = 2.0 * rho / cf.delta;
+      for (int q = tid; q < w * w; q += kBS) {
+        const int r2 = q / w, r1 = q - r2 * w;
+        const int li = (r1 + m) + W * (r2 + m);
+        const double e = (dp[li - 1] + dp[li + 1]) + dp[li - W] + dp[li + W];
+        const double cn = ((dp[li - W - 1] + dp[li - W + 1]) + dp[li + W - 1]) + dp[li + W + 1];
+        const double Ad = (16.0 * dp[li] + 4.0 * e + cn) * (1.0 / 36.0) + TY[li] * dp[li];
+        const double res = R[li] - Ad;
+        R[li] = res;
+        dn[li] = rho * rho_prev * dp[li] + c2 * res * DI[li];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < (TT * TT + kBS - 1) / kBS; ++u) {
+      const int kk = tid + u * kBS;
+      const int r2 = kk / TT, r1 = kk - r2 * TT;
+      if (kk < TT * TT) xo[u] = (k == 0) ? dn[(r1 + S) + W * (r2 + S)] : xo[u] + dn[(r1 + S) + W * (r2 + S)];
+    }
+    double* t = dp; dp = dn; dn = t;
+  }
+#pragma unroll
+  for (int u = 0; u < (TT * TT + kBS - 1) / kBS; ++u) {
+    const int k = tid + u * kBS;
+    const int r2 = k / TT, r1 = k - r2 * TT;
+    const int g1 = t1 + r1, g2 = t2 + r2;
+    if (k < TT * TT && g1 < N && g2 < N) {
+      const int gi = g1 + N * g2, li = (r1 + S) + W * (r2 + S);
+      z[gi] = xo[u];
+      rout[gi] = R[li];
+      dout[gi] = dp[li];
+    }
+  }
 }
 
 // P_T (Sec. 4, block lower triangular [A11 0; B -S_hat]): the p block solves
@@ -348,7 +417,7 @@ __global__ void __launch_bounds__(kBS) k_minres_init(const Inst* __restrict__ Dp
     double* V1 = I.V[1];
     double* Z1 = I.Z[1];
     V1[i] = ry; V1[n + i] = rw; V1[2 * n + i] = rv; V1[3 * n + i] = rp;
-    const bool q1 = I.pde == 3;  // Q1: z_y from k_cheb_step, its part of <v, z> in K4
+    const bool q1 = I.pde == 3;  // Q1: z_y from k_cheb_block, its part of <v, z> in K4
     if (!q1) Z1[i] = zy;
     Z1[n + i] = zw; Z1[2 * n + i] = zv;
 #pragma unroll
@@ -444,7 +513,7 @@ __global__ void __launch_bounds__(kBS) k_minres_k2(const Inst* __restrict__ Dp, 
     }
     double zy, zw, zv;
     apply_A11_inv(I, i, v[0], v[1], v[2], zy, zw, zv);
-    const bool q1 = I.pde == 3;  // Q1: z_y from k_cheb_step, its part of <v, z> in K4
+    const bool q1 = I.pde == 3;  // Q1: z_y from k_cheb_block, its part of <v, z> in K4
     if (!q1) Zn[i] = zy;
     Zn[n + i] = zw; Zn[2 * n + i] = zv;
     ((T*)I.lv[0].b)[i] = (T)v[3];

@@ -930,18 +930,22 @@ static constexpr int kChebSteps = 20;
 
 // z_y = (M + Theta_y)^-1 r_y for every Q1 instance by Chebyshev
 // semi-iteration (Sec. 4.1) on the spectrum [1/4, 9/4] of the diagonally
-// scaled Q1 mass; operands as k_cheb_step takes them.
+// scaled Q1 mass; operands as k_cheb_block takes them.
+// Steps per launch of the blocked kernel (the tile's halo) and its tile width.
+static constexpr int kChebBlockSteps = 5;
+static constexpr int kChebTile = 16;
+static_assert(kChebSteps % kChebBlockSteps == 0, "whole launches of Chebyshev steps");
+
 static void cheb_apply(Group* G, const double* x, double* y, int j, int mpar, int guard, hipStream_t s) {
-  const double theta = 1.25, delta = 1.0;
-  double rho_prev = delta / theta, rho = rho_prev;
-  for (int k = 0; k < kChebSteps; ++k) {
-    if (k > 0) {
-      rho_prev = rho;
-      rho = 1.0 / (2.0 * theta / delta - rho_prev);
-    }
-    hipLaunchKernelGGL(k_cheb_step, gz(G, G->max_n), dim3(kBS), 0, s, G->D, x, y, j, mpar, k, rho, rho_prev, theta,
-                       delta, guard);
-  }
+  ChebCoef cf;
+  cf.theta = 1.25;
+  cf.delta = 1.0;
+  cf.rho[0] = cf.delta / cf.theta;
+  for (int k = 1; k < kChebSteps; ++k) cf.rho[k] = 1.0 / (2.0 * cf.theta / cf.delta - cf.rho[k - 1]);
+  const int nt = div_up(G->maxN[0], kChebTile);
+  for (int L = 0; L * kChebBlockSteps < kChebSteps; ++L)
+    hipLaunchKernelGGL((k_cheb_block<kChebTile, kChebBlockSteps>), dim3(nt, nt, G->zc), dim3(kBS), 0, s, G->D, x, y,
+                       j, mpar, L * kChebBlockSteps, L, cf, guard);
 }
 
 template <typename T>
