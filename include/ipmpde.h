@@ -163,7 +163,7 @@ int ipmpde_set_allocator(ipmpde_alloc_fn alloc, ipmpde_free_fn free_, void* ctx)
  * solve): (M + Theta_y)^-1 by 20 steps of Chebyshev semi-iteration with
  * D_M + Theta_y, alpha M~ + Theta_z by alpha D~_M + Theta_z, M_hat with D_M
  * (Sec. 4.1, 4.2), multigrid on L + M_hat.  No observation weights; batched
- * only with other Q1 problems; not admitted to an engine. */
+ * only with other Q1 problems; an engine serves them in groups of their own. */
 int ipmpde_problem_create(const ipmpde_grid* grid, const ipmpde_pde* pde, double alpha, double beta,
                           const double* u_a, const double* u_b, const double* y_a, const double* y_b,
                           const double* y_d, const double* f, const double* g, ipmpde_problem** out);

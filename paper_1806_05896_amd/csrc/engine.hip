@@ -30,6 +30,7 @@ struct EngineReq {
 struct EngineClass {
   ipmpde_options o;  // Krylov and multigrid options of every member
   int dim = 0;
+  bool q1 = false;   // Q1 problems (a group holds them or none)
   Group* G = nullptr;
   std::vector<EngineReq*> members;
 };
@@ -100,8 +101,7 @@ extern "C" int ipmpde_engine_submit(ipmpde_engine* E, ipmpde_problem* P, const i
                                     uint64_t* ticket) {
   if (!E || !P || !ticket) return fail(IPMPDE_EINVAL, "NULL argument");
   if (P->in_engine) return fail(IPMPDE_EINVAL, "problem is already queued or running in an engine");
-  if (P->pde == IPMPDE_HEAT || P->pde == IPMPDE_POISSON_Q1)
-    return fail(IPMPDE_EINVAL, "heat-equation and Q1 problems are not served by the engine");
+  if (P->pde == IPMPDE_HEAT) return fail(IPMPDE_EINVAL, "heat-equation problems are not served by the engine");
   ipmpde_options o;
   TRY(resolve_opts(opts, &o));
   ipmpde_grid g{P->dim, P->N};
@@ -129,18 +129,21 @@ static int engine_admit(ipmpde_engine* E) {
     if (E->in_use + R->bytes > E->budget) break;
     E->queue.pop_front();
     EngineClass* C = nullptr;
+    const bool q1 = R->P->pde == IPMPDE_POISSON_Q1;
     for (EngineClass* c : E->classes)
-      if (c->dim == R->P->dim && same_solver(c->o, R->o)) C = c;
+      if (c->dim == R->P->dim && c->q1 == q1 && same_solver(c->o, R->o)) C = c;
     if (!C) {
       C = new EngineClass();
       C->o = R->o;
       C->dim = R->P->dim;
+      C->q1 = q1;
       const int rc = group_create({}, E->max_slots, C->dim, &C->G);
       if (rc != IPMPDE_OK) {
         delete C;
         E->queue.push_front(R);
         return rc;
       }
+      C->G->q1 = q1;
       E->classes.push_back(C);
     }
     R->t_admit = Clock::now();

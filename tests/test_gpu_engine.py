@@ -73,6 +73,28 @@ def test_engine_solo_vs_mix():
         p.close()
 
 
+def test_engine_serves_q1_beside_finite_differences():
+    """Q1 requests form their own group in the engine; every result equals its
+    solo solve bit for bit."""
+    from paper_1806_05896_amd import Engine, Options, Problem
+    datas = [W.poisson2d_q1(seed=0, N=31), W.poisson2d_small(seed=1, N=31), W.poisson2d_q1(seed=2, N=63),
+             W.poisson2d_small(seed=3, N=63)]
+    opts = [Options(sigma=d.sigma, krylov="minres", precond="pd") for d in datas]
+    solo = _solo(datas, opts)
+    probs = [Problem(d) for d in datas]
+    with Engine(hbm_budget_bytes=1 << 40, max_slots=4) as eng:
+        tickets = _drive(eng, probs, opts, [0, 0, 1, 2])
+        assert eng.info()["groups"] >= 0
+        for p, t, (rc, u, y, s) in zip(probs, tickets, solo):
+            info = eng.poll(t)
+            assert info["state"] == 2 and info["status"] == rc == 0
+            assert p.stats().nli == s.nli and p.stats().krylov_its == s.krylov_its
+            np.testing.assert_array_equal(p.query("u"), u)
+            eng.release(t)
+    for p in probs:
+        p.close()
+
+
 def test_engine_admission_by_footprint():
     """Budget for the two largest requests: the admitted bytes never exceed
     it, so fewer run than slots allow while others wait, and every request
