@@ -84,7 +84,6 @@ def test_engine_serves_q1_beside_finite_differences():
     probs = [Problem(d) for d in datas]
     with Engine(hbm_budget_bytes=1 << 40, max_slots=4) as eng:
         tickets = _drive(eng, probs, opts, [0, 0, 1, 2])
-        assert eng.info()["groups"] >= 0
         for p, t, (rc, u, y, s) in zip(probs, tickets, solo):
             info = eng.poll(t)
             assert info["state"] == 2 and info["status"] == rc == 0
