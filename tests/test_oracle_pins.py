@@ -152,6 +152,33 @@ def test_schur_complement_formula():
     np.testing.assert_allclose(S, S_paper, rtol=1e-10, atol=1e-10)
 
 
+@pytest.mark.parametrize("pde", ["poisson", "convdiff"])
+def test_ideal_preconditioners_cluster_the_spectrum(pde):
+    """With the exact (1,1) block and the exact Schur complement (Sec. 4, the
+    ideal P_D and P_T), the preconditioned Newton matrix of the oracle has the
+    eigenvalues 1 and (1 +- sqrt 5)/2 only (P_D), or 1 only (P_T), so MINRES
+    and GMRES would stop after three and two iterations."""
+    p = _tiny_problem(N=3)
+    if pde == "convdiff":
+        p.pde, p.eps = "convdiff", 1.0 / 50
+    disc = discretize(p)
+    opts = IPMOptions()
+    st = initial_state(p, opts)
+    st, _ = ipm_step(p, disc, st, opts, 0.2)
+    K = oracle.ipm.newton_matrix(p, disc, st).toarray()
+    n = p.n
+    A11 = K[:3 * n, :3 * n]
+    B = K[3 * n:, :3 * n]
+    S = B @ np.linalg.solve(A11, B.T)
+    Z = np.zeros((3 * n, n))
+    PD = np.block([[A11, Z], [Z.T, S]])
+    PT = np.block([[A11, Z], [B, -S]])
+    for P, want in ((PD, [1.0, (1 + 5 ** 0.5) / 2, (1 - 5 ** 0.5) / 2]), (PT, [1.0])):
+        lam = np.linalg.eigvals(np.linalg.solve(P, K))
+        dist = np.min(np.abs(lam[:, None] - np.array(want)[None, :]), axis=1)
+        assert dist.max() < 1e-6, dist.max()
+
+
 def test_schur_approximation_lower_bound_half():
     """Theorem (Sec. 4.2): lambda(S_hat^-1 S) >= 1/2 for lumped mass, along an IPM run."""
     p = _tiny_problem(N=5, state_bounds=True)
