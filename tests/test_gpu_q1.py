@@ -102,15 +102,16 @@ def test_q1_rhs_and_saddle_matvec(case):
         assert _rel(y, K @ x) <= 1e-13
 
 
+@pytest.mark.parametrize("vcycles", [1, 3])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_q1_pd_symmetric_positive(prec):
+def test_q1_pd_symmetric_positive(prec, vcycles):
     """With the fixed 20-step Chebyshev polynomial in the (1,1) block, P_D^-1
     stays symmetric positive definite (MINRES needs it)."""
     _, Options, Problem = _api()
     data = CASES["q1_31"]()
     disc, st = _generic_state(data)
     mu = st.mu * data.sigma
-    opts = Options(krylov="minres", precond="pd", mg_precision=prec)
+    opts = Options(krylov="minres", precond="pd", mg_precision=prec, vcycles=vcycles)
     rng = np.random.default_rng(3)
     with Problem(data) as prob:
         _load_state(prob, st, True)
@@ -151,20 +152,21 @@ def test_q1_chebyshev_block():
     assert err <= 2 * 0.5 ** 20
 
 
-@pytest.mark.parametrize("krylov,precond,prec", [("fgmres", "pd", "fp64"), ("fgmres", "pd", "fp32"),
-                                                 ("fgmres", "pt", "fp32"), ("fgmres", "pt", "fp64"),
-                                                 ("minres", "pd", "fp32"), ("minres", "pd", "fp64")])
+@pytest.mark.parametrize("krylov,precond,prec,vc", [("fgmres", "pd", "fp64", 1), ("fgmres", "pd", "fp32", 1),
+                                                    ("fgmres", "pt", "fp32", 1), ("fgmres", "pt", "fp64", 1),
+                                                    ("minres", "pd", "fp32", 1), ("minres", "pd", "fp64", 1),
+                                                    ("minres", "pd", "fp32", 3), ("fgmres", "pt", "fp64", 2)])
 @pytest.mark.parametrize("case", ["q1_31", "q1_63_hard"])
-def test_q1_newton_direction_parity(case, krylov, precond, prec):
+def test_q1_newton_direction_parity(case, krylov, precond, prec, vc):
     _, Options, Problem = _api()
-    print(f"[q1 newton] {case} {krylov} {precond} {prec}", flush=True)
+    print(f"[q1 newton] {case} {krylov} {precond} {prec} vcycles={vc}", flush=True)
     data = CASES[case]()
     disc, st = _generic_state(data, steps=3)
     mu = st.mu * data.sigma
     K = newton_matrix(data, disc, st)
     b = newton_rhs(data, disc, st, mu)
     ref = np.concatenate(newton_solve(data, disc, st, mu))
-    opts = Options(krylov=krylov, precond=precond, mg_precision=prec)
+    opts = Options(krylov=krylov, precond=precond, mg_precision=prec, vcycles=vc)
     with Problem(data) as prob:
         _load_state(prob, st, data.y_a is not None)
         info = prob.newton_direction(mu, opts)
