@@ -1,25 +1,25 @@
-"""Bilinear (Q1) finite elements on the uniform square grid (oracle).
+"""Bilinear / trilinear (Q1) finite elements on the uniform grid (oracle).
 
 The paper discretizes with Q1 elements (Sec. 5): state, control and adjoint
-are continuous piecewise bilinear on the N x N interior nodes of (0,1)^2,
-h = 1/(N+1), with
+are continuous piecewise bilinear (2D) or trilinear (3D) on the N^d interior
+nodes of (0,1)^d, h = 1/(N+1), with
 
 * L: the stiffness matrix (Sec. 2), entries of the integrals of grad phi_i .
   grad phi_j,
 * M: the consistent mass matrix (Sec. 2), entries of the integrals of
   phi_i phi_j,
-* D: the lumped mass diag(integral of phi_i) = h^2 I, the weights of the
+* D: the lumped mass diag(integral of phi_i) = h^d I, the weights of the
   nodal quadrature of the L1 term (Sec. 2),
 
-assembled here element by element from the 4 x 4 element matrices of a
-square of side h.  Dirichlet data g enter through the boundary columns of L
-and the source through M: f_hat = M_II f_I - L_IB g_B (the boundary part of
-M f is dropped with f given at interior nodes only).
+assembled here element by element from the element matrices of a square
+(4 x 4) or cube (8 x 8) of side h.  Dirichlet data g enter through the
+boundary columns of L and the source through M: f_hat = M_II f_I - L_IB g_B
+(the boundary part of M f is dropped with f given at interior nodes only).
 
 The problem handed to the interior point method is eq. (pb_fe_lin) divided
-by h^2, the lumped mass of a node (the finite-element counterpart of the
-unit-mass form of fd.py): L / h^2, M / h^2 (rows summing to 1 away from the
-boundary), D / h^2 = I and f_hat / h^2.  The minimizer is unchanged, and the
+by h^d, the lumped mass of a node (the finite-element counterpart of the
+unit-mass form of fd.py): L / h^d, M / h^d (rows summing to 1 away from the
+boundary), D / h^d = I and f_hat / h^d.  The minimizer is unchanged, and the
 barrier parameter and the stopping tolerances keep the meaning they have
 for the finite-difference problems, independent of the mesh.
 """
@@ -45,8 +45,53 @@ def _element_matrices(h: float):
     return Ke, Me
 
 
-def _full_matrices(N: int):
-    """L and M over all (N+2)^2 nodes (lexicographic, x1 fastest)."""
+def _element_matrices_3d(h: float):
+    """Stiffness and mass of one cube element.  A trilinear basis function is
+    the product of one 1D hat function per axis, so each element integral is
+    a product of 1D integrals over [0, h] (stiffness k1 = [[1, -1], [-1, 1]] / h,
+    mass m1 = [[2, 1], [1, 2]] h / 6): the mass takes m1 on every axis, the
+    stiffness sums, over the axes, k1 on that axis times m1 on the others.
+    Local node a = a1 + 2 a2 + 4 a3 sits at the corner (a1, a2, a3) h."""
+    k1 = np.array([[1.0, -1.0], [-1.0, 1.0]]) / h
+    m1 = np.array([[2.0, 1.0], [1.0, 2.0]]) * (h / 6.0)
+    Ke = np.zeros((8, 8))
+    Me = np.zeros((8, 8))
+    for a in range(8):
+        for b in range(8):
+            ca = [(a >> t) & 1 for t in range(3)]
+            cb = [(b >> t) & 1 for t in range(3)]
+            m = [m1[ca[t], cb[t]] for t in range(3)]
+            k = [k1[ca[t], cb[t]] for t in range(3)]
+            Me[a, b] = m[0] * m[1] * m[2]
+            Ke[a, b] = k[0] * m[1] * m[2] + m[0] * k[1] * m[2] + m[0] * m[1] * k[2]
+    return Ke, Me
+
+
+def _full_matrices_3d(N: int):
+    """L and M over all (N+2)^3 nodes (lexicographic, x1 fastest)."""
+    h = 1.0 / (N + 1)
+    P = N + 2
+    Ke, Me = _element_matrices_3d(h)
+    e = np.arange(N + 1)
+    e1, e2, e3 = np.meshgrid(e, e, e, indexing="ij")
+    base = (e1 + P * e2 + P * P * e3).reshape(-1)      # lower corner of every element
+    off = [(a & 1) + P * ((a >> 1) & 1) + P * P * ((a >> 2) & 1) for a in range(8)]
+    rows, cols, kv, mv = [], [], [], []
+    for a in range(8):
+        for b in range(8):
+            rows.append(base + off[a]); cols.append(base + off[b])
+            kv.append(np.full(base.size, Ke[a, b])); mv.append(np.full(base.size, Me[a, b]))
+    rows, cols = np.concatenate(rows), np.concatenate(cols)
+    L = sp.csr_matrix((np.concatenate(kv), (rows, cols)), shape=(P ** 3, P ** 3))
+    M = sp.csr_matrix((np.concatenate(mv), (rows, cols)), shape=(P ** 3, P ** 3))
+    L.sum_duplicates(); M.sum_duplicates()
+    return L, M
+
+
+def _full_matrices(N: int, dim: int = 2):
+    """L and M over all (N+2)^d nodes (lexicographic, x1 fastest)."""
+    if dim == 3:
+        return _full_matrices_3d(N)
     h = 1.0 / (N + 1)
     P = N + 2
     Ke, Me = _element_matrices(h)
@@ -64,35 +109,40 @@ def _full_matrices(N: int):
     return L, M
 
 
-def _interior_index(N: int) -> np.ndarray:
+def _interior_index(N: int, dim: int = 2) -> np.ndarray:
     P = N + 2
-    i1, i2 = np.meshgrid(np.arange(1, N + 1), np.arange(1, N + 1), indexing="xy")
-    return (i1 + P * i2).reshape(-1)
+    r = np.arange(1, N + 1)
+    if dim == 2:
+        i1, i2 = np.meshgrid(r, r, indexing="xy")
+        return (i1 + P * i2).reshape(-1)
+    i3, i2, i1 = np.meshgrid(r, r, r, indexing="ij")
+    return (i1 + P * i2 + P * P * i3).reshape(-1)
 
 
-def q1_matrices(N: int):
+def q1_matrices(N: int, dim: int = 2):
     """(L_II, M_II, D): interior stiffness, consistent mass and lumped mass diagonal."""
-    L, M = _full_matrices(N)
-    I = _interior_index(N)
+    L, M = _full_matrices(N, dim)
+    I = _interior_index(N, dim)
     h = 1.0 / (N + 1)
-    return L[I][:, I].tocsr(), M[I][:, I].tocsr(), np.full(N * N, h * h)
+    return L[I][:, I].tocsr(), M[I][:, I].tocsr(), np.full(N ** dim, h ** dim)
 
 
 def discretize_q1(prob) -> Discretization:
-    """Q1 discretization of the 2D Poisson problem: A = L, the tracking and
-    control masses M, the L1 weights D, f_hat = M f - L_IB g."""
-    if prob.dim != 2:
-        raise ValueError("the Q1 discretization is built in 2D")
-    N = prob.N
-    Lf, Mf = _full_matrices(N)
-    I = _interior_index(N)
+    """Q1 discretization of the Poisson problem (2D or 3D): A = L, the
+    tracking and control masses M, the L1 weights D, f_hat = M f - L_IB g."""
+    if prob.dim not in (2, 3):
+        raise ValueError("the Q1 discretization is built in 2D and 3D")
+    N, dim = prob.N, prob.dim
+    Lf, Mf = _full_matrices(N, dim)
+    I = _interior_index(N, dim)
     h = 1.0 / (N + 1)
     L, M = Lf[I][:, I].tocsr(), Mf[I][:, I].tocsr()
-    f_hat = np.zeros(N * N) if prob.f is None else M @ np.asarray(prob.f, dtype=np.float64)
+    n = N ** dim
+    f_hat = np.zeros(n) if prob.f is None else M @ np.asarray(prob.f, dtype=np.float64)
     if prob.g is not None:
         gg = np.array(prob.g, dtype=np.float64, copy=True)
         gg[I] = 0.0
         f_hat = f_hat - (Lf @ gg)[I]
-    s = 1.0 / (h * h)
-    return Discretization(2, N, (L * s).tocsr(), f_hat * s, Mt=(M * s).tocsr(), Mc=(M * s).tocsr(),
-                          dl=np.ones(N * N))
+    s = 1.0 / h ** dim
+    return Discretization(dim, N, (L * s).tocsr(), f_hat * s, Mt=(M * s).tocsr(), Mc=(M * s).tocsr(),
+                          dl=np.ones(n))

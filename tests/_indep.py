@@ -206,6 +206,32 @@ def dense_q1(N):
     return K, M
 
 
+def dense_q1_3d(N):
+    """Trilinear Q1 stiffness and consistent mass on the interior nodes of the
+    unit cube from their 27-point stencils, one row at a time (neighbours on
+    the boundary dropped).  By the number of nonzero offsets of a neighbour
+    (0: the node, 1: a face, 2: an edge, 3: a corner neighbour): stiffness
+    h (8/3, 0, -1/6, -1/12), mass h^3/216 (64, 16, 4, 1)."""
+    h = 1.0 / (N + 1)
+    n = N ** 3
+    kw = {0: 8.0 / 3.0, 1: 0.0, 2: -1.0 / 6.0, 3: -1.0 / 12.0}
+    mw = {0: 64.0, 1: 16.0, 2: 4.0, 3: 1.0}
+    K = np.zeros((n, n)); M = np.zeros((n, n))
+    for i3 in range(N):
+        for i2 in range(N):
+            for i1 in range(N):
+                r = i1 + N * (i2 + N * i3)
+                for o in itertools.product((-1, 0, 1), repeat=3):
+                    j1, j2, j3 = i1 + o[0], i2 + o[1], i3 + o[2]
+                    if not (0 <= j1 < N and 0 <= j2 < N and 0 <= j3 < N):
+                        continue
+                    c = j1 + N * (j2 + N * j3)
+                    k = sum(1 for t in o if t != 0)
+                    K[r, c] += kw[k] * h
+                    M[r, c] += mw[k] * h ** 3 / 216.0
+    return K, M
+
+
 def fista_weighted(K, M, dl, yd, fhat, alpha, beta, ua, ub, iters=200000, tol=1e-15):
     """min_u 1/2 (y - yd)^T M (y - yd) + alpha/2 u^T M u + beta sum_i dl_i |u_i|
     with K y = M u + fhat and ua <= u <= ub (the finite-element problem),

@@ -610,3 +610,84 @@ def test_q1_ipm_matches_weighted_fista(mu_rule):
     assert ((np.abs(u_ref) > 1e-6) & (u_ref < 1.0 - 1e-6) & (u_ref > -1.5 + 1e-6)).sum() > 0
     np.testing.assert_allclose(r.u, u_ref, rtol=0, atol=1e-7)
     np.testing.assert_allclose(r.y, y_ref, rtol=0, atol=1e-8)
+
+
+# ---------------------------------------------------------------- trilinear Q1 elements in 3D
+
+def test_q1_3d_element_assembly_matches_stencils():
+    """Element-by-element assembly of the trilinear stiffness and mass equals
+    their 27-point stencils written out node by node."""
+    from oracle.fem import q1_matrices
+    for N in (3, 5):
+        L, M, D = q1_matrices(N, 3)
+        Kd, Md = I.dense_q1_3d(N)
+        np.testing.assert_allclose(L.toarray(), Kd, rtol=0, atol=1e-15)
+        np.testing.assert_allclose(M.toarray(), Md, rtol=0, atol=1e-18)
+        np.testing.assert_allclose(D, np.full(N ** 3, (1.0 / (N + 1)) ** 3), rtol=0, atol=0)
+
+
+def test_q1_3d_sine_modes_and_mass_bounds():
+    """The discrete sine modes diagonalize the interior trilinear stiffness and
+    mass: with c_a = cos(k_a pi h), the mass eigenvalue is h^3 prod_a (2 + c_a)/3
+    and the stiffness eigenvalue h sum_a (2 - 2 c_a) prod_(b != a) (2 + c_b)/3.
+    So lambda(D_M^-1 M) = prod_a (1 + c_a / 2) lies in [1/8, 27/8], the
+    Chebyshev interval of the 3D Q1 mass (Sec. 4.1)."""
+    from oracle.fem import q1_matrices
+    import scipy.linalg as sla
+    N = 7
+    h = 1.0 / (N + 1)
+    L, M, _ = q1_matrices(N, 3)
+    rng = np.random.default_rng(8)
+    for _ in range(6):
+        ks = tuple(int(k) for k in rng.integers(1, N + 1, size=3))
+        v = I.sine_mode(3, N, ks)
+        c = [math.cos(k * math.pi * h) for k in ks]
+        lm = h ** 3 * np.prod([(2 + ca) / 3 for ca in c])
+        ll = h * sum((2 - 2 * c[a]) * np.prod([(2 + c[b]) / 3 for b in range(3) if b != a]) for a in range(3))
+        np.testing.assert_allclose(M @ v, lm * v, rtol=0, atol=1e-15 * np.abs(v).max())
+        np.testing.assert_allclose(L @ v, ll * v, rtol=0, atol=1e-13 * np.abs(v).max())
+    Md = M.toarray()
+    lam = np.sort(sla.eigh(Md, np.diag(np.diag(Md)), eigvals_only=True))
+    cs = [math.cos(k * math.pi * h) for k in range(1, N + 1)]
+    expect = np.sort([(1 + a / 2) * (1 + b / 2) * (1 + c / 2) for a in cs for b in cs for c in cs])
+    np.testing.assert_allclose(lam, expect, rtol=0, atol=1e-12)
+    assert lam.min() > 1 / 8 and lam.max() < 27 / 8
+
+
+def test_q1_3d_stiffness_exact_on_cubics_and_mass_on_linears():
+    """On the uniform grid the trilinear stiffness gives h^3 (-Lap u) for any
+    cubic u (each factor of a cubic term is at most quadratic in one
+    variable), and the mass gives h^3 u for any linear u."""
+    from oracle.fem import _full_matrices, _interior_index
+    N = 7
+    h = 1.0 / (N + 1)
+    Lf, Mf = _full_matrices(N, 3)
+    x1, x2, x3 = W.all_coords(3, N)
+    Iidx = _interior_index(N, 3)
+    u = 0.3 * x1 ** 3 - x1 ** 2 * x2 + 0.5 * x1 * x2 * x3 + 2 * x3 ** 2 - x2 * x3 ** 2 + 0.2 * x3
+    lap = 1.8 * x1 - 2 * x2 + 4 - 2 * x2
+    np.testing.assert_allclose((Lf @ u)[Iidx], -h ** 3 * lap[Iidx], rtol=0, atol=1e-14)
+    lin = 0.4 * x1 - 1.1 * x2 + 0.6 * x3 + 0.3
+    np.testing.assert_allclose((Mf @ lin)[Iidx], h ** 3 * lin[Iidx], rtol=0, atol=1e-17)
+
+
+@pytest.mark.parametrize("mu_rule", ["paper", "central"])
+def test_q1_3d_ipm_matches_weighted_fista(mu_rule):
+    """The 3D Q1 problem of eq. (pb_fe): the IPM optimum equals FISTA on the
+    reduced problem in u with the consistent masses and the lumped L1 weights."""
+    N = 3
+    p = W.poisson3d_q1(seed=1, N=N)
+    rng = np.random.default_rng(5)
+    p.y_d = W.sine_modes(rng, 3, N, 4, 2)[0] * 6.0
+    p.alpha, p.beta = 1e-2, 2e-3
+    p.u_a[:] = -1.5; p.u_b[:] = 1.0
+    K, M = I.dense_q1_3d(N)
+    dl = np.full(p.n, 1.0 / (N + 1) ** 3)
+    u_ref, y_ref = I.fista_weighted(K, M, dl, p.y_d, np.zeros(p.n), p.alpha, p.beta, p.u_a, p.u_b)
+    r = oracle.solve(p, IPMOptions(sigma=p.sigma, eps_p=1e-13, eps_d=1e-13, eps_c=1e-13, mu_rule=mu_rule))
+    assert r.status == "converged"
+    assert (np.abs(u_ref) < 1e-12).sum() > 0 and (np.abs(u_ref - 1.0) < 1e-12).sum() > 0
+    assert (np.abs(u_ref + 1.5) < 1e-12).sum() > 0
+    assert ((np.abs(u_ref) > 1e-6) & (u_ref < 1.0 - 1e-6) & (u_ref > -1.5 + 1e-6)).sum() > 0
+    np.testing.assert_allclose(r.u, u_ref, rtol=0, atol=1e-7)
+    np.testing.assert_allclose(r.y, y_ref, rtol=0, atol=1e-8)

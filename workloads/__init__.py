@@ -25,6 +25,8 @@ analytic desired states, Sec. 5):
   * ``served_mix``: a stream of mixed requests (see ``served_requests``).
   * ``poisson2d_q1``: the 511^2 Poisson data with Q1 finite elements
     (pde "poisson_q1": stiffness, consistent and lumped mass).
+  * ``poisson3d_q1``: the 127^3 Poisson data of ``poisson3d_127`` with
+    trilinear Q1 finite elements.
   * ``heat2d``: the heat equation on (0,1)^2 x (0,1] (Sec. 5.3), N=63,
     nt=100 backward Euler steps (tau=0.01), y_d = A sin(pi x1) sin(pi x2) at
     every time step, A ~ N(1, 0.1), y(0) = 0, alpha=1e-4, beta=1e-2,
@@ -52,6 +54,7 @@ CONFIG_IDS = {
     "poisson2d_partial": 5,
     "heat2d": 6,
     "poisson2d_q1": 7,
+    "poisson3d_q1": 8,
 }
 
 
@@ -218,6 +221,16 @@ def poisson2d_q1(seed: int = 0, N: int = 511, instance: int = 0) -> ProblemData:
                        _const(n, -0.2), _const(n, 0.3), y_d, None, None, 0.2, "poisson2d_q1", {"modes": modes})
 
 
+def poisson3d_q1(seed: int = 0, N: int = 127, beta: float = 1e-3, instance: int = 0) -> ProblemData:
+    """The 127^3 Poisson workload (8 sine modes, alpha = 1e-5, beta = 1e-3,
+    u in [-10, 10], no state bounds) discretized with trilinear Q1 elements."""
+    rng = rng_for("poisson3d_q1", instance, seed)
+    y_d, modes = sine_modes(rng, 3, N)
+    n = N ** 3
+    return ProblemData(3, N, "poisson_q1", 1.0, 1e-5, beta, _const(n, -10.0), _const(n, 10.0),
+                       None, None, y_d, None, None, 0.2, "poisson3d_q1", {"modes": modes})
+
+
 def served_requests(n_requests: int = 256, seed: int = 0, sizes=(31, 63, 127, 255), rate: float = 1.0):
     """Request stream for the serving workload: (arrival_time, ProblemData) pairs.
 
@@ -253,4 +266,5 @@ def served_requests(n_requests: int = 256, seed: int = 0, sizes=(31, 63, 127, 25
 def by_name(name: str, seed: int = 0, **kw) -> ProblemData:
     return {"poisson2d_small": poisson2d_small, "poisson2d_511": poisson2d_511,
             "poisson3d_127": poisson3d_127, "convdiff2d_255": convdiff2d_255,
-            "poisson2d_partial": poisson2d_partial, "heat2d": heat2d, "poisson2d_q1": poisson2d_q1}[name](seed=seed, **kw)
+            "poisson2d_partial": poisson2d_partial, "heat2d": heat2d, "poisson2d_q1": poisson2d_q1,
+            "poisson3d_q1": poisson3d_q1}[name](seed=seed, **kw)
