@@ -29,7 +29,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the roofline kernel from rocprofv3 FETCH_SIZE/WRITE_SIZE
 # runs (profiles/k_minres_k1_poisson2d_511x8_pmc.md), valid while the kernel
 # sources hash to the value they were measured with.
-TRAFFIC = {"kernel": 6, "N": 511, "batch": 8, "bytes": 622980403.7, "source_sha": "50576935733ed934"}
+TRAFFIC = {"kernel": 6, "N": 511, "batch": 8, "bytes": 622749824.1, "source_sha": "cfafa8a77063ac5a"}
 KERNEL_NAMES = {0: "k_saddle (saddle matvec)", 1: "k_mg_jacobi (finest-level smoothing sweep)",
                 2: "k_minres_k2 (Lanczos + diagonal preconditioner)", 3: "one V-cycle",
                 4: "k_mg_down2d (finest level: smoothing + residual + restriction)",
@@ -226,6 +226,31 @@ def bench_q1(W, torch, N, reps, batch=8):
     return out
 
 
+def bench_q1_3d(W, torch, N, reps):
+    """The 127^3 Poisson workload with trilinear Q1 elements, one instance:
+    MINRES + P_D and FGMRES(30) + P_T, FP32 V-cycles, 20 Chebyshev steps."""
+    from paper_1806_05896_amd import Options, Problem
+    d = W.poisson3d_q1(seed=0, N=N)
+    stream = torch.cuda.current_stream()
+    out = {"workload": f"poisson3d_q1: 3D Poisson {N}^3, trilinear Q1 elements, alpha=1e-5, beta=1e-3, "
+                       "u in [-10,10], sigma=0.2"}
+    with Problem(d) as p:
+        for name, kry, pre in (("minres_pd", "minres", "pd"), ("fgmres_pt", "fgmres", "pt")):
+            o = Options(sigma=d.sigma, krylov=kry, precond=pre, mg_precision="fp32")
+            p.solve(o, stream=stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                rc = p.solve(o, stream=stream)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / reps
+            s = p.stats()
+            log(f"q1 3d {N}^3 {name}: {1 / t:.2f} solves/s, nli {s.nli}, its {s.krylov_its}")
+            out[name] = {"solves_per_s": 1 / t, "ms_per_solve": t * 1e3, "nli": s.nli,
+                         "krylov_its_per_solve": s.krylov_its, "krylov_its_per_s": s.krylov_its / t, "status": rc}
+    return out
+
+
 def bench_heat_batch(W, torch, N, nt, B, reps):
     """B heat instances (seeds 0..B-1) solved as one batch: the substitution
     kernel runs one workgroup per instance, every other launch serves all."""
@@ -389,7 +414,8 @@ def main():
     ap.add_argument("--heat-nt", type=int, default=100, help="time steps of the heat-equation run")
     ap.add_argument("--heat-batch", type=int, default=16, help="instances of the batched heat run (0: skip)")
     ap.add_argument("--q1-N", type=int, default=511, help="grid of the Q1 finite-element run (0: skip)")
-    ap.add_argument("--only", choices=["serve", "batch", "partial", "heat", "q1"], default=None,
+    ap.add_argument("--q1-3d-N", type=int, default=127, help="grid of the 3D Q1 run (0: skip)")
+    ap.add_argument("--only", choices=["serve", "batch", "partial", "heat", "q1", "q1_3d"], default=None,
                     help="run one extra section alone")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only launch the roofline kernel (20 times) and a 1 GiB device copy, for counter runs")
@@ -419,6 +445,9 @@ def main():
         return
     if args.only == "q1":
         print(json.dumps({"q1": bench_q1(W, torch, args.q1_N, 3)}), flush=True)
+        return
+    if args.only == "q1_3d":
+        print(json.dumps({"q1_3d": bench_q1_3d(W, torch, args.q1_3d_N, 2)}), flush=True)
         return
     if args.only == "heat":
         out = bench_heat(W, torch, args.heat_N, args.heat_nt, 3)
@@ -544,6 +573,8 @@ def main():
         result["partial_observation"] = bench_partial(W, torch, args.partial_N, 2)
     if args.q1_N > 0:
         result["q1"] = bench_q1(W, torch, args.q1_N, 2)
+    if args.q1_3d_N > 0:
+        result["q1_3d"] = bench_q1_3d(W, torch, args.q1_3d_N, 1)
     if args.heat_N > 0:
         result["heat"] = bench_heat(W, torch, args.heat_N, args.heat_nt, 2)
         if args.heat_batch > 0:

@@ -163,6 +163,28 @@ __device__ __forceinline__ T apply_op_s(const T* __restrict__ x, int idx, int i1
     }
     return ih2 * ((T)(2 * dim) * X_(idx) - nb);
   }
+  if (pde == 3 && dim == 3) {
+    // trilinear Q1 stiffness divided by h^3: (8/3 x - 1/6 (the 12 edge
+    // neighbours) - 1/12 (the 8 corner neighbours)) / h^2; the 6 face
+    // neighbours carry 0.  Symmetric.
+    T e = 0, c = 0;
+#pragma unroll
+    for (int o3 = -1; o3 <= 1; ++o3)
+#pragma unroll
+      for (int o2 = -1; o2 <= 1; ++o2)
+#pragma unroll
+        for (int o1 = -1; o1 <= 1; ++o1) {
+          const int k = (o1 != 0) + (o2 != 0) + (o3 != 0);
+          if (k < 2) continue;
+          if ((unsigned)(i1 + o1) >= (unsigned)N || (unsigned)(i2 + o2) >= (unsigned)N ||
+              (unsigned)(i3 + o3) >= (unsigned)N)
+            continue;
+          const T v = X_(idx + o1 + o2 * sy + o3 * sz);
+          if (k == 2) e += v;
+          else c += v;
+        }
+    return (T)(1.0 / (h * h)) * ((T)(8.0 / 3.0) * X_(idx) - (T)(1.0 / 6.0) * e - (T)(1.0 / 12.0) * c);
+  }
   if (pde == 3) {
     // Q1 stiffness divided by h^2 (2D): (8 x - the eight neighbours) / (3 h^2), symmetric
     const T ih2 = (T)(1.0 / (3.0 * h * h));
@@ -263,8 +285,36 @@ __device__ __forceinline__ T inst_op(const Inst& I, const T* __restrict__ x, int
 // neighbours) / 36, so that rows sum to 1 away from the boundary.  Its
 // diagonal, the D_M of the preconditioners, is 4/9.  ABS: with |x|.
 constexpr double kQ1MassDiag = 16.0 / 36.0;
+// The trilinear mass divided by h^3 (3D): (64 x + 16 (face) + 4 (edge) +
+// (corner neighbours)) / 216; its diagonal is 8/27.
+constexpr double kQ1MassDiag3 = 64.0 / 216.0;
+__device__ __forceinline__ double q1_mass_diag(int dim) { return dim == 3 ? kQ1MassDiag3 : kQ1MassDiag; }
+
 template <typename T, bool ABS = false>
-__device__ __forceinline__ T q1_mass(const T* __restrict__ x, int idx, int i1, int i2, int N) {
+__device__ __forceinline__ T q1_mass3(const T* __restrict__ x, int idx, int i1, int i2, int i3, int N) {
+  const int sy = N, sz = N * N;
+  T f = 0, e = 0, c = 0;
+#pragma unroll
+  for (int o3 = -1; o3 <= 1; ++o3)
+#pragma unroll
+    for (int o2 = -1; o2 <= 1; ++o2)
+#pragma unroll
+      for (int o1 = -1; o1 <= 1; ++o1) {
+        const int k = (o1 != 0) + (o2 != 0) + (o3 != 0);
+        if (k == 0) continue;
+        if ((unsigned)(i1 + o1) >= (unsigned)N || (unsigned)(i2 + o2) >= (unsigned)N ||
+            (unsigned)(i3 + o3) >= (unsigned)N)
+          continue;
+        const T v = ldv<T, ABS>(x, idx + o1 + o2 * sy + o3 * sz);
+        if (k == 1) f += v;
+        else if (k == 2) e += v;
+        else c += v;
+      }
+  return ((T)64 * ldv<T, ABS>(x, idx) + (T)16 * f + (T)4 * e + c) * (T)(1.0 / 216.0);
+}
+
+template <typename T, bool ABS = false>
+__device__ __forceinline__ T q1_mass2(const T* __restrict__ x, int idx, int i1, int i2, int N) {
 #define X_(k) ldv<T, ABS>(x, (k))
   const bool l = i1 > 0, r = i1 < N - 1, d = i2 > 0, u = i2 < N - 1;
   T e = 0, c = 0;
@@ -282,6 +332,12 @@ __device__ __forceinline__ T q1_mass(const T* __restrict__ x, int idx, int i1, i
   }
 #undef X_
   return ((T)16 * ldv<T, ABS>(x, idx) + (T)4 * e + c) * (T)(1.0 / 36.0);
+}
+
+// The Q1 mass (divided by the lumped mass h^dim) applied at node idx.
+template <typename T, bool ABS = false>
+__device__ __forceinline__ T q1_mass(const T* __restrict__ x, int idx, int i1, int i2, int i3, int N, int dim) {
+  return dim == 3 ? q1_mass3<T, ABS>(x, idx, i1, i2, i3, N) : q1_mass2<T, ABS>(x, idx, i1, i2, N);
 }
 
 // (|A| |x|)_idx (or with |A^T|) for rounding-error bounds.  Every

@@ -53,10 +53,10 @@ __global__ void __launch_bounds__(kBS) k_measures(const Inst* __restrict__ Dp) {
     const double lwa = I.lwa[i], lwb = I.lwb[i], lva = I.lva[i], lvb = I.lvb[i];
     // unit mass, or Q1: M u, M (y - y_d) and M p in eq. (prdu)
     const bool q1 = I.pde == 3;
-    const double Mu = q1 ? q1_mass<double>(I.w, i, i1, i2, I.N) - q1_mass<double>(I.v, i, i1, i2, I.N) : u;
-    const double Mp = q1 ? q1_mass<double>(I.p, i, i1, i2, I.N) : p;
+    const double Mu = q1 ? q1_mass<double>(I.w, i, i1, i2, i3, I.N, I.dim) - q1_mass<double>(I.v, i, i1, i2, i3, I.N, I.dim) : u;
+    const double Mp = q1 ? q1_mass<double>(I.p, i, i1, i2, i3, I.N, I.dim) : p;
     r[0] = fabs(Ay - Mu - I.fhat[i]);
-    double dy = (q1 ? q1_mass<double>(I.y, i, i1, i2, I.N) - q1_mass<double>(I.yd, i, i1, i2, I.N)
+    double dy = (q1 ? q1_mass<double>(I.y, i, i1, i2, i3, I.N, I.dim) - q1_mass<double>(I.yd, i, i1, i2, i3, I.N, I.dim)
                     : obs_w(I, i) * (y - I.yd[i])) + ATp;
     double pc = nmax(nmax(w * lwa, (ub - w) * lwb), nmax(v * lva, (-ua - v) * lvb));
     if (I.has_y) {
@@ -131,7 +131,7 @@ __global__ void __launch_bounds__(kBS) k_newton_setup(const Inst* __restrict__ D
     if (q1) {
       // Sec. 4.2 with D_M = diag(M): [D_M/alpha - (1/alpha^2)(1/t_w + 1/t_v + 1/(alpha D_M))^-1]
       // = D_M^2 (t_w + t_v) / (alpha D_M (t_w + t_v) + t_w t_v), times D_M + Theta_y, square root
-      const double dm = kQ1MassDiag;
+      const double dm = q1_mass_diag(I.dim);
       sig = dm * dm * (tw + tv) / (I.alpha * dm * (tw + tv) + tw * tv);
       mh = sqrt(sig * (dm + ty));
     } else {
@@ -148,9 +148,9 @@ __global__ void __launch_bounds__(kBS) k_newton_setup(const Inst* __restrict__ D
     const double u = w - v;
     const double Ay = inst_op<double>(I, I.y, i, i1, i2, i3, false);
     const double ATp = inst_op<double>(I, I.p, i, i1, i2, i3, true);
-    const double Mu = q1 ? q1_mass<double>(I.w, i, i1, i2, I.N) - q1_mass<double>(I.v, i, i1, i2, I.N) : u;
-    const double Mp = q1 ? q1_mass<double>(I.p, i, i1, i2, I.N) : p;
-    const double Myd = q1 ? q1_mass<double>(I.y, i, i1, i2, I.N) - q1_mass<double>(I.yd, i, i1, i2, I.N)
+    const double Mu = q1 ? q1_mass<double>(I.w, i, i1, i2, i3, I.N, I.dim) - q1_mass<double>(I.v, i, i1, i2, i3, I.N, I.dim) : u;
+    const double Mp = q1 ? q1_mass<double>(I.p, i, i1, i2, i3, I.N, I.dim) : p;
+    const double Myd = q1 ? q1_mass<double>(I.y, i, i1, i2, i3, I.N, I.dim) - q1_mass<double>(I.yd, i, i1, i2, i3, I.N, I.dim)
                           : ow * (y - I.yd[i]);
     const double ry = -(Myd + ATp + by);
     const double rw = -(I.alpha * Mu + I.beta - Mp - mu / w + mu / gwb);

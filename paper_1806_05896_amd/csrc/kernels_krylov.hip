@@ -41,8 +41,8 @@ __device__ __forceinline__ void saddle_rows(const Inst& I, const double* __restr
   const double xp = x[3 * n + i];
   if (I.pde == 3) {
     // Q1 (Sec. 2): M in the (1,1) block, alpha M~ and the coupling M bar
-    const double My = q1_mass<double>(x, i, i1, i2, I.N), Mw = q1_mass<double>(x + n, i, i1, i2, I.N);
-    const double Mv = q1_mass<double>(x + 2 * n, i, i1, i2, I.N), Mp = q1_mass<double>(x + 3 * n, i, i1, i2, I.N);
+    const double My = q1_mass<double>(x, i, i1, i2, i3, I.N, I.dim), Mw = q1_mass<double>(x + n, i, i1, i2, i3, I.N, I.dim);
+    const double Mv = q1_mass<double>(x + 2 * n, i, i1, i2, i3, I.N, I.dim), Mp = q1_mass<double>(x + 3 * n, i, i1, i2, i3, I.N, I.dim);
     out[0] = s * (My + ty * xy + ATxp);
     out[1] = s * (a * (Mw - Mv) + tw * xw - Mp);
     out[2] = s * (-a * (Mw - Mv) + tv * xv + Mp);
@@ -65,9 +65,9 @@ __device__ __forceinline__ void saddle_rows_abs(const Inst& I, const double* __r
   const double ATxp = inst_op_abs(I, x + 3 * n, i, i1, i2, i3, true);
   const double Axy = inst_op_abs(I, x, i, i1, i2, i3, false);
   if (I.pde == 3) {
-    const double My = q1_mass<double, true>(x, i, i1, i2, I.N), Mw = q1_mass<double, true>(x + n, i, i1, i2, I.N);
-    const double Mv = q1_mass<double, true>(x + 2 * n, i, i1, i2, I.N);
-    const double Mp = q1_mass<double, true>(x + 3 * n, i, i1, i2, I.N);
+    const double My = q1_mass<double, true>(x, i, i1, i2, i3, I.N, I.dim), Mw = q1_mass<double, true>(x + n, i, i1, i2, i3, I.N, I.dim);
+    const double Mv = q1_mass<double, true>(x + 2 * n, i, i1, i2, i3, I.N, I.dim);
+    const double Mp = q1_mass<double, true>(x + 3 * n, i, i1, i2, i3, I.N, I.dim);
     out[0] = My + ty * xy + ATxp;
     out[1] = a * (Mw + Mv) + tw * xw + Mp;
     out[2] = a * (Mw + Mv) + tv * xv + Mp;
@@ -83,7 +83,7 @@ __device__ __forceinline__ void saddle_rows_abs(const Inst& I, const double* __r
 // Per-node inverse of the z block [a+t_w, -a; -a, a+t_v] (alpha M~ + Theta_z
 // with M = I; Sec. 4.1); for Q1 the paper's alpha D~_M + Theta_z, a = alpha D_M.
 __device__ __forceinline__ void apply_z_inv(const Inst& I, int i, double rw, double rv, double& zw, double& zv) {
-  const double tw = I.tw[i], tv = I.tv[i], a = I.pde == 3 ? I.alpha * kQ1MassDiag : I.alpha;
+  const double tw = I.tw[i], tv = I.tv[i], a = I.pde == 3 ? I.alpha * q1_mass_diag(I.dim) : I.alpha;
   const double det = a * (tw + tv) + tw * tv;
   zw = ((a + tv) * rw + a * rv) / det;
   zv = (a * rw + (a + tw) * rv) / det;
@@ -198,7 +198,7 @@ __global__ void __launch_bounds__(kBS) k_precond_diag(const Inst* __restrict__ D
 
 // Q1 (Sec. 4.1): z_y = (M + Theta_y)^-1 r_y approximated by Chebyshev
 // semi-iteration with the diagonal D_M + Theta_y, whose preconditioned
-// spectrum lies in [1/4, 9/4] (the Q1 mass-matrix bounds): with
+// spectrum lies in [1/4, 9/4] (the 2D Q1 mass-matrix bounds): with
 // theta, delta the centre and half-width of that interval and x_0 = 0,
 //   x_1 = d_0 = (D_M + Theta_y)^-1 r / theta,
 //   r_k = r_{k-1} - (M + Theta_y) d_{k-1},
@@ -310,6 +310,45 @@ __global__ void __launch_bounds__(kBS) k_cheb_block(const Inst* __restrict__ Dp,
   }
 }
 
+// The same semi-iteration for the trilinear mass (3D, D_M = 8/27, spectrum
+// [1/8, 27/8]), one step per launch: launch k >= 1 reads d_(k-1) over the
+// 27-point neighbourhood and r_(k-1) at the node (the input r itself for
+// k = 1) and writes r_k, d_k and x_(k+1) = x_k + d_k; launch 0 writes d_0
+// and x_1.  r and d sit in the q workspace by the parity of k (in: k & 1,
+// out: the other), so no thread overwrites a value another still reads.
+// Operands and guard as for k_cheb_block.
+__global__ void __launch_bounds__(kBS) k_cheb_step3(const Inst* __restrict__ Dp, const double* __restrict__ rx,
+                                                    double* __restrict__ zx, int j, int mpar, int k, ChebCoef cf,
+                                                    int guard) {
+  INST_BEGIN
+  if ((guard == 1 && I.ctrl->stop) || (guard == 2 && !I.ctrl->want_restart)) return;
+  const int n = I.n;
+  const int i = blockIdx.x * kBS + threadIdx.x;
+  if (i >= n) return;
+  const double* r = mpar >= 0 ? I.V[1 - mpar] : (rx ? rx : I.fV + (size_t)j * 4 * n);
+  double* z = mpar >= 0 ? I.Z[1 - mpar] : (zx ? zx : I.fZ + (size_t)j * 4 * n);
+  const int in = k & 1, out = 1 - in;
+  double* dout = I.Q + (size_t)(2 + out) * n;
+  const double ty = I.ty[i];
+  const double iv = 1.0 / (kQ1MassDiag3 + ty);
+  if (k == 0) {
+    const double d0 = r[i] * iv / cf.theta;
+    dout[i] = d0;
+    z[i] = d0;
+    return;
+  }
+  const double* rin = k == 1 ? r : I.Q + (size_t)in * n;
+  const double* din = I.Q + (size_t)(2 + in) * n;
+  int i1, i2, i3;
+  node_coords(i, I.N, 3, i1, i2, i3);
+  const double dv = din[i];
+  const double res = rin[i] - (q1_mass3<double>(din, i, i1, i2, i3, I.N) + ty * dv);
+  const double dn = cf.rho[k] * cf.rho[k - 1] * dv + (2.0 * cf.rho[k] / cf.delta) * res * iv;
+  I.Q[(size_t)out * n + i] = res;
+  dout[i] = dn;
+  z[i] += dn;
+}
+
 // P_T (Sec. 4, block lower triangular [A11 0; B -S_hat]): the p block solves
 // S_hat z_p = B z_A - r_p with B z_A = A z_y - z_w + z_v (M = I).
 template <typename T>
@@ -325,7 +364,7 @@ __global__ void __launch_bounds__(kBS) k_pt_rhs(const Inst* __restrict__ Dp, con
   const double* r = rx ? rx : I.fV + (size_t)j * 4 * n;
   const double* z = zx ? zx : I.fZ + (size_t)j * 4 * n;
   const double Bz = I.pde == 3 ? inst_op<double>(I, z, i, i1, i2, i3, false) -
-                                      (q1_mass<double>(z + n, i, i1, i2, I.N) - q1_mass<double>(z + 2 * n, i, i1, i2, I.N))
+                                      (q1_mass<double>(z + n, i, i1, i2, i3, I.N, I.dim) - q1_mass<double>(z + 2 * n, i, i1, i2, i3, I.N, I.dim))
                                 : inst_op<double>(I, z, i, i1, i2, i3, false) - z[n + i] + z[2 * n + i];
   ((T*)I.lv[0].b)[i] = (T)(Bz - r[3 * n + i]);
 }

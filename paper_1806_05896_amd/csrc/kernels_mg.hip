@@ -722,8 +722,8 @@ __global__ void __launch_bounds__(kBS) k_mg_scale_ty(const Inst* __restrict__ Dp
   const T* x = (const T*)((I.coarse_lev == 0 || !outsel) ? I.lv[0].x : I.lv[0].x2);
   if (I.pde == 3) {  // Q1: the middle factor of S_hat is M + Theta_y (Sec. 4.2)
     int i1, i2, i3;
-    node_coords(i, I.N, 2, i1, i2, i3);
-    ((T*)I.lv[0].b)[i] = q1_mass<T>(x, i, i1, i2, I.N) + (T)I.ty[i] * x[i];
+    node_coords(i, I.N, I.dim, i1, i2, i3);
+    ((T*)I.lv[0].b)[i] = q1_mass<T>(x, i, i1, i2, i3, I.N, I.dim) + (T)I.ty[i] * x[i];
     return;
   }
   ((T*)I.lv[0].b)[i] = (T)(obs_w(I, i) + I.ty[i]) * x[i];

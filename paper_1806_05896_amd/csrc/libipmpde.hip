@@ -253,7 +253,7 @@ static int set_coarse_lds_limit() {
 
 static bool is_p2(const ipmpde_problem* P) { return P->dim == 2 && P->pde == IPMPDE_POISSON; }
 // The padded single-workgroup coarse kernel: 2D Poisson (five-point) and Q1 (nine-point).
-static bool padded_coarse(const ipmpde_problem* P) { return is_p2(P) || P->pde == IPMPDE_POISSON_Q1; }
+static bool padded_coarse(const ipmpde_problem* P) { return is_p2(P) || (P->dim == 2 && P->pde == IPMPDE_POISSON_Q1); }
 
 // Reaction-term slots of every multigrid level (see k_mg_select): the
 // Schur-approximation operator's, and the two extra operators of P_Pi.
@@ -929,8 +929,9 @@ static double floor_factor() { return 16.0 * 2.220446049250313e-16; }
 static constexpr int kChebSteps = 20;
 
 // z_y = (M + Theta_y)^-1 r_y for every Q1 instance by Chebyshev
-// semi-iteration (Sec. 4.1) on the spectrum [1/4, 9/4] of the diagonally
-// scaled Q1 mass; operands as k_cheb_block takes them.
+// semi-iteration (Sec. 4.1) on the spectrum of the diagonally scaled Q1
+// mass, [1/4, 9/4] in 2D and [1/8, 27/8] in 3D; operands as k_cheb_block
+// takes them.
 // Steps per launch of the blocked kernel (the tile's halo) and its tile width.
 static constexpr int kChebBlockSteps = 5;
 static constexpr int kChebTile = 16;
@@ -938,10 +939,16 @@ static_assert(kChebSteps % kChebBlockSteps == 0, "whole launches of Chebyshev st
 
 static void cheb_apply(Group* G, const double* x, double* y, int j, int mpar, int guard, hipStream_t s) {
   ChebCoef cf;
-  cf.theta = 1.25;
-  cf.delta = 1.0;
+  const double lo = G->dim == 3 ? 1.0 / 8.0 : 1.0 / 4.0, hi = G->dim == 3 ? 27.0 / 8.0 : 9.0 / 4.0;
+  cf.theta = 0.5 * (hi + lo);
+  cf.delta = 0.5 * (hi - lo);
   cf.rho[0] = cf.delta / cf.theta;
   for (int k = 1; k < kChebSteps; ++k) cf.rho[k] = 1.0 / (2.0 * cf.theta / cf.delta - cf.rho[k - 1]);
+  if (G->dim == 3) {
+    for (int k = 0; k < kChebSteps; ++k)
+      hipLaunchKernelGGL(k_cheb_step3, gz(G, G->max_n), dim3(kBS), 0, s, G->D, x, y, j, mpar, k, cf, guard);
+    return;
+  }
   const int nt = div_up(G->maxN[0], kChebTile);
   for (int L = 0; L * kChebBlockSteps < kChebSteps; ++L)
     hipLaunchKernelGGL((k_cheb_block<kChebTile, kChebBlockSteps>), dim3(nt, nt, G->zc), dim3(kBS), 0, s, G->D, x, y,
@@ -1357,24 +1364,38 @@ static void fold_boundary(int dim, int N, int pde, double eps, const double* g, 
   }
 }
 
-// Q1 (divided by h^2): f_hat = M f - L_IB g with the interior mass stencil
-// (16, 4, 1) / 36 applied to f and the stiffness stencil's boundary
-// neighbours, -1 / (3 h^2) each over the eight neighbours, applied to g.
-static void fold_q1(int N, const double* f, const double* g, std::vector<double>& fhat) {
-  const double h = 1.0 / (N + 1);
-  const int P = N + 2;
-  for (int i2 = 0; i2 < N; ++i2)
-    for (int i1 = 0; i1 < N; ++i1) {
-      double acc = 0.0;
-      for (int b = -1; b <= 1; ++b)
-        for (int a = -1; a <= 1; ++a) {
-          const int j1 = i1 + a, j2 = i2 + b;
-          const bool inside = j1 >= 0 && j1 < N && j2 >= 0 && j2 < N;
-          if (inside && f) acc += (a == 0 && b == 0 ? 16.0 : (a == 0 || b == 0 ? 4.0 : 1.0)) / 36.0 * f[j1 + N * j2];
-          if (!inside && g) acc += g[(j1 + 1) + (size_t)P * (j2 + 1)] / (3.0 * h * h);
-        }
-      fhat[i1 + (size_t)N * i2] = acc;
-    }
+// Q1 (divided by h^dim): f_hat = M f - L_IB g with the interior mass stencil
+// applied to f and the stiffness stencil's boundary neighbours applied to g.
+// By the number k of nonzero offsets of a neighbour: 2D mass (16, 4, 1) / 36
+// and stiffness -1 / (3 h^2) for every neighbour; 3D mass (64, 16, 4, 1) / 216
+// and stiffness (0, -1/6, -1/12) / h^2 for k = 1, 2, 3.
+static void fold_q1(int dim, int N, const double* f, const double* g, std::vector<double>& fhat) {
+  const double h = 1.0 / (N + 1), ih2 = 1.0 / (h * h);
+  const size_t P = N + 2;
+  const int N3 = dim == 3 ? N : 1, r3 = dim == 3 ? 1 : 0;
+  for (int i3 = 0; i3 < N3; ++i3)
+    for (int i2 = 0; i2 < N; ++i2)
+      for (int i1 = 0; i1 < N; ++i1) {
+        double acc = 0.0;
+        for (int c = -r3; c <= r3; ++c)
+          for (int b = -1; b <= 1; ++b)
+            for (int a = -1; a <= 1; ++a) {
+              const int j1 = i1 + a, j2 = i2 + b, j3 = i3 + c;
+              const int k = (a != 0) + (b != 0) + (c != 0);
+              const bool inside = j1 >= 0 && j1 < N && j2 >= 0 && j2 < N && j3 >= 0 && j3 < N3;
+              double m, l;  // mass weight, minus the stiffness weight
+              if (dim == 2) {
+                m = (k == 0 ? 16.0 : k == 1 ? 4.0 : 1.0) / 36.0;
+                l = ih2 / 3.0;
+              } else {
+                m = (k == 0 ? 64.0 : k == 1 ? 16.0 : k == 2 ? 4.0 : 1.0) / 216.0;
+                l = k == 2 ? ih2 / 6.0 : (k == 3 ? ih2 / 12.0 : 0.0);
+              }
+              if (inside && f) acc += m * f[j1 + (size_t)N * (j2 + (size_t)N * j3)];
+              if (!inside && g) acc += l * g[(j1 + 1) + P * ((j2 + 1) + P * (size_t)(dim == 3 ? j3 + 1 : 0))];
+            }
+        fhat[i1 + (size_t)N * (i2 + (size_t)N * i3)] = acc;
+      }
 }
 
 extern "C" const char* ipmpde_version(void) { return "libipmpde 0.2 (gfx950)"; }
@@ -1473,7 +1494,7 @@ static int problem_create_impl(int dim, int N, int kind, double eps, int nt, dou
     if (y0)
       for (size_t i = 0; i < n2; ++i) fhat[i] += y0[i] / tau;
   } else if (kind == IPMPDE_POISSON_Q1) {
-    fold_q1(N, f, g, fhat);
+    fold_q1(dim, N, f, g, fhat);
   } else if (g) {
     fold_boundary(dim, N, kind, kind == IPMPDE_POISSON ? 1.0 : eps, g, fhat);
   }
@@ -1548,7 +1569,6 @@ extern "C" int ipmpde_problem_create(const ipmpde_grid* grid, const ipmpde_pde* 
   if (pde->kind == IPMPDE_HEAT) return fail(IPMPDE_EINVAL, "heat-equation problems are made by ipmpde_heat_create");
   if (pde->kind != IPMPDE_POISSON && pde->kind != IPMPDE_CONVDIFF && pde->kind != IPMPDE_POISSON_Q1)
     return fail(IPMPDE_EINVAL, "unknown pde kind");
-  if (pde->kind == IPMPDE_POISSON_Q1 && grid->dim != 2) return fail(IPMPDE_EINVAL, "Q1 elements are 2D only");
   if (pde->kind == IPMPDE_CONVDIFF && grid->dim != 2) return fail(IPMPDE_EINVAL, "convection-diffusion is 2D only");
   if (pde->kind == IPMPDE_CONVDIFF && !(pde->eps > 0 && std::isfinite(pde->eps)))
     return fail(IPMPDE_EINVAL, "eps must be positive");

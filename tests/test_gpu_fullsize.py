@@ -39,6 +39,8 @@ def _rel(a, b):
     ("poisson3d_127", {"beta": 1e-3}, {}),
     ("poisson3d_127", {"beta": 1e-2}, {}),
     ("poisson3d_127", {"beta": 1e-1}, {}),
+    ("poisson3d_q1", {"N": 63}, {"krylov": "fgmres", "precond": "pt"}),
+    ("poisson3d_q1", {"N": 63}, {}),
 ])
 def test_final_iterate_kkt_certificate(name, kw, opts_kw):
     """The GPU's final iterate satisfies the stopping test (Algorithm A.1, inf-norms of
@@ -106,27 +108,29 @@ def test_ipm_step_parity_at_511():
         assert _rel(a, b) <= 1e-6, (f, _rel(a, b))
 
 
-@pytest.mark.parametrize("name,opts_kw", [
-    ("poisson2d_511", {}),
-    ("poisson2d_511", {"krylov": "fgmres", "precond": "pt"}),
-    ("convdiff2d_255", {"krylov": "fgmres", "precond": "pt"}),
-    ("convdiff2d_255", {}),
-    ("poisson3d_127", {}),
-    ("heat2d", {"krylov": "fgmres", "precond": "pt"}),
-    ("heat2d", {}),
-    ("poisson2d_q1", {"krylov": "fgmres", "precond": "pt"}),
-    ("poisson2d_q1", {"krylov": "fgmres", "precond": "pd"}),
-    ("poisson2d_q1", {}),
+@pytest.mark.parametrize("name,kw,opts_kw", [
+    ("poisson2d_511", {}, {}),
+    ("poisson2d_511", {}, {"krylov": "fgmres", "precond": "pt"}),
+    ("convdiff2d_255", {}, {"krylov": "fgmres", "precond": "pt"}),
+    ("convdiff2d_255", {}, {}),
+    ("poisson3d_127", {}, {}),
+    ("heat2d", {}, {"krylov": "fgmres", "precond": "pt"}),
+    ("heat2d", {}, {}),
+    ("poisson2d_q1", {}, {"krylov": "fgmres", "precond": "pt"}),
+    ("poisson2d_q1", {}, {"krylov": "fgmres", "precond": "pd"}),
+    ("poisson2d_q1", {}, {}),
+    ("poisson3d_q1", {"N": 63}, {"krylov": "fgmres", "precond": "pt"}),
+    ("poisson3d_q1", {"N": 63}, {}),
 ])
-def test_newton_direction_solves_oracle_system(name, opts_kw):
+def test_newton_direction_solves_oracle_system(name, kw, opts_kw):
     """At the full sizes, from a mid-solve GPU state: the GPU Newton direction
     solves the oracle's own sparse FP64 system (eq. (NewtonSystem), assembled on
     the CPU from the same state) to the Krylov tolerance 1e-10, or to the FP64
     attainable-accuracy floor 16 eps |(|K||x| + |b|)| / |b| where that is larger."""
     from paper_1806_05896_amd import Options, Problem
-    data = W.by_name(name, seed=0)
+    data = W.by_name(name, seed=0, **kw)
     opts = Options(sigma=data.sigma, **opts_kw)
-    print(f"[newton-full] {name} {opts_kw}", flush=True)
+    print(f"[newton-full] {name} {kw} {opts_kw}", flush=True)
     with Problem(data) as prob:
         mu = 1.0
         for _ in range(3):
