@@ -60,7 +60,7 @@ enum {
 };
 
 enum { IPMPDE_POISSON = 0, IPMPDE_CONVDIFF = 1, IPMPDE_HEAT = 2 /* ipmpde_heat_create only */,
-       IPMPDE_POISSON_Q1 = 3 /* 2D Poisson with Q1 finite elements, see ipmpde_problem_create */ };
+       IPMPDE_POISSON_Q1 = 3 /* Poisson (2D or 3D) with Q1 finite elements, see ipmpde_problem_create */ };
 enum { IPMPDE_MINRES = 0, IPMPDE_FGMRES = 1 };
 enum { IPMPDE_PD = 0, IPMPDE_PT = 1, IPMPDE_PPI = 2 };
 enum { IPMPDE_FP64 = 0, IPMPDE_FP32 = 1 };
@@ -152,18 +152,25 @@ int ipmpde_set_allocator(ipmpde_alloc_fn alloc, ipmpde_free_fn free_, void* ctx)
  * (zero); g may be NULL (zero), else (N+2)^dim values.  alpha > 0, beta >= 0.
  * Returns IPMPDE_EINVAL for bad shapes, N != 2^k - 1, NaN/Inf, or bounds
  * that violate the above; IPMPDE_ENOMEM if device memory runs out. */
-/* pde->kind = IPMPDE_POISSON_Q1 (2D only): the same problem discretized with
- * bilinear finite elements as in the paper (Sec. 2, eq. (pb_fe_lin); Sec. 5):
- * stiffness L, consistent mass M, lumped mass D = h^2 I, all divided by h^2
- * (the lumped mass of a node, which leaves the minimizer unchanged):
+/* pde->kind = IPMPDE_POISSON_Q1 (dim 2 or 3): the same problem discretized
+ * with bilinear (2D) or trilinear (3D) finite elements as in the paper
+ * (Sec. 2, eq. (pb_fe_lin); Sec. 5): stiffness L, consistent mass M, lumped
+ * mass D = h^dim I, all divided by h^dim (the lumped mass of a node, which
+ * leaves the minimizer unchanged):
  *   minimize 1/2 (y - y_d)^T M (y - y_d) + alpha/2 u^T M u + beta |u|_1
  *   s.t. L y - M u = f_hat,  f_hat = M f - L_IB g,
- * with L = (8, -1 x 8) / (3 h^2) and M = (16, 4 x 4, 1 x 4) / 36 as nine-point
- * stencils.  MINRES + P_D, FGMRES + P_D or P_T (P_Pi: IPMPDE_EINVAL at
- * solve): (M + Theta_y)^-1 by 20 steps of Chebyshev semi-iteration with
- * D_M + Theta_y, alpha M~ + Theta_z by alpha D~_M + Theta_z, M_hat with D_M
- * (Sec. 4.1, 4.2), multigrid on L + M_hat.  No observation weights; batched
- * only with other Q1 problems; an engine serves them in groups of their own. */
+ * with, in 2D, L = (8, -1 x 8) / (3 h^2) and M = (16, 4 x 4, 1 x 4) / 36 as
+ * nine-point stencils and, in 3D, L = (8/3, 0 x 6, -1/6 x 12, -1/12 x 8) / h^2
+ * and M = (64, 16 x 6, 4 x 12, 1 x 8) / 216 over the node and its face, edge
+ * and corner neighbours.  MINRES + P_D, FGMRES + P_D or P_T (P_Pi:
+ * IPMPDE_EINVAL at solve): (M + Theta_y)^-1 by 20 steps of Chebyshev
+ * semi-iteration with D_M + Theta_y on the spectrum [1/4, 9/4] (2D) or
+ * [1/8, 27/8] (3D), alpha M~ + Theta_z by alpha D~_M + Theta_z, M_hat with
+ * D_M (Sec. 4.1, 4.2), multigrid on L + M_hat.  With active state bounds the
+ * FP32 multigrid loses the Schur approximation late in a solve (Theta_y
+ * above ~1e8); mg_precision FP64 solves those instances.  No observation
+ * weights; batched only with other Q1 problems; an engine serves them in
+ * groups of their own. */
 int ipmpde_problem_create(const ipmpde_grid* grid, const ipmpde_pde* pde, double alpha, double beta,
                           const double* u_a, const double* u_b, const double* y_a, const double* y_b,
                           const double* y_d, const double* f, const double* g, ipmpde_problem** out);
