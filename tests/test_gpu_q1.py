@@ -258,3 +258,35 @@ def test_q1_refusals():
             prob.set_observation(np.ones(data.n))
         with pytest.raises(Exception):
             Batch([prob, fd])
+
+
+def test_q1_sparsity_table_of_sec_5_1():
+    """The sparsity table of Sec. 5.1 (h = 2^-5, u in [-2, 1.5],
+    y_d = sin(pi x1) sin(pi x2)) solved on the GPU: for every (alpha, beta)
+    cell the control matches the oracle's and so do the sparsity count and
+    the sum of |u_i| (the oracle's agreement with the printed table is its
+    own pin)."""
+    _, Options, Problem = _api()
+    N = 31
+    x1, x2 = W.interior_coords(2, N)
+    for la in (-2, -4, -6):
+        for beta in (1e-1, 1e-2, 1e-3):
+            print(f"[q1 sparsity] alpha=1e{la} beta={beta:g}", flush=True)
+            d = W.poisson2d_q1(seed=0, N=N)
+            d.y_d = np.sin(math.pi * x1) * np.sin(math.pi * x2)
+            d.alpha, d.beta = 10.0 ** la, beta
+            d.u_a[:] = -2.0; d.u_b[:] = 1.5
+            d.y_a = d.y_b = None
+            ref = oracle.solve(d, IPMOptions(sigma=d.sigma))
+            with Problem(d) as prob:
+                rc = prob.solve(Options(sigma=d.sigma, krylov="fgmres", precond="pt", mg_precision="fp32"))
+                u = prob.query("u")
+                nli = prob.stats().nli
+            assert rc == 0 and nli == ref.nli
+            if beta < 0.1:
+                assert _rel(u, ref.u) <= 1e-6
+            else:  # the control vanishes; both sides end at interior-point residue
+                assert np.abs(u).max() < 1e-4 and np.abs(ref.u).max() < 1e-4
+            margin = np.abs(np.abs(ref.u) - 1e-2) > 1e-6  # decisions not at the threshold
+            assert np.array_equal((np.abs(u) < 1e-2)[margin], (np.abs(ref.u) < 1e-2)[margin])
+            assert abs(np.abs(u).sum() - np.abs(ref.u).sum()) <= 1e-6 * max(1.0, np.abs(ref.u).sum())
