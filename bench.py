@@ -177,27 +177,30 @@ def bench_heat(W, torch, N, nt, reps):
 def bench_q1(W, torch, N, reps, batch=8):
     """The 511^2 Poisson workload with Q1 finite elements (the paper's own
     discretization), one instance: MINRES + P_D and FGMRES(30) + P_T, FP32
-    V-cycles, 20 Chebyshev steps for the mass block; then `batch` instances
-    (seeds 0..batch-1) solved as one batch."""
+    and FP64 V-cycles, 20 Chebyshev steps for the mass block; then `batch`
+    instances solved as one batch (FP32)."""
     from paper_1806_05896_amd import Options, Problem
     d = W.poisson2d_q1(seed=0, N=N)
     stream = torch.cuda.current_stream()
     out = {"workload": f"poisson2d_q1: 2D Poisson {N}x{N}, Q1 elements, alpha=1e-4, beta=1e-3, u in [-5,5], "
                        "y in [-0.2,0.3], sigma=0.2"}
     with Problem(d) as p:
-        for name, kry, pre in (("minres_pd", "minres", "pd"), ("fgmres_pt", "fgmres", "pt")):
-            o = Options(sigma=d.sigma, krylov=kry, precond=pre, mg_precision="fp32")
-            p.solve(o, stream=stream)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                rc = p.solve(o, stream=stream)
-            torch.cuda.synchronize()
-            t = (time.perf_counter() - t0) / reps
-            s = p.stats()
-            log(f"q1 {N}^2 {name}: {1 / t:.2f} solves/s, nli {s.nli}, its {s.krylov_its}")
-            out[name] = {"solves_per_s": 1 / t, "ms_per_solve": t * 1e3, "nli": s.nli,
-                         "krylov_its_per_solve": s.krylov_its, "krylov_its_per_s": s.krylov_its / t, "status": rc}
+        for prec in ("fp32", "fp64"):
+            for name, kry, pre in (("minres_pd", "minres", "pd"), ("fgmres_pt", "fgmres", "pt")):
+                o = Options(sigma=d.sigma, krylov=kry, precond=pre, mg_precision=prec)
+                p.solve(o, stream=stream)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    rc = p.solve(o, stream=stream)
+                torch.cuda.synchronize()
+                t = (time.perf_counter() - t0) / reps
+                s = p.stats()
+                key = name if prec == "fp32" else f"{name}_fp64"
+                log(f"q1 {N}^2 {key}: {1 / t:.2f} solves/s, nli {s.nli}, its {s.krylov_its}")
+                out[key] = {"solves_per_s": 1 / t, "ms_per_solve": t * 1e3, "nli": s.nli,
+                            "krylov_its_per_solve": s.krylov_its, "krylov_its_per_s": s.krylov_its / t,
+                            "mg_precision": prec, "status": rc}
     if batch > 1:
         from paper_1806_05896_amd import Batch
         # seeds 1, 4, 7, 13 and 15 of this workload lose the interior under the
@@ -228,26 +231,77 @@ def bench_q1(W, torch, N, reps, batch=8):
 
 def bench_q1_3d(W, torch, N, reps):
     """The 127^3 Poisson workload with trilinear Q1 elements, one instance:
-    MINRES + P_D and FGMRES(30) + P_T, FP32 V-cycles, 20 Chebyshev steps."""
+    MINRES + P_D and FGMRES(30) + P_T, FP32 and FP64 V-cycles, 20 Chebyshev
+    steps."""
     from paper_1806_05896_amd import Options, Problem
     d = W.poisson3d_q1(seed=0, N=N)
     stream = torch.cuda.current_stream()
     out = {"workload": f"poisson3d_q1: 3D Poisson {N}^3, trilinear Q1 elements, alpha=1e-5, beta=1e-3, "
                        "u in [-10,10], sigma=0.2"}
     with Problem(d) as p:
-        for name, kry, pre in (("minres_pd", "minres", "pd"), ("fgmres_pt", "fgmres", "pt")):
-            o = Options(sigma=d.sigma, krylov=kry, precond=pre, mg_precision="fp32")
-            p.solve(o, stream=stream)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                rc = p.solve(o, stream=stream)
-            torch.cuda.synchronize()
-            t = (time.perf_counter() - t0) / reps
-            s = p.stats()
-            log(f"q1 3d {N}^3 {name}: {1 / t:.2f} solves/s, nli {s.nli}, its {s.krylov_its}")
-            out[name] = {"solves_per_s": 1 / t, "ms_per_solve": t * 1e3, "nli": s.nli,
-                         "krylov_its_per_solve": s.krylov_its, "krylov_its_per_s": s.krylov_its / t, "status": rc}
+        for prec in ("fp32", "fp64"):
+            for name, kry, pre in (("minres_pd", "minres", "pd"), ("fgmres_pt", "fgmres", "pt")):
+                o = Options(sigma=d.sigma, krylov=kry, precond=pre, mg_precision=prec)
+                p.solve(o, stream=stream)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    rc = p.solve(o, stream=stream)
+                torch.cuda.synchronize()
+                t = (time.perf_counter() - t0) / reps
+                s = p.stats()
+                key = name if prec == "fp32" else f"{name}_fp64"
+                log(f"q1 3d {N}^3 {key}: {1 / t:.2f} solves/s, nli {s.nli}, its {s.krylov_its}")
+                out[key] = {"solves_per_s": 1 / t, "ms_per_solve": t * 1e3, "nli": s.nli,
+                            "krylov_its_per_solve": s.krylov_its, "krylov_its_per_s": s.krylov_its / t,
+                            "mg_precision": prec, "status": rc}
+    return out
+
+
+def bench_q1_avli(W, torch):
+    """Average Krylov iterations per IPM step (AV-LI) of the Q1 Poisson problem
+    of Sec. 5.1 (u in [-2, 1.5], y_d = sin(pi x1) sin(pi x2), beta = 1e-2,
+    sigma = 0.2, 9 IPM iterations) for h = 2^-6 .. 2^-9 and alpha = 1e-2,
+    1e-4, 1e-6, with FGMRES + P_T and MINRES + P_D, under the default
+    multigrid (1 V-cycle, 2+2 sweeps, FP32), the same in FP64, and 3 cycles
+    of 5+5 sweeps in FP64, the cycle count and smoothing of the paper's AMG
+    (FP32 cycles after the first gain nothing: the FP32 residual of the
+    Poisson operator bottoms out near eps_32 times its condition number)."""
+    import math
+
+    import numpy as np
+
+    from paper_1806_05896_amd import Options, Problem
+    stream = torch.cuda.current_stream()
+    out = {}
+    for ell in (6, 7, 8, 9):
+        N = 2 ** ell - 1
+        x1, x2 = W.interior_coords(2, N)
+        for la in (-2, -4, -6):
+            d = W.poisson2d_q1(seed=0, N=N)
+            d.y_d = np.sin(math.pi * x1) * np.sin(math.pi * x2)
+            d.alpha, d.beta = 10.0 ** la, 1e-2
+            d.u_a[:] = -2.0
+            d.u_b[:] = 1.5
+            d.y_a = d.y_b = None
+            cell = {}
+            with Problem(d) as p:
+                for mg, kw in (("fp32 1x(2+2)", {"mg_precision": "fp32"}),
+                               ("fp64 1x(2+2)", {"mg_precision": "fp64"}),
+                               ("fp64 3x(5+5)", {"mg_precision": "fp64", "vcycles": 3, "nu_pre": 5, "nu_post": 5})):
+                    for name, kry, pre in (("P_T", "fgmres", "pt"), ("P_D", "minres", "pd")):
+                        o = Options(sigma=0.2, krylov=kry, precond=pre, fixed_nli=9, **kw)
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        rc = p.solve(o, stream=stream)
+                        torch.cuda.synchronize()
+                        t = time.perf_counter() - t0
+                        s = p.stats()
+                        cell[f"{name} {mg}"] = {"av_li": s.krylov_its / max(1, s.nli), "nli": s.nli,
+                                                "ms_per_solve": t * 1e3, "status": rc}
+            out[f"h=2^-{ell} alpha=1e{la}"] = cell
+            log(f"q1 av-li h=2^-{ell} alpha=1e{la}: " +
+                ", ".join(f"{k} {v['av_li']:.1f}" for k, v in cell.items()))
     return out
 
 
@@ -415,7 +469,7 @@ def main():
     ap.add_argument("--heat-batch", type=int, default=16, help="instances of the batched heat run (0: skip)")
     ap.add_argument("--q1-N", type=int, default=511, help="grid of the Q1 finite-element run (0: skip)")
     ap.add_argument("--q1-3d-N", type=int, default=127, help="grid of the 3D Q1 run (0: skip)")
-    ap.add_argument("--only", choices=["serve", "batch", "partial", "heat", "q1", "q1_3d"], default=None,
+    ap.add_argument("--only", choices=["serve", "batch", "partial", "heat", "q1", "q1_3d", "q1_avli"], default=None,
                     help="run one extra section alone")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only launch the roofline kernel (20 times) and a 1 GiB device copy, for counter runs")
@@ -445,6 +499,9 @@ def main():
         return
     if args.only == "q1":
         print(json.dumps({"q1": bench_q1(W, torch, args.q1_N, 3)}), flush=True)
+        return
+    if args.only == "q1_avli":
+        print(json.dumps({"q1_avli": bench_q1_avli(W, torch)}), flush=True)
         return
     if args.only == "q1_3d":
         print(json.dumps({"q1_3d": bench_q1_3d(W, torch, args.q1_3d_N, 2)}), flush=True)
