@@ -65,6 +65,7 @@ enum { IPMPDE_MINRES = 0, IPMPDE_FGMRES = 1 };
 enum { IPMPDE_PD = 0, IPMPDE_PT = 1, IPMPDE_PPI = 2 };
 enum { IPMPDE_FP64 = 0, IPMPDE_FP32 = 1 };
 enum { IPMPDE_MU_PAPER = 0, IPMPDE_MU_CENTRAL = 1 };
+enum { IPMPDE_MASS_UNIT = 0, IPMPDE_MASS_HD = 1 };
 
 /* Fields for ipmpde_query / ipmpde_set_field (each n doubles). */
 enum {
@@ -105,6 +106,16 @@ typedef struct {
                           sigma times the mean complementarity product of the iterate
                           (the duality measure; equal on the central path, and robust when
                           step lengths collapse) */
+  int mass_scaling;    /* IPMPDE_MASS_UNIT (default): the problem divided by the lumped mass
+                          w = h^dim of a node (mesh-independent mu and tolerances), or
+                          IPMPDE_MASS_HD: the literal weighting of eq. (pb_fe_lin), objective and
+                          state equation times w.  Both have the same minimizer, and the HD run
+                          takes the UNIT run's steps from mu0 / w with the tolerances divided by
+                          w; under HD, mu and the measures in the statistics, the bound
+                          multipliers and the Theta fields (query and set_field) and the mu
+                          argument of the single-step entry points are in HD units (w times
+                          the unit ones).  Stationary problems only (IPMPDE_EINVAL for the heat
+                          equation and in an engine). */
 } ipmpde_options;
 
 #define IPMPDE_MAX_HIST 256

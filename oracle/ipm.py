@@ -76,6 +76,8 @@ class IPMOptions:
     fixed_nli: int = 0          # > 0: take exactly this many Newton steps
     newton: str = "auto"        # "full" (4n system) | "schur" (eliminated, SPD in dp) | "auto"
     mu_rule: str = "paper"      # "paper": mu^{k+1} = sigma mu^k | "central": sigma * mean product
+    mass_scaling: str = "unit"  # "unit": the problem divided by the lumped mass h^d of a node |
+                                # "hd": the literal weighting, objective and constraint times h^d
 
 
 @dataclass
@@ -366,10 +368,31 @@ def ipm_step(prob, disc, st: IPMState, opts: IPMOptions, mu_new: float, mode: st
     return nxt, {"alpha_P": aP, "alpha_D": aD, "dy": dy, "dw": dw, "dv": dv, "dp": dp}
 
 
+def hd_weighted(prob, disc: Discretization) -> Discretization:
+    """The literal h^d weighting of eq. (pb_fe_lin): every mass, the L1 weights
+    and the state equation carry the lumped mass w = h^d of a node (M = D = w I
+    for finite differences, w times the scaled masses for Q1), where the unit
+    form divides them out."""
+    h = 1.0 / (prob.N + 1)
+    w = h ** prob.dim
+    n = disc.n
+    Mt = disc.Mt if disc.Mt is not None else sp.diags(_obs(prob))
+    Mc = disc.Mc if disc.Mc is not None else sp.identity(n, format="csr")
+    dl = disc.dl if disc.dl is not None else np.ones(n)
+    return Discretization(disc.dim, disc.N, (w * disc.A).tocsr(), w * disc.f_hat,
+                          Mt=(w * Mt).tocsr(), Mc=(w * Mc).tocsr(), dl=w * np.asarray(dl))
+
+
 def solve(prob, opts: Optional[IPMOptions] = None) -> IPMResult:
     """Algorithm A.1 (Appendix) on the problem described by a workloads.ProblemData."""
     opts = opts or IPMOptions()
     disc = discretize(prob)
+    if opts.mass_scaling == "hd":
+        if prob.pde == "heat":
+            raise ValueError("the h^d weighting is defined for the stationary problems")
+        disc = hd_weighted(prob, disc)
+    elif opts.mass_scaling != "unit":
+        raise ValueError(opts.mass_scaling)
     st = initial_state(prob, opts)
     hist = []
     status = "maxit"

@@ -16,6 +16,7 @@ MINRES, FGMRES = 0, 1
 PD, PT, PPI = 0, 1, 2
 FP64, FP32 = 0, 1
 MU_PAPER, MU_CENTRAL = 0, 1
+MASS_UNIT, MASS_HD = 0, 1
 MAX_HIST = 256
 
 FIELDS = {
@@ -43,7 +44,7 @@ class COptions(C.Structure):
         ("krylov", C.c_int), ("precond", C.c_int), ("restart", C.c_int), ("krylov_tol", C.c_double),
         ("krylov_maxit", C.c_int), ("vcycles", C.c_int), ("nu_pre", C.c_int), ("nu_post", C.c_int),
         ("omega", C.c_double), ("mg_precision", C.c_int), ("chunk", C.c_int), ("use_graphs", C.c_int),
-        ("mu_rule", C.c_int),
+        ("mu_rule", C.c_int), ("mass_scaling", C.c_int),
     ]
 
 

@@ -64,6 +64,7 @@ class Options:
     chunk: int = 8
     use_graphs: bool = True
     mu_rule: str = "paper"          # "paper" (sigma mu^k) | "central" (sigma x mean complementarity)
+    mass_scaling: str = "unit"      # "unit" (divided by the lumped mass h^d) | "hd" (literal weighting)
 
     def to_c(self) -> L.COptions:
         o = L.COptions()
@@ -79,6 +80,8 @@ class Options:
                 v = int(bool(v))
             elif f.name == "mu_rule":
                 v = {"paper": L.MU_PAPER, "central": L.MU_CENTRAL}[v]
+            elif f.name == "mass_scaling":
+                v = {"unit": L.MASS_UNIT, "hd": L.MASS_HD}[v]
             setattr(o, f.name, v)
         return o
 

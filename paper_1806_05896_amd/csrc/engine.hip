@@ -104,6 +104,8 @@ extern "C" int ipmpde_engine_submit(ipmpde_engine* E, ipmpde_problem* P, const i
   if (P->pde == IPMPDE_HEAT) return fail(IPMPDE_EINVAL, "heat-equation problems are not served by the engine");
   ipmpde_options o;
   TRY(resolve_opts(opts, &o));
+  if (o.mass_scaling != IPMPDE_MASS_UNIT) return fail(IPMPDE_EINVAL, "the engine serves the unit-mass form only");
+  P->rep = 1.0;
   ipmpde_grid g{P->dim, P->N};
   ipmpde_pde d{P->pde, P->eps};
   const size_t bytes = ipmpde_footprint_bytes(&g, &d, P->has_y ? 1 : 0, &o);

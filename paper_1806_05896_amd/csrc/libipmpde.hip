@@ -186,6 +186,10 @@ struct ipmpde_problem {
   Group hview;           // D = hs_d + t (one step, zc = 1) or hs_d (all steps, zc = nt)
   ipmpde_stats stats;
   double mu = 1.0;
+  // w of the options last applied: 1 for the unit form, the lumped mass h^dim
+  // of a node under IPMPDE_MASS_HD (reported mu, measures, multipliers and
+  // Theta are w times the internal unit-form values)
+  double rep = 1.0;
   bool setup_done = false;
   int setup_fp32 = -1;
   const Group* setup_group = nullptr;  // group whose descriptors hold the last Newton setup
@@ -654,6 +658,7 @@ extern "C" int ipmpde_default_options(ipmpde_options* o) {
   o->chunk = 8;
   o->use_graphs = 1;
   o->mu_rule = IPMPDE_MU_PAPER;
+  o->mass_scaling = IPMPDE_MASS_UNIT;
   return IPMPDE_OK;
 }
 
@@ -682,6 +687,8 @@ static int check_options(const ipmpde_options& o) {
   if (o.mg_precision != IPMPDE_FP32 && o.mg_precision != IPMPDE_FP64) return fail(IPMPDE_EINVAL, "bad mg_precision");
   if (o.chunk < 2 || o.chunk > 64 || (o.chunk & 1)) return fail(IPMPDE_EINVAL, "chunk must be even in [2,64]");
   if (o.mu_rule != IPMPDE_MU_PAPER && o.mu_rule != IPMPDE_MU_CENTRAL) return fail(IPMPDE_EINVAL, "bad mu_rule");
+  if (o.mass_scaling != IPMPDE_MASS_UNIT && o.mass_scaling != IPMPDE_MASS_HD)
+    return fail(IPMPDE_EINVAL, "bad mass_scaling");
   return IPMPDE_OK;
 }
 
@@ -689,6 +696,26 @@ static int resolve_opts(const ipmpde_options* in, ipmpde_options* out) {
   if (in) *out = *in;
   else ipmpde_default_options(out);
   return check_options(*out);
+}
+
+// The literal weighting of eq. (pb_fe_lin) multiplies the objective and the
+// state equation by the lumped mass w = h^dim of a node; the device always
+// runs the unit form (everything divided by w), which takes the same Newton
+// steps when mu0 and the tolerances are divided by w.  Returns the unit-form
+// options and records w for reporting.
+static int unit_form(ipmpde_problem* P, const ipmpde_options& o, ipmpde_options* u) {
+  *u = o;
+  P->rep = 1.0;
+  if (o.mass_scaling != IPMPDE_MASS_HD) return IPMPDE_OK;
+  if (P->pde == IPMPDE_HEAT) return fail(IPMPDE_EINVAL, "the h^d weighting is defined for the stationary problems");
+  const double h = 1.0 / (P->N + 1);
+  const double w = P->dim == 3 ? h * h * h : h * h;
+  u->mu0 /= w;
+  u->eps_p /= w;
+  u->eps_d /= w;
+  u->eps_c /= w;
+  P->rep = w;
+  return IPMPDE_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1245,15 +1272,16 @@ static int ipm_check(Group* G, int i, int k, const ipmpde_options& oi) {
   ipmpde_problem* P = G->probs[i];
   ipmpde_stats& st = P->stats;
   const double xp = G->stat_h[16 * i], xd = G->stat_h[16 * i + 1], xc = G->stat_h[16 * i + 2];
+  const double w = P->rep;
   if (k < IPMPDE_MAX_HIST) {
-    st.hist_mu[k] = P->mu;
-    st.hist_xi_p[k] = xp;
-    st.hist_xi_d[k] = xd;
-    st.hist_xi_c[k] = xc;
+    st.hist_mu[k] = w * P->mu;
+    st.hist_xi_p[k] = w * xp;
+    st.hist_xi_d[k] = w * xd;
+    st.hist_xi_c[k] = w * xc;
     st.hist_len = k + 1;
   }
   st.nli = k;
-  st.xi_p = xp; st.xi_d = xd; st.xi_c = xc; st.mu = P->mu;
+  st.xi_p = w * xp; st.xi_d = w * xd; st.xi_c = w * xc; st.mu = w * P->mu;
   int finish = -1;
   if (!(xp == xp && xd == xd && xc == xc)) finish = IPMPDE_EBREAKDOWN;
   else if (oi.fixed_nli > 0 ? k >= oi.fixed_nli : (xp <= oi.eps_p && xd <= oi.eps_d && xc <= oi.eps_c))
@@ -1296,8 +1324,10 @@ static int ipm_after_step(Group* G, int i, int k) {
 // leaves the loop (and every later launch) when its own test is met.  po:
 // per-instance options (IPM fields may differ; Krylov/multigrid fields must
 // match).  Per-instance status goes to the problems' stats.
-static int solve_group(Group* G, const std::vector<ipmpde_options>& po, hipStream_t s) {
+static int solve_group(Group* G, const std::vector<ipmpde_options>& po_in, hipStream_t s) {
   auto t0 = std::chrono::steady_clock::now();
+  std::vector<ipmpde_options> po(po_in.size());
+  for (int i = 0; i < G->count; ++i) TRY(unit_form(G->probs[i], po_in[i], &po[i]));
   const ipmpde_options& o = po[0];
   for (int i = 0; i < G->count; ++i) ipm_begin(G->probs[i]);
   TRY(group_select(G, o));
@@ -1638,8 +1668,9 @@ extern "C" int ipmpde_solve(ipmpde_problem* P, const ipmpde_options* opts, ipmpd
 
 extern "C" int ipmpde_reset(ipmpde_problem* P, const ipmpde_options* opts, ipmpde_stream stream) {
   if (!P) return fail(IPMPDE_EINVAL, "problem is NULL");
-  ipmpde_options o;
-  TRY(resolve_opts(opts, &o));
+  ipmpde_options oi, o;
+  TRY(resolve_opts(opts, &oi));
+  TRY(unit_form(P, oi, &o));
   TRY(ensure_self(P, S(stream)));
   TRY(group_select(P->self, o));
   return group_reset(P->self, {o}, S(stream));
@@ -1664,8 +1695,10 @@ extern "C" int ipmpde_ipm_step(ipmpde_problem* P, const ipmpde_options* opts, do
                                double* alpha_p, double* alpha_d, int* krylov_its, double* relres) {
   if (!P) return fail(IPMPDE_EINVAL, "problem is NULL");
   if (!(mu_new > 0)) return fail(IPMPDE_EINVAL, "mu_new must be positive");
-  ipmpde_options o;
-  TRY(resolve_opts(opts, &o));
+  ipmpde_options oi, o;
+  TRY(resolve_opts(opts, &oi));
+  TRY(unit_form(P, oi, &o));
+  mu_new /= P->rep;
   hipStream_t s = S(stream);
   int its = 0;
   double rel = 0;
@@ -1688,8 +1721,10 @@ extern "C" int ipmpde_ipm_step(ipmpde_problem* P, const ipmpde_options* opts, do
 extern "C" int ipmpde_newton_setup(ipmpde_problem* P, const ipmpde_options* opts, double mu_new, ipmpde_stream stream) {
   if (!P) return fail(IPMPDE_EINVAL, "problem is NULL");
   if (!(mu_new > 0)) return fail(IPMPDE_EINVAL, "mu_new must be positive");
-  ipmpde_options o;
-  TRY(resolve_opts(opts, &o));
+  ipmpde_options oi, o;
+  TRY(resolve_opts(opts, &oi));
+  TRY(unit_form(P, oi, &o));
+  mu_new /= P->rep;
   TRY(ensure_self(P, S(stream)));
   Group* G = P->self;
   G->H[0].active = 1;
@@ -1703,9 +1738,10 @@ extern "C" int ipmpde_newton_direction(ipmpde_problem* P, const ipmpde_options* 
                                        ipmpde_stream stream, int* krylov_its, double* relres) {
   if (!P) return fail(IPMPDE_EINVAL, "problem is NULL");
   if (!(mu_new > 0)) return fail(IPMPDE_EINVAL, "mu_new must be positive");
-  ipmpde_options o;
-  TRY(resolve_opts(opts, &o));
-  const int rc = single_newton(P, o, mu_new, S(stream), krylov_its, relres);
+  ipmpde_options oi, o;
+  TRY(resolve_opts(opts, &oi));
+  TRY(unit_form(P, oi, &o));
+  const int rc = single_newton(P, o, mu_new / P->rep, S(stream), krylov_its, relres);
   if (rc == IPMPDE_EKRYLOV) return fail(rc, "Krylov tolerance not reached");
   if (rc != IPMPDE_OK) return fail(rc, "Newton solve broke down");
   return IPMPDE_OK;
@@ -1717,9 +1753,9 @@ extern "C" int ipmpde_measures(ipmpde_problem* P, ipmpde_stream stream, double* 
   Group* G = P->self;
   G->H[0].active = 1;
   TRY(group_measures(G, S(stream)));
-  *xp = G->stat_h[0];
-  *xd = G->stat_h[1];
-  *xc = G->stat_h[2];
+  *xp = P->rep * G->stat_h[0];
+  *xd = P->rep * G->stat_h[1];
+  *xc = P->rep * G->stat_h[2];
   return IPMPDE_OK;
 }
 
@@ -1781,6 +1817,13 @@ extern "C" int ipmpde_set_observation(ipmpde_problem* P, const double* weights, 
   return IPMPDE_OK;
 }
 
+// Fields reported in HD units under IPMPDE_MASS_HD: the bound multipliers and
+// the barrier diagonals Theta (w times their unit-form values).
+static bool hd_scaled(int field) {
+  return (field >= IPMPDE_FIELD_LAM_YA && field <= IPMPDE_FIELD_LAM_VB) ||
+         (field >= IPMPDE_FIELD_THETA_Y && field <= IPMPDE_FIELD_THETA_V);
+}
+
 extern "C" int ipmpde_query(const ipmpde_problem* P, int field, double* out, size_t count) {
   if (!P || !out) return fail(IPMPDE_EINVAL, "NULL argument");
   if (count != (size_t)P->n) return fail(IPMPDE_EINVAL, "count must equal the number of nodes");
@@ -1802,6 +1845,8 @@ extern "C" int ipmpde_query(const ipmpde_problem* P, int field, double* out, siz
   }
   if (!src) return fail(IPMPDE_EINVAL, "field not present (no state bounds)");
   HIP_TRY(hipMemcpy(out, src, count * 8, hipMemcpyDeviceToHost));
+  if (P->rep != 1.0 && hd_scaled(field))
+    for (size_t i = 0; i < count; ++i) out[i] *= P->rep;
   return IPMPDE_OK;
 }
 
@@ -1817,6 +1862,12 @@ extern "C" int ipmpde_set_field(ipmpde_problem* P, int field, const double* in, 
   double* dst = (double*)field_ptr(P, field, &kind);
   if (!dst) return fail(IPMPDE_EINVAL, "field not present (no state bounds)");
   HIP_TRY(hipDeviceSynchronize());
+  if (P->rep != 1.0 && hd_scaled(field)) {
+    std::vector<double> v(in, in + count);
+    for (double& x : v) x /= P->rep;
+    HIP_TRY(hipMemcpy(dst, v.data(), count * 8, hipMemcpyHostToDevice));
+    return IPMPDE_OK;
+  }
   HIP_TRY(hipMemcpy(dst, in, count * 8, hipMemcpyHostToDevice));
   return IPMPDE_OK;
 }

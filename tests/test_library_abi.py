@@ -51,6 +51,32 @@ def test_struct_layouts_match_header(lib):
     assert lib.ipmpde_version().decode().startswith("libipmpde")
 
 
+def test_binding_structs_match_the_c_compiler(tmp_path):
+    """Sizes and field offsets of the binding's option and statistics structs
+    equal those a C compiler gives the header's declarations."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "ipmpde.h"\n'
+                   'int main(void) { printf("%zu %zu %zu %zu %zu\\n", sizeof(ipmpde_options), '
+                   'offsetof(ipmpde_options, mu_rule), offsetof(ipmpde_options, mass_scaling), '
+                   'sizeof(ipmpde_stats), offsetof(ipmpde_stats, hist_krylov_relres)); return 0; }\n')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    want = [C.sizeof(L.COptions), L.COptions.mu_rule.offset, L.COptions.mass_scaling.offset,
+            C.sizeof(L.CStats), L.CStats.hist_krylov_relres.offset]
+    assert got == want
+
+
+def test_default_options_use_the_unit_mass_form(lib):
+    o = L.COptions()
+    assert lib.ipmpde_default_options(C.byref(o)) == L.OK
+    assert o.mass_scaling == L.MASS_UNIT and o.mu0 == 1.0 and o.eps_p == 1e-6
+
+
 def _create(lib, dim=2, N=7, pde=L.POISSON, eps=1.0, alpha=1e-2, beta=1e-3, ua=-1.0, ub=1.0, ya=None, yb=None,
             yd=None):
     n = N ** dim

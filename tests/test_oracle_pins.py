@@ -726,3 +726,32 @@ def test_q1_sparsity_table_of_sec_5_1():
             assert l1 / 1.5 <= s <= l1 * 1.5, (la, beta, s, l1)
         else:
             assert np.abs(r.u).max() < 1e-4
+
+
+@pytest.mark.parametrize("case", ["fd_box", "fd_plain", "q1"])
+def test_hd_weighting_is_the_unit_run_rescaled(case):
+    """The literal h^d weighting (every mass, the L1 weights and the state
+    equation times the lumped mass w = h^d) run through its own arithmetic (the
+    assembled 4n system with explicit masses) takes the same steps as the
+    unit form started from mu0 / w with the tolerances divided by w: equal
+    iteration counts and iterates y, u, p, bound multipliers w times the unit
+    ones, and mu and the measures w times the unit ones at every iteration."""
+    if case == "fd_box":
+        p = W.poisson2d_511(seed=0, N=15)
+    elif case == "fd_plain":
+        p = W.poisson2d_small(seed=0, N=15)
+    else:
+        p = W.poisson2d_q1(seed=0, N=15)
+    w = (1.0 / (p.N + 1)) ** p.dim
+    hd = oracle.solve(p, IPMOptions(sigma=p.sigma, mass_scaling="hd"))
+    un = oracle.solve(p, IPMOptions(sigma=p.sigma, mu0=1.0 / w, eps_p=1e-6 / w, eps_d=1e-6 / w, eps_c=1e-6 / w))
+    assert hd.status == un.status == "converged" and hd.nli == un.nli
+    for a, b in ((hd.u, un.u), (hd.y, un.y), (hd.p, un.p)):
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-8 * np.abs(b).max())
+    for f in ("lwa", "lwb", "lva", "lvb") + (("lya", "lyb") if p.y_a is not None else ()):
+        a, b = getattr(hd.state, f), w * getattr(un.state, f)
+        np.testing.assert_allclose(a, b, rtol=1e-6, atol=1e-12 * np.abs(b).max())
+    for rh, ru in zip(hd.history, un.history):
+        assert rh["mu"] == pytest.approx(w * ru["mu"], rel=1e-12)
+        for key in ("xi_p", "xi_d", "xi_c"):
+            assert rh[key] == pytest.approx(w * ru[key], rel=1e-5, abs=1e-14)
