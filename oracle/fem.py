@@ -16,6 +16,11 @@ assembled here element by element from the element matrices of a square
 boundary columns of L and the source through M: f_hat = M_II f_I - L_IB g_B
 (the boundary part of M f is dropped with f given at interior nodes only).
 
+Partial observation (Sec. 4.3): the tracking term integrates over the
+observed subdomain only, so its mass is assembled from the observed
+elements; `obs` then holds one weight per element ((N+1)^d values, element
+numbered by its lower corner, x1 fastest), 1 observed and 0 not.
+
 The problem handed to the interior point method is eq. (pb_fe_lin) divided
 by h^d, the lumped mass of a node (the finite-element counterpart of the
 unit-mass form of fd.py): L / h^d, M / h^d (rows summing to 1 away from the
@@ -109,6 +114,36 @@ def _full_matrices(N: int, dim: int = 2):
     return L, M
 
 
+def _weighted_mass(N: int, dim: int, elem_w) -> sp.csr_matrix:
+    """Mass over all (N+2)^d nodes with element e's integrals multiplied by
+    elem_w[e] (partial observation, Sec. 4.3: the mass of the observed
+    subdomain is assembled from its elements only).  Elements are numbered
+    by their lower corner (e1, e2[, e3]) in 0..N, x1 fastest."""
+    h = 1.0 / (N + 1)
+    P = N + 2
+    _, Me = _element_matrices(h) if dim == 2 else _element_matrices_3d(h)
+    e = np.arange(N + 1)
+    if dim == 2:
+        e2, e1 = np.meshgrid(e, e, indexing="ij")
+        base = (e1 + P * e2).reshape(-1)
+        # local nodes of _element_matrices: (0,0), (1,0), (1,1), (0,1)
+        off = [0, 1, 1 + P, P]
+    else:
+        e3, e2, e1 = np.meshgrid(e, e, e, indexing="ij")
+        base = (e1 + P * e2 + P * P * e3).reshape(-1)
+        off = [(a & 1) + P * ((a >> 1) & 1) + P * P * ((a >> 2) & 1) for a in range(8)]
+    ew = np.asarray(elem_w, dtype=np.float64).reshape(-1)
+    if ew.size != base.size:
+        raise ValueError("one weight per element, (N+1)^d values")
+    k = len(off)
+    rows = np.concatenate([base + off[a] for a in range(k) for b in range(k)])
+    cols = np.concatenate([base + off[b] for a in range(k) for b in range(k)])
+    vals = np.concatenate([Me[a, b] * ew for a in range(k) for b in range(k)])
+    M = sp.csr_matrix((vals, (rows, cols)), shape=(P ** dim, P ** dim))
+    M.sum_duplicates()
+    return M
+
+
 def _interior_index(N: int, dim: int = 2) -> np.ndarray:
     P = N + 2
     r = np.arange(1, N + 1)
@@ -144,5 +179,8 @@ def discretize_q1(prob) -> Discretization:
         gg[I] = 0.0
         f_hat = f_hat - (Lf @ gg)[I]
     s = 1.0 / h ** dim
-    return Discretization(dim, N, (L * s).tocsr(), f_hat * s, Mt=(M * s).tocsr(), Mc=(M * s).tocsr(),
+    Mt = M
+    if getattr(prob, "obs", None) is not None:  # observed elements only (Sec. 4.3)
+        Mt = _weighted_mass(N, dim, prob.obs)[I][:, I].tocsr()
+    return Discretization(dim, N, (L * s).tocsr(), f_hat * s, Mt=(Mt * s).tocsr(), Mc=(M * s).tocsr(),
                           dl=np.ones(n))

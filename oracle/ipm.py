@@ -281,9 +281,8 @@ def newton_solve(prob, disc: Discretization, st: IPMState, mu: float, mode: str 
             mode = "full" if prob.n <= 30000 else "schur"
         else:
             mode = "full" if (prob.dim == 2 and prob.N <= 127) or (prob.dim == 3 and prob.N <= 31) else "schur"
-        if not np.all(_obs(prob) + ty > 0):  # (1,1) block singular (R9): no elimination of dy
-            mode = "full"
-        if _fem(disc):  # non-diagonal masses: no per-node elimination
+        if _fem(disc) or not np.all(_obs(prob) + ty > 0):
+            # non-diagonal masses, or a singular (1,1) block (R9): no per-node elimination
             mode = "full"
     rhs = newton_rhs(prob, disc, st, mu)
     if mode == "full":

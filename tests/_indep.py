@@ -232,14 +232,45 @@ def dense_q1_3d(N):
     return K, M
 
 
-def fista_weighted(K, M, dl, yd, fhat, alpha, beta, ua, ub, iters=200000, tol=1e-15):
-    """min_u 1/2 (y - yd)^T M (y - yd) + alpha/2 u^T M u + beta sum_i dl_i |u_i|
-    with K y = M u + fhat and ua <= u <= ub (the finite-element problem),
-    by FISTA on u with a per-node weighted soft threshold."""
+def dense_q1_observed(N, elem_w):
+    """2D Q1 mass of the observed elements only: node by node, the sum over
+    the (up to) four elements around it of the element's weight times its
+    mass stencil, h^2/36 times 4 (the node), 2 (an edge neighbour in that
+    element) and 1 (the opposite corner); elements are numbered by their
+    lower corner (e1, e2) in 0..N of the (N+2)^2 grid, e1 fastest."""
+    h = 1.0 / (N + 1)
+    n = N * N
+    ew = np.asarray(elem_w).reshape(N + 1, N + 1)  # [e2, e1]
+    M = np.zeros((n, n))
+    for i2 in range(N):
+        for i1 in range(N):
+            r = i1 + N * i2
+            g1, g2 = i1 + 1, i2 + 1  # position on the (N+2)^2 grid
+            for e2 in (g2 - 1, g2):
+                for e1 in (g1 - 1, g1):
+                    c = ew[e2, e1]
+                    if c == 0:
+                        continue
+                    for n2 in (e2, e2 + 1):
+                        for n1 in (e1, e1 + 1):
+                            j1, j2 = n1 - 1, n2 - 1
+                            if not (0 <= j1 < N and 0 <= j2 < N):
+                                continue
+                            d = (n1 != g1) + (n2 != g2)
+                            M[r, j1 + N * j2] += c * h * h * (4.0, 2.0, 1.0)[d] / 36.0
+    return M
+
+
+def fista_weighted(K, M, dl, yd, fhat, alpha, beta, ua, ub, iters=200000, tol=1e-15, Mt=None):
+    """min_u 1/2 (y - yd)^T Mt (y - yd) + alpha/2 u^T M u + beta sum_i dl_i |u_i|
+    with K y = M u + fhat and ua <= u <= ub (the finite-element problem;
+    Mt = M unless a tracking mass is given), by FISTA on u with a per-node
+    weighted soft threshold."""
+    Mt = M if Mt is None else Mt
     Kinv = np.linalg.inv(K)
     G = Kinv @ M                       # y = G u + Kinv fhat
-    H = G.T @ M @ G + alpha * M        # Hessian in u
-    c = G.T @ M @ (Kinv @ fhat - yd)
+    H = G.T @ Mt @ G + alpha * M       # Hessian in u
+    c = G.T @ Mt @ (Kinv @ fhat - yd)
     L = np.linalg.eigvalsh(H).max()
     u = np.zeros(K.shape[0]); z = u.copy(); t = 1.0
     for _ in range(iters):

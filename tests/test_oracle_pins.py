@@ -755,3 +755,68 @@ def test_hd_weighting_is_the_unit_run_rescaled(case):
         assert rh["mu"] == pytest.approx(w * ru["mu"], rel=1e-12)
         for key in ("xi_p", "xi_d", "xi_c"):
             assert rh[key] == pytest.approx(w * ru[key], rel=1e-5, abs=1e-14)
+
+
+# ---------------------------------------------------------------- Q1 with partial observation (Sec. 4.3)
+
+def _box_elements(N, dim, lo, hi):
+    """Weights of the elements inside the box [lo, hi]^... given in grid
+    units per axis (element e spans [e, e+1] h on every axis)."""
+    e = np.arange(N + 1)
+    axes = [((e >= lo[a]) & (e + 1 <= hi[a])).astype(float) for a in range(dim)]
+    out = axes[0][None, :] * axes[1][:, None] if dim == 2 else \
+        axes[0][None, None, :] * axes[1][None, :, None] * axes[2][:, None, None]
+    return out.reshape(-1)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_q1_observed_mass_integrates_the_hat_functions_over_the_box(dim):
+    """Row sums of the observed-element mass are the integrals of the hat
+    functions over the observed box: h^d times the product over the axes of
+    1 (inside), 1/2 (on a face of the box) or 0 (outside)."""
+    from oracle.fem import _interior_index, _weighted_mass
+    N = 15
+    h = 1.0 / (N + 1)
+    lo, hi = [3, 6, 2][:dim], [7, 14, 16][:dim]
+    M = _weighted_mass(N, dim, _box_elements(N, dim, lo, hi))
+    rows = np.asarray(M.sum(axis=1)).reshape(-1)[_interior_index(N, dim)]
+    g = np.arange(1, N + 1)
+    frac = [np.where((g > lo[a]) & (g < hi[a]), 1.0, np.where((g == lo[a]) | (g == hi[a]), 0.5, 0.0))
+            for a in range(dim)]
+    if dim == 2:
+        want = (frac[0][None, :] * frac[1][:, None]).reshape(-1)
+    else:
+        want = (frac[0][None, None, :] * frac[1][None, :, None] * frac[2][:, None, None]).reshape(-1)
+    np.testing.assert_allclose(rows, h ** dim * want, rtol=0, atol=1e-17)
+    full = _weighted_mass(N, dim, np.ones((N + 1) ** dim))
+    from oracle.fem import _full_matrices
+    np.testing.assert_allclose(full.toarray(), _full_matrices(N, dim)[1].toarray(), rtol=0, atol=1e-18)
+
+
+def test_q1_observed_mass_matches_its_stencil_and_fista():
+    """The observed-element mass equals the node-by-node construction from
+    the element stencil, and the IPM optimum of the partially observed Q1
+    problem equals FISTA on the reduced problem with that tracking mass."""
+    from oracle.fem import q1_matrices
+    N = 7
+    ew = _box_elements(N, 2, [1, 3], [5, 8])
+    Md = I.dense_q1_observed(N, ew)
+    p = W.poisson2d_q1(seed=2, N=N)
+    p.obs = ew
+    rng = np.random.default_rng(6)
+    p.y_d = W.sine_modes(rng, 2, N, 4, 3)[0] * 4.0
+    p.alpha, p.beta = 1e-2, 3e-3
+    p.u_a[:] = -1.5; p.u_b[:] = 1.0
+    p.y_a = p.y_b = None
+    disc = discretize(p)
+    h2 = 1.0 / (N + 1) ** 2
+    np.testing.assert_allclose(disc.Mt.toarray(), Md / h2, rtol=0, atol=1e-14)
+    K, M = I.dense_q1(N)
+    dl = np.full(p.n, h2)
+    u_ref, y_ref = I.fista_weighted(K, M, dl, p.y_d, np.zeros(p.n), p.alpha, p.beta, p.u_a, p.u_b, Mt=Md)
+    r = oracle.solve(p, IPMOptions(sigma=p.sigma, eps_p=1e-13, eps_d=1e-13, eps_c=1e-13))
+    assert r.status == "converged"
+    assert (np.abs(u_ref) < 1e-12).sum() > 0
+    assert ((np.abs(u_ref) > 1e-6) & (u_ref < 1.0 - 1e-6) & (u_ref > -1.5 + 1e-6)).sum() > 0
+    np.testing.assert_allclose(r.u, u_ref, rtol=0, atol=1e-7)
+    np.testing.assert_allclose(r.y, y_ref, rtol=0, atol=1e-8)

@@ -27,6 +27,16 @@ analytic desired states, Sec. 5):
     (pde "poisson_q1": stiffness, consistent and lumped mass).
   * ``poisson3d_q1``: the 127^3 Poisson data of ``poisson3d_127`` with
     trilinear Q1 finite elements.
+  * ``poisson3d_q1_partial``: the 3D partial-observation setting of Sec. 5.1
+    with trilinear Q1 elements: N=31 (h = 2^-5), observed subdomain
+    (0.2,0.4) x (0.4,0.9) x (0,1), alpha=1e-5, beta=1e-3, u in [-2, 1.5],
+    no state bounds, sigma=0.25, 8 sine modes for y_d (the paper's desired
+    state is not given in closed form).  ``poisson2d_q1_partial``: the 2D
+    analogue on the central square (0.25,0.75)^2, N=255.
+
+For Q1 problems ``obs`` holds one weight per element ((N+1)^d values; the
+element with lower corner (e1, ...) of the (N+2)^d grid, x1 fastest): 1 if
+its centre lies in the observed subdomain, else 0.
   * ``heat2d``: the heat equation on (0,1)^2 x (0,1] (Sec. 5.3), N=63,
     nt=100 backward Euler steps (tau=0.01), y_d = A sin(pi x1) sin(pi x2) at
     every time step, A ~ N(1, 0.1), y(0) = 0, alpha=1e-4, beta=1e-2,
@@ -55,6 +65,8 @@ CONFIG_IDS = {
     "heat2d": 6,
     "poisson2d_q1": 7,
     "poisson3d_q1": 8,
+    "poisson3d_q1_partial": 9,
+    "poisson2d_q1_partial": 10,
 }
 
 
@@ -231,6 +243,34 @@ def poisson3d_q1(seed: int = 0, N: int = 127, beta: float = 1e-3, instance: int 
                        None, None, y_d, None, None, 0.2, "poisson3d_q1", {"modes": modes})
 
 
+def element_centres(dim: int, N: int):
+    """Centres of the (N+1)^d elements (lower corner e, x1 fastest), each a flat array."""
+    h = 1.0 / (N + 1)
+    t = (np.arange(N + 1, dtype=np.float64) + 0.5) * h
+    grids = np.meshgrid(*([t] * dim), indexing="ij")
+    return [g_.reshape(-1, order="F") for g_ in grids]
+
+
+def poisson3d_q1_partial(seed: int = 0, N: int = 31, instance: int = 0) -> ProblemData:
+    rng = rng_for("poisson3d_q1_partial", instance, seed)
+    y_d, modes = sine_modes(rng, 3, N)
+    c1, c2, c3 = element_centres(3, N)
+    obs = ((c1 > 0.2) & (c1 < 0.4) & (c2 > 0.4) & (c2 < 0.9)).astype(np.float64)
+    n = N ** 3
+    return ProblemData(3, N, "poisson_q1", 1.0, 1e-5, 1e-3, _const(n, -2.0), _const(n, 1.5), None, None,
+                       y_d, None, None, 0.25, "poisson3d_q1_partial", {"modes": modes}, obs)
+
+
+def poisson2d_q1_partial(seed: int = 0, N: int = 255, instance: int = 0) -> ProblemData:
+    rng = rng_for("poisson2d_q1_partial", instance, seed)
+    y_d, modes = sine_modes(rng, 2, N)
+    c1, c2 = element_centres(2, N)
+    obs = ((c1 > 0.25) & (c1 < 0.75) & (c2 > 0.25) & (c2 < 0.75)).astype(np.float64)
+    n = N * N
+    return ProblemData(2, N, "poisson_q1", 1.0, 1e-4, 1e-3, _const(n, -5.0), _const(n, 5.0), None, None,
+                       y_d, None, None, 0.25, "poisson2d_q1_partial", {"modes": modes}, obs)
+
+
 def served_requests(n_requests: int = 256, seed: int = 0, sizes=(31, 63, 127, 255), rate: float = 1.0):
     """Request stream for the serving workload: (arrival_time, ProblemData) pairs.
 
@@ -267,4 +307,5 @@ def by_name(name: str, seed: int = 0, **kw) -> ProblemData:
     return {"poisson2d_small": poisson2d_small, "poisson2d_511": poisson2d_511,
             "poisson3d_127": poisson3d_127, "convdiff2d_255": convdiff2d_255,
             "poisson2d_partial": poisson2d_partial, "heat2d": heat2d, "poisson2d_q1": poisson2d_q1,
-            "poisson3d_q1": poisson3d_q1}[name](seed=seed, **kw)
+            "poisson3d_q1": poisson3d_q1, "poisson3d_q1_partial": poisson3d_q1_partial,
+            "poisson2d_q1_partial": poisson2d_q1_partial}[name](seed=seed, **kw)
