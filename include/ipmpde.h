@@ -173,15 +173,18 @@ int ipmpde_set_allocator(ipmpde_alloc_fn alloc, ipmpde_free_fn free_, void* ctx)
  * with, in 2D, L = (8, -1 x 8) / (3 h^2) and M = (16, 4 x 4, 1 x 4) / 36 as
  * nine-point stencils and, in 3D, L = (8/3, 0 x 6, -1/6 x 12, -1/12 x 8) / h^2
  * and M = (64, 16 x 6, 4 x 12, 1 x 8) / 216 over the node and its face, edge
- * and corner neighbours.  MINRES + P_D, FGMRES + P_D or P_T (P_Pi:
- * IPMPDE_EINVAL at solve): (M + Theta_y)^-1 by 20 steps of Chebyshev
+ * and corner neighbours.  MINRES + P_D, FGMRES + P_D, P_T or P_Pi.  P_D and
+ * P_T apply (M + Theta_y)^-1 by 20 steps of Chebyshev
  * semi-iteration with D_M + Theta_y on the spectrum [1/4, 9/4] (2D) or
  * [1/8, 27/8] (3D), alpha M~ + Theta_z by alpha D~_M + Theta_z, M_hat with
  * D_M (Sec. 4.1, 4.2), multigrid on L + M_hat.  With active state bounds the
  * FP32 multigrid loses the Schur approximation late in a solve (Theta_y
- * above ~1e8); mg_precision FP64 solves those instances.  No observation
- * weights; batched only with other Q1 problems; an engine serves them in
- * groups of their own. */
+ * above ~1e8); mg_precision FP64 solves those instances.  Partial
+ * observation (ipmpde_set_observation with one weight per element): the
+ * tracking mass is assembled from the observed elements and the solve takes
+ * FGMRES + P_Pi (Sec. 4.3) with M_l its lumped diagonal plus Theta_y and
+ * M_r the diagonal Sigma of P_D; P_D and P_T are refused then.  Batched only
+ * with other Q1 problems; an engine serves them in groups of their own. */
 int ipmpde_problem_create(const ipmpde_grid* grid, const ipmpde_pde* pde, double alpha, double beta,
                           const double* u_a, const double* u_b, const double* y_a, const double* y_b,
                           const double* y_d, const double* f, const double* g, ipmpde_problem** out);
@@ -222,7 +225,11 @@ void ipmpde_problem_destroy(ipmpde_problem* prob);
  * Newton system.  weights NULL restores full observation.  When some weight
  * is 0 and the problem has no state bounds the (1,1) block is singular and
  * only IPMPDE_PPI (with FGMRES) may be used (other preconditioners give
- * IPMPDE_EINVAL at solve).  Adds n doubles of device memory. */
+ * IPMPDE_EINVAL at solve).  Adds n doubles of device memory.
+ * Q1 problems take one weight per element instead, count = (N+1)^dim,
+ * element (e1, e2[, e3]) spanning [e1 h, (e1+1) h] x ... (x1 fastest): the
+ * tracking mass is assembled from the elements with their weights (1 =
+ * observed), and only IPMPDE_PPI may be used while weights are set. */
 int ipmpde_set_observation(ipmpde_problem* prob, const double* weights, size_t count);
 
 /* Bytes of device memory a problem of this shape holds while it is solved

@@ -166,18 +166,21 @@ class Problem:
             L.check(self._lib.ipmpde_problem_create(C.byref(grid), C.byref(pdes), float(alpha), float(beta),
                                                     *[_ptr(a) for a in self._keep], C.byref(h)))
         self._h = h
+        self.pde = pde
         self.has_state_bounds = y_a is not None
         self._keep = None
         if obs is not None:
             self.set_observation(obs)
 
     def set_observation(self, weights):
-        """Observation weights O (Sec. 4.3); None: the whole domain."""
+        """Observation weights (Sec. 4.3); None: the whole domain.  One per
+        node (finite differences) or one per element ((N+1)^dim, Q1)."""
         if weights is None:
             L.check(self._lib.ipmpde_set_observation(self._h, None, 0))
             return
-        w = _f64(weights, self.n, "obs")
-        L.check(self._lib.ipmpde_set_observation(self._h, _ptr(w), self.n))
+        m = (self.N + 1) ** self.dim if self.pde == "poisson_q1" else self.n
+        w = _f64(weights, m, "obs")
+        L.check(self._lib.ipmpde_set_observation(self._h, _ptr(w), m))
 
     def close(self):
         if getattr(self, "_h", None):

@@ -106,6 +106,7 @@ struct Inst {
   void* cpackb;         // base of the coarse LDS images of the three reaction-term slots
   int cpack_slot;       // elements between two slots' images
   const double* obs;    // observation weights O (nullptr: the whole domain, O = I)
+  const double* eobs;   // Q1: observed-element weights, (N+1)^dim by lower corner (nullptr: all)
   int ppi;              // 1: the partial-observation preconditioner P_Pi (three multigrid operators)
   void* kc_b0;          // k-cycle solves (vcycles > 1): the solve's level-0 right-hand side
   void* kc_s[2];        // and its accumulated iterate (ping-pong)
@@ -338,6 +339,61 @@ __device__ __forceinline__ T q1_mass2(const T* __restrict__ x, int idx, int i1, 
 template <typename T, bool ABS = false>
 __device__ __forceinline__ T q1_mass(const T* __restrict__ x, int idx, int i1, int i2, int i3, int N, int dim) {
   return dim == 3 ? q1_mass3<T, ABS>(x, idx, i1, i2, i3, N) : q1_mass2<T, ABS>(x, idx, i1, i2, N);
+}
+
+// Q1 mass of the observed elements (partial observation, Sec. 4.3) at node
+// idx, divided by h^dim: over the 2^dim elements around the node (lower
+// corners (i1 + a, i2 + b[, i3 + c]) on the (N+2)^dim grid), the element's
+// weight times its mass row, (4, 2, 1) / 36 in 2D and (8, 4, 2, 1) / 216 in
+// 3D by the number of coordinates in which the other node differs.
+template <typename T, bool ABS = false>
+__device__ __forceinline__ T q1_mass_obs(const T* __restrict__ x, int idx, int i1, int i2, int i3, int N, int dim,
+                                         const double* __restrict__ ew) {
+  const int E = N + 1;
+  const int nc = dim == 3 ? 2 : 1;
+  T acc = 0;
+  for (int c = 0; c < nc; ++c)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const double we = ew[(i1 + a) + E * ((i2 + b) + (dim == 3 ? E * (i3 + c) : 0))];
+        if (we == 0.0) continue;
+        T sum = 0;
+        for (int s3 = 0; s3 < nc; ++s3)
+#pragma unroll
+          for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+            for (int s1 = 0; s1 < 2; ++s1) {
+              const int o1 = a - 1 + s1, o2 = b - 1 + s2, o3 = dim == 3 ? c - 1 + s3 : 0;
+              if ((unsigned)(i1 + o1) >= (unsigned)N || (unsigned)(i2 + o2) >= (unsigned)N ||
+                  (dim == 3 && (unsigned)(i3 + o3) >= (unsigned)N))
+                continue;
+              const int k = (o1 != 0) + (o2 != 0) + (o3 != 0);
+              const T wk = dim == 3 ? (T)(8 >> k) : (T)(k == 0 ? 4 : (k == 1 ? 2 : 1));
+              sum += wk * ldv<T, ABS>(x, idx + o1 + N * (o2 + N * o3));
+            }
+        acc += (T)we * sum;
+      }
+  return acc * (T)(dim == 3 ? 1.0 / 216.0 : 1.0 / 36.0);
+}
+
+// Diagonal of that mass at node (i1, i2, i3): 4/36 (2D) or 8/216 (3D) times
+// the sum of the weights of the elements around the node.
+__device__ __forceinline__ double q1_obs_diag(int i1, int i2, int i3, int N, int dim, const double* __restrict__ ew) {
+  const int E = N + 1;
+  double sw = 0.0;
+  for (int c = 0; c < (dim == 3 ? 2 : 1); ++c)
+    for (int b = 0; b < 2; ++b)
+      for (int a = 0; a < 2; ++a) sw += ew[(i1 + a) + E * ((i2 + b) + (dim == 3 ? E * (i3 + c) : 0))];
+  return sw * (dim == 3 ? 8.0 / 216.0 : 4.0 / 36.0);
+}
+
+// Tracking mass of a Q1 instance: the observed elements' mass, or the whole mass.
+template <typename T, bool ABS = false>
+__device__ __forceinline__ T q1_mass_track(const Inst& I, const T* __restrict__ x, int idx, int i1, int i2, int i3) {
+  return I.eobs ? q1_mass_obs<T, ABS>(x, idx, i1, i2, i3, I.N, I.dim, I.eobs)
+                : q1_mass<T, ABS>(x, idx, i1, i2, i3, I.N, I.dim);
 }
 
 // (|A| |x|)_idx (or with |A^T|) for rounding-error bounds.  Every

@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(kBS) k_measures(const Inst* __restrict__ Dp) {
     const double Mu = q1 ? q1_mass<double>(I.w, i, i1, i2, i3, I.N, I.dim) - q1_mass<double>(I.v, i, i1, i2, i3, I.N, I.dim) : u;
     const double Mp = q1 ? q1_mass<double>(I.p, i, i1, i2, i3, I.N, I.dim) : p;
     r[0] = fabs(Ay - Mu - I.fhat[i]);
-    double dy = (q1 ? q1_mass<double>(I.y, i, i1, i2, i3, I.N, I.dim) - q1_mass<double>(I.yd, i, i1, i2, i3, I.N, I.dim)
+    double dy = (q1 ? q1_mass_track<double>(I, I.y, i, i1, i2, i3) - q1_mass_track<double>(I, I.yd, i, i1, i2, i3)
                     : obs_w(I, i) * (y - I.yd[i])) + ATp;
     double pc = nmax(nmax(w * lwa, (ub - w) * lwb), nmax(v * lva, (-ua - v) * lvb));
     if (I.has_y) {
@@ -133,7 +133,7 @@ __global__ void __launch_bounds__(kBS) k_newton_setup(const Inst* __restrict__ D
       // = D_M^2 (t_w + t_v) / (alpha D_M (t_w + t_v) + t_w t_v), times D_M + Theta_y, square root
       const double dm = q1_mass_diag(I.dim);
       sig = dm * dm * (tw + tv) / (I.alpha * dm * (tw + tv) + tw * tv);
-      mh = sqrt(sig * (dm + ty));
+      mh = I.ppi ? sig : sqrt(sig * (dm + ty));
     } else {
       sig = (tw + tv) / (I.alpha * (tw + tv) + tw * tv);
       mh = I.ppi ? sig : sqrt(sig * (ow + ty));
@@ -144,13 +144,16 @@ __global__ void __launch_bounds__(kBS) k_newton_setup(const Inst* __restrict__ D
     I.mh[i] = mh;
     // heat equation: every time step's multigrid operator is I/tau + A_h + M_hat
     ((T*)I.lv[0].mh)[i] = (T)(I.pde == 2 ? mh + 1.0 / I.tau : mh);
-    if (I.ppi) ((T*)I.lv[0].mhb)[I.n + i] = (T)(ow + ty);
+    // P_Pi: M_l = O + Theta_y; for Q1 the lumped mass of the observed elements + Theta_y
+    if (I.ppi)
+      ((T*)I.lv[0].mhb)[I.n + i] =
+          (T)((q1 ? (I.eobs ? q1_obs_diag(i1, i2, i3, I.N, I.dim, I.eobs) : q1_mass_diag(I.dim)) : ow) + ty);
     const double u = w - v;
     const double Ay = inst_op<double>(I, I.y, i, i1, i2, i3, false);
     const double ATp = inst_op<double>(I, I.p, i, i1, i2, i3, true);
     const double Mu = q1 ? q1_mass<double>(I.w, i, i1, i2, i3, I.N, I.dim) - q1_mass<double>(I.v, i, i1, i2, i3, I.N, I.dim) : u;
     const double Mp = q1 ? q1_mass<double>(I.p, i, i1, i2, i3, I.N, I.dim) : p;
-    const double Myd = q1 ? q1_mass<double>(I.y, i, i1, i2, i3, I.N, I.dim) - q1_mass<double>(I.yd, i, i1, i2, i3, I.N, I.dim)
+    const double Myd = q1 ? q1_mass_track<double>(I, I.y, i, i1, i2, i3) - q1_mass_track<double>(I, I.yd, i, i1, i2, i3)
                           : ow * (y - I.yd[i]);
     const double ry = -(Myd + ATp + by);
     const double rw = -(I.alpha * Mu + I.beta - Mp - mu / w + mu / gwb);

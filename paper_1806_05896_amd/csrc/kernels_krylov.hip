@@ -41,7 +41,7 @@ __device__ __forceinline__ void saddle_rows(const Inst& I, const double* __restr
   const double xp = x[3 * n + i];
   if (I.pde == 3) {
     // Q1 (Sec. 2): M in the (1,1) block, alpha M~ and the coupling M bar
-    const double My = q1_mass<double>(x, i, i1, i2, i3, I.N, I.dim), Mw = q1_mass<double>(x + n, i, i1, i2, i3, I.N, I.dim);
+    const double My = q1_mass_track<double>(I, x, i, i1, i2, i3), Mw = q1_mass<double>(x + n, i, i1, i2, i3, I.N, I.dim);
     const double Mv = q1_mass<double>(x + 2 * n, i, i1, i2, i3, I.N, I.dim), Mp = q1_mass<double>(x + 3 * n, i, i1, i2, i3, I.N, I.dim);
     out[0] = s * (My + ty * xy + ATxp);
     out[1] = s * (a * (Mw - Mv) + tw * xw - Mp);
@@ -65,7 +65,8 @@ __device__ __forceinline__ void saddle_rows_abs(const Inst& I, const double* __r
   const double ATxp = inst_op_abs(I, x + 3 * n, i, i1, i2, i3, true);
   const double Axy = inst_op_abs(I, x, i, i1, i2, i3, false);
   if (I.pde == 3) {
-    const double My = q1_mass<double, true>(x, i, i1, i2, i3, I.N, I.dim), Mw = q1_mass<double, true>(x + n, i, i1, i2, i3, I.N, I.dim);
+    const double My = q1_mass_track<double, true>(I, x, i, i1, i2, i3);
+    const double Mw = q1_mass<double, true>(x + n, i, i1, i2, i3, I.N, I.dim);
     const double Mv = q1_mass<double, true>(x + 2 * n, i, i1, i2, i3, I.N, I.dim);
     const double Mp = q1_mass<double, true>(x + 3 * n, i, i1, i2, i3, I.N, I.dim);
     out[0] = My + ty * xy + ATxp;
@@ -389,7 +390,25 @@ __global__ void __launch_bounds__(kBS) k_ppi_a(const Inst* __restrict__ Dp, cons
   apply_z_inv(I, i, r[n + i], r[2 * n + i], zw, zv);
   z[n + i] = zw;
   z[2 * n + i] = zv;
-  ((T*)I.lv[0].b)[i] = (T)(zw - zv + r[3 * n + i]);
+  if (I.pde != 3) ((T*)I.lv[0].b)[i] = (T)(zw - zv + r[3 * n + i]);
+}
+
+// Q1, after step a: the right-hand side M (z_w - z_v) + r_p of the L solve
+// (the coupling Mbar applies the mass to the neighbours' z block).
+template <typename T>
+__global__ void __launch_bounds__(kBS) k_ppi_a_q1(const Inst* __restrict__ Dp, const double* __restrict__ rx,
+                                                  const double* __restrict__ zx, int j, int guard) {
+  INST_BEGIN
+  if (guard && I.ctrl->stop) return;
+  const int i = blockIdx.x * kBS + threadIdx.x;
+  if (i >= I.n) return;
+  const int n = I.n;
+  const double* r = rx ? rx : I.fV + (size_t)j * 4 * n;
+  const double* z = zx ? zx : I.fZ + (size_t)j * 4 * n;
+  int i1, i2, i3;
+  node_coords(i, I.N, I.dim, i1, i2, i3);
+  const double Mz = q1_mass<double>(z + n, i, i1, i2, i3, I.N, I.dim) - q1_mass<double>(z + 2 * n, i, i1, i2, i3, I.N, I.dim);
+  ((T*)I.lv[0].b)[i] = (T)(Mz + r[3 * n + i]);
 }
 
 // Step b: z_y = v1 (the L solve's output) and the right-hand side
@@ -404,8 +423,16 @@ __global__ void __launch_bounds__(kBS) k_ppi_b(const Inst* __restrict__ Dp, cons
   const int n = I.n;
   const double* r = rx ? rx : I.fV + (size_t)j * 4 * n;
   double* z = zx ? zx : I.fZ + (size_t)j * 4 * n;
-  const double v1 = (double)mg_out<T>(I, outsel)[i];
+  const T* out = mg_out<T>(I, outsel);
+  const double v1 = (double)out[i];
   z[i] = v1;
+  if (I.pde == 3) {  // Q1: (M_O + Theta_y) v1 - r_y with the observed elements' mass
+    int i1, i2, i3;
+    node_coords(i, I.N, I.dim, i1, i2, i3);
+    const double Mv = (double)q1_mass_track<T>(I, out, i, i1, i2, i3);
+    ((T*)I.lv[0].b)[i] = (T)(Mv + I.ty[i] * v1 - r[i]);
+    return;
+  }
   ((T*)I.lv[0].b)[i] = (T)((obs_w(I, i) + I.ty[i]) * v1 - r[i]);
 }
 
@@ -681,6 +708,7 @@ __global__ void k_ctrl_continue(const Inst* __restrict__ Dp) {
   template __global__ void k_pt_rhs<T>(const Inst*, const double*, const double*, int, int);      \
   template __global__ void k_store_p<T>(const Inst*, double*, int, int, int);                     \
   template __global__ void k_ppi_a<T>(const Inst*, const double*, double*, int, int);              \
+  template __global__ void k_ppi_a_q1<T>(const Inst*, const double*, const double*, int, int);     \
   template __global__ void k_ppi_b<T>(const Inst*, const double*, double*, int, int, int);         \
   template __global__ void k_ppi_c<T>(const Inst*, int, int);                                      \
   template __global__ void k_minres_init<T>(const Inst*, int);                                   \

@@ -161,6 +161,7 @@ struct ipmpde_problem {
   bool need_init = true;   // iterates not yet at the starting point
   bool in_engine = false;  // queued or running in a serving engine
   double* obs = nullptr;   // observation weights (device), nullptr: observed everywhere
+  double* eobs = nullptr;  // Q1: observed-element weights (device), nullptr: observed everywhere
   bool obs_zero = false;   // some node is unobserved
   int nlev = 0;
   Level lv32[kMaxLev];
@@ -579,6 +580,7 @@ static int group_select(Group* G, const ipmpde_options& o) {
     d.cpackb = d.cpack;
     d.cpack_slot = fp32 ? P->cpack_elems32 : P->cpack_elems64;
     d.obs = P->obs;
+    d.eobs = P->eobs;
     d.ppi = o.precond == IPMPDE_PPI ? 1 : 0;
     void* const* kc = fp32 ? P->kc32 : P->kc64;
     d.kc_b0 = kc[0];
@@ -1072,6 +1074,8 @@ static void precond_apply(Group* G, int pt, const double* x, double* y, int j, i
     // Sec. 4.3: v2 (z block), v1 = L^-1 (Mbar v2 + r_p), then
     // v3 = (L + M_r)^-1 L (L^T + M_l)^-1 ((O + Theta_y) v1 - r_y)
     hipLaunchKernelGGL(k_ppi_a<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, x, y, j, guard);
+    if (G->q1)
+      hipLaunchKernelGGL(k_ppi_a_q1<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, x, (const double*)y, j, guard);
     mg_select(G, 2, s);
     mg_solve<T>(G, 0, guard, 0, s);
     hipLaunchKernelGGL(k_ppi_b<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, x, y, j, G->outsel, guard);
@@ -1186,7 +1190,10 @@ static void heat_setup(Group* G, hipStream_t s) {
 static int newton_setup_group(Group* G, const ipmpde_options& o, hipStream_t s) {
   if (G->heat && o.precond == IPMPDE_PPI)
     return fail(IPMPDE_EINVAL, "P_Pi is not available for the heat equation");
-  if (G->q1 && o.precond == IPMPDE_PPI) return fail(IPMPDE_EINVAL, "P_Pi is not available for Q1 problems");
+  if (G->q1 && o.precond != IPMPDE_PPI)
+    for (int i = 0; i < G->count; ++i)
+      if (G->probs[i]->eobs)
+        return fail(IPMPDE_EINVAL, "Q1 problems observed on part of the domain take P_Pi");
   for (int i = 0; i < G->count; ++i) {
     const ipmpde_problem* P = G->probs[i];
     if (o.precond != IPMPDE_PPI && P->obs_zero && !P->has_y)
@@ -1796,8 +1803,23 @@ static const double* field_ptr(const ipmpde_problem* P, int field, int* kind) {
 extern "C" int ipmpde_set_observation(ipmpde_problem* P, const double* weights, size_t count) {
   if (!P) return fail(IPMPDE_EINVAL, "problem is NULL");
   if (P->in_engine) return fail(IPMPDE_EINVAL, "problem is queued or running in an engine");
-  if (P->pde == IPMPDE_POISSON_Q1 && weights)
-    return fail(IPMPDE_EINVAL, "observation weights are defined for the finite-difference problems");
+  if (P->pde == IPMPDE_POISSON_Q1) {
+    // one weight per element ((N+1)^dim, numbered by the lower corner, x1
+    // fastest): the tracking mass is assembled from the observed elements
+    if (!weights) {
+      P->I.eobs = P->eobs = nullptr;
+      return IPMPDE_OK;
+    }
+    const size_t ne = pow_dim(P->N + 1, P->dim);
+    if (count != ne) return fail(IPMPDE_EINVAL, "count must equal the number of elements, (N+1)^dim");
+    for (size_t i = 0; i < count; ++i)
+      if (!(weights[i] >= 0.0 && std::isfinite(weights[i]))) return fail(IPMPDE_EINVAL, "weights must be finite and >= 0");
+    if (!P->eobs) TRY(P->mem.alloc_t(&P->eobs, count));
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(P->eobs, weights, count * sizeof(double), hipMemcpyHostToDevice));
+    P->I.eobs = P->eobs;
+    return IPMPDE_OK;
+  }
   if (!weights) {
     P->I.obs = P->obs = nullptr;
     P->obs_zero = false;

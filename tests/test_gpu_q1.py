@@ -249,13 +249,16 @@ def test_q1_batch_equals_solo():
 
 
 def test_q1_refusals():
+    """A batch mixing Q1 and finite-difference problems, and observation
+    weights per node (Q1 takes one per element) are refused."""
+    import ctypes as C
+
+    from paper_1806_05896_amd import _lib as L
     Batch, Options, Problem = _api()
     data = CASES["q1_31"]()
     with Problem(data) as prob, Problem(W.poisson2d_small(N=15)) as fd:
-        with pytest.raises(Exception):
-            prob.solve(Options(krylov="fgmres", precond="ppi"), raise_on_error=True)
-        with pytest.raises(Exception):
-            prob.set_observation(np.ones(data.n))
+        w = np.ones(data.n)
+        assert prob._lib.ipmpde_set_observation(prob._h, w.ctypes.data_as(C.c_void_p), data.n) == L.EINVAL
         with pytest.raises(Exception):
             Batch([prob, fd])
 
