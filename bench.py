@@ -302,6 +302,49 @@ def bench_q1_avli(W, torch):
             out[f"h=2^-{ell} alpha=1e{la}"] = cell
             log(f"q1 av-li h=2^-{ell} alpha=1e{la}: " +
                 ", ".join(f"{k} {v['av_li']:.1f}" for k, v in cell.items()))
+    # the same problem with state bounds y in [-0.1, 0.8] and u in [-1, 15]
+    # (FGMRES + P_T, the paper's second Poisson table), and the 3D partially
+    # observed problem (FGMRES + P_Pi, h = 2^-3 .. 2^-5, the paper's third)
+    settings = (("fp64 1x(2+2)", {"mg_precision": "fp64"}),
+                ("fp64 3x(5+5)", {"mg_precision": "fp64", "vcycles": 3, "nu_pre": 5, "nu_post": 5}))
+    cases = []
+    for ell in (6, 7, 8, 9):
+        for la in (-2, -4, -6):
+            cases.append(("state", ell, la))
+    for ell in (3, 4, 5):
+        for la in (-2, -4, -6):
+            cases.append(("partial3d", ell, la))
+    for kind, ell, la in cases:
+        N = 2 ** ell - 1
+        if kind == "state":
+            x1, x2 = W.interior_coords(2, N)
+            d = W.poisson2d_q1(seed=0, N=N)
+            d.y_d = np.sin(math.pi * x1) * np.sin(math.pi * x2)
+            d.alpha, d.beta, d.sigma = 10.0 ** la, 1e-2, 0.2
+            d.u_a[:] = -1.0
+            d.u_b[:] = 15.0
+            d.y_a = np.full(d.n, -0.1)
+            d.y_b = np.full(d.n, 0.8)
+            kry, pre = "fgmres", "pt"
+        else:
+            d = W.poisson3d_q1_partial(seed=0, N=N)
+            d.alpha = 10.0 ** la
+            kry, pre = "fgmres", "ppi"
+        cell = {}
+        with Problem(d) as p:
+            for mg, kw in settings:
+                o = Options(sigma=d.sigma, krylov=kry, precond=pre, **kw)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rc = p.solve(o, stream=stream)
+                torch.cuda.synchronize()
+                t = time.perf_counter() - t0
+                s = p.stats()
+                cell[mg] = {"av_li": s.krylov_its / max(1, s.nli), "nli": s.nli, "ms_per_solve": t * 1e3,
+                            "status": rc}
+        out[f"{kind} h=2^-{ell} alpha=1e{la}"] = cell
+        log(f"q1 av-li {kind} h=2^-{ell} alpha=1e{la}: " +
+            ", ".join(f"{k} {v['av_li']:.1f} (nli {v['nli']}, rc {v['status']})" for k, v in cell.items()))
     return out
 
 
