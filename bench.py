@@ -29,7 +29,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the roofline kernel from rocprofv3 FETCH_SIZE/WRITE_SIZE
 # runs (profiles/k_minres_k1_poisson2d_511x8_pmc.md), valid while the kernel
 # sources hash to the value they were measured with.
-TRAFFIC = {"kernel": 6, "N": 511, "batch": 8, "bytes": 622677951.7, "source_sha": "77ff879c48d85849"}
+TRAFFIC = {"kernel": 6, "N": 511, "batch": 8, "bytes": 622627355.4, "source_sha": "431b1cd4d76d19ba"}
 KERNEL_NAMES = {0: "k_saddle (saddle matvec)", 1: "k_mg_jacobi (finest-level smoothing sweep)",
                 2: "k_minres_k2 (Lanczos + diagonal preconditioner)", 3: "one V-cycle",
                 4: "k_mg_down2d (finest level: smoothing + residual + restriction)",

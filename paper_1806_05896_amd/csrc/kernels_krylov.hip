@@ -324,7 +324,7 @@ __global__ void __launch_bounds__(kBS) k_cheb_step3(const Inst* __restrict__ Dp,
   INST_BEGIN
   if ((guard == 1 && I.ctrl->stop) || (guard == 2 && !I.ctrl->want_restart)) return;
   const int n = I.n;
-  const int i = blockIdx.x * kBS + threadIdx.x;
+  const int i = xcd_node(n);  // each XCD sweeps a contiguous range: the neighbour planes stay in its L2
   if (i >= n) return;
   const double* r = mpar >= 0 ? I.V[1 - mpar] : (rx ? rx : I.fV + (size_t)j * 4 * n);
   double* z = mpar >= 0 ? I.Z[1 - mpar] : (zx ? zx : I.fZ + (size_t)j * 4 * n);
