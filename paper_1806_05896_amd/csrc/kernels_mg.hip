@@ -125,7 +125,7 @@ __global__ void __launch_bounds__(kBS) k_mg_jacobi(const Inst* __restrict__ Dp, 
   INST_BEGIN
   if (l >= I.coarse_lev || mg_skip(I, guard)) return;
   const Level& L = I.lv[l];
-  const int i = blockIdx.x * kBS + threadIdx.x;
+  const int i = xcd_node(L.n);  // contiguous node ranges per XCD: neighbour planes stay in its L2
   if (i >= L.n) return;
   lvbuf<T>(L, dst)[i] = jacobi_node<T>(lvbuf<T>(L, src), (const T*)L.b, (const T*)L.mh, i, L.N, I.dim, I.pde, L.h,
                                        I.eps, I.omega, first != 0, transpose != 0);
@@ -138,7 +138,7 @@ __global__ void __launch_bounds__(kBS) k_mg_restrict(const Inst* __restrict__ Dp
   if (l >= I.coarse_lev || mg_skip(I, guard)) return;
   const Level& F = I.lv[l];
   const Level& C = I.lv[l + 1];
-  const int ic = blockIdx.x * kBS + threadIdx.x;
+  const int ic = xcd_node(C.n);
   if (ic >= C.n) return;
   ((T*)C.b)[ic] = restrict_resid_node<T>(lvbuf<T>(F, src), (const T*)F.b, (const T*)F.mh, ic, F.N, C.N, I.dim, I.pde,
                                          F.h, I.eps, transpose != 0);
@@ -152,7 +152,7 @@ __global__ void __launch_bounds__(kBS) k_mg_prolong(const Inst* __restrict__ Dp,
   if (l >= I.coarse_lev || mg_skip(I, guard)) return;
   const Level& F = I.lv[l];
   const Level& C = I.lv[l + 1];
-  const int i = blockIdx.x * kBS + threadIdx.x;
+  const int i = xcd_node(F.n);
   if (i >= F.n) return;
   const T* xc = (l + 1 == I.coarse_lev) ? (const T*)C.x : lvbuf<T>(C, csel);
   lvbuf<T>(F, dst)[i] += prolong_node<T>(xc, i, F.N, C.N, I.dim);
