@@ -26,14 +26,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TUNE_CACHE = os.path.join(ROOT, "paper_1806_05896_amd", "autotune_cache.json")
 # HBM bytes per launch of the roofline kernel from rocprofv3 FETCH_SIZE/WRITE_SIZE
 # runs (profiles/k_minres_k1_poisson2d_511x8_pmc.md), valid while the kernel
 # sources hash to the value they were measured with.
 TRAFFIC = {"kernel": 6, "N": 511, "batch": 8, "bytes": 622627355.4, "source_sha": "431b1cd4d76d19ba"}
-KERNEL_NAMES = {0: "k_saddle (saddle matvec)", 1: "k_mg_jacobi (finest-level smoothing sweep)",
+# kernel ids of ipmpde_time_kernel, named for the 2D Poisson workloads timed
+# here (convection-diffusion would launch k_mg_down2d / k_mg_up2d / k_mg_coarse)
+KERNEL_NAMES = {0: "k_saddle (saddle matvec)",
                 2: "k_minres_k2 (Lanczos + diagonal preconditioner)", 3: "one V-cycle",
-                4: "k_mg_down2d (finest level: smoothing + residual + restriction)",
-                5: "k_mg_up2d (finest level: prolongation + smoothing)",
+                4: "k_mg_down_p2 (finest level: smoothing + residual + restriction)",
+                5: "k_mg_up_p2 (finest level: prolongation + smoothing)",
                 6: "k_minres_k1 (MINRES update + saddle matvec + dots)",
                 7: "k_mg_coarse_p2 (coarse levels in one workgroup)"}
 
@@ -84,26 +87,48 @@ def time_solves(prob, opts, steps, warmup, torch):
     return t, lat, its, prob.stats(), rc
 
 
-def cpu_baseline(data, nli):
-    """The oracle (SuperLU Newton solve) on a bounded sample: the first IPM
-    iteration of the same 511 x 511 problem, scaled to solves/s by the
-    number of IPM iterations of a full solve."""
-    import numpy as np  # noqa: F401
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(data, nli, full=False):
+    """The oracle (Algorithm A.1 with a SuperLU Newton solve) on the host CPU,
+    BLAS and OpenMP pools limited to one thread (SuperLU itself is serial).
+    Default: a bounded sample, the first IPM iteration of the same 511 x 511
+    problem scaled to solves/s by the number of IPM iterations of a full
+    solve; full=True times the whole solve."""
     import oracle
     from oracle.fd import discretize
     from oracle.ipm import IPMOptions, initial_state, ipm_step
-    opts = IPMOptions(sigma=data.sigma)
-    t0 = time.perf_counter()
-    disc = discretize(data)
-    st = initial_state(data, opts)
-    st, _ = ipm_step(data, disc, st, opts, st.mu * opts.sigma)
-    t = time.perf_counter() - t0
-    threads = os.environ.get("OMP_NUM_THREADS")
-    return {"value": 1.0 / (t * nli), "unit": "IPM solves/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"1 of {nli} IPM iterations of the 511x511 workload (SuperLU on the eliminated SPD "
-                      f"Newton system, {t:.1f} s), scaled by {nli}; SuperLU factorization is single-threaded"
-                      + (f"; OMP_NUM_THREADS={threads}" if threads else "")}
+    from threadpoolctl import threadpool_limits
+    opts = IPMOptions(sigma=data.sigma, newton="schur")
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        if full:
+            r = oracle.solve(data, opts)
+            nli_done = r.nli
+        else:
+            disc = discretize(data)
+            st = initial_state(data, opts)
+            st, _ = ipm_step(data, disc, st, opts, st.mu * opts.sigma)
+            nli_done = 1
+        t = time.perf_counter() - t0
+    per_solve = t if full else t * nli
+    host = {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": cpu_model()}
+    if full:
+        sample = (f"full oracle solve of seed 0 ({nli_done} IPM iterations, SuperLU on the eliminated SPD "
+                  f"Newton system, {t:.1f} s)")
+    else:
+        sample = (f"bounded sample: IPM iteration 1 of {nli} of seed 0 (setup + SuperLU factorization and "
+                  f"solve of the eliminated SPD Newton system, {t:.1f} s), scaled by {nli} to one solve")
+    return {"value": 1.0 / per_solve, "unit": "IPM solves/s", "cores": 1, "kind": "oracle",
+            "sample": sample + "; BLAS/OpenMP limited to 1 thread", "host": host}
 
 
 def copy_ceiling(torch, reps=10):
@@ -376,6 +401,106 @@ def bench_heat_batch(W, torch, N, nt, B, reps):
     return out
 
 
+def _time_one(p, o, reps, stream, torch):
+    p.solve(o, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        rc = p.solve(o, stream=stream)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    s = p.stats()
+    return {"solves_per_s": 1 / t, "ms_per_solve": t * 1e3, "nli": s.nli, "krylov_its_per_solve": s.krylov_its,
+            "krylov_its_per_s": s.krylov_its / t, "status": rc}
+
+
+def bench_small(W, torch, reps, batch=64):
+    """The 31 x 31 problem (y_d = A sin(pi x1) sin(pi x2), alpha = 1e-2,
+    beta = 1e-3, u in [-2, 2], no state bounds; MINRES + P_D, FP64 V-cycles):
+    one instance alone, then `batch` instances (seeds 0..batch-1) as one batch."""
+    from paper_1806_05896_amd import Batch, Options, Problem
+    stream = torch.cuda.current_stream()
+    d = W.poisson2d_small(seed=0)
+    o = Options(sigma=d.sigma, mg_precision="fp64")
+    out = {"workload": "poisson2d_small: 2D Poisson 31x31, alpha=1e-2, beta=1e-3, u in [-2,2], sigma=0.2, "
+                       "MINRES + P_D, FP64 V-cycles"}
+    with Problem(d) as p:
+        out["single"] = _time_one(p, o, reps, stream, torch)
+    datas = [W.poisson2d_small(seed=k) for k in range(batch)]
+    probs = [Problem(x) for x in datas]
+    try:
+        with Batch(probs) as b:
+            b.solve(o, stream=stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                st = b.solve(o, stream=stream)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / reps
+        its = sum(p.stats().krylov_its for p in probs)
+        out["batched"] = {"instances": batch, "solves_per_s": batch / t, "ms_per_batch": t * 1e3,
+                          "krylov_its_per_s": its / t, "all_converged": all(x == 0 for x in st)}
+    finally:
+        for p in probs:
+            p.close()
+    log(f"31^2: single {out['single']['solves_per_s']:.1f} solves/s, batch of {batch} "
+        f"{out['batched']['solves_per_s']:.1f} solves/s")
+    return out
+
+
+def bench_fd3d(W, torch, N, betas, reps):
+    """3D Poisson, 7-point finite differences on N^3 (alpha = 1e-5,
+    u in [-10, 10], 8 sine modes), beta swept over `betas`; MINRES + P_D with
+    FP32 V-cycles, one instance per beta; FP64 V-cycles beside it at
+    beta = 1e-3.  The roofline figure is k_minres_k1 (MINRES update + saddle
+    matvec + dots) timed with HIP events after the solve."""
+    from paper_1806_05896_amd import Options, Problem
+    stream = torch.cuda.current_stream()
+    out = {"workload": f"poisson3d_127: 3D Poisson {N}^3 (7-point FD), alpha=1e-5, u in [-10,10], sigma=0.2, "
+                       "MINRES + P_D"}
+    for beta in betas:
+        d = W.poisson3d_127(seed=0, N=N, beta=beta)
+        with Problem(d) as p:
+            o = Options(sigma=d.sigma, mg_precision="fp32")
+            r = _time_one(p, o, reps, stream, torch)
+            ms, nb = p.time_kernel(6, reps=20, opts=o, stream=stream)
+            r["k_minres_k1"] = {"avg_us": ms * 1e3, "GB/s": nb / (ms * 1e-3) / 1e9,
+                                "frac_of_peak": nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            ms, nb = p.time_kernel(2, reps=20, opts=o, stream=stream)
+            r["k_minres_k2"] = {"avg_us": ms * 1e3, "GB/s": nb / (ms * 1e-3) / 1e9}
+            if beta == 1e-3:
+                r64 = _time_one(p, Options(sigma=d.sigma, mg_precision="fp64"), reps, stream, torch)
+                r["fp64_vcycles"] = r64
+                r["fp32_over_fp64"] = r["solves_per_s"] / r64["solves_per_s"]
+        out[f"beta_{beta:g}"] = r
+        log(f"3d fd {N}^3 beta={beta:g}: {r['solves_per_s']:.2f} solves/s, nli {r['nli']}, "
+            f"its {r['krylov_its_per_solve']}, k1 {r['k_minres_k1']['GB/s']:.0f} GB/s")
+    return out
+
+
+def bench_cd(W, torch, N, reps):
+    """Convection-diffusion, eps = 1/200, upwinded FD on N^2 (alpha = beta =
+    1e-3, u in [-3, 3], 8 sine modes): FGMRES(30) + P_T with FP32 V-cycles (and
+    MINRES + P_D beside it), one instance; the multigrid kernels timed with
+    HIP events after the solve."""
+    from paper_1806_05896_amd import Options, Problem
+    stream = torch.cuda.current_stream()
+    d = W.convdiff2d_255(seed=0, N=N)
+    out = {"workload": f"convdiff2d_255: -eps Lap y + w.grad y = u, eps=1/200, wind of Sec. 5.2, upwind FD "
+                       f"{N}x{N}, alpha=beta=1e-3, u in [-3,3], sigma={d.sigma}"}
+    with Problem(d) as p:
+        for name, kry, pre in (("fgmres_pt", "fgmres", "pt"), ("minres_pd", "minres", "pd")):
+            o = Options(sigma=d.sigma, krylov=kry, precond=pre, mg_precision="fp32")
+            out[name] = _time_one(p, o, reps, stream, torch)
+            log(f"cd {N}^2 {name}: {out[name]['solves_per_s']:.2f} solves/s, nli {out[name]['nli']}, "
+                f"its {out[name]['krylov_its_per_solve']}")
+        o = Options(sigma=d.sigma, krylov="fgmres", precond="pt", mg_precision="fp32")
+        for k, name in ((3, "one V-cycle"), (4, "k_mg_down2d (finest level)"), (5, "k_mg_up2d (finest level)")):
+            ms, nb = p.time_kernel(k, reps=20, opts=o, stream=stream)
+            out.setdefault("kernels", {})[name] = {"avg_us": ms * 1e3, "GB/s": nb / (ms * 1e-3) / 1e9}
+    return out
+
+
 def solver_options(d, Options, prec="fp32"):
     """Per-request solver choice: MINRES + P_D for Poisson, FGMRES(30) + P_T
     for convection-diffusion, multigrid in the given precision."""
@@ -512,7 +637,15 @@ def main():
     ap.add_argument("--heat-batch", type=int, default=16, help="instances of the batched heat run (0: skip)")
     ap.add_argument("--q1-N", type=int, default=511, help="grid of the Q1 finite-element run (0: skip)")
     ap.add_argument("--q1-3d-N", type=int, default=127, help="grid of the 3D Q1 run (0: skip)")
-    ap.add_argument("--only", choices=["serve", "batch", "partial", "heat", "q1", "q1_3d", "q1_avli"], default=None,
+    ap.add_argument("--small", type=int, default=1, help="time the 31^2 problem (0: skip)")
+    ap.add_argument("--fd3d-N", type=int, default=127, help="grid of the 3D finite-difference run (0: skip)")
+    ap.add_argument("--fd3d-betas", type=str, default="1e-4,1e-3,1e-2,1e-1")
+    ap.add_argument("--cd-N", type=int, default=255, help="grid of the convection-diffusion run (0: skip)")
+    ap.add_argument("--cpu-full", action="store_true", help="time a full oracle solve instead of one iteration")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="run the default multigrid schedule instead of the autotuner's pick")
+    ap.add_argument("--only", choices=["serve", "batch", "partial", "heat", "q1", "q1_3d", "q1_avli", "small",
+                                       "fd3d", "cd"], default=None,
                     help="run one extra section alone")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only launch the roofline kernel (20 times) and a 1 GiB device copy, for counter runs")
@@ -555,6 +688,16 @@ def main():
             out["batched"] = bench_heat_batch(W, torch, args.heat_N, args.heat_nt, args.heat_batch, 2)
         print(json.dumps({"heat": out}), flush=True)
         return
+    betas = [float(x) for x in args.fd3d_betas.split(",") if x]
+    if args.only == "small":
+        print(json.dumps({"small": bench_small(W, torch, 3)}), flush=True)
+        return
+    if args.only == "fd3d":
+        print(json.dumps({"fd3d": bench_fd3d(W, torch, args.fd3d_N, betas, 2)}), flush=True)
+        return
+    if args.only == "cd":
+        print(json.dumps({"convdiff": bench_cd(W, torch, args.cd_N, 2)}), flush=True)
+        return
     if args.only == "batch":
         print(json.dumps({"batched": bench_batched(W, torch, max(1, args.batch), 2)}), flush=True)
         return
@@ -565,6 +708,18 @@ def main():
     batch = Batch(probs)
     opts = Options(sigma=datas[0].sigma, mg_precision="fp32")
     stream = torch.cuda.current_stream()
+    tune = None
+    if args.autotune and not args.pmc_probe:
+        # the library's autotuner picks the FP32 V-cycle schedule (cycles, sweeps,
+        # level-kernel tiles) of this batch; the committed cache file holds the pick
+        # for this GPU architecture, a miss tunes (two batched solves per candidate)
+        t0 = time.perf_counter()
+        opts, tuned_ms, hit = batch.autotune(opts, cache=TUNE_CACHE, stream=stream)
+        tune = {"cache": "hit" if hit else "miss (tuned now)", "cache_file": os.path.relpath(TUNE_CACHE, ROOT),
+                "pick": {"vcycles": opts.vcycles, "nu_pre": opts.nu_pre, "nu_post": opts.nu_post,
+                         "mg_precision": opts.mg_precision, "mg_tile": opts.mg_tile},
+                "tuned_batch_solve_ms": tuned_ms, "seconds": time.perf_counter() - t0}
+        log(f"autotune: {tune}")
     if args.pmc_probe:
         # the roofline kernel of the batched step at a mid-solve Newton state, then a plain
         # copy of known size (1 GiB, larger than the 256 MB Infinity Cache) that calibrates
@@ -598,6 +753,7 @@ def main():
     t = time.perf_counter() - t0
     stats = [p.stats() for p in probs]
     u32 = [p.query("u") for p in probs]
+    y0_32 = probs[0].query("y")
     result = {
         "metric": "IPM solves/s (2D Poisson 511^2, L1 + control and state boxes)",
         "value": B * args.steps / t,
@@ -614,13 +770,27 @@ def main():
         "config": {"workload": f"poisson2d_511 x{B}: 2D Poisson {args.N}x{args.N} interior, alpha=1e-4, "
                                "beta=1e-3, u in [-5,5], y in [-0.2,0.3], sigma=0.2, IPM tol 1e-6; "
                                f"{B} instances (seeds 0..{B - 1}) solved as one batch per step",
-                   "batch": B, "krylov": "minres", "precond": "P_D", "mg_precision": "fp32", "vcycles": 1,
-                   "nu_pre": 2, "nu_post": 2, "krylov_tol": 1e-10, "status": st},
+                   "batch": B, "krylov": "minres", "precond": "P_D", "mg_precision": opts.mg_precision,
+                   "vcycles": opts.vcycles, "nu_pre": opts.nu_pre, "nu_post": opts.nu_post, "mg_tile": opts.mg_tile,
+                   "krylov_tol": 1e-10, "status": st},
+        "autotune": tune,
         "krylov_its_per_s": its / t,
         "nli": [s_.nli for s_ in stats],
         "krylov_its_per_solve": its / (B * args.steps),
         "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99), "of": "one batched step"},
     }
+
+    # seed 0 against the oracle's stored solution of the same inputs (written by
+    # tests/golden/make_poisson2d_511_oracle.py), with the oracle's own error
+    golden = os.path.join(ROOT, "tests", "golden", "poisson2d_511_seed0_oracle.npz")
+    if args.N == 511 and os.path.exists(golden):
+        g = np.load(golden, allow_pickle=False)
+        result["parity_vs_oracle"] = {
+            "instance": "seed 0", "nli": stats[0].nli, "oracle_nli": int(g["nli"]),
+            "rel_l2_u": float(np.linalg.norm(u32[0] - g["u"]) / np.linalg.norm(g["u"])),
+            "rel_l2_y": float(np.linalg.norm(y0_32 - g["y"]) / np.linalg.norm(g["y"])),
+            "fp64_oracle_error_u": float(g["oracle_error_u"]), "fp64_oracle_error_y": float(g["oracle_error_y"]),
+            "fp64_oracle_error_is": "|u(eps=1e-6) - u(eps=1e-12)| / |u(eps=1e-12)| of the oracle"}
 
     # roofline of the dominant kernel of the batched step, timed with HIP events on the
     # solve stream (one launch serves all instances)
@@ -640,7 +810,7 @@ def main():
     result["kernels"] = kern
 
     if not args.no_fp64:
-        opts64 = Options(sigma=datas[0].sigma, mg_precision="fp64")
+        opts64 = Options(**{**opts.__dict__, "mg_precision": "fp64"})
         batch.solve(opts64, stream=stream)
         torch.cuda.synchronize()
         n64 = max(2, args.steps // 2)
@@ -660,7 +830,8 @@ def main():
 
     # one instance alone (latency of a single solve)
     single = probs[0]
-    ts, lat1, its1, st1, rc1 = time_solves(single, opts, max(3, args.steps // 2), 1, torch)
+    opts1 = Options(**{**opts.__dict__, "mg_tile": "auto"})
+    ts, lat1, its1, st1, rc1 = time_solves(single, opts1, max(3, args.steps // 2), 1, torch)
     n1 = max(3, args.steps // 2)
     result["single_instance"] = {"solves_per_s": n1 / ts, "krylov_its_per_s": its1 / ts, "nli": st1.nli,
                                  "latency_ms": {"p50": percentile(lat1, 50), "p99": percentile(lat1, 99)},
@@ -669,6 +840,12 @@ def main():
     for p in probs:
         p.close()
 
+    if args.small:
+        result["small"] = bench_small(W, torch, 3)
+    if args.fd3d_N > 0:
+        result["fd3d"] = bench_fd3d(W, torch, args.fd3d_N, betas, 1)
+    if args.cd_N > 0:
+        result["convdiff"] = bench_cd(W, torch, args.cd_N, 2)
     if args.partial_N > 0:
         result["partial_observation"] = bench_partial(W, torch, args.partial_N, 2)
     if args.q1_N > 0:
@@ -689,7 +866,7 @@ def main():
 
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample ...")
-        result["cpu_baseline"] = cpu_baseline(data0, st1.nli)
+        result["cpu_baseline"] = cpu_baseline(data0, st1.nli, full=args.cpu_full)
     print(json.dumps(result), flush=True)
 
 

@@ -66,6 +66,7 @@ enum { IPMPDE_PD = 0, IPMPDE_PT = 1, IPMPDE_PPI = 2 };
 enum { IPMPDE_FP64 = 0, IPMPDE_FP32 = 1 };
 enum { IPMPDE_MU_PAPER = 0, IPMPDE_MU_CENTRAL = 1 };
 enum { IPMPDE_MASS_UNIT = 0, IPMPDE_MASS_HD = 1 };
+enum { IPMPDE_TILE_AUTO = 0, IPMPDE_TILE_SMALL = 1, IPMPDE_TILE_LARGE = 2 };
 
 /* Fields for ipmpde_query / ipmpde_set_field (each n doubles). */
 enum {
@@ -116,6 +117,11 @@ typedef struct {
                           argument of the single-step entry points are in HD units (w times
                           the unit ones).  Stationary problems only (IPMPDE_EINVAL for the heat
                           equation and in an engine). */
+  int mg_tile;         /* tile size of the fused 2D Poisson multigrid level kernels:
+                          IPMPDE_TILE_AUTO (default: the large tiles when a launch still has
+                          at least 2048 workgroups of them), IPMPDE_TILE_SMALL (8 coarse / 16
+                          fine nodes per side) or IPMPDE_TILE_LARGE (16 / 32, where the LDS
+                          tile fits); no node's arithmetic depends on it */
 } ipmpde_options;
 
 #define IPMPDE_MAX_HIST 256
@@ -329,6 +335,26 @@ void ipmpde_batch_destroy(ipmpde_batch* batch);
  * once every instance has finished; each problem's outcome is in its
  * stats (ipmpde_get_stats) and its iterates are queryable. */
 int ipmpde_batch_solve(ipmpde_batch* batch, const ipmpde_options* opts, int per_problem, ipmpde_stream stream);
+
+/* Autotuner of the multigrid schedule (the batching form's tile and
+ * smoother schedules): times whole batched solves of this batch for each
+ * candidate (V-cycles and Jacobi sweeps per solve in {1 x 1+1, 1 x 2+2,
+ * 1 x 3+3, 2 x 1+1, 2 x 2+2}, for 2D Poisson batches both tile sizes of the
+ * level kernels, with IPMPDE_TUNE_PRECISION in flags also the other V-cycle
+ * precision) and returns in *best the options `base` (NULL = defaults) with
+ * the fastest candidate's vcycles, nu_pre, nu_post, mg_precision and mg_tile
+ * among those that solve every instance (IPMPDE_ENOTCONVERGED if none does).
+ * Each candidate costs two batched solves, so the problems' iterates hold the
+ * last candidate's result afterwards.  cache_path (may be NULL) names a JSON
+ * file of earlier results keyed by the GPU architecture and the batch's shape
+ * (dimension, PDE kinds, largest N and nt, count, Krylov method,
+ * preconditioner, state bounds, restart, precision unless tuned); a hit
+ * returns the stored pick without solving (*from_cache = 1), a miss tunes and
+ * adds the result to the file.  best_ms (may be NULL) receives the winner's
+ * solve time in milliseconds; from_cache may be NULL. */
+enum { IPMPDE_TUNE_PRECISION = 1 };
+int ipmpde_batch_autotune(ipmpde_batch* batch, const ipmpde_options* base, int flags, const char* cache_path,
+                          ipmpde_stream stream, ipmpde_options* best, double* best_ms, int* from_cache);
 
 /* ipmpde_time_kernel for a whole batch: one launch serves every instance;
  * *bytes sums the instances' algorithmic bytes.  Requires a Newton setup by

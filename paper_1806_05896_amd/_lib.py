@@ -17,6 +17,8 @@ PD, PT, PPI = 0, 1, 2
 FP64, FP32 = 0, 1
 MU_PAPER, MU_CENTRAL = 0, 1
 MASS_UNIT, MASS_HD = 0, 1
+TILE_AUTO, TILE_SMALL, TILE_LARGE = 0, 1, 2
+TUNE_PRECISION = 1
 MAX_HIST = 256
 
 FIELDS = {
@@ -44,7 +46,7 @@ class COptions(C.Structure):
         ("krylov", C.c_int), ("precond", C.c_int), ("restart", C.c_int), ("krylov_tol", C.c_double),
         ("krylov_maxit", C.c_int), ("vcycles", C.c_int), ("nu_pre", C.c_int), ("nu_post", C.c_int),
         ("omega", C.c_double), ("mg_precision", C.c_int), ("chunk", C.c_int), ("use_graphs", C.c_int),
-        ("mu_rule", C.c_int), ("mass_scaling", C.c_int),
+        ("mu_rule", C.c_int), ("mass_scaling", C.c_int), ("mg_tile", C.c_int),
     ]
 
 
@@ -113,6 +115,8 @@ SIGNATURES = {
     "ipmpde_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_void_p)]),
     "ipmpde_batch_destroy": (None, [C.c_void_p]),
     "ipmpde_batch_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
+    "ipmpde_batch_autotune": (C.c_int, [C.c_void_p, C.POINTER(COptions), C.c_int, C.c_char_p, C.c_void_p,
+                                        C.POINTER(COptions), C.POINTER(C.c_double), C.POINTER(C.c_int)]),
     "ipmpde_batch_time_kernel": (C.c_int, [C.c_void_p, C.POINTER(COptions), C.c_int, C.c_int, C.c_void_p,
                                            C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "ipmpde_engine_create": (C.c_int, [C.c_size_t, C.c_int, C.POINTER(C.c_void_p)]),

@@ -65,6 +65,28 @@ class Options:
     use_graphs: bool = True
     mu_rule: str = "paper"          # "paper" (sigma mu^k) | "central" (sigma x mean complementarity)
     mass_scaling: str = "unit"      # "unit" (divided by the lumped mass h^d) | "hd" (literal weighting)
+    mg_tile: str = "auto"           # "auto" | "small" | "large": tiles of the 2D Poisson level kernels
+
+    _ENUMS = {
+        "krylov": {"minres": L.MINRES, "fgmres": L.FGMRES},
+        "precond": {"pd": L.PD, "pt": L.PT, "ppi": L.PPI},
+        "mg_precision": {"fp64": L.FP64, "fp32": L.FP32},
+        "mu_rule": {"paper": L.MU_PAPER, "central": L.MU_CENTRAL},
+        "mass_scaling": {"unit": L.MASS_UNIT, "hd": L.MASS_HD},
+        "mg_tile": {"auto": L.TILE_AUTO, "small": L.TILE_SMALL, "large": L.TILE_LARGE},
+    }
+
+    @classmethod
+    def from_c(cls, o: L.COptions) -> "Options":
+        kw = {}
+        for f in fields(cls):
+            v = getattr(o, f.name)
+            if f.name in cls._ENUMS:
+                v = {c: k for k, c in cls._ENUMS[f.name].items()}[v]
+            elif f.name == "use_graphs":
+                v = bool(v)
+            kw[f.name] = v
+        return cls(**kw)
 
     def to_c(self) -> L.COptions:
         o = L.COptions()
@@ -82,6 +104,8 @@ class Options:
                 v = {"paper": L.MU_PAPER, "central": L.MU_CENTRAL}[v]
             elif f.name == "mass_scaling":
                 v = {"unit": L.MASS_UNIT, "hd": L.MASS_HD}[v]
+            elif f.name == "mg_tile":
+                v = {"auto": L.TILE_AUTO, "small": L.TILE_SMALL, "large": L.TILE_LARGE}[v]
             setattr(o, f.name, v)
         return o
 
@@ -320,6 +344,19 @@ class Batch:
         L.check(self._lib.ipmpde_batch_solve(self._h, ptr, per, _stream_handle(stream)))
         return [p.stats().status for p in self.problems]
 
+    def autotune(self, opts: Optional[Options] = None, cache: Optional[str] = None, tune_precision: bool = False,
+                 stream=None):
+        """The library's autotuner (ipmpde_batch_autotune): returns (Options with
+        the fastest multigrid schedule, its batched solve time in ms, whether
+        it came from the cache file)."""
+        best = L.COptions()
+        ms, hit = C.c_double(), C.c_int()
+        path = None if cache is None else os.fsencode(cache)
+        L.check(self._lib.ipmpde_batch_autotune(self._h, Problem._opts(opts), L.TUNE_PRECISION if tune_precision else 0,
+                                                path, _stream_handle(stream), C.byref(best), C.byref(ms),
+                                                C.byref(hit)))
+        return Options.from_c(best), ms.value, bool(hit.value)
+
     def time_kernel(self, kernel: int, reps: int = 50, opts: Optional[Options] = None, stream=None):
         """(avg_ms, bytes) of one launch serving every instance (after a batch solve)."""
         ms, b = C.c_double(), C.c_double()
@@ -409,6 +446,45 @@ class Engine:
 
     def __exit__(self, *a):
         self.close()
+
+
+# The registered allocator callbacks; kept referenced while registered (the
+# library calls them whenever it allocates or frees device memory).
+_allocator_keep = None
+
+
+def use_torch_allocator(enable: bool = True) -> None:
+    """Route the library's device allocations through PyTorch's caching
+    allocator (ipmpde_set_allocator), or back to hipMalloc/hipFree.
+
+    Affects problems, batches and engines created (and workspaces allocated)
+    afterwards; memory already held keeps the allocator it came from.  Blocks
+    come from the allocator's pool for the current device and stream at the
+    time of the call.  The library synchronizes the device before it frees a
+    problem's or a batch's memory and frees a served request's workspace only
+    after the engine step that retired it has synchronized its stream, so a
+    freed block is idle when the caching allocator hands it out again."""
+    global _allocator_keep
+    lib = L.load()
+    if not enable:
+        L.check(lib.ipmpde_set_allocator(L.ALLOC_FN(), L.FREE_FN(), None))
+        _allocator_keep = None
+        return
+    import torch
+
+    def _alloc(nbytes, ctx):
+        try:
+            return int(torch.cuda.caching_allocator_alloc(int(nbytes)))
+        except Exception:  # out of memory: the library reports ENOMEM
+            return None
+
+    def _free(ptr, ctx):
+        if ptr:
+            torch.cuda.caching_allocator_delete(int(ptr))
+
+    keep = (L.ALLOC_FN(_alloc), L.FREE_FN(_free))
+    L.check(lib.ipmpde_set_allocator(keep[0], keep[1], None))
+    _allocator_keep = keep
 
 
 def footprint_bytes(dim: int, N: int, pde: str = "poisson", has_state_bounds: bool = False,

@@ -49,7 +49,7 @@ static bool same_solver(const ipmpde_options& a, const ipmpde_options& b) {
   return a.krylov == b.krylov && a.precond == b.precond && a.restart == b.restart && a.krylov_tol == b.krylov_tol &&
          a.krylov_maxit == b.krylov_maxit && a.nu_pre == b.nu_pre && a.nu_post == b.nu_post && a.omega == b.omega &&
          a.mg_precision == b.mg_precision && a.chunk == b.chunk && a.use_graphs == b.use_graphs &&
-         a.vcycles == b.vcycles;
+         a.vcycles == b.vcycles && a.mg_tile == b.mg_tile;
 }
 
 static int next_pow2(int x) {

@@ -184,7 +184,7 @@ __device__ __forceinline__ T coarse_resid(const T* __restrict__ x, const T* __re
 template <typename T>
 __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse(const Inst* __restrict__ Dp, int transpose, int guard) {
   INST_BEGIN
-  if (I.coarse_p2 || mg_skip(I, guard)) return;
+  if (I.coarse_p2 || I.pde == 1 || mg_skip(I, guard)) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ CoarseLevel LI[kMaxLev];
   T* lds = (T*)lds_raw;
@@ -512,6 +512,159 @@ __device__ __forceinline__ const T* coarse_p2_cycle(T* lds, const int* LN, const
   return lds + LOFF[cl] + ((alt >> cl) & 1u) * P * P;
 }
 
+// Convection-diffusion (2D upwind) coarse levels in one workgroup.  Per level
+// the operator's coefficients are evaluated once per launch (the wind in
+// FP64, rounded to T) and staged in LDS: the diagonal with the reaction term
+// cd = op_diag + m, its inverse, and the four neighbour coefficients of the
+// node's row of A (west, east, south, north).  A row of A^T takes the
+// neighbours' coefficients towards this node (the east neighbour's west
+// coefficient, ...).  LDS per level: x, x2, b, cd, 1/cd, cW, cE, cS, cN
+// (kCoarseCDArrays arrays of n).
+constexpr int kCoarseCDArrays = 9;
+// Levels of the widest coarse hierarchy (63, 31, 15, 7, 3, 1).
+constexpr int kCoarseP2Levels = 6;
+
+template <typename T>
+__device__ __forceinline__ T cd_row(const T* __restrict__ x, const T* __restrict__ cf, int i, int i1, int i2, int N,
+                                    int n, bool tr) {
+  const T* cW = cf + 2 * n;
+  const T* cE = cf + 3 * n;
+  const T* cS = cf + 4 * n;
+  const T* cN = cf + 5 * n;
+  T r = cf[i] * x[i];
+  if (!tr) {
+    if (i1 > 0) r += cW[i] * x[i - 1];
+    if (i1 < N - 1) r += cE[i] * x[i + 1];
+    if (i2 > 0) r += cS[i] * x[i - N];
+    if (i2 < N - 1) r += cN[i] * x[i + N];
+  } else {
+    if (i1 < N - 1) r += cW[i + 1] * x[i + 1];
+    if (i1 > 0) r += cE[i - 1] * x[i - 1];
+    if (i2 < N - 1) r += cS[i + N] * x[i + N];
+    if (i2 > 0) r += cN[i - N] * x[i - N];
+  }
+  return r;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_cd(const Inst* __restrict__ Dp, int transpose, int guard) {
+  INST_BEGIN
+  if (I.coarse_p2 || I.pde != 1 || mg_skip(I, guard)) return;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ int LN[kMaxLev], LOFF[kMaxLev];
+  T* lds = (T*)lds_raw;
+  const int cl = I.coarse_lev, L = I.nlev;
+  const bool tr = transpose != 0;
+  const int tid = threadIdx.x;
+  const T om = (T)I.omega;
+  const double eps = I.eps;
+  if (tid == 0) {
+    int off = 0;
+    for (int l = cl; l < L; ++l) {
+      LN[l] = I.lv[l].N;
+      LOFF[l] = off;
+      off += kCoarseCDArrays * I.lv[l].n;
+    }
+  }
+  __syncthreads();
+  // stage: the top level's b, and per level the coefficients (layout
+  // x | x2 | b | cd | 1/cd | cW | cE | cS | cN).  The widest level is at
+  // most 31 x 31, so each thread holds at most one node of every level: its
+  // global loads (b and every level's m) are issued together first.
+  const int N0 = I.lv[cl].N;
+  T mreg[kCoarseP2Levels], breg;
+  {
+    const int sh = 31 - __builtin_clz(N0 + 1), j1 = tid & ((1 << sh) - 1), j2 = tid >> sh;
+    breg = (j1 < N0 && j2 < N0) ? ((const T*)I.lv[cl].b)[j1 + N0 * j2] : (T)0;
+  }
+#pragma unroll
+  for (int q = 0; q < kCoarseP2Levels; ++q) {
+    const int N = ((N0 + 1) >> q) - 1;
+    const int sh = 31 - __builtin_clz(N + 1), j1 = tid & ((1 << sh) - 1), j2 = tid >> sh;
+    mreg[q] = (cl + q < L && j1 < N && j2 < N) ? ((const T*)I.lv[cl + q].mh)[j1 + N * j2] : (T)0;
+  }
+#pragma unroll
+  for (int q = 0; q < kCoarseP2Levels; ++q) {
+    if (cl + q < L) {
+      const int N = ((N0 + 1) >> q) - 1, n = N * N;
+      const int sh = 31 - __builtin_clz(N + 1), j1 = tid & ((1 << sh) - 1), j2 = tid >> sh;
+      if (j1 < N && j2 < N) {
+        const int i = j1 + N * j2;
+        const double h = I.lv[cl + q].h, ed = eps / (h * h), ih = 1.0 / h;
+        double w1, w2;
+        wind((j1 + 1) * h, (j2 + 1) * h, w1, w2);
+        T* base = lds + LOFF[cl + q];
+        T* cf = base + 3 * n;
+        const T cd = (T)(4.0 * ed + (fabs(w1) + fabs(w2)) * ih) + mreg[q];
+        cf[i] = cd;
+        cf[n + i] = (T)1 / cd;
+        cf[2 * n + i] = (T)(-ed - fmax(w1, 0.0) * ih);
+        cf[3 * n + i] = (T)(-ed + fmin(w1, 0.0) * ih);
+        cf[4 * n + i] = (T)(-ed - fmax(w2, 0.0) * ih);
+        cf[5 * n + i] = (T)(-ed + fmin(w2, 0.0) * ih);
+        if (q == 0) base[2 * n + i] = breg;
+      }
+    }
+  }
+  __syncthreads();
+  unsigned alt = 0;  // bit l: level l's iterate sits in x2
+  for (int l = cl; l < L - 1; ++l) {
+    const int N = LN[l], n = N * N;
+    T* a = lds + LOFF[l];
+    T* c = a + n;
+    const T* B = a + 2 * n;
+    const T* cf = a + 3 * n;
+    for (int sw = 0; sw < I.nu_pre; ++sw) {
+      P2_FOR(N)
+        c[i] = sw == 0 ? om * B[i] * cf[n + i] : a[i] + om * (B[i] - cd_row<T>(a, cf, i, i1, i2, N, n, tr)) * cf[n + i];
+      P2_END
+      __syncthreads();
+      T* t = a; a = c; c = t;
+      alt ^= 1u << l;
+    }
+    P2_FOR(N) c[i] = B[i] - cd_row<T>(a, cf, i, i1, i2, N, n, tr); P2_END
+    __syncthreads();
+    const int Nc = LN[l + 1];
+    T* Bc = lds + LOFF[l + 1] + 2 * Nc * Nc;
+    P2_FOR(Nc)
+      const int f = (2 * i1 + 1) + N * (2 * i2 + 1);
+      Bc[i] = (T)0.25 * c[f] + (T)0.125 * (c[f - 1] + c[f + 1] + c[f - N] + c[f + N]) +
+              (T)0.0625 * (c[f - 1 - N] + c[f + 1 - N] + c[f - 1 + N] + c[f + 1 + N]);
+    P2_END
+    __syncthreads();
+  }
+  {
+    const int N = LN[L - 1], n = N * N;
+    T* X = lds + LOFF[L - 1];
+    P2_FOR(N) X[i] = X[2 * n + i] * X[4 * n + i]; P2_END
+    __syncthreads();
+  }
+  for (int l = L - 2; l >= cl; --l) {
+    const int N = LN[l], n = N * N, Nc = LN[l + 1];
+    const int ca = (alt >> l) & 1u;
+    T* a = lds + LOFF[l] + ca * n;
+    T* c = lds + LOFF[l] + (1 - ca) * n;
+    const T* B = lds + LOFF[l] + 2 * n;
+    const T* cf = lds + LOFF[l] + 3 * n;
+    const T* xc = lds + LOFF[l + 1] + ((alt >> (l + 1)) & 1u) * Nc * Nc;
+    P2_FOR(N) a[i] += prolong_node<T, true>(xc, i, N, Nc, 2); P2_END
+    __syncthreads();
+    for (int sw = 0; sw < I.nu_post; ++sw) {
+      P2_FOR(N) c[i] = a[i] + om * (B[i] - cd_row<T>(a, cf, i, i1, i2, N, n, tr)) * cf[n + i]; P2_END
+      __syncthreads();
+      T* t = a; a = c; c = t;
+      alt ^= 1u << l;
+    }
+  }
+  const int N = LN[cl];
+  T* xg = (T*)I.lv[cl].x;
+  const T* xs = lds + LOFF[cl] + ((alt >> cl) & 1u) * N * N;
+  P2_FOR(N) xg[i] = xs[i]; P2_END
+}
+template __global__ void k_mg_coarse_cd<float>(const Inst*, int, int);
+template __global__ void k_mg_coarse_cd<double>(const Inst*, int, int);
+
+
 template <typename T>
 __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_p2(const Inst* __restrict__ Dp, int guard) {
   INST_BEGIN
@@ -523,13 +676,29 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_p2(const Inst* __restri
   const int cl = I.coarse_lev, L = I.nlev;
   const int tid = threadIdx.x;
   const int N0 = I.lv[cl].N, n0 = N0 * N0;
-  // the top level's right-hand side, in flight while the image is copied
+  // Global loads first, all in flight together: the top level's right-hand
+  // side and every level's reaction term m (the diagonal is d = 4/h^2 + m, or
+  // 8/(3h^2) + m for the Q1 stiffness).  The iterates start at zero (their
+  // zero rings are never written; the interiors are written before they are
+  // read) and the lower levels' right-hand sides come from the restriction,
+  // so nothing else of the level arrays is read.
   const T* __restrict__ bg = (const T*)I.lv[cl].b;
   T breg[p2_per_thread<T>()];
 #pragma unroll
   for (int j = 0; j < p2_per_thread<T>(); ++j) {
     const int i = tid + j * kCoarseBS;
     breg[j] = i < n0 ? bg[i] : (T)0;
+  }
+  T mreg[kCoarseP2Levels][p2_per_thread<T>()];
+#pragma unroll
+  for (int q = 0; q < kCoarseP2Levels; ++q) {
+    const int N = ((N0 + 1) >> q) - 1, n = N * N;
+    const T* __restrict__ m = cl + q < L ? (const T*)I.lv[cl + q].mh : nullptr;
+#pragma unroll
+    for (int j = 0; j < p2_per_thread<T>(); ++j) {
+      const int i = tid + j * kCoarseBS;
+      mreg[q][j] = (cl + q < L && i < n) ? m[i] : (T)0;
+    }
   }
   if (tid == 0) {
     // level widths, offsets and 1/h^2 from the top width (h = 1 / (N + 1))
@@ -545,25 +714,35 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_p2(const Inst* __restri
   }
   // layout of level l at LOFF[l]: xa[(N+2)^2], xb[(N+2)^2], b[N^2], d[N^2], dinv[N^2]
   {
-    const T* __restrict__ pk = (const T*)I.cpack;
-    const int total = I.cpack_elems;
-    int k = tid;
-    for (; k + 3 * kCoarseBS < total; k += 4 * kCoarseBS) {
-      const T v0 = pk[k], v1 = pk[k + kCoarseBS], v2 = pk[k + 2 * kCoarseBS], v3 = pk[k + 3 * kCoarseBS];
-      lds[k] = v0;
-      lds[k + kCoarseBS] = v1;
-      lds[k + 2 * kCoarseBS] = v2;
-      lds[k + 3 * kCoarseBS] = v3;
-    }
-    for (; k < total; k += kCoarseBS) lds[k] = pk[k];
-  }
-  __syncthreads();
-  {
-    T* b = lds + LOFF[cl] + 2 * (N0 + 2) * (N0 + 2);
+    int off = 0;
 #pragma unroll
-    for (int j = 0; j < p2_per_thread<T>(); ++j) {
-      const int i = tid + j * kCoarseBS;
-      if (i < n0) b[i] = breg[j];
+    for (int q = 0; q < kCoarseP2Levels; ++q) {
+      if (cl + q < L) {
+        const int N = ((N0 + 1) >> q) - 1, n = N * N, PP = (N + 2) * (N + 2);
+        T* x = lds + off;
+        for (int k = tid; k < 2 * PP; k += kCoarseBS) x[k] = (T)0;
+        const double h = I.lv[cl + q].h;
+        const T diag = I.coarse_p2 == 2 ? (T)(8.0 / (3.0 * h * h)) : (T)4 * (T)(1.0 / (h * h));
+        T* d = x + 2 * PP + n;
+#pragma unroll
+        for (int j = 0; j < p2_per_thread<T>(); ++j) {
+          const int i = tid + j * kCoarseBS;
+          if (i < n) {
+            const T dv = diag + mreg[q][j];
+            d[i] = dv;
+            d[n + i] = (T)1 / dv;
+          }
+        }
+        if (q == 0) {
+          T* b = x + 2 * PP;
+#pragma unroll
+          for (int j = 0; j < p2_per_thread<T>(); ++j) {
+            const int i = tid + j * kCoarseBS;
+            if (i < n0) b[i] = breg[j];
+          }
+        }
+        off += coarse_p2_elems(N);
+      }
     }
   }
   __syncthreads();

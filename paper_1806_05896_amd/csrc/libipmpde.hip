@@ -107,10 +107,14 @@ struct GraphKey {
   int mg_fp32, nu_pre, nu_post, chunk, maxit, zc, max_n, max_nlev, max_cl, flags;
   size_t coarse_lds;
   double omega, tol;
+  // FGMRES: 1 + the preconditioner kind, the first Arnoldi step of the
+  // captured range and the vcycles (0 for MINRES chunks)
+  int fg = 0, j0 = 0, vcycles = 0;
   bool operator<(const GraphKey& o) const {
-    return std::tie(mg_fp32, nu_pre, nu_post, chunk, maxit, zc, max_n, max_nlev, max_cl, flags, coarse_lds, omega, tol) <
+    return std::tie(mg_fp32, nu_pre, nu_post, chunk, maxit, zc, max_n, max_nlev, max_cl, flags, coarse_lds, omega, tol,
+                    fg, j0, vcycles) <
            std::tie(o.mg_fp32, o.nu_pre, o.nu_post, o.chunk, o.maxit, o.zc, o.max_n, o.max_nlev, o.max_cl, o.flags,
-                    o.coarse_lds, o.omega, o.tol);
+                    o.coarse_lds, o.omega, o.tol, o.fg, o.j0, o.vcycles);
   }
 };
 static constexpr size_t kMaxGraphs = 64;
@@ -140,7 +144,9 @@ struct Group {
   long maxn[kMaxLev] = {0};
   size_t coarse_lds = 0;
   bool p2 = false;   // some instance is 2D Poisson (padded coarse kernel)
-  bool gen = false;  // some instance uses the generic coarse kernel
+  bool gen = false;  // some instance uses the generic (unpadded) level and coarse kernels
+  bool cd = false;   // some instance is 2D convection-diffusion (its own coarse kernel)
+  bool gen3 = false; // some instance takes the generic coarse kernel (3D)
   int max_cpack = 0; // longest coarse LDS image (Poisson instances)
   bool any_small = false;  // 2D: some instance runs its whole hierarchy in the coarse kernel
   int outsel = 1;    // level-0 output buffer of a V-cycle (x2 = 1)
@@ -148,6 +154,7 @@ struct Group {
   bool q1 = false;   // Q1 finite-element problems (likewise): generic multigrid path
   int sel_pre = 0;   // 3D path: buffer holding the pre-smoothed iterate
   bool fp32 = true;
+  int tile = IPMPDE_TILE_AUTO;  // tile policy of the 2D Poisson level kernels (options.mg_tile)
 };
 
 struct ipmpde_problem {
@@ -216,26 +223,40 @@ static constexpr size_t kCoarseLds = 150 * 1024;
 // the FP64 kernels size their per-thread arrays for coarse levels of at most 31 x 31
 static_assert((size_t)coarse_p2_elems(63) * 8 > kCoarseLds, "an FP64 63 x 63 level must not fit the coarse kernel");
 
-// p2: the Poisson 2D coarse kernel (padded layout), else the generic one.
-static size_t coarse_level_elems(const Level& L, bool p2) {
-  return p2 ? (size_t)coarse_p2_elems(L.N) : 4 * (size_t)L.n;
+// Coarse kernel kinds: the generic one (3D), the padded 2D Poisson one
+// (finite differences and Q1) and the 2D convection-diffusion one with
+// staged stencil coefficients.
+enum { kCoarseGeneric = 0, kCoarseP2 = 1, kCoarseCD = 2 };
+
+static size_t coarse_level_elems(const Level& L, int kind) {
+  if (kind == kCoarseP2) return (size_t)coarse_p2_elems(L.N);
+  if (kind == kCoarseCD) return (size_t)kCoarseCDArrays * L.n;
+  return 4 * (size_t)L.n;
 }
 
-static int pick_coarse(const Level* lv, int nlev, size_t elem, int dim, bool p2) {
-  const int nmax = dim == 2 ? kCoarseP2MaxN : 15;
+// Largest grid of each coarse kernel: the convection-diffusion stencil costs
+// several wind evaluations per node to stage, so its 63 x 63 level runs on
+// the grid-wide level kernels instead.
+static int coarse_max_N(int dim, int kind) {
+  if (dim == 3) return 15;
+  return kind == kCoarseCD ? 31 : kCoarseP2MaxN;
+}
+
+static int pick_coarse(const Level* lv, int nlev, size_t elem, int dim, int kind) {
+  const int nmax = coarse_max_N(dim, kind);
   int cl = nlev - 1;
   size_t need = 0;
   for (int l = nlev - 1; l >= 0; --l) {
-    need += coarse_level_elems(lv[l], p2) * elem;
+    need += coarse_level_elems(lv[l], kind) * elem;
     if (need > kCoarseLds || lv[l].N > nmax) break;
     cl = l;
   }
   return cl;
 }
 
-static size_t coarse_lds_bytes(const Level* lv, int nlev, int cl, size_t elem, bool p2) {
+static size_t coarse_lds_bytes(const Level* lv, int nlev, int cl, size_t elem, int kind) {
   size_t need = 0;
-  for (int l = cl; l < nlev; ++l) need += coarse_level_elems(lv[l], p2) * elem;
+  for (int l = cl; l < nlev; ++l) need += coarse_level_elems(lv[l], kind) * elem;
   return need;
 }
 
@@ -245,6 +266,7 @@ static int set_coarse_lds_limit() {
   static hipError_t err = hipSuccess;
   std::call_once(once, [] {
     const void* fns[] = {(const void*)k_mg_coarse<float>, (const void*)k_mg_coarse<double>,
+                         (const void*)k_mg_coarse_cd<float>, (const void*)k_mg_coarse_cd<double>,
                          (const void*)k_mg_coarse_p2<float>, (const void*)k_mg_coarse_p2<double>,
                          (const void*)k_heat_sweep_p2<float>, (const void*)k_heat_sweep_p2<double>};
     for (const void* f : fns) {
@@ -259,6 +281,10 @@ static int set_coarse_lds_limit() {
 static bool is_p2(const ipmpde_problem* P) { return P->dim == 2 && P->pde == IPMPDE_POISSON; }
 // The padded single-workgroup coarse kernel: 2D Poisson (five-point) and Q1 (nine-point).
 static bool padded_coarse(const ipmpde_problem* P) { return is_p2(P) || (P->dim == 2 && P->pde == IPMPDE_POISSON_Q1); }
+static int coarse_kind(const ipmpde_problem* P) {
+  if (padded_coarse(P)) return kCoarseP2;
+  return P->pde == IPMPDE_CONVDIFF ? kCoarseCD : kCoarseGeneric;
+}
 
 // Reaction-term slots of every multigrid level (see k_mg_select): the
 // Schur-approximation operator's, and the two extra operators of P_Pi.
@@ -288,7 +314,7 @@ static int ensure_mg_heat(ipmpde_problem* P, bool fp32) {
     N = (N - 1) / 2;
   }
   for (void*& a : (fp32 ? P->kc32 : P->kc64)) TRY(P->work.alloc(&a, (size_t)lv[0].n * el * nt));
-  const int cl = pick_coarse(lv, P->nlev, el, 2, true);
+  const int cl = pick_coarse(lv, P->nlev, el, 2, kCoarseP2);
   (fp32 ? P->coarse32 : P->coarse64) = cl;
   int elems = 0;
   for (int l = cl; l < P->nlev; ++l) elems += coarse_p2_elems(lv[l].N);
@@ -328,7 +354,7 @@ static int ensure_mg(ipmpde_problem* P, bool fp32) {
     N = (N - 1) / 2;
   }
   for (void*& a : (fp32 ? P->kc32 : P->kc64)) TRY(P->work.alloc(&a, (size_t)lv[0].n * el));
-  const int cl = pick_coarse(lv, P->nlev, el, P->dim, padded_coarse(P));
+  const int cl = pick_coarse(lv, P->nlev, el, P->dim, coarse_kind(P));
   (fp32 ? P->coarse32 : P->coarse64) = cl;
   if (padded_coarse(P)) {
     int elems = 0;
@@ -515,7 +541,7 @@ static void heat_steps(ipmpde_problem* P, const Inst& d, bool fp32) {
     V.maxN[l] = lv[l].N;
     V.maxn[l] = lv[l].n;
   }
-  V.coarse_lds = coarse_lds_bytes(lv, P->nlev, d.coarse_lev, el, true);
+  V.coarse_lds = coarse_lds_bytes(lv, P->nlev, d.coarse_lev, el, kCoarseP2);
   V.p2 = true;
   V.gen = false;
   V.max_cpack = pe;
@@ -528,12 +554,15 @@ static void heat_steps(ipmpde_problem* P, const Inst& d, bool fp32) {
 static int group_select(Group* G, const ipmpde_options& o) {
   const bool fp32 = o.mg_precision == IPMPDE_FP32;
   G->fp32 = fp32;
+  G->tile = o.mg_tile;
   G->max_n = 0;
   G->max_nlev = 0;
   G->max_cl = 0;
   G->coarse_lds = 0;
   G->p2 = false;
   G->gen = false;
+  G->cd = false;
+  G->gen3 = false;
   G->any_small = false;
   G->max_cpack = 0;
   std::fill(G->maxN, G->maxN + kMaxLev, 0);
@@ -590,7 +619,9 @@ static int group_select(Group* G, const ipmpde_options& o) {
     G->max_cpack = std::max(G->max_cpack, d.cpack_elems);
     G->p2 = G->p2 || padded_coarse(P);
     G->gen = G->gen || !padded_coarse(P);
-    G->coarse_lds = std::max(G->coarse_lds, coarse_lds_bytes(lv, P->nlev, d.coarse_lev, fp32 ? 4 : 8, padded_coarse(P)));
+    G->cd = G->cd || coarse_kind(P) == kCoarseCD;
+    G->gen3 = G->gen3 || coarse_kind(P) == kCoarseGeneric;
+    G->coarse_lds = std::max(G->coarse_lds, coarse_lds_bytes(lv, P->nlev, d.coarse_lev, fp32 ? 4 : 8, coarse_kind(P)));
   }
   if (G->heat)
     for (int i = 0; i < G->count; ++i) {
@@ -661,6 +692,7 @@ extern "C" int ipmpde_default_options(ipmpde_options* o) {
   o->use_graphs = 1;
   o->mu_rule = IPMPDE_MU_PAPER;
   o->mass_scaling = IPMPDE_MASS_UNIT;
+  o->mg_tile = IPMPDE_TILE_AUTO;
   return IPMPDE_OK;
 }
 
@@ -691,6 +723,8 @@ static int check_options(const ipmpde_options& o) {
   if (o.mu_rule != IPMPDE_MU_PAPER && o.mu_rule != IPMPDE_MU_CENTRAL) return fail(IPMPDE_EINVAL, "bad mu_rule");
   if (o.mass_scaling != IPMPDE_MASS_UNIT && o.mass_scaling != IPMPDE_MASS_HD)
     return fail(IPMPDE_EINVAL, "bad mass_scaling");
+  if (o.mg_tile != IPMPDE_TILE_AUTO && o.mg_tile != IPMPDE_TILE_SMALL && o.mg_tile != IPMPDE_TILE_LARGE)
+    return fail(IPMPDE_EINVAL, "bad mg_tile");
   return IPMPDE_OK;
 }
 
@@ -728,8 +762,11 @@ static void launch_coarse(Group* G, int transpose, int guard, hipStream_t s) {
   // each instance takes the kernel it would take alone (the other one
   // returns at once for it), so batched and solo solves round alike
   if (G->p2) hipLaunchKernelGGL(k_mg_coarse_p2<T>, dim3(1, 1, G->zc), dim3(kCoarseBS), G->coarse_lds, s, G->D, guard);
-  if (G->gen)
+  if (G->gen3)
     hipLaunchKernelGGL(k_mg_coarse<T>, dim3(1, 1, G->zc), dim3(kCoarseBS), G->coarse_lds, s, G->D, transpose, guard);
+  if (G->cd)
+    hipLaunchKernelGGL(k_mg_coarse_cd<T>, dim3(1, 1, G->zc), dim3(kCoarseBS), G->coarse_lds, s, G->D, transpose,
+                       guard);
 }
 
 // 3D (generic) V-cycle: per level nu_pre sweeps, residual + restriction,
@@ -778,12 +815,20 @@ static void launch_up2d(int nu, dim3 g, size_t lds, hipStream_t s, const Inst* D
 // has at least this many.
 static constexpr long kBigTileMinGroups = 2048;
 
+// Large tiles for a launch of `groups` large-tile workgroups under the
+// group's policy (options.mg_tile): by the workgroup count, or forced.
+static bool big_tiles(const Group* G, long groups) {
+  if (G->tile == IPMPDE_TILE_SMALL) return false;
+  if (G->tile == IPMPDE_TILE_LARGE) return true;
+  return groups >= kBigTileMinGroups;
+}
+
 template <typename T, int NU, int ST>
 static void launch_down_p2_nu(const Group* G, int l, int scaled, int guard, hipStream_t s) {
   const int Nc = G->maxN[l + 1];
   if constexpr (p2_down_lds<T, NU, 16>() <= kStaticLdsMax) {
     const int nt = div_up(Nc, 16);
-    if ((long)nt * nt * G->zc >= kBigTileMinGroups) {
+    if (big_tiles(G, (long)nt * nt * G->zc)) {
       hipLaunchKernelGGL((k_mg_down_p2<T, NU, 16, ST>), dim3(nt, nt, G->zc), dim3(kBS), 0, s, G->D, l, scaled, guard);
       return;
     }
@@ -797,7 +842,7 @@ static void launch_up_p2_nu(const Group* G, int l, int guard, hipStream_t s) {
   const int N = G->maxN[l];
   if constexpr (p2_up_lds<T, NU, 32>() <= kStaticLdsMax) {
     const int nt = div_up(N, 32);
-    if ((long)nt * nt * G->zc >= kBigTileMinGroups) {
+    if (big_tiles(G, (long)nt * nt * G->zc)) {
       hipLaunchKernelGGL((k_mg_up_p2<T, NU, 32, ST>), dim3(nt, nt, G->zc), dim3(kBS), 0, s, G->D, l, guard);
       return;
     }
@@ -1003,16 +1048,31 @@ static bool any_restart(const Group* G) {
     if (G->H[i].active && G->ctrl_h[i].want_restart) return true;
   return false;
 }
+// After the last restart cycle a solve whose true residual still misses the
+// tolerance is a Krylov failure (counted in the statistics, IPMPDE_EKRYLOV
+// from the single-step entry points), not a success.
+static void mark_unfinished(Group* G) {
+  for (int i = 0; i < G->count; ++i)
+    if (G->H[i].active && G->ctrl_h[i].want_restart) G->ctrl_h[i].failed = 1;
+}
 
-template <typename T>
-static int run_minres_chunk(Group* G, const ipmpde_options& o, hipStream_t s) {
-  if (!o.use_graphs) {
-    for (int t = 0; t < o.chunk; ++t) minres_iteration<T>(G, (1 + t) & 1, o.krylov_maxit, o.krylov_tol, s);
-    return IPMPDE_OK;
-  }
-  const int flags = (G->p2 ? 1 : 0) | (G->gen ? 2 : 0) | (G->any_small ? 4 : 0) | (G->outsel << 3);
+// The graph cache key of a launch sequence for this group and these options.
+static GraphKey graph_key(const Group* G, const ipmpde_options& o, int fg, int j0) {
+  const int flags = (G->p2 ? 1 : 0) | (G->gen ? 2 : 0) | (G->any_small ? 4 : 0) | (G->outsel << 3) |
+                    (G->q1 ? 16 : 0) | (G->heat ? 32 : 0) | (G->tile << 6) | (G->cd ? 256 : 0) | (G->gen3 ? 512 : 0);
   GraphKey key{G->fp32 ? 1 : 0, o.nu_pre, o.nu_post, o.chunk, o.krylov_maxit, G->zc, G->max_n, G->max_nlev,
                G->max_cl, flags, G->coarse_lds, G->H[0].omega, o.krylov_tol};
+  key.fg = fg;
+  key.j0 = j0;
+  key.vcycles = o.vcycles;
+  return key;
+}
+
+// Launch the sequence `body(stream)` through the group's graph cache: the
+// first use of a key captures it on the group's capture stream and
+// instantiates it; later uses launch the instantiated graph on s.
+template <typename F>
+static int launch_cached(Group* G, const GraphKey& key, hipStream_t s, F&& body) {
   auto it = G->graphs.find(key);
   if (it == G->graphs.end()) {
     if (G->graphs.size() >= kMaxGraphs) {
@@ -1021,7 +1081,7 @@ static int run_minres_chunk(Group* G, const ipmpde_options& o, hipStream_t s) {
     }
     hipGraph_t g;
     HIP_TRY(hipStreamBeginCapture(G->cap_stream, hipStreamCaptureModeThreadLocal));
-    for (int t = 0; t < o.chunk; ++t) minres_iteration<T>(G, (1 + t) & 1, o.krylov_maxit, o.krylov_tol, G->cap_stream);
+    body(G->cap_stream);
     HIP_TRY(hipStreamEndCapture(G->cap_stream, &g));
     hipGraphExec_t ge;
     hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
@@ -1031,6 +1091,18 @@ static int run_minres_chunk(Group* G, const ipmpde_options& o, hipStream_t s) {
   }
   HIP_TRY(hipGraphLaunch(it->second, s));
   return IPMPDE_OK;
+}
+
+template <typename T>
+static int run_minres_chunk(Group* G, const ipmpde_options& o, hipStream_t s) {
+  auto body = [&](hipStream_t st) {
+    for (int t = 0; t < o.chunk; ++t) minres_iteration<T>(G, (1 + t) & 1, o.krylov_maxit, o.krylov_tol, st);
+  };
+  if (!o.use_graphs) {
+    body(s);
+    return IPMPDE_OK;
+  }
+  return launch_cached(G, graph_key(G, o, 0, 0), s, body);
 }
 
 // MINRES on every active instance: a cycle from the right-hand side, then
@@ -1059,6 +1131,7 @@ static int minres_group(Group* G, const ipmpde_options& o, hipStream_t s) {
     TRY(read_ctrl(G, s));
     if (!any_restart(G)) return IPMPDE_OK;
   }
+  mark_unfinished(G);
   return IPMPDE_OK;
 }
 
@@ -1116,7 +1189,9 @@ static int fgmres_group(Group* G, const ipmpde_options& o, hipStream_t s) {
   const long n4 = 4L * G->max_n;
   const int pt = o.precond;  // IPMPDE_PD, IPMPDE_PT or IPMPDE_PPI
   const int nbm = fg_multidot_blocks(n4);
-  const int step = 4;
+  // Arnoldi steps between host checks: captured in one graph per range
+  // (the kernels of a stopped instance return at once)
+  const int step = o.use_graphs ? o.chunk : 4;
   hipLaunchKernelGGL(k_krylov_begin, gz(G, n4), dim3(kBS), 0, s, G->D);
   for (int cycle = 0; cycle < 1000; ++cycle) {
     const int src = cycle == 0 ? 0 : 1;
@@ -1124,7 +1199,15 @@ static int fgmres_group(Group* G, const ipmpde_options& o, hipStream_t s) {
     hipLaunchKernelGGL(k_fg_start_scale, gz(G, n4), dim3(kBS), 0, s, G->D, src);
     TRY(read_ctrl(G, s));
     for (int j0 = 0; j0 < o.restart && any_running(G); j0 += step) {
-      for (int j = j0; j < std::min(j0 + step, o.restart); ++j) fgmres_step<T>(G, pt, j, o.krylov_tol, o.krylov_maxit, s);
+      const int j1 = std::min(j0 + step, o.restart);
+      auto body = [&](hipStream_t st) {
+        for (int j = j0; j < j1; ++j) fgmres_step<T>(G, pt, j, o.krylov_tol, o.krylov_maxit, st);
+      };
+      if (o.use_graphs) {
+        TRY(launch_cached(G, graph_key(G, o, 1 + pt, j0 * 64 + j1), s, body));
+      } else {
+        body(s);
+      }
       HIP_TRY(hipGetLastError());
       TRY(read_ctrl(G, s));
     }
@@ -1137,6 +1220,7 @@ static int fgmres_group(Group* G, const ipmpde_options& o, hipStream_t s) {
     TRY(read_ctrl(G, s));
     if (!any_restart(G)) return IPMPDE_OK;
   }
+  mark_unfinished(G);
   return IPMPDE_OK;
 }
 
@@ -1477,7 +1561,7 @@ extern "C" size_t ipmpde_footprint_bytes(const ipmpde_grid* grid, const ipmpde_p
       ++nlev;
       if (N <= 1) break;
     }
-    bytes += A(kReactionSlots * coarse_lds_bytes(lv, nlev, pick_coarse(lv, nlev, el, 2, true), el, true));
+    bytes += A(kReactionSlots * coarse_lds_bytes(lv, nlev, pick_coarse(lv, nlev, el, 2, kCoarseP2), el, kCoarseP2));
   }
   if (o.krylov == IPMPDE_FGMRES) bytes += A((size_t)(o.restart + 1) * n4 * 8) + A((size_t)o.restart * n4 * 8);
   return bytes;
@@ -1488,6 +1572,7 @@ static void problem_free(ipmpde_problem* P) {
   P->self = nullptr;
   if (P->hs_h) (void)hipHostFree(P->hs_h);
   P->hs_h = nullptr;
+  release_work(P);
   P->mem.release();
 }
 
@@ -1988,11 +2073,13 @@ extern "C" int ipmpde_batch_solve(ipmpde_batch* B, const ipmpde_options* opts, i
     const ipmpde_options &a = po[0], &b = po[i];
     if (a.krylov != b.krylov || a.precond != b.precond || a.restart != b.restart || a.krylov_tol != b.krylov_tol ||
         a.krylov_maxit != b.krylov_maxit || a.nu_pre != b.nu_pre || a.nu_post != b.nu_post || a.omega != b.omega ||
-        a.mg_precision != b.mg_precision || a.chunk != b.chunk || a.use_graphs != b.use_graphs || a.vcycles != b.vcycles)
+        a.mg_precision != b.mg_precision || a.chunk != b.chunk || a.use_graphs != b.use_graphs || a.vcycles != b.vcycles ||
+        a.mg_tile != b.mg_tile)
       return fail(IPMPDE_EINVAL, "Krylov and multigrid options must agree across a batch");
   }
   return solve_group(G, po, S(stream));
 }
 
+#include "autotune.hip"
 #include "engine.hip"
 #include "timing.hip"

@@ -60,13 +60,14 @@ def test_binding_structs_match_the_c_compiler(tmp_path):
         pytest.skip("no C compiler")
     src = tmp_path / "layout.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "ipmpde.h"\n'
-                   'int main(void) { printf("%zu %zu %zu %zu %zu\\n", sizeof(ipmpde_options), '
+                   'int main(void) { printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(ipmpde_options), '
                    'offsetof(ipmpde_options, mu_rule), offsetof(ipmpde_options, mass_scaling), '
+                   'offsetof(ipmpde_options, mg_tile), '
                    'sizeof(ipmpde_stats), offsetof(ipmpde_stats, hist_krylov_relres)); return 0; }\n')
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
-    want = [C.sizeof(L.COptions), L.COptions.mu_rule.offset, L.COptions.mass_scaling.offset,
+    want = [C.sizeof(L.COptions), L.COptions.mu_rule.offset, L.COptions.mass_scaling.offset, L.COptions.mg_tile.offset,
             C.sizeof(L.CStats), L.CStats.hist_krylov_relres.offset]
     assert got == want
 
