@@ -279,6 +279,19 @@ int ipmpde_newton_direction(ipmpde_problem* prob, const ipmpde_options* opts, do
  * (inf-norms of eq. (prdu) and of the products of eq. (gap)). */
 int ipmpde_measures(ipmpde_problem* prob, ipmpde_stream stream, double* xi_p, double* xi_d, double* xi_c);
 
+/* ipmpde_measures without any device allocation, for callers that cannot
+ * allocate (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same kernel and results (bit for bit) as
+ * ipmpde_measures; its scratch (launch descriptor, reduction partials and
+ * tickets, results) is a 4 MiB device array of the library that each GPU
+ * holds until the process ends.  The iterates must already be set (by
+ * ipmpde_reset or ipmpde_solve, which allocate), else IPMPDE_EINVAL; at most
+ * 44,648,448 nodes (N^dim, times nt for the heat equation), else
+ * IPMPDE_EINVAL.  Runs on the current device, which must be the problem's.
+ * Every call on a GPU shares that GPU's scratch: calls that overlap on one
+ * GPU (from several threads or streams) race. */
+int ipmpde_measures_noalloc(ipmpde_problem* prob, ipmpde_stream stream, double* xi_p, double* xi_d, double* xi_c);
+
 int ipmpde_get_stats(const ipmpde_problem* prob, ipmpde_stats* out);
 
 /* ---- low-level operators on caller-owned device arrays (FP64) ---- */

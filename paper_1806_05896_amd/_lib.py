@@ -104,6 +104,8 @@ SIGNATURES = {
                                           C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "ipmpde_measures": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                   C.POINTER(C.c_double)]),
+    "ipmpde_measures_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                          C.POINTER(C.c_double)]),
     "ipmpde_get_stats": (C.c_int, [C.c_void_p, C.POINTER(CStats)]),
     "ipmpde_apply_operator": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ipmpde_apply_saddle": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),

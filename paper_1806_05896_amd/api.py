@@ -261,6 +261,13 @@ class Problem:
         L.check(self._lib.ipmpde_measures(self._h, _stream_handle(stream), C.byref(a), C.byref(b), C.byref(c)))
         return a.value, b.value, c.value
 
+    def measures_noalloc(self, stream=None):
+        """measures() through the entry point that allocates no device memory."""
+        a, b, c = C.c_double(), C.c_double(), C.c_double()
+        L.check(self._lib.ipmpde_measures_noalloc(self._h, _stream_handle(stream), C.byref(a), C.byref(b),
+                                                  C.byref(c)))
+        return a.value, b.value, c.value
+
     def query(self, field: str) -> np.ndarray:
         out = np.empty(self.n)
         L.check(self._lib.ipmpde_query(self._h, L.FIELDS[field], out.ctypes.data_as(C.c_void_p), self.n))

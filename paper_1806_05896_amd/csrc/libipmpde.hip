@@ -2082,4 +2082,5 @@ extern "C" int ipmpde_batch_solve(ipmpde_batch* B, const ipmpde_options* opts, i
 
 #include "autotune.hip"
 #include "engine.hip"
+#include "noalloc.hip"
 #include "timing.hip"
