@@ -831,11 +831,21 @@ def main():
     # one instance alone (latency of a single solve)
     single = probs[0]
     opts1 = Options(**{**opts.__dict__, "mg_tile": "auto"})
+    tune1 = None
+    if args.autotune:
+        # a single instance has its own best schedule (launch latency weighs more)
+        with Batch([single]) as b1:
+            opts1, ms1, hit1 = b1.autotune(Options(sigma=datas[0].sigma, mg_precision="fp32"), cache=TUNE_CACHE,
+                                           stream=stream)
+        tune1 = {"cache": "hit" if hit1 else "miss (tuned now)",
+                 "pick": {"vcycles": opts1.vcycles, "nu_pre": opts1.nu_pre, "nu_post": opts1.nu_post,
+                          "mg_precision": opts1.mg_precision, "mg_tile": opts1.mg_tile}, "tuned_solve_ms": ms1}
+        log(f"autotune (single instance): {tune1}")
     ts, lat1, its1, st1, rc1 = time_solves(single, opts1, max(3, args.steps // 2), 1, torch)
     n1 = max(3, args.steps // 2)
     result["single_instance"] = {"solves_per_s": n1 / ts, "krylov_its_per_s": its1 / ts, "nli": st1.nli,
                                  "latency_ms": {"p50": percentile(lat1, 50), "p99": percentile(lat1, 99)},
-                                 "status": rc1}
+                                 "status": rc1, "autotune": tune1}
     data0 = datas[0]
     for p in probs:
         p.close()

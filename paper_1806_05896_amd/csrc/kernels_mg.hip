@@ -42,31 +42,6 @@ __device__ __forceinline__ T resid_node(const T* __restrict__ x, const T* __rest
   return b[i] - (apply_op<T>(x, i, i1, i2, i3, N, dim, pde, h, eps, transpose) + mh[i] * x[i]);
 }
 
-// Full-weighting restriction of the residual onto coarse node ic.
-template <typename T, bool SMALL = false>
-__device__ __forceinline__ T restrict_resid_node(const T* __restrict__ x, const T* __restrict__ b,
-                                                 const T* __restrict__ mh, int ic, int Nf, int Nc, int dim, int pde,
-                                                 double hf, double eps, bool transpose) {
-  int j1, j2, j3;
-  if (SMALL) node_coords_small(ic, Nc, dim, j1, j2, j3);
-  else node_coords(ic, Nc, dim, j1, j2, j3);
-  const int f1 = 2 * j1 + 1, f2 = 2 * j2 + 1, f3 = 2 * j3 + 1;
-  const T wt[3] = {(T)0.25, (T)0.5, (T)0.25};
-  T acc = 0;
-  if (dim == 2) {
-    for (int bb = -1; bb <= 1; ++bb)
-      for (int a = -1; a <= 1; ++a)
-        acc += wt[a + 1] * wt[bb + 1] * resid_node<T>(x, b, mh, f1 + a, f2 + bb, 0, Nf, dim, pde, hf, eps, transpose);
-  } else {
-    for (int c = -1; c <= 1; ++c)
-      for (int bb = -1; bb <= 1; ++bb)
-        for (int a = -1; a <= 1; ++a)
-          acc += wt[a + 1] * wt[bb + 1] * wt[c + 1] *
-                 resid_node<T>(x, b, mh, f1 + a, f2 + bb, f3 + c, Nf, dim, pde, hf, eps, transpose);
-  }
-  return acc;
-}
-
 // Bilinear/trilinear interpolation of the coarse correction at fine node i.
 template <typename T, bool SMALL = false>
 __device__ __forceinline__ T prolong_node(const T* __restrict__ xc, int i, int Nf, int Nc, int dim) {
@@ -131,17 +106,52 @@ __global__ void __launch_bounds__(kBS) k_mg_jacobi(const Inst* __restrict__ Dp, 
                                        I.eps, I.omega, first != 0, transpose != 0);
 }
 
+// Residual b - (A + mh) x[src] of level l at every node, into x[dst] (the
+// iterate buffer the pre-smoothing left free; the post-smoothing overwrites
+// it).  One node per thread: the residual is evaluated once per fine node
+// instead of once per coarse node that weights it.
 template <typename T>
-__global__ void __launch_bounds__(kBS) k_mg_restrict(const Inst* __restrict__ Dp, int l, int src, int transpose,
-                                                     int guard) {
+__global__ void __launch_bounds__(kBS) k_mg_resid(const Inst* __restrict__ Dp, int l, int src, int dst, int transpose,
+                                                  int guard) {
+  INST_BEGIN
+  if (l >= I.coarse_lev || mg_skip(I, guard)) return;
+  const Level& F = I.lv[l];
+  const int i = xcd_node(F.n);
+  if (i >= F.n) return;
+  int i1, i2, i3;
+  node_coords(i, F.N, I.dim, i1, i2, i3);
+  lvbuf<T>(F, dst)[i] = resid_node<T>(lvbuf<T>(F, src), (const T*)F.b, (const T*)F.mh, i1, i2, i3, F.N, I.dim, I.pde,
+                                      F.h, I.eps, transpose != 0);
+}
+
+// Full-weighting restriction of level l's residual (in x[src]) to level
+// l + 1's right-hand side: weights 1/4, 1/2, 1/4 per axis around fine node
+// 2j + 1 (0-based) of coarse node j.
+template <typename T>
+__global__ void __launch_bounds__(kBS) k_mg_restrict_r(const Inst* __restrict__ Dp, int l, int src, int guard) {
   INST_BEGIN
   if (l >= I.coarse_lev || mg_skip(I, guard)) return;
   const Level& F = I.lv[l];
   const Level& C = I.lv[l + 1];
   const int ic = xcd_node(C.n);
   if (ic >= C.n) return;
-  ((T*)C.b)[ic] = restrict_resid_node<T>(lvbuf<T>(F, src), (const T*)F.b, (const T*)F.mh, ic, F.N, C.N, I.dim, I.pde,
-                                         F.h, I.eps, transpose != 0);
+  int j1, j2, j3;
+  node_coords(ic, C.N, I.dim, j1, j2, j3);
+  const T* __restrict__ r = lvbuf<T>(F, src);
+  const int N = F.N;
+  const int f = (2 * j1 + 1) + N * ((2 * j2 + 1) + (I.dim == 3 ? N * (2 * j3 + 1) : 0));
+  const T wt[3] = {(T)0.25, (T)0.5, (T)0.25};
+  T acc = 0;
+  if (I.dim == 2) {
+    for (int bb = -1; bb <= 1; ++bb)
+      for (int a = -1; a <= 1; ++a) acc += wt[a + 1] * wt[bb + 1] * r[f + a + N * bb];
+  } else {
+    const int NN = N * N;
+    for (int c = -1; c <= 1; ++c)
+      for (int bb = -1; bb <= 1; ++bb)
+        for (int a = -1; a <= 1; ++a) acc += wt[a + 1] * wt[bb + 1] * wt[c + 1] * r[f + a + N * bb + NN * c];
+  }
+  ((T*)C.b)[ic] = acc;
 }
 
 // x[dst] at level l += P (level l+1's current iterate: its x if it is the
@@ -181,6 +191,11 @@ __device__ __forceinline__ T coarse_resid(const T* __restrict__ x, const T* __re
   return b[i] - (apply_op_s<T>(x, i, i1, i2, i3, C.N, C.N, C.N * C.N, dim, pde, C.h, eps, tr) + ms[i] * x[i]);
 }
 
+// Levels of the widest generic (3D) coarse hierarchy (15, 7, 3, 1) and the
+// nodes per thread of its widest level.
+constexpr int kCoarse3Levels = 4;
+constexpr int kCoarse3PerThread = (15 * 15 * 15 + kCoarseBS - 1) / kCoarseBS;
+
 template <typename T>
 __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse(const Inst* __restrict__ Dp, int transpose, int guard) {
   INST_BEGIN
@@ -193,6 +208,25 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse(const Inst* __restrict_
   const int tid = threadIdx.x, dim = I.dim, pde = I.pde;
   const double eps = I.eps;
   const T om = (T)I.omega;
+  // global loads first, all in flight together: the top level's b and every
+  // level's reaction term (at most kCoarse3Levels levels, the widest 15^3)
+  const int n0 = I.lv[cl].n;
+  T breg[kCoarse3PerThread], mreg[kCoarse3Levels][kCoarse3PerThread];
+#pragma unroll
+  for (int j = 0; j < kCoarse3PerThread; ++j) {
+    const int i = tid + j * kCoarseBS;
+    breg[j] = i < n0 ? ((const T*)I.lv[cl].b)[i] : (T)0;
+  }
+#pragma unroll
+  for (int q = 0; q < kCoarse3Levels; ++q) {
+    const int nq = cl + q < L ? I.lv[cl + q].n : 0;
+    const T* __restrict__ mg = cl + q < L ? (const T*)I.lv[cl + q].mh : nullptr;
+#pragma unroll
+    for (int j = 0; j < kCoarse3PerThread; ++j) {
+      const int i = tid + j * kCoarseBS;
+      mreg[q][j] = i < nq ? mg[i] : (T)0;
+    }
+  }
   if (tid == 0) {
     int off = 0;
     for (int l = cl; l < L; ++l) {
@@ -202,22 +236,28 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse(const Inst* __restrict_
       LI[l].off = off;
       LI[l].h = Lv.h;
       LI[l].hf = (float)Lv.h;
-      off += 4 * Lv.n;
+      off += 5 * Lv.n;
     }
   }
   __syncthreads();
-  // stage b at the top level and M_hat at every level
-  for (int l = cl; l < L; ++l) {
-    const CoarseLevel C = LI[l];
-    const T* mg = (const T*)I.lv[l].mh;
-    T* ms = lds + C.off + 3 * C.n;
-    for (int i = tid; i < C.n; i += kCoarseBS) ms[i] = mg[i];
-  }
-  {
-    const CoarseLevel C = LI[cl];
-    const T* bg = (const T*)I.lv[cl].b;
-    T* B = lds + C.off + 2 * C.n;
-    for (int i = tid; i < C.n; i += kCoarseBS) B[i] = bg[i];
+  // per level: x | x2 | b | m | 1/d, with d = the operator's diagonal + m
+#pragma unroll
+  for (int q = 0; q < kCoarse3Levels; ++q) {
+    if (cl + q < L) {
+      const CoarseLevel C = LI[cl + q];
+      T* ms = lds + C.off + 3 * C.n;
+#pragma unroll
+      for (int j = 0; j < kCoarse3PerThread; ++j) {
+        const int i = tid + j * kCoarseBS;
+        if (i < C.n) {
+          int i1, i2, i3;
+          node_coords_small(i, C.N, dim, i1, i2, i3);
+          ms[i] = mreg[q][j];
+          ms[C.n + i] = (T)1 / coarse_diag<T>(C, dim, pde, eps, i1, i2, mreg[q][j]);
+          if (q == 0) ms[i - C.n] = breg[j];
+        }
+      }
+    }
   }
   __syncthreads();
   unsigned alt = 0;  // bit l: level l's iterate sits in x2
@@ -228,12 +268,13 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse(const Inst* __restrict_
     T* c = a + C.n;
     const T* B = a + 2 * C.n;
     const T* ms = a + 3 * C.n;
+    const T* dinv = a + 4 * C.n;
     for (int s = 0; s < I.nu_pre; ++s) {
       for (int i = tid; i < C.n; i += kCoarseBS) {
         int i1, i2, i3;
         node_coords_small(i, C.N, dim, i1, i2, i3);
-        const T d = coarse_diag<T>(C, dim, pde, eps, i1, i2, ms[i]);
-        c[i] = (s == 0) ? om * B[i] / d : a[i] + om * coarse_resid<T>(a, B, ms, i, i1, i2, i3, C, dim, pde, eps, tr) / d;
+        c[i] = (s == 0) ? om * B[i] * dinv[i]
+                        : a[i] + om * coarse_resid<T>(a, B, ms, i, i1, i2, i3, C, dim, pde, eps, tr) * dinv[i];
       }
       __syncthreads();
       T* t = a; a = c; c = t;
@@ -276,12 +317,8 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse(const Inst* __restrict_
     const CoarseLevel C = LI[L - 1];
     T* X = lds + C.off;
     const T* B = X + 2 * C.n;
-    const T* ms = X + 3 * C.n;
-    for (int i = tid; i < C.n; i += kCoarseBS) {
-      int i1, i2, i3;
-      node_coords_small(i, C.N, dim, i1, i2, i3);
-      X[i] = B[i] / coarse_diag<T>(C, dim, pde, eps, i1, i2, ms[i]);
-    }
+    const T* dinv = X + 4 * C.n;
+    for (int i = tid; i < C.n; i += kCoarseBS) X[i] = B[i] * dinv[i];
     __syncthreads();
   }
   // ascend
@@ -293,6 +330,7 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse(const Inst* __restrict_
     T* c = lds + C.off + (1 - ca) * C.n;
     const T* B = lds + C.off + 2 * C.n;
     const T* ms = lds + C.off + 3 * C.n;
+    const T* dinv = lds + C.off + 4 * C.n;
     const T* xc = lds + Cc.off + ((alt >> (l + 1)) & 1u) * Cc.n;
     for (int i = tid; i < C.n; i += kCoarseBS) a[i] += prolong_node<T, true>(xc, i, C.N, Cc.N, dim);
     __syncthreads();
@@ -300,8 +338,7 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse(const Inst* __restrict_
       for (int i = tid; i < C.n; i += kCoarseBS) {
         int i1, i2, i3;
         node_coords_small(i, C.N, dim, i1, i2, i3);
-        const T d = coarse_diag<T>(C, dim, pde, eps, i1, i2, ms[i]);
-        c[i] = a[i] + om * coarse_resid<T>(a, B, ms, i, i1, i2, i3, C, dim, pde, eps, tr) / d;
+        c[i] = a[i] + om * coarse_resid<T>(a, B, ms, i, i1, i2, i3, C, dim, pde, eps, tr) * dinv[i];
       }
       __syncthreads();
       T* t = a; a = c; c = t;
@@ -1006,7 +1043,8 @@ __global__ void __launch_bounds__(kBS) k_mg_kc_final(const Inst* __restrict__ Dp
   template __global__ void k_mg_kc_resid<T>(const Inst*, int, int, int, int);         \
   template __global__ void k_mg_kc_final<T>(const Inst*, int, int, int);              \
   template __global__ void k_mg_jacobi<T>(const Inst*, int, int, int, int, int, int); \
-  template __global__ void k_mg_restrict<T>(const Inst*, int, int, int, int);         \
+  template __global__ void k_mg_resid<T>(const Inst*, int, int, int, int, int);       \
+  template __global__ void k_mg_restrict_r<T>(const Inst*, int, int, int);           \
   template __global__ void k_mg_prolong<T>(const Inst*, int, int, int, int);          \
   template __global__ void k_mg_coarse<T>(const Inst*, int, int);                     \
   template __global__ void k_mg_scale_ty<T>(const Inst*, int, int);                   \

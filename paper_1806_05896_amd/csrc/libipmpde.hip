@@ -28,6 +28,7 @@
 #include "kernels_krylov.hip"
 #include "kernels_mg.hip"
 #include "kernels_mg_p2.hip"
+#include "kernels_persist.hip"
 #include "kernels_fgmres.hip"
 
 using namespace ipm;
@@ -149,6 +150,7 @@ struct Group {
   bool gen3 = false; // some instance takes the generic coarse kernel (3D)
   int max_cpack = 0; // longest coarse LDS image (Poisson instances)
   bool any_small = false;  // 2D: some instance runs its whole hierarchy in the coarse kernel
+  bool persist = false;    // some instance takes the persistent single-workgroup MINRES kernel
   int outsel = 1;    // level-0 output buffer of a V-cycle (x2 = 1)
   bool heat = false; // heat-equation problems (a group holds only heat problems or none)
   bool q1 = false;   // Q1 finite-element problems (likewise): generic multigrid path
@@ -231,7 +233,7 @@ enum { kCoarseGeneric = 0, kCoarseP2 = 1, kCoarseCD = 2 };
 static size_t coarse_level_elems(const Level& L, int kind) {
   if (kind == kCoarseP2) return (size_t)coarse_p2_elems(L.N);
   if (kind == kCoarseCD) return (size_t)kCoarseCDArrays * L.n;
-  return 4 * (size_t)L.n;
+  return 5 * (size_t)L.n;
 }
 
 // Largest grid of each coarse kernel: the convection-diffusion stencil costs
@@ -267,6 +269,7 @@ static int set_coarse_lds_limit() {
   std::call_once(once, [] {
     const void* fns[] = {(const void*)k_mg_coarse<float>, (const void*)k_mg_coarse<double>,
                          (const void*)k_mg_coarse_cd<float>, (const void*)k_mg_coarse_cd<double>,
+                         (const void*)k_minres_small<float>, (const void*)k_minres_small<double>,
                          (const void*)k_mg_coarse_p2<float>, (const void*)k_mg_coarse_p2<double>,
                          (const void*)k_heat_sweep_p2<float>, (const void*)k_heat_sweep_p2<double>};
     for (const void* f : fns) {
@@ -564,6 +567,7 @@ static int group_select(Group* G, const ipmpde_options& o) {
   G->cd = false;
   G->gen3 = false;
   G->any_small = false;
+  G->persist = false;
   G->max_cpack = 0;
   std::fill(G->maxN, G->maxN + kMaxLev, 0);
   std::fill(G->maxn, G->maxn + kMaxLev, 0);
@@ -600,6 +604,8 @@ static int group_select(Group* G, const ipmpde_options& o) {
     G->max_nlev = std::max(G->max_nlev, P->nlev);
     G->max_cl = std::max(G->max_cl, d.coarse_lev);
     G->any_small = G->any_small || d.coarse_lev == 0;
+    G->persist = G->persist || (is_p2(P) && d.coarse_lev == 0 && o.krylov == IPMPDE_MINRES && o.precond == IPMPDE_PD &&
+                                o.vcycles == 1 && !P->obs && P->pde != IPMPDE_HEAT);
     for (int l = 0; l < P->nlev; ++l) {
       G->maxN[l] = std::max(G->maxN[l], lv[l].N);
       G->maxn[l] = std::max(G->maxn[l], (long)lv[l].n);
@@ -780,7 +786,8 @@ static void mg_vcycle_generic(Group* G, int transpose, int guard, hipStream_t s)
       hipLaunchKernelGGL(k_mg_jacobi<T>, gz(G, G->maxn[l]), dim3(kBS), 0, s, G->D, l, a, c, sw == 0 ? 1 : 0, transpose, guard);
       std::swap(a, c);
     }
-    hipLaunchKernelGGL(k_mg_restrict<T>, gz(G, G->maxn[l + 1]), dim3(kBS), 0, s, G->D, l, a, transpose, guard);
+    hipLaunchKernelGGL(k_mg_resid<T>, gz(G, G->maxn[l]), dim3(kBS), 0, s, G->D, l, a, c, transpose, guard);
+    hipLaunchKernelGGL(k_mg_restrict_r<T>, gz(G, G->maxn[l + 1]), dim3(kBS), 0, s, G->D, l, c, guard);
   }
   launch_coarse<T>(G, transpose, guard, s);
   for (int l = G->max_cl - 1; l >= 0; --l) {
@@ -1108,11 +1115,22 @@ static int run_minres_chunk(Group* G, const ipmpde_options& o, hipStream_t s) {
 // MINRES on every active instance: a cycle from the right-hand side, then
 // (for instances whose true residual missed the tolerance) cycles from the
 // true residual.  Per-instance results stay in the group's ctrl array.
+static constexpr int kMinresCycles = 16;
+
 template <typename T>
 static int minres_group(Group* G, const ipmpde_options& o, hipStream_t s) {
   const double tol = o.krylov_tol;
   hipLaunchKernelGGL(k_krylov_begin, gz(G, 4L * G->max_n), dim3(kBS), 0, s, G->D);
-  for (int cycle = 0; cycle < 16; ++cycle) {
+  if (G->persist) {
+    // the small 2D Poisson instances run their whole solve in one workgroup
+    // each; the loop below serves the others (and skips these: no pending cycle)
+    hipLaunchKernelGGL(k_minres_small<T>, dim3(1, 1, G->zc), dim3(kCoarseBS), G->coarse_lds, s, G->D, tol,
+                       floor_factor(), o.krylov_maxit, kMinresCycles);
+    HIP_TRY(hipGetLastError());
+    TRY(read_ctrl(G, s));
+    if (!any_restart(G)) return IPMPDE_OK;
+  }
+  for (int cycle = 0; cycle < kMinresCycles; ++cycle) {
     hipLaunchKernelGGL(k_minres_init<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, cycle == 0 ? 0 : 1);
     if (G->q1) cheb_apply(G, nullptr, nullptr, 0, 0, 2, s);
     schur_inv<T>(G, 2, s);

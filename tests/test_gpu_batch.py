@@ -64,3 +64,44 @@ def test_batch_member_limits_do_not_leak():
         assert st[k] == 0
     for p in probs:
         p.close()
+
+
+def test_poisoned_member_is_isolated():
+    """A member whose data overflow in FP64 (desired state of size 1e300, finite
+    and accepted at create) fails (EBREAKDOWN or EKRYLOV) with NaN or Inf
+    confined to its own iterates; its batch-mates and the requests served beside it in an engine
+    group finish exactly as they would alone."""
+    from paper_1806_05896_amd import Batch, Engine, Options, Problem
+    from paper_1806_05896_amd import _lib as L
+    datas = [d for d in _mixed(seed=2) if d.pde == "poisson"][:2]
+    bad = datas[0].copy()
+    bad.y_d = bad.y_d * 1e300
+    members = [datas[0], bad, datas[1]]
+    opts = [Options(sigma=d.sigma) for d in members]
+    solo = []
+    for k in (0, 2):
+        with Problem(members[k]) as p:
+            rc = p.solve(opts[k])
+            solo.append((k, rc, p.query("u"), p.stats().krylov_its))
+    probs = [Problem(d) for d in members]
+    with Batch(probs) as b:
+        st = b.solve(opts)
+    print(f"[poison] batch status {st}", flush=True)
+    assert st[1] in (L.EBREAKDOWN, L.EKRYLOV)
+    for k, rc, u, its in solo:
+        assert st[k] == rc == 0 and probs[k].stats().krylov_its == its
+        np.testing.assert_array_equal(probs[k].query("u"), u)
+    for p in probs:
+        p.close()
+    probs = [Problem(d) for d in members]
+    with Engine(1 << 30, 8) as e:
+        tickets = [e.submit(p, o) for p, o in zip(probs, opts)]
+        e.run()
+        status = [e.poll(t)["status"] for t in tickets]
+    print(f"[poison] engine status {status}", flush=True)
+    assert status[1] in (L.EBREAKDOWN, L.EKRYLOV)
+    for k, rc, u, its in solo:
+        assert status[k] == rc == 0
+        np.testing.assert_array_equal(probs[k].query("u"), u)
+    for p in probs:
+        p.close()

@@ -13,7 +13,8 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 import oracle  # noqa: E402
-import workloads as W  # noqa: E402
+import workloads as W
+from tests._oracle_error import fp64_oracle_error  # noqa: E402
 from oracle.fd import discretize, operator_matrix  # noqa: E402
 from oracle.ipm import IPMOptions, initial_state, ipm_step, newton_matrix, newton_rhs, newton_solve  # noqa: E402
 
@@ -173,7 +174,8 @@ def test_ipm_parity_poisson_small(prec):
         rc = prob.solve(Options(mg_precision=prec))
         u, y = prob.query("u"), prob.query("y")
         s = prob.stats()
-    print(f"  rc={rc} nli={s.nli}/{ref.nli} its={s.krylov_its} rel u={_rel(u, ref.u):.2e} y={_rel(y, ref.y):.2e}")
+    print(f"  rc={rc} nli={s.nli}/{ref.nli} its={s.krylov_its} rel u={_rel(u, ref.u):.2e} y={_rel(y, ref.y):.2e} "
+          f"FP64-oracle error u={fp64_oracle_error(data, IPMOptions(sigma=data.sigma), ref):.2e}")
     assert rc == 0 and s.nli == ref.nli
     assert _rel(u, ref.u) <= 1e-6 and _rel(y, ref.y) <= 1e-6
 
@@ -190,7 +192,8 @@ def test_ipm_parity_cases(case, krylov, precond):
         rc = prob.solve(Options(sigma=data.sigma, krylov=krylov, precond=precond))
         u, y = prob.query("u"), prob.query("y")
         s = prob.stats()
-    print(f"  rc={rc} nli={s.nli}/{ref.nli} its={s.krylov_its} rel u={_rel(u, ref.u):.2e} y={_rel(y, ref.y):.2e}")
+    print(f"  rc={rc} nli={s.nli}/{ref.nli} its={s.krylov_its} rel u={_rel(u, ref.u):.2e} y={_rel(y, ref.y):.2e} "
+          f"FP64-oracle error u={fp64_oracle_error(data, IPMOptions(sigma=data.sigma), ref):.2e}")
     assert rc == 0 and s.nli == ref.nli
     assert _rel(u, ref.u) <= 1e-6 and _rel(y, ref.y) <= 1e-6
 
@@ -209,7 +212,9 @@ def test_ipm_parity_central_mu_rule(seed, N):
         rc = prob.solve(Options(sigma=data.sigma, mu_rule="central"))
         u, y = prob.query("u"), prob.query("y")
         s = prob.stats()
-    print(f"  rc={rc} nli={s.nli}/{ref.nli} its={s.krylov_its} rel u={_rel(u, ref.u):.2e} y={_rel(y, ref.y):.2e}")
+    err = fp64_oracle_error(data, IPMOptions(sigma=data.sigma, mu_rule="central"), ref)
+    print(f"  rc={rc} nli={s.nli}/{ref.nli} its={s.krylov_its} rel u={_rel(u, ref.u):.2e} y={_rel(y, ref.y):.2e} "
+          f"FP64-oracle error u={err:.2e}")
     assert rc == 0 and s.nli == ref.nli
     assert _rel(u, ref.u) <= 1e-6 and _rel(y, ref.y) <= 1e-6
 
