@@ -583,6 +583,56 @@ __device__ __forceinline__ T cd_row(const T* __restrict__ x, const T* __restrict
   return r;
 }
 
+// Descent and ascent of the convection-diffusion coarse V-cycle at level l
+// by the NT threads of the workgroup.
+template <typename T, int NT>
+__device__ __forceinline__ void cd_down(T* lds, const int* LN, const int* LOFF, int l, int tid, T om, int nu, bool tr,
+                                        unsigned& alt) {
+  const int N = LN[l], n = N * N;
+  T* a = lds + LOFF[l];
+  T* c = a + n;
+  const T* B = a + 2 * n;
+  const T* cf = a + 3 * n;
+  for (int sw = 0; sw < nu; ++sw) {
+    P2_FOR_T(N, tid, NT)
+      c[i] = sw == 0 ? om * B[i] * cf[n + i] : a[i] + om * (B[i] - cd_row<T>(a, cf, i, i1, i2, N, n, tr)) * cf[n + i];
+    P2_END
+    __syncthreads();
+    T* t = a; a = c; c = t;
+    alt ^= 1u << l;
+  }
+  P2_FOR_T(N, tid, NT) c[i] = B[i] - cd_row<T>(a, cf, i, i1, i2, N, n, tr); P2_END
+  __syncthreads();
+  const int Nc = LN[l + 1];
+  T* Bc = lds + LOFF[l + 1] + 2 * Nc * Nc;
+  P2_FOR_T(Nc, tid, NT)
+    const int f = (2 * i1 + 1) + N * (2 * i2 + 1);
+    Bc[i] = (T)0.25 * c[f] + (T)0.125 * (c[f - 1] + c[f + 1] + c[f - N] + c[f + N]) +
+            (T)0.0625 * (c[f - 1 - N] + c[f + 1 - N] + c[f - 1 + N] + c[f + 1 + N]);
+  P2_END
+  __syncthreads();
+}
+
+template <typename T, int NT>
+__device__ __forceinline__ void cd_up(T* lds, const int* LN, const int* LOFF, int l, int tid, T om, int nu, bool tr,
+                                      unsigned& alt) {
+  const int N = LN[l], n = N * N, Nc = LN[l + 1];
+  const int ca = (alt >> l) & 1u;
+  T* a = lds + LOFF[l] + ca * n;
+  T* c = lds + LOFF[l] + (1 - ca) * n;
+  const T* B = lds + LOFF[l] + 2 * n;
+  const T* cf = lds + LOFF[l] + 3 * n;
+  const T* xc = lds + LOFF[l + 1] + ((alt >> (l + 1)) & 1u) * Nc * Nc;
+  P2_FOR_T(N, tid, NT) a[i] += prolong_node<T, true>(xc, i, N, Nc, 2); P2_END
+  __syncthreads();
+  for (int sw = 0; sw < nu; ++sw) {
+    P2_FOR_T(N, tid, NT) c[i] = a[i] + om * (B[i] - cd_row<T>(a, cf, i, i1, i2, N, n, tr)) * cf[n + i]; P2_END
+    __syncthreads();
+    T* t = a; a = c; c = t;
+    alt ^= 1u << l;
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_cd(const Inst* __restrict__ Dp, int transpose, int guard) {
   INST_BEGIN
@@ -645,54 +695,14 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_cd(const Inst* __restri
   }
   __syncthreads();
   unsigned alt = 0;  // bit l: level l's iterate sits in x2
-  for (int l = cl; l < L - 1; ++l) {
-    const int N = LN[l], n = N * N;
-    T* a = lds + LOFF[l];
-    T* c = a + n;
-    const T* B = a + 2 * n;
-    const T* cf = a + 3 * n;
-    for (int sw = 0; sw < I.nu_pre; ++sw) {
-      P2_FOR(N)
-        c[i] = sw == 0 ? om * B[i] * cf[n + i] : a[i] + om * (B[i] - cd_row<T>(a, cf, i, i1, i2, N, n, tr)) * cf[n + i];
-      P2_END
-      __syncthreads();
-      T* t = a; a = c; c = t;
-      alt ^= 1u << l;
-    }
-    P2_FOR(N) c[i] = B[i] - cd_row<T>(a, cf, i, i1, i2, N, n, tr); P2_END
-    __syncthreads();
-    const int Nc = LN[l + 1];
-    T* Bc = lds + LOFF[l + 1] + 2 * Nc * Nc;
-    P2_FOR(Nc)
-      const int f = (2 * i1 + 1) + N * (2 * i2 + 1);
-      Bc[i] = (T)0.25 * c[f] + (T)0.125 * (c[f - 1] + c[f + 1] + c[f - N] + c[f + N]) +
-              (T)0.0625 * (c[f - 1 - N] + c[f + 1 - N] + c[f - 1 + N] + c[f + 1 + N]);
-    P2_END
-    __syncthreads();
-  }
+  for (int l = cl; l < L - 1; ++l) cd_down<T, kCoarseBS>(lds, LN, LOFF, l, tid, om, I.nu_pre, tr, alt);
   {
     const int N = LN[L - 1], n = N * N;
     T* X = lds + LOFF[L - 1];
     P2_FOR(N) X[i] = X[2 * n + i] * X[4 * n + i]; P2_END
     __syncthreads();
   }
-  for (int l = L - 2; l >= cl; --l) {
-    const int N = LN[l], n = N * N, Nc = LN[l + 1];
-    const int ca = (alt >> l) & 1u;
-    T* a = lds + LOFF[l] + ca * n;
-    T* c = lds + LOFF[l] + (1 - ca) * n;
-    const T* B = lds + LOFF[l] + 2 * n;
-    const T* cf = lds + LOFF[l] + 3 * n;
-    const T* xc = lds + LOFF[l + 1] + ((alt >> (l + 1)) & 1u) * Nc * Nc;
-    P2_FOR(N) a[i] += prolong_node<T, true>(xc, i, N, Nc, 2); P2_END
-    __syncthreads();
-    for (int sw = 0; sw < I.nu_post; ++sw) {
-      P2_FOR(N) c[i] = a[i] + om * (B[i] - cd_row<T>(a, cf, i, i1, i2, N, n, tr)) * cf[n + i]; P2_END
-      __syncthreads();
-      T* t = a; a = c; c = t;
-      alt ^= 1u << l;
-    }
-  }
+  for (int l = L - 2; l >= cl; --l) cd_up<T, kCoarseBS>(lds, LN, LOFF, l, tid, om, I.nu_post, tr, alt);
   const int N = LN[cl];
   T* xg = (T*)I.lv[cl].x;
   const T* xs = lds + LOFF[cl] + ((alt >> cl) & 1u) * N * N;

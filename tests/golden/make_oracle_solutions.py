@@ -18,6 +18,7 @@ A digest of the inputs lets a test notice a changed generator.
   q1_3d_sb15_central    3D Poisson with trilinear Q1 elements on 15^3, seed 0,
                         state bounds [-0.06, 0.06], the iterate-based barrier
                         rule
+  q1_3d_sb15_paper      the same instance under the paper's barrier rule
   convdiff2d_127_seed0  the convection-diffusion workload (eps = 1/200) on
                         127^2, seed 0, the paper's barrier rule
   poisson3d_31_seed0    the 3D finite-difference Poisson workload on 31^3,
@@ -62,6 +63,8 @@ CASES = {
                             lambda d: oracle.IPMOptions(sigma=d.sigma, newton="schur")),
     "q1_3d_sb15_central": (lambda: q1_3d_bounded(15),
                            lambda d: oracle.IPMOptions(sigma=d.sigma, mu_rule="central")),
+    "q1_3d_sb15_paper": (lambda: q1_3d_bounded(15),
+                         lambda d: oracle.IPMOptions(sigma=d.sigma)),
     "convdiff2d_127_seed0": (lambda: W.convdiff2d_255(seed=0, N=127),
                              lambda d: oracle.IPMOptions(sigma=d.sigma)),
     "poisson3d_31_seed0": (lambda: W.poisson3d_127(seed=0, N=31),
