@@ -65,8 +65,10 @@ def test_final_iterate_kkt_certificate(name, kw, opts_kw):
 
 def test_hard_instance_reports_breakdown_at_511():
     """The 511^2 state-constrained instance with seed 10, on which Algorithm A.1's
-    fixed decrease of mu outruns the iterate (the oracle loses interiority on the
-    same data at 63^2): the solve ends with a clean EBREAKDOWN status, every
+    fixed decrease of mu outruns the iterate: the oracle with direct Newton
+    solves breaks down on the same data too (at iteration 53, mu = 9e-38,
+    step lengths collapsed to 2e-3 and below; a 19-minute CPU run, so not
+    repeated here).  The solve ends with a clean EBREAKDOWN status, every
     recorded measure is finite up to the failure, and the iterates stay
     queryable."""
     from paper_1806_05896_amd import Options, Problem
