@@ -251,19 +251,9 @@ def test_q1_3d_newton_direction_solves_oracle_system(case, krylov, precond, prec
 # preconditions the Q1 system (the consistent mass couples constrained and
 # free nodes); an exact FP32 solve shows the same on the CPU.
 #
-# The state-bounded 15^3 instance under the paper's fixed barrier decrease
-# does not follow the oracle: the oracle's own run takes 47 iterations, from
-# iteration 4 on with step lengths of 0.03-0.3 while mu falls to 1e-33 and
-# the complementarity products stall near 1e-3..1e-5, so Theta_y grows
-# without bound and the Newton systems become so ill-conditioned that FGMRES
-# with P_T (FP64 multigrid) misses 1e-10 within 500 iterations in 24 steps
-# (GPU: 49 iterations, rel u 2.3e-4).  The same instance under the
-# iterate-based barrier rule is tested below against the stored oracle
-# solution.
-SB15_PAPER_RULE = ("the fixed barrier decrease outruns the iterate on this instance (oracle: 47 iterations, mu "
-                   "down to 1e-33 with stalled complementarity); its Newton systems defeat FGMRES + P_T within "
-                   "500 iterations in 24 steps, so the trajectories part (nli 49 vs 47, rel u 2.3e-4); tested "
-                   "under the iterate-based rule instead (test_q1_3d_state_bounded_15_central)")
+# The state-bounded 15^3 instance (both barrier rules) is tested below
+# against stored oracle solutions, with FGMRES(60): P_T's iteration counts
+# grow with Theta_y there and FGMRES(30) stagnates.
 
 
 @pytest.mark.parametrize("case,krylov,precond,prec", [("q1_3d_7", "minres", "pd", "fp32"),
@@ -272,9 +262,7 @@ SB15_PAPER_RULE = ("the fixed barrier decrease outruns the iterate on this insta
                                                       ("q1_3d_sb_7", "fgmres", "pt", "fp64"),
                                                       ("q1_3d_sb_7", "minres", "pd", "fp64"),
                                                       ("q1_3d_data_7", "fgmres", "pd", "fp32"),
-                                                      ("q1_3d_15", "fgmres", "pt", "fp32"),
-                                                      pytest.param("q1_3d_sb_15", "fgmres", "pt", "fp64",
-                                                                   marks=pytest.mark.skip(reason=SB15_PAPER_RULE))])
+                                                      ("q1_3d_15", "fgmres", "pt", "fp32")])
 def test_q1_3d_ipm_parity(case, krylov, precond, prec):
     _, Options, Problem = _api()
     print(f"[q1 3d ipm] {case} {krylov} {precond} {prec}", flush=True)
@@ -312,27 +300,31 @@ def test_q1_3d_batch_equals_solo():
             p.close()
 
 
-def test_q1_3d_state_bounded_15_central():
-    """The state-bounded 15^3 instance under the iterate-based barrier rule
-    (FGMRES + P_T, FP64 multigrid) against the oracle's solution under the
-    same rule, stored by tests/golden/make_oracle_solutions.py (its run takes
-    minutes): equal iteration count and rel-L2 <= 1e-6 in u, y and p.
+@pytest.mark.parametrize("rule", ["central", "paper"])
+def test_q1_3d_state_bounded_15(rule):
+    """The state-bounded 15^3 instance (FGMRES + P_T, FP64 multigrid) under the
+    iterate-based barrier rule and under the paper's fixed decrease, against
+    the oracle's solutions under the same rule, stored by
+    tests/golden/make_oracle_solutions.py (its runs take minutes): equal
+    iteration count and rel-L2 <= 1e-6 in u, y and p.
 
     P_T loses strength on this problem as the iterate approaches the state
-    bounds: FGMRES iterations per IPM step grow from 9 to about 530 (k = 27).
-    FGMRES(30) then stagnates between restarts (up to 3800 iterations per
-    step, over the default limit of 500 from k = 22, after which the
-    trajectory leaves the oracle's), so the solve runs FGMRES(60) with a limit
-    of 4000; every Newton system then reaches 1e-10."""
+    bounds.  Under the iterate-based rule, FGMRES iterations per IPM step grow
+    from 9 to about 530 (k = 27).  FGMRES(30) then stagnates between restarts:
+    up to 3800 iterations per step, over the default limit of 500 from k = 22,
+    after which the trajectory leaves the oracle's.  Under the fixed decrease
+    the oracle itself needs 47 iterations (mu down to 1e-33 with step lengths
+    of 0.03-0.3).  So the solve runs FGMRES(60) with a limit of 4000, and every
+    Newton system then reaches 1e-10 under both rules."""
     import json
     import os
     _, Options, Problem = _api()
-    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "q1_3d_sb15_central_oracle.npz"), allow_pickle=False)
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", f"q1_3d_sb15_{rule}_oracle.npz"), allow_pickle=False)
     data = _bounded(15)
-    print("[q1 3d sb15 central] fgmres pt fp64", flush=True)
+    print(f"[q1 3d sb15 {rule}] fgmres(60) pt fp64", flush=True)
     with Problem(data) as prob:
         rc = prob.solve(Options(sigma=data.sigma, krylov="fgmres", precond="pt", mg_precision="fp64",
-                                mu_rule="central", restart=60, krylov_maxit=4000))
+                                mu_rule=rule, restart=60, krylov_maxit=4000))
         u, y, p = prob.query("u"), prob.query("y"), prob.query("p")
         s = prob.stats()
     hist = json.loads(str(g["history"]))
