@@ -35,6 +35,7 @@ struct KrylovCtrl {
   double c_prev, c, s_prev, s;
   double eta, eta0;
   double a1, a2, a3, coef_x, gamma_w;  // coefficients of the pending direction/solution update
+  double coef_x_def;   // coefficient of the direction whose solution update was deferred (odd iterations)
   double est;          // |eta| / eta0: relative preconditioned residual estimate
   double trigger;      // estimate at which the host checks the true residual
   double dot_tmp;      // partial result of a split reduction (diagonal blocks)

@@ -501,7 +501,12 @@ __global__ void __launch_bounds__(kBS) k_minres_init(const Inst* __restrict__ Dp
 
 // K1: pending update of iteration j-1 (direction w, solution x), then
 // q = K z_j / gamma_j and delta_j = <q, z_j/gamma_j>.  par = parity of j;
-// timing = 1 only for stand-alone timing.
+// timing = 1 only for stand-alone timing.  The solution takes the updates
+// of two iterations at a time: after an odd iteration i only w_i is formed
+// (its coefficient is kept in coef_x_def), after the next one
+// x += c_i w_i + c_{i+1} w_{i+1} (w_i is the w read for the recurrence
+// anyway), which halves the traffic of x; k_minres_flush adds what is left.
+// The direction vectors stream through once per iteration (nontemporal).
 __global__ void __launch_bounds__(kBS) k_minres_k1(const Inst* __restrict__ Dp, int par, int timing) {
   INST_BEGIN
   __shared__ double smem[kBS / 64];
@@ -519,13 +524,18 @@ __global__ void __launch_bounds__(kBS) k_minres_k1(const Inst* __restrict__ Dp, 
   if (i < I.n) {
     const int n = I.n;
     if (pending) {
-      const double g = C->gamma_w, a1 = C->a1, a2 = C->a2, a3 = C->a3, cx = C->coef_x;
+      const double g = C->gamma_w, a1 = C->a1, a2 = C->a2, a3 = C->a3, cx = C->coef_x, cxd = C->coef_x_def;
+      // the pending update belongs to iteration C->iter; stand-alone timing
+      // takes the full form (x updated) every launch
+      const bool defer = !timing && (C->iter & 1);
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int j = k * n + i;
-        const double wi = (Zprev[j] / g - a3 * Wsame[j] - a2 * Wother[j]) / a1;
-        Wsame[j] = wi;
-        X[j] += cx * wi;
+        const double wo = __builtin_nontemporal_load(&Wother[j]);
+        const double wi = (__builtin_nontemporal_load(&Zprev[j]) / g - a3 * __builtin_nontemporal_load(&Wsame[j]) -
+                           a2 * wo) / a1;
+        __builtin_nontemporal_store(wi, &Wsame[j]);
+        if (!defer) __builtin_nontemporal_store(__builtin_nontemporal_load(&X[j]) + (cxd * wo + cx * wi), &X[j]);
       }
     }
     const double s = 1.0 / C->gamma;
@@ -533,7 +543,7 @@ __global__ void __launch_bounds__(kBS) k_minres_k1(const Inst* __restrict__ Dp, 
     saddle_rows(I, Zc, i, s, o);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      Q[k * n + i] = o[k];
+      __builtin_nontemporal_store(o[k], &Q[k * n + i]);
       acc[0] += o[k] * (Zc[k * n + i] * s);
     }
   }
@@ -546,7 +556,8 @@ __global__ void __launch_bounds__(kBS) k_minres_k1(const Inst* __restrict__ Dp, 
 // K2: Lanczos vector v_{j+1} (overwrites v_{j-1}), z_{j+1} on the diagonal
 // blocks, partial <v_{j+1}, z_{j+1}>, b_0 = (T) v_{j+1,p} for the multigrid;
 // the pending residual update with v_j and, in the last block, the stop test
-// on |r_{j-1}|_2.  timing = 1 only for stand-alone timing.
+// on |r_{j-1}|_2.  timing = 1 only for stand-alone timing.  The Lanczos and
+// residual vectors stream through once per iteration (nontemporal).
 template <typename T>
 __global__ void __launch_bounds__(kBS) k_minres_k2(const Inst* __restrict__ Dp, int par, int timing) {
   INST_BEGIN
@@ -568,12 +579,12 @@ __global__ void __launch_bounds__(kBS) k_minres_k2(const Inst* __restrict__ Dp, 
     double v[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const double vc = Vc[k * n + i];
-      v[k] = Q[k * n + i] - c1 * vc - c2 * Vn[k * n + i];
-      Vn[k * n + i] = v[k];
+      const double vc = __builtin_nontemporal_load(&Vc[k * n + i]);
+      v[k] = __builtin_nontemporal_load(&Q[k * n + i]) - c1 * vc - c2 * __builtin_nontemporal_load(&Vn[k * n + i]);
+      __builtin_nontemporal_store(v[k], &Vn[k * n + i]);
       if (rpend) {
-        const double r = rs2 * Rt[k * n + i] + rc * vc;
-        Rt[k * n + i] = r;
+        const double r = rs2 * __builtin_nontemporal_load(&Rt[k * n + i]) + rc * vc;
+        __builtin_nontemporal_store(r, &Rt[k * n + i]);
         acc[1] += r * r;
       }
     }
@@ -658,6 +669,7 @@ __global__ void __launch_bounds__(kBS) k_minres_k4(const Inst* __restrict__ Dp, 
   const double a3 = C->s_prev * g;
   const double cn = a0 / a1, sn = gn / a1;
   C->a1 = a1; C->a2 = a2; C->a3 = a3;
+  if (C->iter & 1) C->coef_x_def = C->coef_x;  // the previous iteration's x update waits for this one's
   C->coef_x = cn * C->eta;
   C->gamma_w = g;
   C->pending = 1;
@@ -673,24 +685,31 @@ __global__ void __launch_bounds__(kBS) k_minres_k4(const Inst* __restrict__ Dp, 
   if (gn == 0.0 || C->its_total + C->iter >= maxit || !isfinite(a1) || a1 == 0.0) C->stop = 1;
 }
 
-// Pending update alone (after the loop stopped), with the parity of the
-// instance's own last iteration.
+// After the loop stopped: the pending update (with the parity of the
+// instance's own last iteration) and the solution updates still deferred.
 __global__ void __launch_bounds__(kBS) k_minres_flush(const Inst* __restrict__ Dp) {
   INST_BEGIN
   const KrylovCtrl* C = I.ctrl;
-  if (!C->want_restart || !C->pending) return;
+  const int it = C->iter;
+  if (!C->want_restart || !(C->pending || (it & 1))) return;
   const int i = blockIdx.x * kBS + threadIdx.x;
   if (i >= I.n) return;
-  const int it = C->iter, n = I.n;
+  const int n = I.n;
   const double* Zi = I.Z[it & 1];
   double* Wsame = I.W[it & 1];
   const double* Wother = I.W[(it + 1) & 1];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int q = k * n + i;
-    const double wi = (Zi[q] / C->gamma_w - C->a3 * Wsame[q] - C->a2 * Wother[q]) / C->a1;
-    Wsame[q] = wi;
-    I.X[q] += C->coef_x * wi;
+    if (C->pending) {
+      // w_it; with it even, w_(it-1) still owes its x update
+      const double wi = (Zi[q] / C->gamma_w - C->a3 * Wsame[q] - C->a2 * Wother[q]) / C->a1;
+      Wsame[q] = wi;
+      I.X[q] += (it & 1) ? C->coef_x * wi : (C->coef_x_def * Wother[q] + C->coef_x * wi);
+    } else {
+      // the last K1 formed w_it (it odd) and deferred its x update
+      I.X[q] += C->coef_x * Wsame[q];
+    }
   }
 }
 

@@ -6,6 +6,9 @@ FP64-oracle error printed beside each result.
 * 2D convection-diffusion (eps = 1/200, wind of Sec. 5.2) on 127^2 with the
   solver of the 255^2 benchmark (FGMRES(30) + P_T, FP32 V-cycles) and with
   MINRES + P_D;
+* 3D Poisson (7-point finite differences) on 31^3 with MINRES + P_D and FP32
+  V-cycles (the solver of the 127^3 benchmark), the size at which the finest
+  3D levels leave the single-workgroup coarse kernel.
 Bar: the same number of IPM iterations and rel-L2 <= 1e-6 in u, y and p."""
 import hashlib
 import json
@@ -44,11 +47,13 @@ def _rel(a, b):
 
 CASES = {
     "convdiff2d_127_seed0": lambda: W.convdiff2d_255(seed=0, N=127),
+    "poisson3d_31_seed0": lambda: W.poisson3d_127(seed=0, N=31),
 }
 
 
 @pytest.mark.parametrize("name,krylov,precond", [("convdiff2d_127_seed0", "fgmres", "pt"),
-                                                 ("convdiff2d_127_seed0", "minres", "pd")])
+                                                 ("convdiff2d_127_seed0", "minres", "pd"),
+                                                 ("poisson3d_31_seed0", "minres", "pd")])
 def test_whole_solve_against_stored_oracle(name, krylov, precond):
     from paper_1806_05896_amd import Options, Problem
     g = np.load(os.path.join(GOLDEN, f"{name}_oracle.npz"), allow_pickle=False)
