@@ -10,10 +10,12 @@
 namespace ipm {
 
 constexpr int kMaxLev = 16;
+// Levels of the widest single-workgroup coarse hierarchy (63, 31, 15, 7, 3, 1).
+constexpr int kCoarseLevels = 6;
 constexpr int kBS = 256;        // threads per block of the elementwise and stencil kernels
 constexpr int kCoarseBS = 1024;  // threads of the single-workgroup coarse-grid kernel
 constexpr int kTicketGroups = 8;   // sub-counters of the grid reduction ticket
-constexpr int kTicketStride = 64;  // unsigned words between sub-counters (one 256-byte line)  // threads of the single-workgroup coarse-grid kernel
+constexpr int kTicketStride = 64;  // unsigned words between sub-counters (one 256-byte line)
 
 // One multigrid level.  Arrays hold T = float or double (the V-cycle precision).
 struct Level {
@@ -116,6 +118,13 @@ struct Inst {
   int nu_pre, nu_post, vcycles;
   double omega;
   Level lv[kMaxLev];
+  // copies for the single-workgroup coarse kernels: lv[coarse_lev + q].mh
+  // (null past the last level), lv[coarse_lev].b, .x and .N, so their loads
+  // need not wait for coarse_lev
+  const void* cmh[kCoarseLevels];
+  const void* cb;
+  void* cx;
+  int cN0;
   const Level* lvd;     // the same level table in device memory (for loops over levels)
   const Inst* hsteps;   // heat equation: the nt per-time-step multigrid descriptors (device)
 };
@@ -565,6 +574,49 @@ __device__ __forceinline__ int xcd_node(int n) {
   if (b >= nb) return n;
   return ((b & 7) * (nb >> 3) + (b >> 3)) * kBS + threadIdx.x;
 }
+
+// Descriptor fields loaded together.  A kernel starts with cold caches, and
+// each load the compiler places behind a branch on an earlier one (active?
+// this level? stopped?) adds a memory round trip before the first byte of
+// data is requested: five of them cost several microseconds, more than the
+// work of a small launch.  IPM_LOAD_TOGETHER(gate, a, b, ...) makes the
+// uniform values a, b, ... inputs of one empty asm statement that also
+// rewrites gate, so every load producing them is issued before it and waited
+// for once, and the branches that test gate come after.  Up to 24 values.
+#define IPM_S_(a) "s"(a)
+#define IPM_SN_1(a) IPM_S_(a)
+#define IPM_SN_2(a, ...) IPM_S_(a), IPM_SN_1(__VA_ARGS__)
+#define IPM_SN_3(a, ...) IPM_S_(a), IPM_SN_2(__VA_ARGS__)
+#define IPM_SN_4(a, ...) IPM_S_(a), IPM_SN_3(__VA_ARGS__)
+#define IPM_SN_5(a, ...) IPM_S_(a), IPM_SN_4(__VA_ARGS__)
+#define IPM_SN_6(a, ...) IPM_S_(a), IPM_SN_5(__VA_ARGS__)
+#define IPM_SN_7(a, ...) IPM_S_(a), IPM_SN_6(__VA_ARGS__)
+#define IPM_SN_8(a, ...) IPM_S_(a), IPM_SN_7(__VA_ARGS__)
+#define IPM_SN_9(a, ...) IPM_S_(a), IPM_SN_8(__VA_ARGS__)
+#define IPM_SN_10(a, ...) IPM_S_(a), IPM_SN_9(__VA_ARGS__)
+#define IPM_SN_11(a, ...) IPM_S_(a), IPM_SN_10(__VA_ARGS__)
+#define IPM_SN_12(a, ...) IPM_S_(a), IPM_SN_11(__VA_ARGS__)
+#define IPM_SN_13(a, ...) IPM_S_(a), IPM_SN_12(__VA_ARGS__)
+#define IPM_SN_14(a, ...) IPM_S_(a), IPM_SN_13(__VA_ARGS__)
+#define IPM_SN_15(a, ...) IPM_S_(a), IPM_SN_14(__VA_ARGS__)
+#define IPM_SN_16(a, ...) IPM_S_(a), IPM_SN_15(__VA_ARGS__)
+#define IPM_SN_17(a, ...) IPM_S_(a), IPM_SN_16(__VA_ARGS__)
+#define IPM_SN_18(a, ...) IPM_S_(a), IPM_SN_17(__VA_ARGS__)
+#define IPM_SN_19(a, ...) IPM_S_(a), IPM_SN_18(__VA_ARGS__)
+#define IPM_SN_20(a, ...) IPM_S_(a), IPM_SN_19(__VA_ARGS__)
+#define IPM_SN_21(a, ...) IPM_S_(a), IPM_SN_20(__VA_ARGS__)
+#define IPM_SN_22(a, ...) IPM_S_(a), IPM_SN_21(__VA_ARGS__)
+#define IPM_SN_23(a, ...) IPM_S_(a), IPM_SN_22(__VA_ARGS__)
+#define IPM_SN_24(a, ...) IPM_S_(a), IPM_SN_23(__VA_ARGS__)
+#define IPM_NARGS_(_1, _2, _3, _4, _5, _6, _7, _8, _9, _10, _11, _12, _13, _14, _15, _16, _17, _18, _19, _20, _21, \
+                   _22, _23, _24, N, ...)                                                                          \
+  N
+#define IPM_NARGS(...) \
+  IPM_NARGS_(__VA_ARGS__, 24, 23, 22, 21, 20, 19, 18, 17, 16, 15, 14, 13, 12, 11, 10, 9, 8, 7, 6, 5, 4, 3, 2, 1, 0)
+#define IPM_CAT_(a, b) a##b
+#define IPM_CAT(a, b) IPM_CAT_(a, b)
+#define IPM_LOAD_TOGETHER(gate, ...) \
+  asm volatile("" : "+s"(gate) : IPM_CAT(IPM_SN_, IPM_NARGS(__VA_ARGS__))(__VA_ARGS__))
 
 // Start of every kernel: the instance of this block, skipped when inactive.
 #define INST_BEGIN                         \

@@ -612,23 +612,41 @@ __global__ void __launch_bounds__(kBS) k_minres_k2(const Inst* __restrict__ Dp, 
 template <typename T>
 __global__ void __launch_bounds__(kBS) k_minres_k4(const Inst* __restrict__ Dp, int nb, int mode, double tol, int maxit,
                                                    int outsel) {
-  INST_BEGIN
-  __shared__ double smem[kBS / 64];
+  const Inst& I = Dp[blockIdx.z];
+  int go = I.active;
   KrylovCtrl* C = I.ctrl;
-  if (mode == 0 ? !C->want_restart : C->stop) return;
+  const int n = I.n, pde = I.pde, cl = I.coarse_lev;
   const double* __restrict__ Vn = I.V[nb];
   double* __restrict__ Zn = I.Z[nb];
-  const T* __restrict__ xmg = mg_out<T>(I, outsel);
+  const void* x0 = I.lv[0].x;
+  const void* x02 = I.lv[0].x2;
+  double* partials = I.partials;
+  unsigned* counter = I.counter;
+  IPM_LOAD_TOGETHER(go, C, n, pde, cl, Vn, Zn, x0, x02, partials, counter);
+  if (!go) return;
+  __shared__ double smem[kBS / 64];
+  // the multigrid output (as mg_out)
+  const T* __restrict__ xmg = (const T*)((cl == 0 || !outsel) ? x0 : x02);
   const int i = blockIdx.x * kBS + threadIdx.x;
-  double acc[1] = {0.0};
-  if (i < I.n) {
-    const int n = I.n;
-    const double z = (double)xmg[i];
-    Zn[3 * n + i] = z;
-    acc[0] = Vn[3 * n + i] * z;
-    if (I.pde == 3) acc[0] += Vn[i] * Zn[i];
+  // the stop flag is requested with the node's data and tested before the store
+  const int f_stop = C->stop, f_want = C->want_restart;
+  double z = 0.0, v3 = 0.0, v0 = 0.0, z0 = 0.0;
+  if (i < n) {
+    z = (double)xmg[i];
+    v3 = Vn[3 * n + i];
+    if (pde == 3) {
+      v0 = Vn[i];
+      z0 = Zn[i];
+    }
   }
-  if (!grid_reduce<kSum, 1, kBS>(acc, I.partials, I.counter, gridDim.x, blockIdx.x, smem) || threadIdx.x != 0) return;
+  if (mode == 0 ? !f_want : f_stop) return;
+  double acc[1] = {0.0};
+  if (i < n) {
+    Zn[3 * n + i] = z;
+    acc[0] = v3 * z;
+    if (pde == 3) acc[0] += v0 * z0;
+  }
+  if (!grid_reduce<kSum, 1, kBS>(acc, partials, counter, gridDim.x, blockIdx.x, smem) || threadIdx.x != 0) return;
   const double dot = C->dot_tmp + acc[0];
   if (mode == 0) {
     C->iter = 0;

@@ -559,7 +559,7 @@ __device__ __forceinline__ const T* coarse_p2_cycle(T* lds, const int* LN, const
 // (kCoarseCDArrays arrays of n).
 constexpr int kCoarseCDArrays = 9;
 // Levels of the widest coarse hierarchy (63, 31, 15, 7, 3, 1).
-constexpr int kCoarseP2Levels = 6;
+constexpr int kCoarseP2Levels = kCoarseLevels;
 
 template <typename T>
 __device__ __forceinline__ T cd_row(const T* __restrict__ x, const T* __restrict__ cf, int i, int i1, int i2, int N,
@@ -714,22 +714,32 @@ template __global__ void k_mg_coarse_cd<double>(const Inst*, int, int);
 
 template <typename T>
 __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_p2(const Inst* __restrict__ Dp, int guard) {
-  INST_BEGIN
-  if (!I.coarse_p2 || mg_skip(I, guard)) return;
+  static_assert(kCoarseP2Levels == 6, "the descriptor loads below name six levels");
+  const Inst& I = Dp[blockIdx.z];
+  int go = I.active;
+  const int kind = I.coarse_p2, cl = I.coarse_lev, L = I.nlev, N0 = I.cN0, nu_pre = I.nu_pre, nu_post = I.nu_post;
+  const double omega = I.omega;
+  const KrylovCtrl* ctrl = I.ctrl;
+  const T* __restrict__ bg = (const T*)I.cb;
+  T* __restrict__ xg = (T*)I.cx;
+  const void *m0 = I.cmh[0], *m1 = I.cmh[1], *m2 = I.cmh[2], *m3 = I.cmh[3], *m4 = I.cmh[4], *m5 = I.cmh[5];
+  IPM_LOAD_TOGETHER(go, kind, cl, L, N0, nu_pre, nu_post, omega, ctrl, bg, xg, m0, m1, m2, m3, m4, m5);
+  if (!go || !kind) return;
+  const T* const mlev[kCoarseP2Levels] = {(const T*)m0, (const T*)m1, (const T*)m2,
+                                          (const T*)m3, (const T*)m4, (const T*)m5};
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ int LN[kMaxLev], LOFF[kMaxLev];
   __shared__ T LIH2[kMaxLev];
   T* lds = (T*)lds_raw;
-  const int cl = I.coarse_lev, L = I.nlev;
   const int tid = threadIdx.x;
-  const int N0 = I.lv[cl].N, n0 = N0 * N0;
-  // Global loads first, all in flight together: the top level's right-hand
-  // side and every level's reaction term m (the diagonal is d = 4/h^2 + m, or
-  // 8/(3h^2) + m for the Q1 stiffness).  The iterates start at zero (their
-  // zero rings are never written; the interiors are written before they are
-  // read) and the lower levels' right-hand sides come from the restriction,
-  // so nothing else of the level arrays is read.
-  const T* __restrict__ bg = (const T*)I.lv[cl].b;
+  const int n0 = N0 * N0;
+  // Global loads first, all in flight together with the stop flag: the top
+  // level's right-hand side and every level's reaction term m (the diagonal
+  // is d = 4/h^2 + m, or 8/(3h^2) + m for the Q1 stiffness).  The iterates
+  // start at zero (their zero rings are never written; the interiors are
+  // written before they are read) and the lower levels' right-hand sides come
+  // from the restriction, so nothing else of the level arrays is read.
+  const int f_stop = ctrl->stop, f_want = ctrl->want_restart;
   T breg[p2_per_thread<T>()];
 #pragma unroll
   for (int j = 0; j < p2_per_thread<T>(); ++j) {
@@ -740,13 +750,15 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_p2(const Inst* __restri
 #pragma unroll
   for (int q = 0; q < kCoarseP2Levels; ++q) {
     const int N = ((N0 + 1) >> q) - 1, n = N * N;
-    const T* __restrict__ m = cl + q < L ? (const T*)I.lv[cl + q].mh : nullptr;
+    const T* __restrict__ m = mlev[q];
 #pragma unroll
     for (int j = 0; j < p2_per_thread<T>(); ++j) {
       const int i = tid + j * kCoarseBS;
       mreg[q][j] = (cl + q < L && i < n) ? m[i] : (T)0;
     }
   }
+  // uniform over the workgroup, before any LDS or global store
+  if ((guard == 1 && f_stop) || (guard == 2 && !f_want)) return;
   if (tid == 0) {
     // level widths, offsets and 1/h^2 from the top width (h = 1 / (N + 1))
     int off = 0, N = N0;
@@ -768,8 +780,8 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_p2(const Inst* __restri
         const int N = ((N0 + 1) >> q) - 1, n = N * N, PP = (N + 2) * (N + 2);
         T* x = lds + off;
         for (int k = tid; k < 2 * PP; k += kCoarseBS) x[k] = (T)0;
-        const double h = I.lv[cl + q].h;
-        const T diag = I.coarse_p2 == 2 ? (T)(8.0 / (3.0 * h * h)) : (T)4 * (T)(1.0 / (h * h));
+        const double h = 1.0 / (N + 1);  // the level's mesh width, as the host sets it
+        const T diag = kind == 2 ? (T)(8.0 / (3.0 * h * h)) : (T)4 * (T)(1.0 / (h * h));
         T* d = x + 2 * PP + n;
 #pragma unroll
         for (int j = 0; j < p2_per_thread<T>(); ++j) {
@@ -794,11 +806,10 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_p2(const Inst* __restri
   }
   __syncthreads();
   // coarse_p2 2: the Q1 nine-point stiffness
-  const T* a = I.coarse_p2 == 2 ? coarse_p2_cycle<T, 9>(lds, LN, LOFF, LIH2, cl, L, (T)I.omega, I.nu_pre, I.nu_post)
-                                : coarse_p2_cycle<T, 5>(lds, LN, LOFF, LIH2, cl, L, (T)I.omega, I.nu_pre, I.nu_post);
+  const T* a = kind == 2 ? coarse_p2_cycle<T, 9>(lds, LN, LOFF, LIH2, cl, L, (T)omega, nu_pre, nu_post)
+                         : coarse_p2_cycle<T, 5>(lds, LN, LOFF, LIH2, cl, L, (T)omega, nu_pre, nu_post);
   {
     const int N = LN[cl];
-    T* xg = (T*)I.lv[cl].x;
     P2_FOR(N) xg[i] = a[p]; P2_END
   }
 }
@@ -994,6 +1005,8 @@ __global__ void k_mg_select(Inst* __restrict__ Dp, int slot) {
   if (l < I.nlev) {
     Level& L = I.lv[l];
     L.mh = (char*)L.mhb + (size_t)slot * L.n * (I.mg_fp32 ? 4 : 8);
+    const int q = l - I.coarse_lev;
+    if (q >= 0 && q < kCoarseLevels) I.cmh[q] = L.mh;
   }
   if (l == 0 && I.cpackb)
     I.cpack = (char*)I.cpackb + (size_t)slot * I.cpack_slot * (I.mg_fp32 ? 4 : 8);

@@ -34,8 +34,8 @@ constexpr size_t kStaticLdsMax = 65536;
 // the x-th contiguous eighth of them (a band of tile rows), so the halo rows
 // a tile shares with the tiles above and below are mostly in the same L2.
 // The order of the tiles changes no node's arithmetic.
-__device__ __forceinline__ void xcd_tile(int& tx, int& ty) {
-  const int nx = gridDim.x, nt = nx * gridDim.y;
+__device__ __forceinline__ void xcd_tile(int nx, int ny, int& tx, int& ty) {
+  const int nt = nx * ny;
   int t = blockIdx.x + nx * blockIdx.y;
   if ((nt & 7) == 0) t = (t & 7) * (nt >> 3) + (t >> 3);
   ty = t / nx;
@@ -72,24 +72,35 @@ __device__ __forceinline__ float omega_over<float>(float om, float d) { return o
 // ascent.
 template <typename T, int NU, int TC, int ST = 5>
 __global__ void __launch_bounds__(kBS) k_mg_down_p2(const Inst* __restrict__ Dp, int l, int scaled, int guard) {
-  INST_BEGIN
-  if (I.coarse_p2 != (ST == 5 ? 1 : 2) || l >= I.coarse_lev || mg_skip(I, guard)) return;
-  const Level& F = I.lv[l];
-  const Level& C = I.lv[l + 1];
-  const int N = F.N, Nc = C.N;
+  const Inst& I = Dp[blockIdx.z];
+  int go = I.active;
+  const int kind = I.coarse_p2, cl = I.coarse_lev;
+  const KrylovCtrl* ctrl = I.ctrl;
+  const int N = I.lv[l].N, Nc = I.lv[l + 1].N;
+  const double h = I.lv[l].h, omega = I.omega;
+  const T* __restrict__ bsrc = (const T*)(scaled ? I.lv[l].x2 : I.lv[l].b);
+  const T* __restrict__ mh = (const T*)I.lv[l].mh;
+  T* __restrict__ xfine = (T*)I.lv[l].x;
+  T* __restrict__ bfine = (T*)I.lv[l].b;
+  T* __restrict__ bcoarse = (T*)I.lv[l + 1].b;
+  const double* __restrict__ tyv = scaled ? I.ty : nullptr;
+  const double* __restrict__ obs = I.obs;
+  const int gx = gridDim.x, gy = gridDim.y;
+  IPM_LOAD_TOGETHER(go, kind, cl, ctrl, N, Nc, h, omega, bsrc, mh, xfine, bfine, bcoarse, tyv, obs, gx, gy);
+  if (!go || kind != (ST == 5 ? 1 : 2) || l >= cl) return;
   int tx, ty;
-  xcd_tile(tx, ty);
+  xcd_tile(gx, gy, tx, ty);
   const int J1 = tx * TC, J2 = ty * TC;
   if (J1 >= Nc || J2 >= Nc) return;
   constexpr int W = p2_down_width(NU, TC);
   __shared__ T bs[W * W], ds[W * W], xa[W * W], xb[W * W];
   const int o1 = 2 * J1 - NU, o2 = 2 * J2 - NU;  // fine coordinates of LDS (0, 0)
-  const T* __restrict__ bsrc = (const T*)(scaled ? F.x2 : F.b);
-  const double* __restrict__ tyv = scaled ? I.ty : nullptr;
-  const T* __restrict__ mh = (const T*)F.mh;
-  const T ih2 = p2l_scale<T, ST>(F.h), dg = p2l_diag<T, ST>(F.h);
-  const T om = (T)I.omega, om1 = (T)1 - om;
+  const T ih2 = p2l_scale<T, ST>(h), dg = p2l_diag<T, ST>(h);
+  const T om = (T)omega, om1 = (T)1 - om;
   const int tid = threadIdx.x;
+  // the stop flag is requested with the tile's data and tested before the
+  // first global store (the staging writes LDS only)
+  const int f_stop = ctrl->stop, f_want = ctrl->want_restart;
   for (int k = tid; k < W * W; k += kBS) {
     const int q2 = k / W, q1 = k - q2 * W;
     const int g1 = o1 + q1, g2 = o2 + q2;
@@ -97,7 +108,7 @@ __global__ void __launch_bounds__(kBS) k_mg_down_p2(const Inst* __restrict__ Dp,
     if ((unsigned)g1 < (unsigned)N && (unsigned)g2 < (unsigned)N) {
       const int gi = g1 + N * g2;
       bv = bsrc[gi];
-      if (tyv) bv = (T)(obs_w(I, gi) + tyv[gi]) * bv;
+      if (tyv) bv = (T)((obs ? obs[gi] : 1.0) + tyv[gi]) * bv;
       dv = dg + mh[gi];
       wv = omega_over<T>(om, dv);
     }
@@ -105,9 +116,11 @@ __global__ void __launch_bounds__(kBS) k_mg_down_p2(const Inst* __restrict__ Dp,
     ds[k] = dv;
     xa[k] = wv * bv;
   }
+  // uniform over the workgroup
+  if ((guard == 1 && f_stop) || (guard == 2 && !f_want)) return;
   __syncthreads();
   if (tyv) {
-    T* __restrict__ bout = (T*)F.b;
+    T* __restrict__ bout = bfine;
     for (int k = tid; k < 4 * TC * TC; k += kBS) {
       const int r2 = k / (2 * TC), r1 = k - r2 * (2 * TC);
       const int g1 = 2 * J1 + r1, g2 = 2 * J2 + r2;
@@ -130,7 +143,7 @@ __global__ void __launch_bounds__(kBS) k_mg_down_p2(const Inst* __restrict__ Dp,
     T* t = a; a = c; c = t;
   }
   {
-    T* __restrict__ xout = (T*)F.x;
+    T* __restrict__ xout = xfine;
     for (int k = tid; k < 4 * TC * TC; k += kBS) {
       const int r2 = k / (2 * TC), r1 = k - r2 * (2 * TC);
       const int g1 = 2 * J1 + r1, g2 = 2 * J2 + r2;
@@ -153,7 +166,7 @@ __global__ void __launch_bounds__(kBS) k_mg_down_p2(const Inst* __restrict__ Dp,
       const int li = (NU + 2 * j1 + 1) + W * (NU + 2 * j2 + 1);  // fine node 2c + 1
       const T v = (T)0.25 * c[li] + (T)0.125 * ((c[li - 1] + c[li + 1]) + (c[li - W] + c[li + W])) +
                   (T)0.0625 * ((c[li - 1 - W] + c[li + 1 - W]) + (c[li - 1 + W] + c[li + 1 + W]));
-      ((T*)C.b)[c1 + Nc * c2] = v;
+      bcoarse[c1 + Nc * c2] = v;
     }
   }
 }
@@ -163,12 +176,25 @@ __global__ void __launch_bounds__(kBS) k_mg_down_p2(const Inst* __restrict__ Dp,
 // writes the tile's own nodes to level l's x2.
 template <typename T, int NU, int TF, int ST = 5>
 __global__ void __launch_bounds__(kBS) k_mg_up_p2(const Inst* __restrict__ Dp, int l, int guard) {
-  INST_BEGIN
-  if (I.coarse_p2 != (ST == 5 ? 1 : 2) || l >= I.coarse_lev || mg_skip(I, guard)) return;
-  const Level& F = I.lv[l];
-  const int N = F.N, Nc = I.lv[l + 1].N;
+  const Inst& I = Dp[blockIdx.z];
+  int go = I.active;
+  const int kind = I.coarse_p2, cl = I.coarse_lev;
+  const KrylovCtrl* ctrl = I.ctrl;
+  const int N = I.lv[l].N, Nc = I.lv[l + 1].N;
+  const double h = I.lv[l].h, omega = I.omega;
+  const void* xc1 = I.lv[l + 1].x;
+  const void* xc2 = I.lv[l + 1].x2;
+  const T* __restrict__ xpre = (const T*)I.lv[l].x;
+  const T* __restrict__ b = (const T*)I.lv[l].b;
+  const T* __restrict__ mh = (const T*)I.lv[l].mh;
+  T* __restrict__ xout = (T*)I.lv[l].x2;
+  const int gx = gridDim.x, gy = gridDim.y;
+  IPM_LOAD_TOGETHER(go, kind, cl, ctrl, N, Nc, h, omega, xc1, xc2, xpre, b, mh, xout, gx, gy);
+  if (!go || kind != (ST == 5 ? 1 : 2) || l >= cl) return;
+  // the coarse iterate: the coarse kernel's output at the coarsest fused level
+  const T* __restrict__ xc = (const T*)(l + 1 == cl ? xc1 : xc2);
   int tx, ty;
-  xcd_tile(tx, ty);
+  xcd_tile(gx, gy, tx, ty);
   if (tx * TF >= N || ty * TF >= N) return;
   constexpr int W = p2_up_width(NU, TF);
   constexpr int WC = p2_up_coarse_width(NU, TF);
@@ -177,13 +203,12 @@ __global__ void __launch_bounds__(kBS) k_mg_up_p2(const Inst* __restrict__ Dp, i
   // coarse 1-based index of the patch's first column/row: the lower coarse
   // neighbour of the region's first fine node (fine 1-based index o + 1)
   const int cb1 = (o1 + 1) >> 1, cb2 = (o2 + 1) >> 1;
-  const T* __restrict__ xc = (const T*)(l + 1 == I.coarse_lev ? I.lv[l + 1].x : I.lv[l + 1].x2);
-  const T* __restrict__ xpre = (const T*)F.x;
-  const T* __restrict__ b = (const T*)F.b;
-  const T* __restrict__ mh = (const T*)F.mh;
-  const T ih2 = p2l_scale<T, ST>(F.h), dg = p2l_diag<T, ST>(F.h);
-  const T om = (T)I.omega, om1 = (T)1 - om;
+  const T ih2 = p2l_scale<T, ST>(h), dg = p2l_diag<T, ST>(h);
+  const T om = (T)omega, om1 = (T)1 - om;
   const int tid = threadIdx.x;
+  // the stop flag is requested with the tile's data and tested before the
+  // first global store (the staging writes LDS only)
+  const int f_stop = ctrl->stop, f_want = ctrl->want_restart;
   for (int k = tid; k < WC * WC; k += kBS) {
     const int p2 = k / WC, p1 = k - p2 * WC;
     const int c1 = cb1 + p1 - 1, c2 = cb2 + p2 - 1;  // 0-based coarse node
@@ -203,6 +228,8 @@ __global__ void __launch_bounds__(kBS) k_mg_up_p2(const Inst* __restrict__ Dp, i
     ws[k] = wv;
     xa[k] = xv;
   }
+  // uniform over the workgroup
+  if ((guard == 1 && f_stop) || (guard == 2 && !f_want)) return;
   __syncthreads();
   for (int k = tid; k < W * W; k += kBS) {
     const int q2 = k / W, q1 = k - q2 * W;
@@ -235,7 +262,6 @@ __global__ void __launch_bounds__(kBS) k_mg_up_p2(const Inst* __restrict__ Dp, i
     __syncthreads();
     T* t = a; a = c; c = t;
   }
-  T* __restrict__ xout = (T*)F.x2;
   for (int k = tid; k < TF * TF; k += kBS) {
     const int r2 = k / TF, r1 = k - r2 * TF;
     const int g1 = tx * TF + r1, g2 = ty * TF + r2;

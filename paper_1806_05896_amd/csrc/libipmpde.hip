@@ -485,6 +485,16 @@ static int group_create(const std::vector<ipmpde_problem*>& probs, int cap, int 
   return IPMPDE_OK;
 }
 
+// The coarse kernels' copies of their level pointers (after lv, nlev and
+// coarse_lev are set; k_mg_select keeps cmh in step with lv[].mh).
+static void coarse_copies(Inst& d) {
+  const int cl = d.coarse_lev;
+  d.cN0 = d.lv[cl].N;
+  d.cb = d.lv[cl].b;
+  d.cx = d.lv[cl].x;
+  for (int q = 0; q < kCoarseLevels; ++q) d.cmh[q] = cl + q < d.nlev ? d.lv[cl + q].mh : nullptr;
+}
+
 // Heat equation: the per-time-step descriptors (from the problem's filled
 // descriptor d) and the launch view over them.  Step t is a 2D Poisson-type
 // instance with operator I/tau + A_h + M_hat_t whose arrays are the t-th
@@ -527,6 +537,7 @@ static void heat_steps(ipmpde_problem* P, const Inst& d, bool fp32) {
     S.cpack_elems = pe;
     S.ppi = 0;
     S.lvd = nullptr;
+    coarse_copies(S);
   }
   Group& V = P->hview;
   V.count = 1;
@@ -622,6 +633,7 @@ static int group_select(Group* G, const ipmpde_options& o) {
     d.kc_s[0] = kc[1];
     d.kc_s[1] = kc[2];
     d.cpack_elems = fp32 ? P->cpack_elems32 : P->cpack_elems64;
+    coarse_copies(d);
     G->max_cpack = std::max(G->max_cpack, d.cpack_elems);
     G->p2 = G->p2 || padded_coarse(P);
     G->gen = G->gen || !padded_coarse(P);
