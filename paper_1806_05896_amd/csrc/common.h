@@ -125,6 +125,10 @@ struct Inst {
   const void* cb;
   void* cx;
   int cN0;
+  // per coarse level q: 1/h^2 and 8/(3 h^2) (the Q1 diagonal), h = 1/(N_q + 1),
+  // computed once on the host
+  double cih2[kCoarseLevels];
+  double cq1d[kCoarseLevels];
   const Level* lvd;     // the same level table in device memory (for loops over levels)
   const Inst* hsteps;   // heat equation: the nt per-time-step multigrid descriptors (device)
 };
@@ -582,7 +586,7 @@ __device__ __forceinline__ int xcd_node(int n) {
 // work of a small launch.  IPM_LOAD_TOGETHER(gate, a, b, ...) makes the
 // uniform values a, b, ... inputs of one empty asm statement that also
 // rewrites gate, so every load producing them is issued before it and waited
-// for once, and the branches that test gate come after.  Up to 24 values.
+// for once, and the branches that test gate come after.  Up to 28 values.
 #define IPM_S_(a) "s"(a)
 #define IPM_SN_1(a) IPM_S_(a)
 #define IPM_SN_2(a, ...) IPM_S_(a), IPM_SN_1(__VA_ARGS__)
@@ -608,11 +612,16 @@ __device__ __forceinline__ int xcd_node(int n) {
 #define IPM_SN_22(a, ...) IPM_S_(a), IPM_SN_21(__VA_ARGS__)
 #define IPM_SN_23(a, ...) IPM_S_(a), IPM_SN_22(__VA_ARGS__)
 #define IPM_SN_24(a, ...) IPM_S_(a), IPM_SN_23(__VA_ARGS__)
+#define IPM_SN_25(a, ...) IPM_S_(a), IPM_SN_24(__VA_ARGS__)
+#define IPM_SN_26(a, ...) IPM_S_(a), IPM_SN_25(__VA_ARGS__)
+#define IPM_SN_27(a, ...) IPM_S_(a), IPM_SN_26(__VA_ARGS__)
+#define IPM_SN_28(a, ...) IPM_S_(a), IPM_SN_27(__VA_ARGS__)
 #define IPM_NARGS_(_1, _2, _3, _4, _5, _6, _7, _8, _9, _10, _11, _12, _13, _14, _15, _16, _17, _18, _19, _20, _21, \
-                   _22, _23, _24, N, ...)                                                                          \
+                   _22, _23, _24, _25, _26, _27, _28, N, ...)                                                      \
   N
-#define IPM_NARGS(...) \
-  IPM_NARGS_(__VA_ARGS__, 24, 23, 22, 21, 20, 19, 18, 17, 16, 15, 14, 13, 12, 11, 10, 9, 8, 7, 6, 5, 4, 3, 2, 1, 0)
+#define IPM_NARGS(...)                                                                                            \
+  IPM_NARGS_(__VA_ARGS__, 28, 27, 26, 25, 24, 23, 22, 21, 20, 19, 18, 17, 16, 15, 14, 13, 12, 11, 10, 9, 8, 7, 6, 5, \
+             4, 3, 2, 1, 0)
 #define IPM_CAT_(a, b) a##b
 #define IPM_CAT(a, b) IPM_CAT_(a, b)
 #define IPM_LOAD_TOGETHER(gate, ...) \

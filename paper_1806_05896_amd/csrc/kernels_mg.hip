@@ -452,11 +452,30 @@ __device__ __forceinline__ T p2_nb(const T* __restrict__ a, int p, int P, T ihs)
   }
 }
 
+// Per-thread node loop of the coarse kernel's levels with the per-node
+// values held in registers: the nodes of a thread at level N are
+// (i1, i20 + j step), j < R (the P2_FOR_T layout, unrolled), and R nodes per
+// thread cover the widest level (R NT >= N (N + 1)).
+#define P2_FOR_R(R_)                                                   \
+  _Pragma("unroll") for (int j = 0; j < (R_); ++j) {                   \
+    const int i2 = i20 + j * step;                                     \
+    if (i2 < N && i1 < N) {                                            \
+      const int i = i1 + N * i2;                                       \
+      const int p = (i1 + 1) + P * (i2 + 1);                           \
+      (void)i; (void)p;
+#define P2_END_R \
+    }            \
+  }
+
 // Descent at level l: nu_pre damped-Jacobi sweeps from zero, the residual and
-// its full-weighting restriction to level l + 1's right-hand side.
+// its full-weighting restriction to level l + 1's right-hand side.  The
+// right-hand side, d and 1/d of the thread's nodes are read from LDS once.
 template <typename T, int NT, int ST = 5>
 __device__ __forceinline__ void p2_down(int nu_pre, T* lds, const int* LN, const int* LOFF, const T* LIH2, int l,
                                         int tid, T om, unsigned& alt) {
+  constexpr int R = p2_per_thread<T>();
+  // the widest level in LDS: 63 x 63 in FP32, 31 x 31 in FP64 (the coarse level choice keeps to these)
+  static_assert(R * NT >= (sizeof(T) == 8 ? 31 * 32 : kCoarseP2MaxN * (kCoarseP2MaxN + 1)), "nodes per thread");
   const int N = LN[l], P = N + 2, n = N * N;
   const T ih2 = ST == 5 ? LIH2[l] : LIH2[l] * (T)(1.0 / 3.0);
   T* a = lds + LOFF[l];
@@ -464,24 +483,27 @@ __device__ __forceinline__ void p2_down(int nu_pre, T* lds, const int* LN, const
   const T* b = c + P * P;
   const T* d = b + n;
   const T* dinv = d + n;
+  const int sh = 31 - __builtin_clz(N + 1), step = NT >> sh, i1 = tid & ((1 << sh) - 1), i20 = tid >> sh;
+  T rb[R], rd[R], rdi[R];
+  P2_FOR_R(R) rb[j] = b[i]; rd[j] = d[i]; rdi[j] = dinv[i]; P2_END_R
   for (int s = 0; s < nu_pre; ++s) {
     if (s == 0) {
-      P2_FOR_T(N, tid, NT) c[p] = om * b[i] * dinv[i]; P2_END
+      P2_FOR_R(R) c[p] = om * rb[j] * rdi[j]; P2_END_R
     } else {
-      P2_FOR_T(N, tid, NT) c[p] = a[p] + om * (b[i] - d[i] * a[p] + p2_nb<T, ST>(a, p, P, ih2)) * dinv[i]; P2_END
+      P2_FOR_R(R) c[p] = a[p] + om * (rb[j] - rd[j] * a[p] + p2_nb<T, ST>(a, p, P, ih2)) * rdi[j]; P2_END_R
     }
     __syncthreads();
     T* t = a; a = c; c = t;
     alt ^= 1u << l;
   }
-  P2_FOR_T(N, tid, NT) c[p] = b[i] - d[i] * a[p] + p2_nb<T, ST>(a, p, P, ih2); P2_END
+  P2_FOR_R(R) c[p] = rb[j] - rd[j] * a[p] + p2_nb<T, ST>(a, p, P, ih2); P2_END_R
   __syncthreads();
   const int Nc = LN[l + 1];
   T* bc = lds + LOFF[l + 1] + 2 * (Nc + 2) * (Nc + 2);
   {
-    const int sh = 31 - __builtin_clz(Nc + 1), msk = (1 << sh) - 1, step = NT >> sh;
+    const int shc = 31 - __builtin_clz(Nc + 1), msk = (1 << shc) - 1, stepc = NT >> shc;
     const int j1 = tid & msk;
-    for (int j2 = tid >> sh; j2 < Nc && j1 < Nc; j2 += step) {
+    for (int j2 = tid >> shc; j2 < Nc && j1 < Nc; j2 += stepc) {
       const int ic = j1 + Nc * j2;
       const int p = (2 * j1 + 2) + P * (2 * j2 + 2);  // fine node 2j+1 (0-based) in padded coordinates
       bc[ic] = (T)0.25 * c[p] + (T)0.125 * (c[p - 1] + c[p + 1] + c[p - P] + c[p + P]) +
@@ -492,10 +514,12 @@ __device__ __forceinline__ void p2_down(int nu_pre, T* lds, const int* LN, const
 }
 
 // Ascent at level l: bilinear prolongation of level l + 1's iterate (in xb
-// when bit l + 1 of alt is set) added to the iterate, nu_post sweeps.
+// when bit l + 1 of alt is set) added to the iterate, nu_post sweeps (the
+// right-hand side, d and 1/d of the thread's nodes in registers).
 template <typename T, int NT, int ST = 5>
 __device__ __forceinline__ void p2_up(int nu_post, T* lds, const int* LN, const int* LOFF, const T* LIH2, int l,
                                       int tid, T om, unsigned& alt) {
+  constexpr int R = p2_per_thread<T>();
   const int N = LN[l], P = N + 2, n = N * N;
   const int Nc = LN[l + 1], Pc = Nc + 2;
   const T ih2 = ST == 5 ? LIH2[l] : LIH2[l] * (T)(1.0 / 3.0);
@@ -507,17 +531,20 @@ __device__ __forceinline__ void p2_up(int nu_post, T* lds, const int* LN, const 
   const T* d = b + n;
   const T* dinv = d + n;
   const T* xc = lds + LOFF[l + 1] + ((alt >> (l + 1)) & 1u) * Pc * Pc;
-  P2_FOR_T(N, tid, NT)
+  const int sh = 31 - __builtin_clz(N + 1), step = NT >> sh, i1 = tid & ((1 << sh) - 1), i20 = tid >> sh;
+  T rb[R], rd[R], rdi[R];
+  P2_FOR_R(R)
+    rb[j] = b[i]; rd[j] = d[i]; rdi[j] = dinv[i];
     // bilinear interpolation: fine 1-based F maps to coarse F/2 (even) or the two neighbours (odd);
     // in padded coarse coordinates the boundary nodes are the zero ring
     const int F1 = i1 + 1, F2 = i2 + 1;
     const int lo1 = F1 >> 1, hi1 = (F1 + 1) >> 1, lo2 = F2 >> 1, hi2 = (F2 + 1) >> 1;
     const T v = (T)0.25 * (xc[lo1 + Pc * lo2] + xc[hi1 + Pc * lo2] + xc[lo1 + Pc * hi2] + xc[hi1 + Pc * hi2]);
     a[F1 + P * F2] += v;
-  P2_END
+  P2_END_R
   __syncthreads();
   for (int s = 0; s < nu_post; ++s) {
-    P2_FOR_T(N, tid, NT) c[p] = a[p] + om * (b[i] - d[i] * a[p] + p2_nb<T, ST>(a, p, P, ih2)) * dinv[i]; P2_END
+    P2_FOR_R(R) c[p] = a[p] + om * (rb[j] - rd[j] * a[p] + p2_nb<T, ST>(a, p, P, ih2)) * rdi[j]; P2_END_R
     __syncthreads();
     T* t = a; a = c; c = t;
     alt ^= 1u << l;
@@ -723,8 +750,13 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_p2(const Inst* __restri
   const T* __restrict__ bg = (const T*)I.cb;
   T* __restrict__ xg = (T*)I.cx;
   const void *m0 = I.cmh[0], *m1 = I.cmh[1], *m2 = I.cmh[2], *m3 = I.cmh[3], *m4 = I.cmh[4], *m5 = I.cmh[5];
-  IPM_LOAD_TOGETHER(go, kind, cl, L, N0, nu_pre, nu_post, omega, ctrl, bg, xg, m0, m1, m2, m3, m4, m5);
+  const double ih0 = I.cih2[0], ih1 = I.cih2[1], ih2 = I.cih2[2], ih3 = I.cih2[3], ih4 = I.cih2[4], ih5 = I.cih2[5];
+  const double qd0 = I.cq1d[0], qd1 = I.cq1d[1], qd2 = I.cq1d[2], qd3 = I.cq1d[3], qd4 = I.cq1d[4], qd5 = I.cq1d[5];
+  IPM_LOAD_TOGETHER(go, kind, cl, L, N0, nu_pre, nu_post, omega, ctrl, bg, xg, m0, m1, m2, m3, m4, m5, ih0, ih1, ih2,
+                    ih3, ih4, ih5, qd0, qd1, qd2, qd3, qd4, qd5);
   if (!go || !kind) return;
+  const double cih2[kCoarseP2Levels] = {ih0, ih1, ih2, ih3, ih4, ih5};
+  const double cq1d[kCoarseP2Levels] = {qd0, qd1, qd2, qd3, qd4, qd5};
   const T* const mlev[kCoarseP2Levels] = {(const T*)m0, (const T*)m1, (const T*)m2,
                                           (const T*)m3, (const T*)m4, (const T*)m5};
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -759,17 +791,14 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_p2(const Inst* __restri
   }
   // uniform over the workgroup, before any LDS or global store
   if ((guard == 1 && f_stop) || (guard == 2 && !f_want)) return;
-  if (tid == 0) {
+  if (tid < kCoarseP2Levels && cl + tid < L) {
     // level widths, offsets and 1/h^2 from the top width (h = 1 / (N + 1))
-    int off = 0, N = N0;
-    for (int l = cl; l < L; ++l) {
-      LN[l] = N;
-      LOFF[l] = off;
-      const double h = 1.0 / (N + 1);
-      LIH2[l] = (T)(1.0 / (h * h));
-      off += coarse_p2_elems(N);
-      N = (N - 1) / 2;
-    }
+    const int q = tid;
+    int off = 0;
+    for (int r = 0; r < q; ++r) off += coarse_p2_elems(((N0 + 1) >> r) - 1);
+    LN[cl + q] = ((N0 + 1) >> q) - 1;
+    LOFF[cl + q] = off;
+    LIH2[cl + q] = (T)cih2[q];
   }
   // layout of level l at LOFF[l]: xa[(N+2)^2], xb[(N+2)^2], b[N^2], d[N^2], dinv[N^2]
   {
@@ -780,8 +809,7 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_p2(const Inst* __restri
         const int N = ((N0 + 1) >> q) - 1, n = N * N, PP = (N + 2) * (N + 2);
         T* x = lds + off;
         for (int k = tid; k < 2 * PP; k += kCoarseBS) x[k] = (T)0;
-        const double h = 1.0 / (N + 1);  // the level's mesh width, as the host sets it
-        const T diag = kind == 2 ? (T)(8.0 / (3.0 * h * h)) : (T)4 * (T)(1.0 / (h * h));
+        const T diag = kind == 2 ? (T)cq1d[q] : (T)4 * (T)cih2[q];
         T* d = x + 2 * PP + n;
 #pragma unroll
         for (int j = 0; j < p2_per_thread<T>(); ++j) {

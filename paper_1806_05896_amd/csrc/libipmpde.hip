@@ -492,7 +492,13 @@ static void coarse_copies(Inst& d) {
   d.cN0 = d.lv[cl].N;
   d.cb = d.lv[cl].b;
   d.cx = d.lv[cl].x;
-  for (int q = 0; q < kCoarseLevels; ++q) d.cmh[q] = cl + q < d.nlev ? d.lv[cl + q].mh : nullptr;
+  for (int q = 0; q < kCoarseLevels; ++q) {
+    d.cmh[q] = cl + q < d.nlev ? d.lv[cl + q].mh : nullptr;
+    const int N = ((d.cN0 + 1) >> q) - 1;
+    const double h = 1.0 / (N + 1);  // as lv[].h
+    d.cih2[q] = N > 0 ? 1.0 / (h * h) : 0.0;
+    d.cq1d[q] = N > 0 ? 8.0 / (3.0 * h * h) : 0.0;
+  }
 }
 
 // Heat equation: the per-time-step descriptors (from the problem's filled
