@@ -118,17 +118,13 @@ struct Inst {
   int nu_pre, nu_post, vcycles;
   double omega;
   Level lv[kMaxLev];
-  // copies for the single-workgroup coarse kernels: lv[coarse_lev + q].mh
-  // (null past the last level), lv[coarse_lev].b, .x and .N, so their loads
-  // need not wait for coarse_lev
-  const void* cmh[kCoarseLevels];
+  // copies for the 2D Poisson coarse kernel, so its loads need not wait for
+  // coarse_lev: lv[coarse_lev].b, .x and .N, and 1/h^2 of coarse level q
+  // (h = 1/(N_q + 1)), computed once on the host
   const void* cb;
   void* cx;
   int cN0;
-  // per coarse level q: 1/h^2 and 8/(3 h^2) (the Q1 diagonal), h = 1/(N_q + 1),
-  // computed once on the host
   double cih2[kCoarseLevels];
-  double cq1d[kCoarseLevels];
   const Level* lvd;     // the same level table in device memory (for loops over levels)
   const Inst* hsteps;   // heat equation: the nt per-time-step multigrid descriptors (device)
 };

@@ -745,52 +745,57 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_p2(const Inst* __restri
   const Inst& I = Dp[blockIdx.z];
   int go = I.active;
   const int kind = I.coarse_p2, cl = I.coarse_lev, L = I.nlev, N0 = I.cN0, nu_pre = I.nu_pre, nu_post = I.nu_post;
+  const int elems = I.cpack_elems;
   const double omega = I.omega;
   const KrylovCtrl* ctrl = I.ctrl;
   const T* __restrict__ bg = (const T*)I.cb;
   T* __restrict__ xg = (T*)I.cx;
-  const void *m0 = I.cmh[0], *m1 = I.cmh[1], *m2 = I.cmh[2], *m3 = I.cmh[3], *m4 = I.cmh[4], *m5 = I.cmh[5];
+  const T* __restrict__ img = (const T*)I.cpack;
   const double ih0 = I.cih2[0], ih1 = I.cih2[1], ih2 = I.cih2[2], ih3 = I.cih2[3], ih4 = I.cih2[4], ih5 = I.cih2[5];
-  const double qd0 = I.cq1d[0], qd1 = I.cq1d[1], qd2 = I.cq1d[2], qd3 = I.cq1d[3], qd4 = I.cq1d[4], qd5 = I.cq1d[5];
-  IPM_LOAD_TOGETHER(go, kind, cl, L, N0, nu_pre, nu_post, omega, ctrl, bg, xg, m0, m1, m2, m3, m4, m5, ih0, ih1, ih2,
-                    ih3, ih4, ih5, qd0, qd1, qd2, qd3, qd4, qd5);
+  IPM_LOAD_TOGETHER(go, kind, cl, L, N0, nu_pre, nu_post, elems, omega, ctrl, bg, xg, img, ih0, ih1, ih2, ih3, ih4,
+                    ih5);
   if (!go || !kind) return;
   const double cih2[kCoarseP2Levels] = {ih0, ih1, ih2, ih3, ih4, ih5};
-  const double cq1d[kCoarseP2Levels] = {qd0, qd1, qd2, qd3, qd4, qd5};
-  const T* const mlev[kCoarseP2Levels] = {(const T*)m0, (const T*)m1, (const T*)m2,
-                                          (const T*)m3, (const T*)m4, (const T*)m5};
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ int LN[kMaxLev], LOFF[kMaxLev];
   __shared__ T LIH2[kMaxLev];
   T* lds = (T*)lds_raw;
   const int tid = threadIdx.x;
-  const int n0 = N0 * N0;
-  // Global loads first, all in flight together with the stop flag: the top
-  // level's right-hand side and every level's reaction term m (the diagonal
-  // is d = 4/h^2 + m, or 8/(3h^2) + m for the Q1 stiffness).  The iterates
-  // start at zero (their zero rings are never written; the interiors are
-  // written before they are read) and the lower levels' right-hand sides come
-  // from the restriction, so nothing else of the level arrays is read.
+  // Staging, all global loads in flight together with the stop flag: the
+  // coarse levels' image (zero iterates and right-hand sides, d = 4/h^2 + m or
+  // 8/(3 h^2) + m and 1/d of every level, built by k_coarse_pack at the Newton
+  // setup) in 16-byte pieces, and level cl's right-hand side at the nodes
+  // this thread owns in the sweeps.  The iterates' zero rings are never
+  // written; their interiors and the lower levels' right-hand sides are
+  // written before they are read.
   const int f_stop = ctrl->stop, f_want = ctrl->want_restart;
-  T breg[p2_per_thread<T>()];
+  constexpr int VE = 16 / (int)sizeof(T);                                // elements per piece
+  constexpr int MAXV = (int)((150 * 1024 / 16 + kCoarseBS - 1) / kCoarseBS);  // pieces per thread (LDS budget)
+  const bool vec = ((uintptr_t)img & 15) == 0;  // slot images start on 16 bytes (the host rounds the stride)
+  const int nvec = vec ? elems / VE : 0;
+  typedef unsigned int piece_t __attribute__((ext_vector_type(4)));
+  piece_t rv[MAXV];
 #pragma unroll
-  for (int j = 0; j < p2_per_thread<T>(); ++j) {
-    const int i = tid + j * kCoarseBS;
-    breg[j] = i < n0 ? bg[i] : (T)0;
+  for (int j = 0; j < MAXV; ++j) {
+    const int v = tid + j * kCoarseBS;
+    if (v < nvec) rv[j] = reinterpret_cast<const piece_t*>(img)[v];
   }
-  T mreg[kCoarseP2Levels][p2_per_thread<T>()];
+  constexpr int R = p2_per_thread<T>();
+  const int sh = 31 - __builtin_clz(N0 + 1), step = kCoarseBS >> sh, i1 = tid & ((1 << sh) - 1), i20 = tid >> sh;
+  T breg[R];
 #pragma unroll
-  for (int q = 0; q < kCoarseP2Levels; ++q) {
-    const int N = ((N0 + 1) >> q) - 1, n = N * N;
-    const T* __restrict__ m = mlev[q];
-#pragma unroll
-    for (int j = 0; j < p2_per_thread<T>(); ++j) {
-      const int i = tid + j * kCoarseBS;
-      mreg[q][j] = (cl + q < L && i < n) ? m[i] : (T)0;
-    }
+  for (int j = 0; j < R; ++j) {
+    const int i2 = i20 + j * step;
+    if (i2 < N0 && i1 < N0) breg[j] = bg[i1 + N0 * i2];
   }
   // uniform over the workgroup, before any LDS or global store
   if ((guard == 1 && f_stop) || (guard == 2 && !f_want)) return;
+#pragma unroll
+  for (int j = 0; j < MAXV; ++j) {
+    const int v = tid + j * kCoarseBS;
+    if (v < nvec) reinterpret_cast<piece_t*>(lds)[v] = rv[j];
+  }
+  for (int k = nvec * VE + tid; k < elems; k += kCoarseBS) lds[k] = img[k];  // the tail (all of it if unaligned)
   if (tid < kCoarseP2Levels && cl + tid < L) {
     // level widths, offsets and 1/h^2 from the top width (h = 1 / (N + 1))
     const int q = tid;
@@ -800,39 +805,17 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_p2(const Inst* __restri
     LOFF[cl + q] = off;
     LIH2[cl + q] = (T)cih2[q];
   }
-  // layout of level l at LOFF[l]: xa[(N+2)^2], xb[(N+2)^2], b[N^2], d[N^2], dinv[N^2]
+  __syncthreads();
   {
-    int off = 0;
+    // level cl's right-hand side over the image's zeros: each node by the
+    // thread that owns it in the sweeps, the only thread that reads it back
+    T* b0 = lds + 2 * (N0 + 2) * (N0 + 2);
 #pragma unroll
-    for (int q = 0; q < kCoarseP2Levels; ++q) {
-      if (cl + q < L) {
-        const int N = ((N0 + 1) >> q) - 1, n = N * N, PP = (N + 2) * (N + 2);
-        T* x = lds + off;
-        for (int k = tid; k < 2 * PP; k += kCoarseBS) x[k] = (T)0;
-        const T diag = kind == 2 ? (T)cq1d[q] : (T)4 * (T)cih2[q];
-        T* d = x + 2 * PP + n;
-#pragma unroll
-        for (int j = 0; j < p2_per_thread<T>(); ++j) {
-          const int i = tid + j * kCoarseBS;
-          if (i < n) {
-            const T dv = diag + mreg[q][j];
-            d[i] = dv;
-            d[n + i] = (T)1 / dv;
-          }
-        }
-        if (q == 0) {
-          T* b = x + 2 * PP;
-#pragma unroll
-          for (int j = 0; j < p2_per_thread<T>(); ++j) {
-            const int i = tid + j * kCoarseBS;
-            if (i < n0) b[i] = breg[j];
-          }
-        }
-        off += coarse_p2_elems(N);
-      }
+    for (int j = 0; j < R; ++j) {
+      const int i2 = i20 + j * step;
+      if (i2 < N0 && i1 < N0) b0[i1 + N0 * i2] = breg[j];
     }
   }
-  __syncthreads();
   // coarse_p2 2: the Q1 nine-point stiffness
   const T* a = kind == 2 ? coarse_p2_cycle<T, 9>(lds, LN, LOFF, LIH2, cl, L, (T)omega, nu_pre, nu_post)
                          : coarse_p2_cycle<T, 5>(lds, LN, LOFF, LIH2, cl, L, (T)omega, nu_pre, nu_post);
@@ -1033,8 +1016,6 @@ __global__ void k_mg_select(Inst* __restrict__ Dp, int slot) {
   if (l < I.nlev) {
     Level& L = I.lv[l];
     L.mh = (char*)L.mhb + (size_t)slot * L.n * (I.mg_fp32 ? 4 : 8);
-    const int q = l - I.coarse_lev;
-    if (q >= 0 && q < kCoarseLevels) I.cmh[q] = L.mh;
   }
   if (l == 0 && I.cpackb)
     I.cpack = (char*)I.cpackb + (size_t)slot * I.cpack_slot * (I.mg_fp32 ? 4 : 8);

@@ -289,6 +289,11 @@ static int coarse_kind(const ipmpde_problem* P) {
   return P->pde == IPMPDE_CONVDIFF ? kCoarseCD : kCoarseGeneric;
 }
 
+// Elements between two reaction-term slots' coarse images: a multiple of 4,
+// so every slot's image starts on 16 bytes (the coarse kernel copies it in
+// 16-byte pieces).
+static int cpack_stride(int elems) { return (elems + 3) & ~3; }
+
 // Reaction-term slots of every multigrid level (see k_mg_select): the
 // Schur-approximation operator's, and the two extra operators of P_Pi.
 static constexpr int kReactionSlots = 3;
@@ -363,7 +368,7 @@ static int ensure_mg(ipmpde_problem* P, bool fp32) {
     int elems = 0;
     for (int l = cl; l < P->nlev; ++l) elems += coarse_p2_elems(lv[l].N);
     void*& pk = fp32 ? P->cpack32 : P->cpack64;
-    TRY(P->work.alloc(&pk, (size_t)kReactionSlots * elems * el));
+    TRY(P->work.alloc(&pk, (size_t)kReactionSlots * cpack_stride(elems) * el));
     (fp32 ? P->cpack_elems32 : P->cpack_elems64) = elems;
   }
   Level*& lvd = fp32 ? P->lvd32 : P->lvd64;
@@ -485,19 +490,17 @@ static int group_create(const std::vector<ipmpde_problem*>& probs, int cap, int 
   return IPMPDE_OK;
 }
 
-// The coarse kernels' copies of their level pointers (after lv, nlev and
-// coarse_lev are set; k_mg_select keeps cmh in step with lv[].mh).
+// The coarse kernel's copies of its level fields (after lv, nlev and
+// coarse_lev are set).
 static void coarse_copies(Inst& d) {
   const int cl = d.coarse_lev;
   d.cN0 = d.lv[cl].N;
   d.cb = d.lv[cl].b;
   d.cx = d.lv[cl].x;
   for (int q = 0; q < kCoarseLevels; ++q) {
-    d.cmh[q] = cl + q < d.nlev ? d.lv[cl + q].mh : nullptr;
     const int N = ((d.cN0 + 1) >> q) - 1;
     const double h = 1.0 / (N + 1);  // as lv[].h
     d.cih2[q] = N > 0 ? 1.0 / (h * h) : 0.0;
-    d.cq1d[q] = N > 0 ? 8.0 / (3.0 * h * h) : 0.0;
   }
 }
 
@@ -630,7 +633,7 @@ static int group_select(Group* G, const ipmpde_options& o) {
     d.coarse_p2 = is_p2(P) ? 1 : (padded_coarse(P) ? 2 : 0);
     d.cpack = fp32 ? P->cpack32 : P->cpack64;
     d.cpackb = d.cpack;
-    d.cpack_slot = fp32 ? P->cpack_elems32 : P->cpack_elems64;
+    d.cpack_slot = cpack_stride(fp32 ? P->cpack_elems32 : P->cpack_elems64);
     d.obs = P->obs;
     d.eobs = P->eobs;
     d.ppi = o.precond == IPMPDE_PPI ? 1 : 0;
