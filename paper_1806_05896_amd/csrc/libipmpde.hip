@@ -28,6 +28,7 @@
 #include "kernels_krylov.hip"
 #include "kernels_mg.hip"
 #include "kernels_mg_p2.hip"
+#include "kernels_mg_p3.hip"
 #include "kernels_persist.hip"
 #include "kernels_fgmres.hip"
 
@@ -148,8 +149,9 @@ struct Group {
   bool gen = false;  // some instance uses the generic (unpadded) level and coarse kernels
   bool cd = false;   // some instance is 2D convection-diffusion (its own coarse kernel)
   bool gen3 = false; // some instance takes the generic coarse kernel (3D)
+  bool p3 = false;   // 3D, every instance finite-difference Poisson: the fused level kernels
   int max_cpack = 0; // longest coarse LDS image (Poisson instances)
-  bool any_small = false;  // 2D: some instance runs its whole hierarchy in the coarse kernel
+  bool any_small = false;  // some instance runs its whole hierarchy in the coarse kernel
   bool persist = false;    // some instance takes the persistent single-workgroup MINRES kernel
   int outsel = 1;    // level-0 output buffer of a V-cycle (x2 = 1)
   bool heat = false; // heat-equation problems (a group holds only heat problems or none)
@@ -287,6 +289,15 @@ static bool padded_coarse(const ipmpde_problem* P) { return is_p2(P) || (P->dim 
 static int coarse_kind(const ipmpde_problem* P) {
   if (padded_coarse(P)) return kCoarseP2;
   return P->pde == IPMPDE_CONVDIFF ? kCoarseCD : kCoarseGeneric;
+}
+
+// The fused 3D level kernels stage cubes of (2 TC + 1 + 2 nu)^3 (descent) and
+// (TF + 2 nu)^3 nodes (ascent) in static LDS; a sweep count is served when a
+// cube of TC >= 1 (TF >= 2) fits (the launch takes the largest that does).
+static bool p3_fits(size_t el, int nu) {
+  if (nu < 1 || nu > 6) return false;
+  const size_t wd = 3 + 2 * nu, wu = 2 + 2 * nu, wc = wu / 2 + 2;
+  return 4 * el * wd * wd * wd <= 65536 && el * (4 * wu * wu * wu + wc * wc * wc) <= 65536;
 }
 
 // Elements between two reaction-term slots' coarse images: a multiple of 4,
@@ -586,6 +597,7 @@ static int group_select(Group* G, const ipmpde_options& o) {
   G->gen = false;
   G->cd = false;
   G->gen3 = false;
+  G->p3 = false;
   G->any_small = false;
   G->persist = false;
   G->max_cpack = 0;
@@ -655,7 +667,9 @@ static int group_select(Group* G, const ipmpde_options& o) {
       heat_steps(G->probs[i], G->H[i], fp32);
       G->H[i].hsteps = G->probs[i]->hs_d;
     }
-  if (G->dim == 2) {
+  G->p3 = G->dim == 3 && !G->heat && p3_fits(fp32 ? 4 : 8, o.nu_pre) && p3_fits(fp32 ? 4 : 8, o.nu_post);
+  for (int i = 0; i < G->count; ++i) G->p3 = G->p3 && G->probs[i]->pde == IPMPDE_POISSON;
+  if (G->dim == 2 || G->p3) {
     G->outsel = 1;
   } else {
     G->sel_pre = o.nu_pre & 1;
@@ -937,17 +951,78 @@ static void mg_vcycle_2d(Group* G, int transpose, int guard, int scaled, hipStre
   for (int l = G->max_cl - 1; l >= 0; --l) launch_up_level<T>(G, l, transpose, guard, s);
 }
 
+template <typename T, int NU>
+static void launch_down_p3_nu(const Group* G, int l, int scaled, int guard, hipStream_t s) {
+  const int Nc = G->maxN[l + 1];
+#define L_(TC)                                                                                                 \
+  {                                                                                                            \
+    const int nt = div_up(Nc, TC);                                                                             \
+    hipLaunchKernelGGL((k_mg_down_p3<T, NU, TC>), dim3(nt, nt * nt, G->zc), dim3(kBS), 0, s, G->D, l, scaled, \
+                       guard);                                                                                 \
+  }
+  if constexpr (p3_down_lds<T, NU, 4>() <= kStaticLdsMax) L_(4)
+  else if constexpr (p3_down_lds<T, NU, 2>() <= kStaticLdsMax) L_(2)
+  else if constexpr (p3_down_lds<T, NU, 1>() <= kStaticLdsMax) L_(1)
+#undef L_
+}
+
+template <typename T, int NU>
+static void launch_up_p3_nu(const Group* G, int l, int guard, hipStream_t s) {
+  const int N = G->maxN[l];
+#define L_(TF)                                                                                                     \
+  {                                                                                                                \
+    const int nt = div_up(N, TF);                                                                                  \
+    hipLaunchKernelGGL((k_mg_up_p3<T, NU, TF>), dim3(nt, nt * nt, G->zc), dim3(kBS), 0, s, G->D, l, guard);       \
+  }
+  if constexpr (p3_up_lds<T, NU, 8>() <= kStaticLdsMax) L_(8)
+  else if constexpr (p3_up_lds<T, NU, 4>() <= kStaticLdsMax) L_(4)
+  else if constexpr (p3_up_lds<T, NU, 2>() <= kStaticLdsMax) L_(2)
+#undef L_
+}
+
+// 3D finite-difference V-cycle with the fused level kernels (as the 2D one).
+// Output: level 0's x2 (x for instances whose whole hierarchy fits the coarse
+// kernel).
+template <typename T>
+static void mg_vcycle_p3(Group* G, int transpose, int guard, int scaled, hipStream_t s) {
+  const int nu_pre = G->H[0].nu_pre, nu_post = G->H[0].nu_post;
+  for (int l = 0; l < G->max_cl; ++l) {
+    const int sc = l == 0 ? scaled : 0;
+    switch (nu_pre) {
+#define D_(NU) case NU: launch_down_p3_nu<T, NU>(G, l, sc, guard, s); break;
+      D_(1) D_(2) D_(3) D_(4) D_(5) D_(6)
+#undef D_
+    }
+  }
+  launch_coarse<T>(G, transpose, guard, s);
+  for (int l = G->max_cl - 1; l >= 0; --l) {
+    switch (nu_post) {
+#define U_(NU) case NU: launch_up_p3_nu<T, NU>(G, l, guard, s); break;
+      U_(1) U_(2) U_(3) U_(4) U_(5) U_(6)
+#undef U_
+    }
+  }
+}
+
+// One V-cycle of the group's multigrid path.
+template <typename T>
+static void mg_vcycle(Group* G, int transpose, int guard, int scaled, hipStream_t s) {
+  if (G->dim == 2) mg_vcycle_2d<T>(G, transpose, guard, scaled, s);
+  else if (G->p3) mg_vcycle_p3<T>(G, transpose, guard, scaled, s);
+  else mg_vcycle_generic<T>(G, transpose, guard, s);
+}
+
 // One multigrid solve with A + M_hat (transpose: its transpose) from level
 // 0's b: vcycles V-cycles as a k-cycle iteration (the first may take the
-// scaled right-hand side, 2D path).  Output: the level-0 output array.
+// scaled right-hand side: the 2D and fused 3D paths).  Output: the level-0
+// output array.
 template <typename T>
 static void mg_solve(Group* G, int transpose, int guard, int scaled, hipStream_t s) {
   const int k = G->H[0].vcycles;
   for (int j = 1; j <= k; ++j) {
     if (j > 1)
       hipLaunchKernelGGL(k_mg_kc_resid<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, G->outsel, transpose, j - 1, guard);
-    if (G->dim == 2) mg_vcycle_2d<T>(G, transpose, guard, j == 1 ? scaled : 0, s);
-    else mg_vcycle_generic<T>(G, transpose, guard, s);
+    mg_vcycle<T>(G, transpose, guard, j == 1 ? scaled : 0, s);
   }
   if (k > 1) hipLaunchKernelGGL(k_mg_kc_final<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, G->outsel, k, guard);
 }
@@ -1005,7 +1080,7 @@ static void schur_inv(Group* G, int guard, hipStream_t s) {
     heat_schur_inv<T>(G, guard, s);
     return;
   }
-  if (G->dim == 2 && !G->q1) {  // Q1: the middle factor M + Theta_y is a stencil, applied below
+  if ((G->dim == 2 && !G->q1) || G->p3) {  // Q1: the middle factor M + Theta_y is a stencil, applied below
     mg_solve<T>(G, 0, guard, 0, s);
     // instances whose whole hierarchy is in the coarse kernel never run a
     // descent kernel, so their scaled right-hand side is formed here; the

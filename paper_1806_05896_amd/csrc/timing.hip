@@ -81,8 +81,8 @@ static int time_kernel_group(Group* G, const ipmpde_options& o, int kernel, int 
         else hipLaunchKernelGGL(k_minres_k2<double>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, 1, 1);
         break;
       case 3:
-        if (f32) mg_vcycle_2d<float>(G, 0, 0, 0, s);
-        else mg_vcycle_2d<double>(G, 0, 0, 0, s);
+        if (f32) mg_vcycle<float>(G, 0, 0, 0, s);
+        else mg_vcycle<double>(G, 0, 0, 0, s);
         break;
       case 4:
         if (f32) launch_down_level<float>(G, 0, 0, 0, 0, s);

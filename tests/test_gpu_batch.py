@@ -46,6 +46,33 @@ def test_batch_equals_solo(prec):
         p.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_3d_equals_solo(prec):
+    """3D finite-difference problems of different sizes in one batch (the fused cube level
+    kernels for the 31^3 and 63^3 members, the whole hierarchy in the coarse kernel for the
+    15^3 one) give each member its solo result bit for bit."""
+    from paper_1806_05896_amd import Batch, Options, Problem
+    datas = [W.poisson3d_127(seed=1, N=31), W.poisson3d_127(seed=2, N=15), W.poisson3d_127(seed=3, N=63)]
+    print("[batch3d]", prec, [d.N for d in datas], flush=True)
+    opts = [Options(sigma=d.sigma, mg_precision=prec) for d in datas]
+    solo = []
+    for d, o in zip(datas, opts):
+        with Problem(d) as p:
+            rc = p.solve(o)
+            solo.append((rc, p.query("u"), p.stats()))
+    probs = [Problem(d) for d in datas]
+    with Batch(probs) as b:
+        st = b.solve(opts)
+    for k, (p, (rc, u, s)) in enumerate(zip(probs, solo)):
+        ub, sb = p.query("u"), p.stats()
+        print(f"  {k}: N={p.N} rc={rc}/{st[k]} nli={s.nli}/{sb.nli} its={s.krylov_its}/{sb.krylov_its} "
+              f"max|du|={np.abs(ub - u).max():.1e}", flush=True)
+        assert st[k] == rc == 0
+        assert sb.nli == s.nli and sb.krylov_its == s.krylov_its
+        np.testing.assert_array_equal(ub, u)
+        p.close()
+
+
 def test_batch_member_limits_do_not_leak():
     """One member with an IPM iteration limit of 2 stops early (ENOTCONVERGED);
     its batch-mates converge exactly as they would alone."""
