@@ -11,7 +11,9 @@
 // and the residual is b + (sum of the neighbours) / h^2 - d x.  Nodes of the
 // LDS cube outside the grid hold b = d = w = x = 0: the homogeneous Dirichlet
 // condition with no tests in the sweeps.  The cube size is a template
-// parameter (a launch choice); it changes no node's arithmetic.
+// parameter (the launch takes 4^3 coarse nodes per descent cube and 8^3 fine
+// nodes per ascent cube, where they fit the LDS); it changes no node's
+// arithmetic.
 #include "common.h"
 
 namespace ipm {

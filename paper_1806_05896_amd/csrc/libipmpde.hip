@@ -291,12 +291,15 @@ static int coarse_kind(const ipmpde_problem* P) {
   return P->pde == IPMPDE_CONVDIFF ? kCoarseCD : kCoarseGeneric;
 }
 
-// The fused 3D level kernels stage cubes of (2 TC + 1 + 2 nu)^3 (descent) and
-// (TF + 2 nu)^3 nodes (ascent) in static LDS; a sweep count is served when a
-// cube of TC >= 1 (TF >= 2) fits (the launch takes the largest that does).
+// The fused 3D level kernels stage cubes of (2 TC + 1 + 2 nu)^3 (descent,
+// TC = 4 coarse nodes per axis) and (TF + 2 nu)^3 nodes (ascent, TF = 8) in
+// static LDS; a sweep count is served when both fit (FP32: nu <= 3, FP64:
+// nu = 1).  Smaller cubes recompute so much halo that the one-node-per-thread
+// kernels are faster (measured: FP64 with 2^3-node cubes, 2.28 against 2.52
+// solves/s at 127^3), so the other cases take those.
 static bool p3_fits(size_t el, int nu) {
   if (nu < 1 || nu > 6) return false;
-  const size_t wd = 3 + 2 * nu, wu = 2 + 2 * nu, wc = wu / 2 + 2;
+  const size_t wd = 9 + 2 * nu, wu = 8 + 2 * nu, wc = wu / 2 + 2;
   return 4 * el * wd * wd * wd <= 65536 && el * (4 * wu * wu * wu + wc * wc * wc) <= 65536;
 }
 
@@ -960,9 +963,7 @@ static void launch_down_p3_nu(const Group* G, int l, int scaled, int guard, hipS
     hipLaunchKernelGGL((k_mg_down_p3<T, NU, TC>), dim3(nt, nt * nt, G->zc), dim3(kBS), 0, s, G->D, l, scaled, \
                        guard);                                                                                 \
   }
-  if constexpr (p3_down_lds<T, NU, 4>() <= kStaticLdsMax) L_(4)
-  else if constexpr (p3_down_lds<T, NU, 2>() <= kStaticLdsMax) L_(2)
-  else if constexpr (p3_down_lds<T, NU, 1>() <= kStaticLdsMax) L_(1)
+  if constexpr (p3_down_lds<T, NU, 4>() <= kStaticLdsMax) L_(4)  // else never called: p3_fits excludes it
 #undef L_
 }
 
@@ -974,9 +975,7 @@ static void launch_up_p3_nu(const Group* G, int l, int guard, hipStream_t s) {
     const int nt = div_up(N, TF);                                                                                  \
     hipLaunchKernelGGL((k_mg_up_p3<T, NU, TF>), dim3(nt, nt * nt, G->zc), dim3(kBS), 0, s, G->D, l, guard);       \
   }
-  if constexpr (p3_up_lds<T, NU, 8>() <= kStaticLdsMax) L_(8)
-  else if constexpr (p3_up_lds<T, NU, 4>() <= kStaticLdsMax) L_(4)
-  else if constexpr (p3_up_lds<T, NU, 2>() <= kStaticLdsMax) L_(2)
+  if constexpr (p3_up_lds<T, NU, 8>() <= kStaticLdsMax) L_(8)  // else never called: p3_fits excludes it
 #undef L_
 }
 

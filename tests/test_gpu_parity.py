@@ -255,8 +255,9 @@ def test_schur_multigrid_quality(case, prec):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_schur_multigrid_quality_3d_cubes(prec):
-    """The fused 3D level kernels (31^3: one cube descent and ascent above the coarse kernel's
-    15^3) apply S_hat^-1 (Sec. 4.2) as the V-cycle should: against the exact SciPy
+    """The fused 3D level kernels (FP32 31^3: one cube descent and ascent above the coarse
+    kernel's 15^3; FP64 with 2+2 or 3+3 sweeps takes the one-node-per-thread kernels, whose
+    cubes would not fit the LDS) apply S_hat^-1 (Sec. 4.2) as the V-cycle should: against the exact SciPy
     (A + M_hat)^-T (I + Theta_y) (A + M_hat)^-1 at the IPM's starting point, one cycle of
     2+2 sweeps below 0.45 and of 3+3 below 0.35 (the one-node-per-thread kernels they replace
     give 0.426 and 0.322 on this input; a wrong restriction, prolongation or coarse solve lands
