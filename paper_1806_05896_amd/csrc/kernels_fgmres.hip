@@ -32,10 +32,21 @@ __global__ void __launch_bounds__(kBS) k_fg_multidot(const Inst* __restrict__ Dp
   __shared__ double smem[kBS / 64];
   const int k = blockIdx.y;
   const long n4 = 4L * I.n;
-  const double* v = fg_v(I, k);
-  const double* w = fg_v(I, j + 1);
+  const double* __restrict__ v = fg_v(I, k);
+  const double* __restrict__ w = fg_v(I, j + 1);
   double acc[1] = {0.0};
-  for (long i = (long)blockIdx.x * kBS + threadIdx.x; i < n4; i += (long)gridDim.x * kBS) acc[0] += v[i] * w[i];
+  // grid-stride loop, four strides' loads in flight before the (sequential) accumulation
+  const long S = (long)gridDim.x * kBS;
+  long i = (long)blockIdx.x * kBS + threadIdx.x;
+  for (; i + 3 * S < n4; i += 4 * S) {
+    const double v0 = v[i], v1 = v[i + S], v2 = v[i + 2 * S], v3 = v[i + 3 * S];
+    const double w0 = w[i], w1 = w[i + S], w2 = w[i + 2 * S], w3 = w[i + 3 * S];
+    acc[0] += v0 * w0;
+    acc[0] += v1 * w1;
+    acc[0] += v2 * w2;
+    acc[0] += v3 * w3;
+  }
+  for (; i < n4; i += S) acc[0] += v[i] * w[i];
   block_reduce<kSum, 1, kBS>(acc, smem);
   if (threadIdx.x == 0) I.partials[(size_t)k * gridDim.x + blockIdx.x] = acc[0];
 }
@@ -66,8 +77,22 @@ __global__ void __launch_bounds__(kBS) k_fg_orth(const Inst* __restrict__ Dp, in
   const long i = (long)blockIdx.x * kBS + threadIdx.x;
   if (i >= n4) return;
   double* w = fg_v(I, j + 1);
+  const double* __restrict__ V = I.fV;
+  const long stride = 4L * I.n;
   double acc = w[i];
-  for (int k = 0; k <= j; ++k) acc -= C->hpass[k] * fg_v(I, k)[i];
+  // eight basis vectors' loads in flight before the (sequential) updates
+  int k = 0;
+  for (; k + 8 <= j + 1; k += 8) {
+    double vk[8], hk[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      vk[u] = V[(k + u) * stride + i];
+      hk[u] = C->hpass[k + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc -= hk[u] * vk[u];
+  }
+  for (; k <= j; ++k) acc -= C->hpass[k] * V[k * stride + i];
   w[i] = acc;
 }
 
@@ -175,8 +200,22 @@ __global__ void __launch_bounds__(kBS) k_fg_update_x(const Inst* __restrict__ Dp
   const long i = (long)blockIdx.x * kBS + threadIdx.x;
   if (i >= n4) return;
   const int k = C->j;
+  const double* __restrict__ Z = I.fZ;
+  const long stride = 4L * I.n;
   double acc = I.X[i];
-  for (int c = 0; c < k; ++c) acc += C->y[c] * fg_z(I, c)[i];
+  // eight preconditioned vectors' loads in flight before the (sequential) updates
+  int c = 0;
+  for (; c + 8 <= k; c += 8) {
+    double zc[8], yc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      zc[u] = Z[(c + u) * stride + i];
+      yc[u] = C->y[c + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += yc[u] * zc[u];
+  }
+  for (; c < k; ++c) acc += C->y[c] * Z[c * stride + i];
   I.X[i] = acc;
 }
 
