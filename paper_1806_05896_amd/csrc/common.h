@@ -12,6 +12,8 @@ namespace ipm {
 constexpr int kMaxLev = 16;
 // Levels of the widest single-workgroup coarse hierarchy (63, 31, 15, 7, 3, 1).
 constexpr int kCoarseLevels = 6;
+// Width of the 2D Poisson coarse level solved exactly (by its stored inverse).
+constexpr int kCoarseInvN = 7;
 constexpr int kBS = 256;        // threads per block of the elementwise and stencil kernels
 constexpr int kCoarseBS = 1024;  // threads of the single-workgroup coarse-grid kernel
 constexpr int kTicketGroups = 8;   // sub-counters of the grid reduction ticket

@@ -428,6 +428,66 @@ __global__ void __launch_bounds__(kBS) k_coarse_pack(const Inst* __restrict__ Dp
 template __global__ void k_coarse_pack<float>(const Inst*);
 template __global__ void k_coarse_pack<double>(const Inst*);
 
+// Offsets in the coarse image of a hierarchy whose top width is N0 with nl
+// levels: the 7 x 7 level (-1: none) and the end of the levels, where the
+// inverse of that level's operator follows (when there is one).
+__host__ __device__ inline void coarse_p2_inv_offsets(int N0, int nl, int& off7, int& end) {
+  off7 = -1;
+  end = 0;
+  for (int q = 0, N = N0; q < nl; ++q, N = (N - 1) / 2) {
+    if (N == kCoarseInvN) off7 = end;
+    end += coarse_p2_elems(N);
+  }
+}
+
+// The inverse of the 7 x 7 level's operator A + M_hat (the five-point or Q1
+// stencil divided by h^2 plus the reaction term, the image's diagonal d) by
+// Gauss-Jordan elimination in FP64 (symmetric positive definite: no
+// pivoting), symmetrized and stored after the image's levels, once per
+// Newton setup; the coarse V-cycle then solves that level exactly.
+template <typename T>
+__global__ void __launch_bounds__(kBS) k_coarse_inv7(const Inst* __restrict__ Dp) {
+  INST_BEGIN
+  if (!I.coarse_p2) return;
+  constexpr int M = kCoarseInvN, n = M * M, P = M + 2;
+  int off7, end;
+  coarse_p2_inv_offsets(I.lv[I.coarse_lev].N, I.nlev - I.coarse_lev, off7, end);
+  if (off7 < 0) return;
+  T* img = (T*)I.cpack;
+  const T* d = img + off7 + 2 * P * P + n;
+  __shared__ double A[n * n], f[n];
+  const double h = 1.0 / (M + 1);
+  const double off = I.coarse_p2 == 2 ? -1.0 / (3.0 * h * h) : -1.0 / (h * h);
+  const int tid = threadIdx.x;
+  for (int e = tid; e < n * n; e += kBS) {
+    const int r = e / n, c = e - r * n;
+    const int dr1 = r % M - c % M, dr2 = r / M - c / M;
+    const int a1 = dr1 < 0 ? -dr1 : dr1, a2 = dr2 < 0 ? -dr2 : dr2;
+    const bool nb = I.coarse_p2 == 2 ? (a1 <= 1 && a2 <= 1 && r != c) : (a1 + a2 == 1);
+    A[e] = r == c ? (double)d[r] : (nb ? off : 0.0);
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    const double p = A[k * n + k];
+    __syncthreads();
+    for (int j = tid; j < n; j += kBS) A[k * n + j] = j == k ? 1.0 / p : A[k * n + j] / p;
+    for (int i = tid; i < n; i += kBS) f[i] = A[i * n + k];
+    __syncthreads();
+    for (int e = tid; e < n * n; e += kBS) {
+      const int i = e / n, j = e - i * n;
+      if (i != k) A[e] = j == k ? -f[i] * A[k * n + k] : A[e] - f[i] * A[k * n + j];
+    }
+    __syncthreads();
+  }
+  T* inv = img + end;
+  for (int e = tid; e < n * n; e += kBS) {
+    const int i = e / n, j = e - i * n;
+    inv[e] = (T)(0.5 * (A[e] + A[j * n + i]));
+  }
+}
+template __global__ void k_coarse_inv7<float>(const Inst*);
+template __global__ void k_coarse_inv7<double>(const Inst*);
+
 // Loop over the nodes of an N x N level with NT threads (thread t), as P2_FOR.
 #define P2_FOR_T(NN, T_, NT_)                                                        \
   {                                                                                  \
@@ -558,20 +618,39 @@ __device__ __forceinline__ void p2_up(int nu_post, T* lds, const int* LN, const 
 // iterate (padded layout) in LDS.
 template <typename T, int ST = 5>
 __device__ __forceinline__ const T* coarse_p2_cycle(T* lds, const int* LN, const int* LOFF, const T* LIH2, int cl,
-                                                    int L, T om, int nu_pre, int nu_post) {
+                                                    int L, T om, int nu_pre, int nu_post, const T* ainv7 = nullptr) {
   const int tid = threadIdx.x;
   unsigned alt = 0;  // bit l: level l's iterate sits in xb
-  for (int l = cl; l < L - 1; ++l) p2_down<T, kCoarseBS, ST>(nu_pre, lds, LN, LOFF, LIH2, l, tid, om, alt);
-  {
+  // with the inverse of the 7 x 7 level's operator (ainv7, row-major 49 x 49
+  // in LDS) the descent stops there and that level is solved exactly
+  int lx = L - 1;
+  if (ainv7)
+    for (int l = cl; l < L; ++l)
+      if (LN[l] == kCoarseInvN) lx = l;
+  for (int l = cl; l < lx; ++l) p2_down<T, kCoarseBS, ST>(nu_pre, lds, LN, LOFF, LIH2, l, tid, om, alt);
+  if (LN[lx] == kCoarseInvN && ainv7) {
+    constexpr int n = kCoarseInvN * kCoarseInvN, P = kCoarseInvN + 2;
+    // with no descent before it the right-hand side was written by the threads
+    // owning its nodes in the sweeps, not by the rows' threads here
+    if (lx == cl) __syncthreads();
+    T* a = lds + LOFF[lx];
+    const T* b = a + 2 * P * P;
+    if (tid < n) {
+      T acc = 0;
+      for (int c = 0; c < n; ++c) acc += ainv7[tid * n + c] * b[c];
+      a[(tid % kCoarseInvN + 1) + P * (tid / kCoarseInvN + 1)] = acc;
+    }
+    __syncthreads();
+  } else {
     // coarsest grid (one node): exact solve
-    const int l = L - 1, N = LN[l], P = N + 2, n = N * N;
+    const int l = lx, N = LN[l], P = N + 2, n = N * N;
     T* a = lds + LOFF[l];
     const T* b = a + 2 * P * P;
     const T* dinv = b + 2 * n;
     P2_FOR_T(N, tid, kCoarseBS) a[p] = b[i] * dinv[i]; P2_END
     __syncthreads();
   }
-  for (int l = L - 2; l >= cl; --l) p2_up<T, kCoarseBS, ST>(nu_post, lds, LN, LOFF, LIH2, l, tid, om, alt);
+  for (int l = lx - 1; l >= cl; --l) p2_up<T, kCoarseBS, ST>(nu_post, lds, LN, LOFF, LIH2, l, tid, om, alt);
   const int N = LN[cl], P = N + 2;
   return lds + LOFF[cl] + ((alt >> cl) & 1u) * P * P;
 }
@@ -817,8 +896,14 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_p2(const Inst* __restri
     }
   }
   // coarse_p2 2: the Q1 nine-point stiffness
-  const T* a = kind == 2 ? coarse_p2_cycle<T, 9>(lds, LN, LOFF, LIH2, cl, L, (T)omega, nu_pre, nu_post)
-                         : coarse_p2_cycle<T, 5>(lds, LN, LOFF, LIH2, cl, L, (T)omega, nu_pre, nu_post);
+  int off7, end;
+  coarse_p2_inv_offsets(N0, L - cl, off7, end);
+  // copied with the image, which holds it after its levels (the per-time-step
+  // images of the heat equation do not: there the V-cycle runs to one node)
+  const T* ainv7 = off7 >= 0 && elems >= end + kCoarseInvN * kCoarseInvN * kCoarseInvN * kCoarseInvN ? lds + end
+                                                                                                   : nullptr;
+  const T* a = kind == 2 ? coarse_p2_cycle<T, 9>(lds, LN, LOFF, LIH2, cl, L, (T)omega, nu_pre, nu_post, ainv7)
+                         : coarse_p2_cycle<T, 5>(lds, LN, LOFF, LIH2, cl, L, (T)omega, nu_pre, nu_post, ainv7);
   {
     const int N = LN[cl];
     P2_FOR(N) xg[i] = a[p]; P2_END

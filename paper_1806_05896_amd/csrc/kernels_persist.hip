@@ -51,14 +51,14 @@ __device__ __forceinline__ void bsum(double (&v)[K], double* smem, double* bc) {
 // of level 0's iterate area).
 template <typename T>
 __device__ __forceinline__ const T* small_schur(const Inst& I, T* lds, const int* LN, const int* LOFF, const T* LIH2,
-                                                int L) {
+                                                int L, const T* ainv7) {
   const int tid = threadIdx.x, N = LN[0], P = N + 2;
   T* b = lds + LOFF[0] + 2 * P * P;
-  const T* a = coarse_p2_cycle<T, 5>(lds, LN, LOFF, LIH2, 0, L, (T)I.omega, I.nu_pre, I.nu_post);
+  const T* a = coarse_p2_cycle<T, 5>(lds, LN, LOFF, LIH2, 0, L, (T)I.omega, I.nu_pre, I.nu_post, ainv7);
   // the scaled right-hand side of the second solve, as k_mg_scale_ty_small forms it
   P2_FOR(N) b[i] = (T)(1.0 + I.ty[i]) * a[p]; P2_END
   __syncthreads();
-  return coarse_p2_cycle<T, 5>(lds, LN, LOFF, LIH2, 0, L, (T)I.omega, I.nu_pre, I.nu_post);
+  return coarse_p2_cycle<T, 5>(lds, LN, LOFF, LIH2, 0, L, (T)I.omega, I.nu_pre, I.nu_post, ainv7);
 }
 
 template <typename T>
@@ -103,6 +103,17 @@ __global__ void __launch_bounds__(kCoarseBS) k_minres_small(const Inst* __restri
       d[nl + i] = (T)1 / dv;
     }
   }
+  // the inverse of the 7 x 7 level's operator, stored after the levels of the
+  // Newton setup's image
+  int off7, end;
+  coarse_p2_inv_offsets(N0, L, off7, end);
+  const T* ainv7 = nullptr;
+  constexpr int n7 = kCoarseInvN * kCoarseInvN * kCoarseInvN * kCoarseInvN;
+  if (off7 >= 0 && I.cpack_elems >= end + n7) {
+    const T* __restrict__ src = (const T*)I.cpack + end;
+    for (int e = tid; e < n7; e += kCoarseBS) lds[end + e] = src[e];
+    ainv7 = lds + end;
+  }
   __syncthreads();
   T* bmg = lds + LOFF[0] + 2 * P0 * P0;  // level 0's right-hand side (compact layout)
 
@@ -137,7 +148,7 @@ __global__ void __launch_bounds__(kCoarseBS) k_minres_small(const Inst* __restri
     }
     double dot_tmp = acc[0];
     {
-      const T* out = small_schur<T>(I, lds, LN, LOFF, LIH2, L);
+      const T* out = small_schur<T>(I, lds, LN, LOFF, LIH2, L, ainv7);
       double t[1] = {0.0};
       P2_FOR(N0)
         const double z = (double)out[p];
@@ -230,7 +241,7 @@ __global__ void __launch_bounds__(kCoarseBS) k_minres_small(const Inst* __restri
       }
       // multigrid: z_{j+1,p} = S_hat^-1 v_{j+1,p}; K4: the rest of <v, z> and the recurrence
       {
-        const T* out = small_schur<T>(I, lds, LN, LOFF, LIH2, L);
+        const T* out = small_schur<T>(I, lds, LN, LOFF, LIH2, L, ainv7);
         double t4[1] = {0.0};
         P2_FOR(N0)
           const double z = (double)out[p];

@@ -246,10 +246,19 @@ static int coarse_max_N(int dim, int kind) {
   return kind == kCoarseCD ? 31 : kCoarseP2MaxN;
 }
 
+// Elements of the 2D Poisson coarse image after its levels: the inverse of
+// the 7 x 7 level's operator when the hierarchy has that level.
+static size_t coarse_p2_tail(const Level* lv, int nlev, int kind) {
+  if (kind != kCoarseP2) return 0;
+  for (int l = 0; l < nlev; ++l)
+    if (lv[l].N == kCoarseInvN) return (size_t)kCoarseInvN * kCoarseInvN * kCoarseInvN * kCoarseInvN;
+  return 0;
+}
+
 static int pick_coarse(const Level* lv, int nlev, size_t elem, int dim, int kind) {
   const int nmax = coarse_max_N(dim, kind);
   int cl = nlev - 1;
-  size_t need = 0;
+  size_t need = coarse_p2_tail(lv, nlev, kind) * elem;
   for (int l = nlev - 1; l >= 0; --l) {
     need += coarse_level_elems(lv[l], kind) * elem;
     if (need > kCoarseLds || lv[l].N > nmax) break;
@@ -259,7 +268,7 @@ static int pick_coarse(const Level* lv, int nlev, size_t elem, int dim, int kind
 }
 
 static size_t coarse_lds_bytes(const Level* lv, int nlev, int cl, size_t elem, int kind) {
-  size_t need = 0;
+  size_t need = coarse_p2_tail(lv, nlev, kind) * elem;
   for (int l = cl; l < nlev; ++l) need += coarse_level_elems(lv[l], kind) * elem;
   return need;
 }
@@ -379,7 +388,7 @@ static int ensure_mg(ipmpde_problem* P, bool fp32) {
   const int cl = pick_coarse(lv, P->nlev, el, P->dim, coarse_kind(P));
   (fp32 ? P->coarse32 : P->coarse64) = cl;
   if (padded_coarse(P)) {
-    int elems = 0;
+    int elems = (int)coarse_p2_tail(lv, P->nlev, kCoarseP2);
     for (int l = cl; l < P->nlev; ++l) elems += coarse_p2_elems(lv[l].N);
     void*& pk = fp32 ? P->cpack32 : P->cpack64;
     TRY(P->work.alloc(&pk, (size_t)kReactionSlots * cpack_stride(elems) * el));
@@ -1352,6 +1361,14 @@ static int krylov_status(const Group* G, int i) {
 // ---------------------------------------------------------------------------
 // Newton setup and IPM steps (all instances)
 
+// The 2D Poisson coarse LDS image of the current reaction-term slot, with the
+// inverse of its 7 x 7 level's operator.
+template <typename T>
+static void coarse_image(Group* G, hipStream_t s) {
+  hipLaunchKernelGGL(k_coarse_pack<T>, gz(G, G->max_cpack), dim3(kBS), 0, s, G->D);
+  hipLaunchKernelGGL(k_coarse_inv7<T>, dim3(1, 1, G->zc), dim3(kBS), 0, s, G->D);
+}
+
 // P_Pi's extra operators: M_l (slot 1, written at level 0 by the Newton setup)
 // restricted to every level and its coarse image; the coarse image of the
 // zero slot (L alone); back to slot 0.
@@ -1360,9 +1377,9 @@ static void ppi_setup(Group* G, hipStream_t s) {
   mg_select(G, 1, s);
   for (int l = 0; l + 1 < G->max_nlev; ++l)
     hipLaunchKernelGGL(k_restrict_diag<T>, gz(G, G->maxn[l + 1]), dim3(kBS), 0, s, G->D, l);
-  if (G->p2) hipLaunchKernelGGL(k_coarse_pack<T>, gz(G, G->max_cpack), dim3(kBS), 0, s, G->D);
+  if (G->p2) coarse_image<T>(G, s);
   mg_select(G, 2, s);
-  if (G->p2) hipLaunchKernelGGL(k_coarse_pack<T>, gz(G, G->max_cpack), dim3(kBS), 0, s, G->D);
+  if (G->p2) coarse_image<T>(G, s);
   mg_select(G, 0, s);
 }
 
@@ -1408,13 +1425,13 @@ static int newton_setup_group(Group* G, const ipmpde_options& o, hipStream_t s) 
     hipLaunchKernelGGL(k_newton_setup<float>, gz(G, G->max_n), dim3(kBS), 0, s, G->D);
     for (int l = 0; l + 1 < G->max_nlev; ++l)
       hipLaunchKernelGGL(k_restrict_diag<float>, gz(G, G->maxn[l + 1]), dim3(kBS), 0, s, G->D, l);
-    if (G->p2) hipLaunchKernelGGL(k_coarse_pack<float>, gz(G, G->max_cpack), dim3(kBS), 0, s, G->D);
+    if (G->p2) coarse_image<float>(G, s);
     if (o.precond == IPMPDE_PPI) ppi_setup<float>(G, s);
   } else {
     hipLaunchKernelGGL(k_newton_setup<double>, gz(G, G->max_n), dim3(kBS), 0, s, G->D);
     for (int l = 0; l + 1 < G->max_nlev; ++l)
       hipLaunchKernelGGL(k_restrict_diag<double>, gz(G, G->maxn[l + 1]), dim3(kBS), 0, s, G->D, l);
-    if (G->p2) hipLaunchKernelGGL(k_coarse_pack<double>, gz(G, G->max_cpack), dim3(kBS), 0, s, G->D);
+    if (G->p2) coarse_image<double>(G, s);
     if (o.precond == IPMPDE_PPI) ppi_setup<double>(G, s);
   }
   HIP_TRY(hipGetLastError());
