@@ -14,6 +14,8 @@ constexpr int kMaxLev = 16;
 constexpr int kCoarseLevels = 6;
 // Width of the 2D Poisson coarse level solved exactly (by its stored inverse).
 constexpr int kCoarseInvN = 7;
+// Arrays of n per level in the convection-diffusion coarse image.
+constexpr int kCoarseCDArrays = 9;
 constexpr int kBS = 256;        // threads per block of the elementwise and stencil kernels
 constexpr int kCoarseBS = 1024;  // threads of the single-workgroup coarse-grid kernel
 constexpr int kTicketGroups = 8;   // sub-counters of the grid reduction ticket

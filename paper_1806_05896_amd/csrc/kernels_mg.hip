@@ -488,6 +488,52 @@ __global__ void __launch_bounds__(kBS) k_coarse_inv7(const Inst* __restrict__ Dp
 template __global__ void k_coarse_inv7<float>(const Inst*);
 template __global__ void k_coarse_inv7<double>(const Inst*);
 
+// The LDS image of every convection-diffusion instance's coarse levels after
+// a Newton setup (layout of k_mg_coarse_cd, kCoarseCDArrays arrays of n per
+// level): zero iterates and right-hand side, the diagonal with the reaction
+// term cd = op_diag + m, 1/cd and the four upwind neighbour coefficients of
+// the node's row of A (the wind in FP64, rounded to T).
+template <typename T>
+__global__ void __launch_bounds__(kBS) k_coarse_pack_cd(const Inst* __restrict__ Dp) {
+  INST_BEGIN
+  if (I.coarse_p2 || I.pde != 1 || !I.cpack) return;
+  const int k = blockIdx.x * kBS + threadIdx.x;
+  if (k >= I.cpack_elems) return;
+  const int cl = I.coarse_lev;
+  int off = 0, q = -1;
+  for (int l = cl; l < I.nlev; ++l) {
+    const int e = kCoarseCDArrays * I.lv[l].n;
+    if (k < off + e) {
+      q = l;
+      break;
+    }
+    off += e;
+  }
+  T v = 0;
+  if (q >= 0) {
+    const Level& Lv = I.lv[q];
+    const int n = Lv.n, N = Lv.N, r = k - off, a = r / n, i = r - a * n;
+    if (a >= 3) {
+      const int j1 = i % N, j2 = i / N;
+      const double h = Lv.h, ed = I.eps / (h * h), ih = 1.0 / h;
+      double w1, w2;
+      wind((j1 + 1) * h, (j2 + 1) * h, w1, w2);
+      const T cd = (T)(4.0 * ed + (fabs(w1) + fabs(w2)) * ih) + ((const T*)Lv.mh)[i];
+      switch (a) {
+        case 3: v = cd; break;
+        case 4: v = (T)1 / cd; break;
+        case 5: v = (T)(-ed - fmax(w1, 0.0) * ih); break;
+        case 6: v = (T)(-ed + fmin(w1, 0.0) * ih); break;
+        case 7: v = (T)(-ed - fmax(w2, 0.0) * ih); break;
+        default: v = (T)(-ed + fmin(w2, 0.0) * ih); break;
+      }
+    }
+  }
+  ((T*)I.cpack)[k] = v;
+}
+template __global__ void k_coarse_pack_cd<float>(const Inst*);
+template __global__ void k_coarse_pack_cd<double>(const Inst*);
+
 // Loop over the nodes of an N x N level with NT threads (thread t), as P2_FOR.
 #define P2_FOR_T(NN, T_, NT_)                                                        \
   {                                                                                  \
@@ -663,7 +709,6 @@ __device__ __forceinline__ const T* coarse_p2_cycle(T* lds, const int* LN, const
 // neighbours' coefficients towards this node (the east neighbour's west
 // coefficient, ...).  LDS per level: x, x2, b, cd, 1/cd, cW, cE, cS, cN
 // (kCoarseCDArrays arrays of n).
-constexpr int kCoarseCDArrays = 9;
 // Levels of the widest coarse hierarchy (63, 31, 15, 7, 3, 1).
 constexpr int kCoarseP2Levels = kCoarseLevels;
 
@@ -741,76 +786,76 @@ __device__ __forceinline__ void cd_up(T* lds, const int* LN, const int* LOFF, in
 
 template <typename T>
 __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_cd(const Inst* __restrict__ Dp, int transpose, int guard) {
-  INST_BEGIN
-  if (I.coarse_p2 || I.pde != 1 || mg_skip(I, guard)) return;
+  const Inst& I = Dp[blockIdx.z];
+  int go = I.active;
+  const int p2 = I.coarse_p2, pde = I.pde, cl = I.coarse_lev, L = I.nlev, N0 = I.cN0, nu_pre = I.nu_pre,
+            nu_post = I.nu_post, elems = I.cpack_elems;
+  const double omega = I.omega;
+  const KrylovCtrl* ctrl = I.ctrl;
+  const T* __restrict__ bg = (const T*)I.cb;
+  T* __restrict__ xg = (T*)I.cx;
+  const T* __restrict__ img = (const T*)I.cpack;
+  IPM_LOAD_TOGETHER(go, p2, pde, cl, L, N0, nu_pre, nu_post, elems, omega, ctrl, bg, xg, img);
+  if (!go || p2 || pde != 1) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ int LN[kMaxLev], LOFF[kMaxLev];
   T* lds = (T*)lds_raw;
-  const int cl = I.coarse_lev, L = I.nlev;
   const bool tr = transpose != 0;
   const int tid = threadIdx.x;
-  const T om = (T)I.omega;
-  const double eps = I.eps;
-  if (tid == 0) {
+  const T om = (T)omega;
+  // Staging, all global loads in flight together with the stop flag: the
+  // levels' image (zero iterates and right-hand sides, the upwind
+  // coefficients, d and 1/d, built by k_coarse_pack_cd at the Newton setup;
+  // layout x | x2 | b | cd | 1/cd | cW | cE | cS | cN per level) in 16-byte
+  // pieces, and the top level's right-hand side at the node this thread owns
+  // in the sweeps (the widest level is at most 31 x 31: one node per thread).
+  const int f_stop = ctrl->stop, f_want = ctrl->want_restart;
+  constexpr int VE = 16 / (int)sizeof(T);
+  constexpr int MAXV = (int)((150 * 1024 / 16 + kCoarseBS - 1) / kCoarseBS);
+  typedef unsigned int piece_t __attribute__((ext_vector_type(4)));
+  const bool vec = ((uintptr_t)img & 15) == 0;
+  const int nvec = vec ? elems / VE : 0;
+  piece_t rv[MAXV];
+#pragma unroll
+  for (int j = 0; j < MAXV; ++j) {
+    const int v = tid + j * kCoarseBS;
+    if (v < nvec) rv[j] = reinterpret_cast<const piece_t*>(img)[v];
+  }
+  const int sh0 = 31 - __builtin_clz(N0 + 1), j1 = tid & ((1 << sh0) - 1), j2 = tid >> sh0;
+  const bool own = j1 < N0 && j2 < N0;
+  const T breg = own ? bg[j1 + N0 * j2] : (T)0;
+  // uniform over the workgroup, before any LDS or global store
+  if ((guard == 1 && f_stop) || (guard == 2 && !f_want)) return;
+#pragma unroll
+  for (int j = 0; j < MAXV; ++j) {
+    const int v = tid + j * kCoarseBS;
+    if (v < nvec) reinterpret_cast<piece_t*>(lds)[v] = rv[j];
+  }
+  for (int k = nvec * VE + tid; k < elems; k += kCoarseBS) lds[k] = img[k];  // the tail (all of it if unaligned)
+  if (tid < kCoarseP2Levels && cl + tid < L) {
+    const int q = tid;
     int off = 0;
-    for (int l = cl; l < L; ++l) {
-      LN[l] = I.lv[l].N;
-      LOFF[l] = off;
-      off += kCoarseCDArrays * I.lv[l].n;
+    for (int r = 0; r < q; ++r) {
+      const int Nr = ((N0 + 1) >> r) - 1;
+      off += kCoarseCDArrays * Nr * Nr;
     }
+    LN[cl + q] = ((N0 + 1) >> q) - 1;
+    LOFF[cl + q] = off;
   }
   __syncthreads();
-  // stage: the top level's b, and per level the coefficients (layout
-  // x | x2 | b | cd | 1/cd | cW | cE | cS | cN).  The widest level is at
-  // most 31 x 31, so each thread holds at most one node of every level: its
-  // global loads (b and every level's m) are issued together first.
-  const int N0 = I.lv[cl].N;
-  T mreg[kCoarseP2Levels], breg;
-  {
-    const int sh = 31 - __builtin_clz(N0 + 1), j1 = tid & ((1 << sh) - 1), j2 = tid >> sh;
-    breg = (j1 < N0 && j2 < N0) ? ((const T*)I.lv[cl].b)[j1 + N0 * j2] : (T)0;
-  }
-#pragma unroll
-  for (int q = 0; q < kCoarseP2Levels; ++q) {
-    const int N = ((N0 + 1) >> q) - 1;
-    const int sh = 31 - __builtin_clz(N + 1), j1 = tid & ((1 << sh) - 1), j2 = tid >> sh;
-    mreg[q] = (cl + q < L && j1 < N && j2 < N) ? ((const T*)I.lv[cl + q].mh)[j1 + N * j2] : (T)0;
-  }
-#pragma unroll
-  for (int q = 0; q < kCoarseP2Levels; ++q) {
-    if (cl + q < L) {
-      const int N = ((N0 + 1) >> q) - 1, n = N * N;
-      const int sh = 31 - __builtin_clz(N + 1), j1 = tid & ((1 << sh) - 1), j2 = tid >> sh;
-      if (j1 < N && j2 < N) {
-        const int i = j1 + N * j2;
-        const double h = I.lv[cl + q].h, ed = eps / (h * h), ih = 1.0 / h;
-        double w1, w2;
-        wind((j1 + 1) * h, (j2 + 1) * h, w1, w2);
-        T* base = lds + LOFF[cl + q];
-        T* cf = base + 3 * n;
-        const T cd = (T)(4.0 * ed + (fabs(w1) + fabs(w2)) * ih) + mreg[q];
-        cf[i] = cd;
-        cf[n + i] = (T)1 / cd;
-        cf[2 * n + i] = (T)(-ed - fmax(w1, 0.0) * ih);
-        cf[3 * n + i] = (T)(-ed + fmin(w1, 0.0) * ih);
-        cf[4 * n + i] = (T)(-ed - fmax(w2, 0.0) * ih);
-        cf[5 * n + i] = (T)(-ed + fmin(w2, 0.0) * ih);
-        if (q == 0) base[2 * n + i] = breg;
-      }
-    }
-  }
-  __syncthreads();
+  // the top level's right-hand side over the image's zeros, each node by the
+  // thread that owns it in the sweeps (the only thread that reads it back)
+  if (own) lds[2 * N0 * N0 + j1 + N0 * j2] = breg;
   unsigned alt = 0;  // bit l: level l's iterate sits in x2
-  for (int l = cl; l < L - 1; ++l) cd_down<T, kCoarseBS>(lds, LN, LOFF, l, tid, om, I.nu_pre, tr, alt);
+  for (int l = cl; l < L - 1; ++l) cd_down<T, kCoarseBS>(lds, LN, LOFF, l, tid, om, nu_pre, tr, alt);
   {
     const int N = LN[L - 1], n = N * N;
     T* X = lds + LOFF[L - 1];
     P2_FOR(N) X[i] = X[2 * n + i] * X[4 * n + i]; P2_END
     __syncthreads();
   }
-  for (int l = L - 2; l >= cl; --l) cd_up<T, kCoarseBS>(lds, LN, LOFF, l, tid, om, I.nu_post, tr, alt);
+  for (int l = L - 2; l >= cl; --l) cd_up<T, kCoarseBS>(lds, LN, LOFF, l, tid, om, nu_post, tr, alt);
   const int N = LN[cl];
-  T* xg = (T*)I.lv[cl].x;
   const T* xs = lds + LOFF[cl] + ((alt >> cl) & 1u) * N * N;
   P2_FOR(N) xg[i] = xs[i]; P2_END
 }
@@ -1203,18 +1248,25 @@ __device__ __forceinline__ T jacobi_lds(const T* __restrict__ xa, const T* __res
 template <typename T, int NU>
 __global__ void __launch_bounds__(kBS) k_mg_down2d(const Inst* __restrict__ Dp, int l, int scaled, int transpose,
                                                    int guard) {
-  INST_BEGIN
-  if (I.coarse_p2 || l >= I.coarse_lev || mg_skip(I, guard)) return;
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  const Level& F = I.lv[l];
-  const Level& C = I.lv[l + 1];
+  const Inst& I = Dp[blockIdx.z];
+  int go = I.active;
+  const int p2 = I.coarse_p2, cl = I.coarse_lev, pde = I.pde;
+  const KrylovCtrl* ctrl = I.ctrl;
+  const int N = I.lv[l].N, Nc = I.lv[l + 1].N;
+  const double h = I.lv[l].h, eps = I.eps, om = I.omega;
   // scaled (level 0 only): the right-hand side is (1 + Theta_y) times the
   // first solve's output (level 0's x2)
-  const T* __restrict__ bsrc = (const T*)(scaled ? F.x2 : F.b);
+  const T* __restrict__ bsrc = (const T*)(scaled ? I.lv[l].x2 : I.lv[l].b);
   const double* __restrict__ ty = scaled ? I.ty : nullptr;
-  T* __restrict__ xout = (T*)F.x;
-  if ((int)(blockIdx.x * kTC) >= C.N || (int)(blockIdx.y * kTC) >= C.N) return;
-  const int N = F.N, Nc = C.N;
+  const double* __restrict__ obs = I.obs;
+  const T* __restrict__ mh = (const T*)I.lv[l].mh;
+  T* __restrict__ xout = (T*)I.lv[l].x;
+  T* __restrict__ bfine = (T*)I.lv[l].b;
+  T* __restrict__ bcoarse = (T*)I.lv[l + 1].b;
+  IPM_LOAD_TOGETHER(go, p2, cl, pde, ctrl, N, Nc, h, eps, om, bsrc, ty, obs, mh, xout, bfine, bcoarse);
+  if (!go || p2 || l >= cl) return;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  if ((int)(blockIdx.x * kTC) >= Nc || (int)(blockIdx.y * kTC) >= Nc) return;
   constexpr int nu = NU;
   constexpr int W = down_width(NU);
   T* bs = (T*)lds_raw;
@@ -1223,30 +1275,32 @@ __global__ void __launch_bounds__(kBS) k_mg_down2d(const Inst* __restrict__ Dp, 
   T* xb = xa + W * W;
   const int J1 = blockIdx.x * kTC, J2 = blockIdx.y * kTC;
   const int o1 = 2 * J1 - nu, o2 = 2 * J2 - nu;  // global fine coords of LDS (0, 0)
-  const T* __restrict__ mh = (const T*)F.mh;
-  const double h = F.h, eps = I.eps, om = I.omega;
-  const int pde = I.pde;
   const bool tr = transpose != 0;
   const int tid = threadIdx.x;
+  // the stop flag is requested with the tile's data and tested before the
+  // first global store (the staging writes LDS only)
+  const int f_stop = ctrl->stop, f_want = ctrl->want_restart;
   for (int k = tid; k < W * W; k += kBS) {
     const int g1 = o1 + k % W, g2 = o2 + k / W;
     T bv = 0, mv = 0;
     if (g1 >= 0 && g1 < N && g2 >= 0 && g2 < N) {
       const int gi = g1 + N * g2;
       bv = bsrc[gi];
-      if (ty) bv = (T)(obs_w(I, gi) + ty[gi]) * bv;
+      if (ty) bv = (T)((obs ? obs[gi] : 1.0) + ty[gi]) * bv;
       mv = mh[gi];
     }
     bs[k] = bv;
     ms[k] = mv;
   }
+  // uniform over the workgroup
+  if ((guard == 1 && f_stop) || (guard == 2 && !f_want)) return;
   __syncthreads();
   if (ty) {
     // keep the scaled right-hand side for the ascent (the tile's own fine nodes)
     for (int k = tid; k < 4 * kTC * kTC; k += kBS) {
       const int q1 = nu + k % (2 * kTC), q2 = nu + k / (2 * kTC);
       const int g1 = o1 + q1, g2 = o2 + q2;
-      if (g1 < N && g2 < N) ((T*)F.b)[g1 + N * g2] = bs[q1 + W * q2];
+      if (g1 < N && g2 < N) bfine[g1 + N * g2] = bs[q1 + W * q2];
     }
   }
   // first sweep from zero on the whole region
@@ -1303,7 +1357,7 @@ __global__ void __launch_bounds__(kBS) k_mg_down2d(const Inst* __restrict__ Dp, 
       const int li = q1 + W * q2;
       const T v = (T)0.25 * c[li] + (T)0.125 * (c[li - 1] + c[li + 1] + c[li - W] + c[li + W]) +
                   (T)0.0625 * (c[li - 1 - W] + c[li + 1 - W] + c[li - 1 + W] + c[li + 1 + W]);
-      ((T*)C.b)[c1 + Nc * c2] = v;
+      bcoarse[c1 + Nc * c2] = v;
     }
   }
 }
@@ -1312,15 +1366,24 @@ __global__ void __launch_bounds__(kBS) k_mg_down2d(const Inst* __restrict__ Dp, 
 // tile of TF x TF fine nodes (halo nu in LDS).
 template <typename T, int NU>
 __global__ void __launch_bounds__(kBS) k_mg_up2d(const Inst* __restrict__ Dp, int l, int transpose, int guard) {
-  INST_BEGIN
-  if (I.coarse_p2 || l >= I.coarse_lev || mg_skip(I, guard)) return;
+  const Inst& I = Dp[blockIdx.z];
+  int go = I.active;
+  const int p2 = I.coarse_p2, cl = I.coarse_lev, pde = I.pde;
+  const KrylovCtrl* ctrl = I.ctrl;
+  const int N = I.lv[l].N, Nc = I.lv[l + 1].N;
+  const double h = I.lv[l].h, eps = I.eps, om = I.omega;
+  const void* xc1 = I.lv[l + 1].x;
+  const void* xc2 = I.lv[l + 1].x2;
+  const T* __restrict__ xpre = (const T*)I.lv[l].x;
+  const T* __restrict__ mh = (const T*)I.lv[l].mh;
+  const T* __restrict__ b = (const T*)I.lv[l].b;
+  T* __restrict__ xout = (T*)I.lv[l].x2;
+  IPM_LOAD_TOGETHER(go, p2, cl, pde, ctrl, N, Nc, h, eps, om, xc1, xc2, xpre, mh, b, xout);
+  if (!go || p2 || l >= cl) return;
+  // the coarse iterate: the coarse kernel's output at the coarsest level here
+  const T* __restrict__ xc = (const T*)(l + 1 == cl ? xc1 : xc2);
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  const Level& F = I.lv[l];
-  const T* __restrict__ xpre = (const T*)F.x;
-  const T* __restrict__ xc = (const T*)(l + 1 == I.coarse_lev ? I.lv[l + 1].x : I.lv[l + 1].x2);
-  T* __restrict__ xout = (T*)F.x2;
-  if ((int)(blockIdx.x * kTF) >= F.N || (int)(blockIdx.y * kTF) >= F.N) return;
-  const int N = F.N, Nc = I.lv[l + 1].N;
+  if ((int)(blockIdx.x * kTF) >= N || (int)(blockIdx.y * kTF) >= N) return;
   constexpr int nu = NU;
   constexpr int W = up_width(NU);
   T* bs = (T*)lds_raw;
@@ -1328,12 +1391,9 @@ __global__ void __launch_bounds__(kBS) k_mg_up2d(const Inst* __restrict__ Dp, in
   T* xa = ms + W * W;
   T* xb = xa + W * W;
   const int o1 = blockIdx.x * kTF - nu, o2 = blockIdx.y * kTF - nu;
-  const T* __restrict__ mh = (const T*)F.mh;
-  const T* __restrict__ b = (const T*)F.b;
-  const double h = F.h, eps = I.eps, om = I.omega;
-  const int pde = I.pde;
   const bool tr = transpose != 0;
   const int tid = threadIdx.x;
+  const int f_stop = ctrl->stop, f_want = ctrl->want_restart;
   for (int k = tid; k < W * W; k += kBS) {
     const int g1 = o1 + k % W, g2 = o2 + k / W;
     T bv = 0, mv = 0, xv = 0;
@@ -1347,6 +1407,8 @@ __global__ void __launch_bounds__(kBS) k_mg_up2d(const Inst* __restrict__ Dp, in
     ms[k] = mv;
     xa[k] = xv;
   }
+  // uniform over the workgroup
+  if ((guard == 1 && f_stop) || (guard == 2 && !f_want)) return;
   __syncthreads();
   T* a = xa;
   T* c = xb;

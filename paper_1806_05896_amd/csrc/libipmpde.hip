@@ -387,9 +387,15 @@ static int ensure_mg(ipmpde_problem* P, bool fp32) {
   for (void*& a : (fp32 ? P->kc32 : P->kc64)) TRY(P->work.alloc(&a, (size_t)lv[0].n * el));
   const int cl = pick_coarse(lv, P->nlev, el, P->dim, coarse_kind(P));
   (fp32 ? P->coarse32 : P->coarse64) = cl;
-  if (padded_coarse(P)) {
-    int elems = (int)coarse_p2_tail(lv, P->nlev, kCoarseP2);
-    for (int l = cl; l < P->nlev; ++l) elems += coarse_p2_elems(lv[l].N);
+  if (padded_coarse(P) || coarse_kind(P) == kCoarseCD) {
+    // the coarse kernel's LDS image per reaction-term slot
+    int elems = 0;
+    if (padded_coarse(P)) {
+      elems = (int)coarse_p2_tail(lv, P->nlev, kCoarseP2);
+      for (int l = cl; l < P->nlev; ++l) elems += coarse_p2_elems(lv[l].N);
+    } else {
+      for (int l = cl; l < P->nlev; ++l) elems += (int)coarse_level_elems(lv[l], kCoarseCD);
+    }
     void*& pk = fp32 ? P->cpack32 : P->cpack64;
     TRY(P->work.alloc(&pk, (size_t)kReactionSlots * cpack_stride(elems) * el));
     (fp32 ? P->cpack_elems32 : P->cpack_elems64) = elems;
@@ -1361,12 +1367,15 @@ static int krylov_status(const Group* G, int i) {
 // ---------------------------------------------------------------------------
 // Newton setup and IPM steps (all instances)
 
-// The 2D Poisson coarse LDS image of the current reaction-term slot, with the
-// inverse of its 7 x 7 level's operator.
+// The coarse LDS images of the current reaction-term slot: 2D Poisson (with
+// the inverse of its 7 x 7 level's operator) and convection-diffusion.
 template <typename T>
 static void coarse_image(Group* G, hipStream_t s) {
-  hipLaunchKernelGGL(k_coarse_pack<T>, gz(G, G->max_cpack), dim3(kBS), 0, s, G->D);
-  hipLaunchKernelGGL(k_coarse_inv7<T>, dim3(1, 1, G->zc), dim3(kBS), 0, s, G->D);
+  if (G->p2) {
+    hipLaunchKernelGGL(k_coarse_pack<T>, gz(G, G->max_cpack), dim3(kBS), 0, s, G->D);
+    hipLaunchKernelGGL(k_coarse_inv7<T>, dim3(1, 1, G->zc), dim3(kBS), 0, s, G->D);
+  }
+  if (G->cd) hipLaunchKernelGGL(k_coarse_pack_cd<T>, gz(G, G->max_cpack), dim3(kBS), 0, s, G->D);
 }
 
 // P_Pi's extra operators: M_l (slot 1, written at level 0 by the Newton setup)
@@ -1377,9 +1386,9 @@ static void ppi_setup(Group* G, hipStream_t s) {
   mg_select(G, 1, s);
   for (int l = 0; l + 1 < G->max_nlev; ++l)
     hipLaunchKernelGGL(k_restrict_diag<T>, gz(G, G->maxn[l + 1]), dim3(kBS), 0, s, G->D, l);
-  if (G->p2) coarse_image<T>(G, s);
+  if (G->p2 || G->cd) coarse_image<T>(G, s);
   mg_select(G, 2, s);
-  if (G->p2) coarse_image<T>(G, s);
+  if (G->p2 || G->cd) coarse_image<T>(G, s);
   mg_select(G, 0, s);
 }
 
@@ -1425,13 +1434,13 @@ static int newton_setup_group(Group* G, const ipmpde_options& o, hipStream_t s) 
     hipLaunchKernelGGL(k_newton_setup<float>, gz(G, G->max_n), dim3(kBS), 0, s, G->D);
     for (int l = 0; l + 1 < G->max_nlev; ++l)
       hipLaunchKernelGGL(k_restrict_diag<float>, gz(G, G->maxn[l + 1]), dim3(kBS), 0, s, G->D, l);
-    if (G->p2) coarse_image<float>(G, s);
+    if (G->p2 || G->cd) coarse_image<float>(G, s);
     if (o.precond == IPMPDE_PPI) ppi_setup<float>(G, s);
   } else {
     hipLaunchKernelGGL(k_newton_setup<double>, gz(G, G->max_n), dim3(kBS), 0, s, G->D);
     for (int l = 0; l + 1 < G->max_nlev; ++l)
       hipLaunchKernelGGL(k_restrict_diag<double>, gz(G, G->maxn[l + 1]), dim3(kBS), 0, s, G->D, l);
-    if (G->p2) coarse_image<double>(G, s);
+    if (G->p2 || G->cd) coarse_image<double>(G, s);
     if (o.precond == IPMPDE_PPI) ppi_setup<double>(G, s);
   }
   HIP_TRY(hipGetLastError());
