@@ -29,17 +29,20 @@ constexpr size_t p2_up_lds() {
 }
 constexpr size_t kStaticLdsMax = 65536;
 
-// Tile of this workgroup.  The tiles of a launch are dispatched round-robin
-// over the 8 XCDs; when an instance has a multiple of 8 tiles, XCD x takes
-// the x-th contiguous eighth of them (a band of tile rows), so the halo rows
-// a tile shares with the tiles above and below are mostly in the same L2.
-// The order of the tiles changes no node's arithmetic.
-__device__ __forceinline__ void xcd_tile(int nx, int ny, int& tx, int& ty) {
-  const int nt = nx * ny;
-  int t = blockIdx.x + nx * blockIdx.y;
-  if ((nt & 7) == 0) t = (t & 7) * (nt >> 3) + (t >> 3);
-  ty = t / nx;
-  tx = t - ty * nx;
+// Tiles of this workgroup: a run of tpw consecutive tiles (row-major over the
+// nt x nt tiles of the level) starting at tile w tpw, w the workgroup index.
+// The workgroups of a launch are dispatched round-robin over the 8 XCDs;
+// when their count is a multiple of 8, XCD x takes the x-th contiguous eighth
+// of them (a band of tile rows), so the halo rows a tile shares with the
+// tiles above and below are mostly in the same L2, and consecutive tiles of a
+// run share their halo columns.  While a tile is smoothed in LDS the next
+// tile's data are already on their way into registers.  The order of the
+// tiles changes no node's arithmetic.
+__device__ __forceinline__ void tile_run(int nwg, int tpw, int ntiles, int& t0, int& t1) {
+  int w = blockIdx.x;
+  if ((nwg & 7) == 0) w = (w & 7) * (nwg >> 3) + (w >> 3);
+  t0 = w * tpw;
+  t1 = t0 + tpw < ntiles ? t0 + tpw : ntiles;
 }
 
 // Neighbour sum of LDS node li (row pitch W) scaled by s, for stencil ST.
@@ -71,7 +74,8 @@ __device__ __forceinline__ float omega_over<float>(float om, float d) { return o
 // x2 (the first solve's output); it is also stored as level 0's b for the
 // ascent.
 template <typename T, int NU, int TC, int ST = 5>
-__global__ void __launch_bounds__(kBS) k_mg_down_p2(const Inst* __restrict__ Dp, int l, int scaled, int guard) {
+__global__ void __launch_bounds__(kBS) k_mg_down_p2(const Inst* __restrict__ Dp, int l, int scaled, int guard, int nt,
+                                                    int tpw) {
   const Inst& I = Dp[blockIdx.z];
   int go = I.active;
   const int kind = I.coarse_p2, cl = I.coarse_lev;
@@ -85,89 +89,120 @@ __global__ void __launch_bounds__(kBS) k_mg_down_p2(const Inst* __restrict__ Dp,
   T* __restrict__ bcoarse = (T*)I.lv[l + 1].b;
   const double* __restrict__ tyv = scaled ? I.ty : nullptr;
   const double* __restrict__ obs = I.obs;
-  const int gx = gridDim.x, gy = gridDim.y;
-  IPM_LOAD_TOGETHER(go, kind, cl, ctrl, N, Nc, h, omega, bsrc, mh, xfine, bfine, bcoarse, tyv, obs, gx, gy);
+  const int gx = gridDim.x;
+  IPM_LOAD_TOGETHER(go, kind, cl, ctrl, N, Nc, h, omega, bsrc, mh, xfine, bfine, bcoarse, tyv, obs, gx);
   if (!go || kind != (ST == 5 ? 1 : 2) || l >= cl) return;
-  int tx, ty;
-  xcd_tile(gx, gy, tx, ty);
-  const int J1 = tx * TC, J2 = ty * TC;
-  if (J1 >= Nc || J2 >= Nc) return;
+  int t0, t1;
+  tile_run(gx, tpw, nt * nt, t0, t1);
+  if (t0 >= t1) return;
   constexpr int W = p2_down_width(NU, TC);
+  constexpr int R = (W * W + kBS - 1) / kBS;  // staged nodes per thread
   __shared__ T bs[W * W], ds[W * W], xa[W * W], xb[W * W];
-  const int o1 = 2 * J1 - NU, o2 = 2 * J2 - NU;  // fine coordinates of LDS (0, 0)
   const T ih2 = p2l_scale<T, ST>(h), dg = p2l_diag<T, ST>(h);
   const T om = (T)omega, om1 = (T)1 - om;
   const int tid = threadIdx.x;
-  // the stop flag is requested with the tile's data and tested before the
-  // first global store (the staging writes LDS only)
+  // the stop flag is requested with the first tile's data and tested before
+  // the first global store (the staging writes LDS only)
   const int f_stop = ctrl->stop, f_want = ctrl->want_restart;
-  for (int k = tid; k < W * W; k += kBS) {
-    const int q2 = k / W, q1 = k - q2 * W;
-    const int g1 = o1 + q1, g2 = o2 + q2;
-    T bv = 0, dv = 0, wv = 0;
-    if ((unsigned)g1 < (unsigned)N && (unsigned)g2 < (unsigned)N) {
-      const int gi = g1 + N * g2;
-      bv = bsrc[gi];
-      if (tyv) bv = (T)((obs ? obs[gi] : 1.0) + tyv[gi]) * bv;
-      dv = dg + mh[gi];
-      wv = omega_over<T>(om, dv);
+  // the tile's right-hand side (and Theta_y, O when scaled) and M_hat in registers
+  T rb[R], rm[R];
+  double rt[R], ro[R];
+  auto fetch = [&](int t) {
+    const int o1 = 2 * (t % nt) * TC - NU, o2 = 2 * (t / nt) * TC - NU;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int k = tid + r * kBS;
+      const int q2 = k / W, q1 = k - q2 * W;
+      const int g1 = o1 + q1, g2 = o2 + q2;
+      if (k < W * W && (unsigned)g1 < (unsigned)N && (unsigned)g2 < (unsigned)N) {
+        const int gi = g1 + N * g2;
+        rb[r] = bsrc[gi];
+        rm[r] = mh[gi];
+        if (tyv) {
+          rt[r] = tyv[gi];
+          ro[r] = obs ? obs[gi] : 1.0;
+        }
+      }
     }
-    bs[k] = bv;
-    ds[k] = dv;
-    xa[k] = wv * bv;
-  }
+  };
+  fetch(t0);
   // uniform over the workgroup
   if ((guard == 1 && f_stop) || (guard == 2 && !f_want)) return;
-  __syncthreads();
-  if (tyv) {
-    T* __restrict__ bout = bfine;
-    for (int k = tid; k < 4 * TC * TC; k += kBS) {
-      const int r2 = k / (2 * TC), r1 = k - r2 * (2 * TC);
-      const int g1 = 2 * J1 + r1, g2 = 2 * J2 + r2;
-      if (g1 < N && g2 < N) bout[g1 + N * g2] = bs[(NU + r1) + W * (NU + r2)];
-    }
-  }
-  T* a = xa;
-  T* c = xb;
+  for (int t = t0; t < t1; ++t) {
+    const int J1 = (t % nt) * TC, J2 = (t / nt) * TC;
+    const bool live = J1 < Nc && J2 < Nc;  // uniform: the tile lies in this instance's grid
+    if (live) {
+      const int o1 = 2 * J1 - NU, o2 = 2 * J2 - NU;  // fine coordinates of LDS (0, 0)
 #pragma unroll
-  for (int s = 1; s < NU; ++s) {
-    const int w = W - 2 * s;  // the region shrinks by one node per sweep
-    for (int k = tid; k < w * w; k += kBS) {
-      const int r2 = k / w, r1 = k - r2 * w;
-      const int li = (r1 + s) + W * (r2 + s);
-      const T d = ds[li];
-      const T wv = d > (T)0 ? omega_over<T>(om, d) : (T)0;
-      c[li] = om1 * a[li] + wv * (bs[li] + p2l_nb<T, ST>(a, li, W, ih2));
+      for (int r = 0; r < R; ++r) {
+        const int k = tid + r * kBS;
+        if (k < W * W) {
+          const int q2 = k / W, q1 = k - q2 * W;
+          const int g1 = o1 + q1, g2 = o2 + q2;
+          T bv = 0, dv = 0, wv = 0;
+          if ((unsigned)g1 < (unsigned)N && (unsigned)g2 < (unsigned)N) {
+            bv = rb[r];
+            if (tyv) bv = (T)(ro[r] + rt[r]) * bv;
+            dv = dg + rm[r];
+            wv = omega_over<T>(om, dv);
+          }
+          bs[k] = bv;
+          ds[k] = dv;
+          xa[k] = wv * bv;
+        }
+      }
     }
     __syncthreads();
-    T* t = a; a = c; c = t;
-  }
-  {
-    T* __restrict__ xout = xfine;
-    for (int k = tid; k < 4 * TC * TC; k += kBS) {
-      const int r2 = k / (2 * TC), r1 = k - r2 * (2 * TC);
-      const int g1 = 2 * J1 + r1, g2 = 2 * J2 + r2;
-      if (g1 < N && g2 < N) xout[g1 + N * g2] = a[(NU + r1) + W * (NU + r2)];
+    if (t + 1 < t1) fetch(t + 1);
+    if (live) {
+      if (tyv) {
+        for (int k = tid; k < 4 * TC * TC; k += kBS) {
+          const int r2 = k / (2 * TC), r1 = k - r2 * (2 * TC);
+          const int g1 = 2 * J1 + r1, g2 = 2 * J2 + r2;
+          if (g1 < N && g2 < N) bfine[g1 + N * g2] = bs[(NU + r1) + W * (NU + r2)];
+        }
+      }
+      T* a = xa;
+      T* c = xb;
+#pragma unroll
+      for (int s = 1; s < NU; ++s) {
+        const int w = W - 2 * s;  // the region shrinks by one node per sweep
+        for (int k = tid; k < w * w; k += kBS) {
+          const int r2 = k / w, r1 = k - r2 * w;
+          const int li = (r1 + s) + W * (r2 + s);
+          const T d = ds[li];
+          const T wv = d > (T)0 ? omega_over<T>(om, d) : (T)0;
+          c[li] = om1 * a[li] + wv * (bs[li] + p2l_nb<T, ST>(a, li, W, ih2));
+        }
+        __syncthreads();
+        T* tmp = a; a = c; c = tmp;
+      }
+      for (int k = tid; k < 4 * TC * TC; k += kBS) {
+        const int r2 = k / (2 * TC), r1 = k - r2 * (2 * TC);
+        const int g1 = 2 * J1 + r1, g2 = 2 * J2 + r2;
+        if (g1 < N && g2 < N) xfine[g1 + N * g2] = a[(NU + r1) + W * (NU + r2)];
+      }
+      {
+        constexpr int w = 2 * TC + 1;
+        for (int k = tid; k < w * w; k += kBS) {
+          const int r2 = k / w, r1 = k - r2 * w;
+          const int li = (r1 + NU) + W * (r2 + NU);
+          c[li] = bs[li] + p2l_nb<T, ST>(a, li, W, ih2) - ds[li] * a[li];
+        }
+      }
+      __syncthreads();
+      for (int k = tid; k < TC * TC; k += kBS) {
+        const int j2 = k / TC, j1 = k - j2 * TC;
+        const int c1 = J1 + j1, c2 = J2 + j2;
+        if (c1 < Nc && c2 < Nc) {
+          const int li = (NU + 2 * j1 + 1) + W * (NU + 2 * j2 + 1);  // fine node 2c + 1
+          const T v = (T)0.25 * c[li] + (T)0.125 * ((c[li - 1] + c[li + 1]) + (c[li - W] + c[li + W])) +
+                      (T)0.0625 * ((c[li - 1 - W] + c[li + 1 - W]) + (c[li - 1 + W] + c[li + 1 + W]));
+          bcoarse[c1 + Nc * c2] = v;
+        }
+      }
     }
-  }
-  {
-    constexpr int w = 2 * TC + 1;
-    for (int k = tid; k < w * w; k += kBS) {
-      const int r2 = k / w, r1 = k - r2 * w;
-      const int li = (r1 + NU) + W * (r2 + NU);
-      c[li] = bs[li] + p2l_nb<T, ST>(a, li, W, ih2) - ds[li] * a[li];
-    }
-  }
-  __syncthreads();
-  for (int k = tid; k < TC * TC; k += kBS) {
-    const int j2 = k / TC, j1 = k - j2 * TC;
-    const int c1 = J1 + j1, c2 = J2 + j2;
-    if (c1 < Nc && c2 < Nc) {
-      const int li = (NU + 2 * j1 + 1) + W * (NU + 2 * j2 + 1);  // fine node 2c + 1
-      const T v = (T)0.25 * c[li] + (T)0.125 * ((c[li - 1] + c[li + 1]) + (c[li - W] + c[li + W])) +
-                  (T)0.0625 * ((c[li - 1 - W] + c[li + 1 - W]) + (c[li - 1 + W] + c[li + 1 + W]));
-      bcoarse[c1 + Nc * c2] = v;
-    }
+    __syncthreads();  // the next tile's staging overwrites the LDS
   }
 }
 
@@ -175,7 +210,7 @@ __global__ void __launch_bounds__(kBS) k_mg_down_p2(const Inst* __restrict__ Dp,
 // (bilinear prolongation from a coarse patch staged in LDS), then NU sweeps;
 // writes the tile's own nodes to level l's x2.
 template <typename T, int NU, int TF, int ST = 5>
-__global__ void __launch_bounds__(kBS) k_mg_up_p2(const Inst* __restrict__ Dp, int l, int guard) {
+__global__ void __launch_bounds__(kBS) k_mg_up_p2(const Inst* __restrict__ Dp, int l, int guard, int nt, int tpw) {
   const Inst& I = Dp[blockIdx.z];
   int go = I.active;
   const int kind = I.coarse_p2, cl = I.coarse_lev;
@@ -188,84 +223,124 @@ __global__ void __launch_bounds__(kBS) k_mg_up_p2(const Inst* __restrict__ Dp, i
   const T* __restrict__ b = (const T*)I.lv[l].b;
   const T* __restrict__ mh = (const T*)I.lv[l].mh;
   T* __restrict__ xout = (T*)I.lv[l].x2;
-  const int gx = gridDim.x, gy = gridDim.y;
-  IPM_LOAD_TOGETHER(go, kind, cl, ctrl, N, Nc, h, omega, xc1, xc2, xpre, b, mh, xout, gx, gy);
+  const int gx = gridDim.x;
+  IPM_LOAD_TOGETHER(go, kind, cl, ctrl, N, Nc, h, omega, xc1, xc2, xpre, b, mh, xout, gx);
   if (!go || kind != (ST == 5 ? 1 : 2) || l >= cl) return;
   // the coarse iterate: the coarse kernel's output at the coarsest fused level
   const T* __restrict__ xc = (const T*)(l + 1 == cl ? xc1 : xc2);
-  int tx, ty;
-  xcd_tile(gx, gy, tx, ty);
-  if (tx * TF >= N || ty * TF >= N) return;
+  int t0, t1;
+  tile_run(gx, tpw, nt * nt, t0, t1);
+  if (t0 >= t1) return;
   constexpr int W = p2_up_width(NU, TF);
   constexpr int WC = p2_up_coarse_width(NU, TF);
+  constexpr int R = (W * W + kBS - 1) / kBS, RC = (WC * WC + kBS - 1) / kBS;  // staged nodes per thread
   __shared__ T bs[W * W], ws[W * W], xa[W * W], xb[W * W], cs[WC * WC];
-  const int o1 = tx * TF - NU, o2 = ty * TF - NU;
-  // coarse 1-based index of the patch's first column/row: the lower coarse
-  // neighbour of the region's first fine node (fine 1-based index o + 1)
-  const int cb1 = (o1 + 1) >> 1, cb2 = (o2 + 1) >> 1;
   const T ih2 = p2l_scale<T, ST>(h), dg = p2l_diag<T, ST>(h);
   const T om = (T)omega, om1 = (T)1 - om;
   const int tid = threadIdx.x;
-  // the stop flag is requested with the tile's data and tested before the
-  // first global store (the staging writes LDS only)
+  // the stop flag is requested with the first tile's data and tested before
+  // the first global store (the staging writes LDS only)
   const int f_stop = ctrl->stop, f_want = ctrl->want_restart;
-  for (int k = tid; k < WC * WC; k += kBS) {
-    const int p2 = k / WC, p1 = k - p2 * WC;
-    const int c1 = cb1 + p1 - 1, c2 = cb2 + p2 - 1;  // 0-based coarse node
-    cs[k] = ((unsigned)c1 < (unsigned)Nc && (unsigned)c2 < (unsigned)Nc) ? xc[c1 + Nc * c2] : (T)0;
-  }
-  for (int k = tid; k < W * W; k += kBS) {
-    const int q2 = k / W, q1 = k - q2 * W;
-    const int g1 = o1 + q1, g2 = o2 + q2;
-    T bv = 0, wv = 0, xv = 0;
-    if ((unsigned)g1 < (unsigned)N && (unsigned)g2 < (unsigned)N) {
-      const int gi = g1 + N * g2;
-      bv = b[gi];
-      wv = omega_over<T>(om, dg + mh[gi]);
-      xv = xpre[gi];
+  // the tile's coarse patch, right-hand side, M_hat and pre-smoothed iterate in registers
+  T rc[RC], rb[R], rm[R], rx[R];
+  auto fetch = [&](int t) {
+    const int o1 = (t % nt) * TF - NU, o2 = (t / nt) * TF - NU;
+    // coarse 1-based index of the patch's first column/row: the lower coarse
+    // neighbour of the region's first fine node (fine 1-based index o + 1)
+    const int cb1 = (o1 + 1) >> 1, cb2 = (o2 + 1) >> 1;
+#pragma unroll
+    for (int r = 0; r < RC; ++r) {
+      const int k = tid + r * kBS;
+      const int p2 = k / WC, p1 = k - p2 * WC;
+      const int c1 = cb1 + p1 - 1, c2 = cb2 + p2 - 1;  // 0-based coarse node
+      rc[r] = (k < WC * WC && (unsigned)c1 < (unsigned)Nc && (unsigned)c2 < (unsigned)Nc) ? xc[c1 + Nc * c2] : (T)0;
     }
-    bs[k] = bv;
-    ws[k] = wv;
-    xa[k] = xv;
-  }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int k = tid + r * kBS;
+      const int q2 = k / W, q1 = k - q2 * W;
+      const int g1 = o1 + q1, g2 = o2 + q2;
+      if (k < W * W && (unsigned)g1 < (unsigned)N && (unsigned)g2 < (unsigned)N) {
+        const int gi = g1 + N * g2;
+        rb[r] = b[gi];
+        rm[r] = mh[gi];
+        rx[r] = xpre[gi];
+      }
+    }
+  };
+  fetch(t0);
   // uniform over the workgroup
   if ((guard == 1 && f_stop) || (guard == 2 && !f_want)) return;
-  __syncthreads();
-  for (int k = tid; k < W * W; k += kBS) {
-    const int q2 = k / W, q1 = k - q2 * W;
-    const int g1 = o1 + q1, g2 = o2 + q2;
-    if ((unsigned)g1 < (unsigned)N && (unsigned)g2 < (unsigned)N) {
-      // fine 1-based F: even -> coarse F/2; odd -> (F-1)/2 and (F+1)/2, 1/2 each
-      const int F1 = g1 + 1, F2 = g2 + 1;
-      const int pi = ((F1 >> 1) - cb1) + WC * ((F2 >> 1) - cb2);
-      T v;
-      if (F1 & 1) {
-        v = (F2 & 1) ? (T)0.25 * ((cs[pi] + cs[pi + 1]) + (cs[pi + WC] + cs[pi + WC + 1]))
-                     : (T)0.5 * (cs[pi] + cs[pi + 1]);
-      } else {
-        v = (F2 & 1) ? (T)0.5 * (cs[pi] + cs[pi + WC]) : cs[pi];
-      }
-      xa[k] += v;
-    }
-  }
-  __syncthreads();
-  T* a = xa;
-  T* c = xb;
+  for (int t = t0; t < t1; ++t) {
+    const int tx = t % nt, ty = t / nt;
+    const bool live = tx * TF < N && ty * TF < N;  // uniform: the tile lies in this instance's grid
+    const int o1 = tx * TF - NU, o2 = ty * TF - NU;
+    const int cb1 = (o1 + 1) >> 1, cb2 = (o2 + 1) >> 1;
+    if (live) {
 #pragma unroll
-  for (int s = 1; s <= NU; ++s) {
-    const int w = W - 2 * s;
-    for (int k = tid; k < w * w; k += kBS) {
-      const int r2 = k / w, r1 = k - r2 * w;
-      const int li = (r1 + s) + W * (r2 + s);
-      c[li] = om1 * a[li] + ws[li] * (bs[li] + p2l_nb<T, ST>(a, li, W, ih2));
+      for (int r = 0; r < RC; ++r) {
+        const int k = tid + r * kBS;
+        if (k < WC * WC) cs[k] = rc[r];
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int k = tid + r * kBS;
+        if (k < W * W) {
+          const int q2 = k / W, q1 = k - q2 * W;
+          const int g1 = o1 + q1, g2 = o2 + q2;
+          T bv = 0, wv = 0, xv = 0;
+          if ((unsigned)g1 < (unsigned)N && (unsigned)g2 < (unsigned)N) {
+            bv = rb[r];
+            wv = omega_over<T>(om, dg + rm[r]);
+            xv = rx[r];
+          }
+          bs[k] = bv;
+          ws[k] = wv;
+          xa[k] = xv;
+        }
+      }
     }
     __syncthreads();
-    T* t = a; a = c; c = t;
-  }
-  for (int k = tid; k < TF * TF; k += kBS) {
-    const int r2 = k / TF, r1 = k - r2 * TF;
-    const int g1 = tx * TF + r1, g2 = ty * TF + r2;
-    if (g1 < N && g2 < N) xout[g1 + N * g2] = a[(NU + r1) + W * (NU + r2)];
+    if (t + 1 < t1) fetch(t + 1);
+    if (live) {
+      for (int k = tid; k < W * W; k += kBS) {
+        const int q2 = k / W, q1 = k - q2 * W;
+        const int g1 = o1 + q1, g2 = o2 + q2;
+        if ((unsigned)g1 < (unsigned)N && (unsigned)g2 < (unsigned)N) {
+          // fine 1-based F: even -> coarse F/2; odd -> (F-1)/2 and (F+1)/2, 1/2 each
+          const int F1 = g1 + 1, F2 = g2 + 1;
+          const int pi = ((F1 >> 1) - cb1) + WC * ((F2 >> 1) - cb2);
+          T v;
+          if (F1 & 1) {
+            v = (F2 & 1) ? (T)0.25 * ((cs[pi] + cs[pi + 1]) + (cs[pi + WC] + cs[pi + WC + 1]))
+                         : (T)0.5 * (cs[pi] + cs[pi + 1]);
+          } else {
+            v = (F2 & 1) ? (T)0.5 * (cs[pi] + cs[pi + WC]) : cs[pi];
+          }
+          xa[k] += v;
+        }
+      }
+      __syncthreads();
+      T* a = xa;
+      T* c = xb;
+#pragma unroll
+      for (int s = 1; s <= NU; ++s) {
+        const int w = W - 2 * s;
+        for (int k = tid; k < w * w; k += kBS) {
+          const int r2 = k / w, r1 = k - r2 * w;
+          const int li = (r1 + s) + W * (r2 + s);
+          c[li] = om1 * a[li] + ws[li] * (bs[li] + p2l_nb<T, ST>(a, li, W, ih2));
+        }
+        __syncthreads();
+        T* tmp = a; a = c; c = tmp;
+      }
+      for (int k = tid; k < TF * TF; k += kBS) {
+        const int r2 = k / TF, r1 = k - r2 * TF;
+        const int g1 = tx * TF + r1, g2 = ty * TF + r2;
+        if (g1 < N && g2 < N) xout[g1 + N * g2] = a[(NU + r1) + W * (NU + r2)];
+      }
+    }
+    __syncthreads();  // the next tile's staging overwrites the LDS
   }
 }
 

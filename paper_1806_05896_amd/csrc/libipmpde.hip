@@ -883,18 +883,31 @@ static bool big_tiles(const Group* G, long groups) {
   return groups >= kBigTileMinGroups;
 }
 
+// Workgroups of a Poisson level launch: each takes a run of tiles, as many as
+// keep the launch near this many workgroups (8 per CU, all resident at
+// once), so that a workgroup loads its next tile while it smooths the current
+// one instead of a new workgroup waiting for its first loads.
+static constexpr long kTileRunGroups = 2048;
+static int tile_run_length(int nt, int zc) {
+  return std::max(1, div_up((long)nt * nt * zc, kTileRunGroups));
+}
+
 template <typename T, int NU, int ST>
 static void launch_down_p2_nu(const Group* G, int l, int scaled, int guard, hipStream_t s) {
   const int Nc = G->maxN[l + 1];
   if constexpr (p2_down_lds<T, NU, 16>() <= kStaticLdsMax) {
     const int nt = div_up(Nc, 16);
     if (big_tiles(G, (long)nt * nt * G->zc)) {
-      hipLaunchKernelGGL((k_mg_down_p2<T, NU, 16, ST>), dim3(nt, nt, G->zc), dim3(kBS), 0, s, G->D, l, scaled, guard);
+      const int tpw = tile_run_length(nt, G->zc);
+      hipLaunchKernelGGL((k_mg_down_p2<T, NU, 16, ST>), dim3(div_up((long)nt * nt, tpw), 1, G->zc), dim3(kBS), 0, s,
+                         G->D, l, scaled, guard, nt, tpw);
       return;
     }
   }
   const int nt = div_up(Nc, 8);
-  hipLaunchKernelGGL((k_mg_down_p2<T, NU, 8, ST>), dim3(nt, nt, G->zc), dim3(kBS), 0, s, G->D, l, scaled, guard);
+  const int tpw = tile_run_length(nt, G->zc);
+  hipLaunchKernelGGL((k_mg_down_p2<T, NU, 8, ST>), dim3(div_up((long)nt * nt, tpw), 1, G->zc), dim3(kBS), 0, s, G->D,
+                     l, scaled, guard, nt, tpw);
 }
 
 template <typename T, int NU, int ST>
@@ -903,12 +916,16 @@ static void launch_up_p2_nu(const Group* G, int l, int guard, hipStream_t s) {
   if constexpr (p2_up_lds<T, NU, 32>() <= kStaticLdsMax) {
     const int nt = div_up(N, 32);
     if (big_tiles(G, (long)nt * nt * G->zc)) {
-      hipLaunchKernelGGL((k_mg_up_p2<T, NU, 32, ST>), dim3(nt, nt, G->zc), dim3(kBS), 0, s, G->D, l, guard);
+      const int tpw = tile_run_length(nt, G->zc);
+      hipLaunchKernelGGL((k_mg_up_p2<T, NU, 32, ST>), dim3(div_up((long)nt * nt, tpw), 1, G->zc), dim3(kBS), 0, s,
+                         G->D, l, guard, nt, tpw);
       return;
     }
   }
   const int nt = div_up(N, 16);
-  hipLaunchKernelGGL((k_mg_up_p2<T, NU, 16, ST>), dim3(nt, nt, G->zc), dim3(kBS), 0, s, G->D, l, guard);
+  const int tpw = tile_run_length(nt, G->zc);
+  hipLaunchKernelGGL((k_mg_up_p2<T, NU, 16, ST>), dim3(div_up((long)nt * nt, tpw), 1, G->zc), dim3(kBS), 0, s, G->D,
+                     l, guard, nt, tpw);
 }
 
 // One descent (smoothing + residual + restriction) of level l for every
