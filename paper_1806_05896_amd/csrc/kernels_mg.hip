@@ -574,9 +574,11 @@ __device__ __forceinline__ T p2_nb(const T* __restrict__ a, int p, int P, T ihs)
   }
 
 // Descent at level l: nu_pre damped-Jacobi sweeps from zero, the residual and
-// its full-weighting restriction to level l + 1's right-hand side.  The
-// right-hand side, d and 1/d of the thread's nodes are read from LDS once.
-template <typename T, int NT, int ST = 5>
+// its full-weighting restriction to level l + 1's right-hand side.  With REG
+// the right-hand side, d and 1/d of the thread's nodes are read from LDS once
+// and kept in registers; without it every sweep reads them from LDS (fewer
+// registers, for kernels that hold other state across the cycle).
+template <typename T, int NT, int ST = 5, bool REG = true>
 __device__ __forceinline__ void p2_down(int nu_pre, T* lds, const int* LN, const int* LOFF, const T* LIH2, int l,
                                         int tid, T om, unsigned& alt) {
   constexpr int R = p2_per_thread<T>();
@@ -590,19 +592,33 @@ __device__ __forceinline__ void p2_down(int nu_pre, T* lds, const int* LN, const
   const T* d = b + n;
   const T* dinv = d + n;
   const int sh = 31 - __builtin_clz(N + 1), step = NT >> sh, i1 = tid & ((1 << sh) - 1), i20 = tid >> sh;
-  T rb[R], rd[R], rdi[R];
-  P2_FOR_R(R) rb[j] = b[i]; rd[j] = d[i]; rdi[j] = dinv[i]; P2_END_R
-  for (int s = 0; s < nu_pre; ++s) {
-    if (s == 0) {
-      P2_FOR_R(R) c[p] = om * rb[j] * rdi[j]; P2_END_R
-    } else {
-      P2_FOR_R(R) c[p] = a[p] + om * (rb[j] - rd[j] * a[p] + p2_nb<T, ST>(a, p, P, ih2)) * rdi[j]; P2_END_R
+  if constexpr (REG) {
+    T rb[R], rd[R], rdi[R];
+    P2_FOR_R(R) rb[j] = b[i]; rd[j] = d[i]; rdi[j] = dinv[i]; P2_END_R
+    for (int s = 0; s < nu_pre; ++s) {
+      if (s == 0) {
+        P2_FOR_R(R) c[p] = om * rb[j] * rdi[j]; P2_END_R
+      } else {
+        P2_FOR_R(R) c[p] = a[p] + om * (rb[j] - rd[j] * a[p] + p2_nb<T, ST>(a, p, P, ih2)) * rdi[j]; P2_END_R
+      }
+      __syncthreads();
+      T* t = a; a = c; c = t;
+      alt ^= 1u << l;
     }
-    __syncthreads();
-    T* t = a; a = c; c = t;
-    alt ^= 1u << l;
+    P2_FOR_R(R) c[p] = rb[j] - rd[j] * a[p] + p2_nb<T, ST>(a, p, P, ih2); P2_END_R
+  } else {
+    for (int s = 0; s < nu_pre; ++s) {
+      if (s == 0) {
+        P2_FOR_T(N, tid, NT) c[p] = om * b[i] * dinv[i]; P2_END
+      } else {
+        P2_FOR_T(N, tid, NT) c[p] = a[p] + om * (b[i] - d[i] * a[p] + p2_nb<T, ST>(a, p, P, ih2)) * dinv[i]; P2_END
+      }
+      __syncthreads();
+      T* t = a; a = c; c = t;
+      alt ^= 1u << l;
+    }
+    P2_FOR_T(N, tid, NT) c[p] = b[i] - d[i] * a[p] + p2_nb<T, ST>(a, p, P, ih2); P2_END
   }
-  P2_FOR_R(R) c[p] = rb[j] - rd[j] * a[p] + p2_nb<T, ST>(a, p, P, ih2); P2_END_R
   __syncthreads();
   const int Nc = LN[l + 1];
   T* bc = lds + LOFF[l + 1] + 2 * (Nc + 2) * (Nc + 2);
@@ -621,8 +637,8 @@ __device__ __forceinline__ void p2_down(int nu_pre, T* lds, const int* LN, const
 
 // Ascent at level l: bilinear prolongation of level l + 1's iterate (in xb
 // when bit l + 1 of alt is set) added to the iterate, nu_post sweeps (the
-// right-hand side, d and 1/d of the thread's nodes in registers).
-template <typename T, int NT, int ST = 5>
+// right-hand side, d and 1/d of the thread's nodes in registers with REG).
+template <typename T, int NT, int ST = 5, bool REG = true>
 __device__ __forceinline__ void p2_up(int nu_post, T* lds, const int* LN, const int* LOFF, const T* LIH2, int l,
                                       int tid, T om, unsigned& alt) {
   constexpr int R = p2_per_thread<T>();
@@ -637,24 +653,40 @@ __device__ __forceinline__ void p2_up(int nu_post, T* lds, const int* LN, const 
   const T* d = b + n;
   const T* dinv = d + n;
   const T* xc = lds + LOFF[l + 1] + ((alt >> (l + 1)) & 1u) * Pc * Pc;
-  const int sh = 31 - __builtin_clz(N + 1), step = NT >> sh, i1 = tid & ((1 << sh) - 1), i20 = tid >> sh;
-  T rb[R], rd[R], rdi[R];
-  P2_FOR_R(R)
-    rb[j] = b[i]; rd[j] = d[i]; rdi[j] = dinv[i];
-    // bilinear interpolation: fine 1-based F maps to coarse F/2 (even) or the two neighbours (odd);
-    // in padded coarse coordinates the boundary nodes are the zero ring
-    const int F1 = i1 + 1, F2 = i2 + 1;
-    const int lo1 = F1 >> 1, hi1 = (F1 + 1) >> 1, lo2 = F2 >> 1, hi2 = (F2 + 1) >> 1;
-    const T v = (T)0.25 * (xc[lo1 + Pc * lo2] + xc[hi1 + Pc * lo2] + xc[lo1 + Pc * hi2] + xc[hi1 + Pc * hi2]);
-    a[F1 + P * F2] += v;
-  P2_END_R
-  __syncthreads();
-  for (int s = 0; s < nu_post; ++s) {
-    P2_FOR_R(R) c[p] = a[p] + om * (rb[j] - rd[j] * a[p] + p2_nb<T, ST>(a, p, P, ih2)) * rdi[j]; P2_END_R
-    __syncthreads();
-    T* t = a; a = c; c = t;
-    alt ^= 1u << l;
+  // bilinear interpolation: fine 1-based F maps to coarse F/2 (even) or the two neighbours (odd);
+  // in padded coarse coordinates the boundary nodes are the zero ring
+#define P2_PROLONG_ADD                                                                                          \
+  {                                                                                                             \
+    const int F1 = i1 + 1, F2 = i2 + 1;                                                                         \
+    const int lo1 = F1 >> 1, hi1 = (F1 + 1) >> 1, lo2 = F2 >> 1, hi2 = (F2 + 1) >> 1;                           \
+    a[F1 + P * F2] +=                                                                                           \
+        (T)0.25 * (xc[lo1 + Pc * lo2] + xc[hi1 + Pc * lo2] + xc[lo1 + Pc * hi2] + xc[hi1 + Pc * hi2]);          \
   }
+  if constexpr (REG) {
+    const int sh = 31 - __builtin_clz(N + 1), step = NT >> sh, i1 = tid & ((1 << sh) - 1), i20 = tid >> sh;
+    T rb[R], rd[R], rdi[R];
+    P2_FOR_R(R)
+      rb[j] = b[i]; rd[j] = d[i]; rdi[j] = dinv[i];
+      P2_PROLONG_ADD
+    P2_END_R
+    __syncthreads();
+    for (int s = 0; s < nu_post; ++s) {
+      P2_FOR_R(R) c[p] = a[p] + om * (rb[j] - rd[j] * a[p] + p2_nb<T, ST>(a, p, P, ih2)) * rdi[j]; P2_END_R
+      __syncthreads();
+      T* t = a; a = c; c = t;
+      alt ^= 1u << l;
+    }
+  } else {
+    P2_FOR_T(N, tid, NT) P2_PROLONG_ADD P2_END
+    __syncthreads();
+    for (int s = 0; s < nu_post; ++s) {
+      P2_FOR_T(N, tid, NT) c[p] = a[p] + om * (b[i] - d[i] * a[p] + p2_nb<T, ST>(a, p, P, ih2)) * dinv[i]; P2_END
+      __syncthreads();
+      T* t = a; a = c; c = t;
+      alt ^= 1u << l;
+    }
+  }
+#undef P2_PROLONG_ADD
 }
 
 // The V-cycle of the Poisson coarse kernel on the LDS image (level tables
@@ -662,7 +694,7 @@ __device__ __forceinline__ void p2_up(int nu_post, T* lds, const int* LN, const 
 // residual and restriction down to the single-node grid, its exact solve,
 // prolongation and post-smoothing back up.  Returns the top level's final
 // iterate (padded layout) in LDS.
-template <typename T, int ST = 5>
+template <typename T, int ST = 5, bool REG = true>
 __device__ __forceinline__ const T* coarse_p2_cycle(T* lds, const int* LN, const int* LOFF, const T* LIH2, int cl,
                                                     int L, T om, int nu_pre, int nu_post, const T* ainv7 = nullptr) {
   const int tid = threadIdx.x;
@@ -673,7 +705,7 @@ __device__ __forceinline__ const T* coarse_p2_cycle(T* lds, const int* LN, const
   if (ainv7)
     for (int l = cl; l < L; ++l)
       if (LN[l] == kCoarseInvN) lx = l;
-  for (int l = cl; l < lx; ++l) p2_down<T, kCoarseBS, ST>(nu_pre, lds, LN, LOFF, LIH2, l, tid, om, alt);
+  for (int l = cl; l < lx; ++l) p2_down<T, kCoarseBS, ST, REG>(nu_pre, lds, LN, LOFF, LIH2, l, tid, om, alt);
   if (LN[lx] == kCoarseInvN && ainv7) {
     constexpr int n = kCoarseInvN * kCoarseInvN, P = kCoarseInvN + 2;
     // with no descent before it the right-hand side was written by the threads
@@ -696,7 +728,7 @@ __device__ __forceinline__ const T* coarse_p2_cycle(T* lds, const int* LN, const
     P2_FOR_T(N, tid, kCoarseBS) a[p] = b[i] * dinv[i]; P2_END
     __syncthreads();
   }
-  for (int l = lx - 1; l >= cl; --l) p2_up<T, kCoarseBS, ST>(nu_post, lds, LN, LOFF, LIH2, l, tid, om, alt);
+  for (int l = lx - 1; l >= cl; --l) p2_up<T, kCoarseBS, ST, REG>(nu_post, lds, LN, LOFF, LIH2, l, tid, om, alt);
   const int N = LN[cl], P = N + 2;
   return lds + LOFF[cl] + ((alt >> cl) & 1u) * P * P;
 }
@@ -1066,7 +1098,7 @@ __global__ void __launch_bounds__(kCoarseBS) k_heat_sweep_p2(const Inst* __restr
     }
     __syncthreads();
     if (k + 1 < nt) prefetch(steps[dir > 0 ? t + 1 : t - 1]);
-    const T* a = coarse_p2_cycle<T>(lds, LN, LOFF, LIH2, 0, L, om, nu_pre, nu_post);
+    const T* a = coarse_p2_cycle<T, 5, false>(lds, LN, LOFF, LIH2, 0, L, om, nu_pre, nu_post);
     T* xg = (T*)St.lv[0].x;
     {
       const int P = N0 + 2;
