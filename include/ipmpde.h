@@ -122,6 +122,18 @@ typedef struct {
                           at least 2048 workgroups of them), IPMPDE_TILE_SMALL (8 coarse / 16
                           fine nodes per side) or IPMPDE_TILE_LARGE (16 / 32, where the LDS
                           tile fits); no node's arithmetic depends on it */
+  int lanes;           /* batches only: the instances are split into this many sub-batches
+                          (balanced by node count), each solved on a stream of its own by a host
+                          thread of its own, so that the latency-bound multigrid launches of one
+                          lane overlap the bandwidth-bound Krylov launches of another; default 1
+                          (0 is taken as 1), at most 16, more than the batch's count is clamped to
+                          it.  The lanes start after the work queued on the caller's stream,
+                          which waits for every lane before the call returns.  No instance's
+                          arithmetic depends on it.  Lanes overlap only where their streams
+                          hold hardware queues of their own: HIP shares GPU_MAX_HW_QUEUES
+                          queues (4 unless set before the runtime starts) among all streams
+                          of the process, and lanes on a shared queue run one after another.
+                          Ignored by single-problem calls and by the engine. */
 } ipmpde_options;
 
 #define IPMPDE_MAX_HIST 256
@@ -355,13 +367,16 @@ int ipmpde_batch_solve(ipmpde_batch* batch, const ipmpde_options* opts, int per_
  * 1 x 3+3, 2 x 1+1, 2 x 2+2}, for 2D Poisson batches both tile sizes of the
  * level kernels, with IPMPDE_TUNE_PRECISION in flags also the other V-cycle
  * precision) and returns in *best the options `base` (NULL = defaults) with
- * the fastest candidate's vcycles, nu_pre, nu_post, mg_precision and mg_tile
- * among those that solve every instance (IPMPDE_ENOTCONVERGED if none does).
+ * the fastest candidate's vcycles, nu_pre, nu_post, mg_precision, mg_tile and lanes
+ * among those that solve every instance (IPMPDE_ENOTCONVERGED if none does);
+ * each candidate is also timed with the instances split into 2, 4 and 8 lanes
+ * (as many as the batch has instances), and *best carries the fastest lanes.
  * Each candidate costs two batched solves, so the problems' iterates hold the
  * last candidate's result afterwards.  cache_path (may be NULL) names a JSON
  * file of earlier results keyed by the GPU architecture and the batch's shape
  * (dimension, PDE kinds, largest N and nt, count, Krylov method,
- * preconditioner, state bounds, restart, precision unless tuned); a hit
+ * preconditioner, state bounds, restart, precision unless tuned, and the
+ * process's hardware queue count GPU_MAX_HW_QUEUES); a hit
  * returns the stored pick without solving (*from_cache = 1), a miss tunes and
  * adds the result to the file.  best_ms (may be NULL) receives the winner's
  * solve time in milliseconds; from_cache may be NULL. */

@@ -46,7 +46,7 @@ class COptions(C.Structure):
         ("krylov", C.c_int), ("precond", C.c_int), ("restart", C.c_int), ("krylov_tol", C.c_double),
         ("krylov_maxit", C.c_int), ("vcycles", C.c_int), ("nu_pre", C.c_int), ("nu_post", C.c_int),
         ("omega", C.c_double), ("mg_precision", C.c_int), ("chunk", C.c_int), ("use_graphs", C.c_int),
-        ("mu_rule", C.c_int), ("mass_scaling", C.c_int), ("mg_tile", C.c_int),
+        ("mu_rule", C.c_int), ("mass_scaling", C.c_int), ("mg_tile", C.c_int), ("lanes", C.c_int),
     ]
 
 

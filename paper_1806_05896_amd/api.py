@@ -66,6 +66,7 @@ class Options:
     mu_rule: str = "paper"          # "paper" (sigma mu^k) | "central" (sigma x mean complementarity)
     mass_scaling: str = "unit"      # "unit" (divided by the lumped mass h^d) | "hd" (literal weighting)
     mg_tile: str = "auto"           # "auto" | "small" | "large": tiles of the 2D Poisson level kernels
+    lanes: int = 1                  # batches: sub-batches solved concurrently, one stream and host thread each
 
     _ENUMS = {
         "krylov": {"minres": L.MINRES, "fgmres": L.FGMRES},

@@ -1,13 +1,14 @@
 // Autotuner of a batch's multigrid schedule: V-cycles per solve, Jacobi
-// sweeps, the tile size of the 2D Poisson level kernels and (optionally) the
-// V-cycle precision, picked by timing whole batched solves.  Results are kept
+// sweeps, the tile size of the 2D Poisson level kernels, (optionally) the
+// V-cycle precision, and the number of lanes the instances are split into,
+// picked by timing whole batched solves.  Results are kept
 // in a JSON file keyed by the GPU architecture and the batch's shape, so a
 // shape is tuned once per machine type.
 
 namespace {
 
 struct TuneEntry {
-  int vcycles = 1, nu_pre = 2, nu_post = 2, mg_precision = IPMPDE_FP32, mg_tile = IPMPDE_TILE_AUTO;
+  int vcycles = 1, nu_pre = 2, nu_post = 2, mg_precision = IPMPDE_FP32, mg_tile = IPMPDE_TILE_AUTO, lanes = 1;
   double ms = 0;
 };
 
@@ -20,7 +21,17 @@ std::string device_arch() {
   return c == std::string::npos ? a : a.substr(0, c);
 }
 
-// arch/d<dim>/pde<mask of kinds>/N<largest N>/nt<largest nt>/x<count>/kry<k>/pc<p>/y<state bounds>/r<restart>
+// Hardware queues HIP gives the process (GPU_MAX_HW_QUEUES, 4 when unset):
+// lanes whose streams share a queue run one after the other, so the best lane
+// count depends on it.
+int hw_queues() {
+  const char* v = std::getenv("GPU_MAX_HW_QUEUES");
+  const int q = v ? std::atoi(v) : 0;
+  return q > 0 ? q : 4;
+}
+
+// arch/d<dim>/pde<mask of kinds>/N<largest N>/nt<largest nt>/x<count>/kry<k>/pc<p>/y<state bounds>/r<restart>/
+// mp<precision or -1 when tuned>/q<hardware queues>
 std::string tune_key(const Group* G, const ipmpde_options& o, int flags) {
   int maxN = 0, maxnt = 1, mask = 0, any_y = 0;
   for (const ipmpde_problem* P : G->probs) {
@@ -30,14 +41,15 @@ std::string tune_key(const Group* G, const ipmpde_options& o, int flags) {
     any_y |= P->has_y ? 1 : 0;
   }
   char buf[256];
-  std::snprintf(buf, sizeof buf, "%s/d%d/pde%d/N%d/nt%d/x%d/kry%d/pc%d/y%d/r%d/mp%d", device_arch().c_str(), G->dim,
-                mask, maxN, maxnt, G->count, o.krylov, o.precond, any_y, o.krylov == IPMPDE_FGMRES ? o.restart : 0,
-                (flags & IPMPDE_TUNE_PRECISION) ? -1 : o.mg_precision);
+  std::snprintf(buf, sizeof buf, "%s/d%d/pde%d/N%d/nt%d/x%d/kry%d/pc%d/y%d/r%d/mp%d/q%d", device_arch().c_str(),
+                G->dim, mask, maxN, maxnt, G->count, o.krylov, o.precond, any_y,
+                o.krylov == IPMPDE_FGMRES ? o.restart : 0, (flags & IPMPDE_TUNE_PRECISION) ? -1 : o.mg_precision,
+                hw_queues());
   return buf;
 }
 
 // The cache: one entry per line, `  "key": {"vcycles": v, ...}` inside a
-// JSON object.
+// JSON object (entries written before lanes were tuned read as one lane).
 std::map<std::string, TuneEntry> read_cache(const char* path) {
   std::map<std::string, TuneEntry> m;
   FILE* f = std::fopen(path, "r");
@@ -50,6 +62,10 @@ std::map<std::string, TuneEntry> read_cache(const char* path) {
     if (!q1) continue;
     TuneEntry e;
     if (std::sscanf(q1 + 1,
+                    ": {\"vcycles\": %d, \"nu_pre\": %d, \"nu_post\": %d, \"mg_precision\": %d, \"mg_tile\": %d, "
+                    "\"lanes\": %d, \"ms\": %lf}",
+                    &e.vcycles, &e.nu_pre, &e.nu_post, &e.mg_precision, &e.mg_tile, &e.lanes, &e.ms) == 7 ||
+        std::sscanf(q1 + 1,
                     ": {\"vcycles\": %d, \"nu_pre\": %d, \"nu_post\": %d, \"mg_precision\": %d, \"mg_tile\": %d, "
                     "\"ms\": %lf}",
                     &e.vcycles, &e.nu_pre, &e.nu_post, &e.mg_precision, &e.mg_tile, &e.ms) == 6)
@@ -69,8 +85,8 @@ bool write_cache(const char* path, const std::map<std::string, TuneEntry>& m) {
     const TuneEntry& e = kv.second;
     std::fprintf(f,
                  "  \"%s\": {\"vcycles\": %d, \"nu_pre\": %d, \"nu_post\": %d, \"mg_precision\": %d, \"mg_tile\": %d, "
-                 "\"ms\": %.3f}%s\n",
-                 kv.first.c_str(), e.vcycles, e.nu_pre, e.nu_post, e.mg_precision, e.mg_tile, e.ms,
+                 "\"lanes\": %d, \"ms\": %.3f}%s\n",
+                 kv.first.c_str(), e.vcycles, e.nu_pre, e.nu_post, e.mg_precision, e.mg_tile, e.lanes, e.ms,
                  ++k < m.size() ? "," : "");
   }
   std::fprintf(f, "}\n");
@@ -84,6 +100,7 @@ void apply_entry(const TuneEntry& e, ipmpde_options* o) {
   o->nu_post = e.nu_post;
   o->mg_precision = e.mg_precision;
   o->mg_tile = e.mg_tile;
+  o->lanes = e.lanes;
 }
 
 }  // namespace
@@ -132,12 +149,21 @@ extern "C" int ipmpde_batch_autotune(ipmpde_batch* B, const ipmpde_options* base
   std::vector<ipmpde_options> po(G->count, o);
   int found = 0;
   TuneEntry win;
-  for (TuneEntry& e : cands) {
+  // lane counts outermost, so each lane split is built once
+  std::vector<TuneEntry> runs;
+  for (int L : {1, 2, 4, 8})
+    if (L <= G->count)
+      for (TuneEntry e : cands) {
+        e.lanes = L;
+        runs.push_back(e);
+      }
+  for (TuneEntry& e : runs) {
     for (auto& x : po) apply_entry(e, &x);
+    auto solve = [&]() { return e.lanes > 1 ? batch_solve_lanes(B, po, e.lanes, s) : solve_group(G, po, s); };
     // the first solve captures graphs and allocates the precision's levels
-    TRY(solve_group(G, po, s));
+    TRY(solve());
     const auto t0 = std::chrono::steady_clock::now();
-    TRY(solve_group(G, po, s));
+    TRY(solve());
     e.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     bool ok = true;
     for (const ipmpde_problem* P : G->probs) ok = ok && P->stats.status == IPMPDE_OK;

@@ -14,11 +14,13 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -137,7 +139,8 @@ struct Group {
   KrylovCtrl* ctrl_h = nullptr;  // pinned (the prefix up to hcol is copied back)
   double* stat_d = nullptr;
   double* stat_h = nullptr;      // pinned, 16 per instance
-  hipStream_t cap_stream = nullptr;
+  hipStream_t cap_stream = nullptr;  // created at the first capture unless set (then not owned)
+  bool own_cap = true;
   std::map<GraphKey, hipGraphExec_t> graphs;
   AllocList mem;
   // grid sizes (maxima over instances) after group_select
@@ -477,7 +480,7 @@ static void group_release(Group* G) {
   if (G->H) (void)hipHostFree(G->H);
   if (G->ctrl_h) (void)hipHostFree(G->ctrl_h);
   if (G->stat_h) (void)hipHostFree(G->stat_h);
-  if (G->cap_stream) (void)hipStreamDestroy(G->cap_stream);
+  if (G->cap_stream && G->own_cap) (void)hipStreamDestroy(G->cap_stream);
   delete G;
 }
 
@@ -501,8 +504,7 @@ static int group_create(const std::vector<ipmpde_problem*>& probs, int cap, int 
       (e = hipMemset(G->stat_d, 0, 16 * sizeof(double) * cap)) != hipSuccess ||
       (e = hipHostMalloc((void**)&G->H, sizeof(Inst) * cap, hipHostMallocDefault)) != hipSuccess ||
       (e = hipHostMalloc((void**)&G->ctrl_h, sizeof(KrylovCtrl) * cap, hipHostMallocDefault)) != hipSuccess ||
-      (e = hipHostMalloc((void**)&G->stat_h, 16 * sizeof(double) * cap, hipHostMallocDefault)) != hipSuccess ||
-      (e = hipStreamCreateWithFlags(&G->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+      (e = hipHostMalloc((void**)&G->stat_h, 16 * sizeof(double) * cap, hipHostMallocDefault)) != hipSuccess)
     return bail(fail(IPMPDE_EDEVICE, std::string("group setup: ") + hipGetErrorString(e)));
   std::memset(G->ctrl_h, 0, sizeof(KrylovCtrl) * cap);
   std::memset(G->stat_h, 0, 16 * sizeof(double) * cap);
@@ -752,8 +754,12 @@ extern "C" int ipmpde_default_options(ipmpde_options* o) {
   o->mu_rule = IPMPDE_MU_PAPER;
   o->mass_scaling = IPMPDE_MASS_UNIT;
   o->mg_tile = IPMPDE_TILE_AUTO;
+  o->lanes = 1;
   return IPMPDE_OK;
 }
+
+// Largest number of lanes (concurrent sub-batches) of a batch solve.
+static constexpr int kMaxLanes = 16;
 
 static int check_options(const ipmpde_options& o) {
   if (!(o.sigma > 0 && o.sigma < 1)) return fail(IPMPDE_EINVAL, "sigma must lie in (0,1)");
@@ -784,6 +790,7 @@ static int check_options(const ipmpde_options& o) {
     return fail(IPMPDE_EINVAL, "bad mass_scaling");
   if (o.mg_tile != IPMPDE_TILE_AUTO && o.mg_tile != IPMPDE_TILE_SMALL && o.mg_tile != IPMPDE_TILE_LARGE)
     return fail(IPMPDE_EINVAL, "bad mg_tile");
+  if (o.lanes < 0 || o.lanes > kMaxLanes) return fail(IPMPDE_EINVAL, "lanes must be in [0, 16]");
   return IPMPDE_OK;
 }
 
@@ -1205,8 +1212,9 @@ static GraphKey graph_key(const Group* G, const ipmpde_options& o, int fg, int j
 }
 
 // Launch the sequence `body(stream)` through the group's graph cache: the
-// first use of a key captures it on the group's capture stream and
-// instantiates it; later uses launch the instantiated graph on s.
+// first use of a key captures it on the group's capture stream (created on
+// the first capture: every stream holds one of the process's few hardware
+// queues) and instantiates it; later uses launch the instantiated graph on s.
 template <typename F>
 static int launch_cached(Group* G, const GraphKey& key, hipStream_t s, F&& body) {
   auto it = G->graphs.find(key);
@@ -1216,6 +1224,7 @@ static int launch_cached(Group* G, const GraphKey& key, hipStream_t s, F&& body)
       G->graphs.clear();
     }
     hipGraph_t g;
+    if (!G->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&G->cap_stream, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(G->cap_stream, hipStreamCaptureModeThreadLocal));
     body(G->cap_stream);
     HIP_TRY(hipStreamEndCapture(G->cap_stream, &g));
@@ -2187,9 +2196,130 @@ extern "C" int ipmpde_apply_precond(ipmpde_problem* P, const ipmpde_options* opt
 // ---------------------------------------------------------------------------
 // batches
 
+// A batch: one group over all instances, and for solves split into lanes
+// (options.lanes > 1) one group per lane over its share of the instances,
+// built on first use of a lane count.  Each lane runs on a stream of the
+// batch's own (default priority), which also serves as its group's capture
+// stream: a process has only a few hardware queues, and two lanes whose
+// streams share one run one after the other.
 struct ipmpde_batch {
   Group* G = nullptr;
+  std::vector<Group*> lane_G;
+  std::vector<std::vector<int>> lane_idx;  // instances of each lane (ascending)
+  std::vector<hipStream_t> lane_s;
+  std::vector<hipEvent_t> lane_ev;         // lane k's end
+  hipEvent_t start_ev = nullptr;           // the caller's stream at the start of a solve
 };
+
+static void batch_release_lanes(ipmpde_batch* B) {
+  for (Group* g : B->lane_G) group_release(g);
+  for (hipStream_t s : B->lane_s)
+    if (s) (void)hipStreamDestroy(s);
+  for (hipEvent_t e : B->lane_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (B->start_ev) (void)hipEventDestroy(B->start_ev);
+  B->start_ev = nullptr;
+  B->lane_G.clear();
+  B->lane_idx.clear();
+  B->lane_s.clear();
+  B->lane_ev.clear();
+}
+
+// Split the batch's instances into L lanes of about equal work: the largest
+// instances (by node count, times the steps of a heat problem) first, each to
+// the lane with the least work so far.
+static int batch_make_lanes(ipmpde_batch* B, int L) {
+  if ((int)B->lane_G.size() == L) return IPMPDE_OK;
+  batch_release_lanes(B);
+  const Group* G = B->G;
+  std::vector<int> order(G->count);
+  for (int i = 0; i < G->count; ++i) order[i] = i;
+  auto work = [&](int i) { return (double)G->probs[i]->n * std::max(1, G->probs[i]->nt); };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
+  std::vector<double> load(L, 0.0);
+  B->lane_idx.assign(L, {});
+  for (int i : order) {
+    const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    B->lane_idx[k].push_back(i);
+    load[k] += work(i);
+  }
+  B->lane_G.assign(L, nullptr);
+  B->lane_s.assign(L, nullptr);
+  B->lane_ev.assign(L, nullptr);
+  hipError_t e = hipEventCreateWithFlags(&B->start_ev, hipEventDisableTiming);
+  // the streams first, one after the other, so that they take distinct hardware queues where there are enough
+  for (int k = 0; k < L && e == hipSuccess; ++k) e = hipStreamCreateWithFlags(&B->lane_s[k], hipStreamNonBlocking);
+  for (int k = 0; k < L && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&B->lane_ev[k], hipEventDisableTiming);
+  if (e != hipSuccess) {
+    batch_release_lanes(B);
+    return fail(IPMPDE_EDEVICE, std::string("lane setup: ") + hipGetErrorString(e));
+  }
+  for (int k = 0; k < L; ++k) {
+    std::sort(B->lane_idx[k].begin(), B->lane_idx[k].end());
+    std::vector<ipmpde_problem*> v;
+    for (int i : B->lane_idx[k]) v.push_back(G->probs[i]);
+    const int rc = group_create(v, (int)v.size(), G->dim, &B->lane_G[k]);
+    if (rc != IPMPDE_OK) {
+      batch_release_lanes(B);
+      return rc;
+    }
+    B->lane_G[k]->cap_stream = B->lane_s[k];
+    B->lane_G[k]->own_cap = false;
+  }
+  return IPMPDE_OK;
+}
+
+// Solve the batch split into L > 1 lanes, each lane's group on its own stream
+// from a host thread of its own (lane 0 from the calling thread), between an
+// event on the caller's stream and the caller's stream waiting for every
+// lane.  The workspaces are allocated here first, so every allocation (the
+// registered allocator's included) happens on the calling thread.
+static int batch_solve_lanes(ipmpde_batch* B, const std::vector<ipmpde_options>& po, int L, hipStream_t s) {
+  TRY(batch_make_lanes(B, L));
+  std::vector<std::vector<ipmpde_options>> lpo(L);
+  for (int k = 0; k < L; ++k) {
+    for (int i : B->lane_idx[k]) lpo[k].push_back(po[i]);
+    ipmpde_options u;
+    TRY(unit_form(B->lane_G[k]->probs[0], lpo[k][0], &u));
+    TRY(group_select(B->lane_G[k], u));
+  }
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipEventRecord(B->start_ev, s));
+  for (int k = 0; k < L; ++k) HIP_TRY(hipStreamWaitEvent(B->lane_s[k], B->start_ev, 0));
+  std::vector<int> rc(L, IPMPDE_OK);
+  std::vector<std::string> msg(L);
+  auto run = [&](int k) {
+    if (k > 0) {
+      const hipError_t e = hipSetDevice(dev);
+      if (e != hipSuccess) {
+        rc[k] = IPMPDE_EDEVICE;
+        msg[k] = std::string("hipSetDevice: ") + hipGetErrorString(e);
+        return;
+      }
+    }
+    rc[k] = solve_group(B->lane_G[k], lpo[k], B->lane_s[k]);
+    if (rc[k] != IPMPDE_OK) msg[k] = g_err;
+  };
+  std::vector<std::thread> th;
+  try {
+    for (int k = 1; k < L; ++k) th.emplace_back(run, k);
+  } catch (const std::exception& ex) {
+    for (int k = (int)th.size() + 1; k < L; ++k) {
+      rc[k] = IPMPDE_EDEVICE;
+      msg[k] = std::string("cannot start a lane thread: ") + ex.what();
+    }
+  }
+  run(0);
+  for (auto& t : th) t.join();
+  for (int k = 0; k < L; ++k) {
+    HIP_TRY(hipEventRecord(B->lane_ev[k], B->lane_s[k]));
+    HIP_TRY(hipStreamWaitEvent(s, B->lane_ev[k], 0));
+  }
+  for (int k = 0; k < L; ++k)
+    if (rc[k] != IPMPDE_OK) return fail(rc[k], msg[k]);
+  return IPMPDE_OK;
+}
 
 extern "C" int ipmpde_batch_create(ipmpde_problem* const* probs, int count, ipmpde_batch** out) {
   if (!out) return fail(IPMPDE_EINVAL, "out is NULL");
@@ -2218,6 +2348,7 @@ extern "C" int ipmpde_batch_create(ipmpde_problem* const* probs, int count, ipmp
 extern "C" void ipmpde_batch_destroy(ipmpde_batch* B) {
   if (!B) return;
   (void)hipDeviceSynchronize();
+  batch_release_lanes(B);
   group_release(B->G);
   delete B;
 }
@@ -2232,9 +2363,11 @@ extern "C" int ipmpde_batch_solve(ipmpde_batch* B, const ipmpde_options* opts, i
     if (a.krylov != b.krylov || a.precond != b.precond || a.restart != b.restart || a.krylov_tol != b.krylov_tol ||
         a.krylov_maxit != b.krylov_maxit || a.nu_pre != b.nu_pre || a.nu_post != b.nu_post || a.omega != b.omega ||
         a.mg_precision != b.mg_precision || a.chunk != b.chunk || a.use_graphs != b.use_graphs || a.vcycles != b.vcycles ||
-        a.mg_tile != b.mg_tile)
-      return fail(IPMPDE_EINVAL, "Krylov and multigrid options must agree across a batch");
+        a.mg_tile != b.mg_tile || std::max(a.lanes, 1) != std::max(b.lanes, 1))
+      return fail(IPMPDE_EINVAL, "Krylov, multigrid and lane options must agree across a batch");
   }
+  const int L = std::min(std::max(po[0].lanes, 1), G->count);
+  if (L > 1) return batch_solve_lanes(B, po, L, S(stream));
   return solve_group(G, po, S(stream));
 }
 

@@ -73,6 +73,66 @@ def test_batch_3d_equals_solo(prec):
         p.close()
 
 
+@pytest.fixture(scope="module")
+def mixed_solo():
+    from paper_1806_05896_amd import Options, Problem
+    datas = _mixed(seed=3)
+    opts = [Options(sigma=d.sigma) for d in datas]
+    solo = []
+    for d, o in zip(datas, opts):
+        with Problem(d) as p:
+            rc = p.solve(o)
+            solo.append((rc, p.query("u"), p.stats()))
+    return datas, opts, solo
+
+
+@pytest.mark.parametrize("lanes", [2, 5, 16])
+def test_batch_lanes_equal_solo(lanes, mixed_solo):
+    """The instances split into lanes (sub-batches, each on a stream of its own and driven
+    by a host thread of its own; 16 is clamped to the batch's 12 instances) give each
+    member its solo result bit for bit, and so does the same batch solved again in one lane."""
+    from dataclasses import replace
+
+    from paper_1806_05896_amd import Batch, Problem
+    datas, opts, solo = mixed_solo
+    print(f"[lanes] {lanes} lanes, sizes {[d.N for d in datas]}", flush=True)
+    probs = [Problem(d) for d in datas]
+    with Batch(probs) as b:
+        for ln in (lanes, 1):
+            st = b.solve([replace(o, lanes=ln) for o in opts])
+            for k, (p, (rc, u, s)) in enumerate(zip(probs, solo)):
+                ub, sb = p.query("u"), p.stats()
+                print(f"  lanes {ln} member {k}: N={p.N} rc={rc}/{st[k]} its={s.krylov_its}/{sb.krylov_its}",
+                      flush=True)
+                assert st[k] == rc == 0
+                assert sb.nli == s.nli and sb.krylov_its == s.krylov_its
+                np.testing.assert_array_equal(ub, u)
+    for p in probs:
+        p.close()
+
+
+def test_autotuner_picks_lanes_and_keeps_results(mixed_solo, tmp_path):
+    """The autotuner times lane splits too; its pick solves every member to its solo result."""
+    from paper_1806_05896_amd import Batch, Options, Problem
+    datas, opts, solo = mixed_solo
+    datas, solo = datas[:4], solo[:4]
+    probs = [Problem(d) for d in datas]
+    with Batch(probs) as b:
+        best, ms, hit = b.autotune(Options(sigma=datas[0].sigma), cache=str(tmp_path / "tune.json"))
+        print(f"[lanes] autotuner pick {best} ({ms:.1f} ms, cache hit {hit})", flush=True)
+        assert not hit and 1 <= best.lanes <= 4
+        best2, _, hit2 = b.autotune(Options(sigma=datas[0].sigma), cache=str(tmp_path / "tune.json"))
+        assert hit2 and best2.lanes == best.lanes and best2.nu_pre == best.nu_pre
+        st = b.solve([Options(**{**best.__dict__, "sigma": d.sigma}) for d in datas])
+    for k, (p, (rc, u, s)) in enumerate(zip(probs, solo)):
+        if best.vcycles == 1 and best.nu_pre == 2 and best.mg_precision == "fp32":
+            assert st[k] == rc == 0 and p.stats().krylov_its == s.krylov_its
+            np.testing.assert_array_equal(p.query("u"), u)
+        else:
+            assert st[k] == 0
+        p.close()
+
+
 def test_batch_member_limits_do_not_leak():
     """One member with an IPM iteration limit of 2 stops early (ENOTCONVERGED);
     its batch-mates converge exactly as they would alone."""

@@ -48,6 +48,7 @@ def test_struct_layouts_match_header(lib):
     assert lib.ipmpde_default_options(C.byref(o)) == L.OK
     assert o.sigma == 0.2 and o.alpha0 == 0.995 and o.krylov_tol == 1e-10
     assert o.nu_pre == 2 and o.nu_post == 2 and o.restart == 30 and o.chunk == 8
+    assert o.lanes == 1
     assert lib.ipmpde_version().decode().startswith("libipmpde")
 
 
@@ -60,15 +61,15 @@ def test_binding_structs_match_the_c_compiler(tmp_path):
         pytest.skip("no C compiler")
     src = tmp_path / "layout.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "ipmpde.h"\n'
-                   'int main(void) { printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(ipmpde_options), '
+                   'int main(void) { printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(ipmpde_options), '
                    'offsetof(ipmpde_options, mu_rule), offsetof(ipmpde_options, mass_scaling), '
-                   'offsetof(ipmpde_options, mg_tile), '
+                   'offsetof(ipmpde_options, mg_tile), offsetof(ipmpde_options, lanes), '
                    'sizeof(ipmpde_stats), offsetof(ipmpde_stats, hist_krylov_relres)); return 0; }\n')
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     want = [C.sizeof(L.COptions), L.COptions.mu_rule.offset, L.COptions.mass_scaling.offset, L.COptions.mg_tile.offset,
-            C.sizeof(L.CStats), L.CStats.hist_krylov_relres.offset]
+            L.COptions.lanes.offset, C.sizeof(L.CStats), L.CStats.hist_krylov_relres.offset]
     assert got == want
 
 
