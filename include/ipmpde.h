@@ -408,8 +408,11 @@ int ipmpde_batch_time_kernel(ipmpde_batch* batch, const ipmpde_options* opts, in
  * problem can be queried and reused (its stats hold the outcome).  While a
  * problem is queued or running, every other entry point on it fails with
  * IPMPDE_EINVAL; destroying it then is undefined.  An engine is not
- * thread-safe; it issues all work on the stream passed to
- * ipmpde_engine_step and synchronises that stream before returning. */
+ * thread-safe.  ipmpde_engine_step runs the groups of different solver
+ * options concurrently, each on a stream of the engine's own (default
+ * priority) driven by a host thread of its own; they start after the work
+ * queued on the stream passed, that stream waits for all of them, and every
+ * group's stream has been synchronised when the call returns. */
 typedef struct ipmpde_engine ipmpde_engine;
 
 enum { IPMPDE_REQ_QUEUED = 0, IPMPDE_REQ_RUNNING = 1, IPMPDE_REQ_DONE = 2 };

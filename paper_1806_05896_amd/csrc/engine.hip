@@ -12,7 +12,9 @@
 // step, starting from its own initial point, so requests at different IPM
 // iterations share every launch.  Each request takes exactly the arithmetic
 // of a solo solve (per-instance reductions and kernel choices), so its
-// result does not depend on what else is in flight.
+// result does not depend on what else is in flight.  The groups of one step
+// run concurrently, each on a stream of its own driven by a host thread of
+// its own, so the latency-bound launches of one overlap those of another.
 
 using Clock = std::chrono::steady_clock;
 
@@ -32,8 +34,18 @@ struct EngineClass {
   int dim = 0;
   bool q1 = false;   // Q1 problems (a group holds them or none)
   Group* G = nullptr;
+  hipStream_t stream = nullptr;  // the class's stream (default priority), also its group's capture stream
+  hipEvent_t done = nullptr;     // the class's stream at the end of a step
+  bool any_fresh = false;        // a member still to be put at its starting point
   std::vector<EngineReq*> members;
 };
+
+static void engine_class_free(EngineClass* C) {
+  group_release(C->G);
+  if (C->stream) (void)hipStreamDestroy(C->stream);
+  if (C->done) (void)hipEventDestroy(C->done);
+  delete C;
+}
 
 struct ipmpde_engine {
   size_t budget = 0, in_use = 0, peak = 0;
@@ -43,6 +55,7 @@ struct ipmpde_engine {
   std::deque<EngineReq*> queue;
   std::vector<EngineClass*> classes;
   std::map<uint64_t, EngineReq*> reqs;
+  hipEvent_t start_ev = nullptr;  // the caller's stream at the start of a step
 };
 
 static bool same_solver(const ipmpde_options& a, const ipmpde_options& b) {
@@ -90,10 +103,8 @@ extern "C" void ipmpde_engine_destroy(ipmpde_engine* E) {
     if (R->state != IPMPDE_REQ_DONE) R->P->in_engine = false;
     delete R;
   }
-  for (EngineClass* C : E->classes) {
-    group_release(C->G);
-    delete C;
-  }
+  for (EngineClass* C : E->classes) engine_class_free(C);
+  if (E->start_ev) (void)hipEventDestroy(E->start_ev);
   delete E;
 }
 
@@ -139,13 +150,20 @@ static int engine_admit(ipmpde_engine* E) {
       C->o = R->o;
       C->dim = R->P->dim;
       C->q1 = q1;
-      const int rc = group_create({}, E->max_slots, C->dim, &C->G);
+      int rc = group_create({}, E->max_slots, C->dim, &C->G);
+      hipError_t e = hipSuccess;
+      if (rc == IPMPDE_OK && (e = hipStreamCreateWithFlags(&C->stream, hipStreamNonBlocking)) == hipSuccess)
+        e = hipEventCreateWithFlags(&C->done, hipEventDisableTiming);
+      if (rc == IPMPDE_OK && e != hipSuccess)
+        rc = fail(IPMPDE_EDEVICE, std::string("engine class setup: ") + hipGetErrorString(e));
       if (rc != IPMPDE_OK) {
-        delete C;
+        engine_class_free(C);
         E->queue.push_front(R);
         return rc;
       }
       C->G->q1 = q1;
+      C->G->cap_stream = C->stream;
+      C->G->own_cap = false;
       E->classes.push_back(C);
     }
     R->t_admit = Clock::now();
@@ -166,24 +184,34 @@ static int engine_admit(ipmpde_engine* E) {
   return IPMPDE_OK;
 }
 
-// One IPM iteration of every member of one class.
-static int engine_class_step(ipmpde_engine* E, EngineClass* C, hipStream_t s) {
+// The members and descriptors of one class for this step; runs on the
+// calling thread (group_select allocates the multigrid levels a member has
+// not used yet).
+static int engine_class_prepare(EngineClass* C) {
   Group* G = C->G;
   const int m = (int)C->members.size();
   G->probs.resize(m);
   G->count = m;
   G->zc = std::min(next_pow2(m), G->cap);
-  bool any_fresh = false;
+  C->any_fresh = false;
   for (int i = 0; i < m; ++i) {
     EngineReq* R = C->members[i];
     G->probs[i] = R->P;
     G->H[i].active = 1;
     G->H[i].mu = R->P->mu;
     G->H[i].alpha0 = R->o.alpha0;
-    any_fresh = any_fresh || R->fresh;
+    C->any_fresh = C->any_fresh || R->fresh;
   }
-  TRY(group_select(G, C->o));
-  if (any_fresh) {
+  return group_select(G, C->o);
+}
+
+// One IPM iteration of every member of one class on stream s; fin[i] >= 0
+// is the final status of a member that has finished.  Touches only the
+// class, its group and its members' problems.
+static int engine_class_run(EngineClass* C, hipStream_t s, std::vector<int>& fin) {
+  Group* G = C->G;
+  const int m = (int)C->members.size();
+  if (C->any_fresh) {
     // the starting point of the new members only
     for (int i = 0; i < m; ++i) {
       EngineReq* R = C->members[i];
@@ -206,7 +234,7 @@ static int engine_class_step(ipmpde_engine* E, EngineClass* C, hipStream_t s) {
   bool mean = false;
   for (const EngineReq* R : C->members) mean = mean || R->o.mu_rule == IPMPDE_MU_CENTRAL;
   TRY(group_measures(G, s, mean));
-  std::vector<int> fin(m, -1);
+  fin.assign(m, -1);
   int alive = 0;
   for (int i = 0; i < m; ++i) {
     fin[i] = ipm_check(G, i, C->members[i]->k, C->members[i]->o);
@@ -220,23 +248,73 @@ static int engine_class_step(ipmpde_engine* E, EngineClass* C, hipStream_t s) {
       C->members[i]->k += 1;
     }
   }
-  // the stream is idle here (group_step and group_measures end with a
-  // read-back), so finished members' workspace can go
+  return IPMPDE_OK;
+}
+
+// Retire the finished members (calling thread).  The class's stream is idle
+// here (group_step and group_measures end with a read-back), so their
+// workspace can go.
+static void engine_class_finish(ipmpde_engine* E, EngineClass* C, const std::vector<int>& fin) {
   std::vector<EngineReq*> keep;
-  for (int i = 0; i < m; ++i) {
-    if (fin[i] >= 0) engine_retire(E, C->members[i], fin[i]);
+  for (size_t i = 0; i < C->members.size(); ++i) {
+    if (i < fin.size() && fin[i] >= 0) engine_retire(E, C->members[i], fin[i]);
     else keep.push_back(C->members[i]);
   }
   C->members.swap(keep);
-  return IPMPDE_OK;
 }
 
 extern "C" int ipmpde_engine_step(ipmpde_engine* E, ipmpde_stream stream, int* running, int* queued) {
   if (!E) return fail(IPMPDE_EINVAL, "engine is NULL");
   hipStream_t s = S(stream);
   TRY(engine_admit(E));
+  std::vector<EngineClass*> act;
   for (EngineClass* C : E->classes)
-    if (!C->members.empty()) TRY(engine_class_step(E, C, s));
+    if (!C->members.empty()) act.push_back(C);
+  for (EngineClass* C : act) TRY(engine_class_prepare(C));
+  if (!act.empty()) {
+    if (!E->start_ev) HIP_TRY(hipEventCreateWithFlags(&E->start_ev, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(E->start_ev, s));
+    for (EngineClass* C : act) HIP_TRY(hipStreamWaitEvent(C->stream, E->start_ev, 0));
+    const size_t na = act.size();
+    std::vector<std::vector<int>> fin(na);
+    std::vector<int> rc(na, IPMPDE_OK);
+    std::vector<std::string> msg(na);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    auto run = [&](size_t k) {
+      if (k > 0) {
+        const hipError_t e = hipSetDevice(dev);
+        if (e != hipSuccess) {
+          rc[k] = IPMPDE_EDEVICE;
+          msg[k] = std::string("hipSetDevice: ") + hipGetErrorString(e);
+          return;
+        }
+      }
+      rc[k] = engine_class_run(act[k], act[k]->stream, fin[k]);
+      if (rc[k] != IPMPDE_OK) msg[k] = g_err;
+    };
+    std::vector<std::thread> th;
+    try {
+      for (size_t k = 1; k < na; ++k) th.emplace_back(run, k);
+    } catch (const std::exception& ex) {
+      for (size_t k = th.size() + 1; k < na; ++k) {
+        rc[k] = IPMPDE_EDEVICE;
+        msg[k] = std::string("cannot start a class thread: ") + ex.what();
+      }
+    }
+    run(0);
+    for (auto& t : th) t.join();
+    for (EngineClass* C : act) {
+      HIP_TRY(hipEventRecord(C->done, C->stream));
+      HIP_TRY(hipStreamWaitEvent(s, C->done, 0));
+    }
+    int first = -1;
+    for (size_t k = 0; k < na; ++k) {
+      if (rc[k] == IPMPDE_OK) engine_class_finish(E, act[k], fin[k]);
+      else if (first < 0) first = (int)k;
+    }
+    if (first >= 0) return fail(rc[first], msg[first]);
+  }
   E->steps += 1;
   if (running) *running = E->running;
   if (queued) *queued = (int)E->queue.size();
