@@ -33,6 +33,7 @@ struct EngineClass {
   ipmpde_options o;  // Krylov and multigrid options of every member
   int dim = 0;
   bool q1 = false;   // Q1 problems (a group holds them or none)
+  int band = 0;      // size band of the members (engine_band)
   Group* G = nullptr;
   hipStream_t stream = nullptr;  // the class's stream (default priority), also its group's capture stream
   hipEvent_t done = nullptr;     // the class's stream at the end of a step
@@ -64,6 +65,12 @@ static bool same_solver(const ipmpde_options& a, const ipmpde_options& b) {
          a.mg_precision == b.mg_precision && a.chunk == b.chunk && a.use_graphs == b.use_graphs &&
          a.vcycles == b.vcycles && a.mg_tile == b.mg_tile;
 }
+
+// Requests are grouped by size as well as by solver options: a group's
+// launches cover its largest member and each Krylov chunk runs until its
+// slowest member stops, so small requests beside large ones would wait on
+// them, while groups of different bands run concurrently.
+static int engine_band(const ipmpde_problem* P) { return P->n > 8192 ? 1 : 0; }
 
 static int next_pow2(int x) {
   int p = 1;
@@ -143,13 +150,15 @@ static int engine_admit(ipmpde_engine* E) {
     E->queue.pop_front();
     EngineClass* C = nullptr;
     const bool q1 = R->P->pde == IPMPDE_POISSON_Q1;
+    const int band = engine_band(R->P);
     for (EngineClass* c : E->classes)
-      if (c->dim == R->P->dim && c->q1 == q1 && same_solver(c->o, R->o)) C = c;
+      if (c->dim == R->P->dim && c->q1 == q1 && c->band == band && same_solver(c->o, R->o)) C = c;
     if (!C) {
       C = new EngineClass();
       C->o = R->o;
       C->dim = R->P->dim;
       C->q1 = q1;
+      C->band = band;
       int rc = group_create({}, E->max_slots, C->dim, &C->G);
       hipError_t e = hipSuccess;
       if (rc == IPMPDE_OK && (e = hipStreamCreateWithFlags(&C->stream, hipStreamNonBlocking)) == hipSuccess)
