@@ -199,7 +199,8 @@ constexpr int kCoarse3PerThread = (15 * 15 * 15 + kCoarseBS - 1) / kCoarseBS;
 template <typename T>
 __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse(const Inst* __restrict__ Dp, int transpose, int guard) {
   INST_BEGIN
-  if (I.coarse_p2 || I.pde == 1 || mg_skip(I, guard)) return;
+  // (3D finite-difference Poisson instances take k_mg_coarse_f3)
+  if (I.coarse_p2 || I.pde == 1 || (I.dim == 3 && I.pde == 0) || mg_skip(I, guard)) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ CoarseLevel LI[kMaxLev];
   T* lds = (T*)lds_raw;
