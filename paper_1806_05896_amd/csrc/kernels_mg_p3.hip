@@ -80,7 +80,8 @@ __global__ void __launch_bounds__(kBS) k_mg_down_p3(const Inst* __restrict__ Dp,
   int tx, ty, tz;
   xcd_cube(gx, tx, ty, tz);
   const int J1 = tx * TC, J2 = ty * TC, J3 = tz * TC;
-  if (J1 >= Nc || J2 >= Nc || J3 >= Nc) return;
+  // a cube owns fine nodes 2 J ... 2 J + 2 TC - 1 (the last fine node, 2 Nc, has no coarse node of its own)
+  if (J1 > Nc || J2 > Nc || J3 > Nc) return;
   constexpr int W = p3_down_width(NU, TC), WW = W * W;
   __shared__ T bs[W * WW], ds[W * WW], xa[W * WW], xb[W * WW];
   const int o1 = 2 * J1 - NU, o2 = 2 * J2 - NU, o3 = 2 * J3 - NU;  // fine coordinates of LDS (0, 0, 0)

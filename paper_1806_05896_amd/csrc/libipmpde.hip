@@ -1006,12 +1006,14 @@ static void mg_vcycle_2d(Group* G, int transpose, int guard, int scaled, hipStre
 template <typename T, int NU>
 static void launch_down_p3_nu(const Group* G, int l, int scaled, int guard, hipStream_t s) {
   const int Nc = G->maxN[l + 1];
+  // the cubes' own fine nodes 2 J ... 2 J + 2 TC - 1 must cover the N = 2 Nc + 1 fine nodes
 #define L_(TC)                                                                                                 \
   {                                                                                                            \
-    const int nt = div_up(Nc, TC);                                                                             \
+    const int nt = div_up(Nc + 1, TC);                                                                         \
     hipLaunchKernelGGL((k_mg_down_p3<T, NU, TC>), dim3(nt, nt * nt, G->zc), dim3(kBS), 0, s, G->D, l, scaled, \
                        guard);                                                                                 \
   }
+  // (5^3 coarse nodes per cube, 54 KB of LDS in FP32, measured slower: fewer workgroups fit a CU)
   if constexpr (p3_down_lds<T, NU, 4>() <= kStaticLdsMax) L_(4)  // else never called: p3_fits excludes it
 #undef L_
 }
