@@ -386,8 +386,9 @@ int ipmpde_batch_autotune(ipmpde_batch* batch, const ipmpde_options* base, int f
 
 /* ipmpde_time_kernel for a whole batch: one launch serves every instance;
  * *bytes sums the instances' algorithmic bytes.  Requires a Newton setup by
- * this batch (a batch solve) in the same multigrid precision; kernel 0 (the
- * saddle matvec on explicit vectors) is for single problems only. */
+ * this batch in one lane (a batch solve with lanes = 1) in the same
+ * multigrid precision (IPMPDE_EINVAL otherwise); kernel 0 (the saddle matvec
+ * on explicit vectors) is for single problems only. */
 int ipmpde_batch_time_kernel(ipmpde_batch* batch, const ipmpde_options* opts, int kernel, int reps,
                              ipmpde_stream stream, double* avg_ms, double* bytes);
 
