@@ -453,7 +453,7 @@ __global__ void __launch_bounds__(kBS) k_coarse_inv7(const Inst* __restrict__ Dp
   constexpr int M = kCoarseInvN, n = M * M, P = M + 2;
   int off7, end;
   coarse_p2_inv_offsets(I.lv[I.coarse_lev].N, I.nlev - I.coarse_lev, off7, end);
-  if (off7 < 0) return;
+  if (off7 < 0 || I.cpack_elems < end + n * n) return;  // no 7 x 7 level, or no room for its inverse
   T* img = (T*)I.cpack;
   const T* d = img + off7 + 2 * P * P + n;
   __shared__ double A[n * n], f[n];
@@ -1001,8 +1001,11 @@ template __global__ void k_mg_coarse_p2<double>(const Inst*, int);
 // first pre-smoothing sweep starts from zero) and never writes the zero
 // rings, so later steps copy only d and 1/d of each level.
 // d and 1/d of every level of the largest image, and per thread.
-constexpr int kHeatDD = 2 * (63 * 63 + 31 * 31 + 15 * 15 + 7 * 7 + 3 * 3 + 1);
-constexpr int kHeatDD64 = 2 * (31 * 31 + 15 * 15 + 7 * 7 + 3 * 3 + 1);  // FP64: widest 31 (p2_per_thread)
+// Per-step image elements the heat kernel reloads at every time step: the
+// levels' d and 1/d, and the inverse of the 7 x 7 level's operator.
+constexpr int kHeatInv = kCoarseInvN * kCoarseInvN * kCoarseInvN * kCoarseInvN;
+constexpr int kHeatDD = 2 * (63 * 63 + 31 * 31 + 15 * 15 + 7 * 7 + 3 * 3 + 1) + kHeatInv;
+constexpr int kHeatDD64 = 2 * (31 * 31 + 15 * 15 + 7 * 7 + 3 * 3 + 1) + kHeatInv;  // FP64: widest 31 (p2_per_thread)
 template <typename T>
 constexpr int heat_dd_per_thread() { return ((sizeof(T) == 8 ? kHeatDD64 : kHeatDD) + kCoarseBS - 1) / kCoarseBS; }
 
@@ -1039,8 +1042,13 @@ __global__ void __launch_bounds__(kCoarseBS) k_heat_sweep_p2(const Inst* __restr
     }
   }
   __syncthreads();
-  // image offsets of this thread's share of the levels' d and 1/d (-1: none),
-  // so that each step issues all its loads at once
+  // the inverse of each step's 7 x 7 level operator, when its image holds one
+  // (the V-cycle then solves that level exactly)
+  int off7, end;
+  coarse_p2_inv_offsets(N0, L, off7, end);
+  const bool inv = off7 >= 0 && I0.cpack_elems >= end + kHeatInv;
+  // image offsets of this thread's share of the levels' d and 1/d and of the
+  // inverse (-1: none), so that each step issues all its loads at once
   int ddo[heat_dd_per_thread<T>()];
 #pragma unroll
   for (int j = 0; j < heat_dd_per_thread<T>(); ++j) {
@@ -1053,6 +1061,8 @@ __global__ void __launch_bounds__(kCoarseBS) k_heat_sweep_p2(const Inst* __restr
       }
       e -= m;
     }
+    // past the levels e counts from their end (every level was subtracted)
+    if (o < 0 && inv && e < kHeatInv) o = end + e;
     ddo[j] = o;
   }
   // the next step's right-hand side and d, 1/d are loaded while the current
@@ -1099,7 +1109,7 @@ __global__ void __launch_bounds__(kCoarseBS) k_heat_sweep_p2(const Inst* __restr
     }
     __syncthreads();
     if (k + 1 < nt) prefetch(steps[dir > 0 ? t + 1 : t - 1]);
-    const T* a = coarse_p2_cycle<T, 5, false>(lds, LN, LOFF, LIH2, 0, L, om, nu_pre, nu_post);
+    const T* a = coarse_p2_cycle<T, 5, false>(lds, LN, LOFF, LIH2, 0, L, om, nu_pre, nu_post, inv ? lds + end : nullptr);
     T* xg = (T*)St.lv[0].x;
     {
       const int P = N0 + 2;

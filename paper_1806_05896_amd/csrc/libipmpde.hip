@@ -355,7 +355,8 @@ static int ensure_mg_heat(ipmpde_problem* P, bool fp32) {
   for (void*& a : (fp32 ? P->kc32 : P->kc64)) TRY(P->work.alloc(&a, (size_t)lv[0].n * el * nt));
   const int cl = pick_coarse(lv, P->nlev, el, 2, kCoarseP2);
   (fp32 ? P->coarse32 : P->coarse64) = cl;
-  int elems = 0;
+  // per step: the levels and the inverse of the 7 x 7 level's operator
+  int elems = (int)coarse_p2_tail(lv, P->nlev, kCoarseP2);
   for (int l = cl; l < P->nlev; ++l) elems += coarse_p2_elems(lv[l].N);
   void*& pk = fp32 ? P->cpack32 : P->cpack64;
   TRY(P->work.alloc(&pk, nt * elems * el));
@@ -1445,6 +1446,7 @@ static void heat_setup(Group* G, hipStream_t s) {
     for (int l = 0; l + 1 < V->max_nlev; ++l)
       hipLaunchKernelGGL(k_restrict_diag<T>, gz(V, V->maxn[l + 1]), dim3(kBS), 0, s, V->D, l);
     hipLaunchKernelGGL(k_coarse_pack<T>, gz(V, V->max_cpack), dim3(kBS), 0, s, V->D);
+    hipLaunchKernelGGL(k_coarse_inv7<T>, dim3(1, 1, V->zc), dim3(kBS), 0, s, V->D);
     V->zc = 1;
   }
 }
