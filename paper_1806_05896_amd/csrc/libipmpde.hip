@@ -1732,7 +1732,9 @@ extern "C" size_t ipmpde_footprint_bytes(const ipmpde_grid* grid, const ipmpde_p
   }
   bytes += 3 * A(n * el);  // k-cycle level-0 arrays
   bytes += A(kMaxLev * sizeof(Level));
-  if (grid->dim == 2 && (pde->kind == IPMPDE_POISSON || pde->kind == IPMPDE_POISSON_Q1)) {  // coarse LDS image
+  if (grid->dim == 2 && (pde->kind == IPMPDE_POISSON || pde->kind == IPMPDE_POISSON_Q1 ||
+                         pde->kind == IPMPDE_CONVDIFF)) {  // coarse LDS images, one per reaction-term slot
+    const int kind = pde->kind == IPMPDE_CONVDIFF ? kCoarseCD : kCoarseP2;
     Level lv[kMaxLev];
     int nlev = 0;
     for (int N = grid->n;; N = (N - 1) / 2) {
@@ -1741,7 +1743,10 @@ extern "C" size_t ipmpde_footprint_bytes(const ipmpde_grid* grid, const ipmpde_p
       ++nlev;
       if (N <= 1) break;
     }
-    bytes += A(kReactionSlots * coarse_lds_bytes(lv, nlev, pick_coarse(lv, nlev, el, 2, kCoarseP2), el, kCoarseP2));
+    const int cl = pick_coarse(lv, nlev, el, 2, kind);
+    size_t elems = coarse_p2_tail(lv, nlev, kind);
+    for (int l = cl; l < nlev; ++l) elems += coarse_level_elems(lv[l], kind);
+    bytes += A((size_t)kReactionSlots * cpack_stride((int)elems) * el);
   }
   if (o.krylov == IPMPDE_FGMRES) bytes += A((size_t)(o.restart + 1) * n4 * 8) + A((size_t)o.restart * n4 * 8);
   return bytes;
