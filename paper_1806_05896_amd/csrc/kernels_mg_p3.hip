@@ -18,6 +18,10 @@
 
 namespace ipm {
 
+// Threads per workgroup of the cube kernels (8 waves: a cube's phases are
+// latency bound, so more threads per cube shorten them).
+constexpr int kP3BS = 512;
+
 __host__ __device__ constexpr int p3_down_width(int nu, int tc) { return 2 * tc + 1 + 2 * nu; }
 __host__ __device__ constexpr int p3_up_width(int nu, int tf) { return tf + 2 * nu; }
 __host__ __device__ constexpr int p3_up_coarse_width(int nu, int tf) { return p3_up_width(nu, tf) / 2 + 2; }
@@ -60,7 +64,7 @@ __device__ __forceinline__ T p3_nb(const T* __restrict__ a, int li) {
 // side is (O + Theta_y) times level 0's x2 (the first solve's output); it is
 // also stored as level 0's b for the ascent.
 template <typename T, int NU, int TC>
-__global__ void __launch_bounds__(kBS) k_mg_down_p3(const Inst* __restrict__ Dp, int l, int scaled, int guard) {
+__global__ void __launch_bounds__(kP3BS) k_mg_down_p3(const Inst* __restrict__ Dp, int l, int scaled, int guard) {
   const Inst& I = Dp[blockIdx.z];
   int go = I.active;
   const int dim = I.dim, pde = I.pde, cl = I.coarse_lev;
@@ -91,7 +95,7 @@ __global__ void __launch_bounds__(kBS) k_mg_down_p3(const Inst* __restrict__ Dp,
   // the stop flag is requested with the cube's data and tested before the
   // first global store (the staging writes LDS only)
   const int f_stop = ctrl->stop, f_want = ctrl->want_restart;
-  for (int k = tid; k < W * WW; k += kBS) {
+  for (int k = tid; k < W * WW; k += kP3BS) {
     const int q3 = k / WW, q2 = (k - q3 * WW) / W, q1 = k - q3 * WW - q2 * W;
     const int g1 = o1 + q1, g2 = o2 + q2, g3 = o3 + q3;
     T bv = 0, dv = 0, wv = 0;
@@ -110,7 +114,7 @@ __global__ void __launch_bounds__(kBS) k_mg_down_p3(const Inst* __restrict__ Dp,
   if ((guard == 1 && f_stop) || (guard == 2 && !f_want)) return;
   __syncthreads();
   if (tyv) {
-    for (int k = tid; k < 8 * TC * TC * TC; k += kBS) {
+    for (int k = tid; k < 8 * TC * TC * TC; k += kP3BS) {
       const int r3 = k / (4 * TC * TC), r2 = (k / (2 * TC)) % (2 * TC), r1 = k % (2 * TC);
       const int g1 = 2 * J1 + r1, g2 = 2 * J2 + r2, g3 = 2 * J3 + r3;
       if (g1 < N && g2 < N && g3 < N) bfine[g1 + N * (g2 + N * g3)] = bs[(NU + r1) + W * (NU + r2) + WW * (NU + r3)];
@@ -121,7 +125,7 @@ __global__ void __launch_bounds__(kBS) k_mg_down_p3(const Inst* __restrict__ Dp,
 #pragma unroll
   for (int s = 1; s < NU; ++s) {
     const int w = W - 2 * s;  // the cube shrinks by one node per side per sweep
-    for (int k = tid; k < w * w * w; k += kBS) {
+    for (int k = tid; k < w * w * w; k += kP3BS) {
       const int r3 = k / (w * w), r2 = (k - r3 * w * w) / w, r1 = k - r3 * w * w - r2 * w;
       const int li = (r1 + s) + W * (r2 + s) + WW * (r3 + s);
       const T d = ds[li];
@@ -131,14 +135,14 @@ __global__ void __launch_bounds__(kBS) k_mg_down_p3(const Inst* __restrict__ Dp,
     __syncthreads();
     T* t = a; a = c; c = t;
   }
-  for (int k = tid; k < 8 * TC * TC * TC; k += kBS) {
+  for (int k = tid; k < 8 * TC * TC * TC; k += kP3BS) {
     const int r3 = k / (4 * TC * TC), r2 = (k / (2 * TC)) % (2 * TC), r1 = k % (2 * TC);
     const int g1 = 2 * J1 + r1, g2 = 2 * J2 + r2, g3 = 2 * J3 + r3;
     if (g1 < N && g2 < N && g3 < N) xfine[g1 + N * (g2 + N * g3)] = a[(NU + r1) + W * (NU + r2) + WW * (NU + r3)];
   }
   {
     constexpr int w = 2 * TC + 1;
-    for (int k = tid; k < w * w * w; k += kBS) {
+    for (int k = tid; k < w * w * w; k += kP3BS) {
       const int r3 = k / (w * w), r2 = (k - r3 * w * w) / w, r1 = k - r3 * w * w - r2 * w;
       const int li = (r1 + NU) + W * (r2 + NU) + WW * (r3 + NU);
       c[li] = bs[li] + ih2 * p3_nb<T, W>(a, li) - ds[li] * a[li];
@@ -146,7 +150,7 @@ __global__ void __launch_bounds__(kBS) k_mg_down_p3(const Inst* __restrict__ Dp,
   }
   __syncthreads();
   const T wt[3] = {(T)0.25, (T)0.5, (T)0.25};
-  for (int k = tid; k < TC * TC * TC; k += kBS) {
+  for (int k = tid; k < TC * TC * TC; k += kP3BS) {
     const int j3 = k / (TC * TC), j2 = (k / TC) % TC, j1 = k % TC;
     const int c1 = J1 + j1, c2 = J2 + j2, c3 = J3 + j3;
     if (c1 < Nc && c2 < Nc && c3 < Nc) {
@@ -168,7 +172,7 @@ __global__ void __launch_bounds__(kBS) k_mg_down_p3(const Inst* __restrict__ Dp,
 // (trilinear prolongation from a coarse patch staged in LDS), then NU
 // sweeps; writes the cube's own nodes to level l's x2.
 template <typename T, int NU, int TF>
-__global__ void __launch_bounds__(kBS) k_mg_up_p3(const Inst* __restrict__ Dp, int l, int guard) {
+__global__ void __launch_bounds__(kP3BS) k_mg_up_p3(const Inst* __restrict__ Dp, int l, int guard) {
   const Inst& I = Dp[blockIdx.z];
   int go = I.active;
   const int dim = I.dim, pde = I.pde, cl = I.coarse_lev;
@@ -200,14 +204,14 @@ __global__ void __launch_bounds__(kBS) k_mg_up_p3(const Inst* __restrict__ Dp, i
   const T om = (T)omega, om1 = (T)1 - om;
   const int tid = threadIdx.x;
   const int f_stop = ctrl->stop, f_want = ctrl->want_restart;
-  for (int k = tid; k < WC * WC * WC; k += kBS) {
+  for (int k = tid; k < WC * WC * WC; k += kP3BS) {
     const int p3 = k / (WC * WC), p2 = (k / WC) % WC, p1 = k % WC;
     const int c1 = cb1 + p1 - 1, c2 = cb2 + p2 - 1, c3 = cb3 + p3 - 1;  // 0-based coarse node
     cs[k] = ((unsigned)c1 < (unsigned)Nc && (unsigned)c2 < (unsigned)Nc && (unsigned)c3 < (unsigned)Nc)
                 ? xc[c1 + Nc * (c2 + Nc * c3)]
                 : (T)0;
   }
-  for (int k = tid; k < W * WW; k += kBS) {
+  for (int k = tid; k < W * WW; k += kP3BS) {
     const int q3 = k / WW, q2 = (k - q3 * WW) / W, q1 = k - q3 * WW - q2 * W;
     const int g1 = o1 + q1, g2 = o2 + q2, g3 = o3 + q3;
     T bv = 0, wv = 0, xv = 0;
@@ -224,7 +228,7 @@ __global__ void __launch_bounds__(kBS) k_mg_up_p3(const Inst* __restrict__ Dp, i
   // uniform over the workgroup
   if ((guard == 1 && f_stop) || (guard == 2 && !f_want)) return;
   __syncthreads();
-  for (int k = tid; k < W * WW; k += kBS) {
+  for (int k = tid; k < W * WW; k += kP3BS) {
     const int q3 = k / WW, q2 = (k - q3 * WW) / W, q1 = k - q3 * WW - q2 * W;
     const int g1 = o1 + q1, g2 = o2 + q2, g3 = o3 + q3;
     if ((unsigned)g1 < (unsigned)N && (unsigned)g2 < (unsigned)N && (unsigned)g3 < (unsigned)N) {
@@ -249,7 +253,7 @@ __global__ void __launch_bounds__(kBS) k_mg_up_p3(const Inst* __restrict__ Dp, i
 #pragma unroll
   for (int s = 1; s <= NU; ++s) {
     const int w = W - 2 * s;
-    for (int k = tid; k < w * w * w; k += kBS) {
+    for (int k = tid; k < w * w * w; k += kP3BS) {
       const int r3 = k / (w * w), r2 = (k - r3 * w * w) / w, r1 = k - r3 * w * w - r2 * w;
       const int li = (r1 + s) + W * (r2 + s) + WW * (r3 + s);
       c[li] = om1 * a[li] + ws[li] * (bs[li] + ih2 * p3_nb<T, W>(a, li));
@@ -257,7 +261,7 @@ __global__ void __launch_bounds__(kBS) k_mg_up_p3(const Inst* __restrict__ Dp, i
     __syncthreads();
     T* t = a; a = c; c = t;
   }
-  for (int k = tid; k < TF * TF * TF; k += kBS) {
+  for (int k = tid; k < TF * TF * TF; k += kP3BS) {
     const int r3 = k / (TF * TF), r2 = (k / TF) % TF, r1 = k % TF;
     const int g1 = tx * TF + r1, g2 = ty * TF + r2, g3 = tz * TF + r3;
     if (g1 < N && g2 < N && g3 < N) xout[g1 + N * (g2 + N * g3)] = a[(NU + r1) + W * (NU + r2) + WW * (NU + r3)];

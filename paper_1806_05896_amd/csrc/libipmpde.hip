@@ -1011,7 +1011,7 @@ static void launch_down_p3_nu(const Group* G, int l, int scaled, int guard, hipS
 #define L_(TC)                                                                                                 \
   {                                                                                                            \
     const int nt = div_up(Nc + 1, TC);                                                                         \
-    hipLaunchKernelGGL((k_mg_down_p3<T, NU, TC>), dim3(nt, nt * nt, G->zc), dim3(kBS), 0, s, G->D, l, scaled, \
+    hipLaunchKernelGGL((k_mg_down_p3<T, NU, TC>), dim3(nt, nt * nt, G->zc), dim3(kP3BS), 0, s, G->D, l, scaled, \
                        guard);                                                                                 \
   }
   // (5^3 coarse nodes per cube, 54 KB of LDS in FP32, measured slower: fewer workgroups fit a CU)
@@ -1025,7 +1025,7 @@ static void launch_up_p3_nu(const Group* G, int l, int guard, hipStream_t s) {
 #define L_(TF)                                                                                                     \
   {                                                                                                                \
     const int nt = div_up(N, TF);                                                                                  \
-    hipLaunchKernelGGL((k_mg_up_p3<T, NU, TF>), dim3(nt, nt * nt, G->zc), dim3(kBS), 0, s, G->D, l, guard);       \
+    hipLaunchKernelGGL((k_mg_up_p3<T, NU, TF>), dim3(nt, nt * nt, G->zc), dim3(kP3BS), 0, s, G->D, l, guard);       \
   }
   if constexpr (p3_up_lds<T, NU, 8>() <= kStaticLdsMax) L_(8)  // else never called: p3_fits excludes it
 #undef L_
