@@ -73,8 +73,8 @@ __device__ __forceinline__ float omega_over<float>(float om, float d) { return o
 // scaled (level 0 only): the right-hand side is (1 + Theta_y) times level 0's
 // x2 (the first solve's output); it is also stored as level 0's b for the
 // ascent.
-template <typename T, int NU, int TC, int ST = 5>
-__global__ void __launch_bounds__(kBS) k_mg_down_p2(const Inst* __restrict__ Dp, int l, int scaled, int guard, int nt,
+template <typename T, int NU, int TC, int ST = 5, int BS = kBS>
+__global__ void __launch_bounds__(BS) k_mg_down_p2(const Inst* __restrict__ Dp, int l, int scaled, int guard, int nt,
                                                     int tpw) {
   const Inst& I = Dp[blockIdx.z];
   int go = I.active;
@@ -96,7 +96,7 @@ __global__ void __launch_bounds__(kBS) k_mg_down_p2(const Inst* __restrict__ Dp,
   tile_run(gx, tpw, nt * nt, t0, t1);
   if (t0 >= t1) return;
   constexpr int W = p2_down_width(NU, TC);
-  constexpr int R = (W * W + kBS - 1) / kBS;  // staged nodes per thread
+  constexpr int R = (W * W + BS - 1) / BS;  // staged nodes per thread
   __shared__ T bs[W * W], ds[W * W], xa[W * W], xb[W * W];
   const T ih2 = p2l_scale<T, ST>(h), dg = p2l_diag<T, ST>(h);
   const T om = (T)omega, om1 = (T)1 - om;
@@ -111,7 +111,7 @@ __global__ void __launch_bounds__(kBS) k_mg_down_p2(const Inst* __restrict__ Dp,
     const int o1 = 2 * (t % nt) * TC - NU, o2 = 2 * (t / nt) * TC - NU;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const int k = tid + r * kBS;
+      const int k = tid + r * BS;
       const int q2 = k / W, q1 = k - q2 * W;
       const int g1 = o1 + q1, g2 = o2 + q2;
       if (k < W * W && (unsigned)g1 < (unsigned)N && (unsigned)g2 < (unsigned)N) {
@@ -135,7 +135,7 @@ __global__ void __launch_bounds__(kBS) k_mg_down_p2(const Inst* __restrict__ Dp,
       const int o1 = 2 * J1 - NU, o2 = 2 * J2 - NU;  // fine coordinates of LDS (0, 0)
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int k = tid + r * kBS;
+        const int k = tid + r * BS;
         if (k < W * W) {
           const int q2 = k / W, q1 = k - q2 * W;
           const int g1 = o1 + q1, g2 = o2 + q2;
@@ -156,7 +156,7 @@ __global__ void __launch_bounds__(kBS) k_mg_down_p2(const Inst* __restrict__ Dp,
     if (t + 1 < t1) fetch(t + 1);
     if (live) {
       if (tyv) {
-        for (int k = tid; k < 4 * TC * TC; k += kBS) {
+        for (int k = tid; k < 4 * TC * TC; k += BS) {
           const int r2 = k / (2 * TC), r1 = k - r2 * (2 * TC);
           const int g1 = 2 * J1 + r1, g2 = 2 * J2 + r2;
           if (g1 < N && g2 < N) bfine[g1 + N * g2] = bs[(NU + r1) + W * (NU + r2)];
@@ -167,7 +167,7 @@ __global__ void __launch_bounds__(kBS) k_mg_down_p2(const Inst* __restrict__ Dp,
 #pragma unroll
       for (int s = 1; s < NU; ++s) {
         const int w = W - 2 * s;  // the region shrinks by one node per sweep
-        for (int k = tid; k < w * w; k += kBS) {
+        for (int k = tid; k < w * w; k += BS) {
           const int r2 = k / w, r1 = k - r2 * w;
           const int li = (r1 + s) + W * (r2 + s);
           const T d = ds[li];
@@ -177,21 +177,21 @@ __global__ void __launch_bounds__(kBS) k_mg_down_p2(const Inst* __restrict__ Dp,
         __syncthreads();
         T* tmp = a; a = c; c = tmp;
       }
-      for (int k = tid; k < 4 * TC * TC; k += kBS) {
+      for (int k = tid; k < 4 * TC * TC; k += BS) {
         const int r2 = k / (2 * TC), r1 = k - r2 * (2 * TC);
         const int g1 = 2 * J1 + r1, g2 = 2 * J2 + r2;
         if (g1 < N && g2 < N) xfine[g1 + N * g2] = a[(NU + r1) + W * (NU + r2)];
       }
       {
         constexpr int w = 2 * TC + 1;
-        for (int k = tid; k < w * w; k += kBS) {
+        for (int k = tid; k < w * w; k += BS) {
           const int r2 = k / w, r1 = k - r2 * w;
           const int li = (r1 + NU) + W * (r2 + NU);
           c[li] = bs[li] + p2l_nb<T, ST>(a, li, W, ih2) - ds[li] * a[li];
         }
       }
       __syncthreads();
-      for (int k = tid; k < TC * TC; k += kBS) {
+      for (int k = tid; k < TC * TC; k += BS) {
         const int j2 = k / TC, j1 = k - j2 * TC;
         const int c1 = J1 + j1, c2 = J2 + j2;
         if (c1 < Nc && c2 < Nc) {
@@ -209,8 +209,8 @@ __global__ void __launch_bounds__(kBS) k_mg_down_p2(const Inst* __restrict__ Dp,
 // Ascent at level l for a tile of TF x TF fine nodes: x = x_pre + P x_c
 // (bilinear prolongation from a coarse patch staged in LDS), then NU sweeps;
 // writes the tile's own nodes to level l's x2.
-template <typename T, int NU, int TF, int ST = 5>
-__global__ void __launch_bounds__(kBS) k_mg_up_p2(const Inst* __restrict__ Dp, int l, int guard, int nt, int tpw) {
+template <typename T, int NU, int TF, int ST = 5, int BS = kBS>
+__global__ void __launch_bounds__(BS) k_mg_up_p2(const Inst* __restrict__ Dp, int l, int guard, int nt, int tpw) {
   const Inst& I = Dp[blockIdx.z];
   int go = I.active;
   const int kind = I.coarse_p2, cl = I.coarse_lev;
@@ -233,7 +233,7 @@ __global__ void __launch_bounds__(kBS) k_mg_up_p2(const Inst* __restrict__ Dp, i
   if (t0 >= t1) return;
   constexpr int W = p2_up_width(NU, TF);
   constexpr int WC = p2_up_coarse_width(NU, TF);
-  constexpr int R = (W * W + kBS - 1) / kBS, RC = (WC * WC + kBS - 1) / kBS;  // staged nodes per thread
+  constexpr int R = (W * W + BS - 1) / BS, RC = (WC * WC + BS - 1) / BS;  // staged nodes per thread
   __shared__ T bs[W * W], ws[W * W], xa[W * W], xb[W * W], cs[WC * WC];
   const T ih2 = p2l_scale<T, ST>(h), dg = p2l_diag<T, ST>(h);
   const T om = (T)omega, om1 = (T)1 - om;
@@ -250,14 +250,14 @@ __global__ void __launch_bounds__(kBS) k_mg_up_p2(const Inst* __restrict__ Dp, i
     const int cb1 = (o1 + 1) >> 1, cb2 = (o2 + 1) >> 1;
 #pragma unroll
     for (int r = 0; r < RC; ++r) {
-      const int k = tid + r * kBS;
+      const int k = tid + r * BS;
       const int p2 = k / WC, p1 = k - p2 * WC;
       const int c1 = cb1 + p1 - 1, c2 = cb2 + p2 - 1;  // 0-based coarse node
       rc[r] = (k < WC * WC && (unsigned)c1 < (unsigned)Nc && (unsigned)c2 < (unsigned)Nc) ? xc[c1 + Nc * c2] : (T)0;
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const int k = tid + r * kBS;
+      const int k = tid + r * BS;
       const int q2 = k / W, q1 = k - q2 * W;
       const int g1 = o1 + q1, g2 = o2 + q2;
       if (k < W * W && (unsigned)g1 < (unsigned)N && (unsigned)g2 < (unsigned)N) {
@@ -279,12 +279,12 @@ __global__ void __launch_bounds__(kBS) k_mg_up_p2(const Inst* __restrict__ Dp, i
     if (live) {
 #pragma unroll
       for (int r = 0; r < RC; ++r) {
-        const int k = tid + r * kBS;
+        const int k = tid + r * BS;
         if (k < WC * WC) cs[k] = rc[r];
       }
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int k = tid + r * kBS;
+        const int k = tid + r * BS;
         if (k < W * W) {
           const int q2 = k / W, q1 = k - q2 * W;
           const int g1 = o1 + q1, g2 = o2 + q2;
@@ -303,7 +303,7 @@ __global__ void __launch_bounds__(kBS) k_mg_up_p2(const Inst* __restrict__ Dp, i
     __syncthreads();
     if (t + 1 < t1) fetch(t + 1);
     if (live) {
-      for (int k = tid; k < W * W; k += kBS) {
+      for (int k = tid; k < W * W; k += BS) {
         const int q2 = k / W, q1 = k - q2 * W;
         const int g1 = o1 + q1, g2 = o2 + q2;
         if ((unsigned)g1 < (unsigned)N && (unsigned)g2 < (unsigned)N) {
@@ -326,7 +326,7 @@ __global__ void __launch_bounds__(kBS) k_mg_up_p2(const Inst* __restrict__ Dp, i
 #pragma unroll
       for (int s = 1; s <= NU; ++s) {
         const int w = W - 2 * s;
-        for (int k = tid; k < w * w; k += kBS) {
+        for (int k = tid; k < w * w; k += BS) {
           const int r2 = k / w, r1 = k - r2 * w;
           const int li = (r1 + s) + W * (r2 + s);
           c[li] = om1 * a[li] + ws[li] * (bs[li] + p2l_nb<T, ST>(a, li, W, ih2));
@@ -334,7 +334,7 @@ __global__ void __launch_bounds__(kBS) k_mg_up_p2(const Inst* __restrict__ Dp, i
         __syncthreads();
         T* tmp = a; a = c; c = tmp;
       }
-      for (int k = tid; k < TF * TF; k += kBS) {
+      for (int k = tid; k < TF * TF; k += BS) {
         const int r2 = k / TF, r1 = k - r2 * TF;
         const int g1 = tx * TF + r1, g2 = ty * TF + r2;
         if (g1 < N && g2 < N) xout[g1 + N * g2] = a[(NU + r1) + W * (NU + r2)];

@@ -906,6 +906,9 @@ static bool big_tiles(const Group* G, long groups) {
 // (runs of 8 / 4 / 2 tiles at the finest level): 512 workgroups 229.9 ms,
 // 1024 198.6 ms, 2048 189.3 ms, 4096 186.3 ms.
 static constexpr long kTileRunGroups = 4096;
+// Threads per workgroup of the large tiles (their regions hold 37^2 / 36^2
+// nodes, about three per thread per phase at 512 threads).
+static constexpr int kP2BigBS = 512;
 static int tile_run_length(int nt, int zc) {
   return std::max(1, div_up((long)nt * nt * zc, kTileRunGroups));
 }
@@ -917,8 +920,8 @@ static void launch_down_p2_nu(const Group* G, int l, int scaled, int guard, hipS
     const int nt = div_up(Nc, 16);
     if (big_tiles(G, (long)nt * nt * G->zc)) {
       const int tpw = tile_run_length(nt, G->zc);
-      hipLaunchKernelGGL((k_mg_down_p2<T, NU, 16, ST>), dim3(div_up((long)nt * nt, tpw), 1, G->zc), dim3(kBS), 0, s,
-                         G->D, l, scaled, guard, nt, tpw);
+      hipLaunchKernelGGL((k_mg_down_p2<T, NU, 16, ST, kP2BigBS>), dim3(div_up((long)nt * nt, tpw), 1, G->zc),
+                         dim3(kP2BigBS), 0, s, G->D, l, scaled, guard, nt, tpw);
       return;
     }
   }
@@ -935,8 +938,8 @@ static void launch_up_p2_nu(const Group* G, int l, int guard, hipStream_t s) {
     const int nt = div_up(N, 32);
     if (big_tiles(G, (long)nt * nt * G->zc)) {
       const int tpw = tile_run_length(nt, G->zc);
-      hipLaunchKernelGGL((k_mg_up_p2<T, NU, 32, ST>), dim3(div_up((long)nt * nt, tpw), 1, G->zc), dim3(kBS), 0, s,
-                         G->D, l, guard, nt, tpw);
+      hipLaunchKernelGGL((k_mg_up_p2<T, NU, 32, ST, kP2BigBS>), dim3(div_up((long)nt * nt, tpw), 1, G->zc),
+                         dim3(kP2BigBS), 0, s, G->D, l, guard, nt, tpw);
       return;
     }
   }
