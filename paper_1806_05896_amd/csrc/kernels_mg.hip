@@ -441,6 +441,27 @@ __host__ __device__ inline void coarse_p2_inv_offsets(int N0, int nl, int& off7,
   }
 }
 
+// In-place inverse of the n x n matrix A (row-major, FP64, in LDS) by
+// Gauss-Jordan elimination without pivoting (the coarse operators are
+// diagonally dominant M-matrices), by the kBS threads of the workgroup; f is
+// LDS scratch of n entries.
+template <int n>
+__device__ __forceinline__ void gauss_jordan_inverse(double* A, double* f) {
+  const int tid = threadIdx.x;
+  for (int k = 0; k < n; ++k) {
+    const double p = A[k * n + k];
+    __syncthreads();
+    for (int j = tid; j < n; j += kBS) A[k * n + j] = j == k ? 1.0 / p : A[k * n + j] / p;
+    for (int i = tid; i < n; i += kBS) f[i] = A[i * n + k];
+    __syncthreads();
+    for (int e = tid; e < n * n; e += kBS) {
+      const int i = e / n, j = e - i * n;
+      if (i != k) A[e] = j == k ? -f[i] * A[k * n + k] : A[e] - f[i] * A[k * n + j];
+    }
+    __syncthreads();
+  }
+}
+
 // The inverse of the 7 x 7 level's operator A + M_hat (the five-point or Q1
 // stencil divided by h^2 plus the reaction term, the image's diagonal d) by
 // Gauss-Jordan elimination in FP64 (symmetric positive definite: no
@@ -468,18 +489,7 @@ __global__ void __launch_bounds__(kBS) k_coarse_inv7(const Inst* __restrict__ Dp
     A[e] = r == c ? (double)d[r] : (nb ? off : 0.0);
   }
   __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    const double p = A[k * n + k];
-    __syncthreads();
-    for (int j = tid; j < n; j += kBS) A[k * n + j] = j == k ? 1.0 / p : A[k * n + j] / p;
-    for (int i = tid; i < n; i += kBS) f[i] = A[i * n + k];
-    __syncthreads();
-    for (int e = tid; e < n * n; e += kBS) {
-      const int i = e / n, j = e - i * n;
-      if (i != k) A[e] = j == k ? -f[i] * A[k * n + k] : A[e] - f[i] * A[k * n + j];
-    }
-    __syncthreads();
-  }
+  gauss_jordan_inverse<n>(A, f);
   T* inv = img + end;
   for (int e = tid; e < n * n; e += kBS) {
     const int i = e / n, j = e - i * n;
@@ -534,6 +544,53 @@ __global__ void __launch_bounds__(kBS) k_coarse_pack_cd(const Inst* __restrict__
 }
 template __global__ void k_coarse_pack_cd<float>(const Inst*);
 template __global__ void k_coarse_pack_cd<double>(const Inst*);
+
+// Offsets in a convection-diffusion coarse image of nl levels from width N0:
+// the 7 x 7 level (-1: none) and the end of the levels, where the inverse of
+// that level's operator follows (when the image has room for it).
+__host__ __device__ inline void coarse_cd_inv_offsets(int N0, int nl, int& off7, int& end) {
+  off7 = -1;
+  end = 0;
+  for (int q = 0, N = N0; q < nl; ++q, N = (N - 1) / 2) {
+    if (N == kCoarseInvN) off7 = end;
+    end += kCoarseCDArrays * N * N;
+  }
+}
+
+// The inverse of the 7 x 7 convection-diffusion level's operator (upwind
+// stencil plus reaction term, from the image's cd and neighbour
+// coefficients) by Gauss-Jordan in FP64, stored row-major after the image's
+// levels, once per Newton setup; the coarse V-cycle then solves that level
+// exactly, with the inverse or its transpose.
+template <typename T>
+__global__ void __launch_bounds__(kBS) k_coarse_inv7_cd(const Inst* __restrict__ Dp) {
+  INST_BEGIN
+  if (I.coarse_p2 || I.pde != 1 || !I.cpack) return;
+  constexpr int M = kCoarseInvN, n = M * M;
+  int off7, end;
+  coarse_cd_inv_offsets(I.lv[I.coarse_lev].N, I.nlev - I.coarse_lev, off7, end);
+  if (off7 < 0 || I.cpack_elems < end + n * n) return;
+  T* img = (T*)I.cpack;
+  const T* cf = img + off7 + 3 * n;  // cd | 1/cd | cW | cE | cS | cN
+  __shared__ double A[n * n], f[n];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < n * n; e += kBS) {
+    const int r = e / n, c = e - r * n, r1 = r % M;
+    double v = 0.0;
+    if (c == r) v = (double)cf[r];
+    else if (c == r - 1 && r1 > 0) v = (double)cf[2 * n + r];
+    else if (c == r + 1 && r1 < M - 1) v = (double)cf[3 * n + r];
+    else if (c == r - M) v = (double)cf[4 * n + r];
+    else if (c == r + M) v = (double)cf[5 * n + r];
+    A[e] = v;
+  }
+  __syncthreads();
+  gauss_jordan_inverse<n>(A, f);
+  T* inv = img + end;
+  for (int e = tid; e < n * n; e += kBS) inv[e] = (T)A[e];
+}
+template __global__ void k_coarse_inv7_cd<float>(const Inst*);
+template __global__ void k_coarse_inv7_cd<double>(const Inst*);
 
 // Loop over the nodes of an N x N level with NT threads (thread t), as P2_FOR.
 #define P2_FOR_T(NN, T_, NT_)                                                        \
@@ -879,15 +936,39 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_cd(const Inst* __restri
   // the top level's right-hand side over the image's zeros, each node by the
   // thread that owns it in the sweeps (the only thread that reads it back)
   if (own) lds[2 * N0 * N0 + j1 + N0 * j2] = breg;
+  // with the inverse of the 7 x 7 level's operator after the levels, the
+  // descent stops there and that level is solved exactly (A^-T b for the
+  // transposed operator)
+  constexpr int n7 = kCoarseInvN * kCoarseInvN;
+  int off7, end;
+  coarse_cd_inv_offsets(N0, L - cl, off7, end);
+  const bool inv = off7 >= 0 && elems >= end + n7 * n7;
+  int lx = L - 1;
+  if (inv)
+    for (int q = 0; q < L - cl; ++q)
+      if (((N0 + 1) >> q) - 1 == kCoarseInvN) lx = cl + q;
   unsigned alt = 0;  // bit l: level l's iterate sits in x2
-  for (int l = cl; l < L - 1; ++l) cd_down<T, kCoarseBS>(lds, LN, LOFF, l, tid, om, nu_pre, tr, alt);
-  {
+  for (int l = cl; l < lx; ++l) cd_down<T, kCoarseBS>(lds, LN, LOFF, l, tid, om, nu_pre, tr, alt);
+  if (inv) {
+    // with no descent before it the right-hand side was written by the
+    // threads owning its nodes, not by the rows' threads here
+    if (lx == cl) __syncthreads();
+    T* X = lds + LOFF[lx];
+    const T* B = X + 2 * n7;
+    const T* Ai = lds + end;
+    if (tid < n7) {
+      T acc = 0;
+      for (int c = 0; c < n7; ++c) acc += (tr ? Ai[c * n7 + tid] : Ai[tid * n7 + c]) * B[c];
+      X[tid] = acc;
+    }
+    __syncthreads();
+  } else {
     const int N = LN[L - 1], n = N * N;
     T* X = lds + LOFF[L - 1];
     P2_FOR(N) X[i] = X[2 * n + i] * X[4 * n + i]; P2_END
     __syncthreads();
   }
-  for (int l = L - 2; l >= cl; --l) cd_up<T, kCoarseBS>(lds, LN, LOFF, l, tid, om, nu_post, tr, alt);
+  for (int l = lx - 1; l >= cl; --l) cd_up<T, kCoarseBS>(lds, LN, LOFF, l, tid, om, nu_post, tr, alt);
   const int N = LN[cl];
   const T* xs = lds + LOFF[cl] + ((alt >> cl) & 1u) * N * N;
   P2_FOR(N) xg[i] = xs[i]; P2_END

@@ -255,7 +255,7 @@ static int coarse_max_N(int dim, int kind) {
 // Elements of the 2D Poisson coarse image after its levels: the inverse of
 // the 7 x 7 level's operator when the hierarchy has that level.
 static size_t coarse_p2_tail(const Level* lv, int nlev, int kind) {
-  if (kind != kCoarseP2) return 0;
+  if (kind != kCoarseP2 && kind != kCoarseCD) return 0;
   for (int l = 0; l < nlev; ++l)
     if (lv[l].N == kCoarseInvN) return (size_t)kCoarseInvN * kCoarseInvN * kCoarseInvN * kCoarseInvN;
   return 0;
@@ -403,6 +403,7 @@ static int ensure_mg(ipmpde_problem* P, bool fp32) {
       elems = (int)coarse_p2_tail(lv, P->nlev, kCoarseP2);
       for (int l = cl; l < P->nlev; ++l) elems += coarse_p2_elems(lv[l].N);
     } else {
+      elems = (int)coarse_p2_tail(lv, P->nlev, kCoarseCD);
       for (int l = cl; l < P->nlev; ++l) elems += (int)coarse_level_elems(lv[l], kCoarseCD);
     }
     void*& pk = fp32 ? P->cpack32 : P->cpack64;
@@ -1418,7 +1419,10 @@ static void coarse_image(Group* G, hipStream_t s) {
     hipLaunchKernelGGL(k_coarse_pack<T>, gz(G, G->max_cpack), dim3(kBS), 0, s, G->D);
     hipLaunchKernelGGL(k_coarse_inv7<T>, dim3(1, 1, G->zc), dim3(kBS), 0, s, G->D);
   }
-  if (G->cd) hipLaunchKernelGGL(k_coarse_pack_cd<T>, gz(G, G->max_cpack), dim3(kBS), 0, s, G->D);
+  if (G->cd) {
+    hipLaunchKernelGGL(k_coarse_pack_cd<T>, gz(G, G->max_cpack), dim3(kBS), 0, s, G->D);
+    hipLaunchKernelGGL(k_coarse_inv7_cd<T>, dim3(1, 1, G->zc), dim3(kBS), 0, s, G->D);
+  }
 }
 
 // P_Pi's extra operators: M_l (slot 1, written at level 0 by the Newton setup)
