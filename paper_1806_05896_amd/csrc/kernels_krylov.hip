@@ -318,21 +318,42 @@ __global__ void __launch_bounds__(kBS) k_cheb_block(const Inst* __restrict__ Dp,
 // and x_1.  r and d sit in the q workspace by the parity of k (in: k & 1,
 // out: the other), so no thread overwrites a value another still reads.
 // Operands and guard as for k_cheb_block.
+// Blocks of the 3D step: 16 x 4 x 4 nodes per workgroup (one per thread),
+// their d with a one-node halo staged in LDS (zero outside the grid), so the
+// 27-point mass is summed from LDS with no boundary tests or divisions.
+constexpr int kCb1 = 16, kCb2 = 4, kCb3 = 4;
+static_assert(kCb1 * kCb2 * kCb3 == kBS, "one node per thread");
+__host__ __device__ constexpr int cheb3_blocks(int N) {
+  return ((N + kCb1 - 1) / kCb1) * ((N + kCb2 - 1) / kCb2) * ((N + kCb3 - 1) / kCb3);
+}
+
 __global__ void __launch_bounds__(kBS) k_cheb_step3(const Inst* __restrict__ Dp, const double* __restrict__ rx,
                                                     double* __restrict__ zx, int j, int mpar, int k, ChebCoef cf,
                                                     int guard) {
   INST_BEGIN
   if ((guard == 1 && I.ctrl->stop) || (guard == 2 && !I.ctrl->want_restart)) return;
-  const int n = I.n;
-  const int i = xcd_node(n);  // each XCD sweeps a contiguous range: the neighbour planes stay in its L2
-  if (i >= n) return;
+  const int n = I.n, N = I.N;
+  // the launch's blocks are dispatched round-robin over the 8 XCDs: XCD x
+  // takes the x-th contiguous eighth (a slab of block layers), so the
+  // neighbouring planes of d stay in its L2
+  int b = blockIdx.x;
+  if ((gridDim.x & 7) == 0) b = (b & 7) * (gridDim.x >> 3) + (b >> 3);
+  const int nb1 = (N + kCb1 - 1) / kCb1, nb2 = (N + kCb2 - 1) / kCb2;
+  if (b >= cheb3_blocks(N)) return;
+  const int b1 = b % nb1, bq = b / nb1, b2 = bq % nb2, b3 = bq / nb2;
+  const int tid = threadIdx.x;
+  const int t1 = tid % kCb1, t2 = (tid / kCb1) % kCb2, t3 = tid / (kCb1 * kCb2);
+  const int i1 = b1 * kCb1 + t1, i2 = b2 * kCb2 + t2, i3 = b3 * kCb3 + t3;
+  const bool own = i1 < N && i2 < N && i3 < N;
+  const int i = own ? i1 + N * (i2 + N * i3) : 0;
   const double* r = mpar >= 0 ? I.V[1 - mpar] : (rx ? rx : I.fV + (size_t)j * 4 * n);
   double* z = mpar >= 0 ? I.Z[1 - mpar] : (zx ? zx : I.fZ + (size_t)j * 4 * n);
   const int in = k & 1, out = 1 - in;
   double* dout = I.Q + (size_t)(2 + out) * n;
-  const double ty = I.ty[i];
+  const double ty = own ? I.ty[i] : 0.0;
   const double iv = 1.0 / (kQ1MassDiag3 + ty);
   if (k == 0) {
+    if (!own) return;
     const double d0 = r[i] * iv / cf.theta;
     dout[i] = d0;
     z[i] = d0;
@@ -340,10 +361,36 @@ __global__ void __launch_bounds__(kBS) k_cheb_step3(const Inst* __restrict__ Dp,
   }
   const double* rin = k == 1 ? r : I.Q + (size_t)in * n;
   const double* din = I.Q + (size_t)(2 + in) * n;
-  int i1, i2, i3;
-  node_coords(i, I.N, 3, i1, i2, i3);
-  const double dv = din[i];
-  const double res = rin[i] - (q1_mass3<double>(din, i, i1, i2, i3, I.N) + ty * dv);
+  constexpr int H1 = kCb1 + 2, H2 = kCb2 + 2, H3 = kCb3 + 2;
+  __shared__ double sd[H1 * H2 * H3];
+  for (int e = tid; e < H1 * H2 * H3; e += kBS) {
+    const int e1 = e % H1, e2 = (e / H1) % H2, e3 = e / (H1 * H2);
+    const int g1 = b1 * kCb1 - 1 + e1, g2 = b2 * kCb2 - 1 + e2, g3 = b3 * kCb3 - 1 + e3;
+    sd[e] = ((unsigned)g1 < (unsigned)N && (unsigned)g2 < (unsigned)N && (unsigned)g3 < (unsigned)N)
+                ? din[g1 + N * (g2 + N * g3)]
+                : 0.0;
+  }
+  __syncthreads();
+  if (!own) return;
+  // the 27-point mass in the order of q1_mass3 (off-grid neighbours are zeros here)
+  const int li = (t1 + 1) + H1 * ((t2 + 1) + H2 * (t3 + 1));
+  double f = 0, e = 0, c = 0;
+#pragma unroll
+  for (int o3 = -1; o3 <= 1; ++o3)
+#pragma unroll
+    for (int o2 = -1; o2 <= 1; ++o2)
+#pragma unroll
+      for (int o1 = -1; o1 <= 1; ++o1) {
+        const int kk = (o1 != 0) + (o2 != 0) + (o3 != 0);
+        if (kk == 0) continue;
+        const double v = sd[li + o1 + H1 * (o2 + H2 * o3)];
+        if (kk == 1) f += v;
+        else if (kk == 2) e += v;
+        else c += v;
+      }
+  const double dv = sd[li];
+  const double mass = (64.0 * dv + 16.0 * f + 4.0 * e + c) * (1.0 / 216.0);
+  const double res = rin[i] - (mass + ty * dv);
   const double dn = cf.rho[k] * cf.rho[k - 1] * dv + (2.0 * cf.rho[k] / cf.delta) * res * iv;
   I.Q[(size_t)out * n + i] = res;
   dout[i] = dn;

@@ -1177,8 +1177,9 @@ static void cheb_apply(Group* G, const double* x, double* y, int j, int mpar, in
   cf.rho[0] = cf.delta / cf.theta;
   for (int k = 1; k < kChebSteps; ++k) cf.rho[k] = 1.0 / (2.0 * cf.theta / cf.delta - cf.rho[k - 1]);
   if (G->dim == 3) {
+    const int nb = (cheb3_blocks(G->maxN[0]) + 7) & ~7;  // a multiple of 8 for the XCD slabs
     for (int k = 0; k < kChebSteps; ++k)
-      hipLaunchKernelGGL(k_cheb_step3, gz(G, G->max_n), dim3(kBS), 0, s, G->D, x, y, j, mpar, k, cf, guard);
+      hipLaunchKernelGGL(k_cheb_step3, dim3(nb, 1, G->zc), dim3(kBS), 0, s, G->D, x, y, j, mpar, k, cf, guard);
     return;
   }
   const int nt = div_up(G->maxN[0], kChebTile);
