@@ -124,6 +124,100 @@ __global__ void __launch_bounds__(kBS) k_mg_resid(const Inst* __restrict__ Dp, i
                                       F.h, I.eps, transpose != 0);
 }
 
+// The same Jacobi sweep and residual for the 3D finite-difference and Q1
+// levels in blocks of 16 x 4 x 4 nodes (one per thread): the block's input
+// iterate with a one-node halo is staged in LDS (zero outside the grid), so
+// the 7- or 27-point stencil is summed from LDS with no boundary tests or
+// divisions, in the order of apply_op_s (the values are the same).
+constexpr int kMb1 = 16, kMb2 = 4, kMb3 = 4;
+static_assert(kMb1 * kMb2 * kMb3 == kBS, "one node per thread");
+__host__ __device__ constexpr int mg3_blocks(int N) {
+  return ((N + kMb1 - 1) / kMb1) * ((N + kMb2 - 1) / kMb2) * ((N + kMb3 - 1) / kMb3);
+}
+// (A x) at the block node li of the staged tile (pitches H1, H1*H2) for the
+// 3D 7-point (pde 0) or Q1 27-point (pde 3) operator.
+template <typename T, int H1, int H2>
+__device__ __forceinline__ T mg3_apply(const T* __restrict__ a, int li, int pde, double h) {
+  if (pde == 0) {
+    const T ih2 = (T)(1.0 / (h * h));
+    T nb = 0;
+    nb += a[li - 1];
+    nb += a[li + 1];
+    nb += a[li - H1];
+    nb += a[li + H1];
+    nb += a[li - H1 * H2];
+    nb += a[li + H1 * H2];
+    return ih2 * ((T)6 * a[li] - nb);
+  }
+  T e = 0, c = 0;
+#pragma unroll
+  for (int o3 = -1; o3 <= 1; ++o3)
+#pragma unroll
+    for (int o2 = -1; o2 <= 1; ++o2)
+#pragma unroll
+      for (int o1 = -1; o1 <= 1; ++o1) {
+        const int k = (o1 != 0) + (o2 != 0) + (o3 != 0);
+        if (k < 2) continue;
+        const T v = a[li + o1 + H1 * (o2 + H2 * o3)];
+        if (k == 2) e += v;
+        else c += v;
+      }
+  return (T)(1.0 / (h * h)) * ((T)(8.0 / 3.0) * a[li] - (T)(1.0 / 6.0) * e - (T)(1.0 / 12.0) * c);
+}
+// mode 0: Jacobi sweep (first: from a zero iterate) into x[dst]; mode 1: the
+// residual b - (A + mh) x[src] into x[dst].
+template <typename T>
+__global__ void __launch_bounds__(kBS) k_mg_level3(const Inst* __restrict__ Dp, int l, int src, int dst, int first,
+                                                   int mode, int guard) {
+  INST_BEGIN
+  if (l >= I.coarse_lev || mg_skip(I, guard)) return;
+  const Level& L = I.lv[l];
+  const int N = L.N, pde = I.pde;
+  int b = blockIdx.x;
+  if ((gridDim.x & 7) == 0) b = (b & 7) * (gridDim.x >> 3) + (b >> 3);  // a slab of block layers per XCD
+  if (b >= mg3_blocks(N)) return;
+  const int nb1 = (N + kMb1 - 1) / kMb1, nb2 = (N + kMb2 - 1) / kMb2;
+  const int b1 = b % nb1, bq = b / nb1, b2 = bq % nb2, b3 = bq / nb2;
+  const int tid = threadIdx.x;
+  const int t1 = tid % kMb1, t2 = (tid / kMb1) % kMb2, t3 = tid / (kMb1 * kMb2);
+  const int i1 = b1 * kMb1 + t1, i2 = b2 * kMb2 + t2, i3 = b3 * kMb3 + t3;
+  const bool own = i1 < N && i2 < N && i3 < N;
+  const int i = own ? i1 + N * (i2 + N * i3) : 0;
+  const T* __restrict__ xin = lvbuf<T>(L, src);
+  T* __restrict__ xout = lvbuf<T>(L, dst);
+  const T* __restrict__ bv = (const T*)L.b;
+  const T* __restrict__ mh = (const T*)L.mh;
+  const double h = L.h;
+  const T om = (T)I.omega;
+  if (mode == 0 && first) {
+    if (!own) return;
+    const T d = (T)op_diag(3, pde, h, I.eps, i1, i2) + mh[i];
+    xout[i] = om * bv[i] / d;
+    return;
+  }
+  constexpr int H1 = kMb1 + 2, H2 = kMb2 + 2, H3 = kMb3 + 2;
+  __shared__ T sx[H1 * H2 * H3];
+  for (int e = tid; e < H1 * H2 * H3; e += kBS) {
+    const int e1 = e % H1, e2 = (e / H1) % H2, e3 = e / (H1 * H2);
+    const int g1 = b1 * kMb1 - 1 + e1, g2 = b2 * kMb2 - 1 + e2, g3 = b3 * kMb3 - 1 + e3;
+    sx[e] = ((unsigned)g1 < (unsigned)N && (unsigned)g2 < (unsigned)N && (unsigned)g3 < (unsigned)N)
+                ? xin[g1 + N * (g2 + N * g3)]
+                : (T)0;
+  }
+  __syncthreads();
+  if (!own) return;
+  const int li = (t1 + 1) + H1 * ((t2 + 1) + H2 * (t3 + 1));
+  const T m = mh[i];
+  const T xi = sx[li];
+  const T Ax = mg3_apply<T, H1, H2>(sx, li, pde, h) + m * xi;
+  if (mode == 1) {
+    xout[i] = bv[i] - Ax;
+    return;
+  }
+  const T d = (T)op_diag(3, pde, h, I.eps, i1, i2) + m;
+  xout[i] = xi + om * (bv[i] - Ax) / d;
+}
+
 // Full-weighting restriction of level l's residual (in x[src]) to level
 // l + 1's right-hand side: weights 1/4, 1/2, 1/4 per axis around fine node
 // 2j + 1 (0-based) of coarse node j.
@@ -1330,6 +1424,7 @@ __global__ void __launch_bounds__(kBS) k_mg_kc_final(const Inst* __restrict__ Dp
   template __global__ void k_mg_kc_final<T>(const Inst*, int, int, int);              \
   template __global__ void k_mg_jacobi<T>(const Inst*, int, int, int, int, int, int); \
   template __global__ void k_mg_resid<T>(const Inst*, int, int, int, int, int);       \
+  template __global__ void k_mg_level3<T>(const Inst*, int, int, int, int, int, int); \
   template __global__ void k_mg_restrict_r<T>(const Inst*, int, int, int);           \
   template __global__ void k_mg_prolong<T>(const Inst*, int, int, int, int);          \
   template __global__ void k_mg_coarse<T>(const Inst*, int, int);                     \
