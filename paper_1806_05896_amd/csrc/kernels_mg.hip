@@ -16,32 +16,6 @@ namespace ipm {
 
 // ---------------------------------------------------------------- per-node pieces
 
-// Jacobi update at node i of level (N, h): x_out = x_in + omega (b - (A + mh) x_in) / d,
-// or omega b / d from a zero iterate.
-template <typename T, bool SMALL = false>
-__device__ __forceinline__ T jacobi_node(const T* __restrict__ xin, const T* __restrict__ b, const T* __restrict__ mh,
-                                         int i, int N, int dim, int pde, double h, double eps, double omega,
-                                         bool first, bool transpose) {
-  int i1, i2, i3;
-  if (SMALL) node_coords_small(i, N, dim, i1, i2, i3);
-  else node_coords(i, N, dim, i1, i2, i3);
-  const T m = mh[i];
-  const T d = (T)op_diag(dim, pde, h, eps, i1, i2) + m;
-  if (first) return (T)omega * b[i] / d;
-  const T xi = xin[i];
-  const T Ax = apply_op<T>(xin, i, i1, i2, i3, N, dim, pde, h, eps, transpose) + m * xi;
-  return xi + (T)omega * (b[i] - Ax) / d;
-}
-
-// Residual b - (A + mh) x at fine node (i1, i2, i3).
-template <typename T>
-__device__ __forceinline__ T resid_node(const T* __restrict__ x, const T* __restrict__ b, const T* __restrict__ mh,
-                                        int i1, int i2, int i3, int N, int dim, int pde, double h, double eps,
-                                        bool transpose) {
-  const int i = i1 + N * (i2 + N * i3);
-  return b[i] - (apply_op<T>(x, i, i1, i2, i3, N, dim, pde, h, eps, transpose) + mh[i] * x[i]);
-}
-
 // Bilinear/trilinear interpolation of the coarse correction at fine node i.
 template <typename T, bool SMALL = false>
 __device__ __forceinline__ T prolong_node(const T* __restrict__ xc, int i, int Nf, int Nc, int dim) {
@@ -94,38 +68,11 @@ __device__ __forceinline__ T* lvbuf(const Level& L, int sel) {
 }
 
 // One damped Jacobi sweep at level l (3D path): x[dst] = sweep(x[src]).
-template <typename T>
-__global__ void __launch_bounds__(kBS) k_mg_jacobi(const Inst* __restrict__ Dp, int l, int src, int dst, int first,
-                                                   int transpose, int guard) {
-  INST_BEGIN
-  if (l >= I.coarse_lev || mg_skip(I, guard)) return;
-  const Level& L = I.lv[l];
-  const int i = xcd_node(L.n);  // contiguous node ranges per XCD: neighbour planes stay in its L2
-  if (i >= L.n) return;
-  lvbuf<T>(L, dst)[i] = jacobi_node<T>(lvbuf<T>(L, src), (const T*)L.b, (const T*)L.mh, i, L.N, I.dim, I.pde, L.h,
-                                       I.eps, I.omega, first != 0, transpose != 0);
-}
-
-// Residual b - (A + mh) x[src] of level l at every node, into x[dst] (the
-// iterate buffer the pre-smoothing left free; the post-smoothing overwrites
-// it).  One node per thread: the residual is evaluated once per fine node
-// instead of once per coarse node that weights it.
-template <typename T>
-__global__ void __launch_bounds__(kBS) k_mg_resid(const Inst* __restrict__ Dp, int l, int src, int dst, int transpose,
-                                                  int guard) {
-  INST_BEGIN
-  if (l >= I.coarse_lev || mg_skip(I, guard)) return;
-  const Level& F = I.lv[l];
-  const int i = xcd_node(F.n);
-  if (i >= F.n) return;
-  int i1, i2, i3;
-  node_coords(i, F.N, I.dim, i1, i2, i3);
-  lvbuf<T>(F, dst)[i] = resid_node<T>(lvbuf<T>(F, src), (const T*)F.b, (const T*)F.mh, i1, i2, i3, F.N, I.dim, I.pde,
-                                      F.h, I.eps, transpose != 0);
-}
-
-// The same Jacobi sweep and residual for the 3D finite-difference and Q1
-// levels in blocks of 16 x 4 x 4 nodes (one per thread): the block's input
+// Damped-Jacobi sweep (x_out = x_in + omega (b - (A + mh) x_in) / d, or
+// omega b / d from a zero iterate) and residual b - (A + mh) x of the 3D
+// finite-difference and Q1 levels, into the iterate buffer dst (for the
+// residual the one the pre-smoothing left free, which the post-smoothing
+// overwrites), in blocks of 16 x 4 x 4 nodes (one per thread): the block's input
 // iterate with a one-node halo is staged in LDS (zero outside the grid), so
 // the 7- or 27-point stencil is summed from LDS with no boundary tests or
 // divisions, in the order of apply_op_s (the values are the same).
@@ -1422,8 +1369,6 @@ __global__ void __launch_bounds__(kBS) k_mg_kc_final(const Inst* __restrict__ Dp
 #define IPM_MG_INST(T)                                                              \
   template __global__ void k_mg_kc_resid<T>(const Inst*, int, int, int, int);         \
   template __global__ void k_mg_kc_final<T>(const Inst*, int, int, int);              \
-  template __global__ void k_mg_jacobi<T>(const Inst*, int, int, int, int, int, int); \
-  template __global__ void k_mg_resid<T>(const Inst*, int, int, int, int, int);       \
   template __global__ void k_mg_level3<T>(const Inst*, int, int, int, int, int, int); \
   template __global__ void k_mg_restrict_r<T>(const Inst*, int, int, int);           \
   template __global__ void k_mg_prolong<T>(const Inst*, int, int, int, int);          \

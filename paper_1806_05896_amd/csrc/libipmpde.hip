@@ -850,12 +850,10 @@ static void launch_coarse(Group* G, int transpose, int guard, hipStream_t s) {
 template <typename T>
 static void mg_vcycle_generic(Group* G, int transpose, int guard, hipStream_t s) {
   const int nu_pre = G->H[0].nu_pre, nu_post = G->H[0].nu_post;
-  // 3D levels: the LDS-blocked sweep and residual (the same values)
-  const bool b3 = G->dim == 3;
+  // the LDS-blocked sweep and residual (the 3D operators are symmetric: transpose changes nothing)
   auto g3 = [&](int l) { return dim3((mg3_blocks(G->maxN[l]) + 7) & ~7, 1, G->zc); };
   auto sweep = [&](int l, int a, int c, int first) {
-    if (b3) hipLaunchKernelGGL(k_mg_level3<T>, g3(l), dim3(kBS), 0, s, G->D, l, a, c, first, 0, guard);
-    else hipLaunchKernelGGL(k_mg_jacobi<T>, gz(G, G->maxn[l]), dim3(kBS), 0, s, G->D, l, a, c, first, transpose, guard);
+    hipLaunchKernelGGL(k_mg_level3<T>, g3(l), dim3(kBS), 0, s, G->D, l, a, c, first, 0, guard);
   };
   for (int l = 0; l < G->max_cl; ++l) {
     int a = 0, c = 1;
@@ -863,8 +861,7 @@ static void mg_vcycle_generic(Group* G, int transpose, int guard, hipStream_t s)
       sweep(l, a, c, sw == 0 ? 1 : 0);
       std::swap(a, c);
     }
-    if (b3) hipLaunchKernelGGL(k_mg_level3<T>, g3(l), dim3(kBS), 0, s, G->D, l, a, c, 0, 1, guard);
-    else hipLaunchKernelGGL(k_mg_resid<T>, gz(G, G->maxn[l]), dim3(kBS), 0, s, G->D, l, a, c, transpose, guard);
+    hipLaunchKernelGGL(k_mg_level3<T>, g3(l), dim3(kBS), 0, s, G->D, l, a, c, 0, 1, guard);
     hipLaunchKernelGGL(k_mg_restrict_r<T>, gz(G, G->maxn[l + 1]), dim3(kBS), 0, s, G->D, l, c, guard);
   }
   launch_coarse<T>(G, transpose, guard, s);
