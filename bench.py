@@ -39,7 +39,7 @@ TUNE_CACHE = os.path.join(ROOT, "paper_1806_05896_amd", "autotune_cache.json")
 # HBM bytes per launch of the roofline kernel from rocprofv3 FETCH_SIZE/WRITE_SIZE
 # runs (profiles/k_minres_k1_poisson2d_511x8_pmc.md), valid while the kernel
 # sources hash to the value they were measured with.
-TRAFFIC = {"kernel": 6, "N": 511, "batch": 8, "bytes": 613612838.9, "source_sha": "af1b96d6dc435d6f"}
+TRAFFIC = {"kernel": 6, "N": 511, "batch": 8, "bytes": 613191533.2, "source_sha": "12e5a857dd29eec6"}
 # kernel ids of ipmpde_time_kernel, named for the 2D Poisson workloads timed
 # here (convection-diffusion would launch k_mg_down2d / k_mg_up2d / k_mg_coarse)
 KERNEL_NAMES = {0: "k_saddle (saddle matvec)",
