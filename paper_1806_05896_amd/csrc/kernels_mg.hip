@@ -241,7 +241,7 @@ template <typename T>
 __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse(const Inst* __restrict__ Dp, int transpose, int guard) {
   INST_BEGIN
   // (3D finite-difference Poisson instances take k_mg_coarse_f3)
-  if (I.coarse_p2 || I.pde == 1 || (I.dim == 3 && I.pde == 0) || mg_skip(I, guard)) return;
+  if (I.coarse_p2 || I.pde == 1 || (I.dim == 3 && (I.pde == 0 || I.pde == 3)) || mg_skip(I, guard)) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ CoarseLevel LI[kMaxLev];
   T* lds = (T*)lds_raw;

@@ -1,7 +1,9 @@
-// Single-workgroup coarse V-cycle for 3D finite-difference Poisson levels
-// (Sec. 4.2: the Schur approximation's factor A + M_hat, here the 7-point
-// stencil (6 x - the six neighbours) / h^2 plus the restricted reaction term
-// m, inverted by the multigrid's coarsest levels, 15^3 and below).
+// Single-workgroup coarse V-cycle for the 3D Poisson levels (Sec. 4.2: the
+// Schur approximation's factor A + M_hat inverted by the multigrid's coarsest
+// levels, 15^3 and below), A the 7-point finite-difference stencil
+// (6 x - the six neighbours) / h^2 or the trilinear Q1 stiffness
+// (8/3 x - (the 12 edge neighbours) / 6 - (the 8 corner neighbours) / 12) / h^2
+// (Sec. 2), plus the restricted reaction term m.
 //
 // The iterates are stored with a zero ring (pitch N + 2), so sweeps read
 // their neighbours without boundary tests; each thread owns the same slots of
@@ -46,10 +48,37 @@ __device__ __forceinline__ T f3_nb(const T* __restrict__ a, int p, int P) {
   return ((((a[p - 1] + a[p + 1]) + a[p - P]) + a[p + P]) + a[p - PP]) + a[p + PP];
 }
 
-// Residual b - (A + m) x at padded node p of a level with 1/h^2 = ih2.
-template <typename T>
+// Residual b - (A + m) x at padded node p of a level with 1/h^2 = ih2 (Q1:
+// the 27-point stiffness, its sums in the order of the generic stencil).
+template <typename T, bool Q1>
 __device__ __forceinline__ T f3_res(const T* __restrict__ a, int p, int P, T ih2, T b, T m) {
-  return b - (ih2 * ((T)6 * a[p] - f3_nb<T>(a, p, P)) + m * a[p]);
+  if constexpr (!Q1) {
+    return b - (ih2 * ((T)6 * a[p] - f3_nb<T>(a, p, P)) + m * a[p]);
+  } else {
+    const int PP = P * P;
+    T e = 0, c = 0;
+#pragma unroll
+    for (int o3 = -1; o3 <= 1; ++o3)
+#pragma unroll
+      for (int o2 = -1; o2 <= 1; ++o2)
+#pragma unroll
+        for (int o1 = -1; o1 <= 1; ++o1) {
+          const int k = (o1 != 0) + (o2 != 0) + (o3 != 0);
+          if (k < 2) continue;
+          const T v = a[p + o1 + P * o2 + PP * o3];
+          if (k == 2) e += v;
+          else c += v;
+        }
+    return b - (ih2 * ((T)(8.0 / 3.0) * a[p] - (T)(1.0 / 6.0) * e - (T)(1.0 / 12.0) * c) + m * a[p]);
+  }
+}
+
+// The operator's diagonal at a level of width M - 1 (h = 1 / M).
+template <typename T, bool Q1>
+__device__ __forceinline__ T f3_diag(int M) {
+  if constexpr (!Q1) return (T)6 * (T)(M * M);
+  const double h = 1.0 / M;
+  return (T)(8.0 / (3.0 * h * h));
 }
 
 // Level q's geometry from the top width N0: width, pitch and LDS offset.
@@ -62,7 +91,7 @@ __device__ __forceinline__ void f3_level(int N0, int q, int& N, int& off) {
 // Descent at level Q (compile-time, so the per-slot registers stay
 // registers): nu_pre sweeps from zero, the residual, and its full weighting
 // into level Q + 1's right-hand side.  rb, rm, rd: the thread's b, m, 1/d.
-template <typename T, int S>
+template <typename T, int S, bool Q1>
 __device__ __forceinline__ void f3_down(T* lds, int N0, int Q, int nu_pre, T om, unsigned& alt, const T* rb,
                                         const T* rm, const T* rd) {
   const int tid = threadIdx.x;
@@ -77,13 +106,13 @@ __device__ __forceinline__ void f3_down(T* lds, int N0, int Q, int nu_pre, T om,
     if (s == 0) {
       F3_FOR(S, N) c[p] = om * rb[j] * rd[j]; F3_END
     } else {
-      F3_FOR(S, N) c[p] = a[p] + om * f3_res<T>(a, p, P, ih2, rb[j], rm[j]) * rd[j]; F3_END
+      F3_FOR(S, N) c[p] = a[p] + om * f3_res<T, Q1>(a, p, P, ih2, rb[j], rm[j]) * rd[j]; F3_END
     }
     __syncthreads();
     T* t = a; a = c; c = t;
     alt ^= 1u << Q;
   }
-  F3_FOR(S, N) c[p] = f3_res<T>(a, p, P, ih2, rb[j], rm[j]); F3_END
+  F3_FOR(S, N) c[p] = f3_res<T, Q1>(a, p, P, ih2, rb[j], rm[j]); F3_END
   __syncthreads();
   const int Pc = Nc + 2;
   T* bc = lds + offc + 2 * Pc * Pc * Pc;
@@ -104,7 +133,7 @@ __device__ __forceinline__ void f3_down(T* lds, int N0, int Q, int nu_pre, T om,
 
 // Ascent at level Q: trilinear prolongation of level Q + 1's iterate added to
 // the iterate, nu_post sweeps.
-template <typename T, int S>
+template <typename T, int S, bool Q1>
 __device__ __forceinline__ void f3_up(T* lds, int N0, int Q, int nu_post, T om, unsigned& alt, const T* rb,
                                       const T* rm, const T* rd) {
   const int tid = threadIdx.x;
@@ -130,7 +159,7 @@ __device__ __forceinline__ void f3_up(T* lds, int N0, int Q, int nu_post, T om, 
   F3_END
   __syncthreads();
   for (int s = 0; s < nu_post; ++s) {
-    F3_FOR(S, N) c[p] = a[p] + om * f3_res<T>(a, p, P, ih2, rb[j], rm[j]) * rd[j]; F3_END
+    F3_FOR(S, N) c[p] = a[p] + om * f3_res<T, Q1>(a, p, P, ih2, rb[j], rm[j]) * rd[j]; F3_END
     __syncthreads();
     T* t = a; a = c; c = t;
     alt ^= 1u << Q;
@@ -154,7 +183,7 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_f3(const Inst* __restri
   const double omega = I.omega;
   const KrylovCtrl* ctrl = I.ctrl;
   IPM_LOAD_TOGETHER(go, dim, pde, cl, L, nu_pre, nu_post, omega, ctrl);
-  if (!go || dim != 3 || pde != 0) return;
+  if (!go || dim != 3 || (pde != 0 && pde != 3)) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* lds = (T*)lds_raw;
   const int tid = threadIdx.x, nl = L - cl;
@@ -187,39 +216,43 @@ __global__ void __launch_bounds__(kCoarseBS) k_mg_coarse_f3(const Inst* __restri
     for (int q = 0; q < nl; ++q) tot += coarse_f3_elems(((N0 + 1) >> q) - 1);
     for (int k = tid; k < tot; k += kCoarseBS) lds[k] = (T)0;
   }
-  // 1/d with d = 6 / h^2 + m (h = 1 / (N + 1))
-  {
-#pragma unroll
-    for (int j = 0; j < kF3TopSlots; ++j) rd0[j] = (T)1 / ((T)6 * (T)((N0 + 1) * (N0 + 1)) + rm0[j]);
-    const int M1 = (N0 + 1) >> 1, M2 = (N0 + 1) >> 2, M3 = (N0 + 1) >> 3;
-    rd1[0] = (T)1 / ((T)6 * (T)(M1 * M1) + rm1[0]);
-    rd2[0] = (T)1 / ((T)6 * (T)(M2 * M2) + rm2[0]);
-    rd3[0] = (T)1 / ((T)6 * (T)(M3 * M3) + rm3[0]);
-  }
   __syncthreads();
   const T om = (T)omega;
-  unsigned alt = 0;  // bit q: level q's iterate sits in x2
-  // descent; level q's right-hand side below the top comes from the restriction
-  auto rhs = [&](int q, T* rb) {
-    int N, off;
-    f3_level(N0, q, N, off);
-    const T* b = lds + off + 2 * (N + 2) * (N + 2) * (N + 2);
-    F3_FOR(1, N) rb[0] = b[i]; F3_END
+  // the cycle for the stencil Q1 (compile time, so the per-slot values stay in registers)
+  auto cycle = [&](auto q1c) {
+    constexpr bool Q1 = decltype(q1c)::value;
+    // 1/d with d = the operator's diagonal + m (h = 1 / (N + 1))
+#pragma unroll
+    for (int j = 0; j < kF3TopSlots; ++j) rd0[j] = (T)1 / (f3_diag<T, Q1>(N0 + 1) + rm0[j]);
+    const int M1 = (N0 + 1) >> 1, M2 = (N0 + 1) >> 2, M3 = (N0 + 1) >> 3;
+    rd1[0] = (T)1 / (f3_diag<T, Q1>(M1) + rm1[0]);
+    rd2[0] = (T)1 / (f3_diag<T, Q1>(M2) + rm2[0]);
+    rd3[0] = (T)1 / (f3_diag<T, Q1>(M3) + rm3[0]);
+    unsigned alt = 0;  // bit q: level q's iterate sits in x2
+    // descent; level q's right-hand side below the top comes from the restriction
+    auto rhs = [&](int q, T* rb) {
+      int N, off;
+      f3_level(N0, q, N, off);
+      const T* b = lds + off + 2 * (N + 2) * (N + 2) * (N + 2);
+      F3_FOR(1, N) rb[0] = b[i]; F3_END
+    };
+    if (nl > 1) f3_down<T, kF3TopSlots, Q1>(lds, N0, 0, nu_pre, om, alt, rb0, rm0, rd0);
+    if (nl > 2) { rhs(1, rb1); f3_down<T, 1, Q1>(lds, N0, 1, nu_pre, om, alt, rb1, rm1, rd1); }
+    if (nl > 3) { rhs(2, rb2); f3_down<T, 1, Q1>(lds, N0, 2, nu_pre, om, alt, rb2, rm2, rd2); }
+    // the single-node level
+    if (nl == 1) f3_solve1<T>(lds, N0, 0, rb0[0], rd0[0]);
+    if (nl == 2) { rhs(1, rb1); f3_solve1<T>(lds, N0, 1, rb1[0], rd1[0]); }
+    if (nl == 3) { rhs(2, rb2); f3_solve1<T>(lds, N0, 2, rb2[0], rd2[0]); }
+    if (nl == 4) { rhs(3, rb3); f3_solve1<T>(lds, N0, 3, rb3[0], rd3[0]); }
+    // ascent
+    if (nl > 3) f3_up<T, 1, Q1>(lds, N0, 2, nu_post, om, alt, rb2, rm2, rd2);
+    if (nl > 2) f3_up<T, 1, Q1>(lds, N0, 1, nu_post, om, alt, rb1, rm1, rd1);
+    if (nl > 1) f3_up<T, kF3TopSlots, Q1>(lds, N0, 0, nu_post, om, alt, rb0, rm0, rd0);
+    const T* a = lds + (alt & 1u) * (N0 + 2) * (N0 + 2) * (N0 + 2);
+    F3_FOR(kF3TopSlots, N0) xg[i] = a[p]; F3_END
   };
-  if (nl > 1) f3_down<T, kF3TopSlots>(lds, N0, 0, nu_pre, om, alt, rb0, rm0, rd0);
-  if (nl > 2) { rhs(1, rb1); f3_down<T, 1>(lds, N0, 1, nu_pre, om, alt, rb1, rm1, rd1); }
-  if (nl > 3) { rhs(2, rb2); f3_down<T, 1>(lds, N0, 2, nu_pre, om, alt, rb2, rm2, rd2); }
-  // the single-node level
-  if (nl == 1) f3_solve1<T>(lds, N0, 0, rb0[0], rd0[0]);
-  if (nl == 2) { rhs(1, rb1); f3_solve1<T>(lds, N0, 1, rb1[0], rd1[0]); }
-  if (nl == 3) { rhs(2, rb2); f3_solve1<T>(lds, N0, 2, rb2[0], rd2[0]); }
-  if (nl == 4) { rhs(3, rb3); f3_solve1<T>(lds, N0, 3, rb3[0], rd3[0]); }
-  // ascent
-  if (nl > 3) f3_up<T, 1>(lds, N0, 2, nu_post, om, alt, rb2, rm2, rd2);
-  if (nl > 2) f3_up<T, 1>(lds, N0, 1, nu_post, om, alt, rb1, rm1, rd1);
-  if (nl > 1) f3_up<T, kF3TopSlots>(lds, N0, 0, nu_post, om, alt, rb0, rm0, rd0);
-  const T* a = lds + (alt & 1u) * (N0 + 2) * (N0 + 2) * (N0 + 2);
-  F3_FOR(kF3TopSlots, N0) xg[i] = a[p]; F3_END
+  if (pde == 3) cycle(std::true_type{});
+  else cycle(std::false_type{});
 }
 template __global__ void k_mg_coarse_f3<float>(const Inst*, int);
 template __global__ void k_mg_coarse_f3<double>(const Inst*, int);

@@ -22,6 +22,7 @@
 #include <string>
 #include <thread>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/ipmpde.h"
@@ -304,7 +305,7 @@ static bool is_p2(const ipmpde_problem* P) { return P->dim == 2 && P->pde == IPM
 static bool padded_coarse(const ipmpde_problem* P) { return is_p2(P) || (P->dim == 2 && P->pde == IPMPDE_POISSON_Q1); }
 static int coarse_kind(const ipmpde_problem* P) {
   if (padded_coarse(P)) return kCoarseP2;
-  if (P->dim == 3 && P->pde == IPMPDE_POISSON) return kCoarseF3;
+  if (P->dim == 3 && (P->pde == IPMPDE_POISSON || P->pde == IPMPDE_POISSON_Q1)) return kCoarseF3;
   return P->pde == IPMPDE_CONVDIFF ? kCoarseCD : kCoarseGeneric;
 }
 
