@@ -209,191 +209,6 @@ __global__ void __launch_bounds__(kBS) k_mg_prolong(const Inst* __restrict__ Dp,
   lvbuf<T>(F, dst)[i] += prolong_node<T>(xc, i, F.N, C.N, I.dim);
 }
 
-// All levels l >= coarse_lev in one workgroup: V-cycle from b at coarse_lev
-// (global) to x at coarse_lev (global).  Every level's x, x2, b and M_hat
-// diagonal live in LDS, and the level table is staged in LDS once, so the
-// phases (sweeps, restrictions, prolongations) touch no global memory.
-struct CoarseLevel {
-  int N, n, off;     // grid width, nodes, LDS offset (elements) of the level's 4 arrays
-  float hf;          // mesh width
-  double h;
-};
-
-template <typename T>
-__device__ __forceinline__ T coarse_diag(const CoarseLevel& C, int dim, int pde, double eps, int i1, int i2, T m) {
-  if (pde == 0) return (T)(2 * dim) / ((T)C.hf * (T)C.hf) + m;
-  return (T)op_diag(dim, pde, C.h, eps, i1, i2) + m;
-}
-
-template <typename T>
-__device__ __forceinline__ T coarse_resid(const T* __restrict__ x, const T* __restrict__ b, const T* __restrict__ ms,
-                                          int i, int i1, int i2, int i3, const CoarseLevel& C, int dim, int pde,
-                                          double eps, bool tr) {
-  return b[i] - (apply_op_s<T>(x, i, i1, i2, i3, C.N, C.N, C.N * C.N, dim, pde, C.h, eps, tr) + ms[i] * x[i]);
-}
-
-// Levels of the widest generic (3D) coarse hierarchy (15, 7, 3, 1) and the
-// nodes per thread of its widest level.
-constexpr int kCoarse3Levels = 4;
-constexpr int kCoarse3PerThread = (15 * 15 * 15 + kCoarseBS - 1) / kCoarseBS;
-
-template <typename T>
-__global__ void __launch_bounds__(kCoarseBS) k_mg_coarse(const Inst* __restrict__ Dp, int transpose, int guard) {
-  INST_BEGIN
-  // (3D finite-difference Poisson instances take k_mg_coarse_f3)
-  if (I.coarse_p2 || I.pde == 1 || (I.dim == 3 && (I.pde == 0 || I.pde == 3)) || mg_skip(I, guard)) return;
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  __shared__ CoarseLevel LI[kMaxLev];
-  T* lds = (T*)lds_raw;
-  const int cl = I.coarse_lev, L = I.nlev;
-  const bool tr = transpose != 0;
-  const int tid = threadIdx.x, dim = I.dim, pde = I.pde;
-  const double eps = I.eps;
-  const T om = (T)I.omega;
-  // global loads first, all in flight together: the top level's b and every
-  // level's reaction term (at most kCoarse3Levels levels, the widest 15^3)
-  const int n0 = I.lv[cl].n;
-  T breg[kCoarse3PerThread], mreg[kCoarse3Levels][kCoarse3PerThread];
-#pragma unroll
-  for (int j = 0; j < kCoarse3PerThread; ++j) {
-    const int i = tid + j * kCoarseBS;
-    breg[j] = i < n0 ? ((const T*)I.lv[cl].b)[i] : (T)0;
-  }
-#pragma unroll
-  for (int q = 0; q < kCoarse3Levels; ++q) {
-    const int nq = cl + q < L ? I.lv[cl + q].n : 0;
-    const T* __restrict__ mg = cl + q < L ? (const T*)I.lv[cl + q].mh : nullptr;
-#pragma unroll
-    for (int j = 0; j < kCoarse3PerThread; ++j) {
-      const int i = tid + j * kCoarseBS;
-      mreg[q][j] = i < nq ? mg[i] : (T)0;
-    }
-  }
-  if (tid == 0) {
-    int off = 0;
-    for (int l = cl; l < L; ++l) {
-      const Level& Lv = I.lv[l];
-      LI[l].N = Lv.N;
-      LI[l].n = Lv.n;
-      LI[l].off = off;
-      LI[l].h = Lv.h;
-      LI[l].hf = (float)Lv.h;
-      off += 5 * Lv.n;
-    }
-  }
-  __syncthreads();
-  // per level: x | x2 | b | m | 1/d, with d = the operator's diagonal + m
-#pragma unroll
-  for (int q = 0; q < kCoarse3Levels; ++q) {
-    if (cl + q < L) {
-      const CoarseLevel C = LI[cl + q];
-      T* ms = lds + C.off + 3 * C.n;
-#pragma unroll
-      for (int j = 0; j < kCoarse3PerThread; ++j) {
-        const int i = tid + j * kCoarseBS;
-        if (i < C.n) {
-          int i1, i2, i3;
-          node_coords_small(i, C.N, dim, i1, i2, i3);
-          ms[i] = mreg[q][j];
-          ms[C.n + i] = (T)1 / coarse_diag<T>(C, dim, pde, eps, i1, i2, mreg[q][j]);
-          if (q == 0) ms[i - C.n] = breg[j];
-        }
-      }
-    }
-  }
-  __syncthreads();
-  unsigned alt = 0;  // bit l: level l's iterate sits in x2
-  // descend
-  for (int l = cl; l < L - 1; ++l) {
-    const CoarseLevel C = LI[l];
-    T* a = lds + C.off;
-    T* c = a + C.n;
-    const T* B = a + 2 * C.n;
-    const T* ms = a + 3 * C.n;
-    const T* dinv = a + 4 * C.n;
-    for (int s = 0; s < I.nu_pre; ++s) {
-      for (int i = tid; i < C.n; i += kCoarseBS) {
-        int i1, i2, i3;
-        node_coords_small(i, C.N, dim, i1, i2, i3);
-        c[i] = (s == 0) ? om * B[i] * dinv[i]
-                        : a[i] + om * coarse_resid<T>(a, B, ms, i, i1, i2, i3, C, dim, pde, eps, tr) * dinv[i];
-      }
-      __syncthreads();
-      T* t = a; a = c; c = t;
-      alt ^= 1u << l;
-    }
-    // residual into c, then full weighting into the next level's b
-    for (int i = tid; i < C.n; i += kCoarseBS) {
-      int i1, i2, i3;
-      node_coords_small(i, C.N, dim, i1, i2, i3);
-      c[i] = coarse_resid<T>(a, B, ms, i, i1, i2, i3, C, dim, pde, eps, tr);
-    }
-    __syncthreads();
-    const CoarseLevel Cc = LI[l + 1];
-    T* Bc = lds + Cc.off + 2 * Cc.n;
-    const int N = C.N;
-    for (int ic = tid; ic < Cc.n; ic += kCoarseBS) {
-      int j1, j2, j3;
-      node_coords_small(ic, Cc.N, dim, j1, j2, j3);
-      const int f = (2 * j1 + 1) + N * ((2 * j2 + 1) + (dim == 3 ? N * (2 * j3 + 1) : 0));
-      T acc;
-      if (dim == 2) {
-        acc = (T)0.25 * c[f] + (T)0.125 * (c[f - 1] + c[f + 1] + c[f - N] + c[f + N]) +
-              (T)0.0625 * (c[f - 1 - N] + c[f + 1 - N] + c[f - 1 + N] + c[f + 1 + N]);
-      } else {
-        acc = 0;
-        const int NN = N * N;
-        for (int cc = -1; cc <= 1; ++cc)
-          for (int bb = -1; bb <= 1; ++bb)
-            for (int aa = -1; aa <= 1; ++aa) {
-              const T w = (aa ? (T)0.25 : (T)0.5) * (bb ? (T)0.25 : (T)0.5) * (cc ? (T)0.25 : (T)0.5);
-              acc += w * c[f + aa + N * bb + NN * cc];
-            }
-      }
-      Bc[ic] = acc;
-    }
-    __syncthreads();
-  }
-  // coarsest grid (a single node): exact solve
-  {
-    const CoarseLevel C = LI[L - 1];
-    T* X = lds + C.off;
-    const T* B = X + 2 * C.n;
-    const T* dinv = X + 4 * C.n;
-    for (int i = tid; i < C.n; i += kCoarseBS) X[i] = B[i] * dinv[i];
-    __syncthreads();
-  }
-  // ascend
-  for (int l = L - 2; l >= cl; --l) {
-    const CoarseLevel C = LI[l];
-    const CoarseLevel Cc = LI[l + 1];
-    const int ca = (alt >> l) & 1u;
-    T* a = lds + C.off + ca * C.n;
-    T* c = lds + C.off + (1 - ca) * C.n;
-    const T* B = lds + C.off + 2 * C.n;
-    const T* ms = lds + C.off + 3 * C.n;
-    const T* dinv = lds + C.off + 4 * C.n;
-    const T* xc = lds + Cc.off + ((alt >> (l + 1)) & 1u) * Cc.n;
-    for (int i = tid; i < C.n; i += kCoarseBS) a[i] += prolong_node<T, true>(xc, i, C.N, Cc.N, dim);
-    __syncthreads();
-    for (int s = 0; s < I.nu_post; ++s) {
-      for (int i = tid; i < C.n; i += kCoarseBS) {
-        int i1, i2, i3;
-        node_coords_small(i, C.N, dim, i1, i2, i3);
-        c[i] = a[i] + om * coarse_resid<T>(a, B, ms, i, i1, i2, i3, C, dim, pde, eps, tr) * dinv[i];
-      }
-      __syncthreads();
-      T* t = a; a = c; c = t;
-      alt ^= 1u << l;
-    }
-  }
-  const CoarseLevel C = LI[cl];
-  T* xg = (T*)I.lv[cl].x;
-  const T* xs = lds + C.off + ((alt >> cl) & 1u) * C.n;
-  for (int i = tid; i < C.n; i += kCoarseBS) xg[i] = xs[i];
-}
-
-
 // Poisson 2D specialization of the single-workgroup coarse V-cycle.  Per
 // level the iterates are stored with a zero ring (pitch N+2), so sweeps need
 // no boundary tests, and the diagonal d = 4/h^2 + M_hat and 1/d are staged
@@ -1372,7 +1187,6 @@ __global__ void __launch_bounds__(kBS) k_mg_kc_final(const Inst* __restrict__ Dp
   template __global__ void k_mg_level3<T>(const Inst*, int, int, int, int, int, int); \
   template __global__ void k_mg_restrict_r<T>(const Inst*, int, int, int);           \
   template __global__ void k_mg_prolong<T>(const Inst*, int, int, int, int);          \
-  template __global__ void k_mg_coarse<T>(const Inst*, int, int);                     \
   template __global__ void k_mg_scale_ty<T>(const Inst*, int, int);                   \
   template __global__ void k_mg_scale_ty_small<T>(const Inst*, int);                   \
   template __global__ void k_heat_couple<T>(const Inst*, int, int, int);

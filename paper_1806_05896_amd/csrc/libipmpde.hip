@@ -153,7 +153,6 @@ struct Group {
   bool p2 = false;   // some instance is 2D Poisson (padded coarse kernel)
   bool gen = false;  // some instance uses the generic (unpadded) level and coarse kernels
   bool cd = false;   // some instance is 2D convection-diffusion (its own coarse kernel)
-  bool gen3 = false; // some instance takes the generic coarse kernel (3D Q1)
   bool f3 = false;   // some instance takes the 3D finite-difference Poisson coarse kernel
   bool p3 = false;   // 3D, every instance finite-difference Poisson: the fused level kernels
   int max_cpack = 0; // longest coarse LDS image (Poisson instances)
@@ -233,16 +232,15 @@ static constexpr size_t kCoarseLds = 150 * 1024;
 // the FP64 kernels size their per-thread arrays for coarse levels of at most 31 x 31
 static_assert((size_t)coarse_p2_elems(63) * 8 > kCoarseLds, "an FP64 63 x 63 level must not fit the coarse kernel");
 
-// Coarse kernel kinds: the generic one (3D Q1), the padded 2D Poisson one
-// (finite differences and Q1), the 2D convection-diffusion one with staged
-// stencil coefficients and the padded 3D finite-difference Poisson one.
-enum { kCoarseGeneric = 0, kCoarseP2 = 1, kCoarseCD = 2, kCoarseF3 = 3 };
+// Coarse kernel kinds: the padded 2D Poisson one (finite differences and
+// Q1), the 2D convection-diffusion one with staged stencil coefficients and
+// the padded 3D Poisson one (finite differences and Q1).
+enum { kCoarseP2 = 1, kCoarseCD = 2, kCoarseF3 = 3 };
 
 static size_t coarse_level_elems(const Level& L, int kind) {
   if (kind == kCoarseP2) return (size_t)coarse_p2_elems(L.N);
   if (kind == kCoarseCD) return (size_t)kCoarseCDArrays * L.n;
-  if (kind == kCoarseF3) return (size_t)coarse_f3_elems(L.N);
-  return 5 * (size_t)L.n;
+  return (size_t)coarse_f3_elems(L.N);  // kCoarseF3
 }
 
 // Largest grid of each coarse kernel: the convection-diffusion stencil costs
@@ -285,8 +283,7 @@ static int set_coarse_lds_limit() {
   static std::once_flag once;
   static hipError_t err = hipSuccess;
   std::call_once(once, [] {
-    const void* fns[] = {(const void*)k_mg_coarse<float>, (const void*)k_mg_coarse<double>,
-                         (const void*)k_mg_coarse_cd<float>, (const void*)k_mg_coarse_cd<double>,
+    const void* fns[] = {(const void*)k_mg_coarse_cd<float>, (const void*)k_mg_coarse_cd<double>,
                          (const void*)k_minres_small<float>, (const void*)k_minres_small<double>,
                          (const void*)k_mg_coarse_p2<float>, (const void*)k_mg_coarse_p2<double>,
                          (const void*)k_mg_coarse_f3<float>, (const void*)k_mg_coarse_f3<double>,
@@ -305,8 +302,7 @@ static bool is_p2(const ipmpde_problem* P) { return P->dim == 2 && P->pde == IPM
 static bool padded_coarse(const ipmpde_problem* P) { return is_p2(P) || (P->dim == 2 && P->pde == IPMPDE_POISSON_Q1); }
 static int coarse_kind(const ipmpde_problem* P) {
   if (padded_coarse(P)) return kCoarseP2;
-  if (P->dim == 3 && (P->pde == IPMPDE_POISSON || P->pde == IPMPDE_POISSON_Q1)) return kCoarseF3;
-  return P->pde == IPMPDE_CONVDIFF ? kCoarseCD : kCoarseGeneric;
+  return P->pde == IPMPDE_CONVDIFF ? kCoarseCD : kCoarseF3;  // 3D: Poisson, finite differences or Q1
 }
 
 // The fused 3D level kernels stage cubes of (2 TC + 1 + 2 nu)^3 (descent,
@@ -624,7 +620,6 @@ static int group_select(Group* G, const ipmpde_options& o) {
   G->p2 = false;
   G->gen = false;
   G->cd = false;
-  G->gen3 = false;
   G->f3 = false;
   G->p3 = false;
   G->any_small = false;
@@ -688,7 +683,6 @@ static int group_select(Group* G, const ipmpde_options& o) {
     G->p2 = G->p2 || padded_coarse(P);
     G->gen = G->gen || !padded_coarse(P);
     G->cd = G->cd || coarse_kind(P) == kCoarseCD;
-    G->gen3 = G->gen3 || coarse_kind(P) == kCoarseGeneric;
     G->f3 = G->f3 || coarse_kind(P) == kCoarseF3;
     G->coarse_lds = std::max(G->coarse_lds, coarse_lds_bytes(lv, P->nlev, d.coarse_lev, fp32 ? 4 : 8, coarse_kind(P)));
   }
@@ -838,8 +832,6 @@ static void launch_coarse(Group* G, int transpose, int guard, hipStream_t s) {
   // each instance takes the kernel it would take alone (the other one
   // returns at once for it), so batched and solo solves round alike
   if (G->p2) hipLaunchKernelGGL(k_mg_coarse_p2<T>, dim3(1, 1, G->zc), dim3(kCoarseBS), G->coarse_lds, s, G->D, guard);
-  if (G->gen3)
-    hipLaunchKernelGGL(k_mg_coarse<T>, dim3(1, 1, G->zc), dim3(kCoarseBS), G->coarse_lds, s, G->D, transpose, guard);
   if (G->f3) hipLaunchKernelGGL(k_mg_coarse_f3<T>, dim3(1, 1, G->zc), dim3(kCoarseBS), G->coarse_lds, s, G->D, guard);
   if (G->cd)
     hipLaunchKernelGGL(k_mg_coarse_cd<T>, dim3(1, 1, G->zc), dim3(kCoarseBS), G->coarse_lds, s, G->D, transpose,
@@ -1224,7 +1216,7 @@ static void mark_unfinished(Group* G) {
 // The graph cache key of a launch sequence for this group and these options.
 static GraphKey graph_key(const Group* G, const ipmpde_options& o, int fg, int j0) {
   const int flags = (G->p2 ? 1 : 0) | (G->gen ? 2 : 0) | (G->any_small ? 4 : 0) | (G->outsel << 3) |
-                    (G->q1 ? 16 : 0) | (G->heat ? 32 : 0) | (G->tile << 6) | (G->cd ? 256 : 0) | (G->gen3 ? 512 : 0) |
+                    (G->q1 ? 16 : 0) | (G->heat ? 32 : 0) | (G->tile << 6) | (G->cd ? 256 : 0) |
                     (G->f3 ? 1024 : 0);
   GraphKey key{G->fp32 ? 1 : 0, o.nu_pre, o.nu_post, o.chunk, o.krylov_maxit, G->zc, G->max_n, G->max_nlev,
                G->max_cl, flags, G->coarse_lds, G->H[0].omega, o.krylov_tol};
