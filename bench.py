@@ -41,7 +41,7 @@ TUNE_CACHE = os.path.join(ROOT, "paper_1806_05896_amd", "autotune_cache.json")
 # sources hash to the value they were measured with.
 TRAFFIC = {"kernel": 6, "N": 511, "batch": 8, "bytes": 613191533.2, "source_sha": "12e5a857dd29eec6"}
 # kernel ids of ipmpde_time_kernel, named for the 2D Poisson workloads timed
-# here (convection-diffusion would launch k_mg_down2d / k_mg_up2d / k_mg_coarse)
+# here (convection-diffusion would launch k_mg_down2d / k_mg_up2d / k_mg_coarse_cd)
 KERNEL_NAMES = {0: "k_saddle (saddle matvec)",
                 2: "k_minres_k2 (Lanczos + diagonal preconditioner)", 3: "one V-cycle",
                 4: "k_mg_down_p2 (finest level: smoothing + residual + restriction)",
