@@ -112,12 +112,16 @@ __device__ __forceinline__ T mg3_apply(const T* __restrict__ a, int li, int pde,
   return (T)(1.0 / (h * h)) * ((T)(8.0 / 3.0) * a[li] - (T)(1.0 / 6.0) * e - (T)(1.0 / 12.0) * c);
 }
 // mode 0: Jacobi sweep (first: from a zero iterate) into x[dst]; mode 1: the
-// residual b - (A + mh) x[src] into x[dst].
+// residual b - (A + mh) x[src] into x[dst]; mode 2 (l = 0, between the two
+// solves of S_hat^-1, Sec. 4.2): b = (M + Theta_y) x[src] with the Q1 mass
+// (pde 3, summed as q1_mass does), else (1 + Theta_y) x[src] (x when the
+// whole hierarchy ran in the coarse kernel).
 template <typename T>
 __global__ void __launch_bounds__(kBS) k_mg_level3(const Inst* __restrict__ Dp, int l, int src, int dst, int first,
                                                    int mode, int guard) {
   INST_BEGIN
-  if (l >= I.coarse_lev || mg_skip(I, guard)) return;
+  if ((mode != 2 && l >= I.coarse_lev) || mg_skip(I, guard)) return;
+  if (mode == 2 && I.coarse_lev == 0) src = 0;
   const Level& L = I.lv[l];
   const int N = L.N, pde = I.pde;
   int b = blockIdx.x;
@@ -136,6 +140,10 @@ __global__ void __launch_bounds__(kBS) k_mg_level3(const Inst* __restrict__ Dp, 
   const T* __restrict__ mh = (const T*)L.mh;
   const double h = L.h;
   const T om = (T)I.omega;
+  if (mode == 2 && pde != 3) {
+    if (own) ((T*)L.b)[i] = (T)(obs_w(I, i) + I.ty[i]) * xin[i];
+    return;
+  }
   if (mode == 0 && first) {
     if (!own) return;
     const T d = (T)op_diag(3, pde, h, I.eps, i1, i2) + mh[i];
@@ -154,6 +162,25 @@ __global__ void __launch_bounds__(kBS) k_mg_level3(const Inst* __restrict__ Dp, 
   __syncthreads();
   if (!own) return;
   const int li = (t1 + 1) + H1 * ((t2 + 1) + H2 * (t3 + 1));
+  if (mode == 2) {
+    T f = 0, e = 0, c = 0;
+#pragma unroll
+    for (int o3 = -1; o3 <= 1; ++o3)
+#pragma unroll
+      for (int o2 = -1; o2 <= 1; ++o2)
+#pragma unroll
+        for (int o1 = -1; o1 <= 1; ++o1) {
+          const int k = (o1 != 0) + (o2 != 0) + (o3 != 0);
+          if (k == 0) continue;
+          const T v = sx[li + o1 + H1 * (o2 + H2 * o3)];
+          if (k == 1) f += v;
+          else if (k == 2) e += v;
+          else c += v;
+        }
+    const T xi = sx[li];
+    ((T*)L.b)[i] = ((T)64 * xi + (T)16 * f + (T)4 * e + c) * (T)(1.0 / 216.0) + (T)I.ty[i] * xi;
+    return;
+  }
   const T m = mh[i];
   const T xi = sx[li];
   const T Ax = mg3_apply<T, H1, H2>(sx, li, pde, h) + m * xi;

@@ -1143,7 +1143,11 @@ static void schur_inv(Group* G, int guard, hipStream_t s) {
     return;
   }
   mg_solve<T>(G, 0, guard, 0, s);
-  hipLaunchKernelGGL(k_mg_scale_ty<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, G->outsel, guard);
+  if (G->dim == 3)  // 3D: the Q1 mass summed from an LDS-staged block (mode 2)
+    hipLaunchKernelGGL(k_mg_level3<T>, dim3((mg3_blocks(G->maxN[0]) + 7) & ~7, 1, G->zc), dim3(kBS), 0, s, G->D, 0,
+                       G->outsel, 0, 0, 2, guard);
+  else
+    hipLaunchKernelGGL(k_mg_scale_ty<T>, gz(G, G->max_n), dim3(kBS), 0, s, G->D, G->outsel, guard);
   mg_solve<T>(G, 1, guard, 0, s);
 }
 
