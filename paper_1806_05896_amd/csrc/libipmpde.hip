@@ -1143,7 +1143,7 @@ static void schur_inv(Group* G, int guard, hipStream_t s) {
     return;
   }
   mg_solve<T>(G, 0, guard, 0, s);
-  if (G->dim == 3)  // 3D: the Q1 mass summed from an LDS-staged block (mode 2)
+  if (G->dim == 3 && G->q1)  // the 27-point Q1 mass summed from an LDS-staged block (mode 2)
     hipLaunchKernelGGL(k_mg_level3<T>, dim3((mg3_blocks(G->maxN[0]) + 7) & ~7, 1, G->zc), dim3(kBS), 0, s, G->D, 0,
                        G->outsel, 0, 0, 2, guard);
   else
